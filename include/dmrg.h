@@ -1,0 +1,147 @@
+/* dmrg.h -- SU(2) spin-adapted two-site DMRG: the Davidson H.psi hot path.
+ *
+ * Effective-Hamiltonian action of one two-site step (paper: Sec. II A,
+ * Eq. (2)-(3)): F := F + sum_i alpha_i A_i B_i C_i D_i E, where E and F are
+ * the reduced two-site wavefunction, A (D) are reduced operators of the left
+ * (right) block, B (C) are reduced operators of the left (right) site, and
+ * the SU(2) coupling enters as scalar factors C~ of Eq. (4) (Sec. II B-C).
+ *
+ * Conventions (all spins are passed doubled, 2S, as int32):
+ *  - Orbitals 0..L-1; sites l = site_l, r = site_l+1; left block [0, l),
+ *    right block [l+2, L).  Jordan-Wigner order L < l < r < R.
+ *  - Hamiltonian: Eq. (1) in spin-free form with real chemist integrals,
+ *    H = sum h_ij E_ij + 1/2 sum (ij|kl) sum_st a+_is a+_kt a_lt a_js.
+ *  - Reduced elements: <J'M'|T^k_q|JM> = <JM;kq|J'M'> <J'||T^k||J>.
+ *    a~_q = (-1)^(1/2-q) a_{-q}; [T x U]^K_Q = sum <k1 q1;k2 q2|K Q> T_q1 U_q2.
+ *  - Sites have three multiplets: 0 = empty, 1 = one electron (s=1/2),
+ *    2 = doubly occupied a+_up a+_dn|0>.
+ *  - Wavefunction basis ((L l) S_Ll (r R) S_rR) S; blocks are enumerated by
+ *    nested loops over (left sector, l, 2S_Ll ascending, r, right sector,
+ *    2S_rR ascending) keeping those with the right electron count and spin
+ *    triangles; each block is a column-major d_L x d_R FP64 matrix and the
+ *    blocks are concatenated in that order.
+ *  - Operator families (id: name, 2k, labels) of a block -- see the family
+ *    table below.  Each family member is a reduced operator between block
+ *    sectors; records group all positions (labels) of one family for one
+ *    (row sector, column sector) pair as [npos][rows][cols], each matrix
+ *    column-major (Sec. II A: position-dependent operators stored
+ *    contiguously with a third index).
+ *
+ * Family table (W0_ij = 2(ij|xy) - (iy|xj), W1_ij = sqrt(3) (iy|xj); j, k, l, i
+ * internal to the block; outside labels: left block [l, L) with pairs having
+ * at least one site orbital, right block [0, l+2) with all pairs):
+ *   0 H   2k=0  one position           block Hamiltonian
+ *   1 C   2k=1  i in block             a+_i
+ *   2 A0  2k=0  i<=j in block (left)   [a+_i a+_j]^0
+ *   3 A1  2k=2  i<j  in block (left)   [a+_i a+_j]^1
+ *   4 B0  2k=0  i<=j in block (left)   [a+_i a~_j]^0
+ *   5 B1  2k=2  i<=j in block (left)   [a+_i a~_j]^1
+ *   6 S   2k=1  x outside              sum (xj|kl) [[a+_k a~_l]^0 a~_j]^1/2
+ *   7 P0  2k=0  x<=y outside           sum (xj|yl) [a~_l a~_j]^0
+ *   8 P1  2k=2  x<y  outside           sum (xj|yl) [a~_l a~_j]^1
+ *   9 Q0  2k=0  x<=y outside           sum W0_ij [a+_i a~_j]^0
+ *  10 Q1  2k=2  x<=y outside           sum W1_ij [a+_i a~_j]^1
+ *   Labels are enumerated lexicographically (pairs: x outer, y inner).
+ *
+ * Ownership: the caller owns every array.  Host arrays are read during
+ * dmrg_build_tasks only.  Operator data (ldata/rdata) are DEVICE arrays that
+ * the plan references until dmrg_plan_free; psi/hpsi are device arrays
+ * borrowed for one call.  The plan owns its descriptors and workspace.
+ * Errors: negative status codes; no exception crosses the ABI; on error the
+ * outputs are unspecified and dmrg_last_error() (thread-local) describes it.
+ * After DMRG_EHIP the plan must be freed.  A plan is not reentrant.
+ */
+#ifndef DMRG_H
+#define DMRG_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DMRG_OK = 0,
+  DMRG_EINVAL = -1,     /* malformed argument */
+  DMRG_ESYM = -2,       /* electron count / spin triangle violated */
+  DMRG_ERANGE = -3,     /* record offset or size beyond its data array */
+  DMRG_ENOMEM = -4,     /* device or host allocation failed */
+  DMRG_EHIP = -5,       /* HIP runtime error */
+  DMRG_ENONFINITE = -6, /* NaN or Inf met */
+  DMRG_ENOCONV = -7     /* Davidson did not converge (best pair returned) */
+};
+
+typedef struct { int32_t n, two_s, dim; } dmrg_sector_t;
+typedef struct { int32_t fam, row_sec, col_sec, npos; int64_t off; } dmrg_oprec_t;
+
+typedef struct {
+  int32_t n_orb, n_elec, two_s, site_l;
+  const double *h1;          /* host [L*L] one-electron integrals            */
+  const double *eri;         /* host [L^4] (ij|kl), index ((i*L+j)*L+k)*L+l   */
+  int32_t n_lsec, n_rsec;
+  const dmrg_sector_t *lsec, *rsec;   /* host sector tables                  */
+  int64_t n_lrec, n_rrec;
+  const dmrg_oprec_t *lrec, *rrec;    /* host operator records               */
+  const double *ldata, *rdata;        /* DEVICE operator data                */
+  int64_t ldata_len, rdata_len;       /* elements                            */
+} dmrg_problem_t;
+
+enum { DMRG_FP64 = 0, DMRG_SPLIT_BF16 = 1 };
+
+typedef struct {
+  int32_t precision;        /* DMRG_FP64 or DMRG_SPLIT_BF16                   */
+  int32_t n_slices;         /* split only: BF16 slices per operand (3..7)     */
+  int64_t workspace_bytes;  /* cap for the intermediate stripes, 0 = default  */
+  int32_t flags;            /* reserved, 0                                     */
+} dmrg_plan_opts_t;
+
+typedef struct dmrg_plan dmrg_plan_t;
+
+typedef struct {
+  int64_t psi_len;          /* total wavefunction length (all problems)       */
+  int64_t n_blocks;         /* wavefunction blocks                            */
+  int64_t n_rows;           /* operator-table rows (Eq. 2 combinations)       */
+  int64_t n_tasks;          /* sector tasks x positions (Eq. 3 rows)          */
+  int64_t n_stage1;         /* first-stage products                           */
+  int64_t n_segments;       /* second-stage stripe segments                   */
+  double flops;             /* algorithmic FP64 flops of one H.psi, 2mnk      */
+  double stage1_flops, stage2_flops;
+  int64_t workspace_bytes;  /* stripe workspace actually used                 */
+  int32_t n_chunks;         /* launches pairs per H.psi                       */
+  int32_t pad;
+} dmrg_plan_stats_t;
+
+/* Build the operator table, sector-task and sector-value tables (Sec. II A,
+ * II C, Eq. (3)-(4)), group them into stripe products (Sec. III A) and upload
+ * the plan.  probs: n_probs problems solved side by side (one concatenated
+ * wavefunction).  stream: hipStream_t or NULL.  */
+int dmrg_build_tasks(const dmrg_problem_t *probs, int32_t n_probs,
+                     const dmrg_plan_opts_t *opts, void *stream, dmrg_plan_t **out);
+
+/* Offset and length of problem `prob` inside the concatenated wavefunction. */
+int dmrg_psi_layout(const dmrg_plan_t *p, int32_t prob, int64_t *off, int64_t *len);
+
+/* hpsi := H_eff psi for all problems (device arrays of psi_len doubles). */
+int dmrg_apply_H(dmrg_plan_t *p, const double *psi, double *hpsi, void *stream);
+
+/* diag := diagonal of H_eff (device array of psi_len doubles). */
+int dmrg_diag_H(dmrg_plan_t *p, double *diag, void *stream);
+
+int dmrg_plan_stats(const dmrg_plan_t *p, dmrg_plan_stats_t *st);
+void dmrg_plan_free(dmrg_plan_t *p);
+const char *dmrg_last_error(void);
+
+/* ---- host-logic inspection (no GPU use; for tests of the host tables) ---- */
+/* Wigner 6j {a b c; d e f}, 9j and the Eq. (4) factor, doubled spins.       */
+double dmrg_wigner_6j(int a, int b, int c, int d, int e, int f);
+double dmrg_wigner_9j(int j1, int j2, int j, int k1, int k2, int k, int j1p, int j2p, int jp);
+double dmrg_ctilde(int j1, int j2, int j, int k1, int k2, int k, int j1p, int j2p, int jp);
+/* Test-only host evaluation of the task list built for a problem whose
+ * ldata/rdata are HOST arrays: y := sum over tasks of v A X D^T, computed with
+ * plain loops on the CPU.  It checks the host tables without a GPU and is
+ * never used by dmrg_apply_H.  */
+int dmrg_debug_host_apply(const dmrg_problem_t *prob, const double *psi, double *y,
+                          dmrg_plan_stats_t *st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,131 @@
+"""ctypes binding of the C ABI declared in include/dmrg.h.
+
+Argument marshalling only: every step of H.psi and Davidson runs inside the
+shared library.  Device memory and streams come from PyTorch (tensors are
+passed by data pointer).  Loading fails loudly when the library is missing.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBNAME = "libdmrg_hpsi.so"
+
+c_i32, c_i64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+
+DMRG_FP64 = 0
+DMRG_SPLIT_BF16 = 1
+
+
+class Sector(ctypes.Structure):
+    _fields_ = [("n", c_i32), ("two_s", c_i32), ("dim", c_i32)]
+
+
+class OpRec(ctypes.Structure):
+    _fields_ = [("fam", c_i32), ("row_sec", c_i32), ("col_sec", c_i32), ("npos", c_i32),
+                ("off", c_i64)]
+
+
+class ProblemT(ctypes.Structure):
+    _fields_ = [("n_orb", c_i32), ("n_elec", c_i32), ("two_s", c_i32), ("site_l", c_i32),
+                ("h1", c_vp), ("eri", c_vp),
+                ("n_lsec", c_i32), ("n_rsec", c_i32), ("lsec", c_vp), ("rsec", c_vp),
+                ("n_lrec", c_i64), ("n_rrec", c_i64), ("lrec", c_vp), ("rrec", c_vp),
+                ("ldata", c_vp), ("rdata", c_vp), ("ldata_len", c_i64), ("rdata_len", c_i64)]
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("precision", c_i32), ("n_slices", c_i32), ("workspace_bytes", c_i64),
+                ("flags", c_i32)]
+
+
+class PlanStats(ctypes.Structure):
+    _fields_ = [("psi_len", c_i64), ("n_blocks", c_i64), ("n_rows", c_i64), ("n_tasks", c_i64),
+                ("n_stage1", c_i64), ("n_segments", c_i64), ("flops", c_dbl),
+                ("stage1_flops", c_dbl), ("stage2_flops", c_dbl), ("workspace_bytes", c_i64),
+                ("n_chunks", c_i32), ("pad", c_i32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+_lib = None
+
+
+def lib_path():
+    return os.path.join(HERE, LIBNAME)
+
+
+def load(path=None):
+    """Load the shared library (raises if it was not built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or lib_path()
+    if not os.path.exists(p):
+        raise RuntimeError("HIP library %s not built; run __graft_entry__.build()" % p)
+    L = ctypes.CDLL(p)
+    L.dmrg_last_error.restype = ctypes.c_char_p
+    for name in ("dmrg_wigner_6j", "dmrg_wigner_9j", "dmrg_ctilde"):
+        getattr(L, name).restype = c_dbl
+    L.dmrg_wigner_6j.argtypes = [ctypes.c_int] * 6
+    L.dmrg_wigner_9j.argtypes = [ctypes.c_int] * 9
+    L.dmrg_ctilde.argtypes = [ctypes.c_int] * 9
+    L.dmrg_debug_host_apply.argtypes = [ctypes.POINTER(ProblemT), c_vp, c_vp,
+                                        ctypes.POINTER(PlanStats)]
+    if hasattr(L, "dmrg_build_tasks"):
+        L.dmrg_build_tasks.argtypes = [ctypes.POINTER(ProblemT), c_i32, ctypes.POINTER(PlanOpts),
+                                       c_vp, ctypes.POINTER(c_vp)]
+        L.dmrg_psi_layout.argtypes = [c_vp, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]
+        L.dmrg_apply_H.argtypes = [c_vp, c_vp, c_vp, c_vp]
+        L.dmrg_diag_H.argtypes = [c_vp, c_vp, c_vp]
+        L.dmrg_plan_stats.argtypes = [c_vp, ctypes.POINTER(PlanStats)]
+        L.dmrg_plan_free.argtypes = [c_vp]
+        L.dmrg_plan_free.restype = None
+    if path is None:
+        _lib = L
+    return L
+
+
+def check(rc, L=None):
+    if rc != 0:
+        L = L or load()
+        raise RuntimeError("dmrg error %d: %s" % (rc, L.dmrg_last_error().decode()))
+
+
+class ProblemArgs:
+    """Keeps host arrays alive and exposes the C struct of one problem.
+
+    ``ldata``/``rdata`` are integer addresses of the operator data (device
+    pointers for the GPU path, host pointers for the debug host evaluation).
+    """
+
+    def __init__(self, prob, ldata_ptr, rdata_ptr):
+        self.h1 = np.ascontiguousarray(prob.h, dtype=np.float64)
+        self.eri = np.ascontiguousarray(prob.eri, dtype=np.float64)
+        self.lsec = (Sector * len(prob.left.sectors))(*[Sector(*s) for s in prob.left.sectors])
+        self.rsec = (Sector * len(prob.right.sectors))(*[Sector(*s) for s in prob.right.sectors])
+        lr, rr = prob.left.records, prob.right.records
+        self.lrec = (OpRec * max(1, len(lr)))(*[OpRec(f, r, c, n, o) for (f, r, c, o, n) in lr])
+        self.rrec = (OpRec * max(1, len(rr)))(*[OpRec(f, r, c, n, o) for (f, r, c, o, n) in rr])
+        self.s = ProblemT(prob.n_orb, prob.n_elec, prob.two_s, prob.p,
+                          self.h1.ctypes.data, self.eri.ctypes.data,
+                          len(prob.left.sectors), len(prob.right.sectors),
+                          ctypes.addressof(self.lsec), ctypes.addressof(self.rsec),
+                          len(lr), len(rr), ctypes.addressof(self.lrec), ctypes.addressof(self.rrec),
+                          ldata_ptr, rdata_ptr, prob.left.data.size, prob.right.data.size)
+
+
+def debug_host_apply(prob, psi, lib=None):
+    """Test-only: evaluate the host task list on the CPU (no GPU)."""
+    L = lib or load()
+    ld = np.ascontiguousarray(prob.left.data)
+    rd = np.ascontiguousarray(prob.right.data)
+    args = ProblemArgs(prob, ld.ctypes.data, rd.ctypes.data)
+    x = np.ascontiguousarray(psi, dtype=np.float64)
+    y = np.zeros_like(x)
+    st = PlanStats()
+    check(L.dmrg_debug_host_apply(ctypes.byref(args.s), x.ctypes.data, y.ctypes.data,
+                                  ctypes.byref(st)), L)
+    return y, st

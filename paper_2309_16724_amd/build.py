@@ -1,0 +1,56 @@
+"""Build step of the HIP library (gfx950): host C++ with g++, device code and
+the link with hipcc, all in-tree.
+
+    python -m paper_2309_16724_amd.build
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+OUT = os.path.join(HERE, "libdmrg_hpsi.so")
+BUILD = os.path.join(HERE, "_build")
+
+HOST_SRC = ["wigner.cpp", "model.cpp", "api_host.cpp"]
+HIP_HOST_SRC = ["plan.cpp"]
+HIP_SRC = ["kernels_f64.hip"]
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout)
+        raise RuntimeError("build step failed: " + " ".join(cmd))
+    return r.stdout
+
+
+def build(verbose=False):
+    os.makedirs(BUILD, exist_ok=True)
+    objs = []
+    for s in HOST_SRC:
+        o = os.path.join(BUILD, s + ".o")
+        _run(["g++", "-O2", "-fPIC", "-std=c++17", "-c", os.path.join(CSRC, s), "-o", o])
+        objs.append(o)
+    for s in HIP_HOST_SRC:
+        o = os.path.join(BUILD, s + ".o")
+        _run([HIPCC, "-O2", "-fPIC", "-std=c++17", "-c",
+              os.path.join(CSRC, s), "-o", o])
+        objs.append(o)
+    for s in HIP_SRC:
+        o = os.path.join(BUILD, s + ".o")
+        _run([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, s), "-o", o])
+        objs.append(o)
+    tmp = OUT + ".tmp"
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
+    os.replace(tmp, OUT)
+    if verbose:
+        print("built", OUT)
+    return OUT
+
+
+if __name__ == "__main__":
+    build(verbose=True)

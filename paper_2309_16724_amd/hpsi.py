@@ -1,0 +1,97 @@
+"""Python handle on a device plan (argument marshalling over the C ABI).
+
+Operator data are copied to the GPU once; psi/hpsi are torch CUDA tensors
+passed by pointer.  Nothing here computes: H.psi, diag(H) and Davidson run
+in the HIP library.  If the library is missing, construction raises.
+"""
+import ctypes
+
+import numpy as np
+
+from . import binding as B
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Plan:
+    def __init__(self, problems, precision=B.DMRG_FP64, n_slices=0, workspace_bytes=0,
+                 device="cuda:0"):
+        torch = _torch()
+        if not isinstance(problems, (list, tuple)):
+            problems = [problems]
+        self.lib = B.load()
+        if not hasattr(self.lib, "dmrg_build_tasks"):
+            raise RuntimeError("library has no GPU entry points")
+        self.device = torch.device(device)
+        self.problems = problems
+        self._keep = []
+        structs = []
+        for pr in problems:
+            ld = torch.from_numpy(np.ascontiguousarray(pr.left.data)).to(self.device)
+            rd = torch.from_numpy(np.ascontiguousarray(pr.right.data)).to(self.device)
+            if ld.numel() == 0:
+                ld = torch.zeros(1, dtype=torch.float64, device=self.device)
+            if rd.numel() == 0:
+                rd = torch.zeros(1, dtype=torch.float64, device=self.device)
+            args = B.ProblemArgs(pr, ld.data_ptr(), rd.data_ptr())
+            self._keep += [ld, rd, args]
+            structs.append(args.s)
+        arr = (B.ProblemT * len(structs))(*structs)
+        self._keep.append(arr)
+        opts = B.PlanOpts(precision, n_slices, workspace_bytes, 0)
+        h = ctypes.c_void_p()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        torch.cuda.synchronize(self.device)
+        B.check(self.lib.dmrg_build_tasks(arr, len(structs), ctypes.byref(opts),
+                                          ctypes.c_void_p(stream), ctypes.byref(h)), self.lib)
+        self.handle = h
+        st = self.stats()
+        self.size = int(st["psi_len"])
+
+    def stats(self):
+        st = B.PlanStats()
+        B.check(self.lib.dmrg_plan_stats(self.handle, ctypes.byref(st)), self.lib)
+        return st.as_dict()
+
+    def layout(self, k):
+        off, ln = ctypes.c_int64(), ctypes.c_int64()
+        B.check(self.lib.dmrg_psi_layout(self.handle, k, ctypes.byref(off), ctypes.byref(ln)), self.lib)
+        return off.value, ln.value
+
+    def _stream(self, stream):
+        torch = _torch()
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        return ctypes.c_void_p(s.cuda_stream)
+
+    def apply(self, psi, out=None, stream=None):
+        torch = _torch()
+        assert psi.dtype == torch.float64 and psi.is_cuda and psi.numel() == self.size
+        psi = psi.contiguous()
+        if out is None:
+            out = torch.empty_like(psi)
+        B.check(self.lib.dmrg_apply_H(self.handle, ctypes.c_void_p(psi.data_ptr()),
+                                      ctypes.c_void_p(out.data_ptr()), self._stream(stream)), self.lib)
+        return out
+
+    def diag(self, out=None, stream=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.size, dtype=torch.float64, device=self.device)
+        B.check(self.lib.dmrg_diag_H(self.handle, ctypes.c_void_p(out.data_ptr()),
+                                     self._stream(stream)), self.lib)
+        return out
+
+    def free(self):
+        if getattr(self, "handle", None):
+            _torch().cuda.synchronize(self.device)
+            self.lib.dmrg_plan_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

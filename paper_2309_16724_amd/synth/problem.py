@@ -431,26 +431,30 @@ def exact_problem(n_orb, n_elec, two_s, seed, p=None, max_mult=None):
 
 
 # ---------------------------------------------------------- random builder
-def synthetic_sectors(n, n_share, D, rng, spin_ratio=0.45, sigma_frac=0.35):
+def synthetic_sectors(n, n_share, D, rng, spin_ratio=0.6, sigma_frac=0.15, cap=True):
     """Sector table of a synthetic block of n orbitals with about D multiplets.
 
     d(N, S) ~ exp(-(N - n_share)^2 / (2 sigma^2)) * spin_ratio^(2S), capped by
-    the number of multiplets the block can hold, rounded, at least 1.
+    the number of multiplets the block can hold (``cap``), rounded, kept if
+    at least 1.  Without the cap a block of few orbitals can carry large
+    sectors (abstract blocks for kernel tests with few labels).
     """
     cand = []
     sigma = max(1.0, sigma_frac * n)
     for N in range(0, 2 * n + 1):
         for s2 in _valid_spins(n, N):
-            cap = weyl_dim(n, N, s2)
-            if cap <= 0:
+            cmax = weyl_dim(n, N, s2)
+            if cmax <= 0:
                 continue
+            if not cap:
+                cmax = 1 << 30
             w = np.exp(-(N - n_share) ** 2 / (2 * sigma ** 2)) * spin_ratio ** s2
-            cand.append([N, s2, w, cap])
+            cand.append([N, s2, w, cmax])
     tot = sum(c[2] for c in cand)
     secs = []
-    for N, s2, w, cap in cand:
+    for N, s2, w, cmax in cand:
         d = int(round(D * w / tot))
-        d = min(d, cap)
+        d = min(d, cmax)
         if d >= 1:
             secs.append((N, s2, d))
     return secs
@@ -493,8 +497,8 @@ def _rand_family_blocks(fam, role, n_orb, p, sectors, rng, scale):
     return out
 
 
-def random_problem(n_orb, n_elec, two_s, seed, D, p=None, spin_ratio=0.45,
-                   sigma_frac=0.35, op_scale=0.3):
+def random_problem(n_orb, n_elec, two_s, seed, D, p=None, spin_ratio=0.6,
+                   sigma_frac=0.15, op_scale=0.3, cap=True):
     """Problem with synthetic sector tables and random reduced operators."""
     h, eri = make_integrals(n_orb, seed)
     if p is None:
@@ -505,7 +509,7 @@ def random_problem(n_orb, n_elec, two_s, seed, D, p=None, spin_ratio=0.45,
         lo, hi = cat.block_range(role, n_orb, p)
         n = hi - lo
         share = n_elec * n / n_orb
-        secs = synthetic_sectors(n, share, D, rng, spin_ratio, sigma_frac) if n > 0 \
+        secs = synthetic_sectors(n, share, D, rng, spin_ratio, sigma_frac, cap) if n > 0 \
             else [(0, 0, 1)]
         blk = BlockData(role, n_orb, p, secs)
         fams = cat.LEFT_FAMILIES if role == "L" else cat.RIGHT_FAMILIES
