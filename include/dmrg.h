@@ -126,6 +126,15 @@ int dmrg_apply_H(dmrg_plan_t *p, const double *psi, double *hpsi, void *stream);
 int dmrg_diag_H(dmrg_plan_t *p, double *diag, void *stream);
 
 int dmrg_plan_stats(const dmrg_plan_t *p, dmrg_plan_stats_t *st);
+
+/* Profiling: when on, dmrg_apply_H records a hipEvent pair on its stream
+ * around each first-stage (stage 1) and second-stage (stage 2) kernel launch.
+ * dmrg_get_profile waits for the recorded events and returns the number of
+ * launches, their summed duration and summed algorithmic flops since the
+ * last dmrg_set_profiling call. */
+int dmrg_set_profiling(dmrg_plan_t *p, int32_t on);
+int dmrg_get_profile(dmrg_plan_t *p, int32_t stage, int64_t *n_launches, double *total_ms,
+                     double *total_flops);
 void dmrg_plan_free(dmrg_plan_t *p);
 const char *dmrg_last_error(void);
 
@@ -140,6 +149,11 @@ double dmrg_ctilde(int j1, int j2, int j, int k1, int k2, int k, int j1p, int j2
  * never used by dmrg_apply_H.  */
 int dmrg_debug_host_apply(const dmrg_problem_t *prob, const double *psi, double *y,
                           dmrg_plan_stats_t *st);
+/* Test-only: build the device plan's tile and segment lists for one problem
+ * with HOST operator data and execute them on the CPU with the kernels'
+ * addressing.  Never used by dmrg_apply_H. */
+int dmrg_debug_plan_host_apply(const dmrg_problem_t *prob, const double *psi, double *y,
+                               int64_t workspace_bytes);
 
 #ifdef __cplusplus
 }

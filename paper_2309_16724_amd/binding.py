@@ -83,6 +83,10 @@ def load(path=None):
         L.dmrg_plan_stats.argtypes = [c_vp, ctypes.POINTER(PlanStats)]
         L.dmrg_plan_free.argtypes = [c_vp]
         L.dmrg_plan_free.restype = None
+        L.dmrg_set_profiling.argtypes = [c_vp, c_i32]
+        L.dmrg_get_profile.argtypes = [c_vp, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_dbl),
+                                       ctypes.POINTER(c_dbl)]
+        L.dmrg_debug_plan_host_apply.argtypes = [ctypes.POINTER(ProblemT), c_vp, c_vp, c_i64]
     if path is None:
         _lib = L
     return L
@@ -115,6 +119,19 @@ class ProblemArgs:
                           ctypes.addressof(self.lsec), ctypes.addressof(self.rsec),
                           len(lr), len(rr), ctypes.addressof(self.lrec), ctypes.addressof(self.rrec),
                           ldata_ptr, rdata_ptr, prob.left.data.size, prob.right.data.size)
+
+
+def debug_plan_host_apply(prob, psi, workspace_bytes=0, lib=None):
+    """Test-only: run the device plan's tile lists on the CPU (no GPU)."""
+    L = lib or load()
+    ld = np.ascontiguousarray(prob.left.data)
+    rd = np.ascontiguousarray(prob.right.data)
+    args = ProblemArgs(prob, ld.ctypes.data, rd.ctypes.data)
+    x = np.ascontiguousarray(psi, dtype=np.float64)
+    y = np.zeros_like(x)
+    check(L.dmrg_debug_plan_host_apply(ctypes.byref(args.s), x.ctypes.data, y.ctypes.data,
+                                       workspace_bytes), L)
+    return y
 
 
 def debug_host_apply(prob, psi, lib=None):

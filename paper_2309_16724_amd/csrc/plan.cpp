@@ -35,6 +35,14 @@ struct dmrg_plan {
   dmrg_plan_stats_t stats;
   int precision = 0, n_slices = 0;
   std::vector<void *> allocs;
+  // profiling: events around every first- and second-stage launch
+  int profiling = 0;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<int, int>>> ev_marks;   // (stage, (start ev, stop ev))
+  std::vector<double> ev_flops;                                  // algorithmic flops per mark
+  ~dmrg_plan() {
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -153,6 +161,7 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
         int sidx = (int)ch.seg1.size();
         ch.seg1.push_back(g);
         P->stats.stage1_flops += 2.0 * s.dL * s.dRin * s.dRout;
+        ch.flops1 += 2.0 * s.dL * s.dRin * s.dRout;
         for (int i0 = 0; i0 < s.dL; i0 += TILE)
           for (int j0 = 0; j0 < s.dRout; j0 += TILE) {
             Tile t{};
@@ -218,6 +227,7 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
           g.kb = E.dL;
           g.K = run * E.dL;
           P->stats.stage2_flops += 2.0 * F.dL * g.K * F.dR;
+          ch.flops2 += 2.0 * F.dL * g.K * F.dR;
         } else {
           g.a_base = -1;
           g.K = E.dL;
@@ -386,15 +396,73 @@ extern "C" int dmrg_psi_layout(const dmrg_plan_t *p, int32_t prob, int64_t *off,
   return DMRG_OK;
 }
 
+static int next_event(dmrg_plan *p, size_t &idx) {
+  if (idx >= p->ev_pool.size()) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    p->ev_pool.push_back(e);
+  }
+  return DMRG_OK;
+}
+
 extern "C" int dmrg_apply_H(dmrg_plan_t *p, const double *psi, double *hpsi, void *stream) {
   if (!p || !psi || !hpsi) { set_error("null argument"); return DMRG_EINVAL; }
   if (psi == hpsi) { set_error("psi and hpsi must not alias"); return DMRG_EINVAL; }
   launch_zero(hpsi, p->psi_len, stream);
+  size_t ev = p->ev_marks.empty() ? 0 : (size_t)p->ev_marks.back().second.second + 1;
   for (auto &ch : p->chunks) {
-    launch_tiles_f64(1, ch.d_tile1, ch.d_seg1, (int)ch.tile1.size(), p->d_bases, psi, hpsi, p->d_work, stream);
-    launch_tiles_f64(2, ch.d_tile2, ch.d_seg2, (int)ch.tile2.size(), p->d_bases, psi, hpsi, p->d_work, stream);
+    for (int stage = 1; stage <= 2; stage++) {
+      int e0 = -1;
+      if (p->profiling) {
+        int rc = next_event(p, ev);
+        if (rc) return rc;
+        e0 = (int)ev;
+        HIPCHK(hipEventRecord(p->ev_pool[ev++], (hipStream_t)stream));
+      }
+      if (stage == 1)
+        launch_tiles_f64(1, ch.d_tile1, ch.d_seg1, (int)ch.tile1.size(), p->d_bases, psi, hpsi, p->d_work, stream);
+      else
+        launch_tiles_f64(2, ch.d_tile2, ch.d_seg2, (int)ch.tile2.size(), p->d_bases, psi, hpsi, p->d_work, stream);
+      if (p->profiling) {
+        int rc = next_event(p, ev);
+        if (rc) return rc;
+        HIPCHK(hipEventRecord(p->ev_pool[ev], (hipStream_t)stream));
+        p->ev_marks.push_back({stage, {e0, (int)ev}});
+        p->ev_flops.push_back(stage == 1 ? ch.flops1 : ch.flops2);
+        ev++;
+      }
+    }
   }
   HIPCHK(hipGetLastError());
+  return DMRG_OK;
+}
+
+extern "C" int dmrg_set_profiling(dmrg_plan_t *p, int32_t on) {
+  if (!p) { set_error("null plan"); return DMRG_EINVAL; }
+  p->profiling = on ? 1 : 0;
+  p->ev_marks.clear();
+  p->ev_flops.clear();
+  return DMRG_OK;
+}
+
+extern "C" int dmrg_get_profile(dmrg_plan_t *p, int32_t stage, int64_t *n_launches, double *total_ms,
+                                double *total_flops) {
+  if (!p || stage < 1 || stage > 2) { set_error("bad plan or stage"); return DMRG_EINVAL; }
+  int64_t n = 0;
+  double ms = 0.0, fl = 0.0;
+  for (size_t i = 0; i < p->ev_marks.size(); i++) {
+    if (p->ev_marks[i].first != stage) continue;
+    float t = 0.0f;
+    HIPCHK(hipEventSynchronize(p->ev_pool[p->ev_marks[i].second.second]));
+    HIPCHK(hipEventElapsedTime(&t, p->ev_pool[p->ev_marks[i].second.first],
+                               p->ev_pool[p->ev_marks[i].second.second]));
+    n++;
+    ms += t;
+    fl += p->ev_flops[i];
+  }
+  if (n_launches) *n_launches = n;
+  if (total_ms) *total_ms = ms;
+  if (total_flops) *total_flops = fl;
   return DMRG_OK;
 }
 

@@ -48,6 +48,7 @@ struct Chunk {
   std::vector<Tile> tile1, tile2;
   Seg *d_seg1 = nullptr, *d_seg2 = nullptr;
   Tile *d_tile1 = nullptr, *d_tile2 = nullptr;
+  double flops1 = 0.0, flops2 = 0.0;    // algorithmic flops of each launch
 };
 
 constexpr int TILE = 32;

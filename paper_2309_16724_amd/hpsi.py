@@ -84,6 +84,16 @@ class Plan:
                                      self._stream(stream)), self.lib)
         return out
 
+    def set_profiling(self, on=True):
+        B.check(self.lib.dmrg_set_profiling(self.handle, 1 if on else 0), self.lib)
+
+    def profile(self, stage):
+        """(launches, total ms, total algorithmic flops) of stage 1 or 2 since set_profiling."""
+        n, ms, fl = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        B.check(self.lib.dmrg_get_profile(self.handle, stage, ctypes.byref(n), ctypes.byref(ms),
+                                          ctypes.byref(fl)), self.lib)
+        return n.value, ms.value, fl.value
+
     def free(self):
         if getattr(self, "handle", None):
             _torch().cuda.synchronize(self.device)

@@ -122,3 +122,16 @@ def test_workspace_chunking_same_result(torch):
     assert float((y1 - y2).abs().max()) <= 1e-12 * float(y1.abs().max())
     p1.free()
     p2.free()
+
+
+def test_full_size_matches_oracle(torch):
+    """L=24, D=512 (the benchmark workload): every element against the oracle."""
+    from oracle.hpsi import HEff
+    _say("full size L=24 D=512 vs oracle (about 80 s of CPU)")
+    prob = random_problem(24, 24, 0, 1, D=512)
+    he = HEff(prob)
+    x = np.random.default_rng(12).standard_normal(he.size)
+    y = _gpu_apply(torch, prob, x)
+    _say("gpu done; oracle running")
+    ref = he.apply(x)
+    assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
