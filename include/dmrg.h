@@ -41,7 +41,12 @@
  *   8 P1  2k=2  x<y  outside           sum (xj|yl) [a~_l a~_j]^1
  *   9 Q0  2k=0  x<=y outside           sum W0_ij [a+_i a~_j]^0
  *  10 Q1  2k=2  x<=y outside           sum W1_ij [a+_i a~_j]^1
- *   Labels are enumerated lexicographically (pairs: x outer, y inner).
+ *   Label order: single labels ascending.  Pairs inside the left block (A, B)
+ *   and pairs of the right block's P, Q come in groups: (1) x<y inside the
+ *   left block, lexicographic; (2) (x,x) inside it; (3) (x,l); (4) (x,l+1) with
+ *   x in the left block; (5) site pairs (l,l), (l,l+1), (l+1,l+1) -- groups
+ *   3-5 only for the right block, strict families (x<y) omit diagonal pairs.
+ *   Pairs of the left block's P, Q are lexicographic (x outer, y inner).
  *
  * Ownership: the caller owns every array.  Host arrays are read during
  * dmrg_build_tasks only.  Operator data (ldata/rdata) are DEVICE arrays that
@@ -125,6 +130,31 @@ int dmrg_apply_H(dmrg_plan_t *p, const double *psi, double *hpsi, void *stream);
 /* diag := diagonal of H_eff (device array of psi_len doubles). */
 int dmrg_diag_H(dmrg_plan_t *p, double *diag, void *stream);
 
+/* Davidson solve for the lowest eigenpair of H_eff (paper, Sec. II: the
+ * effective Hamiltonian is diagonalised iteratively by Lanczos or Davidson).
+ * Single-problem plans.  psi: device array, in = starting vector, out =
+ * normalised Ritz vector; evals: host, out = Ritz value.  Block size 1,
+ * thick restart to the current and previous Ritz vectors at m_max, two-pass
+ * Gram-Schmidt, correction -r/(diag - theta) with |diag - theta| >= floor,
+ * stop when ||H u - theta u||_2 <= tol.  Returns DMRG_ENOCONV (with the best
+ * pair in psi/evals) when max_iter is reached.  All vector work runs on the
+ * GPU in FP64; the m x m projected problem is solved on the host. */
+typedef struct {
+  double tol;               /* residual-norm tolerance, e.g. 1e-8            */
+  int32_t max_iter;
+  int32_t m_max;            /* subspace size, 3..64 (24 by default)         */
+  int32_t precond;          /* 0: diagonal                                   */
+  double floor;             /* preconditioner denominator floor, e.g. 1e-8   */
+  int64_t reserved;
+} dmrg_dav_opts_t;
+typedef struct {
+  int32_t iters, n_hpsi, converged, fallbacks;
+  double residual, energy;
+  double t_total_s, t_hpsi_s;
+} dmrg_dav_stats_t;
+int dmrg_davidson(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts_t *o,
+                  dmrg_dav_stats_t *st, void *stream);
+
 int dmrg_plan_stats(const dmrg_plan_t *p, dmrg_plan_stats_t *st);
 
 /* Profiling: when on, dmrg_apply_H records a hipEvent pair on its stream
@@ -151,9 +181,9 @@ int dmrg_debug_host_apply(const dmrg_problem_t *prob, const double *psi, double 
                           dmrg_plan_stats_t *st);
 /* Test-only: build the device plan's tile and segment lists for one problem
  * with HOST operator data and execute them on the CPU with the kernels'
- * addressing.  Never used by dmrg_apply_H. */
+ * addressing (psi or y NULL: only fill *st).  Never used by dmrg_apply_H. */
 int dmrg_debug_plan_host_apply(const dmrg_problem_t *prob, const double *psi, double *y,
-                               int64_t workspace_bytes);
+                               int64_t workspace_bytes, dmrg_plan_stats_t *st);
 
 #ifdef __cplusplus
 }

@@ -40,6 +40,19 @@ class PlanOpts(ctypes.Structure):
                 ("flags", c_i32)]
 
 
+class DavOpts(ctypes.Structure):
+    _fields_ = [("tol", c_dbl), ("max_iter", c_i32), ("m_max", c_i32), ("precond", c_i32),
+                ("floor", c_dbl), ("reserved", c_i64)]
+
+
+class DavStats(ctypes.Structure):
+    _fields_ = [("iters", c_i32), ("n_hpsi", c_i32), ("converged", c_i32), ("fallbacks", c_i32),
+                ("residual", c_dbl), ("energy", c_dbl), ("t_total_s", c_dbl), ("t_hpsi_s", c_dbl)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class PlanStats(ctypes.Structure):
     _fields_ = [("psi_len", c_i64), ("n_blocks", c_i64), ("n_rows", c_i64), ("n_tasks", c_i64),
                 ("n_stage1", c_i64), ("n_segments", c_i64), ("flops", c_dbl),
@@ -83,10 +96,13 @@ def load(path=None):
         L.dmrg_plan_stats.argtypes = [c_vp, ctypes.POINTER(PlanStats)]
         L.dmrg_plan_free.argtypes = [c_vp]
         L.dmrg_plan_free.restype = None
+        L.dmrg_davidson.argtypes = [c_vp, c_vp, ctypes.POINTER(c_dbl), ctypes.POINTER(DavOpts),
+                                    ctypes.POINTER(DavStats), c_vp]
         L.dmrg_set_profiling.argtypes = [c_vp, c_i32]
         L.dmrg_get_profile.argtypes = [c_vp, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_dbl),
                                        ctypes.POINTER(c_dbl)]
-        L.dmrg_debug_plan_host_apply.argtypes = [ctypes.POINTER(ProblemT), c_vp, c_vp, c_i64]
+        L.dmrg_debug_plan_host_apply.argtypes = [ctypes.POINTER(ProblemT), c_vp, c_vp, c_i64,
+                                                 ctypes.POINTER(PlanStats)]
     if path is None:
         _lib = L
     return L
@@ -122,16 +138,23 @@ class ProblemArgs:
 
 
 def debug_plan_host_apply(prob, psi, workspace_bytes=0, lib=None):
-    """Test-only: run the device plan's tile lists on the CPU (no GPU)."""
+    """Test-only: run the device plan's tile lists on the CPU (no GPU).
+
+    ``psi=None`` only builds the plan and returns its statistics."""
     L = lib or load()
     ld = np.ascontiguousarray(prob.left.data)
     rd = np.ascontiguousarray(prob.right.data)
     args = ProblemArgs(prob, ld.ctypes.data, rd.ctypes.data)
+    st = PlanStats()
+    if psi is None:
+        check(L.dmrg_debug_plan_host_apply(ctypes.byref(args.s), None, None, workspace_bytes,
+                                           ctypes.byref(st)), L)
+        return None, st.as_dict()
     x = np.ascontiguousarray(psi, dtype=np.float64)
     y = np.zeros_like(x)
     check(L.dmrg_debug_plan_host_apply(ctypes.byref(args.s), x.ctypes.data, y.ctypes.data,
-                                       workspace_bytes), L)
-    return y
+                                       workspace_bytes, ctypes.byref(st)), L)
+    return y, st.as_dict()
 
 
 def debug_host_apply(prob, psi, lib=None):

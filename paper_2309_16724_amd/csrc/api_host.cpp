@@ -45,6 +45,8 @@ extern "C" int dmrg_debug_host_apply(const dmrg_problem_t *prob, const double *p
     Error err{0, ""};
     if (build_tasks_for_problem(*prob, L, R, T, err)) { set_error(err.msg); return err.code; }
     std::memset(y, 0, sizeof(double) * T.size);
+    std::vector<double> dressed;
+    dress_on_host(T, R, dressed);
     std::vector<double> T1;
     int64_t ntask = 0;
     for (const Task &tk : T.tasks) {
@@ -61,7 +63,9 @@ extern "C" int dmrg_debug_host_apply(const dmrg_problem_t *prob, const double *p
         if (tk.recD >= 0) {
           const dmrg_oprec_t &r = R.rec[tk.recD];
           int rows = R.sec[r.row_sec].dim, cols = R.sec[r.col_sec].dim;
-          const double *D = R.data + r.off + (int64_t)pa.pD * rows * cols;
+          const double *D = tk.dress >= 0
+                                ? dressed.data() + T.dress[tk.dress].off + (int64_t)pa.pD * rows * cols
+                                : R.data + r.off + (int64_t)pa.pD * rows * cols;
           T1.assign((size_t)E.dL * F.dR, 0.0);
           if (!tk.adjD) gemm_ref(E.dL, F.dR, E.dR, 1.0, X, E.dL, false, D, rows, true, T1.data(), E.dL);
           else gemm_ref(E.dL, F.dR, E.dR, 1.0, X, E.dL, false, D, rows, false, T1.data(), E.dL);

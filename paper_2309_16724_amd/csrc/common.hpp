@@ -131,6 +131,21 @@ struct Task {
   int recA, recD;      // records, -1 for identity
   int adjA, adjD;
   double v;            // sector value incl. site elements, C~ factors, signs
+  int dress = -1;      // >= 0: D comes from dressed record `dress` (positions j)
+};
+
+// A dressed right-block record: for operator-table rows with two position
+// indices (one per block) the sum over the right-block index is done once,
+//   Dt[j] = sum_t alpha_t D[rec][pD_t]  for the t belonging to left position j,
+// turning sum_{i,k} alpha_ik A_i X D_k^T into sum_i A_i X Dt_i^T.
+struct Dress {
+  int rec = 0;                 // source record of the right block
+  int rows = 0, cols = 0;      // block shape (same as the source record)
+  int npos = 0;                // dressed positions (distinct left positions)
+  std::vector<int> start;      // [npos+1] ranges into src_pos / src_alpha
+  std::vector<int> src_pos;
+  std::vector<double> src_alpha;
+  int64_t off = 0;             // offset in the dressed-data array
 };
 
 struct Tasks {
@@ -140,7 +155,12 @@ struct Tasks {
   std::vector<Task> tasks;
   SiteAlgebra site;
   double flops = 0.0;
+  std::vector<Dress> dress;
+  int64_t dress_len = 0;       // elements of the dressed-data array
 };
+
+// host evaluation of the dressed records (test paths); out has dress_len entries
+void dress_on_host(const Tasks &T, const BlockModel &R, std::vector<double> &out);
 
 int build_tasks_for_problem(const dmrg_problem_t &pr, BlockModel &L, BlockModel &R,
                             Tasks &T, Error &err);

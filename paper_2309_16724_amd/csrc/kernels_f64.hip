@@ -1,11 +1,15 @@
 // FP64 MFMA kernels for the grouped stripe products of H.psi.
 //
-// Every H.psi is two launches of the same tile kernel: the first computes
-// T = X op(D) for each wavefunction block and right-block operator and
-// writes it as a vertical stripe over positions; the second accumulates
-// Y_F += v A_stripe T_stripe for every output block F (output stationary: a
-// tile owns its outputs, no atomics).  One wavefront computes a 32x32 tile
-// as 2x2 v_mfma_f64_16x16x4 products, operands staged through LDS.
+// Every H.psi is two launches of one work-item routine.  The first stage
+// computes, for each wavefunction block X and run of right-block operator
+// positions, T = X [op(D_1) ... op(D_c)] (positions concatenated along N).
+// The second stage accumulates Y_F += sum v [A_1 ... A_c] [T_1; ...; T_c] for
+// every output block F.  Output tiles are owned by work items; a tile whose
+// segment list is long is split into parts (split K) that write partial
+// tiles, summed afterwards in a fixed order, so no atomics are used and the
+// result is bitwise reproducible.  A wavefront handles one work item: a
+// (16 mb) x (64/mb) tile as mb x (4/mb) v_mfma_f64_16x16x4 products with
+// operands loaded into registers one K step ahead.
 // Lane layout of v_mfma_f64_16x16x4f64 (lane l, accumulator element r):
 // A[l%16][l/16], B[l/16][l%16], D[l/16 + 4r][l%16].
 #include <hip/hip_runtime.h>
@@ -16,99 +20,140 @@ namespace dmrg {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ const double *base_ptr(int id, const double *const *bases, const double *psi,
-                                                  const double *y, const double *work) {
-  return id == BASE_PSI ? psi : id == BASE_Y ? y : id == BASE_WORK ? work : bases[id - BASE_OPS];
+                                                  const double *y, const double *work, const double *part) {
+  return id == BASE_PSI ? psi : id == BASE_Y ? y : id == BASE_WORK ? work : id == BASE_PART ? part
+                                                                                             : bases[id - BASE_OPS];
 }
 
-__device__ __forceinline__ void tiles_f64(const Tile *__restrict__ tiles, const Seg *__restrict__ segs,
-                                          int ntiles, const double *const *__restrict__ bases,
-                                          const double *__restrict__ psi, double *__restrict__ y,
-                                          double *__restrict__ work) {
-  __shared__ double As[TILE][17];
-  __shared__ double Bs[16][TILE + 1];
-  const int lane = threadIdx.x;
-  const int r16 = lane & 15, q4 = lane >> 4;
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const Tile T = tiles[t];
-    v4d acc[2][2];
-    for (int a = 0; a < 2; a++)
-      for (int b = 0; b < 2; b++) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
-    const int mrem = T.m - T.i0, nrem = T.n - T.j0;
-    for (int si = 0; si < T.nseg; si++) {
-      const Seg S = segs[T.seg0 + si];
-      const double *B = base_ptr(S.b_base, bases, psi, y, work) + S.b_off;
-      if (S.a_base < 0) {
-        // identity left operator: tile += s * B (B has the tile's row count)
-        for (int bi = 0; bi < 2; bi++)
-          for (int bj = 0; bj < 2; bj++)
-            for (int r = 0; r < 4; r++) {
-              int i = 16 * bi + q4 + 4 * r, j = 16 * bj + r16;
-              if (i < mrem && j < nrem)
-                acc[bi][bj][r] += S.s * B[(int64_t)(T.i0 + i) * S.b_k + (int64_t)(T.j0 + j) * S.b_j];
-            }
-        continue;
-      }
-      const double *A = base_ptr(S.a_base, bases, psi, y, work) + S.a_off;
-      for (int k0 = 0; k0 < S.K; k0 += 16) {
-        for (int e = lane; e < TILE * 16; e += 64) {
-          int i = e & (TILE - 1), kk = e / TILE;
-          int gi = T.i0 + i, gk = k0 + kk;
-          double v = 0.0;
-          if (i < mrem && gk < S.K) {
-            int p = gk / S.kb, kr = gk - p * S.kb;
-            v = S.s * A[(int64_t)p * S.a_p + (int64_t)gi * S.a_i + (int64_t)kr * S.a_k];
-          }
-          As[i][kk] = v;
-        }
-        for (int e = lane; e < TILE * 16; e += 64) {
-          int kk = e & 15, j = e >> 4;
-          int gk = k0 + kk, gj = T.j0 + j;
-          double v = 0.0;
-          if (j < nrem && gk < S.K) v = B[(int64_t)gk * S.b_k + (int64_t)gj * S.b_j];
-          Bs[kk][j] = v;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < 16; kk += 4) {
-          double a0 = As[r16][kk + q4], a1 = As[r16 + 16][kk + q4];
-          double b0 = Bs[kk + q4][r16], b1 = Bs[kk + q4][r16 + 16];
-          acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-          acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-          acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-          acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-        }
-        __syncthreads();
-      }
+// One work item: tile of MB x NB MFMA blocks (MB * NB == 4).
+template <int MB>
+__device__ __forceinline__ void item_f64(const Tile &T, const Seg *__restrict__ segs, const double *const *bases,
+                                         const double *psi, double *y, double *work, double *part, int r16,
+                                         int q4) {
+  constexpr int NB = 4 / MB;
+  v4d acc[MB][NB];
+  for (int a = 0; a < MB; a++)
+    for (int b = 0; b < NB; b++) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  const int mrem = T.m - T.i0, nrem = T.n - T.j0;
+  for (int si = 0; si < T.nseg; si++) {
+    const Seg S = segs[T.seg0 + si];
+    const double *B = base_ptr(S.b_base, bases, psi, y, work, part) + S.b_off;
+    int64_t boff[NB];
+    bool bok[NB];
+    for (int bj = 0; bj < NB; bj++) {
+      int n = T.j0 + 16 * bj + r16;
+      bok[bj] = (16 * bj + r16) < nrem;
+      int pn = bok[bj] ? n / S.b_nb : 0;
+      boff[bj] = (int64_t)pn * S.b_pn + (int64_t)(n - pn * S.b_nb) * S.b_n;
     }
-    double *C = const_cast<double *>(base_ptr(T.c_base, bases, psi, y, work)) + T.c_off;
-    for (int bi = 0; bi < 2; bi++)
-      for (int bj = 0; bj < 2; bj++)
-        for (int r = 0; r < 4; r++) {
-          int i = 16 * bi + q4 + 4 * r, j = 16 * bj + r16;
-          if (i < mrem && j < nrem) {
-            double *c = C + (int64_t)(T.i0 + i) + (int64_t)(T.j0 + j) * T.ldc;
-            *c = T.accumulate ? *c + acc[bi][bj][r] : acc[bi][bj][r];
+    if (S.a_base < 0) {
+      // identity left operator: tile += s * B restricted to the tile (K == rows)
+      for (int bi = 0; bi < MB; bi++)
+        for (int bj = 0; bj < NB; bj++)
+          for (int r = 0; r < 4; r++) {
+            int i = 16 * bi + q4 + 4 * r;
+            if (i < mrem && bok[bj]) {
+              int k = T.i0 + i;
+              int pk = k / S.b_kb;
+              acc[bi][bj][r] += S.s * B[(int64_t)pk * S.b_pk + (int64_t)(k - pk * S.b_kb) * S.b_k + boff[bj]];
+            }
           }
+      continue;
+    }
+    const double *A = base_ptr(S.a_base, bases, psi, y, work, part) + S.a_off;
+    int64_t aoff[MB];
+    bool aok[MB];
+    for (int bi = 0; bi < MB; bi++) {
+      aok[bi] = (16 * bi + r16) < mrem;
+      aoff[bi] = aok[bi] ? (int64_t)(T.i0 + 16 * bi + r16) * S.a_i : 0;
+    }
+    const double s = S.s;
+    // the lane's k is k0 + q4: track its (block, offset) for A and B
+    int pa = q4 / S.a_kb, ka = q4 - pa * S.a_kb;
+    int pb = q4 / S.b_kb, kb = q4 - pb * S.b_kb;
+    double an[MB], bn[NB];
+    auto fetch = [&](int k0) {
+      const bool kok = (k0 + q4) < S.K;
+      const int64_t ak = (int64_t)pa * S.a_p + (int64_t)ka * S.a_k;
+      const int64_t bk = (int64_t)pb * S.b_pk + (int64_t)kb * S.b_k;
+      for (int bi = 0; bi < MB; bi++) an[bi] = (kok && aok[bi]) ? A[ak + aoff[bi]] : 0.0;
+      for (int bj = 0; bj < NB; bj++) bn[bj] = (kok && bok[bj]) ? B[bk + boff[bj]] : 0.0;
+      ka += 4;
+      while (ka >= S.a_kb) { ka -= S.a_kb; pa++; }
+      kb += 4;
+      while (kb >= S.b_kb) { kb -= S.b_kb; pb++; }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < S.K; k0 += 4) {
+      double ac[MB], bc[NB];
+      for (int bi = 0; bi < MB; bi++) ac[bi] = s * an[bi];
+      for (int bj = 0; bj < NB; bj++) bc[bj] = bn[bj];
+      if (k0 + 4 < S.K) fetch(k0 + 4);
+      for (int bi = 0; bi < MB; bi++)
+        for (int bj = 0; bj < NB; bj++)
+          acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[bi], bc[bj], acc[bi][bj], 0, 0, 0);
+    }
+  }
+  double *C = const_cast<double *>(base_ptr(T.c_base, bases, psi, y, work, part)) + T.c_off;
+  for (int bi = 0; bi < MB; bi++)
+    for (int bj = 0; bj < NB; bj++)
+      for (int r = 0; r < 4; r++) {
+        int i = 16 * bi + q4 + 4 * r, j = 16 * bj + r16;
+        if (i < mrem && j < nrem) {
+          double *c = C + (int64_t)(T.ci0 + i) + (int64_t)(T.cj0 + j) * T.ldc;
+          *c = T.accumulate ? *c + acc[bi][bj][r] : acc[bi][bj][r];
         }
+      }
+}
+
+__device__ __forceinline__ void items_f64(const Tile *__restrict__ tiles, const Seg *__restrict__ segs, int ntiles,
+                                          const double *const *__restrict__ bases, const double *__restrict__ psi,
+                                          double *__restrict__ y, double *__restrict__ work,
+                                          double *__restrict__ part) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, q4 = lane >> 4;
+  for (int t = blockIdx.x * WAVES + wave; t < ntiles; t += gridDim.x * WAVES) {
+    const Tile T = tiles[t];
+    if (T.mb == 1) item_f64<1>(T, segs, bases, psi, y, work, part, r16, q4);
+    else if (T.mb == 4) item_f64<4>(T, segs, bases, psi, y, work, part, r16, q4);
+    else item_f64<2>(T, segs, bases, psi, y, work, part, r16, q4);
   }
 }
 
 // first stage: T stripes = X op(D)
-__global__ void __launch_bounds__(64) stage1_f64_kernel(const Tile *__restrict__ tiles,
-                                                         const Seg *__restrict__ segs, int ntiles,
-                                                         const double *const *__restrict__ bases,
-                                                         const double *__restrict__ psi,
-                                                         double *__restrict__ y, double *__restrict__ work) {
-  tiles_f64(tiles, segs, ntiles, bases, psi, y, work);
+__global__ void __launch_bounds__(64 * WAVES) stage1_f64_kernel(const Tile *__restrict__ tiles,
+                                                                 const Seg *__restrict__ segs, int ntiles,
+                                                                 const double *const *__restrict__ bases,
+                                                                 const double *__restrict__ psi,
+                                                                 double *__restrict__ y, double *__restrict__ work,
+                                                                 double *__restrict__ part) {
+  items_f64(tiles, segs, ntiles, bases, psi, y, work, part);
 }
 
-// second stage: Y_F += sum v A_stripe T_stripe (output stationary)
-__global__ void __launch_bounds__(64) stage2_f64_kernel(const Tile *__restrict__ tiles,
-                                                         const Seg *__restrict__ segs, int ntiles,
-                                                         const double *const *__restrict__ bases,
-                                                         const double *__restrict__ psi,
-                                                         double *__restrict__ y, double *__restrict__ work) {
-  tiles_f64(tiles, segs, ntiles, bases, psi, y, work);
+// second stage: Y_F += sum v A_stripe T_stripe (work items write Y or a partial tile)
+__global__ void __launch_bounds__(64 * WAVES) stage2_f64_kernel(const Tile *__restrict__ tiles,
+                                                                 const Seg *__restrict__ segs, int ntiles,
+                                                                 const double *const *__restrict__ bases,
+                                                                 const double *__restrict__ psi,
+                                                                 double *__restrict__ y, double *__restrict__ work,
+                                                                 double *__restrict__ part) {
+  items_f64(tiles, segs, ntiles, bases, psi, y, work, part);
+}
+
+// Y tile += sum of its partial tiles, in part order
+__global__ void reduce_kernel(const Reduce *__restrict__ red, int nred, const double *__restrict__ part,
+                              double *__restrict__ y) {
+  for (int r = blockIdx.x; r < nred; r += gridDim.x) {
+    const Reduce R = red[r];
+    int mt = min(R.tm, R.m - R.i0);
+    int nt = min(1024 / R.tm, R.n - R.j0);
+    for (int e = threadIdx.x; e < mt * nt; e += blockDim.x) {
+      int i = e % mt, j = e / mt;
+      double v = 0.0;
+      for (int p = 0; p < R.nparts; p++) v += part[R.part_off + (int64_t)p * 1024 + i + (int64_t)j * R.tm];
+      y[R.y_off + (int64_t)(R.i0 + i) + (int64_t)(R.j0 + j) * R.ldc] += v;
+    }
+  }
 }
 
 __global__ void zero_kernel(double *y, int64_t n) {
@@ -136,6 +181,28 @@ __global__ void diag_kernel(const DiagBlock *__restrict__ blocks, const DiagTerm
   }
 }
 
+// dressed right-block operators (once per plan)
+__global__ void dress_kernel(const DressItem *__restrict__ items, int nitems,
+                             const int64_t *__restrict__ src_off, const double *__restrict__ alpha,
+                             const double *const *__restrict__ bases, double *__restrict__ dst) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const DressItem D = items[it];
+    const double *src = bases[D.src_base - BASE_OPS];
+    for (int64_t e = threadIdx.x; e < D.n; e += blockDim.x) {
+      double acc = 0.0;
+      for (int t = D.t0; t < D.t1; t++) acc += alpha[t] * src[src_off[t] + e];
+      dst[D.dst_off + e] = acc;
+    }
+  }
+}
+
+void launch_dress(const DressItem *items, int nitems, const int64_t *src_off, const double *alpha,
+                  const double *const *bases, double *dst, void *stream) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL(dress_kernel, dim3(std::min(nitems, 8192)), dim3(256), 0, (hipStream_t)stream, items,
+                     nitems, src_off, alpha, bases, dst);
+}
+
 void launch_zero(double *y, int64_t n, void *stream) {
   if (n <= 0) return;
   int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
@@ -143,15 +210,21 @@ void launch_zero(double *y, int64_t n, void *stream) {
 }
 
 void launch_tiles_f64(int stage, const Tile *tiles, const Seg *segs, int ntiles, const double *const *bases,
-                      const double *psi, double *y, double *work, void *stream) {
+                      const double *psi, double *y, double *work, double *part, void *stream) {
   if (ntiles <= 0) return;
-  int grid = std::min(ntiles, 256 * 16);
+  int grid = std::min((ntiles + WAVES - 1) / WAVES, 256 * 16);
   if (stage == 1)
-    hipLaunchKernelGGL(stage1_f64_kernel, dim3(grid), dim3(64), 0, (hipStream_t)stream, tiles, segs,
-                       ntiles, bases, psi, y, work);
+    hipLaunchKernelGGL(stage1_f64_kernel, dim3(grid), dim3(64 * WAVES), 0, (hipStream_t)stream, tiles, segs,
+                       ntiles, bases, psi, y, work, part);
   else
-    hipLaunchKernelGGL(stage2_f64_kernel, dim3(grid), dim3(64), 0, (hipStream_t)stream, tiles, segs,
-                       ntiles, bases, psi, y, work);
+    hipLaunchKernelGGL(stage2_f64_kernel, dim3(grid), dim3(64 * WAVES), 0, (hipStream_t)stream, tiles, segs,
+                       ntiles, bases, psi, y, work, part);
+}
+
+void launch_reduce(const Reduce *red, int nred, const double *part, double *y, void *stream) {
+  if (nred <= 0) return;
+  hipLaunchKernelGGL(reduce_kernel, dim3(std::min(nred, 8192)), dim3(256), 0, (hipStream_t)stream, red, nred,
+                     part, y);
 }
 
 void launch_diag(const DiagBlock *blocks, const DiagTerm *terms, int nblocks, const double *const *bases,

@@ -23,22 +23,31 @@ static std::vector<std::array<int, 2>> family_labels(int fam, int role, int L, i
   if (role == 0) for (int x = p; x < L; x++) out.push_back(x);
   else for (int x = 0; x < p + 2; x++) out.push_back(x);
   std::vector<std::array<int, 2>> res;
+  // grouped pair order: x<y inside, (x,x) inside, then (x,p), (x,p+1) and site pairs
+  auto grouped = [&](int a, int b, bool strict, bool sites) {
+    for (int x = a; x < b; x++) for (int y = x + 1; y < b; y++) res.push_back({x, y});
+    if (!strict) for (int x = a; x < b; x++) res.push_back({x, x});
+    if (sites) {
+      for (int x = a; x < b; x++) res.push_back({x, p});
+      for (int x = a; x < b; x++) res.push_back({x, p + 1});
+      if (!strict) res.push_back({p, p});
+      res.push_back({p, p + 1});
+      if (!strict) res.push_back({p + 1, p + 1});
+    }
+  };
   switch (fam) {
     case F_H: res.push_back({-1, -1}); break;
     case F_C: for (int i = lo; i < hi; i++) res.push_back({i, -1}); break;
-    case F_A0: case F_B0: case F_B1:
-      for (int i = lo; i < hi; i++) for (int j = i; j < hi; j++) res.push_back({i, j});
-      break;
-    case F_A1:
-      for (int i = lo; i < hi; i++) for (int j = i + 1; j < hi; j++) res.push_back({i, j});
-      break;
+    case F_A0: case F_B0: case F_B1: grouped(lo, hi, false, false); break;
+    case F_A1: grouped(lo, hi, true, false); break;
     case F_S: for (int x : out) res.push_back({x, -1}); break;
     default: {
       bool strict = fam == F_P1;
+      if (role == 1) { grouped(0, p, strict, true); break; }
       for (int x : out)
         for (int y : out) {
           if (strict ? !(x < y) : !(x <= y)) continue;
-          if (role == 0 && x >= p + 2 && y >= p + 2) continue;
+          if (x >= p + 2 && y >= p + 2) continue;
           res.push_back({x, y});
         }
     }
@@ -685,6 +694,26 @@ int build_tasks_for_problem(const dmrg_problem_t &pr, BlockModel &L, BlockModel 
     const auto &b = T.blocks[i];
     bidx[{b.iL, b.l, b.SLl, b.r, b.iR, b.SrR}] = (int)i;
   }
+  // rows with two position indices: keep, per left position, its list of
+  // (right position, alpha); the row then runs over left positions only
+  std::vector<std::vector<std::pair<int, std::vector<std::pair<int, double>>>>> dress_src(T.rows.size());
+  for (size_t ri = 0; ri < T.rows.size(); ri++) {
+    Row &row = T.rows[ri];
+    std::map<int, std::vector<std::pair<int, double>>> byA;
+    for (auto &pa : row.pos) byA[pa.pA].push_back({pa.pD, pa.alpha});
+    if (byA.size() == row.pos.size()) continue;      // one right position per left one
+    if (row.key.t[3].kind != 1) continue;             // identity on the right: nothing to sum
+    std::vector<PosAlpha> np;
+    int j = 0;
+    for (auto &kv : byA) {
+      np.push_back({kv.first, j++, 1.0});
+      dress_src[ri].push_back({kv.first, kv.second});
+    }
+    row.pos = np;
+  }
+  std::map<std::pair<int, int>, int> dress_of;   // (row, source record) -> dressed record
+  T.dress.clear();
+  T.dress_len = 0;
   CtildeTable wl, wr, wh;
   T.tasks.clear();
   T.flops = 0.0;
@@ -755,6 +784,31 @@ int build_tasks_for_problem(const dmrg_problem_t &pr, BlockModel &L, BlockModel 
                   tk.adjA = tA.adj;
                   tk.adjD = tD.adj;
                   tk.v = v;
+                  if (!dress_src[ri].empty() && tk.recD >= 0) {
+                    auto key = std::make_pair((int)ri, tk.recD);
+                    auto dit = dress_of.find(key);
+                    if (dit == dress_of.end()) {
+                      Dress d;
+                      d.rec = tk.recD;
+                      const dmrg_oprec_t &rr = R.rec[tk.recD];
+                      d.rows = R.sec[rr.row_sec].dim;
+                      d.cols = R.sec[rr.col_sec].dim;
+                      d.npos = (int)dress_src[ri].size();
+                      d.start.push_back(0);
+                      for (auto &e : dress_src[ri]) {
+                        for (auto &pa : e.second) {
+                          d.src_pos.push_back(pa.first);
+                          d.src_alpha.push_back(pa.second);
+                        }
+                        d.start.push_back((int)d.src_pos.size());
+                      }
+                      d.off = T.dress_len;
+                      T.dress_len += (int64_t)d.npos * d.rows * d.cols;
+                      dit = dress_of.emplace(key, (int)T.dress.size()).first;
+                      T.dress.push_back(std::move(d));
+                    }
+                    tk.dress = dit->second;
+                  }
                   T.tasks.push_back(tk);
                   const PsiBlock &Fb = T.blocks[tk.F];
                   double npos = (double)row.pos.size();
@@ -766,6 +820,20 @@ int build_tasks_for_problem(const dmrg_problem_t &pr, BlockModel &L, BlockModel 
     }
   }
   return DMRG_OK;
+}
+
+void dress_on_host(const Tasks &T, const BlockModel &R, std::vector<double> &out) {
+  out.assign((size_t)std::max<int64_t>(T.dress_len, 1), 0.0);
+  for (const Dress &d : T.dress) {
+    const dmrg_oprec_t &r = R.rec[d.rec];
+    int64_t bs = (int64_t)d.rows * d.cols;
+    for (int j = 0; j < d.npos; j++)
+      for (int t = d.start[j]; t < d.start[j + 1]; t++) {
+        const double *src = R.data + r.off + (int64_t)d.src_pos[t] * bs;
+        double *dst = out.data() + d.off + (int64_t)j * bs;
+        for (int64_t e = 0; e < bs; e++) dst[e] += d.src_alpha[t] * src[e];
+      }
+  }
 }
 
 }  // namespace dmrg

@@ -15,7 +15,9 @@ struct ProbPlan {
   BlockModel L, R;
   Tasks T;
   int64_t psi_off = 0;
-  int base_l = 0, base_r = 0;
+  int base_l = 0, base_r = 0, base_dress = 0;
+  double *d_dress = nullptr;          // dressed right-block data (device)
+  std::vector<double> h_dress;        // host copy (test paths only)
 };
 
 }  // namespace
@@ -27,6 +29,8 @@ struct dmrg_plan {
   const double **d_bases = nullptr;
   double *d_work = nullptr;
   int64_t work_elems = 0;
+  double *d_part = nullptr;
+  int64_t part_elems = 0;
   std::vector<Chunk> chunks;
   std::vector<DiagBlock> dblocks;
   std::vector<DiagTerm> dterms;
@@ -70,9 +74,9 @@ int upload(dmrg_plan *p, const std::vector<T> &v, T **out) {
 }
 
 struct StripeKey {
-  int prob, E, rec, adj;
+  int prob, E, rec, adj, dress;
   bool operator<(const StripeKey &o) const {
-    return std::tie(prob, E, rec, adj) < std::tie(o.prob, o.E, o.rec, o.adj);
+    return std::tie(prob, E, rec, adj, dress) < std::tie(o.prob, o.E, o.rec, o.adj, o.dress);
   }
 };
 
@@ -84,6 +88,14 @@ struct Stripe {
 
 struct TaskRef { int prob; int task; };
 
+// MFMA row blocks of the tiles of an m x n output: skinny outputs get 16x64 or
+// 64x16 tiles, the rest 32x32
+int tile_mb(int m, int n) {
+  if (m <= 16) return 1;
+  if (n <= 16) return 4;
+  return 2;
+}
+
 int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
   // ---- split tasks into chunks whose stripes fit the workspace budget
   std::vector<std::vector<TaskRef>> chunk_tasks(1);
@@ -94,7 +106,7 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
     for (int ti = 0; ti < (int)T.tasks.size(); ti++) {
       const Task &tk = T.tasks[ti];
       int64_t add = 0;
-      StripeKey key{k, tk.E, tk.recD, tk.adjD};
+      StripeKey key{k, tk.E, tk.recD, tk.adjD, tk.dress};
       if (tk.recD >= 0) {
         const PsiBlock &E = T.blocks[tk.E], &F = T.blocks[tk.F];
         auto it = cur.find(key);
@@ -126,7 +138,7 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
       const Tasks &T = P->probs[r.prob]->T;
       const Task &tk = T.tasks[r.task];
       if (tk.recD < 0) continue;
-      StripeKey key{r.prob, tk.E, tk.recD, tk.adjD};
+      StripeKey key{r.prob, tk.E, tk.recD, tk.adjD, tk.dress};
       Stripe &s = stripes[key];
       s.dL = T.blocks[tk.E].dL;
       s.dRin = T.blocks[tk.E].dR;
@@ -141,37 +153,52 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
       s.off = woff;
       woff += (int64_t)s.dL * s.dRout * s.slots.size();
       woff = (woff + 31) / 32 * 32;
-      // first-stage tiles: T_slot = X_E op(D_pD)
+      // first stage: T_h = X [op(D_s0) ... op(D_s1-1)] for each run of consecutive positions;
+      // slot s of the stripe is the d_L x d_R' block at off + s * d_L * d_R' (column-major)
       const ProbPlan &pp = *P->probs[kv.first.prob];
       const PsiBlock &E = pp.T.blocks[kv.first.E];
       const dmrg_oprec_t &rec = pp.R.rec[kv.first.rec];
       int rows = pp.R.sec[rec.row_sec].dim, cols = pp.R.sec[rec.col_sec].dim;
-      int64_t ldt = (int64_t)s.dL * s.slots.size();
-      for (size_t si = 0; si < s.slots.size(); si++) {
+      size_t s0 = 0;
+      while (s0 < s.slots.size()) {
+        size_t s1 = s0 + 1;
+        while (s1 < s.slots.size() && s.slots[s1] == s.slots[s1 - 1] + 1) s1++;
         Seg g{};
         g.a_base = BASE_PSI;
         g.a_off = pp.psi_off + E.off;
         g.a_p = 0; g.a_i = 1; g.a_k = s.dL;
-        g.K = s.dRin; g.kb = s.dRin;
-        g.b_base = pp.base_r;
-        g.b_off = rec.off + (int64_t)s.slots[si] * rows * cols;
-        if (!kv.first.adj) { g.b_k = rows; g.b_j = 1; }     // stored D is dR' x dR
-        else { g.b_k = 1; g.b_j = rows; }                   // stored D is dR x dR'
+        g.K = s.dRin; g.a_kb = s.dRin;
+        if (kv.first.dress >= 0) {
+          g.b_base = pp.base_dress;
+          g.b_off = pp.T.dress[kv.first.dress].off + (int64_t)s.slots[s0] * rows * cols;
+        } else {
+          g.b_base = pp.base_r;
+          g.b_off = rec.off + (int64_t)s.slots[s0] * rows * cols;
+        }
+        g.b_kb = s.dRin; g.b_pk = 0;
+        g.b_nb = s.dRout; g.b_pn = (int64_t)rows * cols;
+        if (!kv.first.adj) { g.b_k = rows; g.b_n = 1; }     // op(D) = D^T, stored d_R' x d_R
+        else { g.b_k = 1; g.b_n = rows; }                   // op(D) = D,   stored d_R x d_R'
         g.s = 1.0;
         int sidx = (int)ch.seg1.size();
         ch.seg1.push_back(g);
-        P->stats.stage1_flops += 2.0 * s.dL * s.dRin * s.dRout;
-        ch.flops1 += 2.0 * s.dL * s.dRin * s.dRout;
-        for (int i0 = 0; i0 < s.dL; i0 += TILE)
-          for (int j0 = 0; j0 < s.dRout; j0 += TILE) {
+        int N = (int)(s1 - s0) * s.dRout;
+        double fl = 2.0 * s.dL * s.dRin * N;
+        P->stats.stage1_flops += fl;
+        ch.flops1 += fl;
+        int mb = tile_mb(s.dL, N);
+        for (int i0 = 0; i0 < s.dL; i0 += 16 * mb)
+          for (int j0 = 0; j0 < N; j0 += 64 / mb) {
             Tile t{};
             t.c_base = BASE_WORK;
-            t.c_off = s.off + (int64_t)si * s.dL;
-            t.ldc = ldt;
-            t.m = s.dL; t.n = s.dRout; t.i0 = i0; t.j0 = j0;
+            t.c_off = s.off + (int64_t)s0 * s.dL * s.dRout;
+            t.ldc = s.dL;
+            t.m = s.dL; t.n = N; t.i0 = i0; t.j0 = j0; t.ci0 = i0; t.cj0 = j0;
+            t.mb = mb;
             t.seg0 = sidx; t.nseg = 1; t.accumulate = 0;
             ch.tile1.push_back(t);
           }
+        s0 = s1;
       }
     }
     max_work = std::max(max_work, woff);
@@ -184,7 +211,7 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
       const PsiBlock &E = T.blocks[tk.E], &F = T.blocks[tk.F];
       const Row &row = T.rows[tk.row];
       const Stripe *st = nullptr;
-      if (tk.recD >= 0) st = &stripes.at(StripeKey{r.prob, tk.E, tk.recD, tk.adjD});
+      if (tk.recD >= 0) st = &stripes.at(StripeKey{r.prob, tk.E, tk.recD, tk.adjD, tk.dress});
       auto slot_of = [&](int pD) {
         return (int)(std::lower_bound(st->slots.begin(), st->slots.end(), pD) - st->slots.begin());
       };
@@ -208,56 +235,116 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
         Seg g{};
         g.s = tk.v * row.pos[q].alpha;
         if (st) {
+          // B = [T_s; T_s+1; ...]: slot s of the stripe at s * d_L * d_R'
           g.b_base = BASE_WORK;
-          g.b_off = st->off + (int64_t)slot_of(row.pos[q].pD) * E.dL;
+          g.b_off = st->off + (int64_t)slot_of(row.pos[q].pD) * E.dL * F.dR;
+          g.b_kb = E.dL;
+          g.b_pk = (int64_t)E.dL * F.dR;
           g.b_k = 1;
-          g.b_j = (int64_t)E.dL * st->slots.size();
         } else {
           g.b_base = BASE_PSI;
           g.b_off = pp.psi_off + E.off;
+          g.b_kb = E.dL;
+          g.b_pk = 0;
           g.b_k = 1;
-          g.b_j = E.dL;
         }
+        g.b_nb = F.dR; g.b_pn = 0; g.b_n = E.dL;
         if (tk.recA >= 0) {
           g.a_base = pp.base_l;
           g.a_off = recoffA + (int64_t)row.pos[q].pA * rowsA * colsA;
           g.a_p = (int64_t)rowsA * colsA;
-          if (!tk.adjA) { g.a_i = 1; g.a_k = rowsA; }    // stored A is dL' x dL
-          else { g.a_i = rowsA; g.a_k = 1; }             // stored A is dL x dL'
-          g.kb = E.dL;
+          if (!tk.adjA) { g.a_i = 1; g.a_k = rowsA; }    // stored A is d_L' x d_L
+          else { g.a_i = rowsA; g.a_k = 1; }             // stored A is d_L x d_L'
+          g.a_kb = E.dL;
           g.K = run * E.dL;
           P->stats.stage2_flops += 2.0 * F.dL * g.K * F.dR;
           ch.flops2 += 2.0 * F.dL * g.K * F.dR;
         } else {
           g.a_base = -1;
           g.K = E.dL;
-          g.kb = E.dL;
+          g.a_kb = E.dL;
         }
         segs.push_back(g);
         q = q1;
       }
     }
     std::vector<std::pair<double, Tile>> tiles2;
+    int64_t nslot = 0;
     for (auto &kv : byF) {
       const ProbPlan &pp = *P->probs[kv.first.first];
       const PsiBlock &F = pp.T.blocks[kv.first.second];
-      int seg0 = (int)ch.seg2.size();
-      double kcost = 0.0;
+      // pieces of at most KPART along K, cut at position boundaries
+      std::vector<Seg> pieces;
       for (auto &g : kv.second) {
-        ch.seg2.push_back(g);
-        kcost += g.a_base < 0 ? 1.0 : (double)g.K;
+        if (g.a_base < 0 || g.K <= KPART) { pieces.push_back(g); continue; }
+        int npos = g.K / g.a_kb;
+        int per = std::max(1, KPART / g.a_kb);
+        for (int p0 = 0; p0 < npos; p0 += per) {
+          int p1 = std::min(npos, p0 + per);
+          Seg h = g;
+          h.a_off += (int64_t)p0 * g.a_p;
+          h.b_off += (int64_t)p0 * g.b_pk;
+          h.K = (p1 - p0) * g.a_kb;
+          pieces.push_back(h);
+        }
       }
-      for (int i0 = 0; i0 < F.dL; i0 += TILE)
-        for (int j0 = 0; j0 < F.dR; j0 += TILE) {
+      // parts: consecutive pieces with summed K up to KPART (identity pieces count as d_L)
+      std::vector<std::pair<int, int>> parts;   // [begin, end) into pieces
+      std::vector<double> pcost;
+      int b0 = 0;
+      double cost = 0.0;
+      for (int i = 0; i < (int)pieces.size(); i++) {
+        double c = pieces[i].a_base < 0 ? 0.25 * pieces[i].K : (double)pieces[i].K;
+        if (i > b0 && cost + c > KPART) {
+          parts.push_back({b0, i});
+          pcost.push_back(cost);
+          b0 = i;
+          cost = 0.0;
+        }
+        cost += c;
+      }
+      parts.push_back({b0, (int)pieces.size()});
+      pcost.push_back(cost);
+      int seg0 = (int)ch.seg2.size();
+      for (auto &g : pieces) ch.seg2.push_back(g);
+      int mb = tile_mb(F.dL, F.dR);
+      int tm = 16 * mb, tn = 64 / mb;
+      for (int i0 = 0; i0 < F.dL; i0 += tm)
+        for (int j0 = 0; j0 < F.dR; j0 += tn) {
           Tile t{};
-          t.c_base = BASE_Y;
-          t.c_off = pp.psi_off + F.off;
-          t.ldc = F.dL;
-          t.m = F.dL; t.n = F.dR; t.i0 = i0; t.j0 = j0;
-          t.seg0 = seg0; t.nseg = (int)kv.second.size(); t.accumulate = 1;
-          tiles2.push_back({kcost, t});
+          t.m = F.dL; t.n = F.dR; t.i0 = i0; t.j0 = j0; t.mb = mb;
+          if (parts.size() == 1) {
+            t.c_base = BASE_Y;
+            t.c_off = pp.psi_off + F.off;
+            t.ldc = F.dL;
+            t.ci0 = i0; t.cj0 = j0;
+            t.seg0 = seg0; t.nseg = (int)pieces.size(); t.accumulate = 1;
+            tiles2.push_back({pcost[0], t});
+            continue;
+          }
+          Reduce r{};
+          r.y_off = pp.psi_off + F.off;
+          r.ldc = F.dL;
+          r.part_off = nslot * 1024;
+          r.m = F.dL; r.n = F.dR; r.i0 = i0; r.j0 = j0; r.tm = tm;
+          r.nparts = (int)parts.size();
+          ch.red2.push_back(r);
+          for (size_t pi = 0; pi < parts.size(); pi++) {
+            Tile u = t;
+            u.c_base = BASE_PART;
+            u.c_off = (nslot + (int64_t)pi) * 1024;
+            u.ldc = tm;
+            u.ci0 = 0; u.cj0 = 0;
+            u.seg0 = seg0 + parts[pi].first;
+            u.nseg = parts[pi].second - parts[pi].first;
+            u.accumulate = 0;
+            tiles2.push_back({pcost[pi], u});
+          }
+          nslot += (int64_t)parts.size();
         }
     }
+    ch.part_elems = nslot * 1024;
+    P->part_elems = std::max(P->part_elems, ch.part_elems);
     std::stable_sort(tiles2.begin(), tiles2.end(),
                      [](const std::pair<double, Tile> &a, const std::pair<double, Tile> &b) {
                        return a.first > b.first;
@@ -288,8 +375,13 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
         } else d.a_base = -1;
         if (tk.recD >= 0) {
           const dmrg_oprec_t &rd = pp.R.rec[tk.recD];
-          d.d_base = pp.base_r;
-          d.d_off = rd.off + (int64_t)pa.pD * E.dR * E.dR;
+          if (tk.dress >= 0) {
+            d.d_base = pp.base_dress;
+            d.d_off = T.dress[tk.dress].off + (int64_t)pa.pD * E.dR * E.dR;
+          } else {
+            d.d_base = pp.base_r;
+            d.d_off = rd.off + (int64_t)pa.pD * E.dR * E.dR;
+          }
           d.d_step = E.dR + 1;
         } else d.d_base = -1;
         per[tk.E].push_back(d);
@@ -311,13 +403,48 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
   int rc;
   for (auto &ch : P->chunks) {
     if ((rc = upload(P, ch.seg1, &ch.d_seg1)) || (rc = upload(P, ch.seg2, &ch.d_seg2)) ||
-        (rc = upload(P, ch.tile1, &ch.d_tile1)) || (rc = upload(P, ch.tile2, &ch.d_tile2)))
+        (rc = upload(P, ch.tile1, &ch.d_tile1)) || (rc = upload(P, ch.tile2, &ch.d_tile2)) ||
+        (rc = upload(P, ch.red2, &ch.d_red2)))
       return rc;
     P->stats.n_stage1 += (int64_t)ch.seg1.size();
     P->stats.n_segments += (int64_t)ch.seg2.size();
   }
   if ((rc = upload(P, P->dblocks, &P->d_dblocks)) || (rc = upload(P, P->dterms, &P->d_dterms))) return rc;
   if ((rc = upload(P, P->bases_h, (const double ***)&P->d_bases))) return rc;
+  // dressed right-block operators: computed on the device once
+  for (auto &ppu : P->probs) {
+    ProbPlan &pp = *ppu;
+    if (pp.T.dress.empty()) continue;
+    std::vector<DressItem> items;
+    std::vector<int64_t> soff;
+    std::vector<double> alpha;
+    for (const Dress &d : pp.T.dress) {
+      const dmrg_oprec_t &r = pp.R.rec[d.rec];
+      int64_t bs = (int64_t)d.rows * d.cols;
+      for (int j = 0; j < d.npos; j++) {
+        DressItem it{};
+        it.dst_off = d.off + (int64_t)j * bs;
+        it.n = bs;
+        it.t0 = (int)soff.size();
+        for (int t = d.start[j]; t < d.start[j + 1]; t++) {
+          soff.push_back(r.off + (int64_t)d.src_pos[t] * bs);
+          alpha.push_back(d.src_alpha[t]);
+        }
+        it.t1 = (int)soff.size();
+        it.src_base = pp.base_r;
+        it.dst_base = pp.base_dress;
+        items.push_back(it);
+      }
+    }
+    DressItem *d_items = nullptr;
+    int64_t *d_soff = nullptr;
+    double *d_alpha = nullptr;
+    if ((rc = upload(P, items, &d_items)) || (rc = upload(P, soff, &d_soff)) || (rc = upload(P, alpha, &d_alpha)))
+      return rc;
+    launch_dress(d_items, (int)items.size(), d_soff, d_alpha, P->d_bases, pp.d_dress, nullptr);
+    HIPCHK(hipGetLastError());
+  }
+  HIPCHK(hipDeviceSynchronize());
   if (P->work_elems > 0) {
     void *d = nullptr;
     if (hipMalloc(&d, sizeof(double) * P->work_elems) != hipSuccess) {
@@ -326,6 +453,15 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
     }
     P->allocs.push_back(d);
     P->d_work = (double *)d;
+  }
+  if (P->part_elems > 0) {
+    void *d = nullptr;
+    if (hipMalloc(&d, sizeof(double) * P->part_elems) != hipSuccess) {
+      set_error("hipMalloc failed for the partial-tile buffer");
+      return DMRG_ENOMEM;
+    }
+    P->allocs.push_back(d);
+    P->d_part = (double *)d;
   }
   return DMRG_OK;
 }
@@ -371,6 +507,18 @@ extern "C" int dmrg_build_tasks(const dmrg_problem_t *probs, int32_t n_probs, co
       P->bases_h.push_back(probs[k].ldata);
       pp->base_r = BASE_OPS + (int)P->bases_h.size();
       P->bases_h.push_back(probs[k].rdata);
+      pp->base_dress = BASE_OPS + (int)P->bases_h.size();
+      if (pp->T.dress_len > 0) {
+        void *d = nullptr;
+        if (hipMalloc(&d, sizeof(double) * pp->T.dress_len) != hipSuccess) {
+          set_error("hipMalloc failed for dressed operators");
+          dmrg_plan_free(P);
+          return DMRG_ENOMEM;
+        }
+        P->allocs.push_back(d);
+        pp->d_dress = (double *)d;
+      }
+      P->bases_h.push_back(pp->d_dress);
       P->stats.n_blocks += (int64_t)pp->T.blocks.size();
       P->stats.n_rows += (int64_t)pp->T.rows.size();
       for (auto &tk : pp->T.tasks) P->stats.n_tasks += (int64_t)pp->T.rows[tk.row].pos.size();
@@ -420,9 +568,11 @@ extern "C" int dmrg_apply_H(dmrg_plan_t *p, const double *psi, double *hpsi, voi
         HIPCHK(hipEventRecord(p->ev_pool[ev++], (hipStream_t)stream));
       }
       if (stage == 1)
-        launch_tiles_f64(1, ch.d_tile1, ch.d_seg1, (int)ch.tile1.size(), p->d_bases, psi, hpsi, p->d_work, stream);
+        launch_tiles_f64(1, ch.d_tile1, ch.d_seg1, (int)ch.tile1.size(), p->d_bases, psi, hpsi, p->d_work,
+                         p->d_part, stream);
       else
-        launch_tiles_f64(2, ch.d_tile2, ch.d_seg2, (int)ch.tile2.size(), p->d_bases, psi, hpsi, p->d_work, stream);
+        launch_tiles_f64(2, ch.d_tile2, ch.d_seg2, (int)ch.tile2.size(), p->d_bases, psi, hpsi, p->d_work,
+                         p->d_part, stream);
       if (p->profiling) {
         int rc = next_event(p, ev);
         if (rc) return rc;
@@ -432,6 +582,7 @@ extern "C" int dmrg_apply_H(dmrg_plan_t *p, const double *psi, double *hpsi, voi
         ev++;
       }
     }
+    launch_reduce(ch.d_red2, (int)ch.red2.size(), p->d_part, hpsi, stream);
   }
   HIPCHK(hipGetLastError());
   return DMRG_OK;
@@ -485,20 +636,25 @@ extern "C" int dmrg_plan_stats(const dmrg_plan_t *p, dmrg_plan_stats_t *st) {
 // addressing (no GPU use).  Checks the plan layout without a device.
 static void host_tiles(const std::vector<Tile> &tiles, const std::vector<Seg> &segs,
                        const std::vector<const double *> &bases, const double *psi, double *y,
-                       double *work) {
+                       double *work, double *part) {
   auto base = [&](int id) -> const double * {
-    return id == BASE_PSI ? psi : id == BASE_Y ? y : id == BASE_WORK ? work : bases[id - BASE_OPS];
+    return id == BASE_PSI ? psi : id == BASE_Y ? y : id == BASE_WORK ? work : id == BASE_PART ? part
+                                                                                               : bases[id - BASE_OPS];
+  };
+  auto Bel = [](const Seg &S, const double *B, int64_t k, int64_t n) {
+    int64_t pk = k / S.b_kb, pn = n / S.b_nb;
+    return B[pk * S.b_pk + (k - pk * S.b_kb) * S.b_k + pn * S.b_pn + (n - pn * S.b_nb) * S.b_n];
   };
   for (const Tile &T : tiles) {
-    int mt = std::min(TILE, T.m - T.i0), nt = std::min(TILE, T.n - T.j0);
+    int tm = 16 * T.mb, tn = 64 / T.mb;
+    int mt = std::min(tm, T.m - T.i0), nt = std::min(tn, T.n - T.j0);
     std::vector<double> acc((size_t)mt * nt, 0.0);
     for (int si = 0; si < T.nseg; si++) {
       const Seg &S = segs[T.seg0 + si];
       const double *B = base(S.b_base) + S.b_off;
       if (S.a_base < 0) {
         for (int j = 0; j < nt; j++)
-          for (int i = 0; i < mt; i++)
-            acc[i + (size_t)j * mt] += S.s * B[(int64_t)(T.i0 + i) * S.b_k + (int64_t)(T.j0 + j) * S.b_j];
+          for (int i = 0; i < mt; i++) acc[i + (size_t)j * mt] += S.s * Bel(S, B, T.i0 + i, T.j0 + j);
         continue;
       }
       const double *A = base(S.a_base) + S.a_off;
@@ -506,9 +662,9 @@ static void host_tiles(const std::vector<Tile> &tiles, const std::vector<Seg> &s
         for (int i = 0; i < mt; i++) {
           double a = 0.0;
           for (int k = 0; k < S.K; k++) {
-            int p = k / S.kb, kr = k - p * S.kb;
+            int p = k / S.a_kb, kr = k - p * S.a_kb;
             a += S.s * A[(int64_t)p * S.a_p + (int64_t)(T.i0 + i) * S.a_i + (int64_t)kr * S.a_k] *
-                 B[(int64_t)k * S.b_k + (int64_t)(T.j0 + j) * S.b_j];
+                 Bel(S, B, k, T.j0 + j);
           }
           acc[i + (size_t)j * mt] += a;
         }
@@ -516,14 +672,26 @@ static void host_tiles(const std::vector<Tile> &tiles, const std::vector<Seg> &s
     double *C = const_cast<double *>(base(T.c_base)) + T.c_off;
     for (int j = 0; j < nt; j++)
       for (int i = 0; i < mt; i++) {
-        double &c = C[(int64_t)(T.i0 + i) + (int64_t)(T.j0 + j) * T.ldc];
+        double &c = C[(int64_t)(T.ci0 + i) + (int64_t)(T.cj0 + j) * T.ldc];
         c = T.accumulate ? c + acc[i + (size_t)j * mt] : acc[i + (size_t)j * mt];
       }
   }
 }
 
+static void host_reduce(const std::vector<Reduce> &red, const double *part, double *y) {
+  for (const Reduce &R : red) {
+    int mt = std::min(R.tm, R.m - R.i0), nt = std::min(1024 / R.tm, R.n - R.j0);
+    for (int j = 0; j < nt; j++)
+      for (int i = 0; i < mt; i++) {
+        double v = 0.0;
+        for (int p = 0; p < R.nparts; p++) v += part[R.part_off + (int64_t)p * 1024 + i + (int64_t)j * R.tm];
+        y[R.y_off + (int64_t)(R.i0 + i) + (int64_t)(R.j0 + j) * R.ldc] += v;
+      }
+  }
+}
+
 extern "C" int dmrg_debug_plan_host_apply(const dmrg_problem_t *prob, const double *psi, double *y,
-                                          int64_t workspace_bytes) {
+                                          int64_t workspace_bytes, dmrg_plan_stats_t *st) {
   dmrg_plan *P = new dmrg_plan();
   std::memset(&P->stats, 0, sizeof(P->stats));
   auto pp = std::make_unique<ProbPlan>();
@@ -535,18 +703,67 @@ extern "C" int dmrg_debug_plan_host_apply(const dmrg_problem_t *prob, const doub
   }
   pp->base_l = BASE_OPS;
   pp->base_r = BASE_OPS + 1;
-  P->bases_h = {prob->ldata, prob->rdata};
+  pp->base_dress = BASE_OPS + 2;
+  dress_on_host(pp->T, pp->R, pp->h_dress);
+  P->bases_h = {prob->ldata, prob->rdata, pp->h_dress.data()};
   int64_t n = pp->T.size;
+  P->stats.psi_len = n;
+  P->stats.n_blocks = (int64_t)pp->T.blocks.size();
+  P->stats.n_rows = (int64_t)pp->T.rows.size();
+  for (auto &tk : pp->T.tasks) P->stats.n_tasks += (int64_t)pp->T.rows[tk.row].pos.size();
   P->probs.push_back(std::move(pp));
   P->psi_len = n;
   int rc = build_plan(P, workspace_bytes > 0 ? workspace_bytes : ((int64_t)16 << 30), false);
   if (rc) { delete P; return rc; }
+  for (auto &ch : P->chunks) {
+    P->stats.n_stage1 += (int64_t)ch.seg1.size();
+    P->stats.n_segments += (int64_t)ch.seg2.size();
+  }
+  if (st) *st = P->stats;
+  if (!psi || !y) { delete P; return DMRG_OK; }
   std::vector<double> work((size_t)std::max<int64_t>(P->work_elems, 1), 0.0);
+  std::vector<double> part((size_t)std::max<int64_t>(P->part_elems, 1), 0.0);
   std::memset(y, 0, sizeof(double) * n);
   for (auto &ch : P->chunks) {
-    host_tiles(ch.tile1, ch.seg1, P->bases_h, psi, y, work.data());
-    host_tiles(ch.tile2, ch.seg2, P->bases_h, psi, y, work.data());
+    host_tiles(ch.tile1, ch.seg1, P->bases_h, psi, y, work.data(), part.data());
+    host_tiles(ch.tile2, ch.seg2, P->bases_h, psi, y, work.data(), part.data());
+    host_reduce(ch.red2, part.data(), y);
   }
   delete P;
   return DMRG_OK;
+}
+
+// Test-only: per-tile work of one stage of the plan built for `prob` (host
+// operator data): rows of (m, n, number of segments, summed K).
+extern "C" int64_t dmrg_debug_plan_tiles(const dmrg_problem_t *prob, int32_t stage, int64_t *out,
+                                         int64_t cap) {
+  dmrg_plan *P = new dmrg_plan();
+  std::memset(&P->stats, 0, sizeof(P->stats));
+  auto pp = std::make_unique<ProbPlan>();
+  Error err{0, ""};
+  if (build_tasks_for_problem(*prob, pp->L, pp->R, pp->T, err)) { set_error(err.msg); delete P; return err.code; }
+  pp->base_l = BASE_OPS; pp->base_r = BASE_OPS + 1; pp->base_dress = BASE_OPS + 2;
+  P->bases_h = {prob->ldata, prob->rdata, nullptr};
+  P->psi_len = pp->T.size;
+  P->probs.push_back(std::move(pp));
+  int rc = build_plan(P, (int64_t)16 << 30, false);
+  if (rc) { delete P; return rc; }
+  int64_t n = 0;
+  for (auto &ch : P->chunks) {
+    const auto &tiles = stage == 1 ? ch.tile1 : ch.tile2;
+    const auto &segs = stage == 1 ? ch.seg1 : ch.seg2;
+    for (const Tile &t : tiles) {
+      int64_t sk = 0;
+      for (int i = 0; i < t.nseg; i++) sk += segs[t.seg0 + i].a_base < 0 ? 0 : segs[t.seg0 + i].K;
+      if (n < cap) {
+        out[4 * n] = std::min(16 * t.mb, t.m - t.i0);
+        out[4 * n + 1] = std::min(64 / t.mb, t.n - t.j0);
+        out[4 * n + 2] = t.nseg;
+        out[4 * n + 3] = sk;
+      }
+      n++;
+    }
+  }
+  delete P;
+  return n;
 }

@@ -84,6 +84,25 @@ class Plan:
                                      self._stream(stream)), self.lib)
         return out
 
+    def davidson(self, psi0, tol=1e-8, max_iter=1000, m_max=24, floor=1e-8, stream=None,
+                 check=True):
+        """Lowest eigenpair by the library's Davidson solver.
+
+        psi0: CUDA float64 tensor (starting vector, not modified).  Returns
+        (energy, psi, stats dict).  With check=False a non-converged run
+        returns its best pair instead of raising."""
+        torch = _torch()
+        psi = psi0.detach().clone().contiguous()
+        ev = ctypes.c_double()
+        st = B.DavStats()
+        opts = B.DavOpts(tol, max_iter, m_max, 0, floor, 0)
+        rc = self.lib.dmrg_davidson(self.handle, ctypes.c_void_p(psi.data_ptr()), ctypes.byref(ev),
+                                    ctypes.byref(opts), ctypes.byref(st), self._stream(stream))
+        if rc != 0 and (check or rc != -7):
+            B.check(rc, self.lib)
+        torch.cuda.synchronize(self.device)
+        return ev.value, psi, st.as_dict()
+
     def set_profiling(self, on=True):
         B.check(self.lib.dmrg_set_profiling(self.handle, 1 if on else 0), self.lib)
 

@@ -23,6 +23,17 @@ with W0_ij = 2 (ij|xy) - (iy|xj) and W1_ij = sqrt(3) (iy|xj); the internal
 indices j, k, l, i run over the block.  Outside labels: for L they are the
 orbitals [p, L) and, for pairs, only pairs with at least one site orbital
 (p or p+1); for R they are [0, p+2) and all pairs of them.
+
+Label order (fixes the position index of every family member):
+  single labels: ascending.
+  pairs inside L (A, B) and right-block pairs (P, Q on R), in groups:
+    1. x < y, both in L, lexicographic      2. (x, x), x in L, ascending
+    3. (x, p), x in L, ascending            4. (x, p+1), x in L, ascending
+    5. pairs of the two site orbitals: (p, p), (p, p+1), (p+1, p+1)
+  (groups 3-5 exist only for R; families with x < y drop the diagonal ones).
+  left-block pairs (P, Q on L): lexicographic (x outer, y inner).
+This grouping keeps the positions of the partner operators of one
+operator-table row consecutive, so their products form long stripes.
 """
 
 H, C, A0, A1, B0, B1, S, P0, P1, Q0, Q1 = range(11)
@@ -50,18 +61,32 @@ def labels(fam: int, role: str, n_orb: int, p: int):
     if fam == C:
         return [(i,) for i in inside]
     if fam in (A0, B0, B1):
-        return [(i, j) for i in inside for j in inside if i <= j]
+        return grouped_pairs(inside, p, False, with_sites=False)
     if fam == A1:
-        return [(i, j) for i in inside for j in inside if i < j]
+        return grouped_pairs(inside, p, True, with_sites=False)
     out = outside(role, n_orb, p)
     if fam == S:
         return [(x,) for x in out]
     strict = fam == P1
+    if role == "R":
+        return grouped_pairs(list(range(0, p)), p, strict, with_sites=True)
     res = []
     for x in out:
         for y in out:
             if (x < y) if strict else (x <= y):
-                if role == "L" and x >= p + 2 and y >= p + 2:
+                if x >= p + 2 and y >= p + 2:
                     continue
                 res.append((x, y))
+    return res
+
+
+def grouped_pairs(inner, p, strict, with_sites):
+    """Pairs of ``inner`` orbitals (and, for the right block, sites) in group order."""
+    res = [(x, y) for x in inner for y in inner if x < y]
+    if not strict:
+        res += [(x, x) for x in inner]
+    if with_sites:
+        res += [(x, p) for x in inner]
+        res += [(x, p + 1) for x in inner]
+        res += [(p, p + 1)] if strict else [(p, p), (p, p + 1), (p + 1, p + 1)]
     return res
