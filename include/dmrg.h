@@ -183,7 +183,7 @@ int dmrg_debug_host_apply(const dmrg_problem_t *prob, const double *psi, double 
  * with HOST operator data and execute them on the CPU with the kernels'
  * addressing (psi or y NULL: only fill *st).  Never used by dmrg_apply_H. */
 int dmrg_debug_plan_host_apply(const dmrg_problem_t *prob, const double *psi, double *y,
-                               int64_t workspace_bytes, dmrg_plan_stats_t *st);
+                               const dmrg_plan_opts_t *opts, dmrg_plan_stats_t *st);
 
 #ifdef __cplusplus
 }

@@ -101,8 +101,8 @@ def load(path=None):
         L.dmrg_set_profiling.argtypes = [c_vp, c_i32]
         L.dmrg_get_profile.argtypes = [c_vp, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_dbl),
                                        ctypes.POINTER(c_dbl)]
-        L.dmrg_debug_plan_host_apply.argtypes = [ctypes.POINTER(ProblemT), c_vp, c_vp, c_i64,
-                                                 ctypes.POINTER(PlanStats)]
+        L.dmrg_debug_plan_host_apply.argtypes = [ctypes.POINTER(ProblemT), c_vp, c_vp,
+                                                 ctypes.POINTER(PlanOpts), ctypes.POINTER(PlanStats)]
     if path is None:
         _lib = L
     return L
@@ -137,7 +137,7 @@ class ProblemArgs:
                           ldata_ptr, rdata_ptr, prob.left.data.size, prob.right.data.size)
 
 
-def debug_plan_host_apply(prob, psi, workspace_bytes=0, lib=None):
+def debug_plan_host_apply(prob, psi, workspace_bytes=0, lib=None, precision=0, n_slices=0):
     """Test-only: run the device plan's tile lists on the CPU (no GPU).
 
     ``psi=None`` only builds the plan and returns its statistics."""
@@ -146,14 +146,15 @@ def debug_plan_host_apply(prob, psi, workspace_bytes=0, lib=None):
     rd = np.ascontiguousarray(prob.right.data)
     args = ProblemArgs(prob, ld.ctypes.data, rd.ctypes.data)
     st = PlanStats()
+    opts = PlanOpts(precision, n_slices, workspace_bytes, 0)
     if psi is None:
-        check(L.dmrg_debug_plan_host_apply(ctypes.byref(args.s), None, None, workspace_bytes,
+        check(L.dmrg_debug_plan_host_apply(ctypes.byref(args.s), None, None, ctypes.byref(opts),
                                            ctypes.byref(st)), L)
         return None, st.as_dict()
     x = np.ascontiguousarray(psi, dtype=np.float64)
     y = np.zeros_like(x)
     check(L.dmrg_debug_plan_host_apply(ctypes.byref(args.s), x.ctypes.data, y.ctypes.data,
-                                       workspace_bytes, ctypes.byref(st)), L)
+                                       ctypes.byref(opts), ctypes.byref(st)), L)
     return y, st.as_dict()
 
 

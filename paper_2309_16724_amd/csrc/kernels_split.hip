@@ -1,0 +1,249 @@
+// Split-precision (BF16 slices) kernels for the stripe products of H.psi.
+//
+// A product C = A B of FP64 operands is computed from fixed-point BF16 slices
+// (see SliceJob): C_ij = 2^(e_i + f_j) sum_{t+u <= s-1} 2^(-8(t+u+2)) sum_k a^t_ik b^u_kj.
+// The inner sums run on v_mfma_f32_16x16x32_bf16; products of slices are
+// integers of at most 16 bits, and sums grouped by d = t+u stay exact in FP32
+// for SPLIT_FOLD_K terms, after which they are folded into FP64 with the
+// line scales.  FP64 remains for the fold, the scales and the identity
+// segments.  Lane layout of v_mfma_f32_16x16x32_bf16 (lane l, element e/r):
+// A[l%16][8(l/16)+e], B[8(l/16)+e][l%16], D[4(l/16)+r][l%16].
+#include <hip/hip_runtime.h>
+#include "plan.hpp"
+
+namespace dmrg {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ const double *sbase_ptr(int id, const double *const *bases, const double *psi,
+                                                   const double *y, const double *work, const double *part) {
+  return id == BASE_PSI ? psi : id == BASE_Y ? y : id == BASE_WORK ? work : id == BASE_PART ? part
+                                                                                             : bases[id - BASE_OPS];
+}
+
+// ------------------------------------------------------------------ slicing
+__global__ void __launch_bounds__(256) slice_kernel(const SliceJob *__restrict__ jobs, int njobs, int ns,
+                                                     const double *const *__restrict__ bases,
+                                                     const double *__restrict__ psi,
+                                                     const double *__restrict__ work, SliceBufs bufs) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int jb = blockIdx.x; jb < njobs; jb += gridDim.x) {
+    const SliceJob J = jobs[jb];
+    const double *src = sbase_ptr(J.src_base, bases, psi, nullptr, work, nullptr) + J.src_off;
+    uint16_t *dst = bufs.data[J.dst_buf] + J.dst_off;
+    const int64_t plane = bufs.plane[J.dst_buf];
+    int32_t *exps = bufs.exps[J.dst_buf] + J.exp_off;
+    const int64_t len = (int64_t)J.npos * J.kbp;
+    const int64_t nval = (int64_t)J.npos * J.kb;
+    for (int rho = wave; rho < J.nrho; rho += 4) {
+      const double *line = src + (int64_t)rho * J.s_rho;
+      double m = 0.0;
+      for (int64_t idx = lane; idx < nval; idx += 64) {
+        int p = (int)(idx / J.kb), kk = (int)(idx - (int64_t)p * J.kb);
+        m = fmax(m, fabs(line[(int64_t)p * J.s_pos + (int64_t)kk * J.s_k]));
+      }
+      for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+      int e = 0;
+      if (m > 0.0) {
+        int ex;
+        double mant = frexp(m, &ex);          // m = mant 2^ex, mant in [0.5, 1)
+        e = (mant == 0.5) ? ex - 1 : ex;      // smallest e with m <= 2^e
+      }
+      if (lane == 0) exps[rho] = e;
+      uint16_t *out = dst + (int64_t)rho * len;
+      for (int64_t idx = lane; idx < len; idx += 64) {
+        int p = (int)(idx / J.kbp), kk = (int)(idx - (int64_t)p * J.kbp);
+        double x = kk < J.kb ? line[(int64_t)p * J.s_pos + (int64_t)kk * J.s_k] : 0.0;
+        double yv = ldexp(x, -e);
+        for (int t = 0; t < ns; t++) {
+          double a = rint(yv * 256.0);
+          yv = yv * 256.0 - a;
+          float af = (float)a;                       // integer, |a| <= 256: exact in BF16
+          out[(int64_t)t * plane + idx] = (uint16_t)(__float_as_uint(af) >> 16);
+        }
+      }
+    }
+  }
+}
+
+void launch_slices(const SliceJob *jobs, int njobs, int nslices, const double *const *bases, const double *psi,
+                   const double *work, SliceBufs bufs, void *stream) {
+  if (njobs <= 0) return;
+  hipLaunchKernelGGL(slice_kernel, dim3(std::min(njobs, 8192)), dim3(256), 0, (hipStream_t)stream, jobs, njobs,
+                     nslices, bases, psi, work, bufs);
+}
+
+// ------------------------------------------------------------------ split products
+__device__ __forceinline__ v8bf load8(const uint16_t *p, bool ok) {
+  if (!ok) return (v8bf){};
+  return *reinterpret_cast<const v8bf *>(p);
+}
+
+template <int MB, int NS>
+__device__ __forceinline__ void item_split(const Tile &T, const Seg *__restrict__ segs,
+                                           const SegS *__restrict__ ssegs, const double *const *bases,
+                                           const double *psi, double *y, double *work, double *part,
+                                           const SliceBufs &bufs, int r16, int q4) {
+  constexpr int NB = 4 / MB;
+  v4d acc[MB][NB];
+  for (int a = 0; a < MB; a++)
+    for (int b = 0; b < NB; b++) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  const int mrem = T.m - T.i0, nrem = T.n - T.j0;
+  for (int si = 0; si < T.nseg; si++) {
+    const Seg S = segs[T.seg0 + si];
+    const SegS Q = ssegs[T.seg0 + si];
+    if (Q.K == 0) {
+      // identity left operator: exact FP64 addition of the FP64 operand
+      const double *B = sbase_ptr(S.b_base, bases, psi, y, work, part) + S.b_off;
+      for (int bi = 0; bi < MB; bi++)
+        for (int bj = 0; bj < NB; bj++) {
+          int jj = 16 * bj + r16;
+          if (jj >= nrem) continue;
+          int n = T.j0 + jj;
+          int pn = n / S.b_nb;
+          int64_t bo = (int64_t)pn * S.b_pn + (int64_t)(n - pn * S.b_nb) * S.b_n;
+          for (int r = 0; r < 4; r++) {
+            int i = 16 * bi + 4 * q4 + r;
+            if (i < mrem) {
+              int k = T.i0 + i;
+              int pk = k / S.b_kb;
+              acc[bi][bj][r] += S.s * B[(int64_t)pk * S.b_pk + (int64_t)(k - pk * S.b_kb) * S.b_k + bo];
+            }
+          }
+        }
+      continue;
+    }
+    const uint16_t *A = bufs.data[Q.a_buf] + Q.a_off;
+    const uint16_t *B = bufs.data[Q.b_buf] + Q.b_off;
+    const int64_t pa = bufs.plane[Q.a_buf], pb = bufs.plane[Q.b_buf];
+    const int32_t *ea = bufs.exps[Q.a_buf] + Q.a_exp;
+    const int32_t *eb = bufs.exps[Q.b_buf] + Q.b_exp;
+    const uint16_t *arow[MB];
+    bool aok[MB];
+    for (int bi = 0; bi < MB; bi++) {
+      aok[bi] = (16 * bi + r16) < mrem;
+      arow[bi] = A + (aok[bi] ? (int64_t)(T.i0 + 16 * bi + r16) * Q.a_ld : 0);
+    }
+    const uint16_t *bcol[NB];
+    bool bok[NB];
+    for (int bj = 0; bj < NB; bj++) {
+      bok[bj] = (16 * bj + r16) < nrem;
+      bcol[bj] = B + (bok[bj] ? (int64_t)(T.j0 + 16 * bj + r16) * Q.b_ld : 0);
+    }
+    // scale exponents of this lane's output elements
+    int erow[MB][4], fcol[NB];
+    for (int bi = 0; bi < MB; bi++)
+      for (int r = 0; r < 4; r++) {
+        int i = 16 * bi + 4 * q4 + r;
+        erow[bi][r] = i < mrem ? ea[T.i0 + i] : 0;
+      }
+    for (int bj = 0; bj < NB; bj++) fcol[bj] = bok[bj] ? eb[T.j0 + 16 * bj + r16] : 0;
+    v4f q[MB][NB][NS];
+    for (int bi = 0; bi < MB; bi++)
+      for (int bj = 0; bj < NB; bj++)
+        for (int d = 0; d < NS; d++) q[bi][bj][d] = (v4f){0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < Q.K; k0 += 32) {
+      const int kl = k0 + 8 * q4;
+      const bool kok = kl < Q.K;
+      v8bf as[MB][NS], bs[NB][NS];
+      for (int bi = 0; bi < MB; bi++)
+        for (int t = 0; t < NS; t++) as[bi][t] = load8(arow[bi] + (int64_t)t * pa + kl, kok && aok[bi]);
+      for (int bj = 0; bj < NB; bj++)
+        for (int t = 0; t < NS; t++) bs[bj][t] = load8(bcol[bj] + (int64_t)t * pb + kl, kok && bok[bj]);
+#pragma unroll
+      for (int d = 0; d < NS; d++)
+#pragma unroll
+        for (int t = 0; t <= d; t++)
+          for (int bi = 0; bi < MB; bi++)
+            for (int bj = 0; bj < NB; bj++)
+              q[bi][bj][d] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as[bi][t], bs[bj][d - t], q[bi][bj][d], 0, 0, 0);
+      const bool last = k0 + 32 >= Q.K;
+      if (last || ((k0 + 32) % SPLIT_FOLD_K) == 0) {
+        for (int bi = 0; bi < MB; bi++)
+          for (int bj = 0; bj < NB; bj++)
+            for (int r = 0; r < 4; r++) {
+              double x = 0.0;
+              for (int d = 0; d < NS; d++) x += ldexp((double)q[bi][bj][d][r], -SLICE_BITS * (d + 2));
+              acc[bi][bj][r] += S.s * ldexp(x, erow[bi][r] + fcol[bj]);
+            }
+        for (int bi = 0; bi < MB; bi++)
+          for (int bj = 0; bj < NB; bj++)
+            for (int d = 0; d < NS; d++) q[bi][bj][d] = (v4f){0.f, 0.f, 0.f, 0.f};
+      }
+    }
+  }
+  double *C = const_cast<double *>(sbase_ptr(T.c_base, bases, psi, y, work, part)) + T.c_off;
+  for (int bi = 0; bi < MB; bi++)
+    for (int bj = 0; bj < NB; bj++)
+      for (int r = 0; r < 4; r++) {
+        int i = 16 * bi + 4 * q4 + r, j = 16 * bj + r16;
+        if (i < mrem && j < nrem) {
+          double *c = C + (int64_t)(T.ci0 + i) + (int64_t)(T.cj0 + j) * T.ldc;
+          *c = T.accumulate ? *c + acc[bi][bj][r] : acc[bi][bj][r];
+        }
+      }
+}
+
+template <int NS>
+__device__ __forceinline__ void items_split(const Tile *__restrict__ tiles, const Seg *__restrict__ segs,
+                                            const SegS *__restrict__ ssegs, int ntiles,
+                                            const double *const *__restrict__ bases, const double *__restrict__ psi,
+                                            double *__restrict__ y, double *__restrict__ work,
+                                            double *__restrict__ part, const SliceBufs &bufs) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, q4 = lane >> 4;
+  for (int t = blockIdx.x * WAVES + wave; t < ntiles; t += gridDim.x * WAVES) {
+    const Tile T = tiles[t];
+    if (T.mb == 1) item_split<1, NS>(T, segs, ssegs, bases, psi, y, work, part, bufs, r16, q4);
+    else if (T.mb == 4) item_split<4, NS>(T, segs, ssegs, bases, psi, y, work, part, bufs, r16, q4);
+    else item_split<2, NS>(T, segs, ssegs, bases, psi, y, work, part, bufs, r16, q4);
+  }
+}
+
+#define SPLIT_KERNELS(NS)                                                                                   \
+  __global__ void __launch_bounds__(64 * WAVES) stage1_split##NS##_kernel(                                  \
+      const Tile *__restrict__ tiles, const Seg *__restrict__ segs, const SegS *__restrict__ ssegs,         \
+      int ntiles, const double *const *__restrict__ bases, const double *__restrict__ psi,                  \
+      double *__restrict__ y, double *__restrict__ work, double *__restrict__ part, SliceBufs bufs) {       \
+    items_split<NS>(tiles, segs, ssegs, ntiles, bases, psi, y, work, part, bufs);                           \
+  }                                                                                                         \
+  __global__ void __launch_bounds__(64 * WAVES) stage2_split##NS##_kernel(                                  \
+      const Tile *__restrict__ tiles, const Seg *__restrict__ segs, const SegS *__restrict__ ssegs,         \
+      int ntiles, const double *const *__restrict__ bases, const double *__restrict__ psi,                  \
+      double *__restrict__ y, double *__restrict__ work, double *__restrict__ part, SliceBufs bufs) {       \
+    items_split<NS>(tiles, segs, ssegs, ntiles, bases, psi, y, work, part, bufs);                           \
+  }
+
+SPLIT_KERNELS(3)
+SPLIT_KERNELS(4)
+SPLIT_KERNELS(5)
+SPLIT_KERNELS(6)
+SPLIT_KERNELS(7)
+
+void launch_tiles_split(int stage, const Tile *tiles, const Seg *segs, const SegS *ssegs, int ntiles,
+                        int nslices, const double *const *bases, const double *psi, double *y, double *work,
+                        double *part, SliceBufs bufs, void *stream) {
+  if (ntiles <= 0) return;
+  int grid = std::min((ntiles + WAVES - 1) / WAVES, 256 * 16);
+  hipStream_t s = (hipStream_t)stream;
+#define LAUNCH(NS)                                                                                          \
+  if (nslices == NS) {                                                                                      \
+    if (stage == 1)                                                                                         \
+      hipLaunchKernelGGL(stage1_split##NS##_kernel, dim3(grid), dim3(64 * WAVES), 0, s, tiles, segs, ssegs,   \
+                         ntiles, bases, psi, y, work, part, bufs);                                          \
+    else                                                                                                    \
+      hipLaunchKernelGGL(stage2_split##NS##_kernel, dim3(grid), dim3(64 * WAVES), 0, s, tiles, segs, ssegs,   \
+                         ntiles, bases, psi, y, work, part, bufs);                                          \
+    return;                                                                                                 \
+  }
+  LAUNCH(3)
+  LAUNCH(4)
+  LAUNCH(5)
+  LAUNCH(6)
+  LAUNCH(7)
+#undef LAUNCH
+}
+
+}  // namespace dmrg

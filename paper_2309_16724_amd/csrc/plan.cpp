@@ -38,6 +38,13 @@ struct dmrg_plan {
   DiagTerm *d_dterms = nullptr;
   dmrg_plan_stats_t stats;
   int precision = 0, n_slices = 0;
+  // split precision
+  std::vector<SliceJob> jobs_ops, jobs_psi;
+  SliceJob *d_jobs_ops = nullptr, *d_jobs_psi = nullptr;
+  int64_t sb_elems[N_SBUF] = {0, 0, 0, 0}, sb_exps[N_SBUF] = {0, 0, 0, 0};
+  SliceBufs sb{};
+  std::vector<uint16_t> h_sb[N_SBUF];      // host copies (test emulation only)
+  std::vector<int32_t> h_se[N_SBUF];
   std::vector<void *> allocs;
   // profiling: events around every first- and second-stage launch
   int profiling = 0;
@@ -84,6 +91,7 @@ struct Stripe {
   std::vector<int> slots;   // sorted pD
   int64_t off = 0;
   int dL = 0, dRin = 0, dRout = 0;
+  int index = 0;
 };
 
 struct TaskRef { int prob; int task; };
@@ -151,6 +159,9 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
       std::sort(s.slots.begin(), s.slots.end());
       s.slots.erase(std::unique(s.slots.begin(), s.slots.end()), s.slots.end());
       s.off = woff;
+      s.index = (int)ch.stripes.size();
+      ch.stripes.push_back({kv.first.prob, kv.first.E, kv.first.rec, kv.first.adj, kv.first.dress, woff, s.dL,
+                            s.dRin, s.dRout, (int)s.slots.size(), 0});
       woff += (int64_t)s.dL * s.dRout * s.slots.size();
       woff = (woff + 31) / 32 * 32;
       // first stage: T_h = X [op(D_s0) ... op(D_s1-1)] for each run of consecutive positions;
@@ -182,6 +193,7 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
         g.s = 1.0;
         int sidx = (int)ch.seg1.size();
         ch.seg1.push_back(g);
+        ch.s1info.push_back({s.index, (int)s0, s.slots[s0]});
         int N = (int)(s1 - s0) * s.dRout;
         double fl = 2.0 * s.dL * s.dRin * N;
         P->stats.stage1_flops += fl;
@@ -203,7 +215,7 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
     }
     max_work = std::max(max_work, woff);
     // second stage: segments grouped by output block
-    std::map<std::pair<int, int>, std::vector<Seg>> byF;
+    std::map<std::pair<int, int>, std::vector<std::pair<Seg, Seg2Info>>> byF;
     for (auto &r : ct) {
       const ProbPlan &pp = *P->probs[r.prob];
       const Tasks &T = pp.T;
@@ -249,6 +261,8 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
           g.b_k = 1;
         }
         g.b_nb = F.dR; g.b_pn = 0; g.b_n = E.dL;
+        Seg2Info inf{r.prob, tk.E, st ? st->index : -1, st ? slot_of(row.pos[q].pD) : 0,
+                     tk.recA, tk.adjA, row.pos[q].pA, run};
         if (tk.recA >= 0) {
           g.a_base = pp.base_l;
           g.a_off = recoffA + (int64_t)row.pos[q].pA * rowsA * colsA;
@@ -264,7 +278,7 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
           g.K = E.dL;
           g.a_kb = E.dL;
         }
-        segs.push_back(g);
+        segs.push_back({g, inf});
         q = q1;
       }
     }
@@ -275,8 +289,10 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
       const PsiBlock &F = pp.T.blocks[kv.first.second];
       // pieces of at most KPART along K, cut at position boundaries
       std::vector<Seg> pieces;
-      for (auto &g : kv.second) {
-        if (g.a_base < 0 || g.K <= KPART) { pieces.push_back(g); continue; }
+      std::vector<Seg2Info> pinfo;
+      for (auto &gi : kv.second) {
+        const Seg &g = gi.first;
+        if (g.a_base < 0 || g.K <= KPART) { pieces.push_back(g); pinfo.push_back(gi.second); continue; }
         int npos = g.K / g.a_kb;
         int per = std::max(1, KPART / g.a_kb);
         for (int p0 = 0; p0 < npos; p0 += per) {
@@ -286,6 +302,11 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
           h.b_off += (int64_t)p0 * g.b_pk;
           h.K = (p1 - p0) * g.a_kb;
           pieces.push_back(h);
+          Seg2Info hi = gi.second;
+          hi.pA0 += p0;
+          hi.slot0 += p0;
+          hi.run = p1 - p0;
+          pinfo.push_back(hi);
         }
       }
       // parts: consecutive pieces with summed K up to KPART (identity pieces count as d_L)
@@ -307,6 +328,7 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
       pcost.push_back(cost);
       int seg0 = (int)ch.seg2.size();
       for (auto &g : pieces) ch.seg2.push_back(g);
+      for (auto &gi : pinfo) ch.s2info.push_back(gi);
       int mb = tile_mb(F.dL, F.dR);
       int tm = 16 * mb, tn = 64 / mb;
       for (int i0 = 0; i0 < F.dL; i0 += tm)
@@ -468,6 +490,212 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
 
 }  // namespace
 
+
+// ---------------------------------------------------------------------------
+// Split-precision plan: slice layouts of every operand and split segments
+// parallel to the FP64 segments (same tiles, parts and reduction).
+namespace {
+
+struct VarInfo { int64_t off, exp; int kbp; int64_t line_len; int lines_per_pos; };
+
+static int rup8(int x) { return (x + 7) / 8 * 8; }
+
+void build_split(dmrg_plan *P) {
+  for (int b = 0; b < N_SBUF; b++) P->sb_elems[b] = P->sb_exps[b] = 0;
+  P->jobs_ops.clear();
+  P->jobs_psi.clear();
+  // operator-record variants: 0 A rows (adjA=0), 1 A columns (adjA=1),
+  // 2 D for adjD=0 (lines = stored rows per position), 3 D for adjD=1 (stored columns)
+  std::map<std::array<int, 4>, VarInfo> vars;   // (prob, source (0 L rec, 1 R rec, 2 dressed), index, variant)
+  auto variant = [&](int prob, int srcsel, int idx, int var) -> VarInfo {
+    std::array<int, 4> key{prob, srcsel, idx, var};
+    auto it = vars.find(key);
+    if (it != vars.end()) return it->second;
+    const ProbPlan &pp = *P->probs[prob];
+    int R0, C0, npos, base;
+    int64_t src_off;
+    if (srcsel == 0) {
+      const dmrg_oprec_t &r = pp.L.rec[idx];
+      R0 = pp.L.sec[r.row_sec].dim; C0 = pp.L.sec[r.col_sec].dim; npos = r.npos; base = pp.base_l; src_off = r.off;
+    } else if (srcsel == 1) {
+      const dmrg_oprec_t &r = pp.R.rec[idx];
+      R0 = pp.R.sec[r.row_sec].dim; C0 = pp.R.sec[r.col_sec].dim; npos = r.npos; base = pp.base_r; src_off = r.off;
+    } else {
+      const Dress &d = pp.T.dress[idx];
+      R0 = d.rows; C0 = d.cols; npos = d.npos; base = pp.base_dress; src_off = d.off;
+    }
+    VarInfo v{};
+    v.off = P->sb_elems[SBUF_OPS];
+    v.exp = P->sb_exps[SBUF_OPS];
+    int64_t bs = (int64_t)R0 * C0;
+    if (var == 0 || var == 1) {
+      int nrho = var == 0 ? R0 : C0, kb = var == 0 ? C0 : R0;
+      v.kbp = rup8(kb);
+      v.line_len = (int64_t)npos * v.kbp;
+      v.lines_per_pos = 0;
+      SliceJob j{};
+      j.src_base = base; j.src_off = src_off;
+      j.s_rho = var == 0 ? 1 : R0; j.s_pos = bs; j.s_k = var == 0 ? R0 : 1;
+      j.dst_buf = SBUF_OPS; j.dst_off = v.off; j.exp_off = v.exp;
+      j.nrho = nrho; j.npos = npos; j.kb = kb; j.kbp = v.kbp;
+      P->jobs_ops.push_back(j);
+      P->sb_elems[SBUF_OPS] += (int64_t)nrho * v.line_len;
+      P->sb_exps[SBUF_OPS] += nrho;
+    } else {
+      int nrho = var == 2 ? R0 : C0, kb = var == 2 ? C0 : R0;
+      v.kbp = rup8(kb);
+      v.line_len = v.kbp;
+      v.lines_per_pos = nrho;
+      for (int p = 0; p < npos; p++) {
+        SliceJob j{};
+        j.src_base = base; j.src_off = src_off + (int64_t)p * bs;
+        j.s_rho = var == 2 ? 1 : R0; j.s_pos = 0; j.s_k = var == 2 ? R0 : 1;
+        j.dst_buf = SBUF_OPS; j.dst_off = v.off + (int64_t)p * nrho * v.kbp; j.exp_off = v.exp + (int64_t)p * nrho;
+        j.nrho = nrho; j.npos = 1; j.kb = kb; j.kbp = v.kbp;
+        P->jobs_ops.push_back(j);
+      }
+      P->sb_elems[SBUF_OPS] += (int64_t)npos * nrho * v.kbp;
+      P->sb_exps[SBUF_OPS] += (int64_t)npos * nrho;
+    }
+    vars[key] = v;
+    return v;
+  };
+  // psi slices: every block as a first-stage A operand (rows over columns) and
+  // as a second-stage B operand (columns over rows)
+  std::vector<std::vector<std::array<int64_t, 4>>> psi_off(P->probs.size());   // rows off/exp, cols off/exp
+  for (int k = 0; k < (int)P->probs.size(); k++) {
+    const ProbPlan &pp = *P->probs[k];
+    for (const PsiBlock &E : pp.T.blocks) {
+      std::array<int64_t, 4> o{};
+      SliceJob j{};
+      j.src_base = BASE_PSI; j.src_off = pp.psi_off + E.off;
+      j.s_rho = 1; j.s_pos = 0; j.s_k = E.dL;
+      j.nrho = E.dL; j.npos = 1; j.kb = E.dR; j.kbp = rup8(E.dR);
+      j.dst_buf = SBUF_PSIR; j.dst_off = P->sb_elems[SBUF_PSIR]; j.exp_off = P->sb_exps[SBUF_PSIR];
+      o[0] = j.dst_off; o[1] = j.exp_off;
+      P->sb_elems[SBUF_PSIR] += (int64_t)E.dL * j.kbp;
+      P->sb_exps[SBUF_PSIR] += E.dL;
+      P->jobs_psi.push_back(j);
+      SliceJob c{};
+      c.src_base = BASE_PSI; c.src_off = pp.psi_off + E.off;
+      c.s_rho = E.dL; c.s_pos = 0; c.s_k = 1;
+      c.nrho = E.dR; c.npos = 1; c.kb = E.dL; c.kbp = rup8(E.dL);
+      c.dst_buf = SBUF_PSIC; c.dst_off = P->sb_elems[SBUF_PSIC]; c.exp_off = P->sb_exps[SBUF_PSIC];
+      o[2] = c.dst_off; o[3] = c.exp_off;
+      P->sb_elems[SBUF_PSIC] += (int64_t)E.dR * c.kbp;
+      P->sb_exps[SBUF_PSIC] += E.dR;
+      P->jobs_psi.push_back(c);
+      psi_off[k].push_back(o);
+    }
+  }
+  int64_t t_elems_max = 0, t_exps_max = 0;
+  for (auto &ch : P->chunks) {
+    ch.sseg1.clear();
+    ch.sseg2.clear();
+    ch.tjobs.clear();
+    // stripe slices (second-stage B operands), per chunk
+    std::vector<std::array<int64_t, 3>> toff;   // off, exp, kbp
+    int64_t te = 0, tx = 0;
+    for (const StripeInfo &si : ch.stripes) {
+      SliceJob j{};
+      j.src_base = BASE_WORK; j.src_off = si.off;
+      j.s_rho = si.dL; j.s_pos = (int64_t)si.dL * si.dRout; j.s_k = 1;
+      j.nrho = si.dRout; j.npos = si.nslots; j.kb = si.dL; j.kbp = rup8(si.dL);
+      j.dst_buf = SBUF_T; j.dst_off = te; j.exp_off = tx;
+      toff.push_back({te, tx, j.kbp});
+      te += (int64_t)si.dRout * si.nslots * j.kbp;
+      tx += si.dRout;
+      ch.tjobs.push_back(j);
+    }
+    ch.t_elems = te;
+    ch.t_exps = tx;
+    t_elems_max = std::max(t_elems_max, te);
+    t_exps_max = std::max(t_exps_max, tx);
+    // first stage: X (psi rows) times op(D) (record or dressed variant)
+    for (size_t i = 0; i < ch.seg1.size(); i++) {
+      const Seg1Info &inf = ch.s1info[i];
+      const StripeInfo &si = ch.stripes[inf.stripe];
+      int var = si.adj ? 3 : 2;
+      VarInfo v = si.dress >= 0 ? variant(si.prob, 2, si.dress, var) : variant(si.prob, 1, si.rec, var);
+      SegS q{};
+      q.a_buf = SBUF_PSIR;
+      q.a_off = psi_off[si.prob][si.E][0];
+      q.a_ld = rup8(si.dRin);
+      q.a_exp = psi_off[si.prob][si.E][1];
+      q.b_buf = SBUF_OPS;
+      q.b_off = v.off + (int64_t)inf.pD0 * v.lines_per_pos * v.kbp;
+      q.b_ld = v.kbp;
+      q.b_exp = v.exp + (int64_t)inf.pD0 * v.lines_per_pos;
+      q.K = rup8(si.dRin);
+      ch.sseg1.push_back(q);
+    }
+    // second stage
+    for (size_t i = 0; i < ch.seg2.size(); i++) {
+      const Seg2Info &inf = ch.s2info[i];
+      const PsiBlock &E = P->probs[inf.prob]->T.blocks[inf.E];
+      SegS q{};
+      if (inf.recA < 0) {
+        q.K = 0;
+        ch.sseg2.push_back(q);
+        continue;
+      }
+      VarInfo v = variant(inf.prob, 0, inf.recA, inf.adjA ? 1 : 0);
+      q.a_buf = SBUF_OPS;
+      q.a_off = v.off + (int64_t)inf.pA0 * v.kbp;
+      q.a_ld = v.line_len;
+      q.a_exp = v.exp;
+      if (inf.stripe >= 0) {
+        const StripeInfo &si = ch.stripes[inf.stripe];
+        q.b_buf = SBUF_T;
+        q.b_off = toff[inf.stripe][0] + (int64_t)inf.slot0 * toff[inf.stripe][2];
+        q.b_ld = (int64_t)si.nslots * toff[inf.stripe][2];
+        q.b_exp = toff[inf.stripe][1];
+      } else {
+        q.b_buf = SBUF_PSIC;
+        q.b_off = psi_off[inf.prob][inf.E][2];
+        q.b_ld = rup8(E.dL);
+        q.b_exp = psi_off[inf.prob][inf.E][3];
+      }
+      q.K = inf.run * v.kbp;
+      ch.sseg2.push_back(q);
+    }
+  }
+  P->sb_elems[SBUF_T] = t_elems_max;
+  P->sb_exps[SBUF_T] = t_exps_max;
+}
+
+}  // namespace
+
+namespace {
+int upload_split(dmrg_plan *P) {
+  build_split(P);
+  int rc;
+  if ((rc = upload(P, P->jobs_ops, &P->d_jobs_ops)) || (rc = upload(P, P->jobs_psi, &P->d_jobs_psi))) return rc;
+  for (auto &ch : P->chunks)
+    if ((rc = upload(P, ch.sseg1, &ch.d_sseg1)) || (rc = upload(P, ch.sseg2, &ch.d_sseg2)) ||
+        (rc = upload(P, ch.tjobs, &ch.d_tjobs)))
+      return rc;
+  for (int b = 0; b < N_SBUF; b++) {
+    void *d = nullptr, *e = nullptr;
+    if (hipMalloc(&d, sizeof(uint16_t) * std::max<int64_t>(1, P->sb_elems[b] * P->n_slices)) != hipSuccess ||
+        hipMalloc(&e, sizeof(int32_t) * std::max<int64_t>(1, P->sb_exps[b])) != hipSuccess) {
+      set_error("hipMalloc failed for slice buffers");
+      return DMRG_ENOMEM;
+    }
+    P->allocs.push_back(d);
+    P->allocs.push_back(e);
+    P->sb.data[b] = (uint16_t *)d;
+    P->sb.exps[b] = (int32_t *)e;
+    P->sb.plane[b] = P->sb_elems[b];
+  }
+  // operator slices: once per plan (the operators are constant during Davidson)
+  launch_slices(P->d_jobs_ops, (int)P->jobs_ops.size(), P->n_slices, P->d_bases, nullptr, nullptr, P->sb, nullptr);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipDeviceSynchronize());
+  return DMRG_OK;
+}
+}  // namespace
+
 extern "C" void dmrg_plan_free(dmrg_plan_t *p) {
   if (!p) return;
   for (void *a : p->allocs) (void)hipFree(a);
@@ -485,8 +713,13 @@ extern "C" int dmrg_build_tasks(const dmrg_problem_t *probs, int32_t n_probs, co
   try {
     P->precision = opts ? opts->precision : DMRG_FP64;
     P->n_slices = opts ? opts->n_slices : 0;
-    if (P->precision != DMRG_FP64) {
-      set_error("only DMRG_FP64 is available in this build");
+    if (P->precision != DMRG_FP64 && P->precision != DMRG_SPLIT_BF16) {
+      set_error("unknown precision");
+      dmrg_plan_free(P);
+      return DMRG_EINVAL;
+    }
+    if (P->precision == DMRG_SPLIT_BF16 && (P->n_slices < 3 || P->n_slices > 7)) {
+      set_error("split precision needs 3 <= n_slices <= 7");
       dmrg_plan_free(P);
       return DMRG_EINVAL;
     }
@@ -528,6 +761,10 @@ extern "C" int dmrg_build_tasks(const dmrg_problem_t *probs, int32_t n_probs, co
     P->stats.psi_len = off;
     int rc = build_plan(P, budget, true);
     if (rc) { dmrg_plan_free(P); return rc; }
+    if (P->precision == DMRG_SPLIT_BF16) {
+      rc = upload_split(P);
+      if (rc) { dmrg_plan_free(P); return rc; }
+    }
     *out = P;
     return DMRG_OK;
   } catch (const std::exception &e) {
@@ -557,6 +794,9 @@ extern "C" int dmrg_apply_H(dmrg_plan_t *p, const double *psi, double *hpsi, voi
   if (!p || !psi || !hpsi) { set_error("null argument"); return DMRG_EINVAL; }
   if (psi == hpsi) { set_error("psi and hpsi must not alias"); return DMRG_EINVAL; }
   launch_zero(hpsi, p->psi_len, stream);
+  const bool split = p->precision == DMRG_SPLIT_BF16;
+  if (split)
+    launch_slices(p->d_jobs_psi, (int)p->jobs_psi.size(), p->n_slices, p->d_bases, psi, p->d_work, p->sb, stream);
   size_t ev = p->ev_marks.empty() ? 0 : (size_t)p->ev_marks.back().second.second + 1;
   for (auto &ch : p->chunks) {
     for (int stage = 1; stage <= 2; stage++) {
@@ -567,7 +807,16 @@ extern "C" int dmrg_apply_H(dmrg_plan_t *p, const double *psi, double *hpsi, voi
         e0 = (int)ev;
         HIPCHK(hipEventRecord(p->ev_pool[ev++], (hipStream_t)stream));
       }
-      if (stage == 1)
+      if (split && stage == 2)
+        launch_slices(ch.d_tjobs, (int)ch.tjobs.size(), p->n_slices, p->d_bases, psi, p->d_work, p->sb, stream);
+      if (split) {
+        if (stage == 1)
+          launch_tiles_split(1, ch.d_tile1, ch.d_seg1, ch.d_sseg1, (int)ch.tile1.size(), p->n_slices, p->d_bases,
+                             psi, hpsi, p->d_work, p->d_part, p->sb, stream);
+        else
+          launch_tiles_split(2, ch.d_tile2, ch.d_seg2, ch.d_sseg2, (int)ch.tile2.size(), p->n_slices, p->d_bases,
+                             psi, hpsi, p->d_work, p->d_part, p->sb, stream);
+      } else if (stage == 1)
         launch_tiles_f64(1, ch.d_tile1, ch.d_seg1, (int)ch.tile1.size(), p->d_bases, psi, hpsi, p->d_work,
                          p->d_part, stream);
       else
@@ -678,6 +927,111 @@ static void host_tiles(const std::vector<Tile> &tiles, const std::vector<Seg> &s
   }
 }
 
+// host emulation of slice_kernel
+static void host_slices(const std::vector<SliceJob> &jobs, int ns, const std::vector<const double *> &bases,
+                        const double *psi, const double *work, std::vector<uint16_t> *sbd, const int64_t *plane,
+                        std::vector<int32_t> *sbe) {
+  auto base = [&](int id) -> const double * {
+    return id == BASE_PSI ? psi : id == BASE_WORK ? work : bases[id - BASE_OPS];
+  };
+  for (const SliceJob &J : jobs) {
+    const double *src = base(J.src_base) + J.src_off;
+    int64_t len = (int64_t)J.npos * J.kbp;
+    for (int rho = 0; rho < J.nrho; rho++) {
+      const double *line = src + (int64_t)rho * J.s_rho;
+      double m = 0.0;
+      for (int p = 0; p < J.npos; p++)
+        for (int kk = 0; kk < J.kb; kk++) m = std::max(m, std::fabs(line[(int64_t)p * J.s_pos + (int64_t)kk * J.s_k]));
+      int e = 0;
+      if (m > 0.0) {
+        int ex;
+        double mant = std::frexp(m, &ex);
+        e = (mant == 0.5) ? ex - 1 : ex;
+      }
+      sbe[J.dst_buf][J.exp_off + rho] = e;
+      for (int64_t idx = 0; idx < len; idx++) {
+        int p = (int)(idx / J.kbp), kk = (int)(idx - (int64_t)p * J.kbp);
+        double x = kk < J.kb ? line[(int64_t)p * J.s_pos + (int64_t)kk * J.s_k] : 0.0;
+        double yv = std::ldexp(x, -e);
+        for (int t = 0; t < ns; t++) {
+          double a = std::nearbyint(yv * 256.0);
+          yv = yv * 256.0 - a;
+          float af = (float)a;
+          uint32_t bits;
+          std::memcpy(&bits, &af, 4);
+          sbd[J.dst_buf][J.dst_off + (int64_t)t * plane[J.dst_buf] + (int64_t)rho * len + idx] = (uint16_t)(bits >> 16);
+        }
+      }
+    }
+  }
+}
+
+static double bf16v(uint16_t b) {
+  uint32_t bits = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &bits, 4);
+  return (double)f;
+}
+
+// host emulation of the split work items (same fold points as the kernels)
+static void host_tiles_split(const std::vector<Tile> &tiles, const std::vector<Seg> &segs,
+                             const std::vector<SegS> &ssegs, int ns, const std::vector<const double *> &bases,
+                             const double *psi, double *y, double *work, double *part,
+                             std::vector<uint16_t> *sbd, const int64_t *plane, std::vector<int32_t> *sbe) {
+  auto base = [&](int id) -> const double * {
+    return id == BASE_PSI ? psi : id == BASE_Y ? y : id == BASE_WORK ? work : id == BASE_PART ? part
+                                                                                               : bases[id - BASE_OPS];
+  };
+  for (const Tile &T : tiles) {
+    int tm = 16 * T.mb, tn = 64 / T.mb;
+    int mt = std::min(tm, T.m - T.i0), nt = std::min(tn, T.n - T.j0);
+    std::vector<double> acc((size_t)mt * nt, 0.0);
+    for (int si = 0; si < T.nseg; si++) {
+      const Seg &S = segs[T.seg0 + si];
+      const SegS &Q = ssegs[T.seg0 + si];
+      if (Q.K == 0) {
+        const double *B = base(S.b_base) + S.b_off;
+        for (int j = 0; j < nt; j++)
+          for (int i = 0; i < mt; i++) {
+            int64_t k = T.i0 + i, n = T.j0 + j;
+            int64_t pk = k / S.b_kb, pn = n / S.b_nb;
+            acc[i + (size_t)j * mt] +=
+                S.s * B[pk * S.b_pk + (k - pk * S.b_kb) * S.b_k + pn * S.b_pn + (n - pn * S.b_nb) * S.b_n];
+          }
+        continue;
+      }
+      const uint16_t *A = sbd[Q.a_buf].data() + Q.a_off;
+      const uint16_t *B = sbd[Q.b_buf].data() + Q.b_off;
+      const int32_t *ea = sbe[Q.a_buf].data() + Q.a_exp;
+      const int32_t *eb = sbe[Q.b_buf].data() + Q.b_exp;
+      for (int j = 0; j < nt; j++)
+        for (int i = 0; i < mt; i++) {
+          const uint16_t *ar = A + (int64_t)(T.i0 + i) * Q.a_ld;
+          const uint16_t *bc = B + (int64_t)(T.j0 + j) * Q.b_ld;
+          double tot = 0.0;
+          for (int k0 = 0; k0 < Q.K; k0 += SPLIT_FOLD_K) {
+            double x = 0.0;
+            for (int d = 0; d < ns; d++) {
+              double qd = 0.0;
+              for (int t = 0; t <= d; t++)
+                for (int k = k0; k < std::min(Q.K, k0 + SPLIT_FOLD_K); k++)
+                  qd += bf16v(ar[(int64_t)t * plane[Q.a_buf] + k]) * bf16v(bc[(int64_t)(d - t) * plane[Q.b_buf] + k]);
+              x += std::ldexp(qd, -SLICE_BITS * (d + 2));
+            }
+            tot += S.s * std::ldexp(x, ea[T.i0 + i] + eb[T.j0 + j]);
+          }
+          acc[i + (size_t)j * mt] += tot;
+        }
+    }
+    double *C = const_cast<double *>(base(T.c_base)) + T.c_off;
+    for (int j = 0; j < nt; j++)
+      for (int i = 0; i < mt; i++) {
+        double &c = C[(int64_t)(T.ci0 + i) + (int64_t)(T.cj0 + j) * T.ldc];
+        c = T.accumulate ? c + acc[i + (size_t)j * mt] : acc[i + (size_t)j * mt];
+      }
+  }
+}
+
 static void host_reduce(const std::vector<Reduce> &red, const double *part, double *y) {
   for (const Reduce &R : red) {
     int mt = std::min(R.tm, R.m - R.i0), nt = std::min(1024 / R.tm, R.n - R.j0);
@@ -691,9 +1045,12 @@ static void host_reduce(const std::vector<Reduce> &red, const double *part, doub
 }
 
 extern "C" int dmrg_debug_plan_host_apply(const dmrg_problem_t *prob, const double *psi, double *y,
-                                          int64_t workspace_bytes, dmrg_plan_stats_t *st) {
+                                          const dmrg_plan_opts_t *opts, dmrg_plan_stats_t *st) {
+  int64_t workspace_bytes = opts ? opts->workspace_bytes : 0;
   dmrg_plan *P = new dmrg_plan();
   std::memset(&P->stats, 0, sizeof(P->stats));
+  P->precision = opts ? opts->precision : DMRG_FP64;
+  P->n_slices = opts ? opts->n_slices : 0;
   auto pp = std::make_unique<ProbPlan>();
   Error err{0, ""};
   if (build_tasks_for_problem(*prob, pp->L, pp->R, pp->T, err)) {
@@ -724,6 +1081,28 @@ extern "C" int dmrg_debug_plan_host_apply(const dmrg_problem_t *prob, const doub
   std::vector<double> work((size_t)std::max<int64_t>(P->work_elems, 1), 0.0);
   std::vector<double> part((size_t)std::max<int64_t>(P->part_elems, 1), 0.0);
   std::memset(y, 0, sizeof(double) * n);
+  if (P->precision == DMRG_SPLIT_BF16) {
+    build_split(P);
+    int ns = P->n_slices;
+    int64_t plane[N_SBUF];
+    for (int b = 0; b < N_SBUF; b++) {
+      P->h_sb[b].assign((size_t)std::max<int64_t>(1, P->sb_elems[b] * ns), 0);
+      P->h_se[b].assign((size_t)std::max<int64_t>(1, P->sb_exps[b]), 0);
+      plane[b] = P->sb_elems[b];
+    }
+    host_slices(P->jobs_ops, ns, P->bases_h, psi, work.data(), P->h_sb, plane, P->h_se);
+    host_slices(P->jobs_psi, ns, P->bases_h, psi, work.data(), P->h_sb, plane, P->h_se);
+    for (auto &ch : P->chunks) {
+      host_tiles_split(ch.tile1, ch.seg1, ch.sseg1, ns, P->bases_h, psi, y, work.data(), part.data(), P->h_sb,
+                       plane, P->h_se);
+      host_slices(ch.tjobs, ns, P->bases_h, psi, work.data(), P->h_sb, plane, P->h_se);
+      host_tiles_split(ch.tile2, ch.seg2, ch.sseg2, ns, P->bases_h, psi, y, work.data(), part.data(), P->h_sb,
+                       plane, P->h_se);
+      host_reduce(ch.red2, part.data(), y);
+    }
+    delete P;
+    return DMRG_OK;
+  }
   for (auto &ch : P->chunks) {
     host_tiles(ch.tile1, ch.seg1, P->bases_h, psi, y, work.data(), part.data());
     host_tiles(ch.tile2, ch.seg2, P->bases_h, psi, y, work.data(), part.data());

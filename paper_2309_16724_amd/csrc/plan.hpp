@@ -62,7 +62,61 @@ struct DressItem {
   int32_t src_base, dst_base;
 };
 
+// ---------------------------------------------------------------- split BF16
+// Fixed-point slicing (Ozaki-style): a line x (row of an A operand or column
+// of a B operand, over its K range) is scaled by 2^-e with e the smallest
+// integer such that max|x| <= 2^e, then cut into s integer slices of SLICE_BITS
+// bits, x = 2^e sum_t a_t 2^(-8(t+1)) + O(2^(e-8s)), |a_0| <= 256, |a_t| <= 128:
+// all exact in BF16.  Lines are stored K-contiguous (operand-ready) and each
+// position block of K is padded to a multiple of 8 with zeros.
+constexpr int SLICE_BITS = 8;
+constexpr int SPLIT_FOLD_K = 64;   // summed products stay exact in FP32 up to here
+
+// One slicing job: lines rho < nrho, position blocks p < npos of kb valid
+// entries (padded to kbp);  source x(rho, p, kk) at src[src_off + rho*s_rho + p*s_pos + kk*s_k];
+// destination plane t line rho at dst[dst_off + t*plane + rho*npos*kbp + p*kbp + kk];
+// exponent of line rho at exps[exp_off + rho].
+struct SliceJob {
+  int64_t src_off, s_rho, s_pos, s_k;
+  int64_t dst_off, exp_off;
+  int32_t src_base, dst_buf;
+  int32_t nrho, npos, kb, kbp;
+};
+
+// Split segment (same role as Seg): A lines are operand rows, B lines operand
+// columns, both K-contiguous in slice buffers.
+struct SegS {
+  int64_t a_off, a_ld, a_exp;
+  int64_t b_off, b_ld, b_exp;
+  int32_t a_buf, b_buf;
+  int32_t K;          // padded K (multiple of 8); 0 for an identity segment
+  int32_t pad;
+};
+
+// slice buffers: 0 operator records (plan), 1 psi rows, 2 psi columns, 3 stripes
+enum { SBUF_OPS = 0, SBUF_PSIR = 1, SBUF_PSIC = 2, SBUF_T = 3, N_SBUF = 4 };
+
+struct SliceBufs {
+  uint16_t *data[N_SBUF];     // bf16 bit patterns
+  int64_t plane[N_SBUF];      // plane stride (elements)
+  int32_t *exps[N_SBUF];
+};
+
+
+// bookkeeping that lets the split-precision plan mirror the FP64 segments
+struct StripeInfo {
+  int prob, E, rec, adj, dress;
+  int64_t off;
+  int dL, dRin, dRout, nslots;
+  int first_slot_pos;          // unused
+};
+struct Seg1Info { int stripe, s0, pD0; };
+struct Seg2Info { int prob, E, stripe, slot0, recA, adjA, pA0, run; };
+
 struct Chunk {
+  std::vector<StripeInfo> stripes;
+  std::vector<Seg1Info> s1info;
+  std::vector<Seg2Info> s2info;
   std::vector<Seg> seg1, seg2;
   std::vector<Tile> tile1, tile2;
   std::vector<Reduce> red2;
@@ -71,6 +125,12 @@ struct Chunk {
   Reduce *d_red2 = nullptr;
   double flops1 = 0.0, flops2 = 0.0;    // algorithmic flops of each launch
   int64_t part_elems = 0;               // partial-tile buffer needed
+  // split precision (filled only for split plans)
+  std::vector<SegS> sseg1, sseg2;
+  std::vector<SliceJob> tjobs;          // stripe slicing after the first stage
+  SegS *d_sseg1 = nullptr, *d_sseg2 = nullptr;
+  SliceJob *d_tjobs = nullptr;
+  int64_t t_elems = 0, t_exps = 0;
 };
 
 constexpr int TILE = 32;      // nominal tile edge (tiles are 16*mb x 64/mb)
@@ -85,5 +145,14 @@ void launch_tiles_f64(int stage, const Tile *tiles, const Seg *segs, int ntiles,
 void launch_reduce(const Reduce *red, int nred, const double *part, double *y, void *stream);
 void launch_diag(const DiagBlock *blocks, const DiagTerm *terms, int nblocks,
                  const double *const *bases, double *diag, void *stream);
+
+}  // namespace dmrg
+
+namespace dmrg {
+void launch_slices(const SliceJob *jobs, int njobs, int nslices, const double *const *bases, const double *psi,
+                   const double *work, SliceBufs bufs, void *stream);
+void launch_tiles_split(int stage, const Tile *tiles, const Seg *segs, const SegS *ssegs, int ntiles,
+                        int nslices, const double *const *bases, const double *psi, double *y, double *work,
+                        double *part, SliceBufs bufs, void *stream);
 
 }  // namespace dmrg

@@ -1,0 +1,81 @@
+"""GPU split-BF16 H.psi (dmrg_apply_H with DMRG_SPLIT_BF16) against the oracle.
+
+Expected error of fixed-point slicing with 8-bit slices: about 2^-8s
+relative to the row/column scales; s = 5 must meet 1e-10 relative (max
+norm), s = 3 is reported but cannot (about 1e-7)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2309_16724_amd.synth.problem import exact_problem, random_problem
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    return t
+
+
+def _apply(torch, prob, x, **kw):
+    from paper_2309_16724_amd.hpsi import Plan
+    plan = Plan(prob, **kw)
+    y = plan.apply(torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    out = y.cpu().numpy()
+    plan.free()
+    return out
+
+
+BOUND = {3: 5e-6, 4: 5e-9, 5: 1e-10, 6: 1e-12, 7: 1e-13}
+
+
+@pytest.mark.parametrize("ns", [3, 4, 5, 6, 7])
+def test_split_matches_oracle_small(torch, ns):
+    from oracle.hpsi import HEff
+    _say("split s=%d" % ns)
+    for prob in (exact_problem(8, 8, 0, 0), random_problem(7, 7, 1, 8, D=300, cap=False)):
+        he = HEff(prob)
+        x = np.random.default_rng(3).standard_normal(he.size)
+        ref = he.apply(x)
+        y = _apply(torch, prob, x, precision=1, n_slices=ns)
+        err = np.abs(y - ref).max() / np.abs(ref).max()
+        _say("  rel err %.3e" % err)
+        assert err <= BOUND[ns]
+
+
+def test_split_equals_host_emulation(torch):
+    """The kernels fold at the same points as the host emulation: equal to rounding."""
+    from paper_2309_16724_amd import binding as B
+    prob = random_problem(8, 8, 0, 4, D=160, cap=False)
+    x = np.random.default_rng(1).standard_normal(
+        B.debug_plan_host_apply(prob, None)[1]["psi_len"])
+    yh, _ = B.debug_plan_host_apply(prob, x, precision=1, n_slices=5)
+    y = _apply(torch, prob, x, precision=1, n_slices=5)
+    assert np.abs(y - yh).max() <= 1e-14 * np.abs(yh).max()
+
+
+def test_split_full_size_vs_oracle(torch):
+    """L=24, D=512 (benchmark workload), s=5: <= 1e-10 relative to the oracle."""
+    from oracle.hpsi import HEff
+    _say("split full size L=24 D=512")
+    prob = random_problem(24, 24, 0, 1, D=512)
+    he = HEff(prob)
+    x = np.random.default_rng(12).standard_normal(he.size)
+    y5 = _apply(torch, prob, x, precision=1, n_slices=5)
+    y64 = _apply(torch, prob, x)
+    _say("gpu done; oracle running")
+    ref = he.apply(x)
+    e5 = np.abs(y5 - ref).max() / np.abs(ref).max()
+    e64 = np.abs(y64 - ref).max() / np.abs(ref).max()
+    _say("rel err split %.3e fp64 %.3e" % (e5, e64))
+    assert e5 <= 1e-10 and e64 <= 1e-12

@@ -114,3 +114,29 @@ def test_error_codes(lib):
     assert _run(lib, prob, bad_npos) == -1
     assert _run(lib, prob, nan_integral) == -6
     assert b"integral" in lib.dmrg_last_error()
+
+
+@pytest.mark.parametrize("ns,bound", [(3, 5e-6), (4, 5e-9), (5, 1e-10), (6, 1e-12)])
+def test_split_plan_host_emulation(lib, ns, bound):
+    """The split-BF16 plan (slices, folds, scales) executed on the CPU."""
+    prob = exact_problem(8, 8, 0, 0)
+    he = HEff(prob)
+    x = np.random.default_rng(13).standard_normal(he.size)
+    ref = he.apply(x)
+    y, st = B.debug_plan_host_apply(prob, x, precision=1, n_slices=ns, lib=lib)
+    err = np.abs(y - ref).max() / np.abs(ref).max()
+    assert err <= bound
+    if ns == 3:
+        assert err > 1e-9        # three 8-bit slices cannot reach 1e-10
+
+
+def test_plan_host_emulation_fp64_and_chunked(lib):
+    prob = random_problem(8, 8, 0, 4, D=120, cap=False)
+    he = HEff(prob)
+    x = np.random.default_rng(2).standard_normal(he.size)
+    ref = he.apply(x)
+    for ws in (0, 1 << 16):
+        y, st = B.debug_plan_host_apply(prob, x, workspace_bytes=ws, lib=lib)
+        assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+        if ws:
+            assert st["n_chunks"] > 1
