@@ -131,14 +131,21 @@ int dmrg_apply_H(dmrg_plan_t *p, const double *psi, double *hpsi, void *stream);
 int dmrg_diag_H(dmrg_plan_t *p, double *diag, void *stream);
 
 /* Davidson solve for the lowest eigenpair of H_eff (paper, Sec. II: the
- * effective Hamiltonian is diagonalised iteratively by Lanczos or Davidson).
- * Single-problem plans.  psi: device array, in = starting vector, out =
- * normalised Ritz vector; evals: host, out = Ritz value.  Block size 1,
- * thick restart to the current and previous Ritz vectors at m_max, two-pass
- * Gram-Schmidt, correction -r/(diag - theta) with |diag - theta| >= floor,
- * stop when ||H u - theta u||_2 <= tol.  Returns DMRG_ENOCONV (with the best
- * pair in psi/evals) when max_iter is reached.  All vector work runs on the
- * GPU in FP64; the m x m projected problem is solved on the host. */
+ * effective Hamiltonian is diagonalised iteratively by Lanczos or Davidson),
+ * for every problem of the plan at once (one segment of psi per problem, as
+ * laid out by dmrg_psi_layout).  psi: device array of psi_len doubles, in =
+ * starting vectors, out = normalised Ritz vector of each problem; evals: host
+ * array of n_probs doubles, out = Ritz values.  Block size 1, thick restart
+ * to the current and previous Ritz vectors at m_max (all problems restart
+ * together), two-pass Gram-Schmidt, correction -r/(diag - theta) with
+ * |diag - theta| >= floor, a problem stops when ||H u - theta u||_2 <= tol
+ * (its segment of later basis vectors is zero).  Returns DMRG_ENOCONV (with
+ * the best pairs in psi/evals) when max_iter is reached before every problem
+ * converged.  All vector work runs on the GPU in FP64 (segmented, fixed-order
+ * reductions: bitwise reproducible); the m x m projected problems are solved
+ * on the host.  stats: iters = most iterations of any problem, converged =
+ * number of converged problems, residual = largest final residual, energy =
+ * Ritz value of problem 0. */
 typedef struct {
   double tol;               /* residual-norm tolerance, e.g. 1e-8            */
   int32_t max_iter;

@@ -1,14 +1,17 @@
 // Davidson eigensolver for the lowest eigenpair of H_eff (paper, Sec. II:
 // the effective Hamiltonian is diagonalised by Lanczos or Davidson, 85-90% of
-// the run time).  Built only on the public H.psi entry points; all vector
-// work runs in the FP64 kernels of kernels_vec.hip, the m x m projected
-// problem (m <= 64) is solved by a cyclic Jacobi sweep on the host.
+// the run time), for every problem of a plan at once.  Built on the public
+// H.psi entry points; all vector work runs in the FP64 kernels of
+// kernels_vec.hip (segmented per problem), the small projected problems
+// (m <= 64) are solved by cyclic Jacobi sweeps on the host.
 //
 // Details the paper leaves open (same reading as the oracle): block size 1;
 // thick restart to the current and previous Ritz vectors when the subspace
 // reaches m_max; two-pass classical Gram-Schmidt; correction
 // t = -r / (diag - theta) with |diag - theta| floored; convergence when
-// ||H u - theta u||_2 <= tol for the normalised Ritz vector u.
+// ||H u - theta u||_2 <= tol for the normalised Ritz vector u.  Problems of a
+// batch share the basis-column index: a converged problem stops adding
+// vectors (its segments of later columns are zero), restarts are global.
 #include <hip/hip_runtime_api.h>
 #include <algorithm>
 #include <chrono>
@@ -41,12 +44,12 @@ void jacobi_eigh(int m, const double *A, double *w, double *Z) {
         double theta = (a[q * m + q] - a[p * m + p]) / (2.0 * apq);
         double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
         double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
-        for (int k = 0; k < m; k++) {   // columns p, q
+        for (int k = 0; k < m; k++) {
           double akp = a[k * m + p], akq = a[k * m + q];
           a[k * m + p] = c * akp - s * akq;
           a[k * m + q] = s * akp + c * akq;
         }
-        for (int k = 0; k < m; k++) {   // rows p, q
+        for (int k = 0; k < m; k++) {
           double apk = a[p * m + k], aqk = a[q * m + k];
           a[p * m + k] = c * apk - s * aqk;
           a[q * m + k] = s * apk + c * aqk;
@@ -58,7 +61,6 @@ void jacobi_eigh(int m, const double *A, double *w, double *Z) {
         }
       }
   }
-  // sort ascending
   std::vector<int> idx(m);
   for (int i = 0; i < m; i++) idx[i] = i;
   std::sort(idx.begin(), idx.end(), [&](int x, int y) { return a[x * m + x] < a[y * m + y]; });
@@ -79,12 +81,13 @@ struct DevBuf {
   ~DevBuf() {
     for (void *p : ptrs) (void)hipFree(p);
   }
-  double *get(int64_t n) {
+  void *raw(int64_t bytes) {
     void *p = nullptr;
-    if (hipMalloc(&p, sizeof(double) * std::max<int64_t>(n, 1)) != hipSuccess) return nullptr;
+    if (hipMalloc(&p, std::max<int64_t>(bytes, 8)) != hipSuccess) return nullptr;
     ptrs.push_back(p);
-    return (double *)p;
+    return p;
   }
+  double *get(int64_t n) { return (double *)raw(sizeof(double) * n); }
 };
 
 #define HIPCHK(x)                                                                    \
@@ -95,6 +98,16 @@ struct DevBuf {
       return DMRG_EHIP;                                                              \
     }                                                                                \
   } while (0)
+
+struct ProbState {
+  int64_t off = 0, len = 0;
+  std::vector<int> cols;          // global basis columns that belong to this problem
+  std::vector<double> G;          // projected matrix over `cols` (row-major, size cols^2)
+  std::vector<double> c;          // Ritz coefficients over `cols`
+  double theta = 0.0, rnorm = 0.0;
+  bool active = true, have_prev = false;
+  int iters = 0;
+};
 
 }  // namespace
 
@@ -108,27 +121,50 @@ extern "C" int dmrg_davidson(dmrg_plan_t *p, double *psi, double *evals, const d
     return DMRG_EINVAL;
   }
   if (opt.precond != 0) { set_error("only the diagonal preconditioner is available"); return DMRG_EINVAL; }
-  int64_t off1, len1;
-  if (dmrg_psi_layout(p, 1, &off1, &len1) == DMRG_OK) {
-    set_error("dmrg_davidson needs a single-problem plan");
-    return DMRG_EINVAL;
+  std::vector<ProbState> P;
+  for (int k = 0;; k++) {
+    int64_t off, len;
+    if (dmrg_psi_layout(p, k, &off, &len) != DMRG_OK) break;
+    ProbState s;
+    s.off = off;
+    s.len = len;
+    P.push_back(s);
   }
+  set_error("");
+  const int np = (int)P.size();
+  if (np == 0) { set_error("empty plan"); return DMRG_EINVAL; }
   dmrg_plan_stats_t ps;
   dmrg_plan_stats(p, &ps);
   const int64_t n = ps.psi_len;
   const int M = opt.m_max;
   hipStream_t s = (hipStream_t)stream;
   auto t_start = std::chrono::steady_clock::now();
+  // chunk table
+  std::vector<VChunk> chunks;
+  std::vector<int32_t> seg0;
+  for (int k = 0; k < np; k++) {
+    seg0.push_back((int32_t)chunks.size());
+    for (int64_t i0 = P[k].off; i0 < P[k].off + P[k].len; i0 += VCHUNK)
+      chunks.push_back({i0, std::min(P[k].off + P[k].len, i0 + VCHUNK), k, 0});
+  }
+  seg0.push_back((int32_t)chunks.size());
   DevBuf buf;
+  VChunk *d_chunks = (VChunk *)buf.raw(sizeof(VChunk) * chunks.size());
+  int32_t *d_seg0 = (int32_t *)buf.raw(sizeof(int32_t) * seg0.size());
   double *V = buf.get((int64_t)M * n), *W = buf.get((int64_t)M * n);
   double *u = buf.get(n), *hu = buf.get(n), *r = buf.get(n), *t = buf.get(n), *uprev = buf.get(n);
   double *diag = buf.get(n), *tmp = buf.get(2 * n);
-  double *part = buf.get(vec_dots_part_len(n, M + 2));
-  double *dout = buf.get(2 * M + 4), *dcoef = buf.get(2 * M + 4);
-  if (!V || !W || !u || !hu || !r || !t || !uprev || !diag || !tmp || !part || !dout || !dcoef) {
+  double *part = buf.get((int64_t)std::max<size_t>(chunks.size(), 1) * (M + 2));
+  double *dout = buf.get((int64_t)np * (M + 2)), *dcoef = buf.get((int64_t)np * M);
+  double *dvec = buf.get(np);
+  if (!d_chunks || !d_seg0 || !V || !W || !u || !hu || !r || !t || !uprev || !diag || !tmp || !part || !dout ||
+      !dcoef || !dvec) {
     set_error("hipMalloc failed in Davidson");
     return DMRG_ENOMEM;
   }
+  HIPCHK(hipMemcpy(d_chunks, chunks.data(), sizeof(VChunk) * chunks.size(), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(d_seg0, seg0.data(), sizeof(int32_t) * seg0.size(), hipMemcpyHostToDevice));
+  VecCtx X{d_chunks, (int)chunks.size(), d_seg0, np, part};
   int rc;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -147,146 +183,224 @@ extern "C" int dmrg_davidson(dmrg_plan_t *p, double *psi, double *evals, const d
     n_hpsi++;
     return DMRG_OK;
   };
-  auto dots_host = [&](const double *Vs, int m, const double *x, double *out) -> int {
-    vec_dots(Vs, n, m, x, n, part, dout, stream);
-    HIPCHK(hipMemcpyAsync(out, dout, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+  // per-problem dot products of m columns of Vs with x: host out[k * m + j]
+  std::vector<double> hout((size_t)np * (M + 2));
+  auto dots_host = [&](const double *Vs, int m, const double *x) -> int {
+    vec_dots(X, Vs, n, m, x, dout, stream);
+    HIPCHK(hipMemcpyAsync(hout.data(), dout, sizeof(double) * np * m, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return DMRG_OK;
   };
+  auto put_vec = [&](const std::vector<double> &v) -> int {
+    HIPCHK(hipMemcpyAsync(dvec, v.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
+    return DMRG_OK;
+  };
+  auto put_coef = [&](const std::vector<double> &cf) -> int {   // np x M row-major
+    HIPCHK(hipMemcpyAsync(dcoef, cf.data(), sizeof(double) * np * M, hipMemcpyHostToDevice, s));
+    return DMRG_OK;
+  };
   if ((rc = dmrg_diag_H(p, diag, stream))) return rc;
-  // starting vector
   HIPCHK(hipMemcpyAsync(V, psi, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-  double nn;
-  if ((rc = dots_host(V, 1, V, &nn))) return rc;
-  if (!(nn > 0.0) || !std::isfinite(nn)) { set_error("starting vector is zero or not finite"); return DMRG_ENONFINITE; }
-  vec_scale(V, 1.0 / std::sqrt(nn), n, stream);
+  if ((rc = dots_host(V, 1, V))) return rc;
+  std::vector<double> sc(np);
+  for (int k = 0; k < np; k++) {
+    double nn = hout[k];
+    if (!(nn > 0.0) || !std::isfinite(nn)) { set_error("starting vector is zero or not finite"); return DMRG_ENONFINITE; }
+    sc[k] = 1.0 / std::sqrt(nn);
+  }
+  if ((rc = put_vec(sc))) return rc;
+  vec_scale(X, dvec, V, stream);
   if ((rc = apply(V, W))) return rc;
-  std::vector<double> G((size_t)M * M, 0.0), w(M), Z((size_t)M * M), col(M + 2), c(M);
-  if ((rc = dots_host(V, 1, W, &G[0]))) return rc;
+  if ((rc = dots_host(V, 1, W))) return rc;
+  for (int k = 0; k < np; k++) {
+    P[k].cols = {0};
+    P[k].G = {hout[k]};
+  }
   int m = 1;
-  bool have_prev = false, converged = false;
-  double theta = 0.0, rnorm = 0.0;
   int it = 0;
-  for (it = 1; it <= opt.max_iter; it++) {
-    std::vector<double> Gm((size_t)m * m);
-    for (int i = 0; i < m; i++)
-      for (int j = 0; j < m; j++) Gm[i * m + j] = 0.5 * (G[i * M + j] + G[j * M + i]);
-    jacobi_eigh(m, Gm.data(), w.data(), Z.data());
-    theta = w[0];
-    for (int i = 0; i < m; i++) c[i] = Z[i * m + 0];
-    if (!std::isfinite(theta)) { set_error("non-finite Ritz value"); return DMRG_ENONFINITE; }
-    HIPCHK(hipMemcpyAsync(dcoef, c.data(), sizeof(double) * m, hipMemcpyHostToDevice, s));
-    vec_combo(V, n, m, dcoef, 1.0, 0.0, u, n, stream);
-    vec_combo(W, n, m, dcoef, 1.0, 0.0, hu, n, stream);
-    vec_resid(hu, u, diag, theta, opt.floor, r, t, n, stream);
-    double rr;
-    if ((rc = dots_host(r, 1, r, &rr))) return rc;
-    rnorm = std::sqrt(rr);
-    if (!std::isfinite(rnorm)) { set_error("non-finite residual"); return DMRG_ENONFINITE; }
-    if (rnorm <= opt.tol) { converged = true; break; }
+  int n_active = np;
+  std::vector<double> coef((size_t)np * M, 0.0), thetas(np, 0.0);
+  for (it = 1; it <= opt.max_iter && n_active > 0; it++) {
+    // Ritz pairs
+    std::fill(coef.begin(), coef.end(), 0.0);
+    for (int k = 0; k < np; k++) {
+      ProbState &S = P[k];
+      if (!S.active) continue;
+      int mk = (int)S.cols.size();
+      std::vector<double> Gm((size_t)mk * mk), w(mk), Z((size_t)mk * mk);
+      for (int i = 0; i < mk; i++)
+        for (int j = 0; j < mk; j++) Gm[i * mk + j] = 0.5 * (S.G[i * mk + j] + S.G[j * mk + i]);
+      jacobi_eigh(mk, Gm.data(), w.data(), Z.data());
+      S.theta = w[0];
+      if (!std::isfinite(S.theta)) { set_error("non-finite Ritz value"); return DMRG_ENONFINITE; }
+      S.c.assign(mk, 0.0);
+      for (int i = 0; i < mk; i++) {
+        S.c[i] = Z[i * mk + 0];
+        coef[(size_t)k * M + S.cols[i]] = S.c[i];
+      }
+      thetas[k] = S.theta;
+    }
+    if ((rc = put_coef(coef)) || (rc = put_vec(thetas))) return rc;
+    vec_combo(X, V, n, m, dcoef, M, 1.0, 0.0, u, stream);
+    vec_combo(X, W, n, m, dcoef, M, 1.0, 0.0, hu, stream);
+    vec_resid(X, hu, u, diag, dvec, opt.floor, r, t, stream);
+    if ((rc = dots_host(r, 1, r))) return rc;
+    for (int k = 0; k < np; k++) {
+      ProbState &S = P[k];
+      if (!S.active) continue;
+      S.iters = it;
+      S.rnorm = std::sqrt(hout[k]);
+      if (!std::isfinite(S.rnorm)) { set_error("non-finite residual"); return DMRG_ENONFINITE; }
+      if (S.rnorm <= opt.tol) {
+        S.active = false;
+        n_active--;
+        HIPCHK(hipMemcpyAsync(psi + S.off, u + S.off, sizeof(double) * S.len, hipMemcpyDeviceToDevice, s));
+      }
+    }
+    if (n_active == 0) break;
     if (m >= M) {
-      // thick restart in coefficient space: span{u, u_prev}
-      std::vector<double> c1(c.begin(), c.begin() + m), c2(m, 0.0);
-      double n1 = 0.0;
-      for (double x : c1) n1 += x * x;
-      for (double &x : c1) x /= std::sqrt(n1);
-      int k = 1;
-      if (have_prev) {
-        if ((rc = dots_host(V, m, uprev, c2.data()))) return rc;
-        for (int pass = 0; pass < 2; pass++) {
-          double d = 0.0;
-          for (int i = 0; i < m; i++) d += c1[i] * c2[i];
-          for (int i = 0; i < m; i++) c2[i] -= d * c1[i];
+      // global thick restart: per problem span{u, u_prev} in coefficient space
+      if ((rc = dots_host(V, m, uprev))) return rc;
+      std::vector<double> c0((size_t)np * M, 0.0), c1((size_t)np * M, 0.0);
+      std::vector<std::vector<double>> Cm(np);
+      std::vector<int> kk(np, 0);
+      for (int k = 0; k < np; k++) {
+        ProbState &S = P[k];
+        if (!S.active) continue;
+        int mk = (int)S.cols.size();
+        std::vector<double> a(S.c), b(mk, 0.0);
+        double na = 0.0;
+        for (double x : a) na += x * x;
+        for (double &x : a) x /= std::sqrt(na);
+        kk[k] = 1;
+        if (S.have_prev) {
+          for (int i = 0; i < mk; i++) b[i] = hout[(size_t)k * m + S.cols[i]];
+          for (int pass = 0; pass < 2; pass++) {
+            double d = 0.0;
+            for (int i = 0; i < mk; i++) d += a[i] * b[i];
+            for (int i = 0; i < mk; i++) b[i] -= d * a[i];
+          }
+          double nb = 0.0;
+          for (double x : b) nb += x * x;
+          if (std::sqrt(nb) > 1e-8) {
+            for (double &x : b) x /= std::sqrt(nb);
+            kk[k] = 2;
+          }
         }
-        double n2 = 0.0;
-        for (double x : c2) n2 += x * x;
-        if (std::sqrt(n2) > 1e-8) {
-          for (double &x : c2) x /= std::sqrt(n2);
-          k = 2;
+        Cm[k].assign((size_t)mk * 2, 0.0);
+        for (int i = 0; i < mk; i++) {
+          Cm[k][i * 2] = a[i];
+          Cm[k][i * 2 + 1] = kk[k] == 2 ? b[i] : 0.0;
+          c0[(size_t)k * M + S.cols[i]] = a[i];
+          c1[(size_t)k * M + S.cols[i]] = kk[k] == 2 ? b[i] : 0.0;
         }
       }
-      // new basis vectors and their images, then the projected matrix Cm^T G Cm
-      std::vector<double> Cm((size_t)m * k);
-      for (int i = 0; i < m; i++) {
-        Cm[i * k + 0] = c1[i];
-        if (k == 2) Cm[i * k + 1] = c2[i];
-      }
-      for (int j = 0; j < k; j++) {
-        std::vector<double> cj(m);
-        for (int i = 0; i < m; i++) cj[i] = Cm[i * k + j];
-        HIPCHK(hipMemcpyAsync(dcoef, cj.data(), sizeof(double) * m, hipMemcpyHostToDevice, s));
-        vec_combo(V, n, m, dcoef, 1.0, 0.0, tmp + (int64_t)j * n, n, stream);
+      for (int j = 0; j < 2; j++) {
+        if ((rc = put_coef(j == 0 ? c0 : c1))) return rc;
+        vec_combo(X, V, n, m, dcoef, M, 1.0, 0.0, tmp + (int64_t)j * n, stream);
         HIPCHK(hipStreamSynchronize(s));
       }
-      for (int j = 0; j < k; j++)
-        HIPCHK(hipMemcpyAsync(V + (int64_t)j * n, tmp + (int64_t)j * n, sizeof(double) * n,
-                              hipMemcpyDeviceToDevice, s));
-      for (int j = 0; j < k; j++) {
-        std::vector<double> cj(m);
-        for (int i = 0; i < m; i++) cj[i] = Cm[i * k + j];
-        HIPCHK(hipMemcpyAsync(dcoef, cj.data(), sizeof(double) * m, hipMemcpyHostToDevice, s));
-        vec_combo(W, n, m, dcoef, 1.0, 0.0, tmp + (int64_t)j * n, n, stream);
+      HIPCHK(hipMemcpyAsync(V, tmp, sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, s));
+      for (int j = 0; j < 2; j++) {
+        if ((rc = put_coef(j == 0 ? c0 : c1))) return rc;
+        vec_combo(X, W, n, m, dcoef, M, 1.0, 0.0, tmp + (int64_t)j * n, stream);
         HIPCHK(hipStreamSynchronize(s));
       }
-      for (int j = 0; j < k; j++)
-        HIPCHK(hipMemcpyAsync(W + (int64_t)j * n, tmp + (int64_t)j * n, sizeof(double) * n,
-                              hipMemcpyDeviceToDevice, s));
-      std::vector<double> Gn((size_t)M * M, 0.0);
-      for (int a = 0; a < k; a++)
-        for (int b = 0; b < k; b++) {
-          double x = 0.0;
-          for (int i = 0; i < m; i++)
-            for (int j = 0; j < m; j++) x += Cm[i * k + a] * Gm[i * m + j] * Cm[j * k + b];
-          Gn[a * M + b] = x;
-        }
-      G.swap(Gn);
-      m = k;
+      HIPCHK(hipMemcpyAsync(W, tmp, sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, s));
+      for (int k = 0; k < np; k++) {
+        ProbState &S = P[k];
+        if (!S.active) { S.cols.clear(); continue; }
+        int mk = (int)S.cols.size(), q = kk[k];
+        std::vector<double> Gn((size_t)q * q, 0.0);
+        for (int a = 0; a < q; a++)
+          for (int b = 0; b < q; b++) {
+            double x = 0.0;
+            for (int i = 0; i < mk; i++)
+              for (int j = 0; j < mk; j++)
+                x += Cm[k][i * 2 + a] * 0.5 * (S.G[i * mk + j] + S.G[j * mk + i]) * Cm[k][j * 2 + b];
+            Gn[a * q + b] = x;
+          }
+        S.G = Gn;
+        S.cols.clear();
+        for (int a = 0; a < q; a++) S.cols.push_back(a);
+      }
+      m = 2;
     }
     // two-pass classical Gram-Schmidt of t against V[0:m), written into V[m]
     double *vt = V + (int64_t)m * n;
     HIPCHK(hipMemcpyAsync(vt, t, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     for (int pass = 0; pass < 2; pass++) {
-      vec_dots(V, n, m, vt, n, part, dout, stream);
-      vec_combo(V, n, m, dout, -1.0, 1.0, vt, n, stream);
+      vec_dots(X, V, n, m, vt, dout, stream);
+      vec_combo(X, V, n, m, dout, m, -1.0, 1.0, vt, stream);
     }
-    double tt;
-    if ((rc = dots_host(vt, 1, vt, &tt))) return rc;
-    if (!(std::sqrt(tt) >= 1e-12)) {
-      HIPCHK(hipMemcpyAsync(vt, r, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-      for (int pass = 0; pass < 2; pass++) {
-        vec_dots(V, n, m, vt, n, part, dout, stream);
-        vec_combo(V, n, m, dout, -1.0, 1.0, vt, n, stream);
+    if ((rc = dots_host(vt, 1, vt))) return rc;
+    bool refill = false;
+    for (int k = 0; k < np; k++)
+      if (P[k].active && !(std::sqrt(hout[k]) >= 1e-12)) {
+        HIPCHK(hipMemcpyAsync(vt + P[k].off, r + P[k].off, sizeof(double) * P[k].len, hipMemcpyDeviceToDevice, s));
+        refill = true;
       }
-      if ((rc = dots_host(vt, 1, vt, &tt))) return rc;
-      if (!(tt > 0.0)) { set_error("Davidson subspace collapsed"); return DMRG_ENOCONV; }
+    if (refill) {
+      for (int pass = 0; pass < 2; pass++) {
+        vec_dots(X, V, n, m, vt, dout, stream);
+        vec_combo(X, V, n, m, dout, m, -1.0, 1.0, vt, stream);
+      }
+      if ((rc = dots_host(vt, 1, vt))) return rc;
     }
-    vec_scale(vt, 1.0 / std::sqrt(tt), n, stream);
+    for (int k = 0; k < np; k++) {
+      if (!P[k].active) { sc[k] = 0.0; continue; }
+      if (!(hout[k] > 0.0)) { set_error("Davidson subspace collapsed"); return DMRG_ENOCONV; }
+      sc[k] = 1.0 / std::sqrt(hout[k]);
+    }
+    if ((rc = put_vec(sc))) return rc;
+    vec_scale(X, dvec, vt, stream);
     if ((rc = apply(vt, W + (int64_t)m * n))) return rc;
-    if ((rc = dots_host(V, m + 1, W + (int64_t)m * n, col.data()))) return rc;
-    for (int i = 0; i <= m; i++) {
-      G[i * M + m] = col[i];
-      G[m * M + i] = col[i];
+    if ((rc = dots_host(V, m + 1, W + (int64_t)m * n))) return rc;
+    for (int k = 0; k < np; k++) {
+      ProbState &S = P[k];
+      if (!S.active) continue;
+      int mk = (int)S.cols.size();
+      std::vector<double> Gn((size_t)(mk + 1) * (mk + 1), 0.0);
+      for (int i = 0; i < mk; i++)
+        for (int j = 0; j < mk; j++) Gn[i * (mk + 1) + j] = S.G[i * mk + j];
+      for (int i = 0; i < mk; i++) {
+        double x = hout[(size_t)k * (m + 1) + S.cols[i]];
+        Gn[i * (mk + 1) + mk] = x;
+        Gn[mk * (mk + 1) + i] = x;
+      }
+      Gn[mk * (mk + 1) + mk] = hout[(size_t)k * (m + 1) + m];
+      S.G = Gn;
+      S.cols.push_back(m);
+      S.have_prev = true;
     }
     m++;
     HIPCHK(hipMemcpyAsync(uprev, u, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    have_prev = true;
   }
-  // return the Ritz vector (normalised) and value
-  HIPCHK(hipMemcpyAsync(psi, u, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  // problems still active: return their best pair
+  for (int k = 0; k < np; k++)
+    if (P[k].active)
+      HIPCHK(hipMemcpyAsync(psi + P[k].off, u + P[k].off, sizeof(double) * P[k].len, hipMemcpyDeviceToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
-  evals[0] = theta;
+  int conv = 0, maxit = 0;
+  double maxres = 0.0;
+  for (int k = 0; k < np; k++) {
+    evals[k] = P[k].theta;
+    conv += !P[k].active;
+    maxit = std::max(maxit, P[k].iters);
+    maxres = std::max(maxres, P[k].rnorm);
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st) {
     std::memset(st, 0, sizeof(*st));
-    st->iters = converged ? it : opt.max_iter;
+    st->iters = maxit;
     st->n_hpsi = n_hpsi;
-    st->converged = converged ? 1 : 0;
-    st->residual = rnorm;
-    st->energy = theta;
+    st->converged = conv;
+    st->residual = maxres;
+    st->energy = P[0].theta;
     st->t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     st->t_hpsi_s = t_hpsi;
   }
-  if (!converged) { set_error("Davidson did not converge; best Ritz pair returned"); return DMRG_ENOCONV; }
+  if (conv < np) { set_error("Davidson did not converge for every problem; best Ritz pairs returned"); return DMRG_ENOCONV; }
   return DMRG_OK;
 }

@@ -1,16 +1,32 @@
-// Davidson solver: device vector kernels (kernels_vec.hip) and the host loop.
+// Davidson solver: segmented device vector kernels (kernels_vec.hip) and
+// the host loop (davidson.cpp).
 #pragma once
 #include <cstdint>
 
 namespace dmrg {
-void vec_dots(const double *V, int64_t ldv, int m, const double *x, int64_t n, double *part, double *out,
-              void *stream);
-int64_t vec_dots_part_len(int64_t n, int m);
-void vec_combo(const double *V, int64_t ldv, int m, const double *c, double sign, double beta, double *y,
-               int64_t n, void *stream);
-void vec_resid(const double *hu, const double *u, const double *diag, double theta, double floor_, double *r,
-               double *t, int64_t n, void *stream);
-void vec_scale(double *x, double s, int64_t n, void *stream);
+
+constexpr int64_t VCHUNK = 4096;   // vector elements per chunk
+
+struct VChunk {
+  int64_t i0, i1;   // element range, inside one segment
+  int32_t seg, pad;
+};
+
+// device chunk table of a concatenated vector and a partial-sum buffer
+struct VecCtx {
+  const VChunk *chunks;
+  int nchunks;
+  const int32_t *seg_chunk0;   // [nseg + 1] first chunk of every segment
+  int nseg;
+  double *part;                // >= nchunks * (max m) doubles
+};
+
+void vec_dots(const VecCtx &X, const double *V, int64_t ldv, int m, const double *x, double *out, void *stream);
+void vec_combo(const VecCtx &X, const double *V, int64_t ldv, int m, const double *coef, int ldc, double sign,
+               double beta, double *y, void *stream);
+void vec_resid(const VecCtx &X, const double *hu, const double *u, const double *diag, const double *theta,
+               double floor_, double *r, double *t, void *stream);
+void vec_scale(const VecCtx &X, const double *s, double *x, void *stream);
 // cyclic Jacobi eigensolver of a symmetric m x m matrix (row-major); returns
 // eigenvalues ascending in w and the matching eigenvectors as columns of Z
 void jacobi_eigh(int m, const double *A, double *w, double *Z);

@@ -1,101 +1,118 @@
-// FP64 vector kernels of the Davidson solver.  Reductions are two-pass
-// (per-block partial sums, then a fixed-order sum), so results are bitwise
-// reproducible.
+// FP64 vector kernels of the Davidson solver.  Vectors are concatenations of
+// one segment per problem; work is cut into chunks that never cross a
+// segment, and every reduction is two-pass (per-chunk partial sums, then a
+// fixed-order sum per segment), so results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 #include "davidson.hpp"
 
 namespace dmrg {
 
 constexpr int VB = 256;          // threads per block
-constexpr int VCHUNK = 4096;     // vector elements per block in the dot kernel
 
-// part[b * m + j] = sum_{i in chunk b} V[j * ldv + i] * x[i], j < m
-__global__ void __launch_bounds__(VB) dots_kernel(const double *__restrict__ V, int64_t ldv, int m,
-                                                   const double *__restrict__ x, int64_t n,
-                                                   double *__restrict__ part) {
+// part[c * m + j] = sum_{i in chunk c} V[j * ldv + i] * x[i], j < m
+__global__ void __launch_bounds__(VB) sdots_kernel(const VChunk *__restrict__ chunks, int nchunks,
+                                                    const double *__restrict__ V, int64_t ldv, int m,
+                                                    const double *__restrict__ x, double *__restrict__ part) {
   __shared__ double red[VB];
-  const int64_t i0 = (int64_t)blockIdx.x * VCHUNK;
-  const int64_t i1 = min(n, i0 + VCHUNK);
-  for (int j = 0; j < m; j++) {
-    double acc = 0.0;
-    const double *v = V + (int64_t)j * ldv;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += VB) acc += v[i] * x[i];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = VB / 2; s > 0; s >>= 1) {
-      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+  for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const VChunk C = chunks[c];
+    for (int j = 0; j < m; j++) {
+      double acc = 0.0;
+      const double *v = V + (int64_t)j * ldv;
+      for (int64_t i = C.i0 + threadIdx.x; i < C.i1; i += VB) acc += v[i] * x[i];
+      red[threadIdx.x] = acc;
+      __syncthreads();
+      for (int s = VB / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) part[(int64_t)c * m + j] = red[0];
       __syncthreads();
     }
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * m + j] = red[0];
-    __syncthreads();
   }
 }
 
-// out[j] = sum_b part[b * m + j], in block order
-__global__ void dots_finish_kernel(const double *__restrict__ part, int nb, int m, double *__restrict__ out) {
-  int j = threadIdx.x;
-  if (j < m) {
+// out[k * m + j] = sum of the partials of segment k's chunks, in chunk order
+__global__ void sdots_finish_kernel(const int32_t *__restrict__ seg_chunk0, int nseg, int m,
+                                    const double *__restrict__ part, double *__restrict__ out) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nseg * m; t += gridDim.x * blockDim.x) {
+    int k = t / m, j = t - k * m;
     double s = 0.0;
-    for (int b = 0; b < nb; b++) s += part[(int64_t)b * m + j];
-    out[j] = s;
+    for (int c = seg_chunk0[k]; c < seg_chunk0[k + 1]; c++) s += part[(int64_t)c * m + j];
+    out[t] = s;
   }
 }
 
-// y[i] = beta * y[i] + sign * sum_j c[j] V[j * ldv + i]   (c on the device)
-__global__ void __launch_bounds__(VB) combo_kernel(const double *__restrict__ V, int64_t ldv, int m,
-                                                    const double *__restrict__ c, double sign, double beta,
-                                                    double *__restrict__ y, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) {
-    double acc = 0.0;
-    for (int j = 0; j < m; j++) acc += c[j] * V[(int64_t)j * ldv + i];
-    y[i] = (beta == 0.0 ? 0.0 : beta * y[i]) + sign * acc;
+// y[i] = beta y[i] + sign * sum_j coef[k * ldc + j] V[j * ldv + i]   (k = segment of i)
+__global__ void __launch_bounds__(VB) scombo_kernel(const VChunk *__restrict__ chunks, int nchunks,
+                                                     const double *__restrict__ V, int64_t ldv, int m,
+                                                     const double *__restrict__ coef, int ldc, double sign,
+                                                     double beta, double *__restrict__ y) {
+  for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const VChunk C = chunks[c];
+    const double *cf = coef + (int64_t)C.seg * ldc;
+    for (int64_t i = C.i0 + threadIdx.x; i < C.i1; i += VB) {
+      double acc = 0.0;
+      for (int j = 0; j < m; j++) acc += cf[j] * V[(int64_t)j * ldv + i];
+      y[i] = (beta == 0.0 ? 0.0 : beta * y[i]) + sign * acc;
+    }
   }
 }
 
-// r = hu - theta u ; t = -r / (diag - theta) with |denominator| >= floor
-__global__ void __launch_bounds__(VB) resid_kernel(const double *__restrict__ hu, const double *__restrict__ u,
-                                                    const double *__restrict__ diag, double theta, double floor_,
-                                                    double *__restrict__ r, double *__restrict__ t, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) {
-    double ri = hu[i] - theta * u[i];
-    double d = diag[i] - theta;
-    if (fabs(d) < floor_) d = d < 0.0 ? -floor_ : floor_;
-    r[i] = ri;
-    t[i] = -ri / d;
+// r = hu - theta_k u ; t = -r / (diag - theta_k) with |denominator| >= floor
+__global__ void __launch_bounds__(VB) sresid_kernel(const VChunk *__restrict__ chunks, int nchunks,
+                                                     const double *__restrict__ hu, const double *__restrict__ u,
+                                                     const double *__restrict__ diag,
+                                                     const double *__restrict__ theta, double floor_,
+                                                     double *__restrict__ r, double *__restrict__ t) {
+  for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const VChunk C = chunks[c];
+    const double th = theta[C.seg];
+    for (int64_t i = C.i0 + threadIdx.x; i < C.i1; i += VB) {
+      double ri = hu[i] - th * u[i];
+      double d = diag[i] - th;
+      if (fabs(d) < floor_) d = d < 0.0 ? -floor_ : floor_;
+      r[i] = ri;
+      t[i] = -ri / d;
+    }
   }
 }
 
-// x *= s
-__global__ void __launch_bounds__(VB) scale_kernel(double *__restrict__ x, double s, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) x[i] *= s;
+// x[i] *= s_k
+__global__ void __launch_bounds__(VB) sscale_kernel(const VChunk *__restrict__ chunks, int nchunks,
+                                                     const double *__restrict__ s, double *__restrict__ x) {
+  for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const VChunk C = chunks[c];
+    const double f = s[C.seg];
+    for (int64_t i = C.i0 + threadIdx.x; i < C.i1; i += VB) x[i] *= f;
+  }
 }
 
-static int vgrid(int64_t n) { return (int)std::min<int64_t>((n + VB - 1) / VB, 8192); }
+static int cgrid(int nchunks) { return std::min(std::max(nchunks, 1), 16384); }
 
-void vec_dots(const double *V, int64_t ldv, int m, const double *x, int64_t n, double *part, double *out,
-              void *stream) {
-  int nb = (int)((n + VCHUNK - 1) / VCHUNK);
-  if (nb < 1) nb = 1;
-  hipLaunchKernelGGL(dots_kernel, dim3(nb), dim3(VB), 0, (hipStream_t)stream, V, ldv, m, x, n, part);
-  hipLaunchKernelGGL(dots_finish_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, part, nb, m, out);
+void vec_dots(const VecCtx &X, const double *V, int64_t ldv, int m, const double *x, double *out, void *stream) {
+  hipLaunchKernelGGL(sdots_kernel, dim3(cgrid(X.nchunks)), dim3(VB), 0, (hipStream_t)stream, X.chunks, X.nchunks,
+                     V, ldv, m, x, X.part);
+  int tot = X.nseg * m;
+  hipLaunchKernelGGL(sdots_finish_kernel, dim3(std::max(1, (tot + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                     X.seg_chunk0, X.nseg, m, X.part, out);
 }
 
-int64_t vec_dots_part_len(int64_t n, int m) { return ((n + VCHUNK - 1) / VCHUNK + 1) * (int64_t)m; }
-
-void vec_combo(const double *V, int64_t ldv, int m, const double *c, double sign, double beta, double *y,
-               int64_t n, void *stream) {
-  hipLaunchKernelGGL(combo_kernel, dim3(vgrid(n)), dim3(VB), 0, (hipStream_t)stream, V, ldv, m, c, sign, beta, y,
-                     n);
+void vec_combo(const VecCtx &X, const double *V, int64_t ldv, int m, const double *coef, int ldc, double sign,
+               double beta, double *y, void *stream) {
+  hipLaunchKernelGGL(scombo_kernel, dim3(cgrid(X.nchunks)), dim3(VB), 0, (hipStream_t)stream, X.chunks, X.nchunks,
+                     V, ldv, m, coef, ldc, sign, beta, y);
 }
 
-void vec_resid(const double *hu, const double *u, const double *diag, double theta, double floor_, double *r,
-               double *t, int64_t n, void *stream) {
-  hipLaunchKernelGGL(resid_kernel, dim3(vgrid(n)), dim3(VB), 0, (hipStream_t)stream, hu, u, diag, theta, floor_,
-                     r, t, n);
+void vec_resid(const VecCtx &X, const double *hu, const double *u, const double *diag, const double *theta,
+               double floor_, double *r, double *t, void *stream) {
+  hipLaunchKernelGGL(sresid_kernel, dim3(cgrid(X.nchunks)), dim3(VB), 0, (hipStream_t)stream, X.chunks, X.nchunks,
+                     hu, u, diag, theta, floor_, r, t);
 }
 
-void vec_scale(double *x, double s, int64_t n, void *stream) {
-  hipLaunchKernelGGL(scale_kernel, dim3(vgrid(n)), dim3(VB), 0, (hipStream_t)stream, x, s, n);
+void vec_scale(const VecCtx &X, const double *s, double *x, void *stream) {
+  hipLaunchKernelGGL(sscale_kernel, dim3(cgrid(X.nchunks)), dim3(VB), 0, (hipStream_t)stream, X.chunks, X.nchunks,
+                     s, x);
 }
 
 }  // namespace dmrg

@@ -86,22 +86,25 @@ class Plan:
 
     def davidson(self, psi0, tol=1e-8, max_iter=1000, m_max=24, floor=1e-8, stream=None,
                  check=True):
-        """Lowest eigenpair by the library's Davidson solver.
+        """Lowest eigenpair of every problem by the library's Davidson solver.
 
-        psi0: CUDA float64 tensor (starting vector, not modified).  Returns
-        (energy, psi, stats dict).  With check=False a non-converged run
-        returns its best pair instead of raising."""
+        psi0: CUDA float64 tensor (starting vectors, not modified).  Returns
+        (energy, psi, stats dict): energy is the Ritz value of a single-problem
+        plan, else the list of Ritz values, one per problem.  With check=False
+        a non-converged run returns its best pairs instead of raising."""
         torch = _torch()
+        assert psi0.dtype == torch.float64 and psi0.is_cuda and psi0.numel() == self.size
         psi = psi0.detach().clone().contiguous()
-        ev = ctypes.c_double()
+        ev = (ctypes.c_double * len(self.problems))()
         st = B.DavStats()
         opts = B.DavOpts(tol, max_iter, m_max, 0, floor, 0)
-        rc = self.lib.dmrg_davidson(self.handle, ctypes.c_void_p(psi.data_ptr()), ctypes.byref(ev),
+        rc = self.lib.dmrg_davidson(self.handle, ctypes.c_void_p(psi.data_ptr()), ev,
                                     ctypes.byref(opts), ctypes.byref(st), self._stream(stream))
         if rc != 0 and (check or rc != -7):
             B.check(rc, self.lib)
         torch.cuda.synchronize(self.device)
-        return ev.value, psi, st.as_dict()
+        evs = list(ev)
+        return (evs[0] if len(evs) == 1 else evs), psi, st.as_dict()
 
     def set_profiling(self, on=True):
         B.check(self.lib.dmrg_set_profiling(self.handle, 1 if on else 0), self.lib)

@@ -536,3 +536,23 @@ def random_vector(size, seed):
     """Seeded normalised starting vector (the Davidson initial guess)."""
     v = np.random.default_rng(seed).standard_normal(size)
     return v / np.linalg.norm(v)
+
+
+def batch_specs(n, seed, L_range=(16, 32), D_range=(128, 768), spins=(0, 1)):
+    """(L, N, 2S, seed, D) of n independent solves: L and D uniform over the
+    inclusive ranges, N = L electrons, S drawn from `spins` for even N and
+    shifted by 1/2 for odd N (no state of odd N has integer spin)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        L = int(rng.integers(L_range[0], L_range[1] + 1))
+        D = int(rng.integers(D_range[0], D_range[1] + 1))
+        two_s = 2 * int(rng.choice(spins)) + (L % 2)
+        out.append((L, L, two_s, seed * 1000 + k, D))
+    return out
+
+
+def batch_problems(n, seed, L_range=(16, 32), D_range=(128, 768), spins=(0, 1)):
+    """Seeded batch of random middle-bond problems from batch_specs."""
+    return [random_problem(L, N, s2, sd, D=D)
+            for L, N, s2, sd, D in batch_specs(n, seed, L_range, D_range, spins)]

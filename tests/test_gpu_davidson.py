@@ -54,7 +54,7 @@ def test_fci_energy_L8_triplet(torch):
 @pytest.mark.parametrize("kind,args,kw", [
     ("exact", (8, 8, 0, 0), dict(max_mult=32)),
     ("random", (6, 6, 0, 5), dict(D=60)),
-    ("random", (7, 7, 1, 6), dict(D=120, cap=False)),
+    ("random", (7, 7, 1, 6), dict(D=30, cap=False)),
 ])
 def test_energy_matches_dense_oracle(torch, kind, args, kw):
     from oracle.hpsi import HEff
