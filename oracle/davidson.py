@@ -17,8 +17,13 @@ def _orth(V, t, passes=2):
     return t
 
 
-def davidson(hop, diag, x0, tol=1e-8, max_iter=1000, m_max=24, floor=1e-8):
-    """Return (theta, u, n_iter, residual_norm, n_hop)."""
+def davidson(hop, diag, x0, tol=1e-8, max_iter=1000, m_max=24, floor=1e-8, precond=None,
+             record=None):
+    """Return (theta, u, n_iter, residual_norm, n_hop).
+
+    precond(r, u, theta) -> t replaces the diagonal correction when given;
+    record, a list, receives (r, u, theta) of every iteration that takes a
+    correction step."""
     x = np.asarray(x0, dtype=float)
     x = x / np.linalg.norm(x)
     V = x[:, None]
@@ -38,9 +43,14 @@ def davidson(hop, diag, x0, tol=1e-8, max_iter=1000, m_max=24, floor=1e-8):
         rn = np.linalg.norm(r)
         if rn <= tol:
             return theta, u, it, rn, n_hop
-        den = diag - theta
-        den = np.where(np.abs(den) < floor, np.where(den < 0, -floor, floor), den)
-        t = -r / den
+        if record is not None:
+            record.append((r.copy(), u.copy(), theta))
+        if precond is None:
+            den = diag - theta
+            den = np.where(np.abs(den) < floor, np.where(den < 0, -floor, floor), den)
+            t = -r / den
+        else:
+            t = precond(r, u, theta)
         if V.shape[1] >= m_max:
             # thick restart to span{u, u_prev}, orthonormalised in the
             # coefficient space of the orthonormal basis V
