@@ -19,11 +19,15 @@ here and by the HIP kernels:
   (the step that would converge in one iteration).  One row per element with
   a_i = td_i s, b_i = t*_i s, s = sqrt(n) / ||t*_k||, and the loss is the mean
   over rows of (a_i (1 + g_i) - b_i)^2, so every record weighs the same.
+  Rows whose |a_i| exceeds A_MAX (elements with a nearly vanishing
+  denominator) are scaled by A_MAX / |a_i|: the row keeps its optimum
+  g = b/a - 1 but cannot dominate the least-squares fit.
 * Adam with bias correction.
 """
 import numpy as np
 
 N_IN = 2
+A_MAX = 10.0
 
 
 def n_params(n_in, width):
@@ -112,8 +116,10 @@ def training_rows(diag, r, u, theta, psi_star, floor=1e-8):
     """(x, a, b) of one Davidson iteration given the converged vector."""
     ts = psi_star / (u @ psi_star) - u
     s = np.sqrt(ts.size) / np.linalg.norm(ts)
-    td = diagonal_step(diag, r, theta, floor)
-    return features(diag, r, theta), td * s, ts * s
+    a = diagonal_step(diag, r, theta, floor) * s
+    b = ts * s
+    w = np.minimum(1.0, A_MAX / np.maximum(np.abs(a), 1e-300))
+    return features(diag, r, theta), a * w, b * w
 
 
 def mlp_step(p, width, diag, r, theta, floor=1e-8):

@@ -96,6 +96,20 @@ def test_features_and_rows_by_hand():
     assert np.allclose(a, -np.array([0.0, 1.0, 1.0]) / np.array([0.5, 1.5, 2.5]) * np.sqrt(3) / 0.5)
 
 
+def test_row_weight_cap():
+    """A row with |a| > A_MAX is scaled to |a| = A_MAX, keeping b/a."""
+    u = np.array([1.0, 0.0, 0.0, 0.0])
+    e = np.array([0.0, 0.5, 0.5, 0.5])
+    d = np.array([1.0, 2.0, 0.5 + 1e-6, 3.0])     # element 2: denominator 1e-6
+    r = np.array([0.0, 1.0, 1.0, 1.0])
+    x, a, b = mlp.training_rows(d, r, u, 0.5, (u + e) / np.linalg.norm(u + e))
+    s = np.sqrt(4) / np.linalg.norm(e)
+    raw_a = -r / (d - 0.5) * s
+    assert abs(abs(a[2]) - mlp.A_MAX) < 1e-12
+    assert abs(b[2] / a[2] - (e[2] * s) / raw_a[2]) < 1e-12
+    assert np.allclose(a[[1, 3]], raw_a[[1, 3]]) and np.allclose(b[[1, 3]], e[[1, 3]] * s)
+
+
 def test_zero_network_is_diagonal_davidson():
     prob = random_problem(6, 6, 0, 5, D=60)
     H = HEff(prob).dense()
