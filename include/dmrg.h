@@ -146,14 +146,18 @@ int dmrg_diag_H(dmrg_plan_t *p, double *diag, void *stream);
  * on the host.  stats: iters = most iterations of any problem, converged =
  * number of converged problems, residual = largest final residual, energy =
  * Ritz value of problem 0. */
+typedef struct dmrg_mlp dmrg_mlp_t;
+enum { DMRG_PRECOND_DIAG = 0, DMRG_PRECOND_MLP = 1 };
 typedef struct {
   double tol;               /* residual-norm tolerance, e.g. 1e-8            */
   int32_t max_iter;
   int32_t m_max;            /* subspace size, 3..64 (24 by default)         */
-  int32_t precond;          /* 0: diagonal                                   */
+  int32_t precond;          /* DMRG_PRECOND_DIAG or DMRG_PRECOND_MLP         */
   double floor;             /* preconditioner denominator floor, e.g. 1e-8   */
-  int64_t reserved;
+  const dmrg_mlp_t *mlp;    /* network for DMRG_PRECOND_MLP, else NULL       */
 } dmrg_dav_opts_t;
+/* fallbacks: learned corrections rejected by the guard (non-finite, or
+ * |cos(t_mlp, t_diag)| < DMRG_MLP_GUARD) and replaced by the diagonal step. */
 typedef struct {
   int32_t iters, n_hpsi, converged, fallbacks;
   double residual, energy;
@@ -163,6 +167,61 @@ int dmrg_davidson(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opt
                   dmrg_dav_stats_t *st, void *stream);
 
 int dmrg_plan_stats(const dmrg_plan_t *p, dmrg_plan_stats_t *st);
+
+/* ---- learned Davidson preconditioner ------------------------------------
+ * The paper leaves the Davidson details open (Sec. II).  This optional
+ * preconditioner corrects the diagonal step per element with a 3-layer
+ * perceptron: t_i = td_i (1 + g(x_i)), td_i = -r_i / (d_i - theta) (floored),
+ * g(x) = w3 . relu(W2 relu(W1 x + b1) + b2) + b3, inputs
+ * x_i = (asinh((d_i - theta)/sigma), log10(||r||)/8), sigma the root mean
+ * square of d - theta over the problem.  Parameters are FP32 on the device,
+ * one flat vector: W1[DMRG_MLP_IN][w], b1[w], W2[w][w], b2[w], w3[w], b3
+ * (row-major, W[k][j] maps input k to unit j).  Training data are exact
+ * corrections of converged solves: at iteration k, t*_k = psi* / <u_k|psi*> - u_k;
+ * each element gives a row x, a = td s, b = t* s with s = sqrt(n)/||t*_k||,
+ * both scaled by DMRG_MLP_A_MAX/|a| where |a| exceeds DMRG_MLP_A_MAX (keeps
+ * the row's optimum, bounds its weight); the loss is mean (a (1 + g) - b)^2
+ * over rows.  Widths 32, 64, 128, 256.  */
+enum { DMRG_MLP_IN = 2 };
+#define DMRG_MLP_A_MAX 10.0
+#define DMRG_MLP_GUARD 1e-3
+/* New network, parameters drawn from a seeded generator (He scaling), Adam
+ * state zero.  Device memory is allocated here and by dmrg_mlp_train. */
+int dmrg_mlp_create(int32_t width, uint64_t seed, dmrg_mlp_t **out);
+int64_t dmrg_mlp_num_params(const dmrg_mlp_t *m);
+/* Host <-> device parameter copies of exactly num_params floats; setting the
+ * parameters resets the Adam state. */
+int dmrg_mlp_set_params(dmrg_mlp_t *m, const float *host, int64_t n);
+int dmrg_mlp_get_params(const dmrg_mlp_t *m, float *host, int64_t n);
+/* g[i] := network output for row x[i] (device arrays x[n][2], g[n]). */
+int dmrg_mlp_forward(dmrg_mlp_t *m, const float *x, int64_t n, float *g, void *stream);
+/* loss (host) and its gradient (device array of num_params floats) over the
+ * n rows (x, a, b) (device arrays), by back-propagation. */
+int dmrg_mlp_loss_grad(dmrg_mlp_t *m, const float *x, const float *a, const float *b, int64_t n,
+                       double *loss, float *grad, void *stream);
+/* One Adam update with the gradient grad (device), bias-corrected with the
+ * network's own step counter (incremented first). */
+int dmrg_mlp_adam_step(dmrg_mlp_t *m, const float *grad, float lr, float beta1, float beta2, float eps,
+                       void *stream);
+typedef struct {
+  float lr, beta1, beta2, eps;
+  int32_t batch;            /* rows per step, drawn with replacement         */
+  int32_t steps;
+  uint64_t seed;            /* minibatch index generator (SplitMix64)         */
+} dmrg_mlp_train_opts_t;
+/* Minibatch Adam training on n rows (device arrays x[n][2], a[n], b[n]);
+ * loss_trace: host array of `steps` floats or NULL. */
+int dmrg_mlp_train(dmrg_mlp_t *m, const float *x, const float *a, const float *b, int64_t n,
+                   const dmrg_mlp_train_opts_t *o, float *loss_trace, void *stream);
+/* Training rows from one single-problem plan: solve to convergence from psi0
+ * (device, not modified) with the diagonal preconditioner, then repeat the
+ * identical solve recording the rows of every iteration whose overlap
+ * |<u_k|psi*>| >= 1e-3.  x (device [capacity][2]), a, b (device [capacity]);
+ * rows beyond capacity are dropped (whole iterations).  Outputs the number of
+ * rows and recorded iterations. */
+int dmrg_mlp_collect(dmrg_plan_t *p, const double *psi0, const dmrg_dav_opts_t *o, int64_t capacity,
+                     float *x, float *a, float *b, int64_t *n_rows, int32_t *n_records, void *stream);
+void dmrg_mlp_free(dmrg_mlp_t *m);
 
 /* Profiling: when on, dmrg_apply_H records a hipEvent pair on its stream
  * around each first-stage (stage 1) and second-stage (stage 2) kernel launch.

@@ -42,7 +42,18 @@ class PlanOpts(ctypes.Structure):
 
 class DavOpts(ctypes.Structure):
     _fields_ = [("tol", c_dbl), ("max_iter", c_i32), ("m_max", c_i32), ("precond", c_i32),
-                ("floor", c_dbl), ("reserved", c_i64)]
+                ("floor", c_dbl), ("mlp", c_vp)]
+
+
+DMRG_PRECOND_DIAG = 0
+DMRG_PRECOND_MLP = 1
+DMRG_MLP_IN = 2
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("batch", c_i32), ("steps", c_i32),
+                ("seed", ctypes.c_uint64)]
 
 
 class DavStats(ctypes.Structure):
@@ -103,6 +114,22 @@ def load(path=None):
                                        ctypes.POINTER(c_dbl)]
         L.dmrg_debug_plan_host_apply.argtypes = [ctypes.POINTER(ProblemT), c_vp, c_vp,
                                                  ctypes.POINTER(PlanOpts), ctypes.POINTER(PlanStats)]
+        c_f = ctypes.c_float
+        L.dmrg_mlp_create.argtypes = [c_i32, ctypes.c_uint64, ctypes.POINTER(c_vp)]
+        L.dmrg_mlp_num_params.argtypes = [c_vp]
+        L.dmrg_mlp_num_params.restype = c_i64
+        L.dmrg_mlp_set_params.argtypes = [c_vp, c_vp, c_i64]
+        L.dmrg_mlp_get_params.argtypes = [c_vp, c_vp, c_i64]
+        L.dmrg_mlp_forward.argtypes = [c_vp, c_vp, c_i64, c_vp, c_vp]
+        L.dmrg_mlp_loss_grad.argtypes = [c_vp, c_vp, c_vp, c_vp, c_i64, ctypes.POINTER(c_dbl), c_vp,
+                                         c_vp]
+        L.dmrg_mlp_adam_step.argtypes = [c_vp, c_vp, c_f, c_f, c_f, c_f, c_vp]
+        L.dmrg_mlp_train.argtypes = [c_vp, c_vp, c_vp, c_vp, c_i64, ctypes.POINTER(TrainOpts), c_vp,
+                                     c_vp]
+        L.dmrg_mlp_collect.argtypes = [c_vp, c_vp, ctypes.POINTER(DavOpts), c_i64, c_vp, c_vp, c_vp,
+                                       ctypes.POINTER(c_i64), ctypes.POINTER(c_i32), c_vp]
+        L.dmrg_mlp_free.argtypes = [c_vp]
+        L.dmrg_mlp_free.restype = None
     if path is None:
         _lib = L
     return L

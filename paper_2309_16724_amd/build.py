@@ -6,6 +6,7 @@ the link with hipcc, all in-tree.
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -13,8 +14,8 @@ OUT = os.path.join(HERE, "libdmrg_hpsi.so")
 BUILD = os.path.join(HERE, "_build")
 
 HOST_SRC = ["wigner.cpp", "model.cpp", "api_host.cpp"]
-HIP_HOST_SRC = ["plan.cpp", "davidson.cpp"]
-HIP_SRC = ["kernels_f64.hip", "kernels_vec.hip", "kernels_split.hip"]
+HIP_HOST_SRC = ["plan.cpp", "davidson.cpp", "mlp.cpp"]
+HIP_SRC = ["kernels_f64.hip", "kernels_vec.hip", "kernels_split.hip", "kernels_mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -30,20 +31,20 @@ def _run(cmd):
 
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    jobs = []
     for s in HOST_SRC:
         o = os.path.join(BUILD, s + ".o")
-        _run(["g++", "-O2", "-fPIC", "-std=c++17", "-c", os.path.join(CSRC, s), "-o", o])
-        objs.append(o)
+        jobs.append((["g++", "-O2", "-fPIC", "-std=c++17", "-c", os.path.join(CSRC, s), "-o", o], o))
     for s in HIP_HOST_SRC:
         o = os.path.join(BUILD, s + ".o")
-        _run([HIPCC, "-O2", "-fPIC", "-std=c++17", "-c",
-              os.path.join(CSRC, s), "-o", o])
-        objs.append(o)
+        jobs.append(([HIPCC, "--offload-arch=gfx950", "-O2", "-fPIC", "-std=c++17", "-c", os.path.join(CSRC, s), "-o", o], o))
     for s in HIP_SRC:
         o = os.path.join(BUILD, s + ".o")
-        _run([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, s), "-o", o])
-        objs.append(o)
+        jobs.append(([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, s), "-o", o], o))
+    workers = max(1, min(8, os.cpu_count() or 1, len(jobs)))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(lambda j: _run(j[0]), jobs))
+    objs = [o for _, o in jobs]
     tmp = OUT + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, OUT)

@@ -8,10 +8,12 @@
 // Details the paper leaves open (same reading as the oracle): block size 1;
 // thick restart to the current and previous Ritz vectors when the subspace
 // reaches m_max; two-pass classical Gram-Schmidt; correction
-// t = -r / (diag - theta) with |diag - theta| floored; convergence when
-// ||H u - theta u||_2 <= tol for the normalised Ritz vector u.  Problems of a
-// batch share the basis-column index: a converged problem stops adding
-// vectors (its segments of later columns are zero), restarts are global.
+// t = -r / (diag - theta) with |diag - theta| floored, optionally corrected
+// per element by the learned network (mlp.cpp), with a guard that falls back
+// to the diagonal step; convergence when ||H u - theta u||_2 <= tol for the
+// normalised Ritz vector u.  Problems of a batch share the basis-column
+// index: a converged problem stops adding vectors (its segments of later
+// columns are zero), restarts are global.
 #include <hip/hip_runtime_api.h>
 #include <algorithm>
 #include <chrono>
@@ -20,6 +22,7 @@
 #include <vector>
 #include "common.hpp"
 #include "davidson.hpp"
+#include "mlp.hpp"
 
 using namespace dmrg;
 
@@ -107,20 +110,40 @@ struct ProbState {
   double theta = 0.0, rnorm = 0.0;
   bool active = true, have_prev = false;
   int iters = 0;
+  double sum_d = 0.0, sum_d2 = 0.0;   // sums of diag and diag^2 over the segment
+};
+
+// training-row capture of dmrg_mlp_collect (single-problem plans)
+struct Collect {
+  const double *psi_star = nullptr;   // converged vector, device
+  double *ts = nullptr;               // device scratch, psi_len
+  float *x = nullptr, *a = nullptr, *b = nullptr;
+  int64_t cap = 0, rows = 0;
+  int32_t nrec = 0;
 };
 
 }  // namespace
 
-extern "C" int dmrg_davidson(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts_t *o,
-                             dmrg_dav_stats_t *st, void *stream) {
-  if (!p || !psi || !evals) { set_error("null argument"); return DMRG_EINVAL; }
-  dmrg_dav_opts_t opt = {1e-8, 1000, 24, 0, 1e-8, 0};
-  if (o) opt = *o;
-  if (opt.m_max < 3 || opt.m_max > 64 || opt.max_iter < 1 || !(opt.tol > 0.0) || !(opt.floor > 0.0)) {
+static int check_opts(const dmrg_dav_opts_t *o, dmrg_dav_opts_t *opt) {
+  *opt = {1e-8, 1000, 24, DMRG_PRECOND_DIAG, 1e-8, nullptr};
+  if (o) *opt = *o;
+  if (opt->m_max < 3 || opt->m_max > 64 || opt->max_iter < 1 || !(opt->tol > 0.0) || !(opt->floor > 0.0)) {
     set_error("bad Davidson options (m_max in [3,64], max_iter >= 1, tol > 0, floor > 0)");
     return DMRG_EINVAL;
   }
-  if (opt.precond != 0) { set_error("only the diagonal preconditioner is available"); return DMRG_EINVAL; }
+  if (opt->precond != DMRG_PRECOND_DIAG && opt->precond != DMRG_PRECOND_MLP) {
+    set_error("unknown preconditioner");
+    return DMRG_EINVAL;
+  }
+  if (opt->precond == DMRG_PRECOND_MLP && !opt->mlp) {
+    set_error("learned preconditioner requested without a network");
+    return DMRG_EINVAL;
+  }
+  return DMRG_OK;
+}
+
+static int solve(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts_t &opt, dmrg_dav_stats_t *st,
+                 void *stream, Collect *col) {
   std::vector<ProbState> P;
   for (int k = 0;; k++) {
     int64_t off, len;
@@ -154,11 +177,15 @@ extern "C" int dmrg_davidson(dmrg_plan_t *p, double *psi, double *evals, const d
   double *V = buf.get((int64_t)M * n), *W = buf.get((int64_t)M * n);
   double *u = buf.get(n), *hu = buf.get(n), *r = buf.get(n), *t = buf.get(n), *uprev = buf.get(n);
   double *diag = buf.get(n), *tmp = buf.get(2 * n);
+  const bool use_mlp = opt.precond == DMRG_PRECOND_MLP;
+  double *tm = use_mlp ? buf.get(n) : nullptr, *ones = buf.get(n);
+  double *dth = buf.get(np), *dsig = buf.get(np), *df1 = buf.get(np), *dflag = buf.get(np);
+  int64_t *dsegoff = (int64_t *)buf.raw(sizeof(int64_t) * (np + 1));
   double *part = buf.get((int64_t)std::max<size_t>(chunks.size(), 1) * (M + 2));
   double *dout = buf.get((int64_t)np * (M + 2)), *dcoef = buf.get((int64_t)np * M);
   double *dvec = buf.get(np);
   if (!d_chunks || !d_seg0 || !V || !W || !u || !hu || !r || !t || !uprev || !diag || !tmp || !part || !dout ||
-      !dcoef || !dvec) {
+      !dcoef || !dvec || (use_mlp && !tm) || !ones || !dth || !dsig || !df1 || !dflag || !dsegoff) {
     set_error("hipMalloc failed in Davidson");
     return DMRG_ENOMEM;
   }
@@ -200,6 +227,24 @@ extern "C" int dmrg_davidson(dmrg_plan_t *p, double *psi, double *evals, const d
     return DMRG_OK;
   };
   if ((rc = dmrg_diag_H(p, diag, stream))) return rc;
+  {
+    std::vector<int64_t> so(np + 1);
+    for (int k = 0; k < np; k++) so[k] = P[k].off;
+    so[np] = n;
+    HIPCHK(hipMemcpy(dsegoff, so.data(), sizeof(int64_t) * (np + 1), hipMemcpyHostToDevice));
+  }
+  vec_fill(X, 1.0, ones, stream);
+  if ((rc = dots_host(diag, 1, ones))) return rc;
+  for (int k = 0; k < np; k++) P[k].sum_d = hout[k];
+  if ((rc = dots_host(diag, 1, diag))) return rc;
+  for (int k = 0; k < np; k++) P[k].sum_d2 = hout[k];
+  // root mean square of diag - theta over problem k's segment
+  auto sigma_of = [&](int k, double th) {
+    const ProbState &S = P[k];
+    double v = (S.sum_d2 - 2.0 * th * S.sum_d + (double)S.len * th * th) / (double)std::max<int64_t>(S.len, 1);
+    return std::sqrt(std::max(v, 1e-300));
+  };
+  int fallbacks = 0;
   HIPCHK(hipMemcpyAsync(V, psi, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   if ((rc = dots_host(V, 1, V))) return rc;
   std::vector<double> sc(np);
@@ -258,6 +303,68 @@ extern "C" int dmrg_davidson(dmrg_plan_t *p, double *psi, double *evals, const d
       }
     }
     if (n_active == 0) break;
+    if (col && P[0].active) {
+      // exact correction of this iteration from the converged vector
+      if ((rc = dots_host(u, 1, col->psi_star))) return rc;
+      const double c = hout[0];
+      if (std::fabs(c) >= 1e-3) {
+        launch_exact_corr(col->psi_star, u, n, 1.0 / c, col->ts, stream);
+        if ((rc = dots_host(col->ts, 1, col->ts))) return rc;
+        const double tn = std::sqrt(hout[0]);
+        if (tn > 0.0 && std::isfinite(tn) && col->rows + n <= col->cap) {
+          launch_collect(diag, r, col->ts, n, P[0].theta, sigma_of(0, P[0].theta),
+                         std::log10(std::max(P[0].rnorm, 1e-300)) / 8.0, std::sqrt((double)n) / tn, opt.floor,
+                         col->x + col->rows * MLP_IN, col->a + col->rows, col->b + col->rows, stream);
+          HIPCHK(hipGetLastError());
+          col->rows += n;
+          col->nrec++;
+        }
+      }
+    }
+    if (use_mlp) {
+      // learned correction t_mlp = td (1 + g(x)) into tm, then the guard
+      std::vector<double> sig(np, 1.0), f1(np, 0.0), th(np, 0.0);
+      for (int k = 0; k < np; k++) {
+        th[k] = P[k].theta;
+        if (!P[k].active) continue;
+        sig[k] = sigma_of(k, P[k].theta);
+        f1[k] = std::log10(std::max(P[k].rnorm, 1e-300)) / 8.0;
+      }
+      HIPCHK(hipMemcpyAsync(dth, th.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(dsig, sig.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(df1, f1.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
+      FwdArgs A{};
+      A.params = opt.mlp->p;
+      A.n = n;
+      A.d = diag;
+      A.r = r;
+      A.theta = dth;
+      A.sigma = dsig;
+      A.f1 = df1;
+      A.seg_off = dsegoff;
+      A.nseg = np;
+      A.floor_ = opt.floor;
+      A.t = tm;
+      launch_mlp_forward(opt.mlp->width, 1, A, stream);
+      HIPCHK(hipGetLastError());
+      if ((rc = dots_host(tm, 1, tm))) return rc;
+      std::vector<double> mm(hout.begin(), hout.begin() + np);
+      if ((rc = dots_host(tm, 1, t))) return rc;
+      std::vector<double> mt(hout.begin(), hout.begin() + np);
+      if ((rc = dots_host(t, 1, t))) return rc;
+      std::vector<double> flag(np, 0.0);
+      for (int k = 0; k < np; k++) {
+        if (!P[k].active) continue;
+        const double tt = hout[k];
+        const bool ok = std::isfinite(mm[k]) && std::isfinite(mt[k]) && mm[k] > 0.0 &&
+                        std::fabs(mt[k]) >= DMRG_MLP_GUARD * std::sqrt(mm[k] * tt);
+        flag[k] = ok ? 1.0 : 0.0;
+        fallbacks += !ok;
+      }
+      HIPCHK(hipMemcpyAsync(dflag, flag.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
+      vec_select(X, dflag, tm, t, stream);
+      HIPCHK(hipStreamSynchronize(s));
+    }
     if (m >= M) {
       // global thick restart: per problem span{u, u_prev} in coefficient space
       if ((rc = dots_host(V, m, uprev))) return rc;
@@ -395,6 +502,7 @@ extern "C" int dmrg_davidson(dmrg_plan_t *p, double *psi, double *evals, const d
     std::memset(st, 0, sizeof(*st));
     st->iters = maxit;
     st->n_hpsi = n_hpsi;
+    st->fallbacks = fallbacks;
     st->converged = conv;
     st->residual = maxres;
     st->energy = P[0].theta;
@@ -402,5 +510,55 @@ extern "C" int dmrg_davidson(dmrg_plan_t *p, double *psi, double *evals, const d
     st->t_hpsi_s = t_hpsi;
   }
   if (conv < np) { set_error("Davidson did not converge for every problem; best Ritz pairs returned"); return DMRG_ENOCONV; }
+  return DMRG_OK;
+}
+
+extern "C" int dmrg_davidson(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts_t *o,
+                             dmrg_dav_stats_t *st, void *stream) {
+  if (!p || !psi || !evals) { set_error("null argument"); return DMRG_EINVAL; }
+  dmrg_dav_opts_t opt;
+  int rc = check_opts(o, &opt);
+  if (rc) return rc;
+  return solve(p, psi, evals, opt, st, stream, nullptr);
+}
+
+extern "C" int dmrg_mlp_collect(dmrg_plan_t *p, const double *psi0, const dmrg_dav_opts_t *o, int64_t capacity,
+                                float *x, float *a, float *b, int64_t *n_rows, int32_t *n_records, void *stream) {
+  if (!p || !psi0 || !x || !a || !b || !n_rows || !n_records || capacity < 0) {
+    set_error("null argument");
+    return DMRG_EINVAL;
+  }
+  dmrg_dav_opts_t opt;
+  int rc = check_opts(o, &opt);
+  if (rc) return rc;
+  opt.precond = DMRG_PRECOND_DIAG;
+  opt.mlp = nullptr;
+  int64_t off, len;
+  if (dmrg_psi_layout(p, 1, &off, &len) == DMRG_OK) {
+    set_error("training rows are collected from single-problem plans");
+    return DMRG_EINVAL;
+  }
+  set_error("");
+  if ((rc = dmrg_psi_layout(p, 0, &off, &len))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  DevBuf buf;
+  double *star = buf.get(len), *ts = buf.get(len);
+  if (!star || !ts) { set_error("hipMalloc failed in training-row capture"); return DMRG_ENOMEM; }
+  double ev;
+  HIPCHK(hipMemcpyAsync(star, psi0, sizeof(double) * len, hipMemcpyDeviceToDevice, s));
+  if ((rc = solve(p, star, &ev, opt, nullptr, stream, nullptr))) return rc;
+  double *work = buf.get(len);
+  if (!work) { set_error("hipMalloc failed in training-row capture"); return DMRG_ENOMEM; }
+  HIPCHK(hipMemcpyAsync(work, psi0, sizeof(double) * len, hipMemcpyDeviceToDevice, s));
+  Collect col;
+  col.psi_star = star;
+  col.ts = ts;
+  col.x = x;
+  col.a = a;
+  col.b = b;
+  col.cap = capacity;
+  if ((rc = solve(p, work, &ev, opt, nullptr, stream, &col))) return rc;
+  *n_rows = col.rows;
+  *n_records = col.nrec;
   return DMRG_OK;
 }

@@ -88,6 +88,26 @@ __global__ void __launch_bounds__(VB) sscale_kernel(const VChunk *__restrict__ c
   }
 }
 
+// x[i] = value
+__global__ void __launch_bounds__(VB) sfill_kernel(const VChunk *__restrict__ chunks, int nchunks, double value,
+                                                    double *__restrict__ x) {
+  for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const VChunk C = chunks[c];
+    for (int64_t i = C.i0 + threadIdx.x; i < C.i1; i += VB) x[i] = value;
+  }
+}
+
+// dst[i] = src[i] where the segment's flag is non-zero
+__global__ void __launch_bounds__(VB) sselect_kernel(const VChunk *__restrict__ chunks, int nchunks,
+                                                      const double *__restrict__ flag, const double *__restrict__ src,
+                                                      double *__restrict__ dst) {
+  for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const VChunk C = chunks[c];
+    if (flag[C.seg] == 0.0) continue;
+    for (int64_t i = C.i0 + threadIdx.x; i < C.i1; i += VB) dst[i] = src[i];
+  }
+}
+
 static int cgrid(int nchunks) { return std::min(std::max(nchunks, 1), 16384); }
 
 void vec_dots(const VecCtx &X, const double *V, int64_t ldv, int m, const double *x, double *out, void *stream) {
@@ -113,6 +133,16 @@ void vec_resid(const VecCtx &X, const double *hu, const double *u, const double 
 void vec_scale(const VecCtx &X, const double *s, double *x, void *stream) {
   hipLaunchKernelGGL(sscale_kernel, dim3(cgrid(X.nchunks)), dim3(VB), 0, (hipStream_t)stream, X.chunks, X.nchunks,
                      s, x);
+}
+
+void vec_fill(const VecCtx &X, double value, double *x, void *stream) {
+  hipLaunchKernelGGL(sfill_kernel, dim3(cgrid(X.nchunks)), dim3(VB), 0, (hipStream_t)stream, X.chunks, X.nchunks,
+                     value, x);
+}
+
+void vec_select(const VecCtx &X, const double *flag, const double *src, double *dst, void *stream) {
+  hipLaunchKernelGGL(sselect_kernel, dim3(cgrid(X.nchunks)), dim3(VB), 0, (hipStream_t)stream, X.chunks, X.nchunks,
+                     flag, src, dst);
 }
 
 }  // namespace dmrg

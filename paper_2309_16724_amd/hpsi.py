@@ -85,19 +85,21 @@ class Plan:
         return out
 
     def davidson(self, psi0, tol=1e-8, max_iter=1000, m_max=24, floor=1e-8, stream=None,
-                 check=True):
+                 check=True, mlp=None):
         """Lowest eigenpair of every problem by the library's Davidson solver.
 
-        psi0: CUDA float64 tensor (starting vectors, not modified).  Returns
-        (energy, psi, stats dict): energy is the Ritz value of a single-problem
-        plan, else the list of Ritz values, one per problem.  With check=False
-        a non-converged run returns its best pairs instead of raising."""
+        psi0: CUDA float64 tensor (starting vectors, not modified); mlp: a
+        precond.MLP for the learned preconditioner, else the diagonal one.
+        Returns (energy, psi, stats dict): energy is the Ritz value of a
+        single-problem plan, else the list of Ritz values, one per problem.
+        With check=False a non-converged run returns its best pairs instead of
+        raising."""
         torch = _torch()
         assert psi0.dtype == torch.float64 and psi0.is_cuda and psi0.numel() == self.size
         psi = psi0.detach().clone().contiguous()
         ev = (ctypes.c_double * len(self.problems))()
         st = B.DavStats()
-        opts = B.DavOpts(tol, max_iter, m_max, 0, floor, 0)
+        opts = self._dav_opts(tol, max_iter, m_max, floor, mlp)
         rc = self.lib.dmrg_davidson(self.handle, ctypes.c_void_p(psi.data_ptr()), ev,
                                     ctypes.byref(opts), ctypes.byref(st), self._stream(stream))
         if rc != 0 and (check or rc != -7):
@@ -105,6 +107,34 @@ class Plan:
         torch.cuda.synchronize(self.device)
         evs = list(ev)
         return (evs[0] if len(evs) == 1 else evs), psi, st.as_dict()
+
+    @staticmethod
+    def _dav_opts(tol, max_iter, m_max, floor, mlp=None):
+        if mlp is None:
+            return B.DavOpts(tol, max_iter, m_max, B.DMRG_PRECOND_DIAG, floor, None)
+        return B.DavOpts(tol, max_iter, m_max, B.DMRG_PRECOND_MLP, floor, mlp.handle)
+
+    def collect(self, psi0, capacity, tol=1e-8, max_iter=1000, m_max=24, floor=1e-8,
+                stream=None):
+        """Training rows (x, a, b) of the learned preconditioner from this
+        single-problem plan's solve (see dmrg_mlp_collect): CUDA float32
+        tensors trimmed to the recorded rows, and the number of iterations."""
+        torch = _torch()
+        assert psi0.dtype == torch.float64 and psi0.is_cuda and psi0.numel() == self.size
+        x = torch.empty((capacity, B.DMRG_MLP_IN), dtype=torch.float32, device=self.device)
+        a = torch.empty(capacity, dtype=torch.float32, device=self.device)
+        b = torch.empty(capacity, dtype=torch.float32, device=self.device)
+        nr, nrec = ctypes.c_int64(), ctypes.c_int32()
+        opts = self._dav_opts(tol, max_iter, m_max, floor)
+        B.check(self.lib.dmrg_mlp_collect(self.handle, ctypes.c_void_p(psi0.data_ptr()),
+                                          ctypes.byref(opts), capacity,
+                                          ctypes.c_void_p(x.data_ptr()),
+                                          ctypes.c_void_p(a.data_ptr()),
+                                          ctypes.c_void_p(b.data_ptr()), ctypes.byref(nr),
+                                          ctypes.byref(nrec), self._stream(stream)), self.lib)
+        torch.cuda.synchronize(self.device)
+        n = nr.value
+        return x[:n], a[:n], b[:n], nrec.value
 
     def set_profiling(self, on=True):
         B.check(self.lib.dmrg_set_profiling(self.handle, 1 if on else 0), self.lib)
