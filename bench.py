@@ -71,6 +71,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="L24_D512", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--hpsi-only", choices=("fp64", "split"),
+                    help="time only H.psi of one precision (for profiler runs); also copies "
+                         "256 MiB once with a plain device copy as a counter reference")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -114,6 +117,18 @@ def main():
         plan.free()
         return st, ms, prof, yv
 
+    if args.hpsi_only:
+        ref = torch.empty(32 << 20, dtype=torch.float64, device="cuda")   # 256 MiB
+        ref2 = torch.empty_like(ref)
+        ref.fill_(1.0)
+        ref2.copy_(ref)
+        torch.cuda.synchronize()
+        del ref, ref2
+        prec, ns = (0, 0) if args.hpsi_only == "fp64" else (1, 5)
+        st, ms, prof, _ = run(prec, ns)
+        print(json.dumps({"hpsi_only": args.hpsi_only, "workload": args.workload, "ms_per_step": ms,
+                          "tflops": st["flops"] / (ms * 1e-3) / 1e12, "stages": prof}), flush=True)
+        return
     st64, ms64, prof64, y64 = run(0, 0)
     st5, ms5, prof5, y5 = run(1, 5)
     rel = float(np.abs(y5 - y64).max() / np.abs(y64).max())

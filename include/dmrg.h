@@ -91,11 +91,29 @@ typedef struct {
 
 enum { DMRG_FP64 = 0, DMRG_SPLIT_BF16 = 1 };
 
+/* Plan flags.
+ *  DMRG_PLAN_GRAPH: dmrg_apply_H records its launch sequence once per
+ *    (psi, hpsi) pair into a HIP graph (on a plan-owned capture stream) and
+ *    replays it on the caller's stream; at most 64 graphs are kept (least
+ *    recently created evicted).  Profiling events are not recorded in graphs.
+ *  DMRG_PLAN_NO_XCD: work groups take tiles in launch order instead of giving
+ *    each XCD a contiguous range of tiles.
+ *  DMRG_PLAN_AUTOTUNE: dmrg_build_tasks times dmrg_apply_H under every
+ *    candidate (kpart in {1024, 2048, 4096} x tile_policy in {0, 1} x
+ *    workspace cap in {requested or 16 GiB, 512 MiB, 192 MiB}) and keeps the
+ *    fastest; choices are cached for the process by a hash of the plan's
+ *    block shapes and options.  The chosen values are in dmrg_plan_stats. */
+enum { DMRG_PLAN_GRAPH = 1, DMRG_PLAN_NO_XCD = 2, DMRG_PLAN_AUTOTUNE = 4 };
+
 typedef struct {
   int32_t precision;        /* DMRG_FP64 or DMRG_SPLIT_BF16                   */
   int32_t n_slices;         /* split only: BF16 slices per operand (3..7)     */
   int64_t workspace_bytes;  /* cap for the intermediate stripes, 0 = default  */
-  int32_t flags;            /* reserved, 0                                     */
+  int32_t flags;            /* DMRG_PLAN_* bits                                */
+  int32_t kpart;            /* summed K per second-stage work item, 0 = 2048 */
+  int32_t tile_policy;      /* 0: 16x64 / 32x32 / 64x16 by output shape,
+                               1: 32x32 except outputs of <= 16 rows          */
+  int32_t pad;
 } dmrg_plan_opts_t;
 
 typedef struct dmrg_plan dmrg_plan_t;
@@ -111,7 +129,13 @@ typedef struct {
   double stage1_flops, stage2_flops;
   int64_t workspace_bytes;  /* stripe workspace actually used                 */
   int32_t n_chunks;         /* launches pairs per H.psi                       */
+  int32_t kpart;            /* settings in use (after autotuning)             */
+  int32_t tile_policy;
+  int32_t xcd;
+  int32_t tuned;            /* candidates timed by the autotuner (0: none)   */
   int32_t pad;
+  int64_t workspace_cap;    /* stripe workspace cap in use, bytes            */
+  double tune_ms;           /* autotuner wall time                            */
 } dmrg_plan_stats_t;
 
 /* Build the operator table, sector-task and sector-value tables (Sec. II A,

@@ -16,6 +16,9 @@ c_i32, c_i64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, cty
 
 DMRG_FP64 = 0
 DMRG_SPLIT_BF16 = 1
+DMRG_PLAN_GRAPH = 1
+DMRG_PLAN_NO_XCD = 2
+DMRG_PLAN_AUTOTUNE = 4
 
 
 class Sector(ctypes.Structure):
@@ -37,7 +40,7 @@ class ProblemT(ctypes.Structure):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("precision", c_i32), ("n_slices", c_i32), ("workspace_bytes", c_i64),
-                ("flags", c_i32)]
+                ("flags", c_i32), ("kpart", c_i32), ("tile_policy", c_i32), ("pad", c_i32)]
 
 
 class DavOpts(ctypes.Structure):
@@ -68,7 +71,8 @@ class PlanStats(ctypes.Structure):
     _fields_ = [("psi_len", c_i64), ("n_blocks", c_i64), ("n_rows", c_i64), ("n_tasks", c_i64),
                 ("n_stage1", c_i64), ("n_segments", c_i64), ("flops", c_dbl),
                 ("stage1_flops", c_dbl), ("stage2_flops", c_dbl), ("workspace_bytes", c_i64),
-                ("n_chunks", c_i32), ("pad", c_i32)]
+                ("n_chunks", c_i32), ("kpart", c_i32), ("tile_policy", c_i32), ("xcd", c_i32),
+                ("tuned", c_i32), ("pad", c_i32), ("workspace_cap", c_i64), ("tune_ms", c_dbl)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
@@ -164,7 +168,8 @@ class ProblemArgs:
                           ldata_ptr, rdata_ptr, prob.left.data.size, prob.right.data.size)
 
 
-def debug_plan_host_apply(prob, psi, workspace_bytes=0, lib=None, precision=0, n_slices=0):
+def debug_plan_host_apply(prob, psi, workspace_bytes=0, lib=None, precision=0, n_slices=0, kpart=0,
+                          tile_policy=0):
     """Test-only: run the device plan's tile lists on the CPU (no GPU).
 
     ``psi=None`` only builds the plan and returns its statistics."""
@@ -173,7 +178,7 @@ def debug_plan_host_apply(prob, psi, workspace_bytes=0, lib=None, precision=0, n
     rd = np.ascontiguousarray(prob.right.data)
     args = ProblemArgs(prob, ld.ctypes.data, rd.ctypes.data)
     st = PlanStats()
-    opts = PlanOpts(precision, n_slices, workspace_bytes, 0)
+    opts = PlanOpts(precision, n_slices, workspace_bytes, 0, kpart, tile_policy, 0)
     if psi is None:
         check(L.dmrg_debug_plan_host_apply(ctypes.byref(args.s), None, None, ctypes.byref(opts),
                                            ctypes.byref(st)), L)

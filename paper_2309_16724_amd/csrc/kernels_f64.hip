@@ -13,11 +13,23 @@
 // Lane layout of v_mfma_f64_16x16x4f64 (lane l, accumulator element r):
 // A[l%16][l/16], B[l/16][l%16], D[l/16 + 4r][l%16].
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include "plan.hpp"
 
 namespace dmrg {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int PF = 2;   // K steps (of 4) loaded ahead
+
+// Work-group index used to pick work: consecutive work groups are spread over
+// the 8 XCDs (each with its own L2), so with xcd != 0 the groups resident on
+// one XCD are given consecutive tile indices, which share operands.
+__device__ __forceinline__ int work_block(int xcd) {
+  const int b = blockIdx.x, g = gridDim.x;
+  return (xcd && (g & 7) == 0) ? (b & 7) * (g >> 3) + (b >> 3) : b;
+}
+
 
 __device__ __forceinline__ const double *base_ptr(int id, const double *const *bases, const double *psi,
                                                   const double *y, const double *work, const double *part) {
@@ -71,27 +83,40 @@ __device__ __forceinline__ void item_f64(const Tile &T, const Seg *__restrict__ 
     // the lane's k is k0 + q4: track its (block, offset) for A and B
     int pa = q4 / S.a_kb, ka = q4 - pa * S.a_kb;
     int pb = q4 / S.b_kb, kb = q4 - pb * S.b_kb;
-    double an[MB], bn[NB];
-    auto fetch = [&](int k0) {
+    // operands of PF consecutive K steps are in flight while the previous PF
+    // steps run on the matrix core
+    double an[PF][MB], bn[PF][NB];
+    auto fetch = [&](int k0, int q) {
       const bool kok = (k0 + q4) < S.K;
       const int64_t ak = (int64_t)pa * S.a_p + (int64_t)ka * S.a_k;
       const int64_t bk = (int64_t)pb * S.b_pk + (int64_t)kb * S.b_k;
-      for (int bi = 0; bi < MB; bi++) an[bi] = (kok && aok[bi]) ? A[ak + aoff[bi]] : 0.0;
-      for (int bj = 0; bj < NB; bj++) bn[bj] = (kok && bok[bj]) ? B[bk + boff[bj]] : 0.0;
+      for (int bi = 0; bi < MB; bi++) an[q][bi] = (kok && aok[bi]) ? A[ak + aoff[bi]] : 0.0;
+      for (int bj = 0; bj < NB; bj++) bn[q][bj] = (kok && bok[bj]) ? B[bk + boff[bj]] : 0.0;
       ka += 4;
       while (ka >= S.a_kb) { ka -= S.a_kb; pa++; }
       kb += 4;
       while (kb >= S.b_kb) { kb -= S.b_kb; pb++; }
     };
-    fetch(0);
-    for (int k0 = 0; k0 < S.K; k0 += 4) {
-      double ac[MB], bc[NB];
-      for (int bi = 0; bi < MB; bi++) ac[bi] = s * an[bi];
-      for (int bj = 0; bj < NB; bj++) bc[bj] = bn[bj];
-      if (k0 + 4 < S.K) fetch(k0 + 4);
-      for (int bi = 0; bi < MB; bi++)
-        for (int bj = 0; bj < NB; bj++)
-          acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[bi], bc[bj], acc[bi][bj], 0, 0, 0);
+#pragma unroll
+    for (int q = 0; q < PF; q++) fetch(4 * q, q);
+    for (int k0 = 0; k0 < S.K; k0 += 4 * PF) {
+      double ac[PF][MB], bc[PF][NB];
+#pragma unroll
+      for (int q = 0; q < PF; q++) {
+        for (int bi = 0; bi < MB; bi++) ac[q][bi] = s * an[q][bi];
+        for (int bj = 0; bj < NB; bj++) bc[q][bj] = bn[q][bj];
+      }
+      if (k0 + 4 * PF < S.K) {
+#pragma unroll
+        for (int q = 0; q < PF; q++) fetch(k0 + 4 * PF + 4 * q, q);
+      }
+#pragma unroll
+      for (int q = 0; q < PF; q++) {
+        if (k0 + 4 * q >= S.K) break;
+        for (int bi = 0; bi < MB; bi++)
+          for (int bj = 0; bj < NB; bj++)
+            acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[q][bi], bc[q][bj], acc[bi][bj], 0, 0, 0);
+      }
     }
   }
   double *C = const_cast<double *>(base_ptr(T.c_base, bases, psi, y, work, part)) + T.c_off;
@@ -100,7 +125,8 @@ __device__ __forceinline__ void item_f64(const Tile &T, const Seg *__restrict__ 
       for (int r = 0; r < 4; r++) {
         int i = 16 * bi + q4 + 4 * r, j = 16 * bj + r16;
         if (i < mrem && j < nrem) {
-          double *c = C + (int64_t)(T.ci0 + i) + (int64_t)(T.cj0 + j) * T.ldc;
+          double *c = T.rowmajor ? C + (int64_t)(T.ci0 + i) * T.ldc + (T.cj0 + j)
+                                 : C + (int64_t)(T.ci0 + i) + (int64_t)(T.cj0 + j) * T.ldc;
           *c = T.accumulate ? *c + acc[bi][bj][r] : acc[bi][bj][r];
         }
       }
@@ -109,10 +135,10 @@ __device__ __forceinline__ void item_f64(const Tile &T, const Seg *__restrict__ 
 __device__ __forceinline__ void items_f64(const Tile *__restrict__ tiles, const Seg *__restrict__ segs, int ntiles,
                                           const double *const *__restrict__ bases, const double *__restrict__ psi,
                                           double *__restrict__ y, double *__restrict__ work,
-                                          double *__restrict__ part) {
+                                          double *__restrict__ part, int xcd) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r16 = lane & 15, q4 = lane >> 4;
-  for (int t = blockIdx.x * WAVES + wave; t < ntiles; t += gridDim.x * WAVES) {
+  for (int t = work_block(xcd) * WAVES + wave; t < ntiles; t += gridDim.x * WAVES) {
     const Tile T = tiles[t];
     if (T.mb == 1) item_f64<1>(T, segs, bases, psi, y, work, part, r16, q4);
     else if (T.mb == 4) item_f64<4>(T, segs, bases, psi, y, work, part, r16, q4);
@@ -126,8 +152,8 @@ __global__ void __launch_bounds__(64 * WAVES) stage1_f64_kernel(const Tile *__re
                                                                  const double *const *__restrict__ bases,
                                                                  const double *__restrict__ psi,
                                                                  double *__restrict__ y, double *__restrict__ work,
-                                                                 double *__restrict__ part) {
-  items_f64(tiles, segs, ntiles, bases, psi, y, work, part);
+                                                                 double *__restrict__ part, int xcd) {
+  items_f64(tiles, segs, ntiles, bases, psi, y, work, part, xcd);
 }
 
 // second stage: Y_F += sum v A_stripe T_stripe (work items write Y or a partial tile)
@@ -136,8 +162,8 @@ __global__ void __launch_bounds__(64 * WAVES) stage2_f64_kernel(const Tile *__re
                                                                  const double *const *__restrict__ bases,
                                                                  const double *__restrict__ psi,
                                                                  double *__restrict__ y, double *__restrict__ work,
-                                                                 double *__restrict__ part) {
-  items_f64(tiles, segs, ntiles, bases, psi, y, work, part);
+                                                                 double *__restrict__ part, int xcd) {
+  items_f64(tiles, segs, ntiles, bases, psi, y, work, part, xcd);
 }
 
 // Y tile += sum of its partial tiles, in part order
@@ -210,15 +236,16 @@ void launch_zero(double *y, int64_t n, void *stream) {
 }
 
 void launch_tiles_f64(int stage, const Tile *tiles, const Seg *segs, int ntiles, const double *const *bases,
-                      const double *psi, double *y, double *work, double *part, void *stream) {
+                      const double *psi, double *y, double *work, double *part, int xcd, void *stream) {
   if (ntiles <= 0) return;
   int grid = std::min((ntiles + WAVES - 1) / WAVES, 256 * 16);
+  grid = (grid + 7) / 8 * 8;
   if (stage == 1)
     hipLaunchKernelGGL(stage1_f64_kernel, dim3(grid), dim3(64 * WAVES), 0, (hipStream_t)stream, tiles, segs,
-                       ntiles, bases, psi, y, work, part);
+                       ntiles, bases, psi, y, work, part, xcd);
   else
     hipLaunchKernelGGL(stage2_f64_kernel, dim3(grid), dim3(64 * WAVES), 0, (hipStream_t)stream, tiles, segs,
-                       ntiles, bases, psi, y, work, part);
+                       ntiles, bases, psi, y, work, part, xcd);
 }
 
 void launch_reduce(const Reduce *red, int nred, const double *part, double *y, void *stream) {
@@ -233,6 +260,26 @@ void launch_diag(const DiagBlock *blocks, const DiagTerm *terms, int nblocks, co
   int grid = std::min(nblocks, 4096);
   hipLaunchKernelGGL(diag_kernel, dim3(grid), dim3(256), 0, (hipStream_t)stream, blocks, terms, nblocks,
                      bases, diag);
+}
+
+// dst block (c, r) = src block (r, c) for every position of every job
+__global__ void __launch_bounds__(256) transpose_kernel(const TransJob *__restrict__ jobs, int njobs,
+                                                        const double *__restrict__ src, double *__restrict__ dst) {
+  for (int j = blockIdx.x; j < njobs; j += gridDim.x) {
+    const TransJob J = jobs[j];
+    const int64_t bs = (int64_t)J.rows * J.cols, tot = bs * J.npos;
+    for (int64_t e = threadIdx.x; e < tot; e += 256) {
+      const int64_t p = e / bs, rem = e - p * bs;
+      const int64_t c = rem / J.rows, r = rem - c * J.rows;
+      dst[J.off + p * bs + c + r * J.cols] = src[J.off + e];
+    }
+  }
+}
+
+void launch_transpose(const TransJob *jobs, int njobs, const double *src, double *dst, void *stream) {
+  if (njobs <= 0) return;
+  hipLaunchKernelGGL(transpose_kernel, dim3(std::min(njobs, 65535)), dim3(256), 0, (hipStream_t)stream, jobs, njobs,
+                     src, dst);
 }
 
 }  // namespace dmrg

@@ -180,10 +180,19 @@ __device__ __forceinline__ void item_split(const Tile &T, const Seg *__restrict_
       for (int r = 0; r < 4; r++) {
         int i = 16 * bi + 4 * q4 + r, j = 16 * bj + r16;
         if (i < mrem && j < nrem) {
-          double *c = C + (int64_t)(T.ci0 + i) + (int64_t)(T.cj0 + j) * T.ldc;
+          double *c = T.rowmajor ? C + (int64_t)(T.ci0 + i) * T.ldc + (T.cj0 + j)
+                                 : C + (int64_t)(T.ci0 + i) + (int64_t)(T.cj0 + j) * T.ldc;
           *c = T.accumulate ? *c + acc[bi][bj][r] : acc[bi][bj][r];
         }
       }
+}
+
+// Work-group index used to pick work: consecutive work groups are spread over
+// the 8 XCDs (each with its own L2), so with xcd != 0 the groups resident on
+// one XCD are given consecutive tile indices, which share operands.
+__device__ __forceinline__ int work_block(int xcd) {
+  const int b = blockIdx.x, g = gridDim.x;
+  return (xcd && (g & 7) == 0) ? (b & 7) * (g >> 3) + (b >> 3) : b;
 }
 
 template <int NS>
@@ -191,10 +200,10 @@ __device__ __forceinline__ void items_split(const Tile *__restrict__ tiles, cons
                                             const SegS *__restrict__ ssegs, int ntiles,
                                             const double *const *__restrict__ bases, const double *__restrict__ psi,
                                             double *__restrict__ y, double *__restrict__ work,
-                                            double *__restrict__ part, const SliceBufs &bufs) {
+                                            double *__restrict__ part, const SliceBufs &bufs, int xcd) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r16 = lane & 15, q4 = lane >> 4;
-  for (int t = blockIdx.x * WAVES + wave; t < ntiles; t += gridDim.x * WAVES) {
+  for (int t = work_block(xcd) * WAVES + wave; t < ntiles; t += gridDim.x * WAVES) {
     const Tile T = tiles[t];
     if (T.mb == 1) item_split<1, NS>(T, segs, ssegs, bases, psi, y, work, part, bufs, r16, q4);
     else if (T.mb == 4) item_split<4, NS>(T, segs, ssegs, bases, psi, y, work, part, bufs, r16, q4);
@@ -206,14 +215,16 @@ __device__ __forceinline__ void items_split(const Tile *__restrict__ tiles, cons
   __global__ void __launch_bounds__(64 * WAVES) stage1_split##NS##_kernel(                                  \
       const Tile *__restrict__ tiles, const Seg *__restrict__ segs, const SegS *__restrict__ ssegs,         \
       int ntiles, const double *const *__restrict__ bases, const double *__restrict__ psi,                  \
-      double *__restrict__ y, double *__restrict__ work, double *__restrict__ part, SliceBufs bufs) {       \
-    items_split<NS>(tiles, segs, ssegs, ntiles, bases, psi, y, work, part, bufs);                           \
+      double *__restrict__ y, double *__restrict__ work, double *__restrict__ part, SliceBufs bufs,        \
+      int xcd) {                                                                                            \
+    items_split<NS>(tiles, segs, ssegs, ntiles, bases, psi, y, work, part, bufs, xcd);                      \
   }                                                                                                         \
   __global__ void __launch_bounds__(64 * WAVES) stage2_split##NS##_kernel(                                  \
       const Tile *__restrict__ tiles, const Seg *__restrict__ segs, const SegS *__restrict__ ssegs,         \
       int ntiles, const double *const *__restrict__ bases, const double *__restrict__ psi,                  \
-      double *__restrict__ y, double *__restrict__ work, double *__restrict__ part, SliceBufs bufs) {       \
-    items_split<NS>(tiles, segs, ssegs, ntiles, bases, psi, y, work, part, bufs);                           \
+      double *__restrict__ y, double *__restrict__ work, double *__restrict__ part, SliceBufs bufs,        \
+      int xcd) {                                                                                            \
+    items_split<NS>(tiles, segs, ssegs, ntiles, bases, psi, y, work, part, bufs, xcd);                      \
   }
 
 SPLIT_KERNELS(3)
@@ -224,18 +235,19 @@ SPLIT_KERNELS(7)
 
 void launch_tiles_split(int stage, const Tile *tiles, const Seg *segs, const SegS *ssegs, int ntiles,
                         int nslices, const double *const *bases, const double *psi, double *y, double *work,
-                        double *part, SliceBufs bufs, void *stream) {
+                        double *part, SliceBufs bufs, int xcd, void *stream) {
   if (ntiles <= 0) return;
   int grid = std::min((ntiles + WAVES - 1) / WAVES, 256 * 16);
+  grid = (grid + 7) / 8 * 8;
   hipStream_t s = (hipStream_t)stream;
 #define LAUNCH(NS)                                                                                          \
   if (nslices == NS) {                                                                                      \
     if (stage == 1)                                                                                         \
       hipLaunchKernelGGL(stage1_split##NS##_kernel, dim3(grid), dim3(64 * WAVES), 0, s, tiles, segs, ssegs,   \
-                         ntiles, bases, psi, y, work, part, bufs);                                          \
+                         ntiles, bases, psi, y, work, part, bufs, xcd);                                     \
     else                                                                                                    \
       hipLaunchKernelGGL(stage2_split##NS##_kernel, dim3(grid), dim3(64 * WAVES), 0, s, tiles, segs, ssegs,   \
-                         ntiles, bases, psi, y, work, part, bufs);                                          \
+                         ntiles, bases, psi, y, work, part, bufs, xcd);                                     \
     return;                                                                                                 \
   }
   LAUNCH(3)

@@ -4,7 +4,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <chrono>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <set>
 
 using namespace dmrg;
@@ -16,9 +19,38 @@ struct ProbPlan {
   Tasks T;
   int64_t psi_off = 0;
   int base_l = 0, base_r = 0, base_dress = 0;
+  // transposed copies of every operator block (operators applied as adjoints
+  // are read from these, so that all operand loads run along contiguous rows)
+  int base_lT = 0, base_rT = 0, base_dressT = 0;
   double *d_dress = nullptr;          // dressed right-block data (device)
-  std::vector<double> h_dress;        // host copy (test paths only)
+  double *d_lT = nullptr, *d_rT = nullptr, *d_dressT = nullptr;
+  std::vector<double> h_dress;        // host copies (test paths only)
+  std::vector<double> h_lT, h_rT, h_dressT;
 };
+
+std::vector<TransJob> trans_jobs(const BlockModel &M) {
+  std::vector<TransJob> v;
+  for (const dmrg_oprec_t &r : M.rec)
+    v.push_back({r.off, M.sec[r.row_sec].dim, M.sec[r.col_sec].dim, r.npos, 0});
+  return v;
+}
+
+std::vector<TransJob> trans_jobs(const Tasks &T) {
+  std::vector<TransJob> v;
+  for (const Dress &d : T.dress) v.push_back({d.off, d.rows, d.cols, d.npos, 0});
+  return v;
+}
+
+void transpose_on_host(const std::vector<TransJob> &jobs, const double *src, int64_t len, std::vector<double> &dst) {
+  dst.assign((size_t)std::max<int64_t>(len, 1), 0.0);
+  for (const TransJob &J : jobs) {
+    const int64_t bs = (int64_t)J.rows * J.cols;
+    for (int p = 0; p < J.npos; p++)
+      for (int c = 0; c < J.cols; c++)
+        for (int r = 0; r < J.rows; r++)
+          dst[J.off + p * bs + c + (int64_t)r * J.cols] = src[J.off + p * bs + r + (int64_t)c * J.rows];
+  }
+}
 
 }  // namespace
 
@@ -45,13 +77,37 @@ struct dmrg_plan {
   SliceBufs sb{};
   std::vector<uint16_t> h_sb[N_SBUF];      // host copies (test emulation only)
   std::vector<int32_t> h_se[N_SBUF];
-  std::vector<void *> allocs;
+  std::vector<void *> allocs;          // problem-level device memory (kept across re-planning)
+  std::vector<void *> plan_allocs;     // tile lists, workspace, slices (freed by re-planning)
+  // settings of the tile lists
+  int kpart = KPART, tile_policy = 0, xcd = 1, flags = 0;
+  int64_t budget = (int64_t)16 << 30;
+  int tuned = 0;
+  double tune_ms = 0.0;
   // profiling: events around every first- and second-stage launch
   int profiling = 0;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, std::pair<int, int>>> ev_marks;   // (stage, (start ev, stop ev))
   std::vector<double> ev_flops;                                  // algorithmic flops per mark
+  // recorded launch sequences, one per (psi, hpsi) pair
+  struct GraphEntry {
+    const double *psi;
+    double *y;
+    hipGraph_t g;
+    hipGraphExec_t x;
+  };
+  std::vector<GraphEntry> graphs;
+  hipStream_t cap_stream = nullptr;
+  void drop_graphs() {
+    for (auto &e : graphs) {
+      (void)hipGraphExecDestroy(e.x);
+      (void)hipGraphDestroy(e.g);
+    }
+    graphs.clear();
+  }
   ~dmrg_plan() {
+    drop_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (auto e : ev_pool) (void)hipEventDestroy(e);
   }
 };
@@ -68,13 +124,13 @@ namespace {
   } while (0)
 
 template <class T>
-int upload(dmrg_plan *p, const std::vector<T> &v, T **out) {
+int upload(dmrg_plan *p, const std::vector<T> &v, T **out, bool plan_level = true) {
   *out = nullptr;
   if (v.empty()) return DMRG_OK;
   void *d = nullptr;
   hipError_t e = hipMalloc(&d, sizeof(T) * v.size());
   if (e != hipSuccess) { set_error("hipMalloc failed for plan tables"); return DMRG_ENOMEM; }
-  p->allocs.push_back(d);
+  (plan_level ? p->plan_allocs : p->allocs).push_back(d);
   HIPCHK(hipMemcpy(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
   *out = (T *)d;
   return DMRG_OK;
@@ -98,11 +154,15 @@ struct TaskRef { int prob; int task; };
 
 // MFMA row blocks of the tiles of an m x n output: skinny outputs get 16x64 or
 // 64x16 tiles, the rest 32x32
-int tile_mb(int m, int n) {
+int tile_mb(int m, int n, int policy) {
   if (m <= 16) return 1;
-  if (n <= 16) return 4;
+  if (policy == 0 && n <= 16) return 4;
   return 2;
 }
+
+int prepare_device(dmrg_plan *P);
+int autotune(dmrg_plan *P, void *stream);
+int replan(dmrg_plan *P);
 
 int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
   // ---- split tasks into chunks whose stripes fit the workspace budget
@@ -165,7 +225,8 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
       woff += (int64_t)s.dL * s.dRout * s.slots.size();
       woff = (woff + 31) / 32 * 32;
       // first stage: T_h = X [op(D_s0) ... op(D_s1-1)] for each run of consecutive positions;
-      // slot s of the stripe is the d_L x d_R' block at off + s * d_L * d_R' (column-major)
+      // the stripe is a row-major d_L x (nslots d_R') matrix at off, slot s in
+      // columns [s d_R', (s+1) d_R')
       const ProbPlan &pp = *P->probs[kv.first.prob];
       const PsiBlock &E = pp.T.blocks[kv.first.E];
       const dmrg_oprec_t &rec = pp.R.rec[kv.first.rec];
@@ -179,17 +240,18 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
         g.a_off = pp.psi_off + E.off;
         g.a_p = 0; g.a_i = 1; g.a_k = s.dL;
         g.K = s.dRin; g.a_kb = s.dRin;
-        if (kv.first.dress >= 0) {
-          g.b_base = pp.base_dress;
+        const bool dressed = kv.first.dress >= 0, adj = kv.first.adj != 0;
+        if (dressed) {
+          g.b_base = adj ? pp.base_dressT : pp.base_dress;
           g.b_off = pp.T.dress[kv.first.dress].off + (int64_t)s.slots[s0] * rows * cols;
         } else {
-          g.b_base = pp.base_r;
+          g.b_base = adj ? pp.base_rT : pp.base_r;
           g.b_off = rec.off + (int64_t)s.slots[s0] * rows * cols;
         }
         g.b_kb = s.dRin; g.b_pk = 0;
         g.b_nb = s.dRout; g.b_pn = (int64_t)rows * cols;
-        if (!kv.first.adj) { g.b_k = rows; g.b_n = 1; }     // op(D) = D^T, stored d_R' x d_R
-        else { g.b_k = 1; g.b_n = rows; }                   // op(D) = D,   stored d_R x d_R'
+        if (!adj) { g.b_k = rows; g.b_n = 1; }    // op(D) = D^T, D stored d_R' x d_R
+        else { g.b_k = cols; g.b_n = 1; }         // op(D) = D from the transposed copy (d_R' x d_R)
         g.s = 1.0;
         int sidx = (int)ch.seg1.size();
         ch.seg1.push_back(g);
@@ -198,13 +260,14 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
         double fl = 2.0 * s.dL * s.dRin * N;
         P->stats.stage1_flops += fl;
         ch.flops1 += fl;
-        int mb = tile_mb(s.dL, N);
+        int mb = tile_mb(s.dL, N, P->tile_policy);
         for (int i0 = 0; i0 < s.dL; i0 += 16 * mb)
           for (int j0 = 0; j0 < N; j0 += 64 / mb) {
             Tile t{};
             t.c_base = BASE_WORK;
-            t.c_off = s.off + (int64_t)s0 * s.dL * s.dRout;
-            t.ldc = s.dL;
+            t.c_off = s.off + (int64_t)s0 * s.dRout;
+            t.ldc = (int64_t)s.slots.size() * s.dRout;
+            t.rowmajor = 1;
             t.m = s.dL; t.n = N; t.i0 = i0; t.j0 = j0; t.ci0 = i0; t.cj0 = j0;
             t.mb = mb;
             t.seg0 = sidx; t.nseg = 1; t.accumulate = 0;
@@ -247,28 +310,30 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
         Seg g{};
         g.s = tk.v * row.pos[q].alpha;
         if (st) {
-          // B = [T_s; T_s+1; ...]: slot s of the stripe at s * d_L * d_R'
+          // B = [T_s; T_s+1; ...]: slot s of the row-major stripe in columns s d_R'..
           g.b_base = BASE_WORK;
-          g.b_off = st->off + (int64_t)slot_of(row.pos[q].pD) * E.dL * F.dR;
+          g.b_off = st->off + (int64_t)slot_of(row.pos[q].pD) * F.dR;
           g.b_kb = E.dL;
-          g.b_pk = (int64_t)E.dL * F.dR;
-          g.b_k = 1;
+          g.b_pk = F.dR;
+          g.b_k = (int64_t)st->slots.size() * F.dR;
+          g.b_n = 1;
         } else {
           g.b_base = BASE_PSI;
           g.b_off = pp.psi_off + E.off;
           g.b_kb = E.dL;
           g.b_pk = 0;
           g.b_k = 1;
+          g.b_n = E.dL;
         }
-        g.b_nb = F.dR; g.b_pn = 0; g.b_n = E.dL;
+        g.b_nb = F.dR; g.b_pn = 0;
         Seg2Info inf{r.prob, tk.E, st ? st->index : -1, st ? slot_of(row.pos[q].pD) : 0,
                      tk.recA, tk.adjA, row.pos[q].pA, run};
         if (tk.recA >= 0) {
-          g.a_base = pp.base_l;
+          g.a_base = tk.adjA ? pp.base_lT : pp.base_l;
           g.a_off = recoffA + (int64_t)row.pos[q].pA * rowsA * colsA;
           g.a_p = (int64_t)rowsA * colsA;
           if (!tk.adjA) { g.a_i = 1; g.a_k = rowsA; }    // stored A is d_L' x d_L
-          else { g.a_i = rowsA; g.a_k = 1; }             // stored A is d_L x d_L'
+          else { g.a_i = 1; g.a_k = colsA; }             // A stored d_L x d_L', read from its transpose
           g.a_kb = E.dL;
           g.K = run * E.dL;
           P->stats.stage2_flops += 2.0 * F.dL * g.K * F.dR;
@@ -292,9 +357,9 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
       std::vector<Seg2Info> pinfo;
       for (auto &gi : kv.second) {
         const Seg &g = gi.first;
-        if (g.a_base < 0 || g.K <= KPART) { pieces.push_back(g); pinfo.push_back(gi.second); continue; }
+        if (g.a_base < 0 || g.K <= P->kpart) { pieces.push_back(g); pinfo.push_back(gi.second); continue; }
         int npos = g.K / g.a_kb;
-        int per = std::max(1, KPART / g.a_kb);
+        int per = std::max(1, P->kpart / g.a_kb);
         for (int p0 = 0; p0 < npos; p0 += per) {
           int p1 = std::min(npos, p0 + per);
           Seg h = g;
@@ -316,7 +381,7 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
       double cost = 0.0;
       for (int i = 0; i < (int)pieces.size(); i++) {
         double c = pieces[i].a_base < 0 ? 0.25 * pieces[i].K : (double)pieces[i].K;
-        if (i > b0 && cost + c > KPART) {
+        if (i > b0 && cost + c > P->kpart) {
           parts.push_back({b0, i});
           pcost.push_back(cost);
           b0 = i;
@@ -329,7 +394,7 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
       int seg0 = (int)ch.seg2.size();
       for (auto &g : pieces) ch.seg2.push_back(g);
       for (auto &gi : pinfo) ch.s2info.push_back(gi);
-      int mb = tile_mb(F.dL, F.dR);
+      int mb = tile_mb(F.dL, F.dR, P->tile_policy);
       int tm = 16 * mb, tn = 64 / mb;
       for (int i0 = 0; i0 < F.dL; i0 += tm)
         for (int j0 = 0; j0 < F.dR; j0 += tn) {
@@ -432,7 +497,33 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
     P->stats.n_segments += (int64_t)ch.seg2.size();
   }
   if ((rc = upload(P, P->dblocks, &P->d_dblocks)) || (rc = upload(P, P->dterms, &P->d_dterms))) return rc;
-  if ((rc = upload(P, P->bases_h, (const double ***)&P->d_bases))) return rc;
+  if (P->work_elems > 0) {
+    void *d = nullptr;
+    if (hipMalloc(&d, sizeof(double) * P->work_elems) != hipSuccess) {
+      set_error("hipMalloc failed for the stripe workspace");
+      return DMRG_ENOMEM;
+    }
+    P->plan_allocs.push_back(d);
+    P->d_work = (double *)d;
+  }
+  if (P->part_elems > 0) {
+    void *d = nullptr;
+    if (hipMalloc(&d, sizeof(double) * P->part_elems) != hipSuccess) {
+      set_error("hipMalloc failed for the partial-tile buffer");
+      return DMRG_ENOMEM;
+    }
+    P->plan_allocs.push_back(d);
+    P->d_part = (double *)d;
+  }
+  return DMRG_OK;
+}
+
+// Device data that depend on the problems only: operand base table, dressed
+// right-block operators and transposed operator copies (kept across
+// re-planning).
+int prepare_device(dmrg_plan *P) {
+  int rc;
+  if ((rc = upload(P, P->bases_h, (const double ***)&P->d_bases, false))) return rc;
   // dressed right-block operators: computed on the device once
   for (auto &ppu : P->probs) {
     ProbPlan &pp = *ppu;
@@ -461,30 +552,28 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
     DressItem *d_items = nullptr;
     int64_t *d_soff = nullptr;
     double *d_alpha = nullptr;
-    if ((rc = upload(P, items, &d_items)) || (rc = upload(P, soff, &d_soff)) || (rc = upload(P, alpha, &d_alpha)))
+    if ((rc = upload(P, items, &d_items, false)) || (rc = upload(P, soff, &d_soff, false)) ||
+        (rc = upload(P, alpha, &d_alpha, false)))
       return rc;
     launch_dress(d_items, (int)items.size(), d_soff, d_alpha, P->d_bases, pp.d_dress, nullptr);
     HIPCHK(hipGetLastError());
   }
   HIPCHK(hipDeviceSynchronize());
-  if (P->work_elems > 0) {
-    void *d = nullptr;
-    if (hipMalloc(&d, sizeof(double) * P->work_elems) != hipSuccess) {
-      set_error("hipMalloc failed for the stripe workspace");
-      return DMRG_ENOMEM;
+  // transposed operator copies
+  for (auto &ppu : P->probs) {
+    ProbPlan &pp = *ppu;
+    const double *src[3] = {P->bases_h[pp.base_l - BASE_OPS], P->bases_h[pp.base_r - BASE_OPS], pp.d_dress};
+    double *dst[3] = {pp.d_lT, pp.d_rT, pp.d_dressT};
+    std::vector<TransJob> jobs[3] = {trans_jobs(pp.L), trans_jobs(pp.R), trans_jobs(pp.T)};
+    for (int q = 0; q < 3; q++) {
+      if (!src[q] || !dst[q] || jobs[q].empty()) continue;
+      TransJob *d_jobs = nullptr;
+      if ((rc = upload(P, jobs[q], &d_jobs, false))) return rc;
+      launch_transpose(d_jobs, (int)jobs[q].size(), src[q], dst[q], nullptr);
+      HIPCHK(hipGetLastError());
     }
-    P->allocs.push_back(d);
-    P->d_work = (double *)d;
   }
-  if (P->part_elems > 0) {
-    void *d = nullptr;
-    if (hipMalloc(&d, sizeof(double) * P->part_elems) != hipSuccess) {
-      set_error("hipMalloc failed for the partial-tile buffer");
-      return DMRG_ENOMEM;
-    }
-    P->allocs.push_back(d);
-    P->d_part = (double *)d;
-  }
+  HIPCHK(hipDeviceSynchronize());
   return DMRG_OK;
 }
 
@@ -599,7 +688,7 @@ void build_split(dmrg_plan *P) {
     for (const StripeInfo &si : ch.stripes) {
       SliceJob j{};
       j.src_base = BASE_WORK; j.src_off = si.off;
-      j.s_rho = si.dL; j.s_pos = (int64_t)si.dL * si.dRout; j.s_k = 1;
+      j.s_rho = 1; j.s_pos = si.dRout; j.s_k = (int64_t)si.nslots * si.dRout;
       j.nrho = si.dRout; j.npos = si.nslots; j.kb = si.dL; j.kbp = rup8(si.dL);
       j.dst_buf = SBUF_T; j.dst_off = te; j.exp_off = tx;
       toff.push_back({te, tx, j.kbp});
@@ -682,8 +771,8 @@ int upload_split(dmrg_plan *P) {
       set_error("hipMalloc failed for slice buffers");
       return DMRG_ENOMEM;
     }
-    P->allocs.push_back(d);
-    P->allocs.push_back(e);
+    P->plan_allocs.push_back(d);
+    P->plan_allocs.push_back(e);
     P->sb.data[b] = (uint16_t *)d;
     P->sb.exps[b] = (int32_t *)e;
     P->sb.plane[b] = P->sb_elems[b];
@@ -696,8 +785,156 @@ int upload_split(dmrg_plan *P) {
 }
 }  // namespace
 
+namespace {
+
+// Frees the tile lists, workspace and slices (not the problem-level data).
+void release_plan(dmrg_plan *P) {
+  (void)hipDeviceSynchronize();
+  P->drop_graphs();
+  for (void *a : P->plan_allocs) (void)hipFree(a);
+  P->plan_allocs.clear();
+  P->chunks.clear();
+  P->dblocks.clear();
+  P->dterms.clear();
+  P->d_dblocks = nullptr;
+  P->d_dterms = nullptr;
+  P->d_work = nullptr;
+  P->d_part = nullptr;
+  P->work_elems = P->part_elems = 0;
+  P->jobs_ops.clear();
+  P->jobs_psi.clear();
+  P->d_jobs_ops = P->d_jobs_psi = nullptr;
+  P->sb = SliceBufs{};
+  for (int b = 0; b < N_SBUF; b++) P->sb_elems[b] = P->sb_exps[b] = 0;
+  P->stats.n_stage1 = P->stats.n_segments = 0;
+}
+
+// Tile lists for the plan's current settings.
+int replan(dmrg_plan *P) {
+  release_plan(P);
+  int rc = build_plan(P, P->budget, true);
+  if (!rc && P->precision == DMRG_SPLIT_BF16) rc = upload_split(P);
+  return rc;
+}
+
+// The launch sequence of one H.psi.
+int enqueue(dmrg_plan *p, const double *psi, double *hpsi, void *stream, bool prof);
+
+int time_apply(dmrg_plan *P, const double *x, double *y, void *stream, double *ms) {
+  hipStream_t s = (hipStream_t)stream;
+  int rc = enqueue(P, x, y, stream, false);
+  if (rc) return rc;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, s));
+  for (int i = 0; i < 3 && !rc; i++) rc = enqueue(P, x, y, stream, false);
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventSynchronize(e1));
+  float f = 0.0f;
+  HIPCHK(hipEventElapsedTime(&f, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = f / 3.0;
+  return rc;
+}
+
+// FNV-1a hash of what the tile lists depend on
+uint64_t plan_hash(const dmrg_plan *P) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](int64_t v) {
+    for (int i = 0; i < 8; i++) {
+      h ^= (uint64_t)((v >> (8 * i)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  };
+  mix(P->precision);
+  mix(P->n_slices);
+  mix(P->xcd);
+  mix(P->budget);
+  for (const auto &pp : P->probs) {
+    mix((int64_t)pp->T.blocks.size());
+    for (const PsiBlock &b : pp->T.blocks) mix(((int64_t)b.dL << 32) | b.dR);
+    mix((int64_t)pp->T.tasks.size());
+    mix((int64_t)pp->T.rows.size());
+  }
+  return h;
+}
+
+std::mutex g_tune_mu;
+std::map<uint64_t, std::array<int64_t, 3>> g_tune_cache;   // kpart, tile policy, workspace cap
+
+// Times candidate settings on the live plan and keeps the fastest (see
+// DMRG_PLAN_AUTOTUNE): first kpart x tile policy at the requested workspace
+// cap, then smaller caps (more, smaller launches whose stripes stay in the
+// last-level cache) with the best of the first round.
+int autotune(dmrg_plan *P, void *stream) {
+  auto t0 = std::chrono::steady_clock::now();
+  const uint64_t key = plan_hash(P);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      P->kpart = (int)it->second[0];
+      P->tile_policy = (int)it->second[1];
+      P->budget = it->second[2];
+      P->tuned = 0;
+      int rc = replan(P);
+      P->tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      return rc;
+    }
+  }
+  double *x = nullptr, *y = nullptr;
+  if (hipMalloc((void **)&x, sizeof(double) * std::max<int64_t>(P->psi_len, 1)) != hipSuccess ||
+      hipMalloc((void **)&y, sizeof(double) * std::max<int64_t>(P->psi_len, 1)) != hipSuccess) {
+    if (x) (void)hipFree(x);
+    set_error("hipMalloc failed in the autotuner");
+    return DMRG_ENOMEM;
+  }
+  int rc = hipMemset(x, 0, sizeof(double) * std::max<int64_t>(P->psi_len, 1)) == hipSuccess ? DMRG_OK : DMRG_EHIP;
+  const int64_t base = P->budget;
+  double best = 1e300;
+  std::array<int64_t, 3> bc{P->kpart, P->tile_policy, base};
+  auto trial = [&](int kp, int pol, int64_t budget) {
+    if (rc) return;
+    P->kpart = kp;
+    P->tile_policy = pol;
+    P->budget = budget;
+    double ms = 0.0;
+    rc = replan(P);
+    if (!rc) rc = time_apply(P, x, y, stream, &ms);
+    P->tuned++;
+    if (!rc && ms < best) {
+      best = ms;
+      bc = {kp, pol, budget};
+    }
+  };
+  for (int kp : {1024, 2048, 4096})
+    for (int pol : {0, 1}) trial(kp, pol, base);
+  for (int64_t b : {(int64_t)512 << 20, (int64_t)192 << 20})
+    if (b < base) trial((int)bc[0], (int)bc[1], b);
+  (void)hipFree(x);
+  (void)hipFree(y);
+  if (rc) return rc;
+  P->kpart = (int)bc[0];
+  P->tile_policy = (int)bc[1];
+  P->budget = bc[2];
+  rc = replan(P);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = bc;
+  }
+  P->tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return rc;
+}
+
+}  // namespace
+
 extern "C" void dmrg_plan_free(dmrg_plan_t *p) {
   if (!p) return;
+  (void)hipDeviceSynchronize();
+  p->drop_graphs();
+  for (void *a : p->plan_allocs) (void)hipFree(a);
   for (void *a : p->allocs) (void)hipFree(a);
   delete p;
 }
@@ -752,6 +989,25 @@ extern "C" int dmrg_build_tasks(const dmrg_problem_t *probs, int32_t n_probs, co
         pp->d_dress = (double *)d;
       }
       P->bases_h.push_back(pp->d_dress);
+      // transposed copies (filled on the device by build_plan)
+      double **tdst[3] = {&pp->d_lT, &pp->d_rT, &pp->d_dressT};
+      const int64_t tlen[3] = {probs[k].ldata ? probs[k].ldata_len : 0, probs[k].rdata ? probs[k].rdata_len : 0,
+                               pp->T.dress_len};
+      int *tbase[3] = {&pp->base_lT, &pp->base_rT, &pp->base_dressT};
+      for (int q = 0; q < 3; q++) {
+        *tbase[q] = BASE_OPS + (int)P->bases_h.size();
+        if (tlen[q] > 0) {
+          void *d = nullptr;
+          if (hipMalloc(&d, sizeof(double) * tlen[q]) != hipSuccess) {
+            set_error("hipMalloc failed for transposed operators");
+            dmrg_plan_free(P);
+            return DMRG_ENOMEM;
+          }
+          P->allocs.push_back(d);
+          *tdst[q] = (double *)d;
+        }
+        P->bases_h.push_back(*tdst[q]);
+      }
       P->stats.n_blocks += (int64_t)pp->T.blocks.size();
       P->stats.n_rows += (int64_t)pp->T.rows.size();
       for (auto &tk : pp->T.tasks) P->stats.n_tasks += (int64_t)pp->T.rows[tk.row].pos.size();
@@ -759,12 +1015,19 @@ extern "C" int dmrg_build_tasks(const dmrg_problem_t *probs, int32_t n_probs, co
     }
     P->psi_len = off;
     P->stats.psi_len = off;
-    int rc = build_plan(P, budget, true);
-    if (rc) { dmrg_plan_free(P); return rc; }
-    if (P->precision == DMRG_SPLIT_BF16) {
-      rc = upload_split(P);
-      if (rc) { dmrg_plan_free(P); return rc; }
+    P->flags = opts ? opts->flags : 0;
+    P->xcd = (P->flags & DMRG_PLAN_NO_XCD) ? 0 : 1;
+    P->kpart = (opts && opts->kpart > 0) ? opts->kpart : KPART;
+    P->tile_policy = opts ? opts->tile_policy : 0;
+    P->budget = budget;
+    if (P->kpart < 64 || P->kpart > (1 << 20) || P->tile_policy < 0 || P->tile_policy > 1) {
+      set_error("kpart must be in [64, 2^20] and tile_policy 0 or 1");
+      dmrg_plan_free(P);
+      return DMRG_EINVAL;
     }
+    int rc = prepare_device(P);
+    if (!rc) rc = (P->flags & DMRG_PLAN_AUTOTUNE) ? autotune(P, stream) : replan(P);
+    if (rc) { dmrg_plan_free(P); return rc; }
     *out = P;
     return DMRG_OK;
   } catch (const std::exception &e) {
@@ -790,9 +1053,8 @@ static int next_event(dmrg_plan *p, size_t &idx) {
   return DMRG_OK;
 }
 
-extern "C" int dmrg_apply_H(dmrg_plan_t *p, const double *psi, double *hpsi, void *stream) {
-  if (!p || !psi || !hpsi) { set_error("null argument"); return DMRG_EINVAL; }
-  if (psi == hpsi) { set_error("psi and hpsi must not alias"); return DMRG_EINVAL; }
+namespace {
+int enqueue(dmrg_plan *p, const double *psi, double *hpsi, void *stream, bool prof) {
   launch_zero(hpsi, p->psi_len, stream);
   const bool split = p->precision == DMRG_SPLIT_BF16;
   if (split)
@@ -801,7 +1063,7 @@ extern "C" int dmrg_apply_H(dmrg_plan_t *p, const double *psi, double *hpsi, voi
   for (auto &ch : p->chunks) {
     for (int stage = 1; stage <= 2; stage++) {
       int e0 = -1;
-      if (p->profiling) {
+      if (prof) {
         int rc = next_event(p, ev);
         if (rc) return rc;
         e0 = (int)ev;
@@ -812,17 +1074,17 @@ extern "C" int dmrg_apply_H(dmrg_plan_t *p, const double *psi, double *hpsi, voi
       if (split) {
         if (stage == 1)
           launch_tiles_split(1, ch.d_tile1, ch.d_seg1, ch.d_sseg1, (int)ch.tile1.size(), p->n_slices, p->d_bases,
-                             psi, hpsi, p->d_work, p->d_part, p->sb, stream);
+                             psi, hpsi, p->d_work, p->d_part, p->sb, p->xcd, stream);
         else
           launch_tiles_split(2, ch.d_tile2, ch.d_seg2, ch.d_sseg2, (int)ch.tile2.size(), p->n_slices, p->d_bases,
-                             psi, hpsi, p->d_work, p->d_part, p->sb, stream);
+                             psi, hpsi, p->d_work, p->d_part, p->sb, p->xcd, stream);
       } else if (stage == 1)
         launch_tiles_f64(1, ch.d_tile1, ch.d_seg1, (int)ch.tile1.size(), p->d_bases, psi, hpsi, p->d_work,
-                         p->d_part, stream);
+                         p->d_part, p->xcd, stream);
       else
         launch_tiles_f64(2, ch.d_tile2, ch.d_seg2, (int)ch.tile2.size(), p->d_bases, psi, hpsi, p->d_work,
-                         p->d_part, stream);
-      if (p->profiling) {
+                         p->d_part, p->xcd, stream);
+      if (prof) {
         int rc = next_event(p, ev);
         if (rc) return rc;
         HIPCHK(hipEventRecord(p->ev_pool[ev], (hipStream_t)stream));
@@ -834,6 +1096,47 @@ extern "C" int dmrg_apply_H(dmrg_plan_t *p, const double *psi, double *hpsi, voi
     launch_reduce(ch.d_red2, (int)ch.red2.size(), p->d_part, hpsi, stream);
   }
   HIPCHK(hipGetLastError());
+  return DMRG_OK;
+}
+}  // namespace
+
+extern "C" int dmrg_apply_H(dmrg_plan_t *p, const double *psi, double *hpsi, void *stream) {
+  if (!p || !psi || !hpsi) { set_error("null argument"); return DMRG_EINVAL; }
+  if (psi == hpsi) { set_error("psi and hpsi must not alias"); return DMRG_EINVAL; }
+  if (!(p->flags & DMRG_PLAN_GRAPH) || p->profiling) return enqueue(p, psi, hpsi, stream, p->profiling != 0);
+  dmrg_plan::GraphEntry *ge = nullptr;
+  for (auto &e : p->graphs)
+    if (e.psi == psi && e.y == hpsi) ge = &e;
+  if (!ge) {
+    if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    if (p->graphs.size() >= 64) {
+      (void)hipGraphExecDestroy(p->graphs.front().x);
+      (void)hipGraphDestroy(p->graphs.front().g);
+      p->graphs.erase(p->graphs.begin());
+    }
+    HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue(p, psi, hpsi, p->cap_stream, false);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) {
+      set_error(std::string("HIP error: ") + hipGetErrorString(e) + " at graph capture");
+      return DMRG_EHIP;
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      set_error(std::string("HIP error: ") + hipGetErrorString(e) + " at graph instantiation");
+      return DMRG_EHIP;
+    }
+    p->graphs.push_back({psi, hpsi, g, x});
+    ge = &p->graphs.back();
+  }
+  HIPCHK(hipGraphLaunch(ge->x, (hipStream_t)stream));
   return DMRG_OK;
 }
 
@@ -876,6 +1179,12 @@ extern "C" int dmrg_diag_H(dmrg_plan_t *p, double *diag, void *stream) {
 extern "C" int dmrg_plan_stats(const dmrg_plan_t *p, dmrg_plan_stats_t *st) {
   if (!p || !st) { set_error("null argument"); return DMRG_EINVAL; }
   *st = p->stats;
+  st->kpart = p->kpart;
+  st->tile_policy = p->tile_policy;
+  st->xcd = p->xcd;
+  st->tuned = p->tuned;
+  st->workspace_cap = p->budget;
+  st->tune_ms = p->tune_ms;
   return DMRG_OK;
 }
 
@@ -921,7 +1230,8 @@ static void host_tiles(const std::vector<Tile> &tiles, const std::vector<Seg> &s
     double *C = const_cast<double *>(base(T.c_base)) + T.c_off;
     for (int j = 0; j < nt; j++)
       for (int i = 0; i < mt; i++) {
-        double &c = C[(int64_t)(T.ci0 + i) + (int64_t)(T.cj0 + j) * T.ldc];
+        double &c = T.rowmajor ? C[(int64_t)(T.ci0 + i) * T.ldc + (T.cj0 + j)]
+                               : C[(int64_t)(T.ci0 + i) + (int64_t)(T.cj0 + j) * T.ldc];
         c = T.accumulate ? c + acc[i + (size_t)j * mt] : acc[i + (size_t)j * mt];
       }
   }
@@ -1026,7 +1336,8 @@ static void host_tiles_split(const std::vector<Tile> &tiles, const std::vector<S
     double *C = const_cast<double *>(base(T.c_base)) + T.c_off;
     for (int j = 0; j < nt; j++)
       for (int i = 0; i < mt; i++) {
-        double &c = C[(int64_t)(T.ci0 + i) + (int64_t)(T.cj0 + j) * T.ldc];
+        double &c = T.rowmajor ? C[(int64_t)(T.ci0 + i) * T.ldc + (T.cj0 + j)]
+                               : C[(int64_t)(T.ci0 + i) + (int64_t)(T.cj0 + j) * T.ldc];
         c = T.accumulate ? c + acc[i + (size_t)j * mt] : acc[i + (size_t)j * mt];
       }
   }
@@ -1051,6 +1362,8 @@ extern "C" int dmrg_debug_plan_host_apply(const dmrg_problem_t *prob, const doub
   std::memset(&P->stats, 0, sizeof(P->stats));
   P->precision = opts ? opts->precision : DMRG_FP64;
   P->n_slices = opts ? opts->n_slices : 0;
+  P->kpart = (opts && opts->kpart > 0) ? opts->kpart : KPART;
+  P->tile_policy = opts ? opts->tile_policy : 0;
   auto pp = std::make_unique<ProbPlan>();
   Error err{0, ""};
   if (build_tasks_for_problem(*prob, pp->L, pp->R, pp->T, err)) {
@@ -1061,8 +1374,16 @@ extern "C" int dmrg_debug_plan_host_apply(const dmrg_problem_t *prob, const doub
   pp->base_l = BASE_OPS;
   pp->base_r = BASE_OPS + 1;
   pp->base_dress = BASE_OPS + 2;
+  pp->base_lT = BASE_OPS + 3;
+  pp->base_rT = BASE_OPS + 4;
+  pp->base_dressT = BASE_OPS + 5;
   dress_on_host(pp->T, pp->R, pp->h_dress);
-  P->bases_h = {prob->ldata, prob->rdata, pp->h_dress.data()};
+  if (prob->ldata) transpose_on_host(trans_jobs(pp->L), prob->ldata, prob->ldata_len, pp->h_lT);
+  if (prob->rdata) transpose_on_host(trans_jobs(pp->R), prob->rdata, prob->rdata_len, pp->h_rT);
+  if (!pp->h_dress.empty())
+    transpose_on_host(trans_jobs(pp->T), pp->h_dress.data(), (int64_t)pp->h_dress.size(), pp->h_dressT);
+  P->bases_h = {prob->ldata, prob->rdata, pp->h_dress.data(), pp->h_lT.data(), pp->h_rT.data(),
+                pp->h_dressT.data()};
   int64_t n = pp->T.size;
   P->stats.psi_len = n;
   P->stats.n_blocks = (int64_t)pp->T.blocks.size();

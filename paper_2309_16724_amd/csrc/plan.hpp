@@ -21,9 +21,10 @@ struct Seg {
   int32_t K, a_kb, b_kb, b_nb;
 };
 
-// One work item: a (16*mb) x (64/mb) tile of an m x n column-major output
-// block (rows i0.., columns j0..) accumulated over segments seg0..seg0+nseg-1
-// and stored at C + (ci0 + i) + (cj0 + j) * ldc (C += or C =).
+// One work item: a (16*mb) x (64/mb) tile of an m x n output block (rows
+// i0.., columns j0..) accumulated over segments seg0..seg0+nseg-1 and stored
+// at C + (ci0 + i) + (cj0 + j) * ldc (column-major) or at
+// C + (ci0 + i) * ldc + (cj0 + j) (rowmajor) (C += or C =).
 struct Tile {
   int64_t c_off;
   int64_t ldc;
@@ -33,6 +34,14 @@ struct Tile {
   int32_t mb;           // MFMA row blocks: 1, 2 or 4 (column blocks 4 / mb)
   int32_t seg0, nseg;
   int32_t accumulate;   // 1: C += acc, 0: C = acc
+  int32_t rowmajor;     // output layout, see above
+};
+
+// Transposed copy of one operator record: npos column-major rows x cols
+// blocks at off become cols x rows blocks at the same offset.
+struct TransJob {
+  int64_t off;
+  int32_t rows, cols, npos, pad;
 };
 
 // Deterministic sum of the partial tiles of one output tile into Y.
@@ -141,8 +150,9 @@ void launch_zero(double *y, int64_t n, void *stream);
 void launch_dress(const DressItem *items, int nitems, const int64_t *src_off, const double *alpha,
                   const double *const *bases, double *dst, void *stream);
 void launch_tiles_f64(int stage, const Tile *tiles, const Seg *segs, int ntiles, const double *const *bases,
-                      const double *psi, double *y, double *work, double *part, void *stream);
+                      const double *psi, double *y, double *work, double *part, int xcd, void *stream);
 void launch_reduce(const Reduce *red, int nred, const double *part, double *y, void *stream);
+void launch_transpose(const TransJob *jobs, int njobs, const double *src, double *dst, void *stream);
 void launch_diag(const DiagBlock *blocks, const DiagTerm *terms, int nblocks,
                  const double *const *bases, double *diag, void *stream);
 
@@ -153,6 +163,6 @@ void launch_slices(const SliceJob *jobs, int njobs, int nslices, const double *c
                    const double *work, SliceBufs bufs, void *stream);
 void launch_tiles_split(int stage, const Tile *tiles, const Seg *segs, const SegS *ssegs, int ntiles,
                         int nslices, const double *const *bases, const double *psi, double *y, double *work,
-                        double *part, SliceBufs bufs, void *stream);
+                        double *part, SliceBufs bufs, int xcd, void *stream);
 
 }  // namespace dmrg

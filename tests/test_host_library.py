@@ -140,3 +140,18 @@ def test_plan_host_emulation_fp64_and_chunked(lib):
         assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
         if ws:
             assert st["n_chunks"] > 1
+
+
+@pytest.mark.parametrize("kpart,policy", [(64, 0), (128, 1), (4096, 1)])
+def test_plan_host_emulation_tuning_knobs(lib, kpart, policy):
+    """Every setting the autotuner may choose gives the same H.psi: small
+    split-K parts (many partial tiles), the square tile policy, both precisions."""
+    prob = random_problem(7, 7, 1, 8, D=150, cap=False)
+    he = HEff(prob)
+    x = np.random.default_rng(5).standard_normal(he.size)
+    ref = he.apply(x)
+    y, st = B.debug_plan_host_apply(prob, x, kpart=kpart, tile_policy=policy, lib=lib)
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+    ys, _ = B.debug_plan_host_apply(prob, x, precision=1, n_slices=5, kpart=kpart, tile_policy=policy,
+                                    lib=lib)
+    assert np.abs(ys - ref).max() <= 1e-10 * np.abs(ref).max()
