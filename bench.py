@@ -64,6 +64,88 @@ def cpu_baseline(prob, flops_full, target_s=15.0):
     }
 
 
+def train_preconditioner(torch, specs, steps=2000, batch=4096, seed=0, width=256):
+    """Learned preconditioner: exact-correction rows of the given solves
+    (device capture), then minibatch Adam on the device."""
+    from paper_2309_16724_amd.hpsi import Plan
+    from paper_2309_16724_amd.precond import MLP
+    from paper_2309_16724_amd.synth.problem import random_problem, random_vector
+    t0 = time.time()
+    xs, as_, bs, nrec = [], [], [], 0
+    for L, N, s2, sd, D in specs:
+        plan = Plan(random_problem(L, N, s2, sd, D=D))
+        x0 = torch.from_numpy(random_vector(plan.size, 100)).cuda()
+        x, a, b, nr = plan.collect(x0, capacity=plan.size * 500)
+        plan.free()
+        xs.append(x)
+        as_.append(a)
+        bs.append(b)
+        nrec += nr
+    x, a, b = torch.cat(xs), torch.cat(as_), torch.cat(bs)
+    t1 = time.time()
+    net = MLP(width, seed=seed)
+    tr = net.train(x, a, b, steps=steps, batch=batch, lr=1e-3, seed=seed + 1, trace=True)
+    t2 = time.time()
+    info = {"solves": len(specs), "records": nrec, "rows": int(x.shape[0]), "steps": steps,
+            "batch": batch, "width": width, "collect_s": t1 - t0, "train_s": t2 - t1,
+            "loss_first100": float(tr[:100].mean()), "loss_last100": float(tr[-100:].mean()),
+            "specs": [list(s_) for s_ in specs]}
+    del xs, as_, bs, x, a, b
+    return net, info
+
+
+def run_batch(args):
+    """Batched uneven problems: one plan over many independent middle-bond
+    problems, H.psi in FP64 and split-BF16 (s=5), autotuned."""
+    import numpy as np
+    import torch
+    from paper_2309_16724_amd.binding import DMRG_PLAN_AUTOTUNE
+    from paper_2309_16724_amd.hpsi import Plan
+    from paper_2309_16724_amd.synth.problem import batch_specs, random_problem
+    specs = batch_specs(args.batch, 3, seed0=1000)
+    t0 = time.time()
+    probs = [random_problem(L, N, s2, sd, D=D) for L, N, s2, sd, D in specs]
+    print("# generated %d problems in %.1f s" % (len(probs), time.time() - t0), file=sys.stderr, flush=True)
+    res = {}
+    ys = {}
+    for name, prec, ns in (("fp64", 0, 0), ("split", 1, 5)):
+        t1 = time.time()
+        plan = Plan(probs, precision=prec, n_slices=ns, flags=0 if args.no_autotune else DMRG_PLAN_AUTOTUNE)
+        st = plan.stats()
+        print("# batch plan %s built in %.1f s: %s" % (name, time.time() - t1, json.dumps(st)), file=sys.stderr,
+              flush=True)
+        x = torch.from_numpy(np.random.default_rng(100).standard_normal(plan.size)).cuda()
+        y = torch.empty_like(x)
+        for _ in range(args.warmup):
+            plan.apply(x, y)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            plan.apply(x, y)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        segs = [plan.layout(k) for k in range(len(probs))]
+        ys[name] = (y.cpu().numpy(), segs)
+        res[name] = {"ms_per_step": ms, "tflops": st["flops"] / (ms * 1e-3) / 1e12, "flops": st["flops"],
+                     "psi_len": st["psi_len"], "kpart": st["kpart"], "tile_policy": st["tile_policy"],
+                     "workspace_cap": st["workspace_cap"], "tune_ms": st["tune_ms"]}
+        plan.free()
+    yf, segs = ys["fp64"]
+    yb, _ = ys["split"]
+    errs = [float(np.abs(yb[o:o + n] - yf[o:o + n]).max() / np.abs(yf[o:o + n]).max()) for o, n in segs]
+    out = {"metric": "batched H.psi TFLOP/s (split-BF16 s=5 and FP64)", "value": res["split"]["tflops"],
+           "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": res["split"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bf16x5 slices, fp32 accumulate, fp64 fold", "data": "synthetic",
+           "config": {"workload": "batch%d_L16-32_D128-768" % args.batch, "problems": len(probs),
+                      "specs": [list(s_) for s_ in specs]},
+           "fp64": res["fp64"], "split": res["split"],
+           "split_rel_err_vs_fp64": {"max": max(errs), "median": float(np.median(errs))}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,29 +153,38 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="L24_D512", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the default tile settings instead of autotuning each plan")
+    ap.add_argument("--no-mlp", action="store_true", help="skip the learned-preconditioner Davidson")
     ap.add_argument("--hpsi-only", choices=("fp64", "split"),
                     help="time only H.psi of one precision (for profiler runs); also copies "
                          "256 MiB once with a plain device copy as a counter reference")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="instead of the single workload, time H.psi of a batch of this many "
+                         "uneven problems (L in [16, 32], D in [128, 768], S in {0, 1})")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.batch:
+        return run_batch(args)
     import numpy as np
     import torch
-    from paper_2309_16724_amd.synth.problem import random_problem
+    from paper_2309_16724_amd.binding import DMRG_PLAN_AUTOTUNE
     from paper_2309_16724_amd.hpsi import Plan
+    from paper_2309_16724_amd.synth.problem import random_problem
 
     w = WORKLOADS[args.workload]
-    t0 = time.time()
     prob = random_problem(w["n_orb"], w["n_elec"], w["two_s"], w["seed"], D=w["D"])
     sizer = Plan(prob)
     x_np = np.random.default_rng(100).standard_normal(sizer.size)
     x_np /= np.linalg.norm(x_np)
     sizer.free()
+    plan_flags = 0 if args.no_autotune else DMRG_PLAN_AUTOTUNE
 
     def run(precision, ns):
-        plan = Plan(prob, precision=precision, n_slices=ns)
+        plan = Plan(prob, precision=precision, n_slices=ns, flags=plan_flags)
         st = plan.stats()
         print("# plan %s prec=%d s=%d: %s" % (args.workload, precision, ns, json.dumps(st)),
               file=sys.stderr, flush=True)
@@ -102,6 +193,7 @@ def main():
         for _ in range(args.warmup):
             plan.apply(x, y)
         torch.cuda.synchronize()
+        # the timed region: per-launch HIP events on the library's stream
         plan.set_profiling(True)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record()
@@ -127,18 +219,36 @@ def main():
         prec, ns = (0, 0) if args.hpsi_only == "fp64" else (1, 5)
         st, ms, prof, _ = run(prec, ns)
         print(json.dumps({"hpsi_only": args.hpsi_only, "workload": args.workload, "ms_per_step": ms,
-                          "tflops": st["flops"] / (ms * 1e-3) / 1e12, "stages": prof}), flush=True)
+                          "tflops": st["flops"] / (ms * 1e-3) / 1e12, "stages": prof,
+                          "kpart": st["kpart"], "tile_policy": st["tile_policy"],
+                          "workspace_cap": st["workspace_cap"]}), flush=True)
         return
     st64, ms64, prof64, y64 = run(0, 0)
     st5, ms5, prof5, y5 = run(1, 5)
     rel = float(np.abs(y5 - y64).max() / np.abs(y64).max())
     # Davidson s/step (FP64 path, diagonal preconditioner) on the same workload
-    plan = Plan(prob)
+    plan = Plan(prob, flags=plan_flags)
     x0 = torch.from_numpy(x_np).cuda()
     torch.cuda.synchronize()
     td = time.time()
     e_dav, _, dst = plan.davidson(x0, tol=1e-8)
     t_dav = time.time() - td
+    davidson = {"s_per_step": t_dav, "iterations": dst["iters"], "n_hpsi": dst["n_hpsi"],
+                "residual": dst["residual"], "energy": e_dav, "precision": "fp64",
+                "preconditioner": "diagonal", "t_hpsi_s": dst["t_hpsi_s"]}
+    learned = None
+    if not args.no_mlp:
+        net, info = train_preconditioner(torch, [(24, 24, 0, 10000 + k, 512) for k in range(4)])
+        print("# learned preconditioner: %s" % json.dumps(info), file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        tm = time.time()
+        e_mlp, _, mst = plan.davidson(x0, tol=1e-8, mlp=net, check=False)
+        t_mlp = time.time() - tm
+        net.free()
+        learned = {"s_per_step": t_mlp, "iterations": mst["iters"], "n_hpsi": mst["n_hpsi"],
+                   "converged": mst["converged"], "fallbacks": mst["fallbacks"],
+                   "energy_minus_diagonal": e_mlp - e_dav, "t_hpsi_s": mst["t_hpsi_s"],
+                   "speedup_vs_diagonal": t_dav / t_mlp, "training": info}
     plan.free()
     dom = max((1, 2), key=lambda s_: prof5[s_][1])
     n_l, ms_l, fl_l = prof5[dom]
@@ -148,6 +258,7 @@ def main():
     n6, ms6, fl6 = prof64[dom64]
     tflops5 = st5["flops"] / (ms5 * 1e-3) / 1e12
     tflops64 = st64["flops"] / (ms64 * 1e-3) / 1e12
+    ach64 = (fl6 / n6) / (ms6 / n6 * 1e-3) / 1e12
     out = {
         "metric": "H.psi TFLOP/s (split-BF16 s=5 at <=1e-10 rel err vs FP64; algorithmic FP64-equivalent "
                   "flops); FP64 path and Davidson s/step alongside",
@@ -163,15 +274,16 @@ def main():
         "dtype": "bf16x5 slices, fp32 accumulate, fp64 fold",
         "data": "synthetic",
         "config": {"workload": args.workload, **w, "psi_len": int(x_np.size),
-                   "flops_per_hpsi": st5["flops"], "n_slices": 5},
+                   "flops_per_hpsi": st5["flops"], "n_slices": 5,
+                   "split_plan": {k: st5[k] for k in ("kpart", "tile_policy", "workspace_cap")},
+                   "fp64_plan": {k: st64[k] for k in ("kpart", "tile_policy", "workspace_cap")}},
         "split_rel_err_vs_fp64": rel,
         "fp64": {"value": tflops64, "ms_per_step": ms64,
-                 "dominant_kernel": "stage%d_f64_kernel" % dom64,
-                 "achieved": (fl6 / n6) / (ms6 / n6 * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS},
+                 "roofline": {"bound": "mfma", "kernel": "stage%d_f64_kernel" % dom64, "achieved": ach64,
+                              "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach64 / FP64_PEAK_TFLOPS}},
         "speedup_split_vs_fp64": ms64 / ms5,
-        "davidson": {"s_per_step": t_dav, "iterations": dst["iters"], "n_hpsi": dst["n_hpsi"],
-                     "residual": dst["residual"], "energy": e_dav, "precision": "fp64",
-                     "t_hpsi_s": dst["t_hpsi_s"]},
+        "davidson": davidson,
+        "davidson_learned": learned,
         "roofline": {"bound": "mfma", "kernel": "stage%d_split5_kernel" % dom,
                      "achieved": achieved, "peak": split_peak, "unit": "TFLOP/s",
                      "frac": achieved / split_peak, "traffic": None,

@@ -165,6 +165,7 @@ int autotune(dmrg_plan *P, void *stream);
 int replan(dmrg_plan *P);
 
 int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
+  const bool trow = P->precision != DMRG_SPLIT_BF16;   // stripe layout, see the first stage
   // ---- split tasks into chunks whose stripes fit the workspace budget
   std::vector<std::vector<TaskRef>> chunk_tasks(1);
   std::map<StripeKey, std::set<int>> cur;
@@ -224,9 +225,11 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
                             s.dRin, s.dRout, (int)s.slots.size(), 0});
       woff += (int64_t)s.dL * s.dRout * s.slots.size();
       woff = (woff + 31) / 32 * 32;
-      // first stage: T_h = X [op(D_s0) ... op(D_s1-1)] for each run of consecutive positions;
-      // the stripe is a row-major d_L x (nslots d_R') matrix at off, slot s in
-      // columns [s d_R', (s+1) d_R')
+      // first stage: T_h = X [op(D_s0) ... op(D_s1-1)] for each run of consecutive positions.
+      // FP64 plans store the stripe as a row-major d_L x (nslots d_R') matrix
+      // (slot s in columns [s d_R', (s+1) d_R')), so that both stages access
+      // it along rows; split plans slice it per column and store it
+      // column-major (slot s is the d_L x d_R' block at off + s d_L d_R').
       const ProbPlan &pp = *P->probs[kv.first.prob];
       const PsiBlock &E = pp.T.blocks[kv.first.E];
       const dmrg_oprec_t &rec = pp.R.rec[kv.first.rec];
@@ -265,9 +268,14 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
           for (int j0 = 0; j0 < N; j0 += 64 / mb) {
             Tile t{};
             t.c_base = BASE_WORK;
-            t.c_off = s.off + (int64_t)s0 * s.dRout;
-            t.ldc = (int64_t)s.slots.size() * s.dRout;
-            t.rowmajor = 1;
+            if (trow) {
+              t.c_off = s.off + (int64_t)s0 * s.dRout;
+              t.ldc = (int64_t)s.slots.size() * s.dRout;
+              t.rowmajor = 1;
+            } else {
+              t.c_off = s.off + (int64_t)s0 * s.dL * s.dRout;
+              t.ldc = s.dL;
+            }
             t.m = s.dL; t.n = N; t.i0 = i0; t.j0 = j0; t.ci0 = i0; t.cj0 = j0;
             t.mb = mb;
             t.seg0 = sidx; t.nseg = 1; t.accumulate = 0;
@@ -309,7 +317,7 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
         int run = (int)(q1 - q);
         Seg g{};
         g.s = tk.v * row.pos[q].alpha;
-        if (st) {
+        if (st && trow) {
           // B = [T_s; T_s+1; ...]: slot s of the row-major stripe in columns s d_R'..
           g.b_base = BASE_WORK;
           g.b_off = st->off + (int64_t)slot_of(row.pos[q].pD) * F.dR;
@@ -317,6 +325,14 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
           g.b_pk = F.dR;
           g.b_k = (int64_t)st->slots.size() * F.dR;
           g.b_n = 1;
+        } else if (st) {
+          // column-major stripe: slot s is the d_L x d_R' block at s d_L d_R'
+          g.b_base = BASE_WORK;
+          g.b_off = st->off + (int64_t)slot_of(row.pos[q].pD) * E.dL * F.dR;
+          g.b_kb = E.dL;
+          g.b_pk = (int64_t)E.dL * F.dR;
+          g.b_k = 1;
+          g.b_n = E.dL;
         } else {
           g.b_base = BASE_PSI;
           g.b_off = pp.psi_off + E.off;
@@ -688,7 +704,7 @@ void build_split(dmrg_plan *P) {
     for (const StripeInfo &si : ch.stripes) {
       SliceJob j{};
       j.src_base = BASE_WORK; j.src_off = si.off;
-      j.s_rho = 1; j.s_pos = si.dRout; j.s_k = (int64_t)si.nslots * si.dRout;
+      j.s_rho = si.dL; j.s_pos = (int64_t)si.dL * si.dRout; j.s_k = 1;   // column-major stripes
       j.nrho = si.dRout; j.npos = si.nslots; j.kb = si.dL; j.kbp = rup8(si.dL);
       j.dst_buf = SBUF_T; j.dst_off = te; j.exp_off = tx;
       toff.push_back({te, tx, j.kbp});

@@ -538,21 +538,23 @@ def random_vector(size, seed):
     return v / np.linalg.norm(v)
 
 
-def batch_specs(n, seed, L_range=(16, 32), D_range=(128, 768), spins=(0, 1)):
-    """(L, N, 2S, seed, D) of n independent solves: L and D uniform over the
-    inclusive ranges, N = L electrons, S drawn from `spins` for even N and
-    shifted by 1/2 for odd N (no state of odd N has integer spin)."""
+def batch_specs(n, seed, L_range=(16, 32), D_range=(128, 768), spins=(0, 1), seed0=None):
+    """(L, N, 2S, integral seed, D) of n independent solves: L and D uniform
+    over the inclusive ranges, N = L electrons, S drawn from `spins` for even
+    N and shifted by 1/2 for odd N (no state of odd N has integer spin);
+    integral seeds seed0 + k (default seed * 1000 + k)."""
     rng = np.random.default_rng(seed)
+    base = seed * 1000 if seed0 is None else seed0
     out = []
     for k in range(n):
         L = int(rng.integers(L_range[0], L_range[1] + 1))
         D = int(rng.integers(D_range[0], D_range[1] + 1))
         two_s = 2 * int(rng.choice(spins)) + (L % 2)
-        out.append((L, L, two_s, seed * 1000 + k, D))
+        out.append((L, L, two_s, base + k, D))
     return out
 
 
-def batch_problems(n, seed, L_range=(16, 32), D_range=(128, 768), spins=(0, 1)):
+def batch_problems(n, seed, L_range=(16, 32), D_range=(128, 768), spins=(0, 1), seed0=None):
     """Seeded batch of random middle-bond problems from batch_specs."""
     return [random_problem(L, N, s2, sd, D=D)
-            for L, N, s2, sd, D in batch_specs(n, seed, L_range, D_range, spins)]
+            for L, N, s2, sd, D in batch_specs(n, seed, L_range, D_range, spins, seed0)]
