@@ -156,6 +156,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default tile settings instead of autotuning each plan")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-preconditioner Davidson")
+    ap.add_argument("--no-davidson", action="store_true", help="time H.psi only (large workloads)")
     ap.add_argument("--hpsi-only", choices=("fp64", "split"),
                     help="time only H.psi of one precision (for profiler runs); also copies "
                          "256 MiB once with a plain device copy as a counter reference")
@@ -226,30 +227,39 @@ def main():
     st64, ms64, prof64, y64 = run(0, 0)
     st5, ms5, prof5, y5 = run(1, 5)
     rel = float(np.abs(y5 - y64).max() / np.abs(y64).max())
-    # Davidson s/step (FP64 path, diagonal preconditioner) on the same workload
-    plan = Plan(prob, flags=plan_flags)
-    x0 = torch.from_numpy(x_np).cuda()
-    torch.cuda.synchronize()
-    td = time.time()
-    e_dav, _, dst = plan.davidson(x0, tol=1e-8)
-    t_dav = time.time() - td
-    davidson = {"s_per_step": t_dav, "iterations": dst["iters"], "n_hpsi": dst["n_hpsi"],
-                "residual": dst["residual"], "energy": e_dav, "precision": "fp64",
-                "preconditioner": "diagonal", "t_hpsi_s": dst["t_hpsi_s"]}
-    learned = None
-    if not args.no_mlp:
-        net, info = train_preconditioner(torch, [(24, 24, 0, 10000 + k, 512) for k in range(4)])
-        print("# learned preconditioner: %s" % json.dumps(info), file=sys.stderr, flush=True)
+    davidson, learned, split_dav = None, None, None
+    if not args.no_davidson:
+        # Davidson s/step (FP64 path, diagonal preconditioner) on the same workload
+        plan = Plan(prob, flags=plan_flags)
+        x0 = torch.from_numpy(x_np).cuda()
         torch.cuda.synchronize()
-        tm = time.time()
-        e_mlp, _, mst = plan.davidson(x0, tol=1e-8, mlp=net, check=False)
-        t_mlp = time.time() - tm
-        net.free()
-        learned = {"s_per_step": t_mlp, "iterations": mst["iters"], "n_hpsi": mst["n_hpsi"],
-                   "converged": mst["converged"], "fallbacks": mst["fallbacks"],
-                   "energy_minus_diagonal": e_mlp - e_dav, "t_hpsi_s": mst["t_hpsi_s"],
-                   "speedup_vs_diagonal": t_dav / t_mlp, "training": info}
-    plan.free()
+        td = time.time()
+        e_dav, _, dst = plan.davidson(x0, tol=1e-8)
+        t_dav = time.time() - td
+        davidson = {"s_per_step": t_dav, "iterations": dst["iters"], "n_hpsi": dst["n_hpsi"],
+                    "residual": dst["residual"], "energy": e_dav, "precision": "fp64",
+                    "preconditioner": "diagonal", "t_hpsi_s": dst["t_hpsi_s"]}
+        if not args.no_mlp:
+            net, info = train_preconditioner(torch, [(24, 24, 0, 10000 + k, 512) for k in range(4)])
+            print("# learned preconditioner: %s" % json.dumps(info), file=sys.stderr, flush=True)
+            torch.cuda.synchronize()
+            tm = time.time()
+            e_mlp, _, mst = plan.davidson(x0, tol=1e-8, mlp=net, check=False)
+            t_mlp = time.time() - tm
+            net.free()
+            learned = {"s_per_step": t_mlp, "iterations": mst["iters"], "n_hpsi": mst["n_hpsi"],
+                       "converged": mst["converged"], "fallbacks": mst["fallbacks"],
+                       "energy_minus_diagonal": e_mlp - e_dav, "t_hpsi_s": mst["t_hpsi_s"],
+                       "speedup_vs_diagonal": t_dav / t_mlp, "training": info}
+        plan.free()
+        # the same solve with every H.psi in split precision
+        splan = Plan(prob, precision=1, n_slices=5, flags=plan_flags)
+        torch.cuda.synchronize()
+        tsd = time.time()
+        e_sp, _, sst = splan.davidson(x0, tol=1e-8, check=False)
+        split_dav = {"s_per_step": time.time() - tsd, "iterations": sst["iters"], "converged": sst["converged"],
+                     "residual": sst["residual"], "energy_minus_fp64": e_sp - e_dav}
+        splan.free()
     dom = max((1, 2), key=lambda s_: prof5[s_][1])
     n_l, ms_l, fl_l = prof5[dom]
     achieved = (fl_l / n_l) / (ms_l / n_l * 1e-3) / 1e12
@@ -284,6 +294,7 @@ def main():
         "speedup_split_vs_fp64": ms64 / ms5,
         "davidson": davidson,
         "davidson_learned": learned,
+        "davidson_split": split_dav,
         "roofline": {"bound": "mfma", "kernel": "stage%d_split5_kernel" % dom,
                      "achieved": achieved, "peak": split_peak, "unit": "TFLOP/s",
                      "frac": achieved / split_peak, "traffic": None,

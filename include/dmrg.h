@@ -96,14 +96,16 @@ enum { DMRG_FP64 = 0, DMRG_SPLIT_BF16 = 1 };
  *    (psi, hpsi) pair into a HIP graph (on a plan-owned capture stream) and
  *    replays it on the caller's stream; at most 64 graphs are kept (least
  *    recently created evicted).  Profiling events are not recorded in graphs.
- *  DMRG_PLAN_NO_XCD: work groups take tiles in launch order instead of giving
- *    each XCD a contiguous range of tiles.
- *  DMRG_PLAN_AUTOTUNE: dmrg_build_tasks times dmrg_apply_H under every
- *    candidate (kpart in {1024, 2048, 4096} x tile_policy in {0, 1} x
- *    workspace cap in {requested or 16 GiB, 512 MiB, 192 MiB}) and keeps the
- *    fastest; choices are cached for the process by a hash of the plan's
- *    block shapes and options.  The chosen values are in dmrg_plan_stats. */
-enum { DMRG_PLAN_GRAPH = 1, DMRG_PLAN_NO_XCD = 2, DMRG_PLAN_AUTOTUNE = 4 };
+ *  DMRG_PLAN_XCD: work groups resident on one XCD take a contiguous range of
+ *    tiles (shared L2) instead of taking tiles in launch order (round robin
+ *    over the XCDs, which spreads the cost-sorted tile list evenly).
+ *  DMRG_PLAN_AUTOTUNE: dmrg_build_tasks times dmrg_apply_H under candidate
+ *    settings -- kpart in {1024, 2048, 4096} x tile_policy in {0, 1}, then the
+ *    best of those with the XCD mapping toggled, then with workspace caps of
+ *    512 MiB and 192 MiB -- and keeps the fastest; choices are cached for the
+ *    process by a hash of the plan's block shapes and options.  The chosen
+ *    values are in dmrg_plan_stats. */
+enum { DMRG_PLAN_GRAPH = 1, DMRG_PLAN_XCD = 2, DMRG_PLAN_AUTOTUNE = 4 };
 
 typedef struct {
   int32_t precision;        /* DMRG_FP64 or DMRG_SPLIT_BF16                   */

@@ -17,7 +17,7 @@ c_i32, c_i64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, cty
 DMRG_FP64 = 0
 DMRG_SPLIT_BF16 = 1
 DMRG_PLAN_GRAPH = 1
-DMRG_PLAN_NO_XCD = 2
+DMRG_PLAN_XCD = 2
 DMRG_PLAN_AUTOTUNE = 4
 
 

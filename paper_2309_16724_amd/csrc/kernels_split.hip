@@ -35,13 +35,16 @@ __global__ void __launch_bounds__(256) slice_kernel(const SliceJob *__restrict__
     uint16_t *dst = bufs.data[J.dst_buf] + J.dst_off;
     const int64_t plane = bufs.plane[J.dst_buf];
     int32_t *exps = bufs.exps[J.dst_buf] + J.exp_off;
-    const int64_t len = (int64_t)J.npos * J.kbp;
-    const int64_t nval = (int64_t)J.npos * J.kb;
+    // line lengths fit in 32 bits (checked when the plan is built): the
+    // (position, offset) split of an index is a 32-bit division
+    const int len = J.npos * J.kbp;
+    const int nval = J.npos * J.kb;
+    const unsigned kb = (unsigned)J.kb, kbp = (unsigned)J.kbp;
     for (int rho = wave; rho < J.nrho; rho += 4) {
       const double *line = src + (int64_t)rho * J.s_rho;
       double m = 0.0;
-      for (int64_t idx = lane; idx < nval; idx += 64) {
-        int p = (int)(idx / J.kb), kk = (int)(idx - (int64_t)p * J.kb);
+      for (int idx = lane; idx < nval; idx += 64) {
+        const unsigned p = (unsigned)idx / kb, kk = (unsigned)idx - p * kb;
         m = fmax(m, fabs(line[(int64_t)p * J.s_pos + (int64_t)kk * J.s_k]));
       }
       for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
@@ -53,9 +56,9 @@ __global__ void __launch_bounds__(256) slice_kernel(const SliceJob *__restrict__
       }
       if (lane == 0) exps[rho] = e;
       uint16_t *out = dst + (int64_t)rho * len;
-      for (int64_t idx = lane; idx < len; idx += 64) {
-        int p = (int)(idx / J.kbp), kk = (int)(idx - (int64_t)p * J.kbp);
-        double x = kk < J.kb ? line[(int64_t)p * J.s_pos + (int64_t)kk * J.s_k] : 0.0;
+      for (int idx = lane; idx < len; idx += 64) {
+        const unsigned p = (unsigned)idx / kbp, kk = (unsigned)idx - p * kbp;
+        double x = kk < kb ? line[(int64_t)p * J.s_pos + (int64_t)kk * J.s_k] : 0.0;
         double yv = ldexp(x, -e);
         for (int t = 0; t < ns; t++) {
           double a = rint(yv * 256.0);

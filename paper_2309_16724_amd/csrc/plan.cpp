@@ -9,6 +9,7 @@
 #include <memory>
 #include <mutex>
 #include <set>
+#include <stdexcept>
 
 using namespace dmrg;
 
@@ -80,7 +81,7 @@ struct dmrg_plan {
   std::vector<void *> allocs;          // problem-level device memory (kept across re-planning)
   std::vector<void *> plan_allocs;     // tile lists, workspace, slices (freed by re-planning)
   // settings of the tile lists
-  int kpart = KPART, tile_policy = 0, xcd = 1, flags = 0;
+  int kpart = KPART, tile_policy = 0, xcd = 0, flags = 0;
   int64_t budget = (int64_t)16 << 30;
   int tuned = 0;
   double tune_ms = 0.0;
@@ -605,6 +606,12 @@ struct VarInfo { int64_t off, exp; int kbp; int64_t line_len; int lines_per_pos;
 
 static int rup8(int x) { return (x + 7) / 8 * 8; }
 
+// every slicing job's line must have fewer than 2^31 values (32-bit indexing)
+static void check_jobs(const std::vector<SliceJob> &jobs) {
+  for (const SliceJob &j : jobs)
+    if ((int64_t)j.npos * j.kbp >= ((int64_t)1 << 31)) throw std::length_error("slice line longer than 2^31");
+}
+
 void build_split(dmrg_plan *P) {
   for (int b = 0; b < N_SBUF; b++) P->sb_elems[b] = P->sb_exps[b] = 0;
   P->jobs_ops.clear();
@@ -767,6 +774,9 @@ void build_split(dmrg_plan *P) {
   }
   P->sb_elems[SBUF_T] = t_elems_max;
   P->sb_exps[SBUF_T] = t_exps_max;
+  check_jobs(P->jobs_ops);
+  check_jobs(P->jobs_psi);
+  for (auto &ch : P->chunks) check_jobs(ch.tjobs);
 }
 
 }  // namespace
@@ -878,12 +888,13 @@ uint64_t plan_hash(const dmrg_plan *P) {
 }
 
 std::mutex g_tune_mu;
-std::map<uint64_t, std::array<int64_t, 3>> g_tune_cache;   // kpart, tile policy, workspace cap
+std::map<uint64_t, std::array<int64_t, 4>> g_tune_cache;   // kpart, tile policy, workspace cap, xcd
 
 // Times candidate settings on the live plan and keeps the fastest (see
 // DMRG_PLAN_AUTOTUNE): first kpart x tile policy at the requested workspace
-// cap, then smaller caps (more, smaller launches whose stripes stay in the
-// last-level cache) with the best of the first round.
+// cap and XCD mapping, then the best of those with the mapping toggled, then
+// smaller caps (more, smaller launches whose stripes stay in the last-level
+// cache).
 int autotune(dmrg_plan *P, void *stream) {
   auto t0 = std::chrono::steady_clock::now();
   const uint64_t key = plan_hash(P);
@@ -894,6 +905,7 @@ int autotune(dmrg_plan *P, void *stream) {
       P->kpart = (int)it->second[0];
       P->tile_policy = (int)it->second[1];
       P->budget = it->second[2];
+      P->xcd = (int)it->second[3];
       P->tuned = 0;
       int rc = replan(P);
       P->tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -910,31 +922,35 @@ int autotune(dmrg_plan *P, void *stream) {
   int rc = hipMemset(x, 0, sizeof(double) * std::max<int64_t>(P->psi_len, 1)) == hipSuccess ? DMRG_OK : DMRG_EHIP;
   const int64_t base = P->budget;
   double best = 1e300;
-  std::array<int64_t, 3> bc{P->kpart, P->tile_policy, base};
-  auto trial = [&](int kp, int pol, int64_t budget) {
+  const int xcd0 = P->xcd;
+  std::array<int64_t, 4> bc{P->kpart, P->tile_policy, base, xcd0};
+  auto trial = [&](int kp, int pol, int64_t budget, int xcd) {
     if (rc) return;
     P->kpart = kp;
     P->tile_policy = pol;
     P->budget = budget;
+    P->xcd = xcd;
     double ms = 0.0;
     rc = replan(P);
     if (!rc) rc = time_apply(P, x, y, stream, &ms);
     P->tuned++;
     if (!rc && ms < best) {
       best = ms;
-      bc = {kp, pol, budget};
+      bc = {kp, pol, budget, xcd};
     }
   };
   for (int kp : {1024, 2048, 4096})
-    for (int pol : {0, 1}) trial(kp, pol, base);
+    for (int pol : {0, 1}) trial(kp, pol, base, xcd0);
+  trial((int)bc[0], (int)bc[1], base, 1 - xcd0);
   for (int64_t b : {(int64_t)512 << 20, (int64_t)192 << 20})
-    if (b < base) trial((int)bc[0], (int)bc[1], b);
+    if (b < base) trial((int)bc[0], (int)bc[1], b, (int)bc[3]);
   (void)hipFree(x);
   (void)hipFree(y);
   if (rc) return rc;
   P->kpart = (int)bc[0];
   P->tile_policy = (int)bc[1];
   P->budget = bc[2];
+  P->xcd = (int)bc[3];
   rc = replan(P);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1032,7 +1048,7 @@ extern "C" int dmrg_build_tasks(const dmrg_problem_t *probs, int32_t n_probs, co
     P->psi_len = off;
     P->stats.psi_len = off;
     P->flags = opts ? opts->flags : 0;
-    P->xcd = (P->flags & DMRG_PLAN_NO_XCD) ? 0 : 1;
+    P->xcd = (P->flags & DMRG_PLAN_XCD) ? 1 : 0;
     P->kpart = (opts && opts->kpart > 0) ? opts->kpart : KPART;
     P->tile_policy = opts ? opts->tile_policy : 0;
     P->budget = budget;
@@ -1419,7 +1435,13 @@ extern "C" int dmrg_debug_plan_host_apply(const dmrg_problem_t *prob, const doub
   std::vector<double> part((size_t)std::max<int64_t>(P->part_elems, 1), 0.0);
   std::memset(y, 0, sizeof(double) * n);
   if (P->precision == DMRG_SPLIT_BF16) {
-    build_split(P);
+    try {
+      build_split(P);
+    } catch (const std::exception &e) {
+      set_error(std::string("exception: ") + e.what());
+      delete P;
+      return DMRG_EINVAL;
+    }
     int ns = P->n_slices;
     int64_t plane[N_SBUF];
     for (int b = 0; b < N_SBUF; b++) {

@@ -59,8 +59,8 @@ def test_graph_replays_match_eager(torch, precision, ns):
 def test_xcd_mapping_does_not_change_results(torch):
     from paper_2309_16724_amd.hpsi import Plan
     prob = random_problem(8, 8, 0, 4, D=120, cap=False)
-    a = Plan(prob)
-    b = Plan(prob, flags=B.DMRG_PLAN_NO_XCD)
+    a = Plan(prob, flags=B.DMRG_PLAN_XCD)
+    b = Plan(prob)
     x = torch.from_numpy(random_vector(a.size, 3)).cuda()
     assert a.stats()["xcd"] == 1 and b.stats()["xcd"] == 0
     assert np.array_equal(_apply(torch, a, x), _apply(torch, b, x))
@@ -80,7 +80,7 @@ def test_autotuned_plan_matches_oracle_and_is_cached(torch):
         s1 = p1.stats()
         _say("autotune prec %d: tuned %d kpart %d policy %d cap %d (%.0f ms)"
              % (precision, s1["tuned"], s1["kpart"], s1["tile_policy"], s1["workspace_cap"], s1["tune_ms"]))
-        assert s1["tuned"] >= 6
+        assert s1["tuned"] >= 7
         y = _apply(torch, p1, torch.from_numpy(x).cuda())
         assert np.abs(y - ref).max() <= tol * np.abs(ref).max()
         p2 = Plan(prob, precision=precision, n_slices=ns, flags=B.DMRG_PLAN_AUTOTUNE)
