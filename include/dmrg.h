@@ -250,7 +250,8 @@ int dmrg_mlp_collect(dmrg_plan_t *p, const double *psi0, const dmrg_dav_opts_t *
 void dmrg_mlp_free(dmrg_mlp_t *m);
 
 /* Profiling: when on, dmrg_apply_H records a hipEvent pair on its stream
- * around each first-stage (stage 1) and second-stage (stage 2) kernel launch.
+ * around each first-stage (stage 1) and second-stage (stage 2) kernel launch
+ * (slicing launches of split plans fall outside the pairs).
  * dmrg_get_profile waits for the recorded events and returns the number of
  * launches, their summed duration and summed algorithmic flops since the
  * last dmrg_set_profiling call. */

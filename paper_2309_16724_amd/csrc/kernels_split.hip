@@ -42,11 +42,22 @@ __global__ void __launch_bounds__(256) slice_kernel(const SliceJob *__restrict__
     const unsigned kb = (unsigned)J.kb, kbp = (unsigned)J.kbp;
     for (int rho = wave; rho < J.nrho; rho += 4) {
       const double *line = src + (int64_t)rho * J.s_rho;
-      double m = 0.0;
-      for (int idx = lane; idx < nval; idx += 64) {
+      // four independent loads in flight per lane
+      double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+      auto val = [&](int idx) {
         const unsigned p = (unsigned)idx / kb, kk = (unsigned)idx - p * kb;
-        m = fmax(m, fabs(line[(int64_t)p * J.s_pos + (int64_t)kk * J.s_k]));
+        return fabs(line[(int64_t)p * J.s_pos + (int64_t)kk * J.s_k]);
+      };
+      int idx = lane;
+      for (; idx + 192 < nval; idx += 256) {
+        const double v0 = val(idx), v1 = val(idx + 64), v2 = val(idx + 128), v3 = val(idx + 192);
+        m0 = fmax(m0, v0);
+        m1 = fmax(m1, v1);
+        m2 = fmax(m2, v2);
+        m3 = fmax(m3, v3);
       }
+      for (; idx < nval; idx += 64) m0 = fmax(m0, val(idx));
+      double m = fmax(fmax(m0, m1), fmax(m2, m3));
       for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
       int e = 0;
       if (m > 0.0) {
@@ -56,9 +67,7 @@ __global__ void __launch_bounds__(256) slice_kernel(const SliceJob *__restrict__
       }
       if (lane == 0) exps[rho] = e;
       uint16_t *out = dst + (int64_t)rho * len;
-      for (int idx = lane; idx < len; idx += 64) {
-        const unsigned p = (unsigned)idx / kbp, kk = (unsigned)idx - p * kbp;
-        double x = kk < kb ? line[(int64_t)p * J.s_pos + (int64_t)kk * J.s_k] : 0.0;
+      auto slice_out = [&](int idx, double x) {
         double yv = ldexp(x, -e);
         for (int t = 0; t < ns; t++) {
           double a = rint(yv * 256.0);
@@ -66,7 +75,20 @@ __global__ void __launch_bounds__(256) slice_kernel(const SliceJob *__restrict__
           float af = (float)a;                       // integer, |a| <= 256: exact in BF16
           out[(int64_t)t * plane + idx] = (uint16_t)(__float_as_uint(af) >> 16);
         }
+      };
+      auto raw = [&](int idx) {
+        const unsigned p = (unsigned)idx / kbp, kk = (unsigned)idx - p * kbp;
+        return kk < kb ? line[(int64_t)p * J.s_pos + (int64_t)kk * J.s_k] : 0.0;
+      };
+      int i2 = lane;
+      for (; i2 + 192 < len; i2 += 256) {
+        const double x0 = raw(i2), x1 = raw(i2 + 64), x2 = raw(i2 + 128), x3 = raw(i2 + 192);
+        slice_out(i2, x0);
+        slice_out(i2 + 64, x1);
+        slice_out(i2 + 128, x2);
+        slice_out(i2 + 192, x3);
       }
+      for (; i2 < len; i2 += 64) slice_out(i2, raw(i2));
     }
   }
 }

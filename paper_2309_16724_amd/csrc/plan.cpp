@@ -1094,6 +1094,9 @@ int enqueue(dmrg_plan *p, const double *psi, double *hpsi, void *stream, bool pr
   size_t ev = p->ev_marks.empty() ? 0 : (size_t)p->ev_marks.back().second.second + 1;
   for (auto &ch : p->chunks) {
     for (int stage = 1; stage <= 2; stage++) {
+      // stripe slices of a split plan, outside the stage's event window
+      if (split && stage == 2)
+        launch_slices(ch.d_tjobs, (int)ch.tjobs.size(), p->n_slices, p->d_bases, psi, p->d_work, p->sb, stream);
       int e0 = -1;
       if (prof) {
         int rc = next_event(p, ev);
@@ -1101,8 +1104,6 @@ int enqueue(dmrg_plan *p, const double *psi, double *hpsi, void *stream, bool pr
         e0 = (int)ev;
         HIPCHK(hipEventRecord(p->ev_pool[ev++], (hipStream_t)stream));
       }
-      if (split && stage == 2)
-        launch_slices(ch.d_tjobs, (int)ch.tjobs.size(), p->n_slices, p->d_bases, psi, p->d_work, p->sb, stream);
       if (split) {
         if (stage == 1)
           launch_tiles_split(1, ch.d_tile1, ch.d_seg1, ch.d_sseg1, (int)ch.tile1.size(), p->n_slices, p->d_bases,
