@@ -9,6 +9,7 @@
 // segments.  Lane layout of v_mfma_f32_16x16x32_bf16 (lane l, element e/r):
 // A[l%16][8(l/16)+e], B[8(l/16)+e][l%16], D[4(l/16)+r][l%16].
 #include <hip/hip_runtime.h>
+#include <climits>
 #include "plan.hpp"
 
 namespace dmrg {
@@ -91,6 +92,55 @@ __global__ void __launch_bounds__(256) slice_kernel(const SliceJob *__restrict__
       for (; i2 < len; i2 += 64) slice_out(i2, raw(i2));
     }
   }
+}
+
+// stripe slices, one work group per chunk of TSLICE_CHUNK elements
+__global__ void __launch_bounds__(256) tslice_kernel(const SliceJob *__restrict__ jobs,
+                                                      const TSliceItem *__restrict__ items, int nitems, int ns,
+                                                      const double *__restrict__ work, SliceBufs bufs) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const TSliceItem I = items[it];
+    const SliceJob J = jobs[I.job];
+    const double *src = work + J.src_off;
+    uint16_t *dst = bufs.data[SBUF_T] + J.dst_off;
+    const int64_t plane = bufs.plane[SBUF_T];
+    const int32_t *exps = bufs.exps[SBUF_T] + J.exp_off;
+    const unsigned kb = (unsigned)J.kb, kbp = (unsigned)J.kbp, len = (unsigned)(J.npos * J.kbp);
+    const unsigned tot = len * (unsigned)J.nrho;
+    for (int q = 0; q < TSLICE_CHUNK / 256; q++) {
+      const unsigned e = (unsigned)I.e0 + (unsigned)(q * 256) + threadIdx.x;
+      if (e >= tot) break;
+      const unsigned rho = e / len, idx = e - rho * len;
+      const unsigned p = idx / kbp, kk = idx - p * kbp;
+      const double x = kk < kb ? src[(int64_t)rho * J.s_rho + (int64_t)p * J.s_pos + (int64_t)kk * J.s_k] : 0.0;
+      const int ex = exps[rho];
+      double yv = ldexp(x, ex == INT_MIN ? 0 : -ex);
+      for (int t = 0; t < ns; t++) {
+        const double a = rint(yv * 256.0);
+        yv = yv * 256.0 - a;
+        const float af = (float)a;                 // integer, |a| <= 256: exact in BF16
+        dst[(int64_t)t * plane + e] = (uint16_t)(__float_as_uint(af) >> 16);
+      }
+    }
+  }
+}
+
+__global__ void fill_int_kernel(int32_t *__restrict__ p, int64_t n, int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+void launch_tslices(const SliceJob *jobs, const TSliceItem *items, int nitems, int nslices, const double *work,
+                    SliceBufs bufs, void *stream) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL(tslice_kernel, dim3(std::min(nitems, 65535)), dim3(256), 0, (hipStream_t)stream, jobs, items,
+                     nitems, nslices, work, bufs);
+}
+
+void launch_fill_int(int32_t *p, int64_t n, int32_t v, void *stream) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 65535)), dim3(256), 0,
+                     (hipStream_t)stream, p, n, v);
 }
 
 void launch_slices(const SliceJob *jobs, int njobs, int nslices, const double *const *bases, const double *psi,
@@ -210,6 +260,28 @@ __device__ __forceinline__ void item_split(const Tile &T, const Seg *__restrict_
           *c = T.accumulate ? *c + acc[bi][bj][r] : acc[bi][bj][r];
         }
       }
+  // first-stage tiles: exponent of every stripe column they wrote (smallest e
+  // with max |value| <= 2^e), combined over tiles with atomicMax
+  const SegS Q0 = ssegs[T.seg0];
+  if (Q0.t_exp >= 0) {
+    int32_t *ex = bufs.exps[SBUF_T] + Q0.t_exp;
+    for (int bj = 0; bj < NB; bj++) {
+      const int j = 16 * bj + r16;
+      double m = 0.0;
+      for (int bi = 0; bi < MB; bi++)
+        for (int r = 0; r < 4; r++) {
+          const int i = 16 * bi + 4 * q4 + r;
+          if (i < mrem && j < nrem) m = fmax(m, fabs(acc[bi][bj][r]));
+        }
+      m = fmax(m, __shfl_xor(m, 16));
+      m = fmax(m, __shfl_xor(m, 32));
+      if (q4 == 0 && j < nrem && m > 0.0) {
+        int e2;
+        const double mant = frexp(m, &e2);
+        atomicMax(ex + (T.cj0 + j) % Q0.t_nb, mant == 0.5 ? e2 - 1 : e2);
+      }
+    }
+  }
 }
 
 // Work-group index used to pick work: consecutive work groups are spread over

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <chrono>
+#include <climits>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -705,6 +706,7 @@ void build_split(dmrg_plan *P) {
     ch.sseg1.clear();
     ch.sseg2.clear();
     ch.tjobs.clear();
+    ch.titems.clear();
     // stripe slices (second-stage B operands), per chunk
     std::vector<std::array<int64_t, 3>> toff;   // off, exp, kbp
     int64_t te = 0, tx = 0;
@@ -715,7 +717,10 @@ void build_split(dmrg_plan *P) {
       j.nrho = si.dRout; j.npos = si.nslots; j.kb = si.dL; j.kbp = rup8(si.dL);
       j.dst_buf = SBUF_T; j.dst_off = te; j.exp_off = tx;
       toff.push_back({te, tx, j.kbp});
-      te += (int64_t)si.dRout * si.nslots * j.kbp;
+      const int64_t tot = (int64_t)si.dRout * si.nslots * j.kbp;
+      if (tot >= ((int64_t)1 << 31)) throw std::length_error("stripe slice job longer than 2^31");
+      for (int64_t e0 = 0; e0 < tot; e0 += TSLICE_CHUNK) ch.titems.push_back({(int32_t)ch.tjobs.size(), (int32_t)e0});
+      te += tot;
       tx += si.dRout;
       ch.tjobs.push_back(j);
     }
@@ -739,6 +744,8 @@ void build_split(dmrg_plan *P) {
       q.b_ld = v.kbp;
       q.b_exp = v.exp + (int64_t)inf.pD0 * v.lines_per_pos;
       q.K = rup8(si.dRin);
+      q.t_nb = si.dRout;
+      q.t_exp = toff[inf.stripe][1];
       ch.sseg1.push_back(q);
     }
     // second stage
@@ -746,6 +753,7 @@ void build_split(dmrg_plan *P) {
       const Seg2Info &inf = ch.s2info[i];
       const PsiBlock &E = P->probs[inf.prob]->T.blocks[inf.E];
       SegS q{};
+      q.t_exp = -1;
       if (inf.recA < 0) {
         q.K = 0;
         ch.sseg2.push_back(q);
@@ -788,7 +796,7 @@ int upload_split(dmrg_plan *P) {
   if ((rc = upload(P, P->jobs_ops, &P->d_jobs_ops)) || (rc = upload(P, P->jobs_psi, &P->d_jobs_psi))) return rc;
   for (auto &ch : P->chunks)
     if ((rc = upload(P, ch.sseg1, &ch.d_sseg1)) || (rc = upload(P, ch.sseg2, &ch.d_sseg2)) ||
-        (rc = upload(P, ch.tjobs, &ch.d_tjobs)))
+        (rc = upload(P, ch.tjobs, &ch.d_tjobs)) || (rc = upload(P, ch.titems, &ch.d_titems)))
       return rc;
   for (int b = 0; b < N_SBUF; b++) {
     void *d = nullptr, *e = nullptr;
@@ -1094,9 +1102,11 @@ int enqueue(dmrg_plan *p, const double *psi, double *hpsi, void *stream, bool pr
   size_t ev = p->ev_marks.empty() ? 0 : (size_t)p->ev_marks.back().second.second + 1;
   for (auto &ch : p->chunks) {
     for (int stage = 1; stage <= 2; stage++) {
-      // stripe slices of a split plan, outside the stage's event window
+      // stripe line exponents are maxima taken by the first stage's tiles;
+      // the stripe slices follow it (both outside the stages' event windows)
+      if (split && stage == 1) launch_fill_int(p->sb.exps[SBUF_T], ch.t_exps, INT_MIN, stream);
       if (split && stage == 2)
-        launch_slices(ch.d_tjobs, (int)ch.tjobs.size(), p->n_slices, p->d_bases, psi, p->d_work, p->sb, stream);
+        launch_tslices(ch.d_tjobs, ch.d_titems, (int)ch.titems.size(), p->n_slices, p->d_work, p->sb, stream);
       int e0 = -1;
       if (prof) {
         int rc = next_event(p, ev);

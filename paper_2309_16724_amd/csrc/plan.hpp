@@ -99,7 +99,15 @@ struct SegS {
   int64_t b_off, b_ld, b_exp;
   int32_t a_buf, b_buf;
   int32_t K;          // padded K (multiple of 8); 0 for an identity segment
-  int32_t pad;
+  int32_t t_nb;       // first-stage segments: stripe columns per slot (line = column mod t_nb)
+  int64_t t_exp;      // first-stage segments: exponent offset of the stripe's lines, else -1
+};
+
+// Stripe slicing work item: elements [e0, e0 + TSLICE_CHUNK) of job `job`,
+// flattened line by line (line rho, then padded index along its K range).
+constexpr int TSLICE_CHUNK = 1024;
+struct TSliceItem {
+  int32_t job, e0;
 };
 
 // slice buffers: 0 operator records (plan), 1 psi rows, 2 psi columns, 3 stripes
@@ -137,8 +145,10 @@ struct Chunk {
   // split precision (filled only for split plans)
   std::vector<SegS> sseg1, sseg2;
   std::vector<SliceJob> tjobs;          // stripe slicing after the first stage
+  std::vector<TSliceItem> titems;       // its element chunks
   SegS *d_sseg1 = nullptr, *d_sseg2 = nullptr;
   SliceJob *d_tjobs = nullptr;
+  TSliceItem *d_titems = nullptr;
   int64_t t_elems = 0, t_exps = 0;
 };
 
@@ -161,6 +171,11 @@ void launch_diag(const DiagBlock *blocks, const DiagTerm *terms, int nblocks,
 namespace dmrg {
 void launch_slices(const SliceJob *jobs, int njobs, int nslices, const double *const *bases, const double *psi,
                    const double *work, SliceBufs bufs, void *stream);
+// stripe slicing with line exponents already in place (the first stage's
+// epilogue takes their maxima with atomicMax; sentinel INT_MIN = all zero)
+void launch_tslices(const SliceJob *jobs, const TSliceItem *items, int nitems, int nslices, const double *work,
+                    SliceBufs bufs, void *stream);
+void launch_fill_int(int32_t *p, int64_t n, int32_t v, void *stream);
 void launch_tiles_split(int stage, const Tile *tiles, const Seg *segs, const SegS *ssegs, int ntiles,
                         int nslices, const double *const *bases, const double *psi, double *y, double *work,
                         double *part, SliceBufs bufs, int xcd, void *stream);
