@@ -106,11 +106,25 @@ def run_batch(args):
     t0 = time.time()
     probs = [random_problem(L, N, s2, sd, D=D) for L, N, s2, sd, D in specs]
     print("# generated %d problems in %.1f s" % (len(probs), time.time() - t0), file=sys.stderr, flush=True)
+    from paper_2309_16724_amd.binding import DMRG_PLAN_XCD
     res = {}
     ys = {}
+    # the autotuner times candidates on a sample of four problems spread over
+    # the batch's sizes (re-planning all 64 per candidate would cost minutes);
+    # its choice of kpart, tile policy and XCD mapping is applied to the batch
+    order = sorted(range(len(probs)), key=lambda k: specs[k][0] * specs[k][4] ** 2)
+    sample = [order[int(round(q * (len(order) - 1)))] for q in (0.2, 0.45, 0.7, 0.95)]
     for name, prec, ns in (("fp64", 0, 0), ("split", 1, 5)):
         t1 = time.time()
-        plan = Plan(probs, precision=prec, n_slices=ns, flags=0 if args.no_autotune else DMRG_PLAN_AUTOTUNE)
+        tuned = {"kpart": 0, "tile_policy": 0, "xcd": 0, "sample": None, "tune_ms": 0.0}
+        if not args.no_autotune:
+            tp = Plan([probs[k] for k in sample], precision=prec, n_slices=ns, flags=DMRG_PLAN_AUTOTUNE)
+            ts = tp.stats()
+            tp.free()
+            tuned = {"kpart": ts["kpart"], "tile_policy": ts["tile_policy"], "xcd": ts["xcd"],
+                     "sample": sample, "tune_ms": ts["tune_ms"]}
+        plan = Plan(probs, precision=prec, n_slices=ns, kpart=tuned["kpart"], tile_policy=tuned["tile_policy"],
+                    flags=DMRG_PLAN_XCD if tuned["xcd"] else 0)
         st = plan.stats()
         print("# batch plan %s built in %.1f s: %s" % (name, time.time() - t1, json.dumps(st)), file=sys.stderr,
               flush=True)
@@ -130,7 +144,8 @@ def run_batch(args):
         ys[name] = (y.cpu().numpy(), segs)
         res[name] = {"ms_per_step": ms, "tflops": st["flops"] / (ms * 1e-3) / 1e12, "flops": st["flops"],
                      "psi_len": st["psi_len"], "kpart": st["kpart"], "tile_policy": st["tile_policy"],
-                     "workspace_cap": st["workspace_cap"], "tune_ms": st["tune_ms"]}
+                     "xcd": st["xcd"], "workspace_cap": st["workspace_cap"], "autotune": tuned,
+                     "n_chunks": st["n_chunks"]}
         plan.free()
     yf, segs = ys["fp64"]
     yb, _ = ys["split"]
@@ -157,6 +172,10 @@ def main():
                     help="use the default tile settings instead of autotuning each plan")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-preconditioner Davidson")
     ap.add_argument("--no-davidson", action="store_true", help="time H.psi only (large workloads)")
+    ap.add_argument("--no-split-davidson", action="store_true",
+                    help="skip the Davidson solve with split-precision H.psi")
+    ap.add_argument("--dav-verbose", action="store_true",
+                    help="Davidson progress lines on stderr every 25 iterations (long solves)")
     ap.add_argument("--hpsi-only", choices=("fp64", "split"),
                     help="time only H.psi of one precision (for profiler runs); also copies "
                          "256 MiB once with a plain device copy as a counter reference")
@@ -234,7 +253,7 @@ def main():
         x0 = torch.from_numpy(x_np).cuda()
         torch.cuda.synchronize()
         td = time.time()
-        e_dav, _, dst = plan.davidson(x0, tol=1e-8)
+        e_dav, _, dst = plan.davidson(x0, tol=1e-8, verbose=int(args.dav_verbose))
         t_dav = time.time() - td
         davidson = {"s_per_step": t_dav, "iterations": dst["iters"], "n_hpsi": dst["n_hpsi"],
                     "residual": dst["residual"], "energy": e_dav, "precision": "fp64",
@@ -244,7 +263,7 @@ def main():
             print("# learned preconditioner: %s" % json.dumps(info), file=sys.stderr, flush=True)
             torch.cuda.synchronize()
             tm = time.time()
-            e_mlp, _, mst = plan.davidson(x0, tol=1e-8, mlp=net, check=False)
+            e_mlp, _, mst = plan.davidson(x0, tol=1e-8, mlp=net, check=False, verbose=int(args.dav_verbose))
             t_mlp = time.time() - tm
             net.free()
             learned = {"s_per_step": t_mlp, "iterations": mst["iters"], "n_hpsi": mst["n_hpsi"],
@@ -252,14 +271,16 @@ def main():
                        "energy_minus_diagonal": e_mlp - e_dav, "t_hpsi_s": mst["t_hpsi_s"],
                        "speedup_vs_diagonal": t_dav / t_mlp, "training": info}
         plan.free()
-        # the same solve with every H.psi in split precision
-        splan = Plan(prob, precision=1, n_slices=5, flags=plan_flags)
-        torch.cuda.synchronize()
-        tsd = time.time()
-        e_sp, _, sst = splan.davidson(x0, tol=1e-8, check=False)
-        split_dav = {"s_per_step": time.time() - tsd, "iterations": sst["iters"], "converged": sst["converged"],
-                     "residual": sst["residual"], "energy_minus_fp64": e_sp - e_dav}
-        splan.free()
+        if not args.no_split_davidson:
+            # the same solve with every H.psi in split precision
+            splan = Plan(prob, precision=1, n_slices=5, flags=plan_flags)
+            torch.cuda.synchronize()
+            tsd = time.time()
+            e_sp, _, sst = splan.davidson(x0, tol=1e-8, check=False, verbose=int(args.dav_verbose))
+            split_dav = {"s_per_step": time.time() - tsd, "iterations": sst["iters"],
+                         "converged": sst["converged"], "residual": sst["residual"],
+                         "energy_minus_fp64": e_sp - e_dav}
+            splan.free()
     dom = max((1, 2), key=lambda s_: prof5[s_][1])
     n_l, ms_l, fl_l = prof5[dom]
     achieved = (fl_l / n_l) / (ms_l / n_l * 1e-3) / 1e12
@@ -289,7 +310,7 @@ def main():
                    "fp64_plan": {k: st64[k] for k in ("kpart", "tile_policy", "workspace_cap")}},
         "split_rel_err_vs_fp64": rel,
         "fp64": {"value": tflops64, "ms_per_step": ms64,
-                 "roofline": {"bound": "mfma", "kernel": "stage%d_f64_kernel" % dom64, "achieved": ach64,
+                 "roofline": {"bound": "mfma", "kernel": "stage_f64_kernel<%d>" % dom64, "achieved": ach64,
                               "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach64 / FP64_PEAK_TFLOPS}},
         "speedup_split_vs_fp64": ms64 / ms5,
         "davidson": davidson,

@@ -164,7 +164,8 @@ int dmrg_diag_H(dmrg_plan_t *p, double *diag, void *stream);
  * array of n_probs doubles, out = Ritz values.  Block size 1, thick restart
  * to the current and previous Ritz vectors at m_max (all problems restart
  * together), two-pass Gram-Schmidt, correction -r/(diag - theta) with
- * |diag - theta| >= floor, a problem stops when ||H u - theta u||_2 <= tol
+ * |diag - theta| >= floor (or the learned correction of the network in
+ * o->mlp, see below), a problem stops when ||H u - theta u||_2 <= tol
  * (its segment of later basis vectors is zero).  Returns DMRG_ENOCONV (with
  * the best pairs in psi/evals) when max_iter is reached before every problem
  * converged.  All vector work runs on the GPU in FP64 (segmented, fixed-order
@@ -179,6 +180,7 @@ typedef struct {
   int32_t max_iter;
   int32_t m_max;            /* subspace size, 3..64 (24 by default)         */
   int32_t precond;          /* DMRG_PRECOND_DIAG or DMRG_PRECOND_MLP         */
+  int32_t verbose;          /* > 0: a progress line on stderr every 25 iterations */
   double floor;             /* preconditioner denominator floor, e.g. 1e-8   */
   const dmrg_mlp_t *mlp;    /* network for DMRG_PRECOND_MLP, else NULL       */
 } dmrg_dav_opts_t;

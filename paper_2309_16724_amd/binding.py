@@ -45,7 +45,7 @@ class PlanOpts(ctypes.Structure):
 
 class DavOpts(ctypes.Structure):
     _fields_ = [("tol", c_dbl), ("max_iter", c_i32), ("m_max", c_i32), ("precond", c_i32),
-                ("floor", c_dbl), ("mlp", c_vp)]
+                ("verbose", c_i32), ("floor", c_dbl), ("mlp", c_vp)]
 
 
 DMRG_PRECOND_DIAG = 0

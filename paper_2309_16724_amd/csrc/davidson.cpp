@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 #include "common.hpp"
@@ -125,7 +126,7 @@ struct Collect {
 }  // namespace
 
 static int check_opts(const dmrg_dav_opts_t *o, dmrg_dav_opts_t *opt) {
-  *opt = {1e-8, 1000, 24, DMRG_PRECOND_DIAG, 1e-8, nullptr};
+  *opt = {1e-8, 1000, 24, DMRG_PRECOND_DIAG, 0, 1e-8, nullptr};
   if (o) *opt = *o;
   if (opt->m_max < 3 || opt->m_max > 64 || opt->max_iter < 1 || !(opt->tol > 0.0) || !(opt->floor > 0.0)) {
     set_error("bad Davidson options (m_max in [3,64], max_iter >= 1, tol > 0, floor > 0)");
@@ -303,6 +304,14 @@ static int solve(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts
       }
     }
     if (n_active == 0) break;
+    if (opt.verbose > 0 && it % 25 == 0) {
+      double rmax = 0.0;
+      for (const ProbState &S : P)
+        if (S.active) rmax = std::max(rmax, S.rnorm);
+      std::fprintf(stderr, "# davidson iteration %d: %d of %d problems active, largest residual %.3e\n", it,
+                   n_active, np, rmax);
+      std::fflush(stderr);
+    }
     if (col && P[0].active) {
       // exact correction of this iteration from the converged vector
       if ((rc = dots_host(u, 1, col->psi_star))) return rc;

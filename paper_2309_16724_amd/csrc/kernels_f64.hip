@@ -132,10 +132,15 @@ __device__ __forceinline__ void item_f64(const Tile &T, const Seg *__restrict__ 
       }
 }
 
-__device__ __forceinline__ void items_f64(const Tile *__restrict__ tiles, const Seg *__restrict__ segs, int ntiles,
-                                          const double *const *__restrict__ bases, const double *__restrict__ psi,
-                                          double *__restrict__ y, double *__restrict__ work,
-                                          double *__restrict__ part, int xcd) {
+// One launch per stage: every wavefront takes tiles from the stage's
+// cost-sorted list and runs the work item of the tile's shape.
+template <int STAGE>
+__global__ void __launch_bounds__(64 * WAVES) stage_f64_kernel(const Tile *__restrict__ tiles,
+                                                                const Seg *__restrict__ segs, int ntiles,
+                                                                const double *const *__restrict__ bases,
+                                                                const double *__restrict__ psi,
+                                                                double *__restrict__ y, double *__restrict__ work,
+                                                                double *__restrict__ part, int xcd) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r16 = lane & 15, q4 = lane >> 4;
   for (int t = work_block(xcd) * WAVES + wave; t < ntiles; t += gridDim.x * WAVES) {
@@ -144,26 +149,6 @@ __device__ __forceinline__ void items_f64(const Tile *__restrict__ tiles, const 
     else if (T.mb == 4) item_f64<4>(T, segs, bases, psi, y, work, part, r16, q4);
     else item_f64<2>(T, segs, bases, psi, y, work, part, r16, q4);
   }
-}
-
-// first stage: T stripes = X op(D)
-__global__ void __launch_bounds__(64 * WAVES) stage1_f64_kernel(const Tile *__restrict__ tiles,
-                                                                 const Seg *__restrict__ segs, int ntiles,
-                                                                 const double *const *__restrict__ bases,
-                                                                 const double *__restrict__ psi,
-                                                                 double *__restrict__ y, double *__restrict__ work,
-                                                                 double *__restrict__ part, int xcd) {
-  items_f64(tiles, segs, ntiles, bases, psi, y, work, part, xcd);
-}
-
-// second stage: Y_F += sum v A_stripe T_stripe (work items write Y or a partial tile)
-__global__ void __launch_bounds__(64 * WAVES) stage2_f64_kernel(const Tile *__restrict__ tiles,
-                                                                 const Seg *__restrict__ segs, int ntiles,
-                                                                 const double *const *__restrict__ bases,
-                                                                 const double *__restrict__ psi,
-                                                                 double *__restrict__ y, double *__restrict__ work,
-                                                                 double *__restrict__ part, int xcd) {
-  items_f64(tiles, segs, ntiles, bases, psi, y, work, part, xcd);
 }
 
 // Y tile += sum of its partial tiles, in part order
@@ -241,10 +226,10 @@ void launch_tiles_f64(int stage, const Tile *tiles, const Seg *segs, int ntiles,
   int grid = std::min((ntiles + WAVES - 1) / WAVES, 256 * 16);
   grid = (grid + 7) / 8 * 8;
   if (stage == 1)
-    hipLaunchKernelGGL(stage1_f64_kernel, dim3(grid), dim3(64 * WAVES), 0, (hipStream_t)stream, tiles, segs,
+    hipLaunchKernelGGL(stage_f64_kernel<1>, dim3(grid), dim3(64 * WAVES), 0, (hipStream_t)stream, tiles, segs,
                        ntiles, bases, psi, y, work, part, xcd);
   else
-    hipLaunchKernelGGL(stage2_f64_kernel, dim3(grid), dim3(64 * WAVES), 0, (hipStream_t)stream, tiles, segs,
+    hipLaunchKernelGGL(stage_f64_kernel<2>, dim3(grid), dim3(64 * WAVES), 0, (hipStream_t)stream, tiles, segs,
                        ntiles, bases, psi, y, work, part, xcd);
 }
 

@@ -38,7 +38,7 @@ class MLP:
         return ctypes.c_void_p(s.cuda_stream)
 
     @staticmethod
-    def _dev(t, shape_last=None):
+    def _dev(t):
         torch = _torch()
         assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
         return ctypes.c_void_p(t.data_ptr())
