@@ -279,6 +279,11 @@ int dmrg_debug_host_apply(const dmrg_problem_t *prob, const double *psi, double 
  * addressing (psi or y NULL: only fill *st).  Never used by dmrg_apply_H. */
 int dmrg_debug_plan_host_apply(const dmrg_problem_t *prob, const double *psi, double *y,
                                const dmrg_plan_opts_t *opts, dmrg_plan_stats_t *st);
+/* Test-only: per-tile work of stage 1 or 2 of the default plan for one
+ * problem (operator data not read): rows (tile rows, tile columns, segments,
+ * summed K) written to out[4 * i ..] for i < cap; returns the number of tiles
+ * (call with out = NULL to size) or a negative status. */
+int64_t dmrg_debug_plan_tiles(const dmrg_problem_t *prob, int32_t stage, int64_t *out, int64_t cap);
 
 #ifdef __cplusplus
 }
