@@ -147,6 +147,25 @@ def run_batch(args):
                      "xcd": st["xcd"], "workspace_cap": st["workspace_cap"], "autotune": tuned,
                      "n_chunks": st["n_chunks"]}
         plan.free()
+    batch_dav = None
+    if args.batch_davidson:
+        # all problems solved together: one batched H.psi per iteration
+        t1 = time.time()
+        tn = res["fp64"]["autotune"]
+        plan = Plan(probs, kpart=tn["kpart"], tile_policy=tn["tile_policy"], flags=DMRG_PLAN_XCD if tn["xcd"] else 0)
+        from paper_2309_16724_amd.synth.problem import random_vector
+        x0 = np.zeros(plan.size)
+        for k in range(len(probs)):
+            off, ln = plan.layout(k)
+            x0[off:off + ln] = random_vector(ln, 100 + k)
+        torch.cuda.synchronize()
+        t2 = time.time()
+        es, _, dst = plan.davidson(torch.from_numpy(x0).cuda(), tol=1e-8, check=False, verbose=1)
+        t3 = time.time()
+        plan.free()
+        batch_dav = {"s_per_step": t3 - t2, "plan_build_s": t2 - t1, "iterations_max": dst["iters"],
+                     "n_hpsi": dst["n_hpsi"], "converged": dst["converged"], "problems": len(probs),
+                     "residual_max": dst["residual"], "t_hpsi_s": dst["t_hpsi_s"], "energies": es}
     yf, segs = ys["fp64"]
     yb, _ = ys["split"]
     errs = [float(np.abs(yb[o:o + n] - yf[o:o + n]).max() / np.abs(yf[o:o + n]).max()) for o, n in segs]
@@ -157,7 +176,8 @@ def run_batch(args):
            "config": {"workload": "batch%d_L16-32_D128-768" % args.batch, "problems": len(probs),
                       "specs": [list(s_) for s_ in specs]},
            "fp64": res["fp64"], "split": res["split"],
-           "split_rel_err_vs_fp64": {"max": max(errs), "median": float(np.median(errs))}}
+           "split_rel_err_vs_fp64": {"max": max(errs), "median": float(np.median(errs))},
+           "davidson": batch_dav}
     print(json.dumps(out), flush=True)
 
 
@@ -179,6 +199,8 @@ def main():
     ap.add_argument("--hpsi-only", choices=("fp64", "split"),
                     help="time only H.psi of one precision (for profiler runs); also copies "
                          "256 MiB once with a plain device copy as a counter reference")
+    ap.add_argument("--batch-davidson", action="store_true",
+                    help="with --batch: also solve all problems with one batched Davidson (FP64)")
     ap.add_argument("--batch", type=int, default=0,
                     help="instead of the single workload, time H.psi of a batch of this many "
                          "uneven problems (L in [16, 32], D in [128, 768], S in {0, 1})")

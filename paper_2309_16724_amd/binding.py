@@ -92,7 +92,7 @@ def load(path=None):
         return _lib
     p = path or lib_path()
     if not os.path.exists(p):
-        raise RuntimeError("HIP library %s not built; run __graft_entry__.build()" % p)
+        raise RuntimeError("HIP library %s not built; run python -m paper_2309_16724_amd.build" % p)
     L = ctypes.CDLL(p)
     L.dmrg_last_error.restype = ctypes.c_char_p
     for name in ("dmrg_wigner_6j", "dmrg_wigner_9j", "dmrg_ctilde"):

@@ -1,0 +1,24 @@
+"""CPU checks of the entry points around the library: the benchmark refuses
+more than one GPU, and the binding fails loudly when the library is absent
+(there is no CPU fallback)."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+from paper_2309_16724_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_bench_refuses_several_gpus():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_missing_library_raises(tmp_path):
+    with pytest.raises(RuntimeError, match="not built"):
+        B.load(str(tmp_path / "libdmrg_hpsi.so"))
