@@ -20,7 +20,15 @@ namespace dmrg {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int PF = 2;   // K steps (of 4) loaded ahead
+
+// Operand pointers come from a table of generic pointers; every one of them
+// addresses device global memory, and saying so lets the compiler emit global
+// (not flat) loads, whose counters allow waiting for the oldest loads only --
+// otherwise each wait drains every load in flight and the prefetch is lost.
+typedef const double __attribute__((address_space(1))) *gcptr;
+typedef double __attribute__((address_space(1))) *gptr;
+__device__ __forceinline__ double gld(const double *p) { return *(gcptr)p; }
+
 
 // Work-group index used to pick work: consecutive work groups are spread over
 // the 8 XCDs (each with its own L2), so with xcd != 0 the groups resident on
@@ -56,7 +64,7 @@ __device__ __forceinline__ void item_f64(const Tile &T, const Seg *__restrict__ 
       int n = T.j0 + 16 * bj + r16;
       bok[bj] = (16 * bj + r16) < nrem;
       int pn = bok[bj] ? n / S.b_nb : 0;
-      boff[bj] = (int64_t)pn * S.b_pn + (int64_t)(n - pn * S.b_nb) * S.b_n;
+      boff[bj] = bok[bj] ? (int64_t)pn * S.b_pn + (int64_t)(n - pn * S.b_nb) * S.b_n : 0;
     }
     if (S.a_base < 0) {
       // identity left operator: tile += s * B restricted to the tile (K == rows)
@@ -67,7 +75,7 @@ __device__ __forceinline__ void item_f64(const Tile &T, const Seg *__restrict__ 
             if (i < mrem && bok[bj]) {
               int k = T.i0 + i;
               int pk = k / S.b_kb;
-              acc[bi][bj][r] += S.s * B[(int64_t)pk * S.b_pk + (int64_t)(k - pk * S.b_kb) * S.b_k + boff[bj]];
+              acc[bi][bj][r] += S.s * gld(B + (int64_t)pk * S.b_pk + (int64_t)(k - pk * S.b_kb) * S.b_k + boff[bj]);
             }
           }
       continue;
@@ -80,43 +88,46 @@ __device__ __forceinline__ void item_f64(const Tile &T, const Seg *__restrict__ 
       aoff[bi] = aok[bi] ? (int64_t)(T.i0 + 16 * bi + r16) * S.a_i : 0;
     }
     const double s = S.s;
-    // the lane's k is k0 + q4: track its (block, offset) for A and B
-    int pa = q4 / S.a_kb, ka = q4 - pa * S.a_kb;
-    int pb = q4 / S.b_kb, kb = q4 - pb * S.b_kb;
-    // operands of PF consecutive K steps are in flight while the previous PF
-    // steps run on the matrix core
-    double an[PF][MB], bn[PF][NB];
-    auto fetch = [&](int k0, int q) {
-      const bool kok = (k0 + q4) < S.K;
+    // Two operand buffers of one K step each, used alternately: while the
+    // matrix core works on one, the loads of the next-but-one step fill the
+    // other.  The loop is unrolled by two so the buffers are never copied (a
+    // copy would wait for the loads just issued), and no load depends on a
+    // condition: lanes outside the tile read an element inside the operand
+    // (their outputs are never stored), and lanes past the end of K read
+    // element K-1 and scale it by zero instead of s (operands are finite).
+    const unsigned akb = (unsigned)S.a_kb, bkb = (unsigned)S.b_kb;
+    auto fetch = [&](int k0, double *an, double *bn) {
+      const int k = min(k0 + q4, S.K - 1);
+      const unsigned pa = (unsigned)k / akb, ka = (unsigned)k - pa * akb;
+      const unsigned pb = (unsigned)k / bkb, kb = (unsigned)k - pb * bkb;
       const int64_t ak = (int64_t)pa * S.a_p + (int64_t)ka * S.a_k;
       const int64_t bk = (int64_t)pb * S.b_pk + (int64_t)kb * S.b_k;
-      for (int bi = 0; bi < MB; bi++) an[q][bi] = (kok && aok[bi]) ? A[ak + aoff[bi]] : 0.0;
-      for (int bj = 0; bj < NB; bj++) bn[q][bj] = (kok && bok[bj]) ? B[bk + boff[bj]] : 0.0;
-      ka += 4;
-      while (ka >= S.a_kb) { ka -= S.a_kb; pa++; }
-      kb += 4;
-      while (kb >= S.b_kb) { kb -= S.b_kb; pb++; }
+      for (int bi = 0; bi < MB; bi++) an[bi] = gld(A + ak + aoff[bi]);
+      for (int bj = 0; bj < NB; bj++) bn[bj] = gld(B + bk + boff[bj]);
     };
-#pragma unroll
-    for (int q = 0; q < PF; q++) fetch(4 * q, q);
-    for (int k0 = 0; k0 < S.K; k0 += 4 * PF) {
-      double ac[PF][MB], bc[PF][NB];
-#pragma unroll
-      for (int q = 0; q < PF; q++) {
-        for (int bi = 0; bi < MB; bi++) ac[q][bi] = s * an[q][bi];
-        for (int bj = 0; bj < NB; bj++) bc[q][bj] = bn[q][bj];
-      }
-      if (k0 + 4 * PF < S.K) {
-#pragma unroll
-        for (int q = 0; q < PF; q++) fetch(k0 + 4 * PF + 4 * q, q);
-      }
-#pragma unroll
-      for (int q = 0; q < PF; q++) {
-        if (k0 + 4 * q >= S.K) break;
-        for (int bi = 0; bi < MB; bi++)
-          for (int bj = 0; bj < NB; bj++)
-            acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[q][bi], bc[q][bj], acc[bi][bj], 0, 0, 0);
-      }
+    auto step = [&](int k0, const double *an, const double *bn) {
+      const double sk = k0 + q4 < S.K ? s : 0.0;
+      double ac[MB];
+      for (int bi = 0; bi < MB; bi++) ac[bi] = sk * an[bi];
+      for (int bi = 0; bi < MB; bi++)
+        for (int bj = 0; bj < NB; bj++)
+          acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[bi], bn[bj], acc[bi][bj], 0, 0, 0);
+    };
+    double a0[MB], b0[NB], a1[MB], b1[NB];
+    fetch(0, a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    fetch(4, a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
+    // scheduling barriers keep each buffer's refill in program order, so the
+    // older buffer's loads are always the ones waited for
+    for (int k0 = 0; k0 < S.K; k0 += 8) {
+      step(k0, a0, b0);
+      fetch(k0 + 8, a0, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      if (k0 + 4 >= S.K) break;
+      step(k0 + 4, a1, b1);
+      fetch(k0 + 12, a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
   double *C = const_cast<double *>(base_ptr(T.c_base, bases, psi, y, work, part)) + T.c_off;
@@ -125,8 +136,8 @@ __device__ __forceinline__ void item_f64(const Tile &T, const Seg *__restrict__ 
       for (int r = 0; r < 4; r++) {
         int i = 16 * bi + q4 + 4 * r, j = 16 * bj + r16;
         if (i < mrem && j < nrem) {
-          double *c = T.rowmajor ? C + (int64_t)(T.ci0 + i) * T.ldc + (T.cj0 + j)
-                                 : C + (int64_t)(T.ci0 + i) + (int64_t)(T.cj0 + j) * T.ldc;
+          gptr c = (gptr)(T.rowmajor ? C + (int64_t)(T.ci0 + i) * T.ldc + (T.cj0 + j)
+                                     : C + (int64_t)(T.ci0 + i) + (int64_t)(T.cj0 + j) * T.ldc);
           *c = T.accumulate ? *c + acc[bi][bj][r] : acc[bi][bj][r];
         }
       }
@@ -143,7 +154,10 @@ __global__ void __launch_bounds__(64 * WAVES) stage_f64_kernel(const Tile *__res
                                                                 double *__restrict__ part, int xcd) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r16 = lane & 15, q4 = lane >> 4;
-  for (int t = work_block(xcd) * WAVES + wave; t < ntiles; t += gridDim.x * WAVES) {
+  // the tile index is the same for the whole wavefront: saying so makes the
+  // descriptors scalar loads and the K loops uniform (no exec masking)
+  for (int t = __builtin_amdgcn_readfirstlane(work_block(xcd) * WAVES + wave); t < ntiles;
+       t += gridDim.x * WAVES) {
     const Tile T = tiles[t];
     if (T.mb == 1) item_f64<1>(T, segs, bases, psi, y, work, part, r16, q4);
     else if (T.mb == 4) item_f64<4>(T, segs, bases, psi, y, work, part, r16, q4);

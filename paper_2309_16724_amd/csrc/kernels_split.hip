@@ -151,9 +151,11 @@ void launch_slices(const SliceJob *jobs, int njobs, int nslices, const double *c
 }
 
 // ------------------------------------------------------------------ split products
+// slice buffers live in device global memory: global (not flat) loads
+typedef const v8bf __attribute__((address_space(1))) *gv8ptr;
 __device__ __forceinline__ v8bf load8(const uint16_t *p, bool ok) {
   if (!ok) return (v8bf){};
-  return *reinterpret_cast<const v8bf *>(p);
+  return *(gv8ptr)p;
 }
 
 template <int MB, int NS>
