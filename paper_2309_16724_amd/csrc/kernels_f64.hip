@@ -120,11 +120,11 @@ __device__ __forceinline__ void item_f64(const Tile &T, const Seg *__restrict__ 
     __builtin_amdgcn_sched_barrier(0);
     // scheduling barriers keep each buffer's refill in program order, so the
     // older buffer's loads are always the ones waited for
+    // one exit: a second half past K contributes zero (its scale is zero)
     for (int k0 = 0; k0 < S.K; k0 += 8) {
       step(k0, a0, b0);
       fetch(k0 + 8, a0, b0);
       __builtin_amdgcn_sched_barrier(0);
-      if (k0 + 4 >= S.K) break;
       step(k0 + 4, a1, b1);
       fetch(k0 + 12, a1, b1);
       __builtin_amdgcn_sched_barrier(0);
