@@ -4,7 +4,7 @@
 // (see SliceJob): C_ij = 2^(e_i + f_j) sum_{t+u <= s-1} 2^(-8(t+u+2)) sum_k a^t_ik b^u_kj.
 // The inner sums run on v_mfma_f32_16x16x32_bf16; products of slices are
 // integers of at most 16 bits, and sums grouped by d = t+u stay exact in FP32
-// for SPLIT_FOLD_K terms, after which they are folded into FP64 with the
+// for split_fold_k(s) terms, after which they are folded into FP64 with the
 // line scales.  FP64 remains for the fold, the scales and the identity
 // segments.  Lane layout of v_mfma_f32_16x16x32_bf16 (lane l, element e/r):
 // A[l%16][8(l/16)+e], B[8(l/16)+e][l%16], D[4(l/16)+r][l%16].
@@ -153,16 +153,26 @@ void launch_slices(const SliceJob *jobs, int njobs, int nslices, const double *c
 // ------------------------------------------------------------------ split products
 // slice buffers live in device global memory: global (not flat) loads
 typedef const v8bf __attribute__((address_space(1))) *gv8ptr;
-__device__ __forceinline__ v8bf load8(const uint16_t *p, bool ok) {
-  if (!ok) return (v8bf){};
-  return *(gv8ptr)p;
+typedef const void __attribute__((address_space(1))) *gvptr;
+typedef void __attribute__((address_space(3))) *lvptr;
+typedef const v8bf __attribute__((address_space(3))) *lv8ptr;
+// s_waitcnt immediates (gfx9 encoding): vmcnt(0) alone, lgkmcnt(0) alone
+constexpr int WAIT_VM0 = 0x0F70, WAIT_LGKM0 = 0xC07F;
+// LDS stage of one wavefront: (MB + NB) * NS chunks of 64 lanes x 16 bytes
+constexpr int stage_bytes(int ns) { return 5 * ns * 1024; }
+
+// 2^(-8(d+2)), the weight of slice-product group d
+static_assert(SLICE_BITS == 8, "fold weights assume 8-bit slices");
+__device__ constexpr double fold_scale(int d) {
+  return d == 0 ? 0x1p-16 : d == 1 ? 0x1p-24 : d == 2 ? 0x1p-32 : d == 3 ? 0x1p-40 : d == 4 ? 0x1p-48
+                                                                                             : d == 5 ? 0x1p-56 : 0x1p-64;
 }
 
 template <int MB, int NS>
 __device__ __forceinline__ void item_split(const Tile &T, const Seg *__restrict__ segs,
                                            const SegS *__restrict__ ssegs, const double *const *bases,
                                            const double *psi, double *y, double *work, double *part,
-                                           const SliceBufs &bufs, int r16, int q4) {
+                                           const SliceBufs &bufs, char *stage, int r16, int q4) {
   constexpr int NB = 4 / MB;
   v4d acc[MB][NB];
   for (int a = 0; a < MB; a++)
@@ -197,38 +207,51 @@ __device__ __forceinline__ void item_split(const Tile &T, const Seg *__restrict_
     const int64_t pa = bufs.plane[Q.a_buf], pb = bufs.plane[Q.b_buf];
     const int32_t *ea = bufs.exps[Q.a_buf] + Q.a_exp;
     const int32_t *eb = bufs.exps[Q.b_buf] + Q.b_exp;
-    const uint16_t *arow[MB];
-    bool aok[MB];
-    for (int bi = 0; bi < MB; bi++) {
-      aok[bi] = (16 * bi + r16) < mrem;
-      arow[bi] = A + (aok[bi] ? (int64_t)(T.i0 + 16 * bi + r16) * Q.a_ld : 0);
-    }
-    const uint16_t *bcol[NB];
-    bool bok[NB];
-    for (int bj = 0; bj < NB; bj++) {
-      bok[bj] = (16 * bj + r16) < nrem;
-      bcol[bj] = B + (bok[bj] ? (int64_t)(T.j0 + 16 * bj + r16) * Q.b_ld : 0);
-    }
+    // lanes past the last row / column read the last one: their outputs are
+    // never stored, so every operand load is unconditional.  Addresses are a
+    // wave-uniform slice base plus a 32-bit lane offset within the segment's
+    // lines (checked when the plan is built).
+    uint32_t arow[MB], bcol[NB];   // byte offsets
+    for (int bi = 0; bi < MB; bi++) arow[bi] = (uint32_t)(T.i0 + min(16 * bi + r16, mrem - 1)) * (uint32_t)Q.a_ld * 2u;
+    for (int bj = 0; bj < NB; bj++) bcol[bj] = (uint32_t)(T.j0 + min(16 * bj + r16, nrem - 1)) * (uint32_t)Q.b_ld * 2u;
     // scale exponents of this lane's output elements
     int erow[MB][4], fcol[NB];
     for (int bi = 0; bi < MB; bi++)
-      for (int r = 0; r < 4; r++) {
-        int i = 16 * bi + 4 * q4 + r;
-        erow[bi][r] = i < mrem ? ea[T.i0 + i] : 0;
-      }
-    for (int bj = 0; bj < NB; bj++) fcol[bj] = bok[bj] ? eb[T.j0 + 16 * bj + r16] : 0;
+      for (int r = 0; r < 4; r++) erow[bi][r] = ea[T.i0 + min(16 * bi + 4 * q4 + r, mrem - 1)];
+    for (int bj = 0; bj < NB; bj++) fcol[bj] = eb[T.j0 + min(16 * bj + r16, nrem - 1)];
     v4f q[MB][NB][NS];
     for (int bi = 0; bi < MB; bi++)
       for (int bj = 0; bj < NB; bj++)
         for (int d = 0; d < NS; d++) q[bi][bj][d] = (v4f){0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < Q.K; k0 += 32) {
-      const int kl = k0 + 8 * q4;
-      const bool kok = kl < Q.K;
-      v8bf as[MB][NS], bs[NB][NS];
-      for (int bi = 0; bi < MB; bi++)
-        for (int t = 0; t < NS; t++) as[bi][t] = load8(arow[bi] + (int64_t)t * pa + kl, kok && aok[bi]);
-      for (int bj = 0; bj < NB; bj++)
-        for (int t = 0; t < NS; t++) bs[bj][t] = load8(bcol[bj] + (int64_t)t * pb + kl, kok && bok[bj]);
+    // K is a multiple of 8 and the lines are zero-padded to it, so the chunk
+    // of 8 at min(k, K - 8) is always inside the operand; a lane whose chunk
+    // starts at or past K multiplies a zeroed A operand.  The operands of a
+    // step go straight from global memory into this wave's LDS stage (one
+    // 1 KiB chunk per operand row block and slice, 16 bytes per lane), so the
+    // loads of the next step fly while the MFMAs of this one run without
+    // holding a second set of registers.
+    auto dma = [&](int k0) {
+      const uint32_t kl = 2u * (uint32_t)min(k0 + 8 * q4, Q.K - 8);
+      for (int t = 0; t < NS; t++) {
+        const char *at = (const char *)(A + (int64_t)t * pa), *bt = (const char *)(B + (int64_t)t * pb);
+        for (int bi = 0; bi < MB; bi++)
+          __builtin_amdgcn_global_load_lds((gvptr)(at + (arow[bi] + kl)), (lvptr)(stage + (bi * NS + t) * 1024), 16, 0, 0);
+        for (int bj = 0; bj < NB; bj++)
+          __builtin_amdgcn_global_load_lds((gvptr)(bt + (bcol[bj] + kl)), (lvptr)(stage + ((MB + bj) * NS + t) * 1024),
+                                           16, 0, 0);
+      }
+    };
+    auto rd = [&](v8bf (*as)[NS], v8bf (*bs)[NS]) {
+      const int lo = 16 * (r16 + 16 * q4);
+      for (int t = 0; t < NS; t++) {
+        for (int bi = 0; bi < MB; bi++) as[bi][t] = *(const lv8ptr)(stage + (bi * NS + t) * 1024 + lo);
+        for (int bj = 0; bj < NB; bj++) bs[bj][t] = *(const lv8ptr)(stage + ((MB + bj) * NS + t) * 1024 + lo);
+      }
+    };
+    auto mma = [&](int k0, v8bf (*as)[NS], v8bf (*bs)[NS]) {
+      if (k0 + 32 > Q.K && k0 + 8 * q4 >= Q.K)   // only the last step of a line has such lanes
+        for (int bi = 0; bi < MB; bi++)
+          for (int t = 0; t < NS; t++) as[bi][t] = (v8bf){};
 #pragma unroll
       for (int d = 0; d < NS; d++)
 #pragma unroll
@@ -236,19 +259,33 @@ __device__ __forceinline__ void item_split(const Tile &T, const Seg *__restrict_
           for (int bi = 0; bi < MB; bi++)
             for (int bj = 0; bj < NB; bj++)
               q[bi][bj][d] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as[bi][t], bs[bj][d - t], q[bi][bj][d], 0, 0, 0);
-      const bool last = k0 + 32 >= Q.K;
-      if (last || ((k0 + 32) % SPLIT_FOLD_K) == 0) {
-        for (int bi = 0; bi < MB; bi++)
-          for (int bj = 0; bj < NB; bj++)
-            for (int r = 0; r < 4; r++) {
-              double x = 0.0;
-              for (int d = 0; d < NS; d++) x += ldexp((double)q[bi][bj][d][r], -SLICE_BITS * (d + 2));
-              acc[bi][bj][r] += S.s * ldexp(x, erow[bi][r] + fcol[bj]);
-            }
-        for (int bi = 0; bi < MB; bi++)
-          for (int bj = 0; bj < NB; bj++)
-            for (int d = 0; d < NS; d++) q[bi][bj][d] = (v4f){0.f, 0.f, 0.f, 0.f};
-      }
+    };
+    auto fold = [&]() {
+      for (int bi = 0; bi < MB; bi++)
+        for (int bj = 0; bj < NB; bj++)
+          for (int r = 0; r < 4; r++) {
+            double x = 0.0;   // q * 2^(-8(d+2)) is exact: the FMA rounds the sum only
+            for (int d = 0; d < NS; d++) x = fma((double)q[bi][bj][d][r], fold_scale(d), x);
+            acc[bi][bj][r] += S.s * ldexp(x, erow[bi][r] + fcol[bj]);
+          }
+      for (int bi = 0; bi < MB; bi++)
+        for (int bj = 0; bj < NB; bj++)
+          for (int d = 0; d < NS; d++) q[bi][bj][d] = (v4f){0.f, 0.f, 0.f, 0.f};
+    };
+    constexpr int FOLD = split_fold_k(NS);
+    static_assert(FOLD % 32 == 0, "the K loop folds after whole 32-wide steps");
+    v8bf as[MB][NS], bs[NB][NS];
+    dma(0);
+    for (int k0 = 0; k0 < Q.K; k0 += 32) {
+      __builtin_amdgcn_s_waitcnt(WAIT_VM0);      // this step's chunks are in LDS
+      __builtin_amdgcn_sched_barrier(0);
+      rd(as, bs);
+      __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);    // ... and in registers: the stage is free
+      __builtin_amdgcn_sched_barrier(0);
+      if (k0 + 32 < Q.K) dma(k0 + 32);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(k0, as, bs);
+      if (k0 + 32 >= Q.K || (k0 + 32) % FOLD == 0) fold();
     }
   }
   double *C = const_cast<double *>(sbase_ptr(T.c_base, bases, psi, y, work, part)) + T.c_off;
@@ -300,13 +337,16 @@ __device__ __forceinline__ void items_split(const Tile *__restrict__ tiles, cons
                                             const double *const *__restrict__ bases, const double *__restrict__ psi,
                                             double *__restrict__ y, double *__restrict__ work,
                                             double *__restrict__ part, const SliceBufs &bufs, int xcd) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, q4 = lane >> 4;
-  for (int t = work_block(xcd) * WAVES + wave; t < ntiles; t += gridDim.x * WAVES) {
+  __shared__ __attribute__((aligned(1024))) char lds[WAVES * stage_bytes(NS)];
+  char *stage = lds + wave * stage_bytes(NS);
+  for (int t = __builtin_amdgcn_readfirstlane(work_block(xcd) * WAVES + wave); t < ntiles;
+       t += gridDim.x * WAVES) {
     const Tile T = tiles[t];
-    if (T.mb == 1) item_split<1, NS>(T, segs, ssegs, bases, psi, y, work, part, bufs, r16, q4);
-    else if (T.mb == 4) item_split<4, NS>(T, segs, ssegs, bases, psi, y, work, part, bufs, r16, q4);
-    else item_split<2, NS>(T, segs, ssegs, bases, psi, y, work, part, bufs, r16, q4);
+    if (T.mb == 1) item_split<1, NS>(T, segs, ssegs, bases, psi, y, work, part, bufs, stage, r16, q4);
+    else if (T.mb == 4) item_split<4, NS>(T, segs, ssegs, bases, psi, y, work, part, bufs, stage, r16, q4);
+    else item_split<2, NS>(T, segs, ssegs, bases, psi, y, work, part, bufs, stage, r16, q4);
   }
 }
 

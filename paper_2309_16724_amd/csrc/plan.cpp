@@ -785,6 +785,20 @@ void build_split(dmrg_plan *P) {
   check_jobs(P->jobs_ops);
   check_jobs(P->jobs_psi);
   for (auto &ch : P->chunks) check_jobs(ch.tjobs);
+  // the split kernels address a segment's slice lines with 32-bit byte
+  // offsets from the slice base: rows * ld * 2 bytes must stay below 2^32
+  for (auto &ch : P->chunks)
+    for (int st = 1; st <= 2; st++) {
+      const auto &tiles = st == 1 ? ch.tile1 : ch.tile2;
+      const auto &ss = st == 1 ? ch.sseg1 : ch.sseg2;
+      for (const Tile &t : tiles)
+        for (int i = 0; i < t.nseg; i++) {
+          const SegS &q = ss[t.seg0 + i];
+          if (q.K > 0 && ((int64_t)t.m * q.a_ld * 2 >= ((int64_t)1 << 32) ||
+                          (int64_t)t.n * q.b_ld * 2 >= ((int64_t)1 << 32)))
+            throw std::length_error("split operand lines span 4 GiB or more");
+        }
+    }
 }
 
 }  // namespace
@@ -1362,12 +1376,12 @@ static void host_tiles_split(const std::vector<Tile> &tiles, const std::vector<S
           const uint16_t *ar = A + (int64_t)(T.i0 + i) * Q.a_ld;
           const uint16_t *bc = B + (int64_t)(T.j0 + j) * Q.b_ld;
           double tot = 0.0;
-          for (int k0 = 0; k0 < Q.K; k0 += SPLIT_FOLD_K) {
+          for (int k0 = 0; k0 < Q.K; k0 += split_fold_k(ns)) {
             double x = 0.0;
             for (int d = 0; d < ns; d++) {
               double qd = 0.0;
               for (int t = 0; t <= d; t++)
-                for (int k = k0; k < std::min(Q.K, k0 + SPLIT_FOLD_K); k++)
+                for (int k = k0; k < std::min(Q.K, k0 + split_fold_k(ns)); k++)
                   qd += bf16v(ar[(int64_t)t * plane[Q.a_buf] + k]) * bf16v(bc[(int64_t)(d - t) * plane[Q.b_buf] + k]);
               x += std::ldexp(qd, -SLICE_BITS * (d + 2));
             }

@@ -79,7 +79,12 @@ struct DressItem {
 // all exact in BF16.  Lines are stored K-contiguous (operand-ready) and each
 // position block of K is padded to a multiple of 8 with zeros.
 constexpr int SLICE_BITS = 8;
-constexpr int SPLIT_FOLD_K = 64;   // summed products stay exact in FP32 up to here
+// Sums of slice products are folded into FP64 every split_fold_k(s) terms of
+// K.  Group d sums the products a_t b_(d-t), t = 0..d: the two with t = 0 or
+// t = d are bounded by 256 * 128 = 2^15 and the others by 2^14, so per k the
+// group is at most (s + 2) 2^14 in magnitude for every d < s (s >= 2), and K
+// terms stay integers below 2^24 -- exact in FP32 -- while K (s + 2) <= 2^10.
+constexpr int split_fold_k(int ns) { return ns <= 6 ? 128 : 64; }
 
 // One slicing job: lines rho < nrho, position blocks p < npos of kb valid
 // entries (padded to kbp);  source x(rho, p, kk) at src[src_off + rho*s_rho + p*s_pos + kk*s_k];
