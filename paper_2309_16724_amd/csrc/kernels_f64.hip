@@ -96,15 +96,6 @@ __device__ __forceinline__ void item_f64(const Tile &T, const Seg *__restrict__ 
     // (their outputs are never stored), and lanes past the end of K read
     // element K-1 and scale it by zero instead of s (operands are finite).
     const unsigned akb = (unsigned)S.a_kb, bkb = (unsigned)S.b_kb;
-    auto fetch = [&](int k0, double *an, double *bn) {
-      const int k = min(k0 + q4, S.K - 1);
-      const unsigned pa = (unsigned)k / akb, ka = (unsigned)k - pa * akb;
-      const unsigned pb = (unsigned)k / bkb, kb = (unsigned)k - pb * bkb;
-      const int64_t ak = (int64_t)pa * S.a_p + (int64_t)ka * S.a_k;
-      const int64_t bk = (int64_t)pb * S.b_pk + (int64_t)kb * S.b_k;
-      for (int bi = 0; bi < MB; bi++) an[bi] = gld(A + ak + aoff[bi]);
-      for (int bj = 0; bj < NB; bj++) bn[bj] = gld(B + bk + boff[bj]);
-    };
     auto step = [&](int k0, const double *an, const double *bn) {
       const double sk = k0 + q4 < S.K ? s : 0.0;
       double ac[MB];
@@ -113,21 +104,67 @@ __device__ __forceinline__ void item_f64(const Tile &T, const Seg *__restrict__ 
         for (int bj = 0; bj < NB; bj++)
           acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[bi], bn[bj], acc[bi][bj], 0, 0, 0);
     };
-    double a0[MB], b0[NB], a1[MB], b1[NB];
-    fetch(0, a0, b0);
-    __builtin_amdgcn_sched_barrier(0);
-    fetch(4, a1, b1);
-    __builtin_amdgcn_sched_barrier(0);
     // scheduling barriers keep each buffer's refill in program order, so the
-    // older buffer's loads are always the ones waited for
-    // one exit: a second half past K contributes zero (its scale is zero)
-    for (int k0 = 0; k0 < S.K; k0 += 8) {
-      step(k0, a0, b0);
-      fetch(k0 + 8, a0, b0);
+    // older buffer's loads are always the ones waited for; one exit: a second
+    // half past K contributes zero (its scale is zero)
+    auto kloop = [&](auto &&fetch) {
+      double a0[MB], b0[NB], a1[MB], b1[NB];
+      fetch(0, a0, b0);
       __builtin_amdgcn_sched_barrier(0);
-      step(k0 + 4, a1, b1);
-      fetch(k0 + 12, a1, b1);
+      fetch(4, a1, b1);
       __builtin_amdgcn_sched_barrier(0);
+      for (int k0 = 0; k0 < S.K; k0 += 8) {
+        step(k0, a0, b0);
+        fetch(k0 + 8, a0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        step(k0 + 4, a1, b1);
+        fetch(k0 + 12, a1, b1);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    };
+    if (akb >= 4 && bkb >= 4) {
+      // A lane's K index k0 + q4 moves by 4 per step and crosses at most one
+      // position boundary, so its (position, offset) pairs are carried along
+      // with adds and selects; lanes at or past K read element K - 1, whose
+      // offsets are wave-uniform.
+      const unsigned kl = (unsigned)S.K - 1, pla = kl / akb, plb = kl / bkb;
+      const int64_t al = (int64_t)pla * S.a_p + (int64_t)(kl - pla * akb) * S.a_k;
+      const int64_t bl = (int64_t)plb * S.b_pk + (int64_t)(kl - plb * bkb) * S.b_k;
+      const int64_t ad = 4 * S.a_k, aw = S.a_p - (int64_t)akb * S.a_k;
+      const int64_t bd = 4 * S.b_k, bw = S.b_pk - (int64_t)bkb * S.b_k;
+      unsigned ka = q4, kb = q4;
+      int64_t ao = (int64_t)q4 * S.a_k, bo = (int64_t)q4 * S.b_k;
+      kloop([&](int k0, double *an, double *bn) {
+        int64_t ua = ao, ub = bo;
+        if (k0 + 4 > S.K && k0 + q4 >= S.K) {
+          ua = al;
+          ub = bl;
+        }
+        for (int bi = 0; bi < MB; bi++) an[bi] = gld(A + ua + aoff[bi]);
+        for (int bj = 0; bj < NB; bj++) bn[bj] = gld(B + ub + boff[bj]);
+        ka += 4;
+        ao += ad;
+        if (ka >= akb) {
+          ka -= akb;
+          ao += aw;
+        }
+        kb += 4;
+        bo += bd;
+        if (kb >= bkb) {
+          kb -= bkb;
+          bo += bw;
+        }
+      });
+    } else {
+      kloop([&](int k0, double *an, double *bn) {
+        const int k = min(k0 + q4, S.K - 1);
+        const unsigned pa = (unsigned)k / akb, ka = (unsigned)k - pa * akb;
+        const unsigned pb = (unsigned)k / bkb, kb = (unsigned)k - pb * bkb;
+        const int64_t ak = (int64_t)pa * S.a_p + (int64_t)ka * S.a_k;
+        const int64_t bk = (int64_t)pb * S.b_pk + (int64_t)kb * S.b_k;
+        for (int bi = 0; bi < MB; bi++) an[bi] = gld(A + ak + aoff[bi]);
+        for (int bj = 0; bj < NB; bj++) bn[bj] = gld(B + bk + boff[bj]);
+      });
     }
   }
   double *C = const_cast<double *>(base_ptr(T.c_base, bases, psi, y, work, part)) + T.c_off;

@@ -94,7 +94,12 @@ __global__ void __launch_bounds__(256) slice_kernel(const SliceJob *__restrict__
   }
 }
 
-// stripe slices, one work group per chunk of TSLICE_CHUNK elements
+// stripe slices, one work group per chunk of TSLICE_CHUNK elements, four
+// consecutive elements per thread.  Line lengths, position blocks (kbp), plane
+// strides and job offsets are multiples of 8, so a group of four never
+// straddles a line or a position block and its slices are one aligned 8-byte
+// store per plane.
+static_assert(TSLICE_CHUNK == 4 * 256, "one chunk is 256 threads x 4 elements");
 __global__ void __launch_bounds__(256) tslice_kernel(const SliceJob *__restrict__ jobs,
                                                       const TSliceItem *__restrict__ items, int nitems, int ns,
                                                       const double *__restrict__ work, SliceBufs bufs) {
@@ -107,20 +112,27 @@ __global__ void __launch_bounds__(256) tslice_kernel(const SliceJob *__restrict_
     const int32_t *exps = bufs.exps[SBUF_T] + J.exp_off;
     const unsigned kb = (unsigned)J.kb, kbp = (unsigned)J.kbp, len = (unsigned)(J.npos * J.kbp);
     const unsigned tot = len * (unsigned)J.nrho;
-    for (int q = 0; q < TSLICE_CHUNK / 256; q++) {
-      const unsigned e = (unsigned)I.e0 + (unsigned)(q * 256) + threadIdx.x;
-      if (e >= tot) break;
-      const unsigned rho = e / len, idx = e - rho * len;
-      const unsigned p = idx / kbp, kk = idx - p * kbp;
-      const double x = kk < kb ? src[(int64_t)rho * J.s_rho + (int64_t)p * J.s_pos + (int64_t)kk * J.s_k] : 0.0;
-      const int ex = exps[rho];
-      double yv = ldexp(x, ex == INT_MIN ? 0 : -ex);
-      for (int t = 0; t < ns; t++) {
-        const double a = rint(yv * 256.0);
-        yv = yv * 256.0 - a;
+    const unsigned e = (unsigned)I.e0 + 4u * threadIdx.x;
+    if (e >= tot) continue;
+    const unsigned rho = e / len, idx = e - rho * len;
+    const unsigned p = idx / kbp, kk = idx - p * kbp;
+    const double *line = src + (int64_t)rho * J.s_rho + (int64_t)p * J.s_pos;
+    const int ex = exps[rho];
+    double yv[4];
+    for (int i = 0; i < 4; i++) {
+      const unsigned k = kk + i;
+      const double x = line[(int64_t)min(k, kb - 1) * J.s_k];    // padding reads a valid entry ...
+      yv[i] = ldexp(k < kb ? x : 0.0, ex == INT_MIN ? 0 : -ex);  // ... and slices zero
+    }
+    for (int t = 0; t < ns; t++) {
+      uint64_t packed = 0;
+      for (int i = 0; i < 4; i++) {
+        const double a = rint(yv[i] * 256.0);
+        yv[i] = yv[i] * 256.0 - a;
         const float af = (float)a;                 // integer, |a| <= 256: exact in BF16
-        dst[(int64_t)t * plane + e] = (uint16_t)(__float_as_uint(af) >> 16);
+        packed |= (uint64_t)(__float_as_uint(af) >> 16) << (16 * i);
       }
+      *(uint64_t *)(dst + (int64_t)t * plane + e) = packed;
     }
   }
 }
