@@ -67,6 +67,7 @@ def cpu_baseline(prob, flops_full, target_s=15.0):
 def train_preconditioner(torch, specs, steps=2000, batch=4096, seed=0, width=256):
     """Learned preconditioner: exact-correction rows of the given solves
     (device capture), then minibatch Adam on the device."""
+    import numpy as np
     from paper_2309_16724_amd.hpsi import Plan
     from paper_2309_16724_amd.precond import MLP
     from paper_2309_16724_amd.synth.problem import random_problem, random_vector
@@ -84,12 +85,22 @@ def train_preconditioner(torch, specs, steps=2000, batch=4096, seed=0, width=256
     x, a, b = torch.cat(xs), torch.cat(as_), torch.cat(bs)
     t1 = time.time()
     net = MLP(width, seed=seed)
+    # the training objective on a fixed sample of 2^20 rows (minibatch losses
+    # of heavy-tailed rows are too noisy to compare)
+    g = torch.Generator(device="cpu").manual_seed(seed + 2)
+    idx = torch.randint(0, x.shape[0], (1 << 20,), generator=g).to(x.device)
+    xe, ae, be = x[idx].contiguous(), a[idx].contiguous(), b[idx].contiguous()
+    loss0, _ = net.loss_grad(xe, ae, be)
     tr = net.train(x, a, b, steps=steps, batch=batch, lr=1e-3, seed=seed + 1, trace=True)
+    loss1, _ = net.loss_grad(xe, ae, be)
     t2 = time.time()
     info = {"solves": len(specs), "records": nrec, "rows": int(x.shape[0]), "steps": steps,
             "batch": batch, "width": width, "collect_s": t1 - t0, "train_s": t2 - t1,
-            "loss_first100": float(tr[:100].mean()), "loss_last100": float(tr[-100:].mean()),
+            "sample_loss_diagonal": float(((ae - be) ** 2).mean().item()),
+            "sample_loss_before": float(loss0), "sample_loss_after": float(loss1),
+            "minibatch_loss_deciles": [round(float(v.mean()), 4) for v in np.array_split(tr, 10)],
             "specs": [list(s_) for s_ in specs]}
+    del xe, ae, be, idx
     del xs, as_, bs, x, a, b
     return net, info
 

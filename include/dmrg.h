@@ -183,13 +183,19 @@ typedef struct {
   int32_t verbose;          /* > 0: a progress line on stderr every 25 iterations */
   double floor;             /* preconditioner denominator floor, e.g. 1e-8   */
   const dmrg_mlp_t *mlp;    /* network for DMRG_PRECOND_MLP, else NULL       */
+  int32_t mlp_patience;     /* learned steps of a problem stop after this many
+                               iterations without a new smallest residual
+                               (0: 30); the rest of its solve is diagonal    */
+  int32_t pad;
 } dmrg_dav_opts_t;
 /* fallbacks: learned corrections rejected by the guard (non-finite, or
- * |cos(t_mlp, t_diag)| < DMRG_MLP_GUARD) and replaced by the diagonal step. */
+ * |cos(t_mlp, t_diag)| < DMRG_MLP_GUARD) and replaced by the diagonal step;
+ * switched: problems whose learned steps were stopped by mlp_patience. */
 typedef struct {
   int32_t iters, n_hpsi, converged, fallbacks;
   double residual, energy;
   double t_total_s, t_hpsi_s;
+  int32_t switched, pad;
 } dmrg_dav_stats_t;
 int dmrg_davidson(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts_t *o,
                   dmrg_dav_stats_t *st, void *stream);

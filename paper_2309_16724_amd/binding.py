@@ -45,7 +45,8 @@ class PlanOpts(ctypes.Structure):
 
 class DavOpts(ctypes.Structure):
     _fields_ = [("tol", c_dbl), ("max_iter", c_i32), ("m_max", c_i32), ("precond", c_i32),
-                ("verbose", c_i32), ("floor", c_dbl), ("mlp", c_vp)]
+                ("verbose", c_i32), ("floor", c_dbl), ("mlp", c_vp), ("mlp_patience", c_i32),
+                ("pad", c_i32)]
 
 
 DMRG_PRECOND_DIAG = 0
@@ -61,7 +62,8 @@ class TrainOpts(ctypes.Structure):
 
 class DavStats(ctypes.Structure):
     _fields_ = [("iters", c_i32), ("n_hpsi", c_i32), ("converged", c_i32), ("fallbacks", c_i32),
-                ("residual", c_dbl), ("energy", c_dbl), ("t_total_s", c_dbl), ("t_hpsi_s", c_dbl)]
+                ("residual", c_dbl), ("energy", c_dbl), ("t_total_s", c_dbl), ("t_hpsi_s", c_dbl),
+                ("switched", c_i32), ("pad", c_i32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

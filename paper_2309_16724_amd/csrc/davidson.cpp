@@ -10,7 +10,10 @@
 // reaches m_max; two-pass classical Gram-Schmidt; correction
 // t = -r / (diag - theta) with |diag - theta| floored, optionally corrected
 // per element by the learned network (mlp.cpp), with a guard that falls back
-// to the diagonal step; convergence when ||H u - theta u||_2 <= tol for the
+// to the diagonal step and a patience rule that turns the learned steps of a
+// problem off once its residual stops reaching new minima (a network can be
+// finite and well aligned yet stall the solve); convergence when
+// ||H u - theta u||_2 <= tol for the
 // normalised Ritz vector u.  Problems of a batch share the basis-column
 // index: a converged problem stops adding vectors (its segments of later
 // columns are zero), restarts are global.
@@ -111,6 +114,10 @@ struct ProbState {
   double theta = 0.0, rnorm = 0.0;
   bool active = true, have_prev = false;
   int iters = 0;
+  // learned steps stay on while the residual keeps reaching new minima
+  double best_r = INFINITY;
+  int best_it = 0;
+  bool mlp_on = true;
   double sum_d = 0.0, sum_d2 = 0.0;   // sums of diag and diag^2 over the segment
 };
 
@@ -126,12 +133,14 @@ struct Collect {
 }  // namespace
 
 static int check_opts(const dmrg_dav_opts_t *o, dmrg_dav_opts_t *opt) {
-  *opt = {1e-8, 1000, 24, DMRG_PRECOND_DIAG, 0, 1e-8, nullptr};
+  *opt = {1e-8, 1000, 24, DMRG_PRECOND_DIAG, 0, 1e-8, nullptr, 0, 0};
   if (o) *opt = *o;
-  if (opt->m_max < 3 || opt->m_max > 64 || opt->max_iter < 1 || !(opt->tol > 0.0) || !(opt->floor > 0.0)) {
-    set_error("bad Davidson options (m_max in [3,64], max_iter >= 1, tol > 0, floor > 0)");
+  if (opt->m_max < 3 || opt->m_max > 64 || opt->max_iter < 1 || !(opt->tol > 0.0) || !(opt->floor > 0.0) ||
+      opt->mlp_patience < 0) {
+    set_error("bad Davidson options (m_max in [3,64], max_iter >= 1, tol > 0, floor > 0, mlp_patience >= 0)");
     return DMRG_EINVAL;
   }
+  if (opt->mlp_patience == 0) opt->mlp_patience = 30;
   if (opt->precond != DMRG_PRECOND_DIAG && opt->precond != DMRG_PRECOND_MLP) {
     set_error("unknown preconditioner");
     return DMRG_EINVAL;
@@ -297,6 +306,12 @@ static int solve(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts
       S.iters = it;
       S.rnorm = std::sqrt(hout[k]);
       if (!std::isfinite(S.rnorm)) { set_error("non-finite residual"); return DMRG_ENONFINITE; }
+      if (S.rnorm < S.best_r) {
+        S.best_r = S.rnorm;
+        S.best_it = it;
+      } else if (use_mlp && S.mlp_on && it - S.best_it >= opt.mlp_patience) {
+        S.mlp_on = false;   // stagnating with learned steps: diagonal steps from here on
+      }
       if (S.rnorm <= opt.tol) {
         S.active = false;
         n_active--;
@@ -330,7 +345,9 @@ static int solve(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts
         }
       }
     }
-    if (use_mlp) {
+    bool mlp_live = false;
+    for (const ProbState &S : P) mlp_live = mlp_live || (S.active && S.mlp_on);
+    if (use_mlp && mlp_live) {
       // learned correction t_mlp = td (1 + g(x)) into tm, then the guard
       std::vector<double> sig(np, 1.0), f1(np, 0.0), th(np, 0.0);
       for (int k = 0; k < np; k++) {
@@ -363,7 +380,7 @@ static int solve(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts
       if ((rc = dots_host(t, 1, t))) return rc;
       std::vector<double> flag(np, 0.0);
       for (int k = 0; k < np; k++) {
-        if (!P[k].active) continue;
+        if (!P[k].active || !P[k].mlp_on) continue;
         const double tt = hout[k];
         const bool ok = std::isfinite(mm[k]) && std::isfinite(mt[k]) && mm[k] > 0.0 &&
                         std::fabs(mt[k]) >= DMRG_MLP_GUARD * std::sqrt(mm[k] * tt);
@@ -512,6 +529,8 @@ static int solve(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts
     st->iters = maxit;
     st->n_hpsi = n_hpsi;
     st->fallbacks = fallbacks;
+    st->switched = 0;
+    for (const ProbState &S : P) st->switched += use_mlp && !S.mlp_on;
     st->converged = conv;
     st->residual = maxres;
     st->energy = P[0].theta;

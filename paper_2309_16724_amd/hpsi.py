@@ -85,11 +85,13 @@ class Plan:
         return out
 
     def davidson(self, psi0, tol=1e-8, max_iter=1000, m_max=24, floor=1e-8, stream=None,
-                 check=True, mlp=None, verbose=0):
+                 check=True, mlp=None, verbose=0, mlp_patience=0):
         """Lowest eigenpair of every problem by the library's Davidson solver.
 
         psi0: CUDA float64 tensor (starting vectors, not modified); mlp: a
-        precond.MLP for the learned preconditioner, else the diagonal one.
+        precond.MLP for the learned preconditioner, else the diagonal one;
+        mlp_patience: iterations without a new smallest residual after which a
+        problem's learned steps stop (0: the library default).
         Returns (energy, psi, stats dict): energy is the Ritz value of a
         single-problem plan, else the list of Ritz values, one per problem.
         With check=False a non-converged run returns its best pairs instead of
@@ -99,7 +101,7 @@ class Plan:
         psi = psi0.detach().clone().contiguous()
         ev = (ctypes.c_double * len(self.problems))()
         st = B.DavStats()
-        opts = self._dav_opts(tol, max_iter, m_max, floor, mlp, verbose)
+        opts = self._dav_opts(tol, max_iter, m_max, floor, mlp, verbose, mlp_patience)
         rc = self.lib.dmrg_davidson(self.handle, ctypes.c_void_p(psi.data_ptr()), ev,
                                     ctypes.byref(opts), ctypes.byref(st), self._stream(stream))
         if rc != 0 and (check or rc != -7):
@@ -109,10 +111,10 @@ class Plan:
         return (evs[0] if len(evs) == 1 else evs), psi, st.as_dict()
 
     @staticmethod
-    def _dav_opts(tol, max_iter, m_max, floor, mlp=None, verbose=0):
+    def _dav_opts(tol, max_iter, m_max, floor, mlp=None, verbose=0, mlp_patience=0):
         if mlp is None:
-            return B.DavOpts(tol, max_iter, m_max, B.DMRG_PRECOND_DIAG, verbose, floor, None)
-        return B.DavOpts(tol, max_iter, m_max, B.DMRG_PRECOND_MLP, verbose, floor, mlp.handle)
+            return B.DavOpts(tol, max_iter, m_max, B.DMRG_PRECOND_DIAG, verbose, floor, None, mlp_patience, 0)
+        return B.DavOpts(tol, max_iter, m_max, B.DMRG_PRECOND_MLP, verbose, floor, mlp.handle, mlp_patience, 0)
 
     def collect(self, psi0, capacity, tol=1e-8, max_iter=1000, m_max=24, floor=1e-8,
                 stream=None):

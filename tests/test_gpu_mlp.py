@@ -168,6 +168,24 @@ def test_guard_falls_back_on_corrupted_weights(torch):
     net.free()
 
 
+def test_patience_switches_a_stalling_network_off(torch):
+    """A network with large random weights gives finite steps that pass the
+    guard yet need not help; with a short patience its learned steps are
+    switched off and the solve still reaches the diagonal run's energy."""
+    from paper_2309_16724_amd.precond import MLP
+    prob = random_problem(8, 8, 0, 9, D=40)
+    net = MLP(W, seed=0)
+    net.set_params(mlp_params(2, W, 11, out_scale=10.0) * 3.0)
+    e0, _, s0 = _dav_gpu(torch, prob)
+    e1, _, s1 = _dav_gpu(torch, prob, mlp=net, mlp_patience=2)
+    _say("diagonal %d its; stalling network %d its, switched %d, fallbacks %d"
+         % (s0["iters"], s1["iters"], s1["switched"], s1["fallbacks"]))
+    assert s0["switched"] == 0
+    assert s1["converged"] == 1 and s1["switched"] == 1
+    assert abs(e1 - e0) < 1e-8
+    net.free()
+
+
 TRAIN = [(8, 8, 0, s, 40, True) for s in (20, 21, 22, 23)] + [(7, 7, 1, s, 30, False) for s in (24, 25)]
 HELD_OUT = [("random", (8, 8, 0, 9), dict(D=40)), ("random", (7, 7, 1, 6), dict(D=30, cap=False)),
             ("exact", (8, 8, 0, 0), {}), ("random", (8, 8, 0, 30), dict(D=40)),
