@@ -40,99 +40,109 @@ __device__ inline int seg_of(const int64_t *off, int nseg, int64_t i) {
   return lo;
 }
 
-// MODE 0: rows from x[n][2] (optionally gathered), g out, optional activations.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Output row (within a wavefront's 16) of accumulator element r held by lane
+// group q = lane / 16 in v_mfma_f32_16x16x4f32; the column is lane % 16.
+// Operands: A[lane % 16][lane / 16], B[lane / 16][lane % 16].
+__device__ constexpr int mfma_row(int q, int r) { return 4 * q + r; }
+
+// Features (x0, x1) and, in MODE 1, the diagonal step td of row i.
+template <int MODE>
+__device__ inline void row_inputs(const FwdArgs &A, int64_t i, float &f0, float &f1, double &td) {
+  f0 = f1 = 0.0f;
+  td = 0.0;
+  if (i >= A.n) return;
+  if (MODE == 0) {
+    f0 = A.x[i * MLP_IN];
+    f1 = A.x[i * MLP_IN + 1];
+  } else {
+    const int s = seg_of(A.seg_off, A.nseg, i);
+    const double den = A.d[i] - A.theta[s];
+    td = -A.r[i] / floored(den, A.floor_);
+    f0 = (float)asinh(den / A.sigma[s]);
+    f1 = (float)A.f1[s];
+  }
+}
+
+// MODE 0: rows from x[n][2], g out, optional activations z1, z2 (training).
 // MODE 1: rows from Davidson vectors; t[i] = td_i (1 + g_i), td = -r/(d - theta).
+// Each wavefront takes 16 rows.  Layer 1 goes straight into registers: lane
+// l holds relu(z1) of row l % 16 at k = 4j + l / 16, j < W/4 -- exactly the A
+// operand of the K steps of layer 2, which runs on v_mfma_f32_16x16x4f32 over
+// W/16 column blocks with W2 staged through LDS in chunks of 32 rows shared
+// by the work group's four wavefronts.  Layer 3 reduces over the 16 lanes of
+// each output row.
 template <int W, int MODE>
 __global__ void __launch_bounds__(NT) mlp_fwd_kernel(const FwdArgs A) {
-  constexpr int CPT = W / 16;          // columns per thread
-  constexpr int KC = W < 32 ? W : 32;  // W2 rows per LDS chunk
-  __shared__ float xs[MR][MLP_IN];
-  __shared__ float h1[MR][W + 1];
+  static_assert(W % 32 == 0 && MR == 64 && NT == 256, "64 rows of 4 wavefronts, W2 chunks of 32 rows");
+  constexpr int NB = W / 16, KS = W / 4, KC = 32;
   __shared__ float w2c[KC][W];
-  __shared__ double tds[MR];
   const POff o = poff(W);
   const float *__restrict__ p = A.params;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  const int64_t row0 = (int64_t)blockIdx.x * MR;
-  if (tid < MR) {
-    const int64_t i = row0 + tid;
-    float f0 = 0.0f, f1 = 0.0f;
-    double td = 0.0;
-    if (i < A.n) {
-      if (MODE == 0) {
-        f0 = A.x[i * MLP_IN];
-        f1 = A.x[i * MLP_IN + 1];
-      } else {
-        const int s = seg_of(A.seg_off, A.nseg, i);
-        const double den = A.d[i] - A.theta[s];
-        td = -A.r[i] / floored(den, A.floor_);
-        f0 = (float)asinh(den / A.sigma[s]);
-        f1 = (float)A.f1[s];
-      }
-    }
-    xs[tid][0] = f0;
-    xs[tid][1] = f1;
-    tds[tid] = td;
-  }
-  __syncthreads();
-  // layer 1
-  for (int c = tid; c < W; c += NT) {
-    const float w0 = p[o.W1 + c], w1 = p[o.W1 + W + c], bb = p[o.b1 + c];
-    for (int r = 0; r < MR; r++) {
-      const float z = bb + xs[r][0] * w0 + xs[r][1] * w1;
-      if (A.z1 && row0 + r < A.n) A.z1[(row0 + r) * W + c] = z;
-      h1[r][c] = fmaxf(z, 0.0f);
-    }
-  }
-  // layer 2: thread (tx, ty) owns rows 4ty..4ty+3, columns tx + 16j
-  float acc[4][CPT];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, q = lane >> 4;
+  const int64_t base = (int64_t)blockIdx.x * MR + wave * 16;
+  const int64_t arow = base + l16;
+  float f0, f1;
+  double td_unused;
+  row_inputs<MODE>(A, arow, f0, f1, td_unused);
+  float h[KS];
 #pragma unroll
-  for (int j = 0; j < CPT; j++) {
-    const float bj = p[o.b2 + tx + 16 * j];
-#pragma unroll
-    for (int i = 0; i < 4; i++) acc[i][j] = bj;
+  for (int j = 0; j < KS; j++) {
+    const int k = 4 * j + q;
+    const float z = p[o.b1 + k] + f0 * p[o.W1 + k] + f1 * p[o.W1 + W + k];
+    if (MODE == 0 && A.z1 && arow < A.n) A.z1[arow * W + k] = z;
+    h[j] = fmaxf(z, 0.0f);
   }
+  v4f acc[NB];
+#pragma unroll
+  for (int bj = 0; bj < NB; bj++) acc[bj] = (v4f){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
   for (int k0 = 0; k0 < W; k0 += KC) {
     __syncthreads();
     for (int e = tid; e < KC * W; e += NT) w2c[e / W][e % W] = p[o.W2 + (int64_t)(k0 + e / W) * W + e % W];
     __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < KC; kk++) {
-      float a[4], b[CPT];
 #pragma unroll
-      for (int i = 0; i < 4; i++) a[i] = h1[ty * 4 + i][k0 + kk];
+    for (int kk = 0; kk < KC; kk += 4) {
+      const float a = h[(k0 + kk) / 4];
 #pragma unroll
-      for (int j = 0; j < CPT; j++) b[j] = w2c[kk][tx + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; i++)
-#pragma unroll
-        for (int j = 0; j < CPT; j++) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+      for (int bj = 0; bj < NB; bj++)
+        acc[bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, w2c[kk + q][16 * bj + l16], acc[bj], 0, 0, 0);
     }
   }
   // layer 3
-  float part[4];
+  float part[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int i = 0; i < 4; i++) {
-    part[i] = 0.0f;
-    const int64_t row = row0 + ty * 4 + i;
+  for (int bj = 0; bj < NB; bj++) {
+    const int c = 16 * bj + l16;
+    const float bb = p[o.b2 + c], w3 = p[o.w3 + c];
 #pragma unroll
-    for (int j = 0; j < CPT; j++) {
-      const int c = tx + 16 * j;
-      if (A.z2 && row < A.n) A.z2[row * W + c] = acc[i][j];
-      part[i] = fmaf(fmaxf(acc[i][j], 0.0f), p[o.w3 + c], part[i]);
+    for (int r = 0; r < 4; r++) {
+      const float z = acc[bj][r] + bb;
+      const int64_t orow = base + mfma_row(q, r);
+      if (MODE == 0 && A.z2 && orow < A.n) A.z2[orow * W + c] = z;
+      part[r] = fmaf(fmaxf(z, 0.0f), w3, part[r]);
     }
-#pragma unroll
-    for (int m = 8; m > 0; m >>= 1) part[i] += __shfl_xor(part[i], m, 16);
   }
-  if (tx == 0) {
+#pragma unroll
+  for (int r = 0; r < 4; r++)
+    for (int m = 8; m > 0; m >>= 1) part[r] += __shfl_xor(part[r], m, 16);
+  if (l16 == 0) {
     const float b3 = p[o.b3];
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
-      const int64_t row = row0 + ty * 4 + i;
-      if (row >= A.n) continue;
-      const float g = part[i] + b3;
-      if (MODE == 0) A.g[row] = g;
-      else A.t[row] = tds[ty * 4 + i] * (1.0 + (double)g);
+    for (int r = 0; r < 4; r++) {
+      const int64_t orow = base + mfma_row(q, r);
+      if (orow >= A.n) continue;
+      const float g = part[r] + b3;
+      if (MODE == 0) {
+        A.g[orow] = g;
+      } else {
+        float x0, x1;
+        double td;
+        row_inputs<1>(A, orow, x0, x1, td);
+        A.t[orow] = td * (1.0 + (double)g);
+      }
     }
   }
 }
