@@ -97,6 +97,28 @@ struct DevBuf {
   double *get(int64_t n) { return (double *)raw(sizeof(double) * n); }
 };
 
+// Page-locked host staging for the solver's small transfers (dot products
+// down, coefficients and per-problem scalars up): copies from pageable
+// memory are staged by the runtime and cost about 0.1 ms each.  Uploads are
+// copied into the arena first, so the caller's vectors may change at once;
+// the fill pointer returns to zero only after the stream has been
+// synchronised (no copy from the arena is pending then).
+struct HostStage {
+  double *p = nullptr;
+  size_t cap = 0, used = 0;
+  hipStream_t s = nullptr;
+  ~HostStage() {
+    if (!p) return;
+    (void)hipStreamSynchronize(s);   // an early return may leave a copy pending
+    (void)hipHostFree(p);
+  }
+  bool init(size_t n, hipStream_t stream) {
+    cap = n;
+    s = stream;
+    return hipHostMalloc((void **)&p, sizeof(double) * n, hipHostMallocDefault) == hipSuccess;
+  }
+};
+
 #define HIPCHK(x)                                                                    \
   do {                                                                               \
     hipError_t e_ = (x);                                                             \
@@ -208,12 +230,18 @@ static int solve(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts
   HIPCHK(hipEventCreate(&e1));
   double t_hpsi = 0.0;
   int n_hpsi = 0;
+  HostStage hs, up;
+  if (!hs.init((size_t)np * (M + 2), s) || !up.init((size_t)np * (4 * M + 16), s)) {
+    set_error("hipHostMalloc failed in Davidson");
+    return DMRG_ENOMEM;
+  }
   auto apply = [&](const double *x, double *y) -> int {
     HIPCHK(hipEventRecord(e0, s));
     int c = dmrg_apply_H(p, x, y, stream);
     if (c) return c;
     HIPCHK(hipEventRecord(e1, s));
     HIPCHK(hipEventSynchronize(e1));
+    up.used = 0;   // every earlier copy on the stream has completed
     float ms = 0.0f;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
     t_hpsi += ms * 1e-3;
@@ -221,20 +249,29 @@ static int solve(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts
     return DMRG_OK;
   };
   // per-problem dot products of m columns of Vs with x: host out[k * m + j]
-  std::vector<double> hout((size_t)np * (M + 2));
+  double *const hout = hs.p;
+  // upload of cnt doubles through the page-locked arena
+  auto put = [&](double *dst, const double *src, size_t cnt) -> int {
+    if (up.used + cnt > up.cap) {
+      HIPCHK(hipStreamSynchronize(s));
+      up.used = 0;
+    }
+    double *h = up.p + up.used;
+    std::memcpy(h, src, sizeof(double) * cnt);
+    up.used += cnt;
+    HIPCHK(hipMemcpyAsync(dst, h, sizeof(double) * cnt, hipMemcpyHostToDevice, s));
+    return DMRG_OK;
+  };
   auto dots_host = [&](const double *Vs, int m, const double *x) -> int {
     vec_dots(X, Vs, n, m, x, dout, stream);
-    HIPCHK(hipMemcpyAsync(hout.data(), dout, sizeof(double) * np * m, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hout, dout, sizeof(double) * np * m, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    up.used = 0;
     return DMRG_OK;
   };
-  auto put_vec = [&](const std::vector<double> &v) -> int {
-    HIPCHK(hipMemcpyAsync(dvec, v.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
-    return DMRG_OK;
-  };
+  auto put_vec = [&](const std::vector<double> &v) -> int { return put(dvec, v.data(), (size_t)np); };
   auto put_coef = [&](const std::vector<double> &cf) -> int {   // np x M row-major
-    HIPCHK(hipMemcpyAsync(dcoef, cf.data(), sizeof(double) * np * M, hipMemcpyHostToDevice, s));
-    return DMRG_OK;
+    return put(dcoef, cf.data(), (size_t)np * M);
   };
   if ((rc = dmrg_diag_H(p, diag, stream))) return rc;
   {
@@ -356,9 +393,9 @@ static int solve(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts
         sig[k] = sigma_of(k, P[k].theta);
         f1[k] = std::log10(std::max(P[k].rnorm, 1e-300)) / 8.0;
       }
-      HIPCHK(hipMemcpyAsync(dth, th.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
-      HIPCHK(hipMemcpyAsync(dsig, sig.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
-      HIPCHK(hipMemcpyAsync(df1, f1.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
+      if ((rc = put(dth, th.data(), (size_t)np)) || (rc = put(dsig, sig.data(), (size_t)np)) ||
+          (rc = put(df1, f1.data(), (size_t)np)))
+        return rc;
       FwdArgs A{};
       A.params = opt.mlp->p;
       A.n = n;
@@ -374,9 +411,9 @@ static int solve(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts
       launch_mlp_forward(opt.mlp->width, 1, A, stream);
       HIPCHK(hipGetLastError());
       if ((rc = dots_host(tm, 1, tm))) return rc;
-      std::vector<double> mm(hout.begin(), hout.begin() + np);
+      std::vector<double> mm(hout, hout + np);
       if ((rc = dots_host(tm, 1, t))) return rc;
-      std::vector<double> mt(hout.begin(), hout.begin() + np);
+      std::vector<double> mt(hout, hout + np);
       if ((rc = dots_host(t, 1, t))) return rc;
       std::vector<double> flag(np, 0.0);
       for (int k = 0; k < np; k++) {
@@ -387,7 +424,7 @@ static int solve(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts
         flag[k] = ok ? 1.0 : 0.0;
         fallbacks += !ok;
       }
-      HIPCHK(hipMemcpyAsync(dflag, flag.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
+      if ((rc = put(dflag, flag.data(), (size_t)np))) return rc;
       vec_select(X, dflag, tm, t, stream);
       HIPCHK(hipStreamSynchronize(s));
     }

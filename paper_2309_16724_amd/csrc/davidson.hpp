@@ -5,7 +5,7 @@
 
 namespace dmrg {
 
-constexpr int64_t VCHUNK = 4096;   // vector elements per chunk
+constexpr int64_t VCHUNK = 1024;   // vector elements per chunk (enough chunks to fill the chip)
 
 struct VChunk {
   int64_t i0, i1;   // element range, inside one segment

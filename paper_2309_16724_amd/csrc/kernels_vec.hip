@@ -10,23 +10,43 @@ namespace dmrg {
 constexpr int VB = 256;          // threads per block
 
 // part[c * m + j] = sum_{i in chunk c} V[j * ldv + i] * x[i], j < m
+static_assert(VCHUNK % VB == 0 && VCHUNK / VB <= 8, "a thread holds VCHUNK / VB elements of x");
+// part[c * m + j] = sum over chunk c of V[j * ldv + i] x[i]: x stays in
+// registers, each column is reduced within the wavefront by shuffles, and the
+// four wavefronts' partials are added in wave order after one barrier (fixed
+// order throughout: reproducible bit for bit).
 __global__ void __launch_bounds__(VB) sdots_kernel(const VChunk *__restrict__ chunks, int nchunks,
                                                     const double *__restrict__ V, int64_t ldv, int m,
                                                     const double *__restrict__ x, double *__restrict__ part) {
-  __shared__ double red[VB];
+  constexpr int PT = VCHUNK / VB, NW = VB / 64;
+  __shared__ double red[NW][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
     const VChunk C = chunks[c];
-    for (int j = 0; j < m; j++) {
-      double acc = 0.0;
-      const double *v = V + (int64_t)j * ldv;
-      for (int64_t i = C.i0 + threadIdx.x; i < C.i1; i += VB) acc += v[i] * x[i];
-      red[threadIdx.x] = acc;
-      __syncthreads();
-      for (int s = VB / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
+    double xv[PT];
+    int64_t idx[PT];
+#pragma unroll
+    for (int e = 0; e < PT; e++) {
+      idx[e] = C.i0 + threadIdx.x + (int64_t)e * VB;
+      xv[e] = idx[e] < C.i1 ? x[idx[e]] : 0.0;
+    }
+    for (int j0 = 0; j0 < m; j0 += 64) {
+      const int jn = min(64, m - j0);
+      for (int jj = 0; jj < jn; jj++) {
+        const double *v = V + (int64_t)(j0 + jj) * ldv;
+        double acc = 0.0;
+#pragma unroll
+        for (int e = 0; e < PT; e++)
+          if (idx[e] < C.i1) acc += v[idx[e]] * xv[e];
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (lane == 0) red[wave][jj] = acc;
       }
-      if (threadIdx.x == 0) part[(int64_t)c * m + j] = red[0];
+      __syncthreads();
+      if (threadIdx.x < jn) {
+        double s = 0.0;
+        for (int w = 0; w < NW; w++) s += red[w][threadIdx.x];
+        part[(int64_t)c * m + j0 + threadIdx.x] = s;
+      }
       __syncthreads();
     }
   }
@@ -52,8 +72,17 @@ __global__ void __launch_bounds__(VB) scombo_kernel(const VChunk *__restrict__ c
     const VChunk C = chunks[c];
     const double *cf = coef + (int64_t)C.seg * ldc;
     for (int64_t i = C.i0 + threadIdx.x; i < C.i1; i += VB) {
-      double acc = 0.0;
-      for (int j = 0; j < m; j++) acc += cf[j] * V[(int64_t)j * ldv + i];
+      // four columns per round: independent loads in flight, fixed order
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int j = 0;
+      for (; j + 3 < m; j += 4) {
+        a0 += cf[j] * V[(int64_t)j * ldv + i];
+        a1 += cf[j + 1] * V[(int64_t)(j + 1) * ldv + i];
+        a2 += cf[j + 2] * V[(int64_t)(j + 2) * ldv + i];
+        a3 += cf[j + 3] * V[(int64_t)(j + 3) * ldv + i];
+      }
+      for (; j < m; j++) a0 += cf[j] * V[(int64_t)j * ldv + i];
+      const double acc = (a0 + a1) + (a2 + a3);
       y[i] = (beta == 0.0 ? 0.0 : beta * y[i]) + sign * acc;
     }
   }
