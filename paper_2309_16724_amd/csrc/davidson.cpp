@@ -48,6 +48,15 @@ void jacobi_eigh(int m, const double *A, double *w, double *Z) {
       for (int q = p + 1; q < m; q++) {
         double apq = a[p * m + q];
         if (apq == 0.0) continue;
+        // after a few sweeps an element below the rounding of both diagonal
+        // entries is set to zero (else rounding keeps the off-diagonal mass
+        // above any relative threshold and every solve runs all sweeps)
+        const double g = 100.0 * std::fabs(apq);
+        if (sweep > 3 && std::fabs(a[p * m + p]) + g == std::fabs(a[p * m + p]) &&
+            std::fabs(a[q * m + q]) + g == std::fabs(a[q * m + q])) {
+          a[p * m + q] = a[q * m + p] = 0.0;
+          continue;
+        }
         double theta = (a[q * m + q] - a[p * m + p]) / (2.0 * apq);
         double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
         double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
