@@ -182,8 +182,11 @@ __device__ __forceinline__ void item_f64(const Tile &T, const Seg *__restrict__ 
 
 // One launch per stage: every wavefront takes tiles from the stage's
 // cost-sorted list and runs the work item of the tile's shape.
+// Three wavefronts per SIMD (at most 168 registers, no spills): more loads in
+// flight per SIMD than the two that the register use of an unbounded build
+// allows; four spill.
 template <int STAGE>
-__global__ void __launch_bounds__(64 * WAVES) stage_f64_kernel(const Tile *__restrict__ tiles,
+__global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(3, 3))) stage_f64_kernel(const Tile *__restrict__ tiles,
                                                                 const Seg *__restrict__ segs, int ntiles,
                                                                 const double *const *__restrict__ bases,
                                                                 const double *__restrict__ psi,
