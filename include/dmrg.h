@@ -51,7 +51,11 @@
  * Ownership: the caller owns every array.  Host arrays are read during
  * dmrg_build_tasks only.  Operator data (ldata/rdata) are DEVICE arrays that
  * the plan references until dmrg_plan_free; psi/hpsi are device arrays
- * borrowed for one call.  The plan owns its descriptors and workspace.
+ * borrowed for one call.  The plan owns its descriptors, operator copies,
+ * slices and stripe workspace: device memory taken with hipMalloc by
+ * dmrg_build_tasks (the stripe workspace bounded by opts.workspace_bytes)
+ * and by dmrg_davidson for its basis, all returned by dmrg_plan_free or at
+ * the end of the solve.
  * Errors: negative status codes; no exception crosses the ABI; on error the
  * outputs are unspecified and dmrg_last_error() (thread-local) describes it.
  * After DMRG_EHIP the plan must be freed.  A plan is not reentrant.
