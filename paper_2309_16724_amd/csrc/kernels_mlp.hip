@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(NT) out_grad_kernel(const float *__restrict__ 
   red[threadIdx.x] = e2;
   __syncthreads();
   for (int s = NT / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
   if (threadIdx.x == 0) lpart[blockIdx.x] = red[0];

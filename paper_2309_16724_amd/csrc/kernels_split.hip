@@ -164,7 +164,6 @@ void launch_slices(const SliceJob *jobs, int njobs, int nslices, const double *c
 
 // ------------------------------------------------------------------ split products
 // slice buffers live in device global memory: global (not flat) loads
-typedef const v8bf __attribute__((address_space(1))) *gv8ptr;
 typedef const void __attribute__((address_space(1))) *gvptr;
 typedef void __attribute__((address_space(3))) *lvptr;
 typedef const v8bf __attribute__((address_space(3))) *lv8ptr;

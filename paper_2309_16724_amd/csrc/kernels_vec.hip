@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(VB) sdots_kernel(const VChunk *__restrict__ ch
         if (lane == 0) red[wave][jj] = acc;
       }
       __syncthreads();
-      if (threadIdx.x < jn) {
+      if ((int)threadIdx.x < jn) {
         double s = 0.0;
         for (int w = 0; w < NW; w++) s += red[w][threadIdx.x];
         part[(int64_t)c * m + j0 + threadIdx.x] = s;
