@@ -294,6 +294,11 @@ int dmrg_debug_plan_host_apply(const dmrg_problem_t *prob, const double *psi, do
  * summed K) written to out[4 * i ..] for i < cap; returns the number of tiles
  * (call with out = NULL to size) or a negative status. */
 int64_t dmrg_debug_plan_tiles(const dmrg_problem_t *prob, int32_t stage, int64_t *out, int64_t cap);
+/* Test-only: the host eigensolver dmrg_davidson applies to its projected
+ * matrix (cyclic Jacobi).  A: m x m symmetric, row-major, HOST, 1 <= m <= 64;
+ * w: m eigenvalues ascending; Z: m x m row-major, eigenvector j in column j.
+ * Returns DMRG_EINVAL for m out of range or NULL pointers. */
+int dmrg_debug_jacobi(int32_t m, const double *A, double *w, double *Z);
 
 #ifdef __cplusplus
 }

@@ -102,6 +102,7 @@ def load(path=None):
     L.dmrg_wigner_6j.argtypes = [ctypes.c_int] * 6
     L.dmrg_wigner_9j.argtypes = [ctypes.c_int] * 9
     L.dmrg_ctilde.argtypes = [ctypes.c_int] * 9
+    L.dmrg_debug_jacobi.argtypes = [c_i32, c_vp, c_vp, c_vp]
     L.dmrg_debug_host_apply.argtypes = [ctypes.POINTER(ProblemT), c_vp, c_vp,
                                         ctypes.POINTER(PlanStats)]
     if hasattr(L, "dmrg_build_tasks"):
@@ -190,6 +191,18 @@ def debug_plan_host_apply(prob, psi, workspace_bytes=0, lib=None, precision=0, n
     check(L.dmrg_debug_plan_host_apply(ctypes.byref(args.s), x.ctypes.data, y.ctypes.data,
                                        ctypes.byref(opts), ctypes.byref(st)), L)
     return y, st.as_dict()
+
+
+def debug_jacobi(A, lib=None):
+    """Test-only: eigenvalues (ascending) and eigenvectors (columns) of a
+    symmetric m x m matrix by the Davidson solver's host Jacobi routine."""
+    L = lib or load()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    m = A.shape[0]
+    w = np.zeros(m)
+    Z = np.zeros((m, m))
+    check(L.dmrg_debug_jacobi(m, A.ctypes.data, w.ctypes.data, Z.ctypes.data), L)
+    return w, Z
 
 
 def debug_host_apply(prob, psi, lib=None):

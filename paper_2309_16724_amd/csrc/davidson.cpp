@@ -587,6 +587,15 @@ static int solve(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts
   return DMRG_OK;
 }
 
+extern "C" int dmrg_debug_jacobi(int32_t m, const double *A, double *w, double *Z) {
+  if (m < 1 || m > 64 || !A || !w || !Z) {
+    set_error("dmrg_debug_jacobi: 1 <= m <= 64 and non-NULL arrays");
+    return DMRG_EINVAL;
+  }
+  dmrg::jacobi_eigh(m, A, w, Z);
+  return DMRG_OK;
+}
+
 extern "C" int dmrg_davidson(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts_t *o,
                              dmrg_dav_stats_t *st, void *stream) {
   if (!p || !psi || !evals) { set_error("null argument"); return DMRG_EINVAL; }
