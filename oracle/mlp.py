@@ -108,11 +108,11 @@ def features(diag, r, theta):
     return np.stack([np.arcsinh(den / sigma), np.full(den.size, np.log10(rn) / 8.0)], axis=1)
 
 
-def diagonal_step(diag, r, theta, floor=1e-8):
+def diagonal_step(diag, r, theta, floor=1e-3):
     return -np.asarray(r, float) / floored(np.asarray(diag, float) - theta, floor)
 
 
-def training_rows(diag, r, u, theta, psi_star, floor=1e-8):
+def training_rows(diag, r, u, theta, psi_star, floor=1e-3):
     """(x, a, b) of one Davidson iteration given the converged vector."""
     ts = psi_star / (u @ psi_star) - u
     s = np.sqrt(ts.size) / np.linalg.norm(ts)
@@ -122,7 +122,7 @@ def training_rows(diag, r, u, theta, psi_star, floor=1e-8):
     return features(diag, r, theta), a * w, b * w
 
 
-def mlp_step(p, width, diag, r, theta, floor=1e-8):
+def mlp_step(p, width, diag, r, theta, floor=1e-3):
     """Learned correction t = td (1 + g(x)) of one problem."""
     g, _ = forward(p, features(diag, r, theta), width)
     return diagonal_step(diag, r, theta, floor) * (1.0 + g)

@@ -102,7 +102,8 @@ def test_row_weight_cap():
     e = np.array([0.0, 0.5, 0.5, 0.5])
     d = np.array([1.0, 2.0, 0.5 + 1e-6, 3.0])     # element 2: denominator 1e-6
     r = np.array([0.0, 1.0, 1.0, 1.0])
-    x, a, b = mlp.training_rows(d, r, u, 0.5, (u + e) / np.linalg.norm(u + e))
+    # floor below the 1e-6 denominator, so the unfloored step is the raw row
+    x, a, b = mlp.training_rows(d, r, u, 0.5, (u + e) / np.linalg.norm(u + e), floor=1e-8)
     s = np.sqrt(4) / np.linalg.norm(e)
     raw_a = -r / (d - 0.5) * s
     assert abs(abs(a[2]) - mlp.A_MAX) < 1e-12
