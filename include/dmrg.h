@@ -185,7 +185,9 @@ typedef struct {
   int32_t m_max;            /* subspace size, 3..64 (24 by default)         */
   int32_t precond;          /* DMRG_PRECOND_DIAG or DMRG_PRECOND_MLP         */
   int32_t verbose;          /* > 0: a progress line on stderr every 25 iterations */
-  double floor;             /* preconditioner denominator floor, e.g. 1e-8   */
+  double floor;             /* preconditioner denominator floor (1e-3 with no
+                               options; 1e-8 lets a few elements with
+                               d ~ theta dominate every correction)         */
   const dmrg_mlp_t *mlp;    /* network for DMRG_PRECOND_MLP, else NULL       */
   int32_t mlp_patience;     /* learned steps of a problem stop after this many
                                iterations without a new smallest residual

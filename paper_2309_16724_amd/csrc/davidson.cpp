@@ -164,7 +164,7 @@ struct Collect {
 }  // namespace
 
 static int check_opts(const dmrg_dav_opts_t *o, dmrg_dav_opts_t *opt) {
-  *opt = {1e-8, 1000, 24, DMRG_PRECOND_DIAG, 0, 1e-8, nullptr, 0, 0};
+  *opt = {1e-8, 1000, 24, DMRG_PRECOND_DIAG, 0, 1e-3, nullptr, 0, 0};
   if (o) *opt = *o;
   if (opt->m_max < 3 || opt->m_max > 64 || opt->max_iter < 1 || !(opt->tol > 0.0) || !(opt->floor > 0.0) ||
       opt->mlp_patience < 0) {
