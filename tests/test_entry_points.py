@@ -22,3 +22,21 @@ def test_bench_refuses_several_gpus():
 def test_missing_library_raises(tmp_path):
     with pytest.raises(RuntimeError, match="not built"):
         B.load(str(tmp_path / "libdmrg_hpsi.so"))
+
+
+def test_davidson_defaults_match_the_oracle():
+    """The device-versus-oracle Davidson tests run both sides with their
+    defaults: the preconditioner floor, tolerance and subspace size must
+    agree (reading of the Davidson details, floor 1e-3)."""
+    import inspect
+    from oracle.davidson import davidson as odav
+    from oracle import mlp as omlp
+    from paper_2309_16724_amd.hpsi import Plan
+    lib = inspect.signature(Plan.davidson).parameters
+    ref = inspect.signature(odav).parameters
+    for k in ("floor", "tol", "m_max", "max_iter"):
+        assert lib[k].default == ref[k].default, k
+    col = inspect.signature(Plan.collect).parameters
+    assert col["floor"].default == ref["floor"].default
+    for f in (omlp.diagonal_step, omlp.training_rows, omlp.mlp_step):
+        assert inspect.signature(f).parameters["floor"].default == ref["floor"].default
