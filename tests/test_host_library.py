@@ -162,8 +162,9 @@ def test_davidson_jacobi_matches_numpy_and_terminates(lib, m):
     """The projected-matrix eigensolver of the Davidson solver: eigenvalues
     against numpy's, residuals, orthonormality, ascending order; nearly
     diagonal matrices (as late in a solve) and clustered eigenvalues too.
-    A solve of m = 24 must not run the full sweep limit (it took 4 ms when
-    rounding kept the off-diagonal mass above the stopping threshold)."""
+    A solve of m = 24 must not run the full sweep limit (it took 4.3 ms when
+    rounding kept the off-diagonal mass above the stopping threshold; it
+    takes about 0.15 ms)."""
     import time
     rng = np.random.default_rng(m)
     cases = []
@@ -184,7 +185,7 @@ def test_davidson_jacobi_matches_numpy_and_terminates(lib, m):
         t0 = time.perf_counter()
         for _ in range(20):
             B.debug_jacobi(A, lib=lib)
-        assert (time.perf_counter() - t0) / 20 < 2e-3
+        assert (time.perf_counter() - t0) / 20 < 3e-3
 
 
 def test_davidson_jacobi_rejects_bad_sizes(lib):
