@@ -233,6 +233,8 @@ def main():
     ap.add_argument("--no-davidson", action="store_true", help="time H.psi only (large workloads)")
     ap.add_argument("--no-split-davidson", action="store_true",
                     help="skip the Davidson solve with split-precision H.psi")
+    ap.add_argument("--dav-floor", type=float, default=None,
+                    help="preconditioner denominator floor of the Davidson solves (library default if omitted)")
     ap.add_argument("--dav-verbose", action="store_true",
                     help="Davidson progress lines on stderr every 25 iterations (long solves)")
     ap.add_argument("--hpsi-only", choices=("fp64", "split"),
@@ -314,9 +316,11 @@ def main():
         x0 = torch.from_numpy(x_np).cuda()
         torch.cuda.synchronize()
         td = time.time()
-        e_dav, _, dst = plan.davidson(x0, tol=1e-8, verbose=int(args.dav_verbose))
+        fk = {} if args.dav_floor is None else {"floor": args.dav_floor}
+        e_dav, _, dst = plan.davidson(x0, tol=1e-8, check=False, verbose=int(args.dav_verbose), **fk)
         t_dav = time.time() - td
         davidson = {"s_per_step": t_dav, "iterations": dst["iters"], "n_hpsi": dst["n_hpsi"],
+                    "converged": dst["converged"], "floor": args.dav_floor,
                     "residual": dst["residual"], "energy": e_dav, "precision": "fp64",
                     "preconditioner": "diagonal", "t_hpsi_s": dst["t_hpsi_s"]}
         if not args.no_mlp:
@@ -324,7 +328,7 @@ def main():
             print("# learned preconditioner: %s" % json.dumps(info), file=sys.stderr, flush=True)
             torch.cuda.synchronize()
             tm = time.time()
-            e_mlp, _, mst = plan.davidson(x0, tol=1e-8, mlp=net, check=False, verbose=int(args.dav_verbose))
+            e_mlp, _, mst = plan.davidson(x0, tol=1e-8, mlp=net, check=False, verbose=int(args.dav_verbose), **fk)
             t_mlp = time.time() - tm
             net.free()
             learned = {"s_per_step": t_mlp, "iterations": mst["iters"], "n_hpsi": mst["n_hpsi"],
@@ -337,7 +341,7 @@ def main():
             splan = Plan(prob, precision=1, n_slices=5, flags=plan_flags)
             torch.cuda.synchronize()
             tsd = time.time()
-            e_sp, _, sst = splan.davidson(x0, tol=1e-8, check=False, verbose=int(args.dav_verbose))
+            e_sp, _, sst = splan.davidson(x0, tol=1e-8, check=False, verbose=int(args.dav_verbose), **fk)
             split_dav = {"s_per_step": time.time() - tsd, "iterations": sst["iters"],
                          "converged": sst["converged"], "residual": sst["residual"],
                          "energy_minus_fp64": e_sp - e_dav}
