@@ -5,7 +5,10 @@ diagonalisation (Sec. II) and fixes no details; the reading used here:
 block size 1; subspace of at most m_max = 24 vectors, thick restart to the
 current and previous Ritz vectors; two-pass classical Gram-Schmidt; the
 correction t = -r / (diag - theta) with the denominator's magnitude floored
-at 1e-3; convergence when ||r||_2 <= tol for the normalised Ritz vector.
+at floor * sigma, sigma the root mean square of diag - theta over the vector
+(floor = 1e-2: a relative floor, so that the cap on the few elements with
+diag ~ theta scales with the spread of the diagonal); convergence when
+||r||_2 <= tol for the normalised Ritz vector.
 Pinned in tests/test_oracle_davidson.py against dense eigh.
 """
 import numpy as np
@@ -17,7 +20,16 @@ def _orth(V, t, passes=2):
     return t
 
 
-def davidson(hop, diag, x0, tol=1e-8, max_iter=1000, m_max=24, floor=1e-3, precond=None,
+FLOOR = 1e-2
+
+
+def floor_abs(diag, theta, floor=FLOOR):
+    """Absolute denominator floor: floor times the RMS of diag - theta."""
+    den = np.asarray(diag, dtype=float) - theta
+    return floor * np.sqrt(np.mean(den * den))
+
+
+def davidson(hop, diag, x0, tol=1e-8, max_iter=1000, m_max=24, floor=FLOOR, precond=None,
              record=None):
     """Return (theta, u, n_iter, residual_norm, n_hop).
 
@@ -47,7 +59,8 @@ def davidson(hop, diag, x0, tol=1e-8, max_iter=1000, m_max=24, floor=1e-3, preco
             record.append((r.copy(), u.copy(), theta))
         if precond is None:
             den = diag - theta
-            den = np.where(np.abs(den) < floor, np.where(den < 0, -floor, floor), den)
+            fl = floor_abs(diag, theta, floor)
+            den = np.where(np.abs(den) < fl, np.where(den < 0, -fl, fl), den)
             t = -r / den
         else:
             t = precond(r, u, theta)

@@ -62,9 +62,15 @@ SITE_MULT_STATES = [{0: 0}, {1: 1, -1: 2}, {0: 3}]
 
 
 class MBlock:
-    """M-resolved view of one block: groups (N, 2M) and expanded operators."""
+    """M-resolved view of one block: groups (N, 2M) and expanded operators.
 
-    def __init__(self, blk):
+    ``sel`` (optional) restricts every expanded operator to a set of rows of
+    each group ({group: sorted offsets}); groups missing from it take no
+    rows.  ``tensor(..., side=0)`` returns an operator's selected rows (the
+    rows an output needs); ``side=1`` its selected columns, which is what the
+    selected rows of its transpose are made of."""
+
+    def __init__(self, blk, sel=None):
         self.blk = blk
         self.sectors = blk.sectors
         self.gidx = {}      # (sector, 2M) -> (group, offset)
@@ -75,21 +81,38 @@ class MBlock:
                 o = self.gdim.get(g, 0)
                 self.gidx[(s, M2)] = (g, o)
                 self.gdim[g] = o + d
+        self.sel = sel
         self._cache = {}
+        self._by_fam = {}
+        for rec in blk.records:
+            self._by_fam.setdefault(rec[0], []).append(rec)
+
+    def rows(self, g):
+        """Selected offsets of group g (all of them without a selection)."""
+        if self.sel is None:
+            return np.arange(self.gdim[g])
+        return self.sel.get(g, np.zeros(0, dtype=np.int64))
+
+    def _pick(self, g, o, d):
+        """(positions in the selection of g, offsets within [o, o + d))."""
+        r = self.rows(g)
+        lo, hi = np.searchsorted(r, o), np.searchsorted(r, o + d)
+        return np.arange(lo, hi), r[lo:hi] - o
 
     def identity(self):
-        return {(g, g): np.eye(d) for g, d in self.gdim.items()}
+        return {(g, g): np.eye(d)[self.rows(g)] for g, d in self.gdim.items()}
 
-    def tensor(self, fam, pos, q):
-        """M-resolved component q (doubled) of family member ``pos``: {(g', g): M}."""
-        key = (fam, pos, q)
+    def tensor(self, fam, pos, q, side=0):
+        """M-resolved component q (doubled) of family member ``pos``: {(g', g): M}
+        (selected rows for side 0, selected columns for side 1)."""
+        if self.sel is None:
+            side = 0
+        key = (fam, pos, q, side)
         if key in self._cache:
             return self._cache[key]
         k2 = cat.TWO_K[fam]
         out = {}
-        for (f, b, a, off, npos) in self.blk.records:
-            if f != fam:
-                continue
+        for (f, b, a, off, npos) in self._by_fam.get(fam, ()):
             Nb, Sb, db = self.sectors[b]
             Na, Sa, da = self.sectors[a]
             R = self.blk.data[off + pos * db * da: off + (pos + 1) * db * da]
@@ -103,11 +126,24 @@ class MBlock:
                     continue
                 ga, oa = self.gidx[(a, Ma)]
                 gb, ob = self.gidx[(b, Mb)]
+                if side == 0:
+                    pi, ri = self._pick(gb, ob, db)
+                    if len(pi) == 0:
+                        continue
+                    shape = (len(self.rows(gb)), self.gdim[ga])
+                else:
+                    pi, ci = self._pick(ga, oa, da)
+                    if len(pi) == 0:
+                        continue
+                    shape = (self.gdim[gb], len(self.rows(ga)))
                 m = out.get((gb, ga))
                 if m is None:
-                    m = np.zeros((self.gdim[gb], self.gdim[ga]))
+                    m = np.zeros(shape)
                     out[(gb, ga)] = m
-                m[ob:ob + db, oa:oa + da] += c * R
+                if side == 0:
+                    m[pi, oa:oa + da] += c * R[ri, :]
+                else:
+                    m[ob:ob + db, pi] += c * R[:, ci]
         self._cache[key] = out
         return out
 
@@ -157,7 +193,11 @@ def _memo(fn):
 
 
 class Factors:
-    """Spin-orbital operators of one block, from its stored reduced families."""
+    """Spin-orbital operators of one block, from its stored reduced families.
+
+    Every method takes ``side`` last (see MBlock.tensor): side 0 gives the
+    operator's selected rows, side 1 its selected columns; a transpose
+    swaps the two."""
 
     def __init__(self, mb):
         self.mb = mb
@@ -166,50 +206,51 @@ class Factors:
     @_memo
     def T(self, name, *args):
         """Transpose (adjoint) of the operator returned by method ``name``."""
-        return op_T(getattr(self, name)(*args))
+        *a, side = args
+        return op_T(getattr(self, name)(*a, 1 - side))
 
     @_memo
-    def cre(self, x, s2):                      # a+_{x s}
-        return self.mb.tensor(cat.C, self.mb.pos(cat.C, (x,)), s2)
+    def cre(self, x, s2, side):                # a+_{x s}
+        return self.mb.tensor(cat.C, self.mb.pos(cat.C, (x,)), s2, side)
 
     @_memo
-    def ann(self, x, s2):
-        return op_T(self.cre(x, s2))
+    def ann(self, x, s2, side):
+        return op_T(self.cre(x, s2, 1 - side))
 
     @_memo
-    def cc(self, x, y, s2, t2):               # a+_{x s} a+_{y t}
+    def cc(self, x, y, s2, t2, side):         # a+_{x s} a+_{y t}
         if x > y:
-            return op_lin((-1.0, self.cc(y, x, t2, s2)))
+            return op_lin((-1.0, self.cc(y, x, t2, s2, side)))
         terms = []
         for fam, K2 in ((cat.A0, 0), (cat.A1, 2)):
             if fam == cat.A1 and x == y:
                 continue
             c = cg(1, s2, 1, t2, K2, s2 + t2)
             if c != 0.0:
-                terms.append((c, self.mb.tensor(fam, self.mb.pos(fam, (x, y)), s2 + t2)))
+                terms.append((c, self.mb.tensor(fam, self.mb.pos(fam, (x, y)), s2 + t2, side)))
         return op_lin(*terms)
 
     @_memo
-    def ca(self, x, y, s2, t2):               # a+_{x s} a_{y t}
+    def ca(self, x, y, s2, t2, side):         # a+_{x s} a_{y t}
         if x > y:
-            return op_T(self.ca(y, x, t2, s2))
+            return op_T(self.ca(y, x, t2, s2, 1 - side))
         ph = _ph(1 + t2)                       # (-1)^(1/2 + t)
         terms = []
         for fam, K2 in ((cat.B0, 0), (cat.B1, 2)):
             c = cg(1, s2, 1, -t2, K2, s2 - t2)
             if c != 0.0:
-                terms.append((ph * c, self.mb.tensor(fam, self.mb.pos(fam, (x, y)), s2 - t2)))
+                terms.append((ph * c, self.mb.tensor(fam, self.mb.pos(fam, (x, y)), s2 - t2, side)))
         return op_lin(*terms)
 
     @_memo
-    def S(self, x, s2):                        # (S_x)_s = sum (xj|kl) E_kl a_{j s}
-        t = self.mb.tensor(cat.S, self.mb.pos(cat.S, (x,)), -s2)
+    def S(self, x, s2, side):                  # (S_x)_s = sum (xj|kl) E_kl a_{j s}
+        t = self.mb.tensor(cat.S, self.mb.pos(cat.S, (x,)), -s2, side)
         return op_lin((-sqrt(2.0) * _ph(1 + s2), t))
 
     @_memo
-    def P(self, x, y, t2, s2):                 # (P_xy)_{ts} = sum (xj|yl) a_{l t} a_{j s}
+    def P(self, x, y, t2, s2, side):           # (P_xy)_{ts} = sum (xj|yl) a_{l t} a_{j s}
         if x > y:
-            return op_lin((-1.0, self.P(y, x, s2, t2)))
+            return op_lin((-1.0, self.P(y, x, s2, t2, side)))
         ph = _ph(2 + t2 + s2)                  # (-1)^(1 + t + s)
         terms = []
         for fam, K2 in ((cat.P0, 0), (cat.P1, 2)):
@@ -217,20 +258,21 @@ class Factors:
                 continue
             c = cg(1, -t2, 1, -s2, K2, -t2 - s2)
             if c != 0.0:
-                terms.append((ph * c, self.mb.tensor(fam, self.mb.pos(fam, (x, y)), -t2 - s2)))
+                terms.append((ph * c, self.mb.tensor(fam, self.mb.pos(fam, (x, y)), -t2 - s2, side)))
         return op_lin(*terms)
 
     @_memo
-    def Q(self, x, y, t2, s2):                 # (Q_xy)_{ts}
+    def Q(self, x, y, t2, s2, side):           # (Q_xy)_{ts}
         if x > y:
-            return op_T(self.Q(y, x, s2, t2))
+            return op_T(self.Q(y, x, s2, t2, 1 - side))
         terms = []
         if s2 == t2:
-            terms.append((-1.0 / sqrt(2.0), self.mb.tensor(cat.Q0, self.mb.pos(cat.Q0, (x, y)), 0)))
+            terms.append((-1.0 / sqrt(2.0),
+                          self.mb.tensor(cat.Q0, self.mb.pos(cat.Q0, (x, y)), 0, side)))
         c = cg(1, s2, 1, -t2, 2, s2 - t2)
         if c != 0.0:
             terms.append((-_ph(1 + t2) * c / sqrt(3.0),
-                          self.mb.tensor(cat.Q1, self.mb.pos(cat.Q1, (x, y)), s2 - t2)))
+                          self.mb.tensor(cat.Q1, self.mb.pos(cat.Q1, (x, y)), s2 - t2, side)))
         return op_lin(*terms)
 
 
@@ -238,17 +280,39 @@ class Factors:
 class HEff:
     """Oracle action of H_eff on reduced two-site wavefunctions."""
 
-    def __init__(self, prob):
+    def __init__(self, prob, sample=None):
+        """sample: optional {block index: (rows, cols)} of reduced output
+        elements; with it, ``apply_sample`` evaluates H_eff psi at exactly
+        those elements (rows and columns of each listed output block) and
+        every block operator is expanded only on the product-basis rows those
+        elements project from.  The arithmetic per element is the same."""
         self.prob = prob
         self.L = prob.n_orb
         self.p = prob.p
         self.mL = MBlock(prob.left)
         self.mR = MBlock(prob.right)
-        self.fL = Factors(self.mL)
-        self.fR = Factors(self.mR)
         self.blocks, self.size = psi_blocks(prob.left.sectors, prob.right.sectors,
                                             prob.n_elec, prob.two_s)
         self.M2 = prob.two_s
+        self.sample = None
+        if sample is not None:
+            self.sample = {int(b): (np.unique(np.asarray(r, dtype=np.int64)),
+                                    np.unique(np.asarray(c, dtype=np.int64)))
+                           for b, (r, c) in sample.items()}
+            selL, selR = {}, {}
+            for bi, (rows, cols) in self.sample.items():
+                b = self.blocks[bi]
+                SL, SR = prob.left.sectors[b["iL"]][1], prob.right.sectors[b["iR"]][1]
+                for ML in range(SL, -SL - 1, -2):
+                    g, o = self.mL.gidx[(b["iL"], ML)]
+                    selL.setdefault(g, set()).update((o + rows).tolist())
+                for MR in range(SR, -SR - 1, -2):
+                    g, o = self.mR.gidx[(b["iR"], MR)]
+                    selR.setdefault(g, set()).update((o + cols).tolist())
+            self.mL.sel = {g: np.array(sorted(v), dtype=np.int64) for g, v in selL.items()}
+            self.mR.sel = {g: np.array(sorted(v), dtype=np.int64) for g, v in selR.items()}
+        self.fL = Factors(self.mL)
+        self.fR = Factors(self.mR)
         self._terms = None
 
     # ------------------------------------------------------- partitions
@@ -267,7 +331,7 @@ class HEff:
         if pt in (1, 2):
             return (pt, site_cre(s2) if dagger else site_ann(s2), 1)
         f = self.fL if pt == 0 else self.fR
-        return (pt, f.cre(x, s2) if dagger else f.T("cre", x, s2), 1)
+        return (pt, f.cre(x, s2, 0) if dagger else f.T("cre", x, s2, 0), 1)
 
     # ------------------------------------------------------- term list
     def terms(self):
@@ -295,8 +359,8 @@ class HEff:
             for x in outs:
                 for s in spins:
                     g = "S_L" if X == 0 else "S_R"
-                    yield 1.0, [self.single(x, s, True), (X, f.S(x, s), 1)], g
-                    yield 1.0, [(X, f.T("S", x, s), 1), self.single(x, s, False)], g + "+"
+                    yield 1.0, [self.single(x, s, True), (X, f.S(x, s, 0), 1)], g
+                    yield 1.0, [(X, f.T("S", x, s, 0), 1), self.single(x, s, False)], g + "+"
         # two-index complementary P, Q (n_X = 2)
         for X, f, outs in ((0, self.fL, list(range(p, L)) if p > 0 else []),
                            (3, self.fR, list(range(0, p + 2)) if p + 2 < L else [])):
@@ -307,15 +371,15 @@ class HEff:
                     same_block = X == 3 and x < p and y < p
                     for s in spins:
                         for t in spins:
-                            Pm = f.P(x, y, t, s)
-                            PmT = f.T("P", x, y, t, s)
-                            Qm = f.Q(x, y, t, s)
+                            Pm = f.P(x, y, t, s, 0)
+                            PmT = f.T("P", x, y, t, s, 0)
+                            Qm = f.Q(x, y, t, s, 0)
                             g = ("AB" if same_block else "PQ_L" if X == 0 else "PQ_R")
                             if same_block:
-                                yield 0.5, [(0, self.fL.cc(x, y, s, t), 0), (X, Pm, 0)], g + ":P"
-                                yield 0.5, [(X, PmT, 0), (0, self.fL.T("cc", x, y, s, t), 0)], \
+                                yield 0.5, [(0, self.fL.cc(x, y, s, t, 0), 0), (X, Pm, 0)], g + ":P"
+                                yield 0.5, [(X, PmT, 0), (0, self.fL.T("cc", x, y, s, t, 0), 0)], \
                                     g + ":P+"
-                                yield 1.0, [(X, Qm, 0), (0, self.fL.ca(x, y, t, s), 0)], g + ":Q"
+                                yield 1.0, [(X, Qm, 0), (0, self.fL.ca(x, y, t, s, 0), 0)], g + ":Q"
                             else:
                                 yield 0.5, [self.single(x, s, True), self.single(y, t, True),
                                             (X, Pm, 0)], g + ":P"
@@ -474,13 +538,18 @@ class HEff:
         return self._compiled
 
     def apply_u1(self, u1):
-        """Apply H to a product-basis dict whose values are [nvec, dimL, dimR]."""
+        """Apply H to a product-basis dict whose values are [nvec, dimL, dimR].
+
+        With a sample, outputs hold only the selected rows (left groups) and
+        columns (right groups)."""
         out = {}
+        restricted = self.sample is not None
         for OL, OR, dot, pdot, pR in self.compiled():
             colL = {}
             if OL is None:
                 for g in self.mL.gdim:
-                    colL[g] = [(g, None)]
+                    if not restricted or len(self.mL.rows(g)):
+                        colL[g] = [(g, None)]
             else:
                 for (g2, g), m in OL.items():
                     colL.setdefault(g, []).append((g2, m))
@@ -497,7 +566,10 @@ class HEff:
                 if len(rows) == 0:
                     continue
                 for gL2, mL in colL.get(gL, ()):
-                    Z = X if mL is None else np.matmul(mL, X)
+                    if mL is None:
+                        Z = X[:, self.mL.rows(gL2), :] if restricted else X
+                    else:
+                        Z = np.matmul(mL, X)
                     cacheW = {}
                     for d2 in rows:
                         gR2 = self._gR(gL2, d2)
@@ -505,7 +577,8 @@ class HEff:
                             W = cacheW[gR2]
                         else:
                             if OR is None:
-                                W = Z if gR2 == gR else None
+                                W = None if gR2 != gR else \
+                                    (Z[:, :, self.mR.rows(gR2)] if restricted else Z)
                             else:
                                 mR = OR.get((gR2, gR))
                                 W = None if mR is None else np.matmul(Z, mR.T)
@@ -518,6 +591,44 @@ class HEff:
                             out[key] += val
                         else:
                             out[key] = val.copy()
+        return out
+
+    def apply_sample(self, psi):
+        """H_eff psi at the sample's elements: {block index: [rows, cols]}
+        for psi of shape [size] (the projection of ``project`` restricted to
+        those elements)."""
+        assert self.sample is not None
+        u1 = self.apply_u1(self.expand(np.asarray(psi, dtype=float)))
+        S = self.M2
+        out = {}
+        for bi, (rows, cols) in self.sample.items():
+            b = self.blocks[bi]
+            NL, SL, dL = self.prob.left.sectors[b["iL"]]
+            NR, SR, dR = self.prob.right.sectors[b["iR"]]
+            sl, sr = SITE[b["l"]][1], SITE[b["r"]][1]
+            acc = np.zeros((len(rows), len(cols)))
+            for ML in range(SL, -SL - 1, -2):
+                for ml, stl in SITE_MULT_STATES[b["l"]].items():
+                    c1 = cg(SL, ML, sl, ml, b["SLl"], ML + ml)
+                    if c1 == 0.0:
+                        continue
+                    for mr, str_ in SITE_MULT_STATES[b["r"]].items():
+                        MR = S - ML - ml - mr
+                        if abs(MR) > SR or (SR - MR) % 2:
+                            continue
+                        c = c1 * cg(sr, mr, SR, MR, b["SrR"], mr + MR) \
+                            * cg(b["SLl"], ML + ml, b["SrR"], mr + MR, S, S)
+                        if c == 0.0:
+                            continue
+                        gL, oL = self.mL.gidx[(b["iL"], ML)]
+                        gR, oR = self.mR.gidx[(b["iR"], MR)]
+                        m = u1.get((gL, 4 * stl + str_))
+                        if m is None:
+                            continue
+                        pL = np.searchsorted(self.mL.rows(gL), oL + rows)
+                        pR = np.searchsorted(self.mR.rows(gR), oR + cols)
+                        acc += c * m[0][np.ix_(pL, pR)]
+            out[bi] = acc
         return out
 
     def apply(self, psi):

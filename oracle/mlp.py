@@ -11,7 +11,7 @@ here and by the HIP kernels:
   row-major, W[k][j] multiplying input k into unit j).
 * It corrects the diagonal Davidson step multiplicatively, per element:
   t_i = td_i (1 + g(x_i)), td_i = -r_i / (d_i - theta) (denominator magnitude
-  floored).
+  floored at floor * sigma, the relative floor of the diagonal step).
 * Per element features x_i = (asinh((d_i - theta) / sigma), log10(||r||) / 8),
   sigma = root mean square of d - theta over the problem's vector.
 * Training pairs come from a converged solve psi*: at iteration k with Ritz
@@ -96,23 +96,35 @@ def adam_step(p, m, v, gr, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def floored(den, floor):
-    return np.where(np.abs(den) < floor, np.where(den < 0, -floor, floor), den)
+FLOOR = 1e-2
+
+
+def floored(den, fl):
+    """den with magnitudes below the absolute floor fl raised to fl."""
+    return np.where(np.abs(den) < fl, np.where(den < 0, -fl, fl), den)
+
+
+def sigma_of(diag, theta):
+    """Root mean square of d - theta over one problem's vector."""
+    den = np.asarray(diag, float) - theta
+    return np.sqrt(np.mean(den * den))
 
 
 def features(diag, r, theta):
     """Rows (asinh((d - theta)/sigma), log10 ||r|| / 8) for one problem."""
     den = np.asarray(diag, float) - theta
-    sigma = np.sqrt(np.mean(den * den))
+    sigma = sigma_of(diag, theta)
     rn = np.linalg.norm(r)
     return np.stack([np.arcsinh(den / sigma), np.full(den.size, np.log10(rn) / 8.0)], axis=1)
 
 
-def diagonal_step(diag, r, theta, floor=1e-3):
-    return -np.asarray(r, float) / floored(np.asarray(diag, float) - theta, floor)
+def diagonal_step(diag, r, theta, floor=FLOOR):
+    """-r / (d - theta), |d - theta| floored at floor * sigma (relative floor)."""
+    return -np.asarray(r, float) / floored(np.asarray(diag, float) - theta,
+                                           floor * sigma_of(diag, theta))
 
 
-def training_rows(diag, r, u, theta, psi_star, floor=1e-3):
+def training_rows(diag, r, u, theta, psi_star, floor=FLOOR):
     """(x, a, b) of one Davidson iteration given the converged vector."""
     ts = psi_star / (u @ psi_star) - u
     s = np.sqrt(ts.size) / np.linalg.norm(ts)
@@ -122,7 +134,7 @@ def training_rows(diag, r, u, theta, psi_star, floor=1e-3):
     return features(diag, r, theta), a * w, b * w
 
 
-def mlp_step(p, width, diag, r, theta, floor=1e-3):
+def mlp_step(p, width, diag, r, theta, floor=FLOOR):
     """Learned correction t = td (1 + g(x)) of one problem."""
     g, _ = forward(p, features(diag, r, theta), width)
     return diagonal_step(diag, r, theta, floor) * (1.0 + g)

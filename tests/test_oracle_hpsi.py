@@ -97,3 +97,36 @@ def test_planted_mistakes_are_caught():
                     caught = True
                     break
             assert caught, (g, mode)
+
+
+@pytest.mark.parametrize("kind,args,kw", [
+    ("exact", (8, 8, 0, 0), dict()),
+    ("exact", (6, 6, 0, 3), dict(p=0)),
+    ("random", (24, 24, 0, 1), dict(D=64)),
+    ("random", (7, 7, 1, 5), dict(D=200, cap=False)),
+    ("random", (6, 6, 0, 7), dict(D=300, D_right=40, cap=False)),
+])
+def test_sampled_evaluation_equals_full_apply(kind, args, kw):
+    """HEff with a sample (expanded operators restricted to the rows the
+    sampled outputs project from) gives the full apply's values at those
+    elements, at L = 24 too: the restriction the large-workload references
+    are computed with (tests/golden/make_hpsi_samples.py)."""
+    from paper_2309_16724_amd.synth.problem import random_problem
+    prob = exact_problem(*args, **kw) if kind == "exact" else random_problem(*args, **kw)
+    he = HEff(prob)
+    x = np.random.default_rng(3).standard_normal(he.size)
+    y = he.apply(x)
+    rng = np.random.default_rng(4)
+    nb = len(he.blocks)
+    big = max(range(nb), key=lambda i: he.blocks[i]["dL"] * he.blocks[i]["dR"])
+    pick = sorted({big} | set(rng.choice(nb, size=min(5, nb), replace=False).tolist()))
+    sample = {bi: (rng.choice(he.blocks[bi]["dL"], size=min(3, he.blocks[bi]["dL"]), replace=False),
+                   rng.choice(he.blocks[bi]["dR"], size=min(3, he.blocks[bi]["dR"]), replace=False))
+              for bi in pick}
+    hs = HEff(prob, sample)
+    ys = hs.apply_sample(x)
+    scale = np.abs(y).max()
+    for bi, (r, c) in hs.sample.items():
+        b = he.blocks[bi]
+        Y = y[b["off"]:b["off"] + b["dL"] * b["dR"]].reshape(b["dR"], b["dL"]).T
+        assert np.abs(Y[np.ix_(r, c)] - ys[bi]).max() <= 1e-13 * scale
