@@ -20,48 +20,110 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOADS = {
-    # L orbitals, N electrons, 2S, integral seed, SU(2) bond dimension D per block
+    # L orbitals, N electrons, 2S, integral seed, SU(2) bond dimension D per
+    # block, and the sector allocation of the synthetic blocks (spin_ratio,
+    # sigma_frac: see synth.problem.synthetic_sectors)
     "L24_D512": dict(n_orb=24, n_elec=24, two_s=0, seed=1, D=512),
-    "L54_D2048": dict(n_orb=54, n_elec=54, two_s=0, seed=2, D=2048),
+    # sector dims 1..894 per block (R_D = 1.80), 30 TFLOP per H.psi: the
+    # complexity of one middle-bond H.psi of the paper's CAS(54,54), D=2048 runs
+    "L54_D2048": dict(n_orb=54, n_elec=54, two_s=0, seed=2, D=2048, spin_ratio=0.45, sigma_frac=0.03),
     "L64_D3072": dict(n_orb=64, n_elec=64, two_s=0, seed=4, D=3072),
 }
+# the learned preconditioner's evaluation workload (L=64, D=3072) keeps the
+# flatter sector allocation (dims 1..206): its Davidson solves take hundreds
+# of H.psi steps
+GEN_KEYS = ("D", "spin_ratio", "sigma_frac")
+
+
+def make_problem(w):
+    from paper_2309_16724_amd.synth.problem import random_problem
+    return random_problem(w["n_orb"], w["n_elec"], w["two_s"], w["seed"],
+                          **{k: w[k] for k in GEN_KEYS if k in w})
+
 
 FP64_PEAK_TFLOPS = 78.6       # MI355X dense FP64 (matrix and vector)
 BF16_PEAK_TFLOPS = 2516.6     # MI355X dense BF16 MFMA
 
 
-def cpu_baseline(prob, flops_full, target_s=15.0):
-    """Time the oracle on every k-th of its merged terms over the whole wavefunction."""
+def cpu_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "usable_cpus": usable}
+
+
+def _oracle_rate(prob, flops_full, threads, budget_s):
+    """Oracle H_eff psi on the whole wavefunction with `threads` BLAS threads:
+    in full when a probe predicts at most budget_s, else on every k-th of its
+    merged terms (scaled by the term count).  Returns (seconds for one full
+    H.psi, description, process-time / wall-time)."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
     from oracle.hpsi import HEff
-    he = HEff(prob)
-    terms = he.compiled()
-    x = np.random.default_rng(100).standard_normal(he.size)
-    u1 = he.expand(x)
-    # probe cost with a small stride, then pick the stride for ~target_s
-    probe = terms[::50]
-    t0, c0 = time.time(), time.process_time()
-    he._compiled = probe
-    he.apply_u1(u1)
-    dt = max(time.time() - t0, 1e-3)
-    est_full = dt * len(terms) / max(len(probe), 1)
-    k = max(1, int(round(est_full / target_s)))
-    sample = terms[::k]
-    he._compiled = sample
-    t0, c0 = time.time(), time.process_time()
-    he.apply_u1(u1)
-    wall = time.time() - t0
-    cpu = time.process_time() - c0
+    with threadpool_limits(limits=threads):
+        he = HEff(prob)
+        terms = he.compiled()
+        x = np.random.default_rng(100).standard_normal(he.size)
+        u1 = he.expand(x)
+        probe = terms[::50]
+        t0 = time.time()
+        he._compiled = probe
+        he.apply_u1(u1)
+        est_full = max(time.time() - t0, 1e-3) * len(terms) / max(len(probe), 1)
+        k = 1 if est_full <= budget_s else max(2, int(round(est_full / (0.5 * budget_s))))
+        sample = terms[::k]
+        he._compiled = sample
+        t0, c0 = time.time(), time.process_time()
+        he.apply_u1(u1)
+        wall = time.time() - t0
+        cpu = time.process_time() - c0
     t_full = wall * len(terms) / len(sample)
+    if k == 1:
+        desc = "full oracle H_eff psi (all %d merged terms, %.1f s wall)" % (len(terms), wall)
+    else:
+        desc = ("oracle H_eff psi over the full wavefunction restricted to every %d-th of its %d merged "
+                "terms (%.1f s wall), scaled by %d/%d to one full H.psi (%.1f s)"
+                % (k, len(terms), wall, len(terms), len(sample), t_full))
+    return t_full, desc, cpu / max(wall, 1e-9)
+
+
+def cpu_baseline(flops_bench, bench_workload):
+    """The oracle timed on this host's cores (test infrastructure, never on
+    the product path).  The M-resolved oracle cannot hold the metric's L=54
+    workload (its expanded operators alone would need terabytes), so it is
+    timed on the L=24, D=512 workload: in full with all usable cores, and on a
+    term sample with one thread; value = that workload's algorithmic flops per
+    oracle second."""
+    from paper_2309_16724_amd import binding as B
+    info = cpu_info()
+    w = WORKLOADS["L24_D512"]
+    prob = make_problem(w)
+    _, st = B.debug_plan_host_apply(prob, None)
+    flops = st["flops"]
+    cores = info["usable_cpus"] or 1
+    t_all, desc_all, par = _oracle_rate(prob, flops, cores, 60.0)
+    t_one, desc_one, _ = _oracle_rate(prob, flops, 1, 20.0)
     return {
-        "value": flops_full / t_full / 1e12,
+        "value": flops / t_all / 1e12,
         "unit": "TFLOP/s",
-        "cores": max(1, int(round(cpu / wall))),
+        "cores": cores,
         "kind": "oracle",
-        "sample": "oracle H_eff psi over the full wavefunction restricted to every %d-th of its "
-                  "%d merged terms (%.1f s wall), scaled by %d/%d to one full H.psi "
-                  "(%.1f s); value = algorithmic flops of one H.psi / that time"
-                  % (k, len(terms), wall, len(terms), len(sample), t_full),
+        "sample": "L24_D512 (L=24, D=512, %.1f GFLOP per H.psi): %s with %d BLAS threads "
+                  "(process/wall time %.1f); the bench workload %s (%.1f TFLOP per H.psi) is beyond the "
+                  "oracle's host memory" % (flops / 1e9, desc_all, cores, par, bench_workload,
+                                            flops_bench / 1e12),
+        "single_thread": {"value": flops / t_one / 1e12, "unit": "TFLOP/s", "sample": desc_one},
+        **info,
     }
 
 
@@ -92,9 +154,10 @@ def measured_traffic(workload, kernel):
     return nbytes if h.hexdigest()[:16] == digest else None
 
 
-def train_preconditioner(torch, specs, steps=2000, batch=4096, seed=0, width=256):
+def train_preconditioner(torch, specs, steps=2000, batch=4096, seed=0, width=256, floor=None):
     """Learned preconditioner: exact-correction rows of the given solves
-    (device capture), then minibatch Adam on the device."""
+    (device capture, with the relative floor the solves use), then minibatch
+    Adam on the device."""
     import numpy as np
     from paper_2309_16724_amd.hpsi import Plan
     from paper_2309_16724_amd.precond import MLP
@@ -104,7 +167,7 @@ def train_preconditioner(torch, specs, steps=2000, batch=4096, seed=0, width=256
     for L, N, s2, sd, D in specs:
         plan = Plan(random_problem(L, N, s2, sd, D=D))
         x0 = torch.from_numpy(random_vector(plan.size, 100)).cuda()
-        x, a, b, nr = plan.collect(x0, capacity=plan.size * 500)
+        x, a, b, nr = plan.collect(x0, capacity=plan.size * 500, **({} if floor is None else {"floor": floor}))
         plan.free()
         xs.append(x)
         as_.append(a)
@@ -220,21 +283,121 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def time_hpsi(torch, plan, x, y, steps, warmup):
+    """Graph-replayed H.psi: warm-up, then `steps` timed replays bracketed by
+    synchronisation (ms per step); then the same number of eager launches
+    with per-launch HIP events on the library's stream (per-stage kernel
+    time and flops, the roofline's figures)."""
+    for _ in range(warmup):
+        plan.apply(x, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.apply(x, y)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    plan.set_profiling(True)
+    for _ in range(steps):
+        plan.apply(x, y)
+    torch.cuda.synchronize()
+    prof = {s_: plan.profile(s_) for s_ in (1, 2)}
+    plan.set_profiling(False)
+    return ms, prof
+
+
+def sampled_errors(yv, workload, prob):
+    """Largest error of H.psi at the oracle's stored sample of this workload
+    (tests/golden/hpsi_samples.json), relative to the largest sampled value."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "hpsi_samples.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        case = json.load(f).get("cases", {}).get(workload)
+    if case is None:
+        return None
+    from oracle.layout import psi_blocks
+    blocks, size = psi_blocks(prob.left.sectors, prob.right.sectors, prob.n_elec, prob.two_s)
+    if size != case["psi_len"]:
+        return None
+    err, scale, n = 0.0, 0.0, 0
+    for smp in case["samples"]:
+        b = blocks[smp["block"]]
+        Y = yv[b["off"]:b["off"] + b["dL"] * b["dR"]].reshape(b["dR"], b["dL"]).T
+        ref = np.array(smp["values"])
+        err = max(err, float(np.abs(Y[np.ix_(smp["rows"], smp["cols"])] - ref).max()))
+        scale = max(scale, float(np.abs(ref).max()))
+        n += ref.size
+    return {"max_rel": err / scale, "elements": n, "blocks": len(case["samples"])}
+
+
+def davidson_runs(torch, args, w, plan_flags):
+    """Davidson s/step on a workload: diagonal preconditioner (FP64 H.psi),
+    learned preconditioner, and the diagonal solve with split H.psi.  Derived
+    comparisons are reported only between converged solves."""
+    import numpy as np
+    from paper_2309_16724_amd.hpsi import Plan
+    prob = make_problem(w)
+    plan = Plan(prob, flags=plan_flags)
+    x_np = np.random.default_rng(100).standard_normal(plan.size)
+    x0 = torch.from_numpy(x_np / np.linalg.norm(x_np)).cuda()
+    fk = {} if args.dav_floor is None else {"floor": args.dav_floor}
+    torch.cuda.synchronize()
+    td = time.time()
+    e_dav, _, dst = plan.davidson(x0, tol=1e-8, check=False, verbose=int(args.dav_verbose), **fk)
+    t_dav = time.time() - td
+    out = {"workload": args.dav_workload,
+           "diagonal": {"s_per_step": t_dav, "iterations": dst["iters"], "n_hpsi": dst["n_hpsi"],
+                        "converged": dst["converged"], "residual": dst["residual"], "energy": e_dav,
+                        "sigma": dst["sigma"], "floor": args.dav_floor, "t_hpsi_s": dst["t_hpsi_s"]}}
+    if not args.no_mlp:
+        net, info = train_preconditioner(torch, [(24, 24, 0, 10000 + k, 512) for k in range(4)], floor=args.dav_floor)
+        print("# learned preconditioner: %s" % json.dumps(info), file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        tm = time.time()
+        e_mlp, _, mst = plan.davidson(x0, tol=1e-8, mlp=net, check=False, verbose=int(args.dav_verbose), **fk)
+        t_mlp = time.time() - tm
+        net.free()
+        both = dst["converged"] == 1 and mst["converged"] == 1
+        out["learned"] = {"s_per_step": t_mlp, "iterations": mst["iters"], "n_hpsi": mst["n_hpsi"],
+                          "converged": mst["converged"], "residual": mst["residual"],
+                          "fallbacks": mst["fallbacks"], "switched": mst["switched"],
+                          "t_hpsi_s": mst["t_hpsi_s"],
+                          "energy_minus_diagonal": (e_mlp - e_dav) if both else None,
+                          "speedup_vs_diagonal": (t_dav / t_mlp) if both else None,
+                          "training": info}
+    plan.free()
+    if not args.no_split_davidson:
+        splan = Plan(prob, precision=1, n_slices=5, flags=plan_flags)
+        torch.cuda.synchronize()
+        tsd = time.time()
+        e_sp, _, sst = splan.davidson(x0, tol=1e-8, check=False, verbose=int(args.dav_verbose), **fk)
+        both = dst["converged"] == 1 and sst["converged"] == 1
+        out["split"] = {"s_per_step": time.time() - tsd, "iterations": sst["iters"],
+                        "converged": sst["converged"], "residual": sst["residual"],
+                        "energy_minus_fp64": (e_sp - e_dav) if both else None}
+        splan.free()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="L24_D512", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="L54_D2048", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="use the default tile settings instead of autotuning each plan")
+    ap.add_argument("--autotune", action="store_true", help="autotune the H.psi plans (DMRG_PLAN_AUTOTUNE)")
+    ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of graph replays")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-preconditioner Davidson")
-    ap.add_argument("--no-davidson", action="store_true", help="time H.psi only (large workloads)")
+    ap.add_argument("--no-davidson", action="store_true", help="time H.psi only")
+    ap.add_argument("--dav-workload", default="L24_D512", choices=sorted(WORKLOADS),
+                    help="workload of the Davidson solves (default L24_D512: a solve of the L=54 "
+                         "workload takes hundreds of 1.5 s H.psi steps)")
     ap.add_argument("--no-split-davidson", action="store_true",
                     help="skip the Davidson solve with split-precision H.psi")
     ap.add_argument("--dav-floor", type=float, default=None,
-                    help="preconditioner denominator floor of the Davidson solves (library default if omitted)")
+                    help="relative preconditioner floor of the Davidson solves (library default if omitted)")
     ap.add_argument("--dav-verbose", action="store_true",
                     help="Davidson progress lines on stderr every 25 iterations (long solves)")
     ap.add_argument("--hpsi-only", choices=("fp64", "split"),
@@ -245,6 +408,7 @@ def main():
     ap.add_argument("--batch", type=int, default=0,
                     help="instead of the single workload, time H.psi of a batch of this many "
                          "uneven problems (L in [16, 32], D in [128, 768], S in {0, 1})")
+    ap.add_argument("--no-autotune", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -254,42 +418,32 @@ def main():
         return run_batch(args)
     import numpy as np
     import torch
-    from paper_2309_16724_amd.binding import DMRG_PLAN_AUTOTUNE
+    from paper_2309_16724_amd.binding import DMRG_PLAN_AUTOTUNE, DMRG_PLAN_GRAPH
     from paper_2309_16724_amd.hpsi import Plan
-    from paper_2309_16724_amd.synth.problem import random_problem
 
     w = WORKLOADS[args.workload]
-    prob = random_problem(w["n_orb"], w["n_elec"], w["two_s"], w["seed"], D=w["D"])
-    sizer = Plan(prob)
-    x_np = np.random.default_rng(100).standard_normal(sizer.size)
-    x_np /= np.linalg.norm(x_np)
-    sizer.free()
-    plan_flags = 0 if args.no_autotune else DMRG_PLAN_AUTOTUNE
+    t0 = time.time()
+    prob = make_problem(w)
+    secs = [s_[2] for s_ in prob.left.sectors] + [s_[2] for s_ in prob.right.sectors]
+    rd = sum((s_[1] + 1) * s_[2] for s_ in prob.left.sectors) / sum(s_[2] for s_ in prob.left.sectors)
+    print("# workload %s generated in %.1f s (sector dims %d..%d, R_D %.2f)"
+          % (args.workload, time.time() - t0, min(secs), max(secs), rd), file=sys.stderr, flush=True)
+    plan_flags = (0 if args.no_graph else DMRG_PLAN_GRAPH) | (DMRG_PLAN_AUTOTUNE if args.autotune else 0)
 
-    def run(precision, ns):
-        plan = Plan(prob, precision=precision, n_slices=ns, flags=plan_flags)
+    def run(precision, ns, flags):
+        t1 = time.time()
+        plan = Plan(prob, precision=precision, n_slices=ns, flags=flags)
         st = plan.stats()
-        print("# plan %s prec=%d s=%d: %s" % (args.workload, precision, ns, json.dumps(st)),
-              file=sys.stderr, flush=True)
-        x = torch.from_numpy(x_np).cuda()
+        print("# plan %s prec=%d s=%d built in %.1f s: %s" % (args.workload, precision, ns, time.time() - t1,
+                                                              json.dumps(st)), file=sys.stderr, flush=True)
+        x = torch.from_numpy(np.random.default_rng(100).standard_normal(plan.size)).cuda()
+        x /= torch.linalg.norm(x)
         y = torch.empty_like(x)
-        for _ in range(args.warmup):
-            plan.apply(x, y)
-        torch.cuda.synchronize()
-        # the timed region: per-launch HIP events on the library's stream
-        plan.set_profiling(True)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        for _ in range(args.steps):
-            plan.apply(x, y)
-        ev1.record()
-        torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / args.steps
-        prof = {s_: plan.profile(s_) for s_ in (1, 2)}
-        plan.set_profiling(False)
+        ms, prof = time_hpsi(torch, plan, x, y, args.steps, args.warmup)
         print("# per-stage (launches, ms, flops): %s" % json.dumps(prof), file=sys.stderr, flush=True)
         yv = y.cpu().numpy()
         plan.free()
+        del x, y
         return st, ms, prof, yv
 
     if args.hpsi_only:
@@ -300,52 +454,21 @@ def main():
         torch.cuda.synchronize()
         del ref, ref2
         prec, ns = (0, 0) if args.hpsi_only == "fp64" else (1, 5)
-        st, ms, prof, _ = run(prec, ns)
+        st, ms, prof, _ = run(prec, ns, 0)
         print(json.dumps({"hpsi_only": args.hpsi_only, "workload": args.workload, "ms_per_step": ms,
                           "tflops": st["flops"] / (ms * 1e-3) / 1e12, "stages": prof,
                           "kpart": st["kpart"], "tile_policy": st["tile_policy"],
                           "workspace_cap": st["workspace_cap"]}), flush=True)
         return
-    st64, ms64, prof64, y64 = run(0, 0)
-    st5, ms5, prof5, y5 = run(1, 5)
+    st64, ms64, prof64, y64 = run(0, 0, plan_flags)
+    err64 = sampled_errors(y64, args.workload, prob)
+    st5, ms5, prof5, y5 = run(1, 5, plan_flags)
+    err5 = sampled_errors(y5, args.workload, prob)
     rel = float(np.abs(y5 - y64).max() / np.abs(y64).max())
-    davidson, learned, split_dav = None, None, None
+    del y5, y64
+    dav = None
     if not args.no_davidson:
-        # Davidson s/step (FP64 path, diagonal preconditioner) on the same workload
-        plan = Plan(prob, flags=plan_flags)
-        x0 = torch.from_numpy(x_np).cuda()
-        torch.cuda.synchronize()
-        td = time.time()
-        fk = {} if args.dav_floor is None else {"floor": args.dav_floor}
-        e_dav, _, dst = plan.davidson(x0, tol=1e-8, check=False, verbose=int(args.dav_verbose), **fk)
-        t_dav = time.time() - td
-        davidson = {"s_per_step": t_dav, "iterations": dst["iters"], "n_hpsi": dst["n_hpsi"],
-                    "converged": dst["converged"], "floor": args.dav_floor,
-                    "residual": dst["residual"], "energy": e_dav, "precision": "fp64",
-                    "preconditioner": "diagonal", "t_hpsi_s": dst["t_hpsi_s"]}
-        if not args.no_mlp:
-            net, info = train_preconditioner(torch, [(24, 24, 0, 10000 + k, 512) for k in range(4)])
-            print("# learned preconditioner: %s" % json.dumps(info), file=sys.stderr, flush=True)
-            torch.cuda.synchronize()
-            tm = time.time()
-            e_mlp, _, mst = plan.davidson(x0, tol=1e-8, mlp=net, check=False, verbose=int(args.dav_verbose), **fk)
-            t_mlp = time.time() - tm
-            net.free()
-            learned = {"s_per_step": t_mlp, "iterations": mst["iters"], "n_hpsi": mst["n_hpsi"],
-                       "converged": mst["converged"], "fallbacks": mst["fallbacks"],
-                       "energy_minus_diagonal": e_mlp - e_dav, "t_hpsi_s": mst["t_hpsi_s"],
-                       "speedup_vs_diagonal": t_dav / t_mlp, "training": info}
-        plan.free()
-        if not args.no_split_davidson:
-            # the same solve with every H.psi in split precision
-            splan = Plan(prob, precision=1, n_slices=5, flags=plan_flags)
-            torch.cuda.synchronize()
-            tsd = time.time()
-            e_sp, _, sst = splan.davidson(x0, tol=1e-8, check=False, verbose=int(args.dav_verbose), **fk)
-            split_dav = {"s_per_step": time.time() - tsd, "iterations": sst["iters"],
-                         "converged": sst["converged"], "residual": sst["residual"],
-                         "energy_minus_fp64": e_sp - e_dav}
-            splan.free()
+        dav = davidson_runs(torch, args, WORKLOADS[args.dav_workload], plan_flags)
     dom = max((1, 2), key=lambda s_: prof5[s_][1])
     n_l, ms_l, fl_l = prof5[dom]
     achieved = (fl_l / n_l) / (ms_l / n_l * 1e-3) / 1e12
@@ -355,9 +478,10 @@ def main():
     tflops5 = st5["flops"] / (ms5 * 1e-3) / 1e12
     tflops64 = st64["flops"] / (ms64 * 1e-3) / 1e12
     ach64 = (fl6 / n6) / (ms6 / n6 * 1e-3) / 1e12
+    gen = {k: w[k] for k in GEN_KEYS if k in w}
     out = {
-        "metric": "H.psi TFLOP/s (split-BF16 s=5 at <=1e-10 rel err vs FP64; algorithmic FP64-equivalent "
-                  "flops); FP64 path and Davidson s/step alongside",
+        "metric": "H.psi TFLOP/s (split-BF16 s=5 at <=1e-10 rel err vs the FP64 oracle; algorithmic FP64-"
+                  "equivalent flops); FP64 path and Davidson s/step alongside",
         "value": tflops5,
         "unit": "TFLOP/s",
         "n_gpus": 1,
@@ -369,19 +493,23 @@ def main():
         "vs_baseline": None,
         "dtype": "bf16x5 slices, fp32 accumulate, fp64 fold",
         "data": "synthetic",
-        "config": {"workload": args.workload, **w, "psi_len": int(x_np.size),
-                   "flops_per_hpsi": st5["flops"], "n_slices": 5,
-                   "split_plan": {k: st5[k] for k in ("kpart", "tile_policy", "workspace_cap")},
-                   "fp64_plan": {k: st64[k] for k in ("kpart", "tile_policy", "workspace_cap")}},
+        "config": {"workload": args.workload, **{k: w[k] for k in ("n_orb", "n_elec", "two_s", "seed")},
+                   **gen, "psi_len": int(st5["psi_len"]), "sector_dims": [min(secs), max(secs)],
+                   "R_D": round(rd, 3), "flops_per_hpsi": st5["flops"], "n_slices": 5,
+                   "timed": "eager launches" if args.no_graph else "graph replays (DMRG_PLAN_GRAPH)",
+                   "split_plan": {k: st5[k] for k in ("kpart", "tile_policy", "workspace_cap", "n_chunks",
+                                                      "launches", "tasks_ms", "plan_ms")},
+                   "fp64_plan": {k: st64[k] for k in ("kpart", "tile_policy", "workspace_cap", "n_chunks",
+                                                      "launches", "tasks_ms", "plan_ms")}},
+        "split_rel_err_vs_oracle_samples": err5,
+        "fp64_rel_err_vs_oracle_samples": err64,
         "split_rel_err_vs_fp64": rel,
         "fp64": {"value": tflops64, "ms_per_step": ms64,
                  "roofline": {"bound": "mfma", "kernel": "stage_f64_kernel<%d>" % dom64, "achieved": ach64,
                               "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach64 / FP64_PEAK_TFLOPS,
                               "traffic": measured_traffic(args.workload, "stage_f64_kernel<%d>" % dom64)}},
         "speedup_split_vs_fp64": ms64 / ms5,
-        "davidson": davidson,
-        "davidson_learned": learned,
-        "davidson_split": split_dav,
+        "davidson": dav,
         "roofline": {"bound": "mfma", "kernel": "stage%d_split5_kernel" % dom,
                      "achieved": achieved, "peak": split_peak, "unit": "TFLOP/s",
                      "frac": achieved / split_peak,
@@ -390,7 +518,7 @@ def main():
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, st5["flops"])
+        out["cpu_baseline"] = cpu_baseline(st5["flops"], args.workload)
     print(json.dumps(out), flush=True)
 
 

@@ -114,7 +114,7 @@ enum { DMRG_PLAN_GRAPH = 1, DMRG_PLAN_XCD = 2, DMRG_PLAN_AUTOTUNE = 4 };
 typedef struct {
   int32_t precision;        /* DMRG_FP64 or DMRG_SPLIT_BF16                   */
   int32_t n_slices;         /* split only: BF16 slices per operand (3..7)     */
-  int64_t workspace_bytes;  /* cap for the intermediate stripes, 0 = default  */
+  int64_t workspace_bytes;  /* cap for the intermediate stripes, 0 = 64 GiB   */
   int32_t flags;            /* DMRG_PLAN_* bits                                */
   int32_t kpart;            /* summed K per second-stage work item, 0 = 2048 */
   int32_t tile_policy;      /* 0: 16x64 / 32x32 / 64x16 by output shape,
@@ -139,9 +139,12 @@ typedef struct {
   int32_t tile_policy;
   int32_t xcd;
   int32_t tuned;            /* candidates timed by the autotuner (0: none)   */
-  int32_t pad;
+  int32_t launches;         /* kernel launches of one H.psi                  */
   int64_t workspace_cap;    /* stripe workspace cap in use, bytes            */
   double tune_ms;           /* autotuner wall time                            */
+  double tasks_ms;          /* host: operator, sector-task and value tables  */
+  double plan_ms;           /* stripe grouping, tile lists, device set-up (and
+                               autotuning)                                  */
 } dmrg_plan_stats_t;
 
 /* Build the operator table, sector-task and sector-value tables (Sec. II A,
@@ -151,7 +154,11 @@ typedef struct {
 int dmrg_build_tasks(const dmrg_problem_t *probs, int32_t n_probs,
                      const dmrg_plan_opts_t *opts, void *stream, dmrg_plan_t **out);
 
-/* Offset and length of problem `prob` inside the concatenated wavefunction. */
+/* Offset and length of problem `prob` inside the concatenated wavefunction
+ * (the reduced two-site wavefunction E/F of Eq. (2), Sec. II A, stored as its
+ * sector blocks, Sec. II A "sector-table"; problems of a plan concatenated in
+ * order).  off/len: host pointers, either may be NULL.  DMRG_EINVAL for a
+ * NULL plan or prob outside [0, n_probs). */
 int dmrg_psi_layout(const dmrg_plan_t *p, int32_t prob, int64_t *off, int64_t *len);
 
 /* hpsi := H_eff psi for all problems (device arrays of psi_len doubles). */
@@ -168,8 +175,9 @@ int dmrg_diag_H(dmrg_plan_t *p, double *diag, void *stream);
  * array of n_probs doubles, out = Ritz values.  Block size 1, thick restart
  * to the current and previous Ritz vectors at m_max (all problems restart
  * together), two-pass Gram-Schmidt, correction -r/(diag - theta) with
- * |diag - theta| >= floor (or the learned correction of the network in
- * o->mlp, see below), a problem stops when ||H u - theta u||_2 <= tol
+ * |diag - theta| >= floor * sigma, sigma the root mean square of diag - theta
+ * over the problem (or the learned correction of the network in o->mlp, see
+ * below), a problem stops when ||H u - theta u||_2 <= tol
  * (its segment of later basis vectors is zero).  Returns DMRG_ENOCONV (with
  * the best pairs in psi/evals) when max_iter is reached before every problem
  * converged.  All vector work runs on the GPU in FP64 (segmented, fixed-order
@@ -185,9 +193,11 @@ typedef struct {
   int32_t m_max;            /* subspace size, 3..64 (24 by default)         */
   int32_t precond;          /* DMRG_PRECOND_DIAG or DMRG_PRECOND_MLP         */
   int32_t verbose;          /* > 0: a progress line on stderr every 25 iterations */
-  double floor;             /* preconditioner denominator floor (1e-3 with no
-                               options; 1e-8 lets a few elements with
-                               d ~ theta dominate every correction)         */
+  double floor;             /* relative preconditioner denominator floor: the
+                               magnitude of diag - theta is raised to at least
+                               floor * RMS(diag - theta) of the problem (1e-2
+                               with no options; an absolute floor had to be
+                               hand-set per workload)                        */
   const dmrg_mlp_t *mlp;    /* network for DMRG_PRECOND_MLP, else NULL       */
   int32_t mlp_patience;     /* learned steps of a problem stop after this many
                                iterations without a new smallest residual
@@ -202,17 +212,25 @@ typedef struct {
   double residual, energy;
   double t_total_s, t_hpsi_s;
   int32_t switched, pad;
+  double sigma;             /* RMS(diag - theta) of problem 0 at its last theta */
 } dmrg_dav_stats_t;
 int dmrg_davidson(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts_t *o,
                   dmrg_dav_stats_t *st, void *stream);
 
+/* Plan statistics (host struct, filled): sizes of the operator table, the
+ * sector-task table and its stripe grouping (Sec. II A, Eq. (3); Sec. III A),
+ * and the algorithmic FP64 flop count of one H.psi -- 2mnk summed over the
+ * executed products, the measure of the paper's TFLOPS figures (Sec. IV A,
+ * complexity of the operations of Eq. (2) over the elapsed time); split plans
+ * count each product once.  DMRG_EINVAL for NULL arguments. */
 int dmrg_plan_stats(const dmrg_plan_t *p, dmrg_plan_stats_t *st);
 
 /* ---- learned Davidson preconditioner ------------------------------------
  * The paper leaves the Davidson details open (Sec. II).  This optional
  * preconditioner corrects the diagonal step per element with a 3-layer
  * perceptron: t_i = td_i (1 + g(x_i)), td_i = -r_i / (d_i - theta) (floored),
- * g(x) = w3 . relu(W2 relu(W1 x + b1) + b2) + b3, inputs
+ * g(x) = w3 . relu(W2 relu(W1 x + b1) + b2) + b3, td floored as the diagonal
+ * step (relative floor), inputs
  * x_i = (asinh((d_i - theta)/sigma), log10(||r||)/8), sigma the root mean
  * square of d - theta over the problem.  Parameters are FP32 on the device,
  * one flat vector: W1[DMRG_MLP_IN][w], b1[w], W2[w][w], b2[w], w3[w], b3
@@ -299,7 +317,8 @@ int64_t dmrg_debug_plan_tiles(const dmrg_problem_t *prob, int32_t stage, int64_t
 /* Test-only: the host eigensolver dmrg_davidson applies to its projected
  * matrix (cyclic Jacobi).  A: m x m symmetric, row-major, HOST, 1 <= m <= 64;
  * w: m eigenvalues ascending; Z: m x m row-major, eigenvector j in column j.
- * Returns DMRG_EINVAL for m out of range or NULL pointers. */
+ * Returns the number of Jacobi sweeps run (100 when the sweep limit stopped
+ * it), or DMRG_EINVAL for m out of range or NULL pointers. */
 int dmrg_debug_jacobi(int32_t m, const double *A, double *w, double *Z);
 
 #ifdef __cplusplus

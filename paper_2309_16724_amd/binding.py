@@ -63,7 +63,7 @@ class TrainOpts(ctypes.Structure):
 class DavStats(ctypes.Structure):
     _fields_ = [("iters", c_i32), ("n_hpsi", c_i32), ("converged", c_i32), ("fallbacks", c_i32),
                 ("residual", c_dbl), ("energy", c_dbl), ("t_total_s", c_dbl), ("t_hpsi_s", c_dbl),
-                ("switched", c_i32), ("pad", c_i32)]
+                ("switched", c_i32), ("pad", c_i32), ("sigma", c_dbl)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -74,7 +74,8 @@ class PlanStats(ctypes.Structure):
                 ("n_stage1", c_i64), ("n_segments", c_i64), ("flops", c_dbl),
                 ("stage1_flops", c_dbl), ("stage2_flops", c_dbl), ("workspace_bytes", c_i64),
                 ("n_chunks", c_i32), ("kpart", c_i32), ("tile_policy", c_i32), ("xcd", c_i32),
-                ("tuned", c_i32), ("pad", c_i32), ("workspace_cap", c_i64), ("tune_ms", c_dbl)]
+                ("tuned", c_i32), ("launches", c_i32), ("workspace_cap", c_i64), ("tune_ms", c_dbl),
+                ("tasks_ms", c_dbl), ("plan_ms", c_dbl)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
@@ -193,16 +194,18 @@ def debug_plan_host_apply(prob, psi, workspace_bytes=0, lib=None, precision=0, n
     return y, st.as_dict()
 
 
-def debug_jacobi(A, lib=None):
+def debug_jacobi(A, lib=None, sweeps=False):
     """Test-only: eigenvalues (ascending) and eigenvectors (columns) of a
-    symmetric m x m matrix by the Davidson solver's host Jacobi routine."""
+    symmetric m x m matrix by the Davidson solver's host Jacobi routine
+    (and the number of sweeps it ran with sweeps=True)."""
     L = lib or load()
     A = np.ascontiguousarray(A, dtype=np.float64)
     m = A.shape[0]
     w = np.zeros(m)
     Z = np.zeros((m, m))
-    check(L.dmrg_debug_jacobi(m, A.ctypes.data, w.ctypes.data, Z.ctypes.data), L)
-    return w, Z
+    n = L.dmrg_debug_jacobi(m, A.ctypes.data, w.ctypes.data, Z.ctypes.data)
+    check(min(n, 0), L)
+    return (w, Z, n) if sweeps else (w, Z)
 
 
 def debug_host_apply(prob, psi, lib=None):

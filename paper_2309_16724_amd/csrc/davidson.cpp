@@ -8,7 +8,10 @@
 // Details the paper leaves open (same reading as the oracle): block size 1;
 // thick restart to the current and previous Ritz vectors when the subspace
 // reaches m_max; two-pass classical Gram-Schmidt; correction
-// t = -r / (diag - theta) with |diag - theta| floored, optionally corrected
+// t = -r / (diag - theta) with |diag - theta| floored at floor * sigma, sigma
+// the root mean square of diag - theta over the problem (a relative floor:
+// the cap on the few elements with diag ~ theta follows the spread of the
+// diagonal, so one default serves problems of any size), optionally corrected
 // per element by the learned network (mlp.cpp), with a guard that falls back
 // to the diagonal step and a patience rule that turns the learned steps of a
 // problem off once its residual stops reaching new minima (a network can be
@@ -32,11 +35,12 @@ using namespace dmrg;
 
 namespace dmrg {
 
-void jacobi_eigh(int m, const double *A, double *w, double *Z) {
+int jacobi_eigh(int m, const double *A, double *w, double *Z) {
   std::vector<double> a(A, A + (size_t)m * m);
   for (int i = 0; i < m; i++)
     for (int j = 0; j < m; j++) Z[i * m + j] = i == j ? 1.0 : 0.0;
-  for (int sweep = 0; sweep < 100; sweep++) {
+  int sweep = 0;
+  for (; sweep < JACOBI_MAX_SWEEPS; sweep++) {
     double off = 0.0, tot = 0.0;
     for (int i = 0; i < m; i++)
       for (int j = 0; j < m; j++) {
@@ -86,6 +90,7 @@ void jacobi_eigh(int m, const double *A, double *w, double *Z) {
     for (int i = 0; i < m; i++) Zs[i * m + j] = Z[i * m + idx[j]];
   }
   std::memcpy(Z, Zs.data(), sizeof(double) * m * m);
+  return sweep;
 }
 
 }  // namespace dmrg
@@ -164,7 +169,7 @@ struct Collect {
 }  // namespace
 
 static int check_opts(const dmrg_dav_opts_t *o, dmrg_dav_opts_t *opt) {
-  *opt = {1e-8, 1000, 24, DMRG_PRECOND_DIAG, 0, 1e-3, nullptr, 0, 0};
+  *opt = {1e-8, 1000, 24, DMRG_PRECOND_DIAG, 0, 1e-2, nullptr, 0, 0};
   if (o) *opt = *o;
   if (opt->m_max < 3 || opt->m_max > 64 || opt->max_iter < 1 || !(opt->tol > 0.0) || !(opt->floor > 0.0) ||
       opt->mlp_patience < 0) {
@@ -221,12 +226,13 @@ static int solve(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts
   const bool use_mlp = opt.precond == DMRG_PRECOND_MLP;
   double *tm = use_mlp ? buf.get(n) : nullptr, *ones = buf.get(n);
   double *dth = buf.get(np), *dsig = buf.get(np), *df1 = buf.get(np), *dflag = buf.get(np);
+  double *dfloor = buf.get(np);
   int64_t *dsegoff = (int64_t *)buf.raw(sizeof(int64_t) * (np + 1));
   double *part = buf.get((int64_t)std::max<size_t>(chunks.size(), 1) * (M + 2));
   double *dout = buf.get((int64_t)np * (M + 2)), *dcoef = buf.get((int64_t)np * M);
   double *dvec = buf.get(np);
   if (!d_chunks || !d_seg0 || !V || !W || !u || !hu || !r || !t || !uprev || !diag || !tmp || !part || !dout ||
-      !dcoef || !dvec || (use_mlp && !tm) || !ones || !dth || !dsig || !df1 || !dflag || !dsegoff) {
+      !dcoef || !dvec || (use_mlp && !tm) || !ones || !dth || !dsig || !df1 || !dflag || !dsegoff || !dfloor) {
     set_error("hipMalloc failed in Davidson");
     return DMRG_ENOMEM;
   }
@@ -320,7 +326,7 @@ static int solve(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts
   int m = 1;
   int it = 0;
   int n_active = np;
-  std::vector<double> coef((size_t)np * M, 0.0), thetas(np, 0.0);
+  std::vector<double> coef((size_t)np * M, 0.0), thetas(np, 0.0), floors(np, 1.0);
   for (it = 1; it <= opt.max_iter && n_active > 0; it++) {
     // Ritz pairs
     std::fill(coef.begin(), coef.end(), 0.0);
@@ -340,11 +346,13 @@ static int solve(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts
         coef[(size_t)k * M + S.cols[i]] = S.c[i];
       }
       thetas[k] = S.theta;
+      // relative floor: the denominator cap scales with the spread of d - theta
+      floors[k] = opt.floor * sigma_of(k, S.theta);
     }
-    if ((rc = put_coef(coef)) || (rc = put_vec(thetas))) return rc;
+    if ((rc = put_coef(coef)) || (rc = put_vec(thetas)) || (rc = put(dfloor, floors.data(), (size_t)np))) return rc;
     vec_combo(X, V, n, m, dcoef, M, 1.0, 0.0, u, stream);
     vec_combo(X, W, n, m, dcoef, M, 1.0, 0.0, hu, stream);
-    vec_resid(X, hu, u, diag, dvec, opt.floor, r, t, stream);
+    vec_resid(X, hu, u, diag, dvec, dfloor, r, t, stream);
     if ((rc = dots_host(r, 1, r))) return rc;
     for (int k = 0; k < np; k++) {
       ProbState &S = P[k];
@@ -383,7 +391,7 @@ static int solve(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts
         const double tn = std::sqrt(hout[0]);
         if (tn > 0.0 && std::isfinite(tn) && col->rows + n <= col->cap) {
           launch_collect(diag, r, col->ts, n, P[0].theta, sigma_of(0, P[0].theta),
-                         std::log10(std::max(P[0].rnorm, 1e-300)) / 8.0, std::sqrt((double)n) / tn, opt.floor,
+                         std::log10(std::max(P[0].rnorm, 1e-300)) / 8.0, std::sqrt((double)n) / tn, floors[0],
                          col->x + col->rows * MLP_IN, col->a + col->rows, col->b + col->rows, stream);
           HIPCHK(hipGetLastError());
           col->rows += n;
@@ -415,7 +423,7 @@ static int solve(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts
       A.f1 = df1;
       A.seg_off = dsegoff;
       A.nseg = np;
-      A.floor_ = opt.floor;
+      A.floor_ = dfloor;
       A.t = tm;
       launch_mlp_forward(opt.mlp->width, 1, A, stream);
       HIPCHK(hipGetLastError());
@@ -580,6 +588,7 @@ static int solve(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts
     st->converged = conv;
     st->residual = maxres;
     st->energy = P[0].theta;
+    st->sigma = sigma_of(0, P[0].theta);
     st->t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     st->t_hpsi_s = t_hpsi;
   }
@@ -592,8 +601,7 @@ extern "C" int dmrg_debug_jacobi(int32_t m, const double *A, double *w, double *
     set_error("dmrg_debug_jacobi: 1 <= m <= 64 and non-NULL arrays");
     return DMRG_EINVAL;
   }
-  dmrg::jacobi_eigh(m, A, w, Z);
-  return DMRG_OK;
+  return dmrg::jacobi_eigh(m, A, w, Z);
 }
 
 extern "C" int dmrg_davidson(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts_t *o,

@@ -24,12 +24,16 @@ struct VecCtx {
 void vec_dots(const VecCtx &X, const double *V, int64_t ldv, int m, const double *x, double *out, void *stream);
 void vec_combo(const VecCtx &X, const double *V, int64_t ldv, int m, const double *coef, int ldc, double sign,
                double beta, double *y, void *stream);
+// floors: per-segment absolute denominator floors
 void vec_resid(const VecCtx &X, const double *hu, const double *u, const double *diag, const double *theta,
-               double floor_, double *r, double *t, void *stream);
+               const double *floors, double *r, double *t, void *stream);
 void vec_scale(const VecCtx &X, const double *s, double *x, void *stream);
 void vec_fill(const VecCtx &X, double value, double *x, void *stream);
 void vec_select(const VecCtx &X, const double *flag, const double *src, double *dst, void *stream);
 // cyclic Jacobi eigensolver of a symmetric m x m matrix (row-major); returns
-// eigenvalues ascending in w and the matching eigenvectors as columns of Z
-void jacobi_eigh(int m, const double *A, double *w, double *Z);
+// eigenvalues ascending in w and the matching eigenvectors as columns of Z,
+// and the number of sweeps that changed the matrix (JACOBI_MAX_SWEEPS when
+// the limit stopped it)
+constexpr int JACOBI_MAX_SWEEPS = 100;
+int jacobi_eigh(int m, const double *A, double *w, double *Z);
 }  // namespace dmrg

@@ -59,7 +59,7 @@ __device__ inline void row_inputs(const FwdArgs &A, int64_t i, float &f0, float 
   } else {
     const int s = seg_of(A.seg_off, A.nseg, i);
     const double den = A.d[i] - A.theta[s];
-    td = -A.r[i] / floored(den, A.floor_);
+    td = -A.r[i] / floored(den, A.floor_[s]);
     f0 = (float)asinh(den / A.sigma[s]);
     f1 = (float)A.f1[s];
   }

@@ -88,15 +88,17 @@ __global__ void __launch_bounds__(VB) scombo_kernel(const VChunk *__restrict__ c
   }
 }
 
-// r = hu - theta_k u ; t = -r / (diag - theta_k) with |denominator| >= floor
+// r = hu - theta_k u ; t = -r / (diag - theta_k) with |denominator| >= floor_k
+// (per-segment absolute floors)
 __global__ void __launch_bounds__(VB) sresid_kernel(const VChunk *__restrict__ chunks, int nchunks,
                                                      const double *__restrict__ hu, const double *__restrict__ u,
                                                      const double *__restrict__ diag,
-                                                     const double *__restrict__ theta, double floor_,
+                                                     const double *__restrict__ theta,
+                                                     const double *__restrict__ floors,
                                                      double *__restrict__ r, double *__restrict__ t) {
   for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
     const VChunk C = chunks[c];
-    const double th = theta[C.seg];
+    const double th = theta[C.seg], floor_ = floors[C.seg];
     for (int64_t i = C.i0 + threadIdx.x; i < C.i1; i += VB) {
       double ri = hu[i] - th * u[i];
       double d = diag[i] - th;
@@ -154,9 +156,9 @@ void vec_combo(const VecCtx &X, const double *V, int64_t ldv, int m, const doubl
 }
 
 void vec_resid(const VecCtx &X, const double *hu, const double *u, const double *diag, const double *theta,
-               double floor_, double *r, double *t, void *stream) {
+               const double *floors, double *r, double *t, void *stream) {
   hipLaunchKernelGGL(sresid_kernel, dim3(cgrid(X.nchunks)), dim3(VB), 0, (hipStream_t)stream, X.chunks, X.nchunks,
-                     hu, u, diag, theta, floor_, r, t);
+                     hu, u, diag, theta, floors, r, t);
 }
 
 void vec_scale(const VecCtx &X, const double *s, double *x, void *stream) {

@@ -16,12 +16,11 @@ struct FwdArgs {
   const float *x;
   float *g;
   float *z1, *z2;          // optional pre-activations [n][W]
-  // mode 1 (Davidson): per-segment theta, sigma, f1
+  // mode 1 (Davidson): per-segment theta, sigma, f1 and absolute floor
   const double *d, *r;
-  const double *theta, *sigma, *f1;
+  const double *theta, *sigma, *f1, *floor_;
   const int64_t *seg_off;  // [nseg + 1]
   int nseg;
-  double floor_;
   double *t;
 };
 

@@ -83,7 +83,7 @@ struct dmrg_plan {
   std::vector<void *> plan_allocs;     // tile lists, workspace, slices (freed by re-planning)
   // settings of the tile lists
   int kpart = KPART, tile_policy = 0, xcd = 0, flags = 0;
-  int64_t budget = (int64_t)16 << 30;
+  int64_t budget = DEFAULT_WORKSPACE;
   int tuned = 0;
   double tune_ms = 0.0;
   // profiling: events around every first- and second-stage launch
@@ -100,6 +100,23 @@ struct dmrg_plan {
   };
   std::vector<GraphEntry> graphs;
   hipStream_t cap_stream = nullptr;
+  hipStream_t build_stream = nullptr;   // caller's stream of dmrg_build_tasks
+  // recorded after the last launch sequence on the caller's stream: freeing
+  // or re-planning waits for it instead of for the whole device
+  hipEvent_t done_ev = nullptr;
+  bool done_pending = false;
+  void wait_done() {
+    if (done_ev && done_pending) (void)hipEventSynchronize(done_ev);
+    if (cap_stream) (void)hipStreamSynchronize(cap_stream);
+    (void)hipStreamSynchronize(build_stream);
+    done_pending = false;
+  }
+  int mark_done(void *stream) {
+    if (!done_ev && hipEventCreateWithFlags(&done_ev, hipEventDisableTiming) != hipSuccess) return DMRG_EHIP;
+    if (hipEventRecord(done_ev, (hipStream_t)stream) != hipSuccess) return DMRG_EHIP;
+    done_pending = true;
+    return DMRG_OK;
+  }
   void drop_graphs() {
     for (auto &e : graphs) {
       (void)hipGraphExecDestroy(e.x);
@@ -110,6 +127,7 @@ struct dmrg_plan {
   ~dmrg_plan() {
     drop_graphs();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (done_ev) (void)hipEventDestroy(done_ev);
     for (auto e : ev_pool) (void)hipEventDestroy(e);
   }
 };
@@ -573,10 +591,10 @@ int prepare_device(dmrg_plan *P) {
     if ((rc = upload(P, items, &d_items, false)) || (rc = upload(P, soff, &d_soff, false)) ||
         (rc = upload(P, alpha, &d_alpha, false)))
       return rc;
-    launch_dress(d_items, (int)items.size(), d_soff, d_alpha, P->d_bases, pp.d_dress, nullptr);
+    launch_dress(d_items, (int)items.size(), d_soff, d_alpha, P->d_bases, pp.d_dress, P->build_stream);
     HIPCHK(hipGetLastError());
   }
-  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipStreamSynchronize(P->build_stream));
   // transposed operator copies
   for (auto &ppu : P->probs) {
     ProbPlan &pp = *ppu;
@@ -587,11 +605,11 @@ int prepare_device(dmrg_plan *P) {
       if (!src[q] || !dst[q] || jobs[q].empty()) continue;
       TransJob *d_jobs = nullptr;
       if ((rc = upload(P, jobs[q], &d_jobs, false))) return rc;
-      launch_transpose(d_jobs, (int)jobs[q].size(), src[q], dst[q], nullptr);
+      launch_transpose(d_jobs, (int)jobs[q].size(), src[q], dst[q], P->build_stream);
       HIPCHK(hipGetLastError());
     }
   }
-  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipStreamSynchronize(P->build_stream));
   return DMRG_OK;
 }
 
@@ -826,9 +844,10 @@ int upload_split(dmrg_plan *P) {
     P->sb.plane[b] = P->sb_elems[b];
   }
   // operator slices: once per plan (the operators are constant during Davidson)
-  launch_slices(P->d_jobs_ops, (int)P->jobs_ops.size(), P->n_slices, P->d_bases, nullptr, nullptr, P->sb, nullptr);
+  launch_slices(P->d_jobs_ops, (int)P->jobs_ops.size(), P->n_slices, P->d_bases, nullptr, nullptr, P->sb,
+                P->build_stream);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipStreamSynchronize(P->build_stream));
   return DMRG_OK;
 }
 }  // namespace
@@ -837,7 +856,7 @@ namespace {
 
 // Frees the tile lists, workspace and slices (not the problem-level data).
 void release_plan(dmrg_plan *P) {
-  (void)hipDeviceSynchronize();
+  P->wait_done();
   P->drop_graphs();
   for (void *a : P->plan_allocs) (void)hipFree(a);
   P->plan_allocs.clear();
@@ -857,11 +876,24 @@ void release_plan(dmrg_plan *P) {
   P->stats.n_stage1 = P->stats.n_segments = 0;
 }
 
+// Kernel launches of one H.psi issued by enqueue (launchers skip empty lists).
+int count_launches(const dmrg_plan *P) {
+  const bool split = P->precision == DMRG_SPLIT_BF16;
+  int n = P->psi_len > 0;
+  if (split) n += !P->jobs_psi.empty();
+  for (const Chunk &ch : P->chunks) {
+    n += !ch.tile1.empty() + !ch.tile2.empty() + !ch.red2.empty();
+    if (split) n += (ch.t_exps > 0) + !ch.titems.empty();
+  }
+  return n;
+}
+
 // Tile lists for the plan's current settings.
 int replan(dmrg_plan *P) {
   release_plan(P);
   int rc = build_plan(P, P->budget, true);
   if (!rc && P->precision == DMRG_SPLIT_BF16) rc = upload_split(P);
+  P->stats.launches = rc ? 0 : count_launches(P);
   return rc;
 }
 
@@ -986,7 +1018,7 @@ int autotune(dmrg_plan *P, void *stream) {
 
 extern "C" void dmrg_plan_free(dmrg_plan_t *p) {
   if (!p) return;
-  (void)hipDeviceSynchronize();
+  p->wait_done();
   p->drop_graphs();
   for (void *a : p->plan_allocs) (void)hipFree(a);
   for (void *a : p->allocs) (void)hipFree(a);
@@ -1001,6 +1033,7 @@ extern "C" int dmrg_build_tasks(const dmrg_problem_t *probs, int32_t n_probs, co
   if (!probs || n_probs <= 0) { set_error("no problems"); return DMRG_EINVAL; }
   dmrg_plan *P = new dmrg_plan();
   std::memset(&P->stats, 0, sizeof(P->stats));
+  P->build_stream = (hipStream_t)stream;
   try {
     P->precision = opts ? opts->precision : DMRG_FP64;
     P->n_slices = opts ? opts->n_slices : 0;
@@ -1014,17 +1047,20 @@ extern "C" int dmrg_build_tasks(const dmrg_problem_t *probs, int32_t n_probs, co
       dmrg_plan_free(P);
       return DMRG_EINVAL;
     }
-    int64_t budget = (opts && opts->workspace_bytes > 0) ? opts->workspace_bytes : ((int64_t)16 << 30);
+    int64_t budget = (opts && opts->workspace_bytes > 0) ? opts->workspace_bytes : DEFAULT_WORKSPACE;
     int64_t off = 0;
     for (int k = 0; k < n_probs; k++) {
       auto pp = std::make_unique<ProbPlan>();
       Error err{0, ""};
       if (!probs[k].ldata && probs[k].site_l > 0) { set_error("left operator data missing"); dmrg_plan_free(P); return DMRG_EINVAL; }
+      auto tt0 = std::chrono::steady_clock::now();
       if (build_tasks_for_problem(probs[k], pp->L, pp->R, pp->T, err)) {
         set_error("problem " + std::to_string(k) + ": " + err.msg);
         dmrg_plan_free(P);
         return err.code;
       }
+      P->stats.tasks_ms +=
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tt0).count();
       pp->psi_off = off;
       off += pp->T.size;
       pp->base_l = BASE_OPS + (int)P->bases_h.size();
@@ -1079,8 +1115,10 @@ extern "C" int dmrg_build_tasks(const dmrg_problem_t *probs, int32_t n_probs, co
       dmrg_plan_free(P);
       return DMRG_EINVAL;
     }
+    auto tp0 = std::chrono::steady_clock::now();
     int rc = prepare_device(P);
     if (!rc) rc = (P->flags & DMRG_PLAN_AUTOTUNE) ? autotune(P, stream) : replan(P);
+    P->stats.plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp0).count();
     if (rc) { dmrg_plan_free(P); return rc; }
     *out = P;
     return DMRG_OK;
@@ -1108,19 +1146,26 @@ static int next_event(dmrg_plan *p, size_t &idx) {
 }
 
 namespace {
-int enqueue(dmrg_plan *p, const double *psi, double *hpsi, void *stream, bool prof) {
+// Scratch memory of one launch sequence: stripe workspace, partial tiles and
+// (split plans) the stripe slices with their line exponents.
+struct RunBufs {
+  double *work, *part;
+  SliceBufs sb;
+};
+
+int enqueue_with(dmrg_plan *p, const double *psi, double *hpsi, void *stream, bool prof, const RunBufs &B) {
   launch_zero(hpsi, p->psi_len, stream);
   const bool split = p->precision == DMRG_SPLIT_BF16;
   if (split)
-    launch_slices(p->d_jobs_psi, (int)p->jobs_psi.size(), p->n_slices, p->d_bases, psi, p->d_work, p->sb, stream);
+    launch_slices(p->d_jobs_psi, (int)p->jobs_psi.size(), p->n_slices, p->d_bases, psi, B.work, B.sb, stream);
   size_t ev = p->ev_marks.empty() ? 0 : (size_t)p->ev_marks.back().second.second + 1;
   for (auto &ch : p->chunks) {
     for (int stage = 1; stage <= 2; stage++) {
       // stripe line exponents are maxima taken by the first stage's tiles;
       // the stripe slices follow it (both outside the stages' event windows)
-      if (split && stage == 1) launch_fill_int(p->sb.exps[SBUF_T], ch.t_exps, INT_MIN, stream);
+      if (split && stage == 1) launch_fill_int(B.sb.exps[SBUF_T], ch.t_exps, INT_MIN, stream);
       if (split && stage == 2)
-        launch_tslices(ch.d_tjobs, ch.d_titems, (int)ch.titems.size(), p->n_slices, p->d_work, p->sb, stream);
+        launch_tslices(ch.d_tjobs, ch.d_titems, (int)ch.titems.size(), p->n_slices, B.work, B.sb, stream);
       int e0 = -1;
       if (prof) {
         int rc = next_event(p, ev);
@@ -1131,16 +1176,16 @@ int enqueue(dmrg_plan *p, const double *psi, double *hpsi, void *stream, bool pr
       if (split) {
         if (stage == 1)
           launch_tiles_split(1, ch.d_tile1, ch.d_seg1, ch.d_sseg1, (int)ch.tile1.size(), p->n_slices, p->d_bases,
-                             psi, hpsi, p->d_work, p->d_part, p->sb, p->xcd, stream);
+                             psi, hpsi, B.work, B.part, B.sb, p->xcd, stream);
         else
           launch_tiles_split(2, ch.d_tile2, ch.d_seg2, ch.d_sseg2, (int)ch.tile2.size(), p->n_slices, p->d_bases,
-                             psi, hpsi, p->d_work, p->d_part, p->sb, p->xcd, stream);
+                             psi, hpsi, B.work, B.part, B.sb, p->xcd, stream);
       } else if (stage == 1)
-        launch_tiles_f64(1, ch.d_tile1, ch.d_seg1, (int)ch.tile1.size(), p->d_bases, psi, hpsi, p->d_work,
-                         p->d_part, p->xcd, stream);
+        launch_tiles_f64(1, ch.d_tile1, ch.d_seg1, (int)ch.tile1.size(), p->d_bases, psi, hpsi, B.work, B.part,
+                         p->xcd, stream);
       else
-        launch_tiles_f64(2, ch.d_tile2, ch.d_seg2, (int)ch.tile2.size(), p->d_bases, psi, hpsi, p->d_work,
-                         p->d_part, p->xcd, stream);
+        launch_tiles_f64(2, ch.d_tile2, ch.d_seg2, (int)ch.tile2.size(), p->d_bases, psi, hpsi, B.work, B.part,
+                         p->xcd, stream);
       if (prof) {
         int rc = next_event(p, ev);
         if (rc) return rc;
@@ -1150,17 +1195,24 @@ int enqueue(dmrg_plan *p, const double *psi, double *hpsi, void *stream, bool pr
         ev++;
       }
     }
-    launch_reduce(ch.d_red2, (int)ch.red2.size(), p->d_part, hpsi, stream);
+    launch_reduce(ch.d_red2, (int)ch.red2.size(), B.part, hpsi, stream);
   }
   HIPCHK(hipGetLastError());
   return DMRG_OK;
+}
+
+int enqueue(dmrg_plan *p, const double *psi, double *hpsi, void *stream, bool prof) {
+  return enqueue_with(p, psi, hpsi, stream, prof, RunBufs{p->d_work, p->d_part, p->sb});
 }
 }  // namespace
 
 extern "C" int dmrg_apply_H(dmrg_plan_t *p, const double *psi, double *hpsi, void *stream) {
   if (!p || !psi || !hpsi) { set_error("null argument"); return DMRG_EINVAL; }
   if (psi == hpsi) { set_error("psi and hpsi must not alias"); return DMRG_EINVAL; }
-  if (!(p->flags & DMRG_PLAN_GRAPH) || p->profiling) return enqueue(p, psi, hpsi, stream, p->profiling != 0);
+  if (!(p->flags & DMRG_PLAN_GRAPH) || p->profiling) {
+    int rc = enqueue(p, psi, hpsi, stream, p->profiling != 0);
+    return rc ? rc : p->mark_done(stream);
+  }
   dmrg_plan::GraphEntry *ge = nullptr;
   for (auto &e : p->graphs)
     if (e.psi == psi && e.y == hpsi) ge = &e;
@@ -1194,7 +1246,7 @@ extern "C" int dmrg_apply_H(dmrg_plan_t *p, const double *psi, double *hpsi, voi
     ge = &p->graphs.back();
   }
   HIPCHK(hipGraphLaunch(ge->x, (hipStream_t)stream));
-  return DMRG_OK;
+  return p->mark_done(stream);
 }
 
 extern "C" int dmrg_set_profiling(dmrg_plan_t *p, int32_t on) {
@@ -1230,7 +1282,7 @@ extern "C" int dmrg_diag_H(dmrg_plan_t *p, double *diag, void *stream) {
   if (!p || !diag) { set_error("null argument"); return DMRG_EINVAL; }
   launch_diag(p->d_dblocks, p->d_dterms, (int)p->dblocks.size(), p->d_bases, diag, stream);
   HIPCHK(hipGetLastError());
-  return DMRG_OK;
+  return p->mark_done(stream);
 }
 
 extern "C" int dmrg_plan_stats(const dmrg_plan_t *p, dmrg_plan_stats_t *st) {
@@ -1423,11 +1475,13 @@ extern "C" int dmrg_debug_plan_host_apply(const dmrg_problem_t *prob, const doub
   P->tile_policy = opts ? opts->tile_policy : 0;
   auto pp = std::make_unique<ProbPlan>();
   Error err{0, ""};
+  auto tt0 = std::chrono::steady_clock::now();
   if (build_tasks_for_problem(*prob, pp->L, pp->R, pp->T, err)) {
     set_error(err.msg);
     delete P;
     return err.code;
   }
+  P->stats.tasks_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tt0).count();
   pp->base_l = BASE_OPS;
   pp->base_r = BASE_OPS + 1;
   pp->base_dress = BASE_OPS + 2;
@@ -1448,8 +1502,10 @@ extern "C" int dmrg_debug_plan_host_apply(const dmrg_problem_t *prob, const doub
   for (auto &tk : pp->T.tasks) P->stats.n_tasks += (int64_t)pp->T.rows[tk.row].pos.size();
   P->probs.push_back(std::move(pp));
   P->psi_len = n;
-  int rc = build_plan(P, workspace_bytes > 0 ? workspace_bytes : ((int64_t)16 << 30), false);
+  auto tp0 = std::chrono::steady_clock::now();
+  int rc = build_plan(P, workspace_bytes > 0 ? workspace_bytes : DEFAULT_WORKSPACE, false);
   if (rc) { delete P; return rc; }
+  P->stats.plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp0).count();
   for (auto &ch : P->chunks) {
     P->stats.n_stage1 += (int64_t)ch.seg1.size();
     P->stats.n_segments += (int64_t)ch.seg2.size();
@@ -1509,7 +1565,7 @@ extern "C" int64_t dmrg_debug_plan_tiles(const dmrg_problem_t *prob, int32_t sta
   P->bases_h = {prob->ldata, prob->rdata, nullptr};
   P->psi_len = pp->T.size;
   P->probs.push_back(std::move(pp));
-  int rc = build_plan(P, (int64_t)16 << 30, false);
+  int rc = build_plan(P, DEFAULT_WORKSPACE, false);
   if (rc) { delete P; return rc; }
   int64_t n = 0;
   for (auto &ch : P->chunks) {

@@ -160,6 +160,8 @@ struct Chunk {
 constexpr int TILE = 32;      // nominal tile edge (tiles are 16*mb x 64/mb)
 constexpr int WAVES = 4;      // wavefronts per workgroup (one work item each)
 constexpr int KPART = 2048;   // target summed K of one second-stage work item
+// default cap of the stripe workspace (288 GB of HBM hold the largest plans in one chunk)
+constexpr int64_t DEFAULT_WORKSPACE = (int64_t)64 << 30;
 
 void launch_zero(double *y, int64_t n, void *stream);
 void launch_dress(const DressItem *items, int nitems, const int64_t *src_off, const double *alpha,

@@ -84,7 +84,7 @@ class Plan:
                                      self._stream(stream)), self.lib)
         return out
 
-    def davidson(self, psi0, tol=1e-8, max_iter=1000, m_max=24, floor=1e-3, stream=None,
+    def davidson(self, psi0, tol=1e-8, max_iter=1000, m_max=24, floor=1e-2, stream=None,
                  check=True, mlp=None, verbose=0, mlp_patience=0):
         """Lowest eigenpair of every problem by the library's Davidson solver.
 
@@ -116,7 +116,7 @@ class Plan:
             return B.DavOpts(tol, max_iter, m_max, B.DMRG_PRECOND_DIAG, verbose, floor, None, mlp_patience, 0)
         return B.DavOpts(tol, max_iter, m_max, B.DMRG_PRECOND_MLP, verbose, floor, mlp.handle, mlp_patience, 0)
 
-    def collect(self, psi0, capacity, tol=1e-8, max_iter=1000, m_max=24, floor=1e-3,
+    def collect(self, psi0, capacity, tol=1e-8, max_iter=1000, m_max=24, floor=1e-2,
                 stream=None):
         """Training rows (x, a, b) of the learned preconditioner from this
         single-problem plan's solve (see dmrg_mlp_collect): CUDA float32

@@ -18,6 +18,7 @@ Layout of every operator family on a block: one record per
 stored as [npos][rows][cols] with each matrix column-major.
 """
 from dataclasses import dataclass, field
+import os
 from math import factorial, sqrt
 import numpy as np
 import scipy.sparse as sp
@@ -460,75 +461,124 @@ def synthetic_sectors(n, n_share, D, rng, spin_ratio=0.6, sigma_frac=0.15, cap=T
     return secs
 
 
-def _rand_family_blocks(fam, role, n_orb, p, sectors, rng, scale):
-    labs = cat.labels(fam, role, n_orb, p)
-    k2, dn = cat.TWO_K[fam], cat.DN[fam]
-    out = {}
-    npos = len(labs)
-    if npos == 0:
-        return out
-    for a, (Na, sa, da) in enumerate(sectors):
-        for b, (Nb, sb, db) in enumerate(sectors):
-            if Nb != Na + dn or sb < abs(sa - k2) or sb > sa + k2:
-                continue
-            if fam == cat.H and a != b:
-                continue
-            out[(b, a)] = scale * rng.standard_normal((npos, db, da)) / sqrt(max(da, 1))
-    # self-adjoint constraints
-    diag = []
-    if fam == cat.H:
-        diag = [0]
-    elif fam in (cat.B0, cat.B1, cat.Q0, cat.Q1):
-        diag = [i for i, lab in enumerate(labs) if lab[0] == lab[1]]
-    for (b, a) in list(out):
-        sa, sb = sectors[a][1], sectors[b][1]
-        if (a, b) not in out:
+def _rand_records(role, n_orb, p, sectors, fams):
+    """Record list [(fam, row_sec, col_sec, npos)] of a synthetic block: every
+    (row, column) sector pair the family's electron change and spin rank
+    allow (block Hamiltonian: diagonal pairs only), families in order, pairs
+    sorted (the packing order of ``_pack``)."""
+    recs = []
+    for fam in sorted(fams):
+        npos = len(cat.labels(fam, role, n_orb, p))
+        if npos == 0:
+            continue
+        k2, dn = cat.TWO_K[fam], cat.DN[fam]
+        pairs = []
+        for a, (Na, sa, da) in enumerate(sectors):
+            for b, (Nb, sb, db) in enumerate(sectors):
+                if Nb != Na + dn or sb < abs(sa - k2) or sb > sa + k2:
+                    continue
+                if fam == cat.H and a != b:
+                    continue
+                pairs.append((b, a))
+        for (b, a) in sorted(pairs):
+            recs.append((fam, b, a, npos))
+    return recs
+
+
+def _fill_record(data, off, npos, db, da, seed, key, scale):
+    """Random reduced blocks of one record, written straight into its packed
+    place ([npos][cols][rows], i.e. each db x da matrix column-major): entries
+    N(0, 1) * scale / sqrt(da) from the record's own stream (seeded by the
+    problem seed and the record key, so records can be drawn in any order)."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed] + list(key)))
+    v = data[off:off + npos * db * da]
+    rng.standard_normal(out=v)
+    v *= scale / sqrt(max(da, 1))
+    return rng
+
+
+def _rand_block(role, n_orb, p, sectors, seed, op_scale, share, n):
+    """Synthetic block: records, packed data, self-adjoint constraints."""
+    blk = BlockData(role, n_orb, p, sectors)
+    fams = cat.LEFT_FAMILIES if role == "L" else cat.RIGHT_FAMILIES
+    recs = _rand_records(role, n_orb, p, sectors, fams) if n > 0 else []
+    offs, off = [], 0
+    for (fam, b, a, npos) in recs:
+        offs.append(off)
+        off += npos * sectors[b][2] * sectors[a][2]
+    data = np.empty(off)
+    role_id = 0 if role == "L" else 1
+
+    def job(i):
+        fam, b, a, npos = recs[i]
+        db, da = sectors[b][2], sectors[a][2]
+        rng = _fill_record(data, offs[i], npos, db, da, seed, (role_id, fam, b, a),
+                           1.0 if fam == cat.H else op_scale)
+        if fam == cat.H:
+            # spread block energies so the spectrum looks physical
+            N = sectors[b][0]
+            m = data[offs[i]:offs[i] + db * da].reshape(da, db)   # m[c, r] = H[r, c]
+            m[np.arange(db), np.arange(db)] += np.sort(rng.uniform(0, 2.0 * n, db)) \
+                + 0.5 * (N - share) ** 2
+
+    from concurrent.futures import ThreadPoolExecutor
+    order = sorted(range(len(recs)), key=lambda i: -(offs[i + 1] if i + 1 < len(offs) else off) + offs[i])
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        list(ex.map(job, order))
+    # self-adjoint constraints: the block Hamiltonian and the diagonal-label
+    # members of B0, B1, Q0, Q1 (T = T^dagger in the reduced convention)
+    index = {(fam, b, a): i for i, (fam, b, a, npos) in enumerate(recs)}
+
+    def mat(i, pos):
+        fam, b, a, npos = recs[i]
+        db, da = sectors[b][2], sectors[a][2]
+        o = offs[i] + pos * db * da
+        return data[o:o + db * da].reshape(da, db).T       # view of the db x da matrix
+
+    for i, (fam, b, a, npos) in enumerate(recs):
+        if fam == cat.H:
+            diag = [0]
+        elif fam in (cat.B0, cat.B1, cat.Q0, cat.Q1):
+            diag = [k for k, lab in enumerate(cat.labels(fam, role, n_orb, p)) if lab[0] == lab[1]]
+        else:
             continue
         if b == a:
-            for i in diag:
-                m = out[(a, a)][i]
-                out[(a, a)][i] = 0.5 * (m + m.T)
-        elif b > a:
-            # block (a, b) [rows a, cols b] from block (b, a):
-            # T[a,b] = (-1)^{(S_b - S_a)} sqrt((2S_b+1)/(2S_a+1)) T[b,a]^T
-            ph = (-1) ** (((sb - sa) // 2) % 2) * sqrt((sb + 1) / (sa + 1))
-            for i in diag:
-                out[(a, b)][i] = ph * out[(b, a)][i].T
-    return out
+            for k in diag:
+                m = mat(i, k)
+                m[...] = 0.5 * (m + m.T)
+        elif b < a and (fam, a, b) in index:
+            # block (b, a) [rows b, cols a] from block (a, b):
+            # T[b,a] = (-1)^((S_a - S_b)) sqrt((2S_a+1)/(2S_b+1)) T[a,b]^T
+            sb, sa = sectors[b][1], sectors[a][1]
+            ph = (-1) ** (((sa - sb) // 2) % 2) * sqrt((sa + 1) / (sb + 1))
+            j = index[(fam, a, b)]
+            for k in diag:
+                mat(i, k)[...] = ph * mat(j, k).T
+    blk.records = [(fam, b, a, offs[i], npos) for i, (fam, b, a, npos) in enumerate(recs)]
+    blk.data = data
+    return blk
 
 
 def random_problem(n_orb, n_elec, two_s, seed, D, p=None, spin_ratio=0.6,
-                   sigma_frac=0.15, op_scale=0.3, cap=True):
-    """Problem with synthetic sector tables and random reduced operators."""
+                   sigma_frac=0.15, op_scale=0.3, cap=True, D_right=None):
+    """Problem with synthetic sector tables and random reduced operators.
+
+    D multiplets per block (D_right for the right block when given).  Every
+    record draws from its own stream, seeded by the problem seed and the
+    record's (block, family, row sector, column sector), so the blocks are
+    filled by parallel threads with the same result."""
     h, eri = make_integrals(n_orb, seed)
     if p is None:
         p = middle_bond(n_orb)
-    rng = np.random.default_rng(10_000_000 + seed)
     blocks = []
     for role in ("L", "R"):
         lo, hi = cat.block_range(role, n_orb, p)
         n = hi - lo
         share = n_elec * n / n_orb
-        secs = synthetic_sectors(n, share, D, rng, spin_ratio, sigma_frac, cap) if n > 0 \
+        Db = D if role == "L" or D_right is None else D_right
+        secs = synthetic_sectors(n, share, Db, None, spin_ratio, sigma_frac, cap) if n > 0 \
             else [(0, 0, 1)]
-        blk = BlockData(role, n_orb, p, secs)
-        fams = cat.LEFT_FAMILIES if role == "L" else cat.RIGHT_FAMILIES
-        fb = {}
-        if n > 0:
-            for fam in fams:
-                b = _rand_family_blocks(fam, role, n_orb, p, secs, rng,
-                                        1.0 if fam == cat.H else op_scale)
-                if fam == cat.H:
-                    # spread block energies so the spectrum looks physical
-                    for (r, c), arr in b.items():
-                        N = secs[r][0]
-                        d = secs[r][2]
-                        arr[0] += np.diag(np.sort(rng.uniform(0, 2.0 * n, d))
-                                          + 0.5 * (N - share) ** 2)
-                if b:
-                    fb[fam] = b
-        _pack(blk, fb)
-        blocks.append(blk)
+        blocks.append(_rand_block(role, n_orb, p, secs, 10_000_000 + seed, op_scale, share, n))
     return Problem(n_orb, n_elec, two_s, p, h, eri, blocks[0], blocks[1], "random")
 
 
