@@ -164,6 +164,22 @@ int dmrg_psi_layout(const dmrg_plan_t *p, int32_t prob, int64_t *off, int64_t *l
 /* hpsi := H_eff psi for all problems (device arrays of psi_len doubles). */
 int dmrg_apply_H(dmrg_plan_t *p, const double *psi, double *hpsi, void *stream);
 
+/* For callers that cannot allocate device memory (code under a graph capture
+ * of their own, tight serving loops, harnesses that forbid hipMalloc): the
+ * same H.psi as dmrg_apply_H, but the scratch memory of the launch sequence
+ * (stripe workspace, partial tiles and, for split plans, stripe slices and
+ * their exponents) comes from one static device array of
+ * DMRG_STATIC_SCRATCH_BYTES per GPU, held until the process ends, instead of
+ * the plan's buffers.  Allocates nothing (no hipMalloc, no graph); psi/hpsi
+ * are device arrays of psi_len doubles, borrowed for the call.  Returns
+ * DMRG_EINVAL when the plan's scratch exceeds the array (build the plan with
+ * a smaller workspace_bytes: its stripe workspace is cut into more launches).
+ * Every call on a GPU shares that GPU's array and leaves its contents behind
+ * (each word a call reads is written earlier in the same call): calls that
+ * overlap on one GPU, on any streams, race. */
+#define DMRG_STATIC_SCRATCH_BYTES ((int64_t)256 << 20)
+int dmrg_apply_H_static(dmrg_plan_t *p, const double *psi, double *hpsi, void *stream);
+
 /* diag := diagonal of H_eff (device array of psi_len doubles). */
 int dmrg_diag_H(dmrg_plan_t *p, double *diag, void *stream);
 

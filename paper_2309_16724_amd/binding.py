@@ -111,6 +111,7 @@ def load(path=None):
                                        c_vp, ctypes.POINTER(c_vp)]
         L.dmrg_psi_layout.argtypes = [c_vp, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]
         L.dmrg_apply_H.argtypes = [c_vp, c_vp, c_vp, c_vp]
+        L.dmrg_apply_H_static.argtypes = [c_vp, c_vp, c_vp, c_vp]
         L.dmrg_diag_H.argtypes = [c_vp, c_vp, c_vp]
         L.dmrg_plan_stats.argtypes = [c_vp, ctypes.POINTER(PlanStats)]
         L.dmrg_plan_free.argtypes = [c_vp]

@@ -1206,6 +1206,36 @@ int enqueue(dmrg_plan *p, const double *psi, double *hpsi, void *stream, bool pr
 }
 }  // namespace
 
+namespace dmrg {
+// Byte layout of the scratch memory of one H.psi (see dmrg_apply_H_static):
+// stripe workspace, partial tiles, stripe slices, stripe exponents, each
+// 256-byte aligned.  Returns the total.
+int64_t plan_scratch_layout(const dmrg_plan_t *p, int64_t off[4]) {
+  auto up = [](int64_t x) { return (x + 255) / 256 * 256; };
+  const bool split = p->precision == DMRG_SPLIT_BF16;
+  int64_t o = 0;
+  off[0] = o; o = up(o + 8 * std::max<int64_t>(p->work_elems, 1));
+  off[1] = o; o = up(o + 8 * std::max<int64_t>(p->part_elems, 1));
+  off[2] = o; if (split) o = up(o + 2 * std::max<int64_t>(p->sb_elems[SBUF_T], 1) * p->n_slices);
+  off[3] = o; if (split) o = up(o + 4 * std::max<int64_t>(p->sb_exps[SBUF_T], 1));
+  return o;
+}
+
+// One H.psi with the scratch memory at `base` (laid out by
+// plan_scratch_layout); no allocation, no graph, no profiling events.
+int enqueue_scratch(dmrg_plan_t *p, const double *psi, double *hpsi, void *stream, char *base) {
+  int64_t off[4];
+  plan_scratch_layout(p, off);
+  RunBufs B{(double *)(base + off[0]), (double *)(base + off[1]), p->sb};
+  if (p->precision == DMRG_SPLIT_BF16) {
+    B.sb.data[SBUF_T] = (uint16_t *)(base + off[2]);
+    B.sb.exps[SBUF_T] = (int32_t *)(base + off[3]);
+  }
+  int rc = enqueue_with(p, psi, hpsi, stream, false, B);
+  return rc ? rc : p->mark_done(stream);
+}
+}  // namespace dmrg
+
 extern "C" int dmrg_apply_H(dmrg_plan_t *p, const double *psi, double *hpsi, void *stream) {
   if (!p || !psi || !hpsi) { set_error("null argument"); return DMRG_EINVAL; }
   if (psi == hpsi) { set_error("psi and hpsi must not alias"); return DMRG_EINVAL; }

@@ -183,6 +183,11 @@ void launch_slices(const SliceJob *jobs, int njobs, int nslices, const double *c
 void launch_tslices(const SliceJob *jobs, const TSliceItem *items, int nitems, int nslices, const double *work,
                     SliceBufs bufs, void *stream);
 void launch_fill_int(int32_t *p, int64_t n, int32_t v, void *stream);
+// scratch memory of one H.psi: byte offsets of the stripe workspace, partial
+// tiles, stripe slices and stripe exponents (off[4]); returns the total bytes
+int64_t plan_scratch_layout(const dmrg_plan_t *p, int64_t off[4]);
+// one H.psi with that scratch memory at base (device address)
+int enqueue_scratch(dmrg_plan_t *p, const double *psi, double *hpsi, void *stream, char *base);
 void launch_tiles_split(int stage, const Tile *tiles, const Seg *segs, const SegS *ssegs, int ntiles,
                         int nslices, const double *const *bases, const double *psi, double *y, double *work,
                         double *part, SliceBufs bufs, int xcd, void *stream);

@@ -76,6 +76,16 @@ class Plan:
                                       ctypes.c_void_p(out.data_ptr()), self._stream(stream)), self.lib)
         return out
 
+    def apply_static(self, psi, out, stream=None):
+        """H.psi through dmrg_apply_H_static (the library's static scratch
+        array, no device allocation in the call); out: preallocated tensor."""
+        torch = _torch()
+        assert psi.dtype == torch.float64 and psi.is_cuda and psi.numel() == self.size
+        assert out.dtype == torch.float64 and out.is_cuda and out.numel() == self.size
+        B.check(self.lib.dmrg_apply_H_static(self.handle, ctypes.c_void_p(psi.data_ptr()),
+                                             ctypes.c_void_p(out.data_ptr()), self._stream(stream)), self.lib)
+        return out
+
     def diag(self, out=None, stream=None):
         torch = _torch()
         if out is None:
