@@ -119,7 +119,9 @@ typedef struct {
   int32_t kpart;            /* summed K per second-stage work item, 0 = 2048 */
   int32_t tile_policy;      /* 0: 16x64 / 32x32 / 64x16 by output shape,
                                1: 32x32 except outputs of <= 16 rows          */
-  int32_t pad;
+  int32_t macro_min;        /* split plans: outputs with both sides >= this are
+                               computed in 64x64 tiles by whole work groups
+                               sharing LDS-staged operands (0: 48; < 0: never) */
 } dmrg_plan_opts_t;
 
 typedef struct dmrg_plan dmrg_plan_t;

@@ -40,7 +40,7 @@ class ProblemT(ctypes.Structure):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("precision", c_i32), ("n_slices", c_i32), ("workspace_bytes", c_i64),
-                ("flags", c_i32), ("kpart", c_i32), ("tile_policy", c_i32), ("pad", c_i32)]
+                ("flags", c_i32), ("kpart", c_i32), ("tile_policy", c_i32), ("macro_min", c_i32)]
 
 
 class DavOpts(ctypes.Structure):
@@ -174,7 +174,7 @@ class ProblemArgs:
 
 
 def debug_plan_host_apply(prob, psi, workspace_bytes=0, lib=None, precision=0, n_slices=0, kpart=0,
-                          tile_policy=0):
+                          tile_policy=0, macro_min=0):
     """Test-only: run the device plan's tile lists on the CPU (no GPU).
 
     ``psi=None`` only builds the plan and returns its statistics."""
@@ -183,7 +183,7 @@ def debug_plan_host_apply(prob, psi, workspace_bytes=0, lib=None, precision=0, n
     rd = np.ascontiguousarray(prob.right.data)
     args = ProblemArgs(prob, ld.ctypes.data, rd.ctypes.data)
     st = PlanStats()
-    opts = PlanOpts(precision, n_slices, workspace_bytes, 0, kpart, tile_policy, 0)
+    opts = PlanOpts(precision, n_slices, workspace_bytes, 0, kpart, tile_policy, macro_min)
     if psi is None:
         check(L.dmrg_debug_plan_host_apply(ctypes.byref(args.s), None, None, ctypes.byref(opts),
                                            ctypes.byref(st)), L)

@@ -48,7 +48,7 @@ int scratch_ptr(char **out) {
 extern "C" int dmrg_apply_H_static(dmrg_plan_t *p, const double *psi, double *hpsi, void *stream) {
   if (!p || !psi || !hpsi) { dmrg::set_error("null argument"); return DMRG_EINVAL; }
   if (psi == hpsi) { dmrg::set_error("psi and hpsi must not alias"); return DMRG_EINVAL; }
-  int64_t off[4];
+  int64_t off[dmrg::SCRATCH_REGIONS];
   const int64_t need = dmrg::plan_scratch_layout(p, off);
   if (need > SCRATCH_BYTES) {
     dmrg::set_error("dmrg_apply_H_static: the plan needs " + std::to_string(need) +

@@ -211,11 +211,12 @@ __global__ void reduce_kernel(const Reduce *__restrict__ red, int nred, const do
   for (int r = blockIdx.x; r < nred; r += gridDim.x) {
     const Reduce R = red[r];
     int mt = min(R.tm, R.m - R.i0);
-    int nt = min(1024 / R.tm, R.n - R.j0);
+    int nt = min(R.tn, R.n - R.j0);
+    const int64_t ps = (int64_t)R.tm * R.tn;
     for (int e = threadIdx.x; e < mt * nt; e += blockDim.x) {
       int i = e % mt, j = e / mt;
       double v = 0.0;
-      for (int p = 0; p < R.nparts; p++) v += part[R.part_off + (int64_t)p * 1024 + i + (int64_t)j * R.tm];
+      for (int p = 0; p < R.nparts; p++) v += part[R.part_off + (int64_t)p * ps + i + (int64_t)j * R.tm];
       y[R.y_off + (int64_t)(R.i0 + i) + (int64_t)(R.j0 + j) * R.ldc] += v;
     }
   }

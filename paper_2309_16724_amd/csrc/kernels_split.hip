@@ -361,6 +361,270 @@ __device__ __forceinline__ void items_split(const Tile *__restrict__ tiles, cons
   }
 }
 
+// ------------------------------------------------------------ work-group tiles
+// A 64 x 64 output tile computed by the four wavefronts of a work group: wave
+// w owns the 32 x 32 quarter (w >> 1, w & 1).  Each 32-wide K step of the
+// operands (A: 4 row blocks of 16 rows, B: 4 column blocks of 16 columns, NS
+// slices each) goes from global memory straight into one of two LDS stages --
+// wave w loads row block w and column block w, 16 bytes per lane and slice,
+// in the MFMA operand layout -- and after one barrier every wave reads the two
+// row blocks and two column blocks of its quarter.  The loads of the next step
+// (across segment boundaries) are issued before this step's MFMAs, so each
+// operand byte is fetched once per work group instead of once per wavefront,
+// and the stage's waves overlap their loads with the other work group's MFMAs
+// (two work groups per CU).
+constexpr int mstage_bytes(int ns) { return 8 * ns * 1024; }
+
+template <int NS>
+__device__ __forceinline__ void macro_split(const Tile &T, const Seg *__restrict__ segs,
+                                            const SegS *__restrict__ ssegs, const double *const *bases,
+                                            const double *psi, double *y, double *work, double *part,
+                                            const SliceBufs &bufs, char *lds, int wave, int lane) {
+  constexpr int MB = 2, NB = 2;
+  constexpr int STAGE = mstage_bytes(NS);
+  constexpr int FOLD = split_fold_k(NS);
+  static_assert(FOLD % 32 == 0, "the K loop folds after whole 32-wide steps");
+  const int r16 = lane & 15, q4 = lane >> 4;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int i0 = T.i0 + 32 * wr, j0 = T.j0 + 32 * wc;     // this wave's quarter
+  const int mrem = T.m - i0, nrem = T.n - j0;              // <= 0: quarter outside the output
+  // operand line this lane loads (row block `wave` of A, column block `wave` of
+  // B); lines past the output read the last one (never stored)
+  const uint32_t lrow = (uint32_t)min(T.i0 + 16 * wave + r16, T.m - 1);
+  const uint32_t lcol = (uint32_t)min(T.j0 + 16 * wave + r16, T.n - 1);
+  v4d acc[MB][NB];
+  for (int a = 0; a < MB; a++)
+    for (int b = 0; b < NB; b++) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  // identity left operators: exact FP64 additions of the FP64 operand
+  for (int si = 0; si < T.nseg; si++) {
+    if (ssegs[T.seg0 + si].K != 0) continue;
+    const Seg S = segs[T.seg0 + si];
+    const double *B = sbase_ptr(S.b_base, bases, psi, y, work, part) + S.b_off;
+    for (int bi = 0; bi < MB; bi++)
+      for (int bj = 0; bj < NB; bj++) {
+        const int jj = 16 * bj + r16;
+        if (jj >= nrem) continue;
+        const int n = j0 + jj;
+        const int pn = n / S.b_nb;
+        const int64_t bo = (int64_t)pn * S.b_pn + (int64_t)(n - pn * S.b_nb) * S.b_n;
+        for (int r = 0; r < 4; r++) {
+          const int i = 16 * bi + 4 * q4 + r;
+          if (i < mrem) {
+            const int k = i0 + i;
+            const int pk = k / S.b_kb;
+            acc[bi][bj][r] += S.s * B[(int64_t)pk * S.b_pk + (int64_t)(k - pk * S.b_kb) * S.b_k + bo];
+          }
+        }
+      }
+  }
+  int si = 0;
+  while (si < T.nseg && ssegs[T.seg0 + si].K == 0) si++;
+  // every wave has finished reading the LDS stages of its previous tile
+  __syncthreads();
+  if (si < T.nseg) {
+    // scale exponents of this lane's outputs (clamped inside the output)
+    auto exps = [&](const SegS &Q, int (*er)[4], int *fc) {
+      const int32_t *ea = bufs.exps[Q.a_buf] + Q.a_exp;
+      const int32_t *eb = bufs.exps[Q.b_buf] + Q.b_exp;
+      for (int bi = 0; bi < MB; bi++)
+        for (int r = 0; r < 4; r++) er[bi][r] = ea[min(i0 + 16 * bi + 4 * q4 + r, T.m - 1)];
+      for (int bj = 0; bj < NB; bj++) fc[bj] = eb[min(j0 + 16 * bj + r16, T.n - 1)];
+    };
+    // one K step of segment Q at k0 into LDS stage b (K is a multiple of 8 and
+    // lines are zero-padded to it: the chunk of 8 at min(k, K - 8) is inside
+    // the operand; lanes whose chunk starts at or past K are zeroed at the MFMA)
+    auto issue = [&](const SegS &Q, int k0, int b) {
+      const char *A = (const char *)(bufs.data[Q.a_buf] + Q.a_off);
+      const char *B = (const char *)(bufs.data[Q.b_buf] + Q.b_off);
+      const int64_t pa = 2 * bufs.plane[Q.a_buf], pb = 2 * bufs.plane[Q.b_buf];
+      const uint32_t kl = 2u * (uint32_t)min(k0 + 8 * q4, Q.K - 8);
+      const uint32_t ao = lrow * (uint32_t)Q.a_ld * 2u + kl, bo = lcol * (uint32_t)Q.b_ld * 2u + kl;
+      char *st = lds + b * STAGE;
+      for (int t = 0; t < NS; t++) {
+        __builtin_amdgcn_global_load_lds((gvptr)(A + t * pa + ao), (lvptr)(st + (wave * NS + t) * 1024), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((gvptr)(B + t * pb + bo), (lvptr)(st + ((4 + wave) * NS + t) * 1024), 16,
+                                         0, 0);
+      }
+    };
+    v4f q[MB][NB][NS];
+    for (int bi = 0; bi < MB; bi++)
+      for (int bj = 0; bj < NB; bj++)
+        for (int d = 0; d < NS; d++) q[bi][bj][d] = (v4f){0.f, 0.f, 0.f, 0.f};
+    SegS Q = ssegs[T.seg0 + si];
+    double sc = segs[T.seg0 + si].s;
+    int erow[MB][4], fcol[NB];
+    exps(Q, erow, fcol);
+    issue(Q, 0, 0);
+    int k0 = 0, b = 0;
+    for (;;) {
+      __builtin_amdgcn_s_waitcnt(WAIT_VM0);      // this wave's chunks of the step are in LDS ...
+      __syncthreads();                          // ... and every other wave's; the other stage is free
+      int nsi = si, nk0 = k0 + 32;
+      const bool newseg = nk0 >= Q.K;
+      if (newseg) {
+        nk0 = 0;
+        nsi++;
+        while (nsi < T.nseg && ssegs[T.seg0 + nsi].K == 0) nsi++;
+      }
+      const bool more = nsi < T.nseg;
+      SegS NQ = Q;
+      double nsc = sc;
+      int nerow[MB][4], nfcol[NB];
+      if (more) {
+        if (newseg) {
+          NQ = ssegs[T.seg0 + nsi];
+          nsc = segs[T.seg0 + nsi].s;
+        }
+        issue(NQ, nk0, b ^ 1);
+        if (newseg) exps(NQ, nerow, nfcol);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      v8bf as[MB][NS], bs[NB][NS];
+      const char *st = lds + b * STAGE;
+      for (int t = 0; t < NS; t++) {
+        for (int bi = 0; bi < MB; bi++) as[bi][t] = *(const lv8ptr)(st + ((2 * wr + bi) * NS + t) * 1024 + 16 * lane);
+        for (int bj = 0; bj < NB; bj++)
+          bs[bj][t] = *(const lv8ptr)(st + ((4 + 2 * wc + bj) * NS + t) * 1024 + 16 * lane);
+      }
+      __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
+      __builtin_amdgcn_sched_barrier(0);
+      if (k0 + 32 > Q.K && k0 + 8 * q4 >= Q.K)   // only the last step of a segment has such lanes
+        for (int bi = 0; bi < MB; bi++)
+          for (int t = 0; t < NS; t++) as[bi][t] = (v8bf){};
+#pragma unroll
+      for (int d = 0; d < NS; d++)
+#pragma unroll
+        for (int t = 0; t <= d; t++)
+          for (int bi = 0; bi < MB; bi++)
+            for (int bj = 0; bj < NB; bj++)
+              q[bi][bj][d] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as[bi][t], bs[bj][d - t], q[bi][bj][d], 0, 0, 0);
+      if (newseg || (k0 + 32) % FOLD == 0) {
+        for (int bi = 0; bi < MB; bi++)
+          for (int bj = 0; bj < NB; bj++)
+            for (int r = 0; r < 4; r++) {
+              double x = 0.0;   // q * 2^(-8(d+2)) is exact: the FMA rounds the sum only
+              for (int d = 0; d < NS; d++) x = fma((double)q[bi][bj][d][r], fold_scale(d), x);
+              acc[bi][bj][r] += sc * ldexp(x, erow[bi][r] + fcol[bj]);
+            }
+        for (int bi = 0; bi < MB; bi++)
+          for (int bj = 0; bj < NB; bj++)
+            for (int d = 0; d < NS; d++) q[bi][bj][d] = (v4f){0.f, 0.f, 0.f, 0.f};
+      }
+      if (!more) break;
+      if (newseg) {
+        Q = NQ;
+        sc = nsc;
+        si = nsi;
+        for (int bi = 0; bi < MB; bi++)
+          for (int r = 0; r < 4; r++) erow[bi][r] = nerow[bi][r];
+        for (int bj = 0; bj < NB; bj++) fcol[bj] = nfcol[bj];
+      }
+      k0 = nk0;
+      b ^= 1;
+    }
+  }
+  double *C = const_cast<double *>(sbase_ptr(T.c_base, bases, psi, y, work, part)) + T.c_off;
+  const int ci0 = T.ci0 + 32 * wr, cj0 = T.cj0 + 32 * wc;
+  for (int bi = 0; bi < MB; bi++)
+    for (int bj = 0; bj < NB; bj++)
+      for (int r = 0; r < 4; r++) {
+        const int i = 16 * bi + 4 * q4 + r, j = 16 * bj + r16;
+        if (i < mrem && j < nrem) {
+          double *c = T.rowmajor ? C + (int64_t)(ci0 + i) * T.ldc + (cj0 + j)
+                                 : C + (int64_t)(ci0 + i) + (int64_t)(cj0 + j) * T.ldc;
+          *c = T.accumulate ? *c + acc[bi][bj][r] : acc[bi][bj][r];
+        }
+      }
+  // first-stage tiles: exponent of every stripe column written (see item_split)
+  const SegS Q0 = ssegs[T.seg0];
+  if (Q0.t_exp >= 0) {
+    int32_t *ex = bufs.exps[SBUF_T] + Q0.t_exp;
+    for (int bj = 0; bj < NB; bj++) {
+      const int j = 16 * bj + r16;
+      double m = 0.0;
+      for (int bi = 0; bi < MB; bi++)
+        for (int r = 0; r < 4; r++) {
+          const int i = 16 * bi + 4 * q4 + r;
+          if (i < mrem && j < nrem) m = fmax(m, fabs(acc[bi][bj][r]));
+        }
+      m = fmax(m, __shfl_xor(m, 16));
+      m = fmax(m, __shfl_xor(m, 32));
+      if (q4 == 0 && j < nrem && m > 0.0) {
+        int e2;
+        const double mant = frexp(m, &e2);
+        atomicMax(ex + (cj0 + j) % Q0.t_nb, mant == 0.5 ? e2 - 1 : e2);
+      }
+    }
+  }
+}
+
+template <int NS>
+__device__ __forceinline__ void macro_items(const Tile *__restrict__ tiles, const Seg *__restrict__ segs,
+                                            const SegS *__restrict__ ssegs, const XcdQueues &q,
+                                            int32_t *__restrict__ counters,
+                                            const double *const *__restrict__ bases, const double *__restrict__ psi,
+                                            double *__restrict__ y, double *__restrict__ work,
+                                            double *__restrict__ part, const SliceBufs &bufs) {
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // all of the LDS holds the two operand stages (two work groups per CU); the
+  // tile index taken by thread 0 reaches the other wavefronts through this
+  // work group's mailbox in global memory (atomics: coherent at the L2)
+  __shared__ __attribute__((aligned(1024))) char lds[2 * mstage_bytes(NS)];
+  int32_t *mailbox = counters + NXCD + blockIdx.x;
+  // the XCD this work group runs on (HW_REG_XCC_ID); its own queue first
+  const int x = __builtin_amdgcn_s_getreg((20) | (0 << 6) | (3 << 11)) & (NXCD - 1);
+  int qi = 0;   // queues tried so far (thread 0's state)
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int t = -1;
+      for (; qi < NXCD; qi++) {
+        const int qq = (x + qi) & (NXCD - 1);
+        const int len = q.start[qq + 1] - q.start[qq];
+        if (len <= 0) continue;
+        const int k = atomicAdd(counters + qq, 1);
+        if (k < len) {
+          t = q.start[qq] + k;
+          break;
+        }
+      }
+      atomicExch(mailbox, t);
+    }
+    // every wave reads the mailbox before the barrier inside macro_split, the
+    // earliest point where thread 0 can write it again
+    __syncthreads();
+    int v = 0;
+    if (lane == 0) v = atomicAdd(mailbox, 0);
+    const int t = __builtin_amdgcn_readfirstlane(v);
+    if (t < 0) break;   // every queue is empty: the whole work group leaves
+    const Tile T = tiles[t];
+    macro_split<NS>(T, segs, ssegs, bases, psi, y, work, part, bufs, lds, wave, lane);
+  }
+}
+
+#define MACRO_KERNELS(NS)                                                                                   \
+  __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, 2)))                 \
+  stage1_msplit##NS##_kernel(const Tile *__restrict__ tiles, const Seg *__restrict__ segs,                  \
+                             const SegS *__restrict__ ssegs, XcdQueues q, int32_t *__restrict__ counters,   \
+                             const double *const *__restrict__ bases, const double *__restrict__ psi,       \
+                             double *__restrict__ y, double *__restrict__ work, double *__restrict__ part,   \
+                             SliceBufs bufs) {                                                              \
+    macro_items<NS>(tiles, segs, ssegs, q, counters, bases, psi, y, work, part, bufs);                      \
+  }                                                                                                         \
+  __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, 2)))                 \
+  stage2_msplit##NS##_kernel(const Tile *__restrict__ tiles, const Seg *__restrict__ segs,                  \
+                             const SegS *__restrict__ ssegs, XcdQueues q, int32_t *__restrict__ counters,   \
+                             const double *const *__restrict__ bases, const double *__restrict__ psi,       \
+                             double *__restrict__ y, double *__restrict__ work, double *__restrict__ part,   \
+                             SliceBufs bufs) {                                                              \
+    macro_items<NS>(tiles, segs, ssegs, q, counters, bases, psi, y, work, part, bufs);                      \
+  }
+
+MACRO_KERNELS(3)
+MACRO_KERNELS(4)
+MACRO_KERNELS(5)
+MACRO_KERNELS(6)
+MACRO_KERNELS(7)
+
 #define SPLIT_KERNELS(NS)                                                                                   \
   __global__ void __launch_bounds__(64 * WAVES) stage1_split##NS##_kernel(                                  \
       const Tile *__restrict__ tiles, const Seg *__restrict__ segs, const SegS *__restrict__ ssegs,         \
@@ -383,13 +647,40 @@ SPLIT_KERNELS(5)
 SPLIT_KERNELS(6)
 SPLIT_KERNELS(7)
 
+void launch_macro_split(int stage, const Tile *tiles, const Seg *segs, const SegS *ssegs, int ntiles,
+                        const XcdQueues &q, int32_t *counters, int nslices, const double *const *bases,
+                        const double *psi, double *y, double *work, double *part, SliceBufs bufs, void *stream) {
+  if (ntiles <= 0) return;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, s, counters, (int64_t)NXCD, 0);
+  // two work groups resident per CU (80 KiB of LDS each at s = 5); every work
+  // group takes tiles until all queues are empty
+  const int grid = std::max(8, std::min((ntiles + 7) / 8 * 8, MACRO_GRID));
+#define MLAUNCH(NS)                                                                                         \
+  if (nslices == NS) {                                                                                      \
+    if (stage == 1)                                                                                         \
+      hipLaunchKernelGGL(stage1_msplit##NS##_kernel, dim3(grid), dim3(64 * WAVES), 0, s, tiles, segs, ssegs,  \
+                         q, counters, bases, psi, y, work, part, bufs);                                     \
+    else                                                                                                    \
+      hipLaunchKernelGGL(stage2_msplit##NS##_kernel, dim3(grid), dim3(64 * WAVES), 0, s, tiles, segs, ssegs,  \
+                         q, counters, bases, psi, y, work, part, bufs);                                     \
+    return;                                                                                                 \
+  }
+  MLAUNCH(3)
+  MLAUNCH(4)
+  MLAUNCH(5)
+  MLAUNCH(6)
+  MLAUNCH(7)
+#undef MLAUNCH
+}
+
 void launch_tiles_split(int stage, const Tile *tiles, const Seg *segs, const SegS *ssegs, int ntiles,
                         int nslices, const double *const *bases, const double *psi, double *y, double *work,
                         double *part, SliceBufs bufs, int xcd, void *stream) {
   if (ntiles <= 0) return;
+  hipStream_t s = (hipStream_t)stream;
   int grid = std::min((ntiles + WAVES - 1) / WAVES, 256 * 16);
   grid = (grid + 7) / 8 * 8;
-  hipStream_t s = (hipStream_t)stream;
 #define LAUNCH(NS)                                                                                          \
   if (nslices == NS) {                                                                                      \
     if (stage == 1)                                                                                         \

@@ -65,6 +65,7 @@ struct dmrg_plan {
   int64_t work_elems = 0;
   double *d_part = nullptr;
   int64_t part_elems = 0;
+  int32_t *d_counters = nullptr;      // per-XCD queue counters of the work-group launches
   std::vector<Chunk> chunks;
   std::vector<DiagBlock> dblocks;
   std::vector<DiagTerm> dterms;
@@ -83,6 +84,7 @@ struct dmrg_plan {
   std::vector<void *> plan_allocs;     // tile lists, workspace, slices (freed by re-planning)
   // settings of the tile lists
   int kpart = KPART, tile_policy = 0, xcd = 0, flags = 0;
+  int macro_min = MACRO_MIN;          // split plans: work-group tiles for outputs >= this (0: none)
   int64_t budget = DEFAULT_WORKSPACE;
   int tuned = 0;
   double tune_ms = 0.0;
@@ -180,6 +182,43 @@ int tile_mb(int m, int n, int policy) {
   return 2;
 }
 
+// Grid cells (row tile, column tile) of an nr x nc tile grid in patches of
+// PATCH x PATCH, patch-major, row-major inside a patch.  Work groups take
+// consecutive list entries (on one XCD with DMRG_PLAN_XCD), so the tiles that
+// run side by side share PATCH operand row bands and PATCH column bands in
+// that XCD's L2 instead of each fetching its own.
+constexpr int PATCH = 8;
+std::vector<std::pair<int, int>> patch_order(int nr, int nc) {
+  std::vector<std::pair<int, int>> v;
+  for (int pr = 0; pr < nr; pr += PATCH)
+    for (int pc = 0; pc < nc; pc += PATCH)
+      for (int r = pr; r < std::min(nr, pr + PATCH); r++)
+        for (int c = pc; c < std::min(nc, pc + PATCH); c++) v.push_back({r, c});
+  return v;
+}
+
+// NXCD contiguous ranges of a tile list with about equal summed cost
+XcdQueues xcd_queues(const std::vector<double> &cost) {
+  XcdQueues q{};
+  double tot = 0.0;
+  for (double c : cost) tot += c;
+  const int n = (int)cost.size();
+  double acc = 0.0;
+  int i = 0;
+  q.start[0] = 0;
+  for (int x = 1; x < NXCD; x++) {
+    while (i < n && acc + 0.5 * cost[i] < tot * x / NXCD) acc += cost[i++];
+    q.start[x] = i;
+  }
+  q.start[NXCD] = n;
+  return q;
+}
+
+// work-group tiles for split plans whose output is at least macro_min on both sides
+bool use_macro(const dmrg_plan *P, int m, int n) {
+  return P->precision == DMRG_SPLIT_BF16 && P->macro_min > 0 && m >= P->macro_min && n >= P->macro_min;
+}
+
 int prepare_device(dmrg_plan *P);
 int autotune(dmrg_plan *P, void *stream);
 int replan(dmrg_plan *P);
@@ -235,6 +274,7 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
       for (const auto &pa : T.rows[tk.row].pos) s.slots.push_back(pa.pD);
     }
     int64_t woff = 0;
+    std::vector<double> cost1m;   // K of every stage-1 work-group tile
     for (auto &kv : stripes) {
       Stripe &s = kv.second;
       std::sort(s.slots.begin(), s.slots.end());
@@ -283,9 +323,10 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
         double fl = 2.0 * s.dL * s.dRin * N;
         P->stats.stage1_flops += fl;
         ch.flops1 += fl;
-        int mb = tile_mb(s.dL, N, P->tile_policy);
-        for (int i0 = 0; i0 < s.dL; i0 += 16 * mb)
-          for (int j0 = 0; j0 < N; j0 += 64 / mb) {
+        int mb = use_macro(P, s.dL, N) ? MACRO_MB : tile_mb(s.dL, N, P->tile_policy);
+        const int tr = tile_rows(mb), tc = tile_cols(mb);
+        for (const auto &cell : patch_order((s.dL + tr - 1) / tr, (N + tc - 1) / tc)) {
+            const int i0 = cell.first * tr, j0 = cell.second * tc;
             Tile t{};
             t.c_base = BASE_WORK;
             if (trow) {
@@ -299,7 +340,12 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
             t.m = s.dL; t.n = N; t.i0 = i0; t.j0 = j0; t.ci0 = i0; t.cj0 = j0;
             t.mb = mb;
             t.seg0 = sidx; t.nseg = 1; t.accumulate = 0;
-            ch.tile1.push_back(t);
+            if (mb == MACRO_MB) {
+              ch.tile1m.push_back(t);
+              cost1m.push_back(s.dRin);
+            } else {
+              ch.tile1.push_back(t);
+            }
           }
         s0 = s1;
       }
@@ -383,8 +429,8 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
         q = q1;
       }
     }
-    std::vector<std::pair<double, Tile>> tiles2;
-    int64_t nslot = 0;
+    std::vector<std::pair<double, Tile>> tiles2, tiles2m;
+    int64_t npart = 0;   // partial-tile elements
     for (auto &kv : byF) {
       const ProbPlan &pp = *P->probs[kv.first.first];
       const PsiBlock &F = pp.T.blocks[kv.first.second];
@@ -430,49 +476,62 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
       int seg0 = (int)ch.seg2.size();
       for (auto &g : pieces) ch.seg2.push_back(g);
       for (auto &gi : pinfo) ch.s2info.push_back(gi);
-      int mb = tile_mb(F.dL, F.dR, P->tile_policy);
-      int tm = 16 * mb, tn = 64 / mb;
-      for (int i0 = 0; i0 < F.dL; i0 += tm)
-        for (int j0 = 0; j0 < F.dR; j0 += tn) {
+      const int mb = use_macro(P, F.dL, F.dR) ? MACRO_MB : tile_mb(F.dL, F.dR, P->tile_policy);
+      const int tm = tile_rows(mb), tn = tile_cols(mb);
+      auto &dst = mb == MACRO_MB ? tiles2m : tiles2;
+      const auto cells = patch_order((F.dL + tm - 1) / tm, (F.dR + tn - 1) / tn);
+      const int np = (int)parts.size();
+      // partial tiles of cell c, part p at npart + (c np + p) tm tn; the list
+      // runs over parts (outer) and cells in patch order (inner), so the tiles
+      // that run together share their K range
+      for (int pi = 0; pi < np; pi++)
+        for (size_t c = 0; c < cells.size(); c++) {
+          const int i0 = cells[c].first * tm, j0 = cells[c].second * tn;
           Tile t{};
           t.m = F.dL; t.n = F.dR; t.i0 = i0; t.j0 = j0; t.mb = mb;
-          if (parts.size() == 1) {
+          t.seg0 = seg0 + parts[pi].first;
+          t.nseg = parts[pi].second - parts[pi].first;
+          if (np == 1) {
             t.c_base = BASE_Y;
             t.c_off = pp.psi_off + F.off;
             t.ldc = F.dL;
             t.ci0 = i0; t.cj0 = j0;
-            t.seg0 = seg0; t.nseg = (int)pieces.size(); t.accumulate = 1;
-            tiles2.push_back({pcost[0], t});
-            continue;
+            t.accumulate = 1;
+          } else {
+            if (pi == 0) {
+              Reduce r{};
+              r.y_off = pp.psi_off + F.off;
+              r.ldc = F.dL;
+              r.part_off = npart + (int64_t)c * np * tm * tn;
+              r.m = F.dL; r.n = F.dR; r.i0 = i0; r.j0 = j0; r.tm = tm; r.tn = tn;
+              r.nparts = np;
+              ch.red2.push_back(r);
+            }
+            t.c_base = BASE_PART;
+            t.c_off = npart + ((int64_t)c * np + pi) * tm * tn;
+            t.ldc = tm;
+            t.ci0 = 0; t.cj0 = 0;
+            t.accumulate = 0;
           }
-          Reduce r{};
-          r.y_off = pp.psi_off + F.off;
-          r.ldc = F.dL;
-          r.part_off = nslot * 1024;
-          r.m = F.dL; r.n = F.dR; r.i0 = i0; r.j0 = j0; r.tm = tm;
-          r.nparts = (int)parts.size();
-          ch.red2.push_back(r);
-          for (size_t pi = 0; pi < parts.size(); pi++) {
-            Tile u = t;
-            u.c_base = BASE_PART;
-            u.c_off = (nslot + (int64_t)pi) * 1024;
-            u.ldc = tm;
-            u.ci0 = 0; u.cj0 = 0;
-            u.seg0 = seg0 + parts[pi].first;
-            u.nseg = parts[pi].second - parts[pi].first;
-            u.accumulate = 0;
-            tiles2.push_back({pcost[pi], u});
-          }
-          nslot += (int64_t)parts.size();
+          dst.push_back({pcost[pi], t});
         }
+      if (np > 1) npart += (int64_t)cells.size() * np * tm * tn;
     }
-    ch.part_elems = nslot * 1024;
+    ch.part_elems = npart;
     P->part_elems = std::max(P->part_elems, ch.part_elems);
-    std::stable_sort(tiles2.begin(), tiles2.end(),
-                     [](const std::pair<double, Tile> &a, const std::pair<double, Tile> &b) {
-                       return a.first > b.first;
-                     });
+    auto by_cost = [](const std::pair<double, Tile> &a, const std::pair<double, Tile> &b) {
+      return a.first > b.first;
+    };
+    std::stable_sort(tiles2.begin(), tiles2.end(), by_cost);
+    std::stable_sort(tiles2m.begin(), tiles2m.end(), by_cost);
     for (auto &x : tiles2) ch.tile2.push_back(x.second);
+    std::vector<double> cost2m;
+    for (auto &x : tiles2m) {
+      ch.tile2m.push_back(x.second);
+      cost2m.push_back(x.first);
+    }
+    ch.q1m = xcd_queues(cost1m);
+    ch.q2m = xcd_queues(cost2m);
     P->chunks.push_back(std::move(ch));
   }
   P->stats.flops = P->stats.stage1_flops + P->stats.stage2_flops;
@@ -527,6 +586,7 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
   for (auto &ch : P->chunks) {
     if ((rc = upload(P, ch.seg1, &ch.d_seg1)) || (rc = upload(P, ch.seg2, &ch.d_seg2)) ||
         (rc = upload(P, ch.tile1, &ch.d_tile1)) || (rc = upload(P, ch.tile2, &ch.d_tile2)) ||
+        (rc = upload(P, ch.tile1m, &ch.d_tile1m)) || (rc = upload(P, ch.tile2m, &ch.d_tile2m)) ||
         (rc = upload(P, ch.red2, &ch.d_red2)))
       return rc;
     P->stats.n_stage1 += (int64_t)ch.seg1.size();
@@ -541,6 +601,15 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
     }
     P->plan_allocs.push_back(d);
     P->d_work = (double *)d;
+  }
+  {
+    void *d = nullptr;
+    if (hipMalloc(&d, sizeof(int32_t) * QUEUE_INTS) != hipSuccess) {
+      set_error("hipMalloc failed for the work queue counters");
+      return DMRG_ENOMEM;
+    }
+    P->plan_allocs.push_back(d);
+    P->d_counters = (int32_t *)d;
   }
   if (P->part_elems > 0) {
     void *d = nullptr;
@@ -806,9 +875,9 @@ void build_split(dmrg_plan *P) {
   // the split kernels address a segment's slice lines with 32-bit byte
   // offsets from the slice base: rows * ld * 2 bytes must stay below 2^32
   for (auto &ch : P->chunks)
-    for (int st = 1; st <= 2; st++) {
-      const auto &tiles = st == 1 ? ch.tile1 : ch.tile2;
-      const auto &ss = st == 1 ? ch.sseg1 : ch.sseg2;
+    for (int st = 0; st < 4; st++) {
+      const auto &tiles = st == 0 ? ch.tile1 : st == 1 ? ch.tile1m : st == 2 ? ch.tile2 : ch.tile2m;
+      const auto &ss = st < 2 ? ch.sseg1 : ch.sseg2;
       for (const Tile &t : tiles)
         for (int i = 0; i < t.nseg; i++) {
           const SegS &q = ss[t.seg0 + i];
@@ -867,6 +936,7 @@ void release_plan(dmrg_plan *P) {
   P->d_dterms = nullptr;
   P->d_work = nullptr;
   P->d_part = nullptr;
+  P->d_counters = nullptr;
   P->work_elems = P->part_elems = 0;
   P->jobs_ops.clear();
   P->jobs_psi.clear();
@@ -882,7 +952,9 @@ int count_launches(const dmrg_plan *P) {
   int n = P->psi_len > 0;
   if (split) n += !P->jobs_psi.empty();
   for (const Chunk &ch : P->chunks) {
-    n += !ch.tile1.empty() + !ch.tile2.empty() + !ch.red2.empty();
+    // a work-group tile launch clears its queue counters first
+    n += !ch.tile1.empty() + !ch.tile2.empty() + 2 * !ch.tile1m.empty() + 2 * !ch.tile2m.empty() +
+         !ch.red2.empty();
     if (split) n += (ch.t_exps > 0) + !ch.titems.empty();
   }
   return n;
@@ -931,6 +1003,7 @@ uint64_t plan_hash(const dmrg_plan *P) {
   mix(P->precision);
   mix(P->n_slices);
   mix(P->xcd);
+  mix(P->macro_min);
   mix(P->budget);
   for (const auto &pp : P->probs) {
     mix((int64_t)pp->T.blocks.size());
@@ -1109,6 +1182,7 @@ extern "C" int dmrg_build_tasks(const dmrg_problem_t *probs, int32_t n_probs, co
     P->xcd = (P->flags & DMRG_PLAN_XCD) ? 1 : 0;
     P->kpart = (opts && opts->kpart > 0) ? opts->kpart : KPART;
     P->tile_policy = opts ? opts->tile_policy : 0;
+    P->macro_min = !opts || opts->macro_min == 0 ? MACRO_MIN : std::max(0, opts->macro_min);
     P->budget = budget;
     if (P->kpart < 64 || P->kpart > (1 << 20) || P->tile_policy < 0 || P->tile_policy > 1) {
       set_error("kpart must be in [64, 2^20] and tile_policy 0 or 1");
@@ -1151,6 +1225,7 @@ namespace {
 struct RunBufs {
   double *work, *part;
   SliceBufs sb;
+  int32_t *counters;
 };
 
 int enqueue_with(dmrg_plan *p, const double *psi, double *hpsi, void *stream, bool prof, const RunBufs &B) {
@@ -1174,12 +1249,18 @@ int enqueue_with(dmrg_plan *p, const double *psi, double *hpsi, void *stream, bo
         HIPCHK(hipEventRecord(p->ev_pool[ev++], (hipStream_t)stream));
       }
       if (split) {
-        if (stage == 1)
+        // work-group tiles (the larger outputs) first, then the wavefront tiles
+        if (stage == 1) {
+          launch_macro_split(1, ch.d_tile1m, ch.d_seg1, ch.d_sseg1, (int)ch.tile1m.size(), ch.q1m, B.counters,
+                             p->n_slices, p->d_bases, psi, hpsi, B.work, B.part, B.sb, stream);
           launch_tiles_split(1, ch.d_tile1, ch.d_seg1, ch.d_sseg1, (int)ch.tile1.size(), p->n_slices, p->d_bases,
                              psi, hpsi, B.work, B.part, B.sb, p->xcd, stream);
-        else
+        } else {
+          launch_macro_split(2, ch.d_tile2m, ch.d_seg2, ch.d_sseg2, (int)ch.tile2m.size(), ch.q2m, B.counters,
+                             p->n_slices, p->d_bases, psi, hpsi, B.work, B.part, B.sb, stream);
           launch_tiles_split(2, ch.d_tile2, ch.d_seg2, ch.d_sseg2, (int)ch.tile2.size(), p->n_slices, p->d_bases,
                              psi, hpsi, B.work, B.part, B.sb, p->xcd, stream);
+        }
       } else if (stage == 1)
         launch_tiles_f64(1, ch.d_tile1, ch.d_seg1, (int)ch.tile1.size(), p->d_bases, psi, hpsi, B.work, B.part,
                          p->xcd, stream);
@@ -1202,7 +1283,7 @@ int enqueue_with(dmrg_plan *p, const double *psi, double *hpsi, void *stream, bo
 }
 
 int enqueue(dmrg_plan *p, const double *psi, double *hpsi, void *stream, bool prof) {
-  return enqueue_with(p, psi, hpsi, stream, prof, RunBufs{p->d_work, p->d_part, p->sb});
+  return enqueue_with(p, psi, hpsi, stream, prof, RunBufs{p->d_work, p->d_part, p->sb, p->d_counters});
 }
 }  // namespace
 
@@ -1210,7 +1291,7 @@ namespace dmrg {
 // Byte layout of the scratch memory of one H.psi (see dmrg_apply_H_static):
 // stripe workspace, partial tiles, stripe slices, stripe exponents, each
 // 256-byte aligned.  Returns the total.
-int64_t plan_scratch_layout(const dmrg_plan_t *p, int64_t off[4]) {
+int64_t plan_scratch_layout(const dmrg_plan_t *p, int64_t off[SCRATCH_REGIONS]) {
   auto up = [](int64_t x) { return (x + 255) / 256 * 256; };
   const bool split = p->precision == DMRG_SPLIT_BF16;
   int64_t o = 0;
@@ -1218,15 +1299,16 @@ int64_t plan_scratch_layout(const dmrg_plan_t *p, int64_t off[4]) {
   off[1] = o; o = up(o + 8 * std::max<int64_t>(p->part_elems, 1));
   off[2] = o; if (split) o = up(o + 2 * std::max<int64_t>(p->sb_elems[SBUF_T], 1) * p->n_slices);
   off[3] = o; if (split) o = up(o + 4 * std::max<int64_t>(p->sb_exps[SBUF_T], 1));
+  off[4] = o; o = up(o + 4 * QUEUE_INTS);
   return o;
 }
 
 // One H.psi with the scratch memory at `base` (laid out by
 // plan_scratch_layout); no allocation, no graph, no profiling events.
 int enqueue_scratch(dmrg_plan_t *p, const double *psi, double *hpsi, void *stream, char *base) {
-  int64_t off[4];
+  int64_t off[SCRATCH_REGIONS];
   plan_scratch_layout(p, off);
-  RunBufs B{(double *)(base + off[0]), (double *)(base + off[1]), p->sb};
+  RunBufs B{(double *)(base + off[0]), (double *)(base + off[1]), p->sb, (int32_t *)(base + off[4])};
   if (p->precision == DMRG_SPLIT_BF16) {
     B.sb.data[SBUF_T] = (uint16_t *)(base + off[2]);
     B.sb.exps[SBUF_T] = (int32_t *)(base + off[3]);
@@ -1343,7 +1425,7 @@ static void host_tiles(const std::vector<Tile> &tiles, const std::vector<Seg> &s
     return B[pk * S.b_pk + (k - pk * S.b_kb) * S.b_k + pn * S.b_pn + (n - pn * S.b_nb) * S.b_n];
   };
   for (const Tile &T : tiles) {
-    int tm = 16 * T.mb, tn = 64 / T.mb;
+    int tm = tile_rows(T.mb), tn = tile_cols(T.mb);
     int mt = std::min(tm, T.m - T.i0), nt = std::min(tn, T.n - T.j0);
     std::vector<double> acc((size_t)mt * nt, 0.0);
     for (int si = 0; si < T.nseg; si++) {
@@ -1432,7 +1514,7 @@ static void host_tiles_split(const std::vector<Tile> &tiles, const std::vector<S
                                                                                                : bases[id - BASE_OPS];
   };
   for (const Tile &T : tiles) {
-    int tm = 16 * T.mb, tn = 64 / T.mb;
+    int tm = tile_rows(T.mb), tn = tile_cols(T.mb);
     int mt = std::min(tm, T.m - T.i0), nt = std::min(tn, T.n - T.j0);
     std::vector<double> acc((size_t)mt * nt, 0.0);
     for (int si = 0; si < T.nseg; si++) {
@@ -1484,11 +1566,12 @@ static void host_tiles_split(const std::vector<Tile> &tiles, const std::vector<S
 
 static void host_reduce(const std::vector<Reduce> &red, const double *part, double *y) {
   for (const Reduce &R : red) {
-    int mt = std::min(R.tm, R.m - R.i0), nt = std::min(1024 / R.tm, R.n - R.j0);
+    int mt = std::min(R.tm, R.m - R.i0), nt = std::min(R.tn, R.n - R.j0);
     for (int j = 0; j < nt; j++)
       for (int i = 0; i < mt; i++) {
         double v = 0.0;
-        for (int p = 0; p < R.nparts; p++) v += part[R.part_off + (int64_t)p * 1024 + i + (int64_t)j * R.tm];
+        for (int p = 0; p < R.nparts; p++)
+          v += part[R.part_off + (int64_t)p * R.tm * R.tn + i + (int64_t)j * R.tm];
         y[R.y_off + (int64_t)(R.i0 + i) + (int64_t)(R.j0 + j) * R.ldc] += v;
       }
   }
@@ -1503,6 +1586,7 @@ extern "C" int dmrg_debug_plan_host_apply(const dmrg_problem_t *prob, const doub
   P->n_slices = opts ? opts->n_slices : 0;
   P->kpart = (opts && opts->kpart > 0) ? opts->kpart : KPART;
   P->tile_policy = opts ? opts->tile_policy : 0;
+  P->macro_min = !opts || opts->macro_min == 0 ? MACRO_MIN : std::max(0, opts->macro_min);
   auto pp = std::make_unique<ProbPlan>();
   Error err{0, ""};
   auto tt0 = std::chrono::steady_clock::now();
@@ -1563,9 +1647,13 @@ extern "C" int dmrg_debug_plan_host_apply(const dmrg_problem_t *prob, const doub
     host_slices(P->jobs_ops, ns, P->bases_h, psi, work.data(), P->h_sb, plane, P->h_se);
     host_slices(P->jobs_psi, ns, P->bases_h, psi, work.data(), P->h_sb, plane, P->h_se);
     for (auto &ch : P->chunks) {
+      host_tiles_split(ch.tile1m, ch.seg1, ch.sseg1, ns, P->bases_h, psi, y, work.data(), part.data(), P->h_sb,
+                       plane, P->h_se);
       host_tiles_split(ch.tile1, ch.seg1, ch.sseg1, ns, P->bases_h, psi, y, work.data(), part.data(), P->h_sb,
                        plane, P->h_se);
       host_slices(ch.tjobs, ns, P->bases_h, psi, work.data(), P->h_sb, plane, P->h_se);
+      host_tiles_split(ch.tile2m, ch.seg2, ch.sseg2, ns, P->bases_h, psi, y, work.data(), part.data(), P->h_sb,
+                       plane, P->h_se);
       host_tiles_split(ch.tile2, ch.seg2, ch.sseg2, ns, P->bases_h, psi, y, work.data(), part.data(), P->h_sb,
                        plane, P->h_se);
       host_reduce(ch.red2, part.data(), y);
@@ -1599,14 +1687,15 @@ extern "C" int64_t dmrg_debug_plan_tiles(const dmrg_problem_t *prob, int32_t sta
   if (rc) { delete P; return rc; }
   int64_t n = 0;
   for (auto &ch : P->chunks) {
-    const auto &tiles = stage == 1 ? ch.tile1 : ch.tile2;
+    std::vector<Tile> tiles = stage == 1 ? ch.tile1m : ch.tile2m;
+    for (const Tile &t : stage == 1 ? ch.tile1 : ch.tile2) tiles.push_back(t);
     const auto &segs = stage == 1 ? ch.seg1 : ch.seg2;
     for (const Tile &t : tiles) {
       int64_t sk = 0;
       for (int i = 0; i < t.nseg; i++) sk += segs[t.seg0 + i].a_base < 0 ? 0 : segs[t.seg0 + i].K;
       if (n < cap) {
-        out[4 * n] = std::min(16 * t.mb, t.m - t.i0);
-        out[4 * n + 1] = std::min(64 / t.mb, t.n - t.j0);
+        out[4 * n] = std::min(tile_rows(t.mb), t.m - t.i0);
+        out[4 * n + 1] = std::min(tile_cols(t.mb), t.n - t.j0);
         out[4 * n + 2] = t.nseg;
         out[4 * n + 3] = sk;
       }

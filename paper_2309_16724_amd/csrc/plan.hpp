@@ -21,6 +21,28 @@ struct Seg {
   int32_t K, a_kb, b_kb, b_nb;
 };
 
+// Work-group tiles: a tile with mb == MACRO_MB is a 64 x 64 tile computed by
+// the four wavefronts of a work group together (each a 32 x 32 quarter) from
+// operand tiles they stage in LDS once; the other tiles belong to one
+// wavefront each.
+constexpr int MACRO_MB = 8;
+constexpr int MACRO_EDGE = 64;
+constexpr int MACRO_MIN = 48;   // default: outputs with both dims >= 48 get work-group tiles
+constexpr int tile_rows(int mb) { return mb == MACRO_MB ? MACRO_EDGE : 16 * mb; }
+constexpr int tile_cols(int mb) { return mb == MACRO_MB ? MACRO_EDGE : 64 / mb; }
+
+// Per-XCD queues of a work-group tile list: the list (cost-sorted, operand
+// bands in patches) is cut into NXCD contiguous ranges of equal cost; the work
+// groups of XCD x take the tiles of range x in order through an atomic
+// counter and then help the other ranges, so the tiles that run side by side
+// on one XCD are neighbours in the list and share operand bands in its L2.
+constexpr int NXCD = 8;
+constexpr int MACRO_GRID = 512;          // work groups of a work-group tile launch (two per CU)
+constexpr int QUEUE_INTS = NXCD + MACRO_GRID;   // queue counters, then one mailbox per work group
+struct XcdQueues {
+  int32_t start[NXCD + 1];
+};
+
 // One work item: a (16*mb) x (64/mb) tile of an m x n output block (rows
 // i0.., columns j0..) accumulated over segments seg0..seg0+nseg-1 and stored
 // at C + (ci0 + i) + (cj0 + j) * ldc (column-major) or at
@@ -47,8 +69,8 @@ struct TransJob {
 // Deterministic sum of the partial tiles of one output tile into Y.
 struct Reduce {
   int64_t y_off, ldc;
-  int64_t part_off;     // first partial; partial p at part_off + p * 1024
-  int32_t m, n, i0, j0, tm, nparts;
+  int64_t part_off;     // first partial; partial p at part_off + p * tm * tn (column-major, ld tm)
+  int32_t m, n, i0, j0, tm, tn, nparts, pad;
 };
 
 // Diagonal of H_eff: diag[off + i + j*m] += s * dA_i * dD_j over a block's list
@@ -140,10 +162,13 @@ struct Chunk {
   std::vector<Seg1Info> s1info;
   std::vector<Seg2Info> s2info;
   std::vector<Seg> seg1, seg2;
-  std::vector<Tile> tile1, tile2;
+  std::vector<Tile> tile1, tile2;       // one wavefront per tile
+  std::vector<Tile> tile1m, tile2m;     // work-group (macro) tiles
+  XcdQueues q1m{}, q2m{};               // their per-XCD ranges
   std::vector<Reduce> red2;
   Seg *d_seg1 = nullptr, *d_seg2 = nullptr;
   Tile *d_tile1 = nullptr, *d_tile2 = nullptr;
+  Tile *d_tile1m = nullptr, *d_tile2m = nullptr;
   Reduce *d_red2 = nullptr;
   double flops1 = 0.0, flops2 = 0.0;    // algorithmic flops of each launch
   int64_t part_elems = 0;               // partial-tile buffer needed
@@ -184,12 +209,20 @@ void launch_tslices(const SliceJob *jobs, const TSliceItem *items, int nitems, i
                     SliceBufs bufs, void *stream);
 void launch_fill_int(int32_t *p, int64_t n, int32_t v, void *stream);
 // scratch memory of one H.psi: byte offsets of the stripe workspace, partial
-// tiles, stripe slices and stripe exponents (off[4]); returns the total bytes
-int64_t plan_scratch_layout(const dmrg_plan_t *p, int64_t off[4]);
+// tiles, stripe slices, stripe exponents and work-queue counters; returns the
+// total bytes
+constexpr int SCRATCH_REGIONS = 5;
+int64_t plan_scratch_layout(const dmrg_plan_t *p, int64_t off[SCRATCH_REGIONS]);
 // one H.psi with that scratch memory at base (device address)
 int enqueue_scratch(dmrg_plan_t *p, const double *psi, double *hpsi, void *stream, char *base);
+// wavefront tiles (one tile per wavefront, taken in list order)
 void launch_tiles_split(int stage, const Tile *tiles, const Seg *segs, const SegS *ssegs, int ntiles,
                         int nslices, const double *const *bases, const double *psi, double *y, double *work,
                         double *part, SliceBufs bufs, int xcd, void *stream);
+// work-group (MACRO_MB) tiles from per-XCD queues; counters: QUEUE_INTS ints
+// of device memory, the NXCD queue counters cleared by this call before the launch
+void launch_macro_split(int stage, const Tile *tiles, const Seg *segs, const SegS *ssegs, int ntiles,
+                        const XcdQueues &q, int32_t *counters, int nslices, const double *const *bases,
+                        const double *psi, double *y, double *work, double *part, SliceBufs bufs, void *stream);
 
 }  // namespace dmrg

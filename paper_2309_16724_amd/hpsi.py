@@ -18,7 +18,7 @@ def _torch():
 
 class Plan:
     def __init__(self, problems, precision=B.DMRG_FP64, n_slices=0, workspace_bytes=0,
-                 device="cuda:0", flags=0, kpart=0, tile_policy=0):
+                 device="cuda:0", flags=0, kpart=0, tile_policy=0, macro_min=0):
         torch = _torch()
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
@@ -41,7 +41,7 @@ class Plan:
             structs.append(args.s)
         arr = (B.ProblemT * len(structs))(*structs)
         self._keep.append(arr)
-        opts = B.PlanOpts(precision, n_slices, workspace_bytes, flags, kpart, tile_policy, 0)
+        opts = B.PlanOpts(precision, n_slices, workspace_bytes, flags, kpart, tile_policy, macro_min)
         h = ctypes.c_void_p()
         stream = torch.cuda.current_stream(self.device).cuda_stream
         torch.cuda.synchronize(self.device)

@@ -79,3 +79,29 @@ def test_split_full_size_vs_oracle(torch):
     e64 = np.abs(y64 - ref).max() / np.abs(ref).max()
     _say("rel err split %.3e fp64 %.3e" % (e5, e64))
     assert e5 <= 1e-10 and e64 <= 1e-12
+
+
+@pytest.mark.parametrize("ns", [3, 5, 7])
+def test_workgroup_tiles_match_oracle_and_emulation(torch, ns):
+    """Outputs of 48 and more on both sides go to 64 x 64 work-group tiles
+    (LDS-staged operands shared by four wavefronts): blocks of 23..170 rows
+    with ragged tails, split K (kpart 256) and whole segments; against the
+    oracle, the host emulation of the same tile lists, and the wavefront
+    tiles (macro_min < 0)."""
+    from oracle.hpsi import HEff
+    from paper_2309_16724_amd import binding as B
+    prob = random_problem(6, 6, 0, 7, D=400, D_right=160, cap=False)
+    he = HEff(prob)
+    x = np.random.default_rng(5).standard_normal(he.size)
+    ref = he.apply(x)
+    for kp in (0, 256):
+        _say("  s=%d kpart=%d" % (ns, kp))
+        y = _apply(torch, prob, x, precision=1, n_slices=ns, kpart=kp)
+        yw = _apply(torch, prob, x, precision=1, n_slices=ns, kpart=kp, macro_min=-1)
+        yh, _ = B.debug_plan_host_apply(prob, x, precision=1, n_slices=ns, kpart=kp)
+        err = np.abs(y - ref).max() / np.abs(ref).max()
+        _say("    rel err %.3e vs oracle, %.3e vs emulation, %.3e vs wavefront tiles"
+             % (err, np.abs(y - yh).max() / np.abs(yh).max(), np.abs(y - yw).max() / np.abs(yw).max()))
+        assert err <= BOUND[ns]
+        assert np.abs(y - yh).max() <= 1e-14 * np.abs(yh).max()
+        assert np.abs(y - yw).max() <= 1e-14 * np.abs(yw).max()
