@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 #include <algorithm>
 #include "plan.hpp"
+#include "queue.hpp"
 
 namespace dmrg {
 
@@ -28,15 +29,6 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef const double __attribute__((address_space(1))) *gcptr;
 typedef double __attribute__((address_space(1))) *gptr;
 __device__ __forceinline__ double gld(const double *p) { return *(gcptr)p; }
-
-
-// Work-group index used to pick work: consecutive work groups are spread over
-// the 8 XCDs (each with its own L2), so with xcd != 0 the groups resident on
-// one XCD are given consecutive tile indices, which share operands.
-__device__ __forceinline__ int work_block(int xcd) {
-  const int b = blockIdx.x, g = gridDim.x;
-  return (xcd && (g & 7) == 0) ? (b & 7) * (g >> 3) + (b >> 3) : b;
-}
 
 
 __device__ __forceinline__ const double *base_ptr(int id, const double *const *bases, const double *psi,
@@ -180,24 +172,27 @@ __device__ __forceinline__ void item_f64(const Tile &T, const Seg *__restrict__ 
       }
 }
 
-// One launch per stage: every wavefront takes tiles from the stage's
-// cost-sorted list and runs the work item of the tile's shape.
+// One launch per stage: every wavefront takes tiles from the per-XCD queues
+// of the stage's cost-sorted list and runs the work item of the tile's shape.
 // Three wavefronts per SIMD (at most 168 registers, no spills): more loads in
 // flight per SIMD than the two that the register use of an unbounded build
 // allows; four spill.
 template <int STAGE>
-__global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(3, 3))) stage_f64_kernel(const Tile *__restrict__ tiles,
-                                                                const Seg *__restrict__ segs, int ntiles,
-                                                                const double *const *__restrict__ bases,
-                                                                const double *__restrict__ psi,
-                                                                double *__restrict__ y, double *__restrict__ work,
-                                                                double *__restrict__ part, int xcd) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+__global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(3, 3))) stage_f64_kernel(
+    const Tile *__restrict__ tiles, const Seg *__restrict__ segs, XcdQueues q, int32_t *__restrict__ counters,
+    const double *const *__restrict__ bases, const double *__restrict__ psi, double *__restrict__ y,
+    double *__restrict__ work, double *__restrict__ part) {
+  const int lane = threadIdx.x & 63;
   const int r16 = lane & 15, q4 = lane >> 4;
-  // the tile index is the same for the whole wavefront: saying so makes the
-  // descriptors scalar loads and the K loops uniform (no exec masking)
-  for (int t = __builtin_amdgcn_readfirstlane(work_block(xcd) * WAVES + wave); t < ntiles;
-       t += gridDim.x * WAVES) {
+  const int x = xcc_id();
+  int qi = 0;
+  for (;;) {
+    // the tile index is the same for the whole wavefront: saying so makes the
+    // descriptors scalar loads and the K loops uniform (no exec masking)
+    int v = -1;
+    if (lane == 0) v = queue_next(q, counters, x, qi);
+    const int t = __builtin_amdgcn_readfirstlane(v);
+    if (t < 0) break;
     const Tile T = tiles[t];
     if (T.mb == 1) item_f64<1>(T, segs, bases, psi, y, work, part, r16, q4);
     else if (T.mb == 4) item_f64<4>(T, segs, bases, psi, y, work, part, r16, q4);
@@ -275,17 +270,20 @@ void launch_zero(double *y, int64_t n, void *stream) {
   hipLaunchKernelGGL(zero_kernel, dim3(grid), dim3(256), 0, (hipStream_t)stream, y, n);
 }
 
-void launch_tiles_f64(int stage, const Tile *tiles, const Seg *segs, int ntiles, const double *const *bases,
-                      const double *psi, double *y, double *work, double *part, int xcd, void *stream) {
+void launch_tiles_f64(int stage, const Tile *tiles, const Seg *segs, int ntiles, const XcdQueues &q,
+                      int32_t *counters, const double *const *bases, const double *psi, double *y, double *work,
+                      double *part, void *stream) {
   if (ntiles <= 0) return;
+  hipStream_t s = (hipStream_t)stream;
+  launch_fill_int(counters, NXCD, 0, stream);
   int grid = std::min((ntiles + WAVES - 1) / WAVES, 256 * 16);
   grid = (grid + 7) / 8 * 8;
   if (stage == 1)
-    hipLaunchKernelGGL(stage_f64_kernel<1>, dim3(grid), dim3(64 * WAVES), 0, (hipStream_t)stream, tiles, segs,
-                       ntiles, bases, psi, y, work, part, xcd);
+    hipLaunchKernelGGL(stage_f64_kernel<1>, dim3(grid), dim3(64 * WAVES), 0, s, tiles, segs, q, counters, bases,
+                       psi, y, work, part);
   else
-    hipLaunchKernelGGL(stage_f64_kernel<2>, dim3(grid), dim3(64 * WAVES), 0, (hipStream_t)stream, tiles, segs,
-                       ntiles, bases, psi, y, work, part, xcd);
+    hipLaunchKernelGGL(stage_f64_kernel<2>, dim3(grid), dim3(64 * WAVES), 0, s, tiles, segs, q, counters, bases,
+                       psi, y, work, part);
 }
 
 void launch_reduce(const Reduce *red, int nred, const double *part, double *y, void *stream) {

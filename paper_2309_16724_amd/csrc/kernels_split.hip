@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 #include <climits>
 #include "plan.hpp"
+#include "queue.hpp"
 
 namespace dmrg {
 
@@ -169,6 +170,7 @@ typedef void __attribute__((address_space(3))) *lvptr;
 typedef const v8bf __attribute__((address_space(3))) *lv8ptr;
 // s_waitcnt immediates (gfx9 encoding): vmcnt(0) alone, lgkmcnt(0) alone
 constexpr int WAIT_VM0 = 0x0F70, WAIT_LGKM0 = 0xC07F;
+
 // LDS stage of one wavefront: (MB + NB) * NS chunks of 64 lanes x 16 bytes
 constexpr int stage_bytes(int ns) { return 5 * ns * 1024; }
 
@@ -334,26 +336,26 @@ __device__ __forceinline__ void item_split(const Tile &T, const Seg *__restrict_
   }
 }
 
-// Work-group index used to pick work: consecutive work groups are spread over
-// the 8 XCDs (each with its own L2), so with xcd != 0 the groups resident on
-// one XCD are given consecutive tile indices, which share operands.
-__device__ __forceinline__ int work_block(int xcd) {
-  const int b = blockIdx.x, g = gridDim.x;
-  return (xcd && (g & 7) == 0) ? (b & 7) * (g >> 3) + (b >> 3) : b;
-}
-
+// Wavefront tiles: every wavefront takes its next tile from the per-XCD
+// queues (one lane takes it, the index is wave-uniform).
 template <int NS>
 __device__ __forceinline__ void items_split(const Tile *__restrict__ tiles, const Seg *__restrict__ segs,
-                                            const SegS *__restrict__ ssegs, int ntiles,
+                                            const SegS *__restrict__ ssegs, const XcdQueues &q,
+                                            int32_t *__restrict__ counters,
                                             const double *const *__restrict__ bases, const double *__restrict__ psi,
                                             double *__restrict__ y, double *__restrict__ work,
-                                            double *__restrict__ part, const SliceBufs &bufs, int xcd) {
+                                            double *__restrict__ part, const SliceBufs &bufs) {
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, q4 = lane >> 4;
   __shared__ __attribute__((aligned(1024))) char lds[WAVES * stage_bytes(NS)];
   char *stage = lds + wave * stage_bytes(NS);
-  for (int t = __builtin_amdgcn_readfirstlane(work_block(xcd) * WAVES + wave); t < ntiles;
-       t += gridDim.x * WAVES) {
+  const int x = xcc_id();
+  int qi = 0;
+  for (;;) {
+    int v = -1;
+    if (lane == 0) v = queue_next(q, counters, x, qi);
+    const int t = __builtin_amdgcn_readfirstlane(v);
+    if (t < 0) break;
     const Tile T = tiles[t];
     if (T.mb == 1) item_split<1, NS>(T, segs, ssegs, bases, psi, y, work, part, bufs, stage, r16, q4);
     else if (T.mb == 4) item_split<4, NS>(T, segs, ssegs, bases, psi, y, work, part, bufs, stage, r16, q4);
@@ -470,15 +472,13 @@ __device__ __forceinline__ void macro_split(const Tile &T, const Seg *__restrict
       SegS NQ = Q;
       double nsc = sc;
       int nerow[MB][4], nfcol[NB];
-      if (more) {
-        if (newseg) {
-          NQ = ssegs[T.seg0 + nsi];
-          nsc = segs[T.seg0 + nsi].s;
-        }
-        issue(NQ, nk0, b ^ 1);
-        if (newseg) exps(NQ, nerow, nfcol);
+      if (more && newseg) {
+        NQ = ssegs[T.seg0 + nsi];
+        nsc = segs[T.seg0 + nsi].s;
       }
-      __builtin_amdgcn_sched_barrier(0);
+      // this step's operands: LDS -> registers, all reads complete (and the
+      // next segment's descriptors in) before the next step's loads into the
+      // other stage are issued, so no wait below depends on those loads
       v8bf as[MB][NS], bs[NB][NS];
       const char *st = lds + b * STAGE;
       for (int t = 0; t < NS; t++) {
@@ -487,6 +487,11 @@ __device__ __forceinline__ void macro_split(const Tile &T, const Seg *__restrict
           bs[bj][t] = *(const lv8ptr)(st + ((4 + 2 * wc + bj) * NS + t) * 1024 + 16 * lane);
       }
       __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
+      __builtin_amdgcn_sched_barrier(0);
+      if (more) {
+        issue(NQ, nk0, b ^ 1);
+        if (newseg) exps(NQ, nerow, nfcol);
+      }
       __builtin_amdgcn_sched_barrier(0);
       if (k0 + 32 > Q.K && k0 + 8 * q4 >= Q.K)   // only the last step of a segment has such lanes
         for (int bi = 0; bi < MB; bi++)
@@ -571,24 +576,10 @@ __device__ __forceinline__ void macro_items(const Tile *__restrict__ tiles, cons
   // work group's mailbox in global memory (atomics: coherent at the L2)
   __shared__ __attribute__((aligned(1024))) char lds[2 * mstage_bytes(NS)];
   int32_t *mailbox = counters + NXCD + blockIdx.x;
-  // the XCD this work group runs on (HW_REG_XCC_ID); its own queue first
-  const int x = __builtin_amdgcn_s_getreg((20) | (0 << 6) | (3 << 11)) & (NXCD - 1);
-  int qi = 0;   // queues tried so far (thread 0's state)
+  const int x = xcc_id();   // this work group's XCD: its own range first
+  int qi = 0;               // thread 0's queue state
   for (;;) {
-    if (threadIdx.x == 0) {
-      int t = -1;
-      for (; qi < NXCD; qi++) {
-        const int qq = (x + qi) & (NXCD - 1);
-        const int len = q.start[qq + 1] - q.start[qq];
-        if (len <= 0) continue;
-        const int k = atomicAdd(counters + qq, 1);
-        if (k < len) {
-          t = q.start[qq] + k;
-          break;
-        }
-      }
-      atomicExch(mailbox, t);
-    }
+    if (threadIdx.x == 0) atomicExch(mailbox, queue_next(q, counters, x, qi));
     // every wave reads the mailbox before the barrier inside macro_split, the
     // earliest point where thread 0 can write it again
     __syncthreads();
@@ -628,17 +619,17 @@ MACRO_KERNELS(7)
 #define SPLIT_KERNELS(NS)                                                                                   \
   __global__ void __launch_bounds__(64 * WAVES) stage1_split##NS##_kernel(                                  \
       const Tile *__restrict__ tiles, const Seg *__restrict__ segs, const SegS *__restrict__ ssegs,         \
-      int ntiles, const double *const *__restrict__ bases, const double *__restrict__ psi,                  \
-      double *__restrict__ y, double *__restrict__ work, double *__restrict__ part, SliceBufs bufs,        \
-      int xcd) {                                                                                            \
-    items_split<NS>(tiles, segs, ssegs, ntiles, bases, psi, y, work, part, bufs, xcd);                      \
+      XcdQueues q, int32_t *__restrict__ counters, const double *const *__restrict__ bases,                 \
+      const double *__restrict__ psi, double *__restrict__ y, double *__restrict__ work,                    \
+      double *__restrict__ part, SliceBufs bufs) {                                                          \
+    items_split<NS>(tiles, segs, ssegs, q, counters, bases, psi, y, work, part, bufs);                      \
   }                                                                                                         \
   __global__ void __launch_bounds__(64 * WAVES) stage2_split##NS##_kernel(                                  \
       const Tile *__restrict__ tiles, const Seg *__restrict__ segs, const SegS *__restrict__ ssegs,         \
-      int ntiles, const double *const *__restrict__ bases, const double *__restrict__ psi,                  \
-      double *__restrict__ y, double *__restrict__ work, double *__restrict__ part, SliceBufs bufs,        \
-      int xcd) {                                                                                            \
-    items_split<NS>(tiles, segs, ssegs, ntiles, bases, psi, y, work, part, bufs, xcd);                      \
+      XcdQueues q, int32_t *__restrict__ counters, const double *const *__restrict__ bases,                 \
+      const double *__restrict__ psi, double *__restrict__ y, double *__restrict__ work,                    \
+      double *__restrict__ part, SliceBufs bufs) {                                                          \
+    items_split<NS>(tiles, segs, ssegs, q, counters, bases, psi, y, work, part, bufs);                      \
   }
 
 SPLIT_KERNELS(3)
@@ -675,20 +666,21 @@ void launch_macro_split(int stage, const Tile *tiles, const Seg *segs, const Seg
 }
 
 void launch_tiles_split(int stage, const Tile *tiles, const Seg *segs, const SegS *ssegs, int ntiles,
-                        int nslices, const double *const *bases, const double *psi, double *y, double *work,
-                        double *part, SliceBufs bufs, int xcd, void *stream) {
+                        const XcdQueues &q, int32_t *counters, int nslices, const double *const *bases,
+                        const double *psi, double *y, double *work, double *part, SliceBufs bufs, void *stream) {
   if (ntiles <= 0) return;
   hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, s, counters, (int64_t)NXCD, 0);
   int grid = std::min((ntiles + WAVES - 1) / WAVES, 256 * 16);
   grid = (grid + 7) / 8 * 8;
 #define LAUNCH(NS)                                                                                          \
   if (nslices == NS) {                                                                                      \
     if (stage == 1)                                                                                         \
       hipLaunchKernelGGL(stage1_split##NS##_kernel, dim3(grid), dim3(64 * WAVES), 0, s, tiles, segs, ssegs,   \
-                         ntiles, bases, psi, y, work, part, bufs, xcd);                                     \
+                         q, counters, bases, psi, y, work, part, bufs);                                     \
     else                                                                                                    \
       hipLaunchKernelGGL(stage2_split##NS##_kernel, dim3(grid), dim3(64 * WAVES), 0, s, tiles, segs, ssegs,   \
-                         ntiles, bases, psi, y, work, part, bufs, xcd);                                     \
+                         q, counters, bases, psi, y, work, part, bufs);                                     \
     return;                                                                                                 \
   }
   LAUNCH(3)

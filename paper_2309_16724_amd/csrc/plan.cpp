@@ -274,7 +274,7 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
       for (const auto &pa : T.rows[tk.row].pos) s.slots.push_back(pa.pD);
     }
     int64_t woff = 0;
-    std::vector<double> cost1m;   // K of every stage-1 work-group tile
+    std::vector<double> cost1, cost1m;   // K of every stage-1 tile
     for (auto &kv : stripes) {
       Stripe &s = kv.second;
       std::sort(s.slots.begin(), s.slots.end());
@@ -345,6 +345,7 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
               cost1m.push_back(s.dRin);
             } else {
               ch.tile1.push_back(t);
+              cost1.push_back(s.dRin);
             }
           }
         s0 = s1;
@@ -524,12 +525,17 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
     };
     std::stable_sort(tiles2.begin(), tiles2.end(), by_cost);
     std::stable_sort(tiles2m.begin(), tiles2m.end(), by_cost);
-    for (auto &x : tiles2) ch.tile2.push_back(x.second);
-    std::vector<double> cost2m;
+    std::vector<double> cost2, cost2m;
+    for (auto &x : tiles2) {
+      ch.tile2.push_back(x.second);
+      cost2.push_back(x.first);
+    }
     for (auto &x : tiles2m) {
       ch.tile2m.push_back(x.second);
       cost2m.push_back(x.first);
     }
+    ch.q1 = xcd_queues(cost1);
+    ch.q2 = xcd_queues(cost2);
     ch.q1m = xcd_queues(cost1m);
     ch.q2m = xcd_queues(cost2m);
     P->chunks.push_back(std::move(ch));
@@ -952,8 +958,8 @@ int count_launches(const dmrg_plan *P) {
   int n = P->psi_len > 0;
   if (split) n += !P->jobs_psi.empty();
   for (const Chunk &ch : P->chunks) {
-    // a work-group tile launch clears its queue counters first
-    n += !ch.tile1.empty() + !ch.tile2.empty() + 2 * !ch.tile1m.empty() + 2 * !ch.tile2m.empty() +
+    // every tile launch clears its queue counters first
+    n += 2 * (!ch.tile1.empty() + !ch.tile2.empty() + !ch.tile1m.empty() + !ch.tile2m.empty()) +
          !ch.red2.empty();
     if (split) n += (ch.t_exps > 0) + !ch.titems.empty();
   }
@@ -1253,20 +1259,20 @@ int enqueue_with(dmrg_plan *p, const double *psi, double *hpsi, void *stream, bo
         if (stage == 1) {
           launch_macro_split(1, ch.d_tile1m, ch.d_seg1, ch.d_sseg1, (int)ch.tile1m.size(), ch.q1m, B.counters,
                              p->n_slices, p->d_bases, psi, hpsi, B.work, B.part, B.sb, stream);
-          launch_tiles_split(1, ch.d_tile1, ch.d_seg1, ch.d_sseg1, (int)ch.tile1.size(), p->n_slices, p->d_bases,
-                             psi, hpsi, B.work, B.part, B.sb, p->xcd, stream);
+          launch_tiles_split(1, ch.d_tile1, ch.d_seg1, ch.d_sseg1, (int)ch.tile1.size(), ch.q1, B.counters,
+                             p->n_slices, p->d_bases, psi, hpsi, B.work, B.part, B.sb, stream);
         } else {
           launch_macro_split(2, ch.d_tile2m, ch.d_seg2, ch.d_sseg2, (int)ch.tile2m.size(), ch.q2m, B.counters,
                              p->n_slices, p->d_bases, psi, hpsi, B.work, B.part, B.sb, stream);
-          launch_tiles_split(2, ch.d_tile2, ch.d_seg2, ch.d_sseg2, (int)ch.tile2.size(), p->n_slices, p->d_bases,
-                             psi, hpsi, B.work, B.part, B.sb, p->xcd, stream);
+          launch_tiles_split(2, ch.d_tile2, ch.d_seg2, ch.d_sseg2, (int)ch.tile2.size(), ch.q2, B.counters,
+                             p->n_slices, p->d_bases, psi, hpsi, B.work, B.part, B.sb, stream);
         }
       } else if (stage == 1)
-        launch_tiles_f64(1, ch.d_tile1, ch.d_seg1, (int)ch.tile1.size(), p->d_bases, psi, hpsi, B.work, B.part,
-                         p->xcd, stream);
+        launch_tiles_f64(1, ch.d_tile1, ch.d_seg1, (int)ch.tile1.size(), ch.q1, B.counters, p->d_bases, psi, hpsi,
+                         B.work, B.part, stream);
       else
-        launch_tiles_f64(2, ch.d_tile2, ch.d_seg2, (int)ch.tile2.size(), p->d_bases, psi, hpsi, B.work, B.part,
-                         p->xcd, stream);
+        launch_tiles_f64(2, ch.d_tile2, ch.d_seg2, (int)ch.tile2.size(), ch.q2, B.counters, p->d_bases, psi, hpsi,
+                         B.work, B.part, stream);
       if (prof) {
         int rc = next_event(p, ev);
         if (rc) return rc;

@@ -164,7 +164,7 @@ struct Chunk {
   std::vector<Seg> seg1, seg2;
   std::vector<Tile> tile1, tile2;       // one wavefront per tile
   std::vector<Tile> tile1m, tile2m;     // work-group (macro) tiles
-  XcdQueues q1m{}, q2m{};               // their per-XCD ranges
+  XcdQueues q1{}, q2{}, q1m{}, q2m{};   // per-XCD ranges of the four lists
   std::vector<Reduce> red2;
   Seg *d_seg1 = nullptr, *d_seg2 = nullptr;
   Tile *d_tile1 = nullptr, *d_tile2 = nullptr;
@@ -191,8 +191,11 @@ constexpr int64_t DEFAULT_WORKSPACE = (int64_t)64 << 30;
 void launch_zero(double *y, int64_t n, void *stream);
 void launch_dress(const DressItem *items, int nitems, const int64_t *src_off, const double *alpha,
                   const double *const *bases, double *dst, void *stream);
-void launch_tiles_f64(int stage, const Tile *tiles, const Seg *segs, int ntiles, const double *const *bases,
-                      const double *psi, double *y, double *work, double *part, int xcd, void *stream);
+// tiles from per-XCD queues; counters: QUEUE_INTS ints of device memory, the
+// NXCD queue counters cleared by this call before the launch
+void launch_tiles_f64(int stage, const Tile *tiles, const Seg *segs, int ntiles, const XcdQueues &q,
+                      int32_t *counters, const double *const *bases, const double *psi, double *y, double *work,
+                      double *part, void *stream);
 void launch_reduce(const Reduce *red, int nred, const double *part, double *y, void *stream);
 void launch_transpose(const TransJob *jobs, int njobs, const double *src, double *dst, void *stream);
 void launch_diag(const DiagBlock *blocks, const DiagTerm *terms, int nblocks,
@@ -215,10 +218,10 @@ constexpr int SCRATCH_REGIONS = 5;
 int64_t plan_scratch_layout(const dmrg_plan_t *p, int64_t off[SCRATCH_REGIONS]);
 // one H.psi with that scratch memory at base (device address)
 int enqueue_scratch(dmrg_plan_t *p, const double *psi, double *hpsi, void *stream, char *base);
-// wavefront tiles (one tile per wavefront, taken in list order)
+// wavefront tiles (one tile per wavefront) from per-XCD queues
 void launch_tiles_split(int stage, const Tile *tiles, const Seg *segs, const SegS *ssegs, int ntiles,
-                        int nslices, const double *const *bases, const double *psi, double *y, double *work,
-                        double *part, SliceBufs bufs, int xcd, void *stream);
+                        const XcdQueues &q, int32_t *counters, int nslices, const double *const *bases,
+                        const double *psi, double *y, double *work, double *part, SliceBufs bufs, void *stream);
 // work-group (MACRO_MB) tiles from per-XCD queues; counters: QUEUE_INTS ints
 // of device memory, the NXCD queue counters cleared by this call before the launch
 void launch_macro_split(int stage, const Tile *tiles, const Seg *segs, const SegS *ssegs, int ntiles,
