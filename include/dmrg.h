@@ -271,6 +271,20 @@ int dmrg_mlp_set_params(dmrg_mlp_t *m, const float *host, int64_t n);
 int dmrg_mlp_get_params(const dmrg_mlp_t *m, float *host, int64_t n);
 /* g[i] := network output for row x[i] (device arrays x[n][2], g[n]). */
 int dmrg_mlp_forward(dmrg_mlp_t *m, const float *x, int64_t n, float *g, void *stream);
+/* The learned correction of one preconditioning step, as dmrg_davidson
+ * applies it (same fused kernel): for every segment k, elements
+ * [seg_off[k], seg_off[k+1]) of the device vectors diag, r and t,
+ * t_i = td_i (1 + g(x_i)), td_i = -r_i / (diag_i - theta_k) with
+ * |diag_i - theta_k| raised to at least floor * sigma_k, and
+ * x_i = (asinh((diag_i - theta_k) / sigma_k), log10(rnorm_k) / 8).  theta,
+ * sigma (the RMS of diag - theta over the segment), rnorm (the norm of the
+ * segment of r): host arrays of nseg doubles; seg_off: host array of nseg + 1
+ * offsets starting at 0.  floor: the relative floor (> 0).  Synchronises the
+ * stream; takes a small temporary device buffer.  DMRG_EINVAL for malformed
+ * arguments. */
+int dmrg_mlp_step(const dmrg_mlp_t *m, const double *diag, const double *r, int32_t nseg,
+                  const int64_t *seg_off, const double *theta, const double *sigma, const double *rnorm,
+                  double floor, double *t, void *stream);
 /* loss (host) and its gradient (device array of num_params floats) over the
  * n rows (x, a, b) (device arrays), by back-propagation. */
 int dmrg_mlp_loss_grad(dmrg_mlp_t *m, const float *x, const float *a, const float *b, int64_t n,

@@ -126,6 +126,7 @@ def load(path=None):
         c_f = ctypes.c_float
         L.dmrg_mlp_create.argtypes = [c_i32, ctypes.c_uint64, ctypes.POINTER(c_vp)]
         L.dmrg_mlp_num_params.argtypes = [c_vp]
+        L.dmrg_mlp_step.argtypes = [c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_dbl, c_vp, c_vp]
         L.dmrg_mlp_num_params.restype = c_i64
         L.dmrg_mlp_set_params.argtypes = [c_vp, c_vp, c_i64]
         L.dmrg_mlp_get_params.argtypes = [c_vp, c_vp, c_i64]

@@ -163,6 +163,65 @@ extern "C" int dmrg_mlp_forward(dmrg_mlp_t *m, const float *x, int64_t n, float 
   return DMRG_OK;
 }
 
+extern "C" int dmrg_mlp_step(const dmrg_mlp_t *m, const double *diag, const double *r, int32_t nseg,
+                             const int64_t *seg_off, const double *theta, const double *sigma, const double *rnorm,
+                             double floor, double *t, void *stream) {
+  if (!m || !diag || !r || !t || nseg < 1 || !seg_off || !theta || !sigma || !rnorm || !(floor > 0.0)) {
+    set_error("bad learned-step arguments");
+    return DMRG_EINVAL;
+  }
+  if (seg_off[0] != 0) { set_error("seg_off[0] must be 0"); return DMRG_EINVAL; }
+  for (int k = 0; k < nseg; k++)
+    if (seg_off[k + 1] < seg_off[k] || !(sigma[k] > 0.0) || !(rnorm[k] > 0.0)) {
+      set_error("segments must be ordered, sigma and rnorm positive");
+      return DMRG_EINVAL;
+    }
+  const int64_t n = seg_off[nseg];
+  if (n == 0) return DMRG_OK;
+  // per-segment inputs of the fused kernel: theta, sigma, feature f1, absolute floor, offsets
+  std::vector<double> h((size_t)4 * nseg);
+  for (int k = 0; k < nseg; k++) {
+    h[k] = theta[k];
+    h[nseg + k] = sigma[k];
+    h[2 * nseg + k] = std::log10(rnorm[k]) / 8.0;
+    h[3 * nseg + k] = floor * sigma[k];
+  }
+  void *d = nullptr;
+  if (hipMalloc(&d, sizeof(double) * h.size() + sizeof(int64_t) * (nseg + 1)) != hipSuccess) {
+    set_error("hipMalloc failed in dmrg_mlp_step");
+    return DMRG_ENOMEM;
+  }
+  double *dh = (double *)d;
+  int64_t *doff = (int64_t *)(dh + h.size());
+  hipStream_t s = (hipStream_t)stream;
+  int rc = DMRG_OK;
+  if (hipMemcpyAsync(dh, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(doff, seg_off, sizeof(int64_t) * (nseg + 1), hipMemcpyHostToDevice, s) != hipSuccess) {
+    set_error("copy failed in dmrg_mlp_step");
+    rc = DMRG_EHIP;
+  } else {
+    FwdArgs A{};
+    A.params = m->p;
+    A.n = n;
+    A.d = diag;
+    A.r = r;
+    A.theta = dh;
+    A.sigma = dh + nseg;
+    A.f1 = dh + 2 * nseg;
+    A.floor_ = dh + 3 * nseg;
+    A.seg_off = doff;
+    A.nseg = nseg;
+    A.t = t;
+    launch_mlp_forward(m->width, 1, A, stream);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+      set_error("learned-step kernel failed");
+      rc = DMRG_EHIP;
+    }
+  }
+  (void)hipFree(d);
+  return rc;
+}
+
 extern "C" int dmrg_mlp_loss_grad(dmrg_mlp_t *m, const float *x, const float *a, const float *b, int64_t n,
                                   double *loss, float *grad, void *stream) {
   if (!m || !x || !a || !b || !loss || !grad || n < 1) { set_error("bad gradient arguments"); return DMRG_EINVAL; }

@@ -51,6 +51,24 @@ class MLP:
                                           self._stream(stream)), self.lib)
         return g
 
+    def step(self, diag, r, seg_off, theta, sigma, rnorm, floor=1e-2, stream=None):
+        """Learned correction t (CUDA float64) of one preconditioning step
+        for the segments seg_off (host) with per-segment theta, sigma and
+        residual norms (host sequences), as dmrg_davidson computes it."""
+        import numpy as np
+        torch = _torch()
+        assert diag.dtype == torch.float64 and r.dtype == torch.float64 and diag.is_cuda and r.is_cuda
+        diag, r = diag.contiguous(), r.contiguous()
+        t = torch.empty_like(r)
+        off = np.ascontiguousarray(seg_off, dtype=np.int64)
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        sg = np.ascontiguousarray(sigma, dtype=np.float64)
+        rn = np.ascontiguousarray(rnorm, dtype=np.float64)
+        B.check(self.lib.dmrg_mlp_step(self.handle, ctypes.c_void_p(diag.data_ptr()), ctypes.c_void_p(r.data_ptr()),
+                                       len(th), off.ctypes.data, th.ctypes.data, sg.ctypes.data, rn.ctypes.data,
+                                       floor, ctypes.c_void_p(t.data_ptr()), self._stream(stream)), self.lib)
+        return t
+
     def loss_grad(self, x, a, b, stream=None):
         torch = _torch()
         x, a, b = x.contiguous(), a.contiguous(), b.contiguous()
