@@ -62,6 +62,7 @@
  */
 #ifndef DMRG_H
 #define DMRG_H
+#include <stddef.h>
 #include <stdint.h>
 #ifdef __cplusplus
 extern "C" {
@@ -100,15 +101,15 @@ enum { DMRG_FP64 = 0, DMRG_SPLIT_BF16 = 1 };
  *    (psi, hpsi) pair into a HIP graph (on a plan-owned capture stream) and
  *    replays it on the caller's stream; at most 64 graphs are kept (least
  *    recently created evicted).  Profiling events are not recorded in graphs.
- *  DMRG_PLAN_XCD: work groups resident on one XCD take a contiguous range of
- *    tiles (shared L2) instead of taking tiles in launch order (round robin
- *    over the XCDs, which spreads the cost-sorted tile list evenly).
  *  DMRG_PLAN_AUTOTUNE: dmrg_build_tasks times dmrg_apply_H under candidate
- *    settings -- kpart in {1024, 2048, 4096} x tile_policy in {0, 1}, then the
- *    best of those with the XCD mapping toggled, then with workspace caps of
- *    512 MiB and 192 MiB -- and keeps the fastest; choices are cached for the
- *    process by a hash of the plan's block shapes and options.  The chosen
- *    values are in dmrg_plan_stats. */
+ *    settings -- kpart in {1024, 2048, 4096} x tile_policy in {0, 1}, then
+ *    for split plans the work-group tile threshold (macro_min) in
+ *    {none, 32, 48, 96} at the best of those, then workspace caps of 512 MiB
+ *    and 192 MiB -- and keeps the fastest; choices are cached by a hash of the
+ *    plan's block shapes and options, for the process and in opts.tune_cache.
+ *    The chosen values are in dmrg_plan_stats.
+ *  DMRG_PLAN_XCD: accepted for compatibility; every tile launch takes its
+ *    tiles from per-XCD queues (contiguous equal-cost ranges of the list). */
 enum { DMRG_PLAN_GRAPH = 1, DMRG_PLAN_XCD = 2, DMRG_PLAN_AUTOTUNE = 4 };
 
 typedef struct {
@@ -122,6 +123,20 @@ typedef struct {
   int32_t macro_min;        /* split plans: outputs with both sides >= this are
                                computed in 64x64 tiles by whole work groups
                                sharing LDS-staged operands (0: 48; < 0: never) */
+  /* Device memory of the plan (descriptors, operator copies, slices,
+   * workspace), of the autotuner and of dmrg_davidson / dmrg_mlp_collect on
+   * this plan comes from alloc_fn(bytes, alloc_ctx) and goes back through
+   * free_fn(ptr, alloc_ctx) (at dmrg_plan_free, re-planning, or the end of a
+   * solve); both NULL: hipMalloc / hipFree.  alloc_fn returns NULL on
+   * failure (DMRG_ENOMEM).  The memory must be usable on the streams the plan
+   * is given (e.g. a caching allocator's blocks of that stream). */
+  void *(*alloc_fn)(size_t bytes, void *ctx);
+  void (*free_fn)(void *ptr, void *ctx);
+  void *alloc_ctx;
+  /* DMRG_PLAN_AUTOTUNE: path of a text file of tuned settings (one line per
+   * plan-shape hash), read before tuning and appended after it, so a choice
+   * survives the process; NULL: tuning results are kept for the process. */
+  const char *tune_cache;
 } dmrg_plan_opts_t;
 
 typedef struct dmrg_plan dmrg_plan_t;
@@ -140,13 +155,17 @@ typedef struct {
   int32_t kpart;            /* settings in use (after autotuning)             */
   int32_t tile_policy;
   int32_t xcd;
-  int32_t tuned;            /* candidates timed by the autotuner (0: none)   */
+  int32_t tuned;            /* candidates timed by the autotuner (0: none,
+                               -1: settings read from the tune cache file) */
   int32_t launches;         /* kernel launches of one H.psi                  */
   int64_t workspace_cap;    /* stripe workspace cap in use, bytes            */
   double tune_ms;           /* autotuner wall time                            */
   double tasks_ms;          /* host: operator, sector-task and value tables  */
   double plan_ms;           /* stripe grouping, tile lists, device set-up (and
                                autotuning)                                  */
+  int32_t macro_min;        /* work-group tile threshold in use (0: none)    */
+  int32_t pad2;
+  int64_t device_bytes;     /* device memory the plan holds                  */
 } dmrg_plan_stats_t;
 
 /* Build the operator table, sector-task and sector-value tables (Sec. II A,

@@ -40,7 +40,13 @@ class ProblemT(ctypes.Structure):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("precision", c_i32), ("n_slices", c_i32), ("workspace_bytes", c_i64),
-                ("flags", c_i32), ("kpart", c_i32), ("tile_policy", c_i32), ("macro_min", c_i32)]
+                ("flags", c_i32), ("kpart", c_i32), ("tile_policy", c_i32), ("macro_min", c_i32),
+                ("alloc_fn", c_vp), ("free_fn", c_vp), ("alloc_ctx", c_vp), ("tune_cache", ctypes.c_char_p)]
+
+
+# device allocator callbacks of dmrg_plan_opts_t
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class DavOpts(ctypes.Structure):
@@ -75,7 +81,8 @@ class PlanStats(ctypes.Structure):
                 ("stage1_flops", c_dbl), ("stage2_flops", c_dbl), ("workspace_bytes", c_i64),
                 ("n_chunks", c_i32), ("kpart", c_i32), ("tile_policy", c_i32), ("xcd", c_i32),
                 ("tuned", c_i32), ("launches", c_i32), ("workspace_cap", c_i64), ("tune_ms", c_dbl),
-                ("tasks_ms", c_dbl), ("plan_ms", c_dbl)]
+                ("tasks_ms", c_dbl), ("plan_ms", c_dbl), ("macro_min", c_i32), ("pad2", c_i32),
+                ("device_bytes", c_i64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
@@ -184,7 +191,7 @@ def debug_plan_host_apply(prob, psi, workspace_bytes=0, lib=None, precision=0, n
     rd = np.ascontiguousarray(prob.right.data)
     args = ProblemArgs(prob, ld.ctypes.data, rd.ctypes.data)
     st = PlanStats()
-    opts = PlanOpts(precision, n_slices, workspace_bytes, 0, kpart, tile_policy, macro_min)
+    opts = PlanOpts(precision, n_slices, workspace_bytes, 0, kpart, tile_policy, macro_min, None, None, None, None)
     if psi is None:
         check(L.dmrg_debug_plan_host_apply(ctypes.byref(args.s), None, None, ctypes.byref(opts),
                                            ctypes.byref(st)), L)

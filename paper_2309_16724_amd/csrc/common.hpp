@@ -12,6 +12,10 @@ namespace dmrg {
 
 void set_error(const std::string &msg);
 
+// device memory through the plan's allocator (caller's callbacks or hipMalloc)
+void *plan_dalloc(dmrg_plan_t *p, size_t bytes);
+void plan_dfree(dmrg_plan_t *p, void *ptr);
+
 struct Error {
   int code;
   std::string msg;

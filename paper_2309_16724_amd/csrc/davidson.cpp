@@ -97,14 +97,17 @@ int jacobi_eigh(int m, const double *A, double *w, double *Z) {
 
 namespace {
 
+// device buffers of one solve, from the plan's allocator, returned at the end
 struct DevBuf {
+  dmrg_plan_t *plan;
   std::vector<void *> ptrs;
+  explicit DevBuf(dmrg_plan_t *p) : plan(p) {}
   ~DevBuf() {
-    for (void *p : ptrs) (void)hipFree(p);
+    for (void *p : ptrs) plan_dfree(plan, p);
   }
   void *raw(int64_t bytes) {
-    void *p = nullptr;
-    if (hipMalloc(&p, std::max<int64_t>(bytes, 8)) != hipSuccess) return nullptr;
+    void *p = plan_dalloc(plan, (size_t)std::max<int64_t>(bytes, 8));
+    if (!p) return nullptr;
     ptrs.push_back(p);
     return p;
   }
@@ -217,7 +220,7 @@ static int solve(dmrg_plan_t *p, double *psi, double *evals, const dmrg_dav_opts
       chunks.push_back({i0, std::min(P[k].off + P[k].len, i0 + VCHUNK), k, 0});
   }
   seg0.push_back((int32_t)chunks.size());
-  DevBuf buf;
+  DevBuf buf(p);
   VChunk *d_chunks = (VChunk *)buf.raw(sizeof(VChunk) * chunks.size());
   int32_t *d_seg0 = (int32_t *)buf.raw(sizeof(int32_t) * seg0.size());
   double *V = buf.get((int64_t)M * n), *W = buf.get((int64_t)M * n);
@@ -632,7 +635,7 @@ extern "C" int dmrg_mlp_collect(dmrg_plan_t *p, const double *psi0, const dmrg_d
   set_error("");
   if ((rc = dmrg_psi_layout(p, 0, &off, &len))) return rc;
   hipStream_t s = (hipStream_t)stream;
-  DevBuf buf;
+  DevBuf buf(p);
   double *star = buf.get(len), *ts = buf.get(len);
   if (!star || !ts) { set_error("hipMalloc failed in training-row capture"); return DMRG_ENOMEM; }
   double ev;

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime_api.h>
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <chrono>
 #include <climits>
@@ -82,6 +83,34 @@ struct dmrg_plan {
   std::vector<int32_t> h_se[N_SBUF];
   std::vector<void *> allocs;          // problem-level device memory (kept across re-planning)
   std::vector<void *> plan_allocs;     // tile lists, workspace, slices (freed by re-planning)
+  // device memory source (caller's callbacks or hipMalloc)
+  void *(*alloc_fn)(size_t, void *) = nullptr;
+  void (*free_fn)(void *, void *) = nullptr;
+  void *alloc_ctx = nullptr;
+  std::string tune_cache;
+  std::map<void *, size_t> sizes;      // live allocations and their sizes
+  int64_t held = 0;                    // bytes held
+  void *dalloc(size_t bytes) {
+    bytes = std::max<size_t>(bytes, 8);
+    void *p = nullptr;
+    if (alloc_fn) p = alloc_fn(bytes, alloc_ctx);
+    else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+    if (p) {
+      sizes[p] = bytes;
+      held += (int64_t)bytes;
+    }
+    return p;
+  }
+  void dfree(void *p) {
+    if (!p) return;
+    auto it = sizes.find(p);
+    if (it != sizes.end()) {
+      held -= (int64_t)it->second;
+      sizes.erase(it);
+    }
+    if (free_fn) free_fn(p, alloc_ctx);
+    else (void)hipFree(p);
+  }
   // settings of the tile lists
   int kpart = KPART, tile_policy = 0, xcd = 0, flags = 0;
   int macro_min = MACRO_MIN;          // split plans: work-group tiles for outputs >= this (0: none)
@@ -149,9 +178,8 @@ template <class T>
 int upload(dmrg_plan *p, const std::vector<T> &v, T **out, bool plan_level = true) {
   *out = nullptr;
   if (v.empty()) return DMRG_OK;
-  void *d = nullptr;
-  hipError_t e = hipMalloc(&d, sizeof(T) * v.size());
-  if (e != hipSuccess) { set_error("hipMalloc failed for plan tables"); return DMRG_ENOMEM; }
+  void *d = p->dalloc(sizeof(T) * v.size());
+  if (!d) { set_error("device allocation failed for plan tables"); return DMRG_ENOMEM; }
   (plan_level ? p->plan_allocs : p->allocs).push_back(d);
   HIPCHK(hipMemcpy(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
   *out = (T *)d;
@@ -600,27 +628,27 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
   }
   if ((rc = upload(P, P->dblocks, &P->d_dblocks)) || (rc = upload(P, P->dterms, &P->d_dterms))) return rc;
   if (P->work_elems > 0) {
-    void *d = nullptr;
-    if (hipMalloc(&d, sizeof(double) * P->work_elems) != hipSuccess) {
-      set_error("hipMalloc failed for the stripe workspace");
+    void *d = P->dalloc(sizeof(double) * P->work_elems);
+    if (!d) {
+      set_error("device allocation failed for the stripe workspace");
       return DMRG_ENOMEM;
     }
     P->plan_allocs.push_back(d);
     P->d_work = (double *)d;
   }
   {
-    void *d = nullptr;
-    if (hipMalloc(&d, sizeof(int32_t) * QUEUE_INTS) != hipSuccess) {
-      set_error("hipMalloc failed for the work queue counters");
+    void *d = P->dalloc(sizeof(int32_t) * QUEUE_INTS);
+    if (!d) {
+      set_error("device allocation failed for the work queue counters");
       return DMRG_ENOMEM;
     }
     P->plan_allocs.push_back(d);
     P->d_counters = (int32_t *)d;
   }
   if (P->part_elems > 0) {
-    void *d = nullptr;
-    if (hipMalloc(&d, sizeof(double) * P->part_elems) != hipSuccess) {
-      set_error("hipMalloc failed for the partial-tile buffer");
+    void *d = P->dalloc(sizeof(double) * P->part_elems);
+    if (!d) {
+      set_error("device allocation failed for the partial-tile buffer");
       return DMRG_ENOMEM;
     }
     P->plan_allocs.push_back(d);
@@ -906,13 +934,13 @@ int upload_split(dmrg_plan *P) {
         (rc = upload(P, ch.tjobs, &ch.d_tjobs)) || (rc = upload(P, ch.titems, &ch.d_titems)))
       return rc;
   for (int b = 0; b < N_SBUF; b++) {
-    void *d = nullptr, *e = nullptr;
-    if (hipMalloc(&d, sizeof(uint16_t) * std::max<int64_t>(1, P->sb_elems[b] * P->n_slices)) != hipSuccess ||
-        hipMalloc(&e, sizeof(int32_t) * std::max<int64_t>(1, P->sb_exps[b])) != hipSuccess) {
-      set_error("hipMalloc failed for slice buffers");
+    void *d = P->dalloc(sizeof(uint16_t) * std::max<int64_t>(1, P->sb_elems[b] * P->n_slices));
+    if (d) P->plan_allocs.push_back(d);
+    void *e = d ? P->dalloc(sizeof(int32_t) * std::max<int64_t>(1, P->sb_exps[b])) : nullptr;
+    if (!d || !e) {
+      set_error("device allocation failed for slice buffers");
       return DMRG_ENOMEM;
     }
-    P->plan_allocs.push_back(d);
     P->plan_allocs.push_back(e);
     P->sb.data[b] = (uint16_t *)d;
     P->sb.exps[b] = (int32_t *)e;
@@ -933,7 +961,7 @@ namespace {
 void release_plan(dmrg_plan *P) {
   P->wait_done();
   P->drop_graphs();
-  for (void *a : P->plan_allocs) (void)hipFree(a);
+  for (void *a : P->plan_allocs) P->dfree(a);
   P->plan_allocs.clear();
   P->chunks.clear();
   P->dblocks.clear();
@@ -1021,73 +1049,118 @@ uint64_t plan_hash(const dmrg_plan *P) {
 }
 
 std::mutex g_tune_mu;
-std::map<uint64_t, std::array<int64_t, 4>> g_tune_cache;   // kpart, tile policy, workspace cap, xcd
+// kpart, tile policy, workspace cap, work-group tile threshold
+using TuneChoice = std::array<int64_t, 4>;
+std::map<uint64_t, TuneChoice> g_tune_cache;
+
+// one line per plan-shape hash: "<hash> <kpart> <tile_policy> <cap> <macro_min>"
+bool read_tune_file(const std::string &path, uint64_t key, TuneChoice &out) {
+  if (path.empty()) return false;
+  FILE *f = std::fopen(path.c_str(), "r");
+  if (!f) return false;
+  unsigned long long h;
+  long long a, b, c, d;
+  bool found = false;
+  while (std::fscanf(f, "%llx %lld %lld %lld %lld", &h, &a, &b, &c, &d) == 5)
+    if ((uint64_t)h == key) {   // the last line of a key wins
+      out = {a, b, c, d};
+      found = true;
+    }
+  std::fclose(f);
+  return found;
+}
+
+void append_tune_file(const std::string &path, uint64_t key, const TuneChoice &c) {
+  if (path.empty()) return;
+  FILE *f = std::fopen(path.c_str(), "a");
+  if (!f) return;
+  std::fprintf(f, "%016llx %lld %lld %lld %lld\n", (unsigned long long)key, (long long)c[0], (long long)c[1],
+               (long long)c[2], (long long)c[3]);
+  std::fclose(f);
+}
+
+void apply_choice(dmrg_plan *P, const TuneChoice &c) {
+  P->kpart = (int)c[0];
+  P->tile_policy = (int)c[1];
+  P->budget = c[2];
+  P->macro_min = (int)c[3];
+}
 
 // Times candidate settings on the live plan and keeps the fastest (see
-// DMRG_PLAN_AUTOTUNE): first kpart x tile policy at the requested workspace
-// cap and XCD mapping, then the best of those with the mapping toggled, then
-// smaller caps (more, smaller launches whose stripes stay in the last-level
-// cache).
+// DMRG_PLAN_AUTOTUNE): kpart x tile policy at the requested workspace cap,
+// then (split plans) the work-group tile threshold, then smaller caps (more,
+// smaller launches whose stripes stay in the last-level cache).  Choices are
+// cached for the process and, with a tune_cache path, in that file.
 int autotune(dmrg_plan *P, void *stream) {
   auto t0 = std::chrono::steady_clock::now();
   const uint64_t key = plan_hash(P);
+  TuneChoice hit{};
+  bool have = false;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      P->kpart = (int)it->second[0];
-      P->tile_policy = (int)it->second[1];
-      P->budget = it->second[2];
-      P->xcd = (int)it->second[3];
+      hit = it->second;
+      have = true;
       P->tuned = 0;
-      int rc = replan(P);
-      P->tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-      return rc;
+    } else if (read_tune_file(P->tune_cache, key, hit)) {
+      g_tune_cache[key] = hit;
+      have = true;
+      P->tuned = -1;
     }
   }
-  double *x = nullptr, *y = nullptr;
-  if (hipMalloc((void **)&x, sizeof(double) * std::max<int64_t>(P->psi_len, 1)) != hipSuccess ||
-      hipMalloc((void **)&y, sizeof(double) * std::max<int64_t>(P->psi_len, 1)) != hipSuccess) {
-    if (x) (void)hipFree(x);
-    set_error("hipMalloc failed in the autotuner");
+  if (have) {
+    apply_choice(P, hit);
+    int rc = replan(P);
+    P->tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
+  }
+  double *x = (double *)P->dalloc(sizeof(double) * std::max<int64_t>(P->psi_len, 1));
+  double *y = x ? (double *)P->dalloc(sizeof(double) * std::max<int64_t>(P->psi_len, 1)) : nullptr;
+  if (!x || !y) {
+    P->dfree(x);
+    set_error("device allocation failed in the autotuner");
     return DMRG_ENOMEM;
   }
-  int rc = hipMemset(x, 0, sizeof(double) * std::max<int64_t>(P->psi_len, 1)) == hipSuccess ? DMRG_OK : DMRG_EHIP;
+  int rc = hipMemsetAsync(x, 0, sizeof(double) * std::max<int64_t>(P->psi_len, 1), (hipStream_t)stream) == hipSuccess
+               ? DMRG_OK : DMRG_EHIP;
   const int64_t base = P->budget;
   double best = 1e300;
-  const int xcd0 = P->xcd;
-  std::array<int64_t, 4> bc{P->kpart, P->tile_policy, base, xcd0};
-  auto trial = [&](int kp, int pol, int64_t budget, int xcd) {
+  TuneChoice bc{P->kpart, P->tile_policy, base, P->macro_min};
+  auto trial = [&](const TuneChoice &c) {
     if (rc) return;
-    P->kpart = kp;
-    P->tile_policy = pol;
-    P->budget = budget;
-    P->xcd = xcd;
+    apply_choice(P, c);
     double ms = 0.0;
     rc = replan(P);
     if (!rc) rc = time_apply(P, x, y, stream, &ms);
     P->tuned++;
     if (!rc && ms < best) {
       best = ms;
-      bc = {kp, pol, budget, xcd};
+      bc = c;
     }
   };
+  const int64_t mm0 = P->macro_min;
   for (int kp : {1024, 2048, 4096})
-    for (int pol : {0, 1}) trial(kp, pol, base, xcd0);
-  trial((int)bc[0], (int)bc[1], base, 1 - xcd0);
-  for (int64_t b : {(int64_t)512 << 20, (int64_t)192 << 20})
-    if (b < base) trial((int)bc[0], (int)bc[1], b, (int)bc[3]);
-  (void)hipFree(x);
-  (void)hipFree(y);
+    for (int pol : {0, 1}) trial({kp, pol, base, mm0});
+  if (P->precision == DMRG_SPLIT_BF16) {
+    const TuneChoice b0 = bc;
+    for (int mm : {0, 32, 48, 96})
+      if (mm != mm0) trial({b0[0], b0[1], base, mm});
+  }
+  {
+    const TuneChoice b1 = bc;
+    for (int64_t b : {(int64_t)512 << 20, (int64_t)192 << 20})
+      if (b < base) trial({b1[0], b1[1], b, b1[3]});
+  }
+  P->dfree(x);
+  P->dfree(y);
   if (rc) return rc;
-  P->kpart = (int)bc[0];
-  P->tile_policy = (int)bc[1];
-  P->budget = bc[2];
-  P->xcd = (int)bc[3];
+  apply_choice(P, bc);
   rc = replan(P);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = bc;
+    append_tune_file(P->tune_cache, key, bc);
   }
   P->tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return rc;
@@ -1099,8 +1172,8 @@ extern "C" void dmrg_plan_free(dmrg_plan_t *p) {
   if (!p) return;
   p->wait_done();
   p->drop_graphs();
-  for (void *a : p->plan_allocs) (void)hipFree(a);
-  for (void *a : p->allocs) (void)hipFree(a);
+  for (void *a : p->plan_allocs) p->dfree(a);
+  for (void *a : p->allocs) p->dfree(a);
   delete p;
 }
 
@@ -1113,6 +1186,17 @@ extern "C" int dmrg_build_tasks(const dmrg_problem_t *probs, int32_t n_probs, co
   dmrg_plan *P = new dmrg_plan();
   std::memset(&P->stats, 0, sizeof(P->stats));
   P->build_stream = (hipStream_t)stream;
+  if (opts && (!opts->alloc_fn) != (!opts->free_fn)) {
+    set_error("alloc_fn and free_fn must be given together");
+    delete P;
+    return DMRG_EINVAL;
+  }
+  if (opts) {
+    P->alloc_fn = opts->alloc_fn;
+    P->free_fn = opts->free_fn;
+    P->alloc_ctx = opts->alloc_ctx;
+    if (opts->tune_cache) P->tune_cache = opts->tune_cache;
+  }
   try {
     P->precision = opts ? opts->precision : DMRG_FP64;
     P->n_slices = opts ? opts->n_slices : 0;
@@ -1148,9 +1232,9 @@ extern "C" int dmrg_build_tasks(const dmrg_problem_t *probs, int32_t n_probs, co
       P->bases_h.push_back(probs[k].rdata);
       pp->base_dress = BASE_OPS + (int)P->bases_h.size();
       if (pp->T.dress_len > 0) {
-        void *d = nullptr;
-        if (hipMalloc(&d, sizeof(double) * pp->T.dress_len) != hipSuccess) {
-          set_error("hipMalloc failed for dressed operators");
+        void *d = P->dalloc(sizeof(double) * pp->T.dress_len);
+        if (!d) {
+          set_error("device allocation failed for dressed operators");
           dmrg_plan_free(P);
           return DMRG_ENOMEM;
         }
@@ -1166,9 +1250,9 @@ extern "C" int dmrg_build_tasks(const dmrg_problem_t *probs, int32_t n_probs, co
       for (int q = 0; q < 3; q++) {
         *tbase[q] = BASE_OPS + (int)P->bases_h.size();
         if (tlen[q] > 0) {
-          void *d = nullptr;
-          if (hipMalloc(&d, sizeof(double) * tlen[q]) != hipSuccess) {
-            set_error("hipMalloc failed for transposed operators");
+          void *d = P->dalloc(sizeof(double) * tlen[q]);
+          if (!d) {
+            set_error("device allocation failed for transposed operators");
             dmrg_plan_free(P);
             return DMRG_ENOMEM;
           }
@@ -1294,6 +1378,9 @@ int enqueue(dmrg_plan *p, const double *psi, double *hpsi, void *stream, bool pr
 }  // namespace
 
 namespace dmrg {
+void *plan_dalloc(dmrg_plan_t *p, size_t bytes) { return p->dalloc(bytes); }
+void plan_dfree(dmrg_plan_t *p, void *ptr) { p->dfree(ptr); }
+
 // Byte layout of the scratch memory of one H.psi (see dmrg_apply_H_static):
 // stripe workspace, partial tiles, stripe slices, stripe exponents, each
 // 256-byte aligned.  Returns the total.
@@ -1412,6 +1499,8 @@ extern "C" int dmrg_plan_stats(const dmrg_plan_t *p, dmrg_plan_stats_t *st) {
   st->tuned = p->tuned;
   st->workspace_cap = p->budget;
   st->tune_ms = p->tune_ms;
+  st->macro_min = p->precision == DMRG_SPLIT_BF16 ? p->macro_min : 0;
+  st->device_bytes = p->held;
   return DMRG_OK;
 }
 

@@ -16,9 +16,46 @@ def _torch():
     return torch
 
 
+class TorchAllocator:
+    """Device-memory callbacks for dmrg_plan_opts_t that take the plan's
+    memory from PyTorch's caching allocator on a given stream (counting
+    calls, bytes and live blocks)."""
+
+    def __init__(self, device, stream=None):
+        torch = _torch()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.calls = self.frees = 0
+        self.bytes = 0
+        self.live = {}
+
+        def _alloc(n, ctx):
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(n), self.device.index or 0, self.stream)
+            except Exception:
+                return None
+            self.calls += 1
+            self.bytes += int(n)
+            self.live[int(p)] = int(n)
+            return int(p)
+
+        def _free(p, ctx):
+            if p:
+                self.live.pop(int(p), None)
+                self.frees += 1
+                torch.cuda.caching_allocator_delete(int(p))
+
+        self.alloc_fn = B.ALLOC_FN(_alloc)
+        self.free_fn = B.FREE_FN(_free)
+
+
 class Plan:
     def __init__(self, problems, precision=B.DMRG_FP64, n_slices=0, workspace_bytes=0,
-                 device="cuda:0", flags=0, kpart=0, tile_policy=0, macro_min=0):
+                 device="cuda:0", flags=0, kpart=0, tile_policy=0, macro_min=0, allocator=None,
+                 tune_cache=None):
+        """allocator: None (the library uses hipMalloc), "torch" (PyTorch's
+        caching allocator on the current stream) or a TorchAllocator;
+        tune_cache: file of autotuned settings (with DMRG_PLAN_AUTOTUNE)."""
         torch = _torch()
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
@@ -41,7 +78,15 @@ class Plan:
             structs.append(args.s)
         arr = (B.ProblemT * len(structs))(*structs)
         self._keep.append(arr)
-        opts = B.PlanOpts(precision, n_slices, workspace_bytes, flags, kpart, tile_policy, macro_min)
+        if allocator == "torch":
+            allocator = TorchAllocator(device)
+        self.allocator = allocator
+        fa = ctypes.cast(allocator.alloc_fn, ctypes.c_void_p) if allocator is not None else None
+        ff = ctypes.cast(allocator.free_fn, ctypes.c_void_p) if allocator is not None else None
+        tc = None if tune_cache is None else str(tune_cache).encode()
+        self._keep.append(tc)
+        opts = B.PlanOpts(precision, n_slices, workspace_bytes, flags, kpart, tile_policy, macro_min,
+                          fa, ff, None, tc)
         h = ctypes.c_void_p()
         stream = torch.cuda.current_stream(self.device).cuda_stream
         torch.cuda.synchronize(self.device)
