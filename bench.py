@@ -112,7 +112,7 @@ def cpu_baseline(flops_bench, bench_workload):
     flops = st["flops"]
     cores = info["usable_cpus"] or 1
     t_all, desc_all, par = _oracle_rate(prob, flops, cores, 60.0)
-    t_one, desc_one, _ = _oracle_rate(prob, flops, 1, 20.0)
+    t_one, desc_one, _ = _oracle_rate(prob, flops, 1, 12.0)
     return {
         "value": flops / t_all / 1e12,
         "unit": "TFLOP/s",
@@ -300,9 +300,23 @@ def time_hpsi(torch, plan, x, y, steps, warmup):
     for _ in range(steps):
         plan.apply(x, y)
     torch.cuda.synchronize()
-    prof = {s_: plan.profile(s_) for s_ in (1, 2)}
+    prof = {s_: plan.profile(s_) for s_ in (1, 2, 11, 12, 21, 22)}
     plan.set_profiling(False)
     return ms, prof
+
+
+KERNEL_NAMES = {
+    # profile code -> kernel (split s=5 plans, FP64 plans)
+    11: ("stage1_msplit5_kernel", None), 12: ("stage2_msplit5_kernel", None),
+    21: ("stage1_split5_kernel", "stage_f64_kernel<1>"), 22: ("stage2_split5_kernel", "stage_f64_kernel<2>"),
+}
+
+
+def dominant(prof, split):
+    """(kernel name, launches, ms, flops) of the tile kernel with the most time."""
+    code = max((c for c in (11, 12, 21, 22) if prof[c][0] > 0), key=lambda c: prof[c][1])
+    n, ms, fl = prof[code]
+    return KERNEL_NAMES[code][0 if split else 1], n, ms, fl
 
 
 def sampled_errors(yv, workload, prob):
@@ -331,52 +345,67 @@ def sampled_errors(yv, workload, prob):
     return {"max_rel": err / scale, "elements": n, "blocks": len(case["samples"])}
 
 
-def davidson_runs(torch, args, w, plan_flags):
-    """Davidson s/step on a workload: diagonal preconditioner (FP64 H.psi),
-    learned preconditioner, and the diagonal solve with split H.psi.  Derived
-    comparisons are reported only between converged solves."""
+def davidson_runs(torch, args, plan_flags):
+    """Davidson s/step: the diagonal-preconditioned solve with FP64 and with
+    split H.psi on the --dav-workload, and the learned preconditioner against
+    the diagonal one on the --mlp-workload (trained on L=24 solves).  Derived
+    comparisons are reported only between converged solves; progress lines
+    go to stderr every 25 iterations."""
     import numpy as np
     from paper_2309_16724_amd.hpsi import Plan
-    prob = make_problem(w)
-    plan = Plan(prob, flags=plan_flags)
-    x_np = np.random.default_rng(100).standard_normal(plan.size)
-    x0 = torch.from_numpy(x_np / np.linalg.norm(x_np)).cuda()
     fk = {} if args.dav_floor is None else {"floor": args.dav_floor}
-    torch.cuda.synchronize()
-    td = time.time()
-    e_dav, _, dst = plan.davidson(x0, tol=1e-8, check=False, verbose=int(args.dav_verbose), **fk)
-    t_dav = time.time() - td
-    out = {"workload": args.dav_workload,
-           "diagonal": {"s_per_step": t_dav, "iterations": dst["iters"], "n_hpsi": dst["n_hpsi"],
-                        "converged": dst["converged"], "residual": dst["residual"], "energy": e_dav,
-                        "sigma": dst["sigma"], "floor": args.dav_floor, "t_hpsi_s": dst["t_hpsi_s"]}}
-    if not args.no_mlp:
-        net, info = train_preconditioner(torch, [(24, 24, 0, 10000 + k, 512) for k in range(4)], floor=args.dav_floor)
-        print("# learned preconditioner: %s" % json.dumps(info), file=sys.stderr, flush=True)
+
+    def start(plan):
+        x_np = np.random.default_rng(100).standard_normal(plan.size)
+        return torch.from_numpy(x_np / np.linalg.norm(x_np)).cuda()
+
+    def solve(plan, x0, **kw):
         torch.cuda.synchronize()
-        tm = time.time()
-        e_mlp, _, mst = plan.davidson(x0, tol=1e-8, mlp=net, check=False, verbose=int(args.dav_verbose), **fk)
-        t_mlp = time.time() - tm
-        net.free()
-        both = dst["converged"] == 1 and mst["converged"] == 1
-        out["learned"] = {"s_per_step": t_mlp, "iterations": mst["iters"], "n_hpsi": mst["n_hpsi"],
-                          "converged": mst["converged"], "residual": mst["residual"],
-                          "fallbacks": mst["fallbacks"], "switched": mst["switched"],
-                          "t_hpsi_s": mst["t_hpsi_s"],
-                          "energy_minus_diagonal": (e_mlp - e_dav) if both else None,
-                          "speedup_vs_diagonal": (t_dav / t_mlp) if both else None,
-                          "training": info}
+        t0 = time.time()
+        e, _, st = plan.davidson(x0, tol=1e-8, check=False, verbose=1, **fk, **kw)
+        return e, st, time.time() - t0
+
+    out = {"workload": args.dav_workload}
+    prob = make_problem(WORKLOADS[args.dav_workload])
+    plan = Plan(prob, flags=plan_flags)
+    x0 = start(plan)
+    e_dav, dst, t_dav = solve(plan, x0)
+    print("# davidson fp64 %s: %d iterations, %.1f s" % (args.dav_workload, dst["iters"], t_dav),
+          file=sys.stderr, flush=True)
+    out["diagonal"] = {"s_per_step": t_dav, "iterations": dst["iters"], "n_hpsi": dst["n_hpsi"],
+                       "converged": dst["converged"], "residual": dst["residual"], "energy": e_dav,
+                       "sigma": dst["sigma"], "floor": args.dav_floor, "t_hpsi_s": dst["t_hpsi_s"]}
     plan.free()
     if not args.no_split_davidson:
         splan = Plan(prob, precision=1, n_slices=5, flags=plan_flags)
-        torch.cuda.synchronize()
-        tsd = time.time()
-        e_sp, _, sst = splan.davidson(x0, tol=1e-8, check=False, verbose=int(args.dav_verbose), **fk)
+        e_sp, sst, t_sp = solve(splan, x0)
+        print("# davidson split %s: %d iterations, %.1f s" % (args.dav_workload, sst["iters"], t_sp),
+              file=sys.stderr, flush=True)
         both = dst["converged"] == 1 and sst["converged"] == 1
-        out["split"] = {"s_per_step": time.time() - tsd, "iterations": sst["iters"],
-                        "converged": sst["converged"], "residual": sst["residual"],
-                        "energy_minus_fp64": (e_sp - e_dav) if both else None}
+        out["split"] = {"s_per_step": t_sp, "iterations": sst["iters"], "converged": sst["converged"],
+                        "residual": sst["residual"], "energy_minus_fp64": (e_sp - e_dav) if both else None}
         splan.free()
+    del prob
+    if not args.no_mlp:
+        net, info = train_preconditioner(torch, [(24, 24, 0, 10000 + k, 512) for k in range(4)], floor=args.dav_floor)
+        print("# learned preconditioner: %s" % json.dumps(info), file=sys.stderr, flush=True)
+        mprob = make_problem(WORKLOADS[args.mlp_workload])
+        mplan = Plan(mprob, flags=plan_flags)
+        x1 = start(mplan)
+        e_d, d_st, t_d = solve(mplan, x1)
+        e_m, m_st, t_m = solve(mplan, x1, mlp=net)
+        net.free()
+        mplan.free()
+        both = d_st["converged"] == 1 and m_st["converged"] == 1
+        out["learned"] = {"workload": args.mlp_workload,
+                          "diagonal": {"s_per_step": t_d, "iterations": d_st["iters"],
+                                       "converged": d_st["converged"], "energy": e_d},
+                          "learned": {"s_per_step": t_m, "iterations": m_st["iters"],
+                                      "converged": m_st["converged"], "residual": m_st["residual"],
+                                      "fallbacks": m_st["fallbacks"], "switched": m_st["switched"]},
+                          "energy_minus_diagonal": (e_m - e_d) if both else None,
+                          "speedup_vs_diagonal": (t_d / t_m) if both else None,
+                          "training": info}
     return out
 
 
@@ -391,15 +420,15 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of graph replays")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-preconditioner Davidson")
     ap.add_argument("--no-davidson", action="store_true", help="time H.psi only")
-    ap.add_argument("--dav-workload", default="L24_D512", choices=sorted(WORKLOADS),
-                    help="workload of the Davidson solves (default L24_D512: a solve of the L=54 "
-                         "workload takes hundreds of 1.5 s H.psi steps)")
+    ap.add_argument("--dav-workload", default="L54_D2048", choices=sorted(WORKLOADS),
+                    help="workload of the Davidson solves (default: the H.psi workload's L=54, D=2048)")
+    ap.add_argument("--mlp-workload", default="L24_D512", choices=sorted(WORKLOADS),
+                    help="workload of the learned-versus-diagonal preconditioner comparison "
+                         "(L64_D3072 for the learned preconditioner's evaluation configuration)")
     ap.add_argument("--no-split-davidson", action="store_true",
                     help="skip the Davidson solve with split-precision H.psi")
     ap.add_argument("--dav-floor", type=float, default=None,
                     help="relative preconditioner floor of the Davidson solves (library default if omitted)")
-    ap.add_argument("--dav-verbose", action="store_true",
-                    help="Davidson progress lines on stderr every 25 iterations (long solves)")
     ap.add_argument("--hpsi-only", choices=("fp64", "split"),
                     help="time only H.psi of one precision (for profiler runs); also copies "
                          "256 MiB once with a plain device copy as a counter reference")
@@ -468,13 +497,11 @@ def main():
     del y5, y64
     dav = None
     if not args.no_davidson:
-        dav = davidson_runs(torch, args, WORKLOADS[args.dav_workload], plan_flags)
-    dom = max((1, 2), key=lambda s_: prof5[s_][1])
-    n_l, ms_l, fl_l = prof5[dom]
+        dav = davidson_runs(torch, args, plan_flags)
+    kname5, n_l, ms_l, fl_l = dominant(prof5, True)
     achieved = (fl_l / n_l) / (ms_l / n_l * 1e-3) / 1e12
     split_peak = BF16_PEAK_TFLOPS / 15.0           # s = 5: 15 slice products per FP64 product
-    dom64 = max((1, 2), key=lambda s_: prof64[s_][1])
-    n6, ms6, fl6 = prof64[dom64]
+    kname64, n6, ms6, fl6 = dominant(prof64, False)
     tflops5 = st5["flops"] / (ms5 * 1e-3) / 1e12
     tflops64 = st64["flops"] / (ms64 * 1e-3) / 1e12
     ach64 = (fl6 / n6) / (ms6 / n6 * 1e-3) / 1e12
@@ -505,15 +532,17 @@ def main():
         "fp64_rel_err_vs_oracle_samples": err64,
         "split_rel_err_vs_fp64": rel,
         "fp64": {"value": tflops64, "ms_per_step": ms64,
-                 "roofline": {"bound": "mfma", "kernel": "stage_f64_kernel<%d>" % dom64, "achieved": ach64,
+                 "roofline": {"bound": "mfma", "kernel": kname64, "achieved": ach64,
                               "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach64 / FP64_PEAK_TFLOPS,
-                              "traffic": measured_traffic(args.workload, "stage_f64_kernel<%d>" % dom64)}},
+                              "traffic": measured_traffic(args.workload, kname64)},
+                 "stages_ms_per_step": {str(k): v[1] / args.steps for k, v in prof64.items()}},
         "speedup_split_vs_fp64": ms64 / ms5,
         "davidson": dav,
-        "roofline": {"bound": "mfma", "kernel": "stage%d_split5_kernel" % dom,
+        "split_stages_ms_per_step": {str(k): v[1] / args.steps for k, v in prof5.items()},
+        "roofline": {"bound": "mfma", "kernel": kname5,
                      "achieved": achieved, "peak": split_peak, "unit": "TFLOP/s",
                      "frac": achieved / split_peak,
-                     "traffic": measured_traffic(args.workload, "stage%d_split5_kernel" % dom),
+                     "traffic": measured_traffic(args.workload, kname5),
                      "peak_note": "BF16 dense 2516.6 TF/s divided by 15 slice products (s=5)"},
         "cpu_baseline": None,
     }

@@ -333,11 +333,14 @@ int dmrg_mlp_collect(dmrg_plan_t *p, const double *psi0, const dmrg_dav_opts_t *
 void dmrg_mlp_free(dmrg_mlp_t *m);
 
 /* Profiling: when on, dmrg_apply_H records a hipEvent pair on its stream
- * around each first-stage (stage 1) and second-stage (stage 2) kernel launch
- * (slicing launches of split plans fall outside the pairs).
- * dmrg_get_profile waits for the recorded events and returns the number of
- * launches, their summed duration and summed algorithmic flops since the
- * last dmrg_set_profiling call. */
+ * around each tile launch of the first (1) and second (2) stage -- the
+ * work-group tile launch of split plans and the wavefront tile launch, each
+ * with the algorithmic flops of its tiles (slicing launches fall outside the
+ * pairs).  dmrg_get_profile waits for the recorded events and returns the
+ * number of launches, their summed duration and summed algorithmic flops
+ * since the last dmrg_set_profiling call, for stage 1 or 2 (all its tile
+ * launches), 11 or 12 (its work-group tile launches only) or 21 or 22 (its
+ * wavefront tile launches only). */
 int dmrg_set_profiling(dmrg_plan_t *p, int32_t on);
 int dmrg_get_profile(dmrg_plan_t *p, int32_t stage, int64_t *n_launches, double *total_ms,
                      double *total_flops);

@@ -225,6 +225,18 @@ std::vector<std::pair<int, int>> patch_order(int nr, int nc) {
   return v;
 }
 
+// algorithmic flops of a tile list: 2 (tile rows) (tile columns) K over its
+// segments with a left operator (identity segments are additions)
+double list_flops(const std::vector<Tile> &tiles, const std::vector<Seg> &segs) {
+  double f = 0.0;
+  for (const Tile &t : tiles) {
+    const double mt = std::min(tile_rows(t.mb), t.m - t.i0), nt = std::min(tile_cols(t.mb), t.n - t.j0);
+    for (int i = 0; i < t.nseg; i++)
+      if (segs[t.seg0 + i].a_base >= 0) f += 2.0 * mt * nt * segs[t.seg0 + i].K;
+  }
+  return f;
+}
+
 // NXCD contiguous ranges of a tile list with about equal summed cost
 XcdQueues xcd_queues(const std::vector<double> &cost) {
   XcdQueues q{};
@@ -564,6 +576,10 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
     }
     ch.q1 = xcd_queues(cost1);
     ch.q2 = xcd_queues(cost2);
+    ch.flops1m = list_flops(ch.tile1m, ch.seg1);
+    ch.flops1w = list_flops(ch.tile1, ch.seg1);
+    ch.flops2m = list_flops(ch.tile2m, ch.seg2);
+    ch.flops2w = list_flops(ch.tile2, ch.seg2);
     ch.q1m = xcd_queues(cost1m);
     ch.q2m = xcd_queues(cost2m);
     P->chunks.push_back(std::move(ch));
@@ -1331,40 +1347,53 @@ int enqueue_with(dmrg_plan *p, const double *psi, double *hpsi, void *stream, bo
       if (split && stage == 1) launch_fill_int(B.sb.exps[SBUF_T], ch.t_exps, INT_MIN, stream);
       if (split && stage == 2)
         launch_tslices(ch.d_tjobs, ch.d_titems, (int)ch.titems.size(), p->n_slices, B.work, B.sb, stream);
-      int e0 = -1;
-      if (prof) {
+      // profiling: an event pair around each tile launch, marked 10 + stage
+      // (work-group tiles) or 20 + stage (wavefront tiles) with its flops
+      auto timed = [&](int code, double flops, auto &&launch) -> int {
+        if (!prof) {
+          launch();
+          return DMRG_OK;
+        }
         int rc = next_event(p, ev);
         if (rc) return rc;
-        e0 = (int)ev;
+        const int e0 = (int)ev;
         HIPCHK(hipEventRecord(p->ev_pool[ev++], (hipStream_t)stream));
-      }
+        launch();
+        if ((rc = next_event(p, ev))) return rc;
+        HIPCHK(hipEventRecord(p->ev_pool[ev], (hipStream_t)stream));
+        p->ev_marks.push_back({code, {e0, (int)ev}});
+        p->ev_flops.push_back(flops);
+        ev++;
+        return DMRG_OK;
+      };
+      int rc = DMRG_OK;
       if (split) {
         // work-group tiles (the larger outputs) first, then the wavefront tiles
-        if (stage == 1) {
-          launch_macro_split(1, ch.d_tile1m, ch.d_seg1, ch.d_sseg1, (int)ch.tile1m.size(), ch.q1m, B.counters,
-                             p->n_slices, p->d_bases, psi, hpsi, B.work, B.part, B.sb, stream);
-          launch_tiles_split(1, ch.d_tile1, ch.d_seg1, ch.d_sseg1, (int)ch.tile1.size(), ch.q1, B.counters,
-                             p->n_slices, p->d_bases, psi, hpsi, B.work, B.part, B.sb, stream);
-        } else {
-          launch_macro_split(2, ch.d_tile2m, ch.d_seg2, ch.d_sseg2, (int)ch.tile2m.size(), ch.q2m, B.counters,
-                             p->n_slices, p->d_bases, psi, hpsi, B.work, B.part, B.sb, stream);
-          launch_tiles_split(2, ch.d_tile2, ch.d_seg2, ch.d_sseg2, (int)ch.tile2.size(), ch.q2, B.counters,
-                             p->n_slices, p->d_bases, psi, hpsi, B.work, B.part, B.sb, stream);
-        }
-      } else if (stage == 1)
-        launch_tiles_f64(1, ch.d_tile1, ch.d_seg1, (int)ch.tile1.size(), ch.q1, B.counters, p->d_bases, psi, hpsi,
-                         B.work, B.part, stream);
-      else
-        launch_tiles_f64(2, ch.d_tile2, ch.d_seg2, (int)ch.tile2.size(), ch.q2, B.counters, p->d_bases, psi, hpsi,
-                         B.work, B.part, stream);
-      if (prof) {
-        int rc = next_event(p, ev);
-        if (rc) return rc;
-        HIPCHK(hipEventRecord(p->ev_pool[ev], (hipStream_t)stream));
-        p->ev_marks.push_back({stage, {e0, (int)ev}});
-        p->ev_flops.push_back(stage == 1 ? ch.flops1 : ch.flops2);
-        ev++;
+        const bool s1 = stage == 1;
+        if (!(s1 ? ch.tile1m : ch.tile2m).empty())
+          rc = timed(10 + stage, s1 ? ch.flops1m : ch.flops2m, [&] {
+            launch_macro_split(stage, s1 ? ch.d_tile1m : ch.d_tile2m, s1 ? ch.d_seg1 : ch.d_seg2,
+                               s1 ? ch.d_sseg1 : ch.d_sseg2, (int)(s1 ? ch.tile1m : ch.tile2m).size(),
+                               s1 ? ch.q1m : ch.q2m, B.counters, p->n_slices, p->d_bases, psi, hpsi, B.work,
+                               B.part, B.sb, stream);
+          });
+        if (!rc && !(s1 ? ch.tile1 : ch.tile2).empty())
+          rc = timed(20 + stage, s1 ? ch.flops1w : ch.flops2w, [&] {
+            launch_tiles_split(stage, s1 ? ch.d_tile1 : ch.d_tile2, s1 ? ch.d_seg1 : ch.d_seg2,
+                               s1 ? ch.d_sseg1 : ch.d_sseg2, (int)(s1 ? ch.tile1 : ch.tile2).size(),
+                               s1 ? ch.q1 : ch.q2, B.counters, p->n_slices, p->d_bases, psi, hpsi, B.work,
+                               B.part, B.sb, stream);
+          });
+      } else {
+        const bool s1 = stage == 1;
+        if (!(s1 ? ch.tile1 : ch.tile2).empty())
+          rc = timed(20 + stage, s1 ? ch.flops1w : ch.flops2w, [&] {
+            launch_tiles_f64(stage, s1 ? ch.d_tile1 : ch.d_tile2, s1 ? ch.d_seg1 : ch.d_seg2,
+                             (int)(s1 ? ch.tile1 : ch.tile2).size(), s1 ? ch.q1 : ch.q2, B.counters, p->d_bases,
+                             psi, hpsi, B.work, B.part, stream);
+          });
       }
+      if (rc) return rc;
     }
     launch_reduce(ch.d_red2, (int)ch.red2.size(), B.part, hpsi, stream);
   }
@@ -1464,11 +1493,15 @@ extern "C" int dmrg_set_profiling(dmrg_plan_t *p, int32_t on) {
 
 extern "C" int dmrg_get_profile(dmrg_plan_t *p, int32_t stage, int64_t *n_launches, double *total_ms,
                                 double *total_flops) {
-  if (!p || stage < 1 || stage > 2) { set_error("bad plan or stage"); return DMRG_EINVAL; }
+  if (!p || !(stage == 1 || stage == 2 || stage == 11 || stage == 12 || stage == 21 || stage == 22)) {
+    set_error("bad plan or stage");
+    return DMRG_EINVAL;
+  }
   int64_t n = 0;
   double ms = 0.0, fl = 0.0;
   for (size_t i = 0; i < p->ev_marks.size(); i++) {
-    if (p->ev_marks[i].first != stage) continue;
+    const int code = p->ev_marks[i].first;
+    if (!(code == stage || (stage <= 2 && code % 10 == stage))) continue;
     float t = 0.0f;
     HIPCHK(hipEventSynchronize(p->ev_pool[p->ev_marks[i].second.second]));
     HIPCHK(hipEventElapsedTime(&t, p->ev_pool[p->ev_marks[i].second.first],

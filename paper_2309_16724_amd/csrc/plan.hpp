@@ -170,7 +170,9 @@ struct Chunk {
   Tile *d_tile1 = nullptr, *d_tile2 = nullptr;
   Tile *d_tile1m = nullptr, *d_tile2m = nullptr;
   Reduce *d_red2 = nullptr;
-  double flops1 = 0.0, flops2 = 0.0;    // algorithmic flops of each launch
+  double flops1 = 0.0, flops2 = 0.0;    // algorithmic flops of each stage
+  double flops1m = 0.0, flops2m = 0.0;  // ... of its work-group tiles
+  double flops1w = 0.0, flops2w = 0.0;  // ... of its wavefront tiles
   int64_t part_elems = 0;               // partial-tile buffer needed
   // split precision (filled only for split plans)
   std::vector<SegS> sseg1, sseg2;
