@@ -300,13 +300,14 @@ def time_hpsi(torch, plan, x, y, steps, warmup):
     for _ in range(steps):
         plan.apply(x, y)
     torch.cuda.synchronize()
-    prof = {s_: plan.profile(s_) for s_ in (1, 2, 11, 12, 21, 22)}
+    prof = {s_: plan.profile(s_) for s_ in (1, 2, 11, 12, 21, 22, 31, 32)}
     plan.set_profiling(False)
     return ms, prof
 
 
 KERNEL_NAMES = {
     # profile code -> kernel (split s=5 plans, FP64 plans)
+    31: ("stage1_wsplit5_kernel", None), 32: ("stage2_wsplit5_kernel", None),
     11: ("stage1_msplit5_kernel", None), 12: ("stage2_msplit5_kernel", None),
     21: ("stage1_split5_kernel", "stage_f64_kernel<1>"), 22: ("stage2_split5_kernel", "stage_f64_kernel<2>"),
 }
@@ -314,7 +315,7 @@ KERNEL_NAMES = {
 
 def dominant(prof, split):
     """(kernel name, launches, ms, flops) of the tile kernel with the most time."""
-    code = max((c for c in (11, 12, 21, 22) if prof[c][0] > 0), key=lambda c: prof[c][1])
+    code = max((c for c in (11, 12, 21, 22, 31, 32) if prof[c][0] > 0), key=lambda c: prof[c][1])
     n, ms, fl = prof[code]
     return KERNEL_NAMES[code][0 if split else 1], n, ms, fl
 

@@ -104,8 +104,9 @@ enum { DMRG_FP64 = 0, DMRG_SPLIT_BF16 = 1 };
  *  DMRG_PLAN_AUTOTUNE: dmrg_build_tasks times dmrg_apply_H under candidate
  *    settings -- kpart in {1024, 2048, 4096} x tile_policy in {0, 1}, then
  *    for split plans the work-group tile threshold (macro_min) in
- *    {none, 32, 48, 96} at the best of those, then workspace caps of 512 MiB
- *    and 192 MiB -- and keeps the fastest; choices are cached by a hash of the
+ *    {none, 32, 48, 96} at the best of those and the wide tile threshold
+ *    (wide_min) in {none, 96, 192}, then workspace caps of 512 MiB and
+ *    192 MiB -- and keeps the fastest; choices are cached by a hash of the
  *    plan's block shapes and options, for the process and in opts.tune_cache.
  *    The chosen values are in dmrg_plan_stats.
  *  DMRG_PLAN_XCD: accepted for compatibility; every tile launch takes its
@@ -123,6 +124,11 @@ typedef struct {
   int32_t macro_min;        /* split plans: outputs with both sides >= this are
                                computed in 64x64 tiles by whole work groups
                                sharing LDS-staged operands (0: 48; < 0: never) */
+  int32_t wide_min;         /* split plans with n_slices <= 5: outputs with both
+                               sides >= this are cut into 128x128 tiles of one
+                               work group each (one per CU), the rest of them
+                               into the tiles above (0: 96; < 0: never)     */
+  int32_t pad_opts;
   /* Device memory of the plan (descriptors, operator copies, slices,
    * workspace), of the autotuner and of dmrg_davidson / dmrg_mlp_collect on
    * this plan comes from alloc_fn(bytes, alloc_ctx) and goes back through
@@ -164,7 +170,7 @@ typedef struct {
   double plan_ms;           /* stripe grouping, tile lists, device set-up (and
                                autotuning)                                  */
   int32_t macro_min;        /* work-group tile threshold in use (0: none)    */
-  int32_t pad2;
+  int32_t wide_min;         /* wide tile threshold in use (0: none)          */
   int64_t device_bytes;     /* device memory the plan holds                  */
 } dmrg_plan_stats_t;
 
@@ -333,14 +339,15 @@ int dmrg_mlp_collect(dmrg_plan_t *p, const double *psi0, const dmrg_dav_opts_t *
 void dmrg_mlp_free(dmrg_mlp_t *m);
 
 /* Profiling: when on, dmrg_apply_H records a hipEvent pair on its stream
- * around each tile launch of the first (1) and second (2) stage -- the
- * work-group tile launch of split plans and the wavefront tile launch, each
- * with the algorithmic flops of its tiles (slicing launches fall outside the
- * pairs).  dmrg_get_profile waits for the recorded events and returns the
- * number of launches, their summed duration and summed algorithmic flops
- * since the last dmrg_set_profiling call, for stage 1 or 2 (all its tile
- * launches), 11 or 12 (its work-group tile launches only) or 21 or 22 (its
- * wavefront tile launches only). */
+ * around each tile launch of the first (1) and second (2) stage -- the wide
+ * and the 64 x 64 work-group tile launches of split plans and the wavefront
+ * tile launch, each with the algorithmic flops of its tiles (slicing launches
+ * fall outside the pairs).  dmrg_get_profile waits for the recorded events
+ * and returns the number of launches, their summed duration and summed
+ * algorithmic flops since the last dmrg_set_profiling call, for stage 1 or 2
+ * (all its tile launches), 11 or 12 (its 64 x 64 work-group tile launches
+ * only), 21 or 22 (its wavefront tile launches only) or 31 or 32 (its wide
+ * tile launches only). */
 int dmrg_set_profiling(dmrg_plan_t *p, int32_t on);
 int dmrg_get_profile(dmrg_plan_t *p, int32_t stage, int64_t *n_launches, double *total_ms,
                      double *total_flops);
@@ -363,11 +370,14 @@ int dmrg_debug_host_apply(const dmrg_problem_t *prob, const double *psi, double 
  * addressing (psi or y NULL: only fill *st).  Never used by dmrg_apply_H. */
 int dmrg_debug_plan_host_apply(const dmrg_problem_t *prob, const double *psi, double *y,
                                const dmrg_plan_opts_t *opts, dmrg_plan_stats_t *st);
-/* Test-only: per-tile work of stage 1 or 2 of the default plan for one
- * problem (operator data not read): rows (tile rows, tile columns, segments,
- * summed K) written to out[4 * i ..] for i < cap; returns the number of tiles
- * (call with out = NULL to size) or a negative status. */
-int64_t dmrg_debug_plan_tiles(const dmrg_problem_t *prob, int32_t stage, int64_t *out, int64_t cap);
+/* Test-only: per-tile work of stage 1 or 2 of the plan that opts (NULL:
+ * defaults, FP64) give for one problem (operator data not read): rows (tile
+ * rows and columns inside the output, segments, summed K, rows and columns of
+ * the whole output block, tile kind: 1, 2, 4 wavefront, 8 work-group 64 x 64,
+ * 16 wide 128 x 128) written to out[7 * i ..] for i < cap; returns the number
+ * of tiles (call with out = NULL to size) or a negative status. */
+int64_t dmrg_debug_plan_tiles(const dmrg_problem_t *prob, const dmrg_plan_opts_t *opts, int32_t stage,
+                              int64_t *out, int64_t cap);
 /* Test-only: the host eigensolver dmrg_davidson applies to its projected
  * matrix (cyclic Jacobi).  A: m x m symmetric, row-major, HOST, 1 <= m <= 64;
  * w: m eigenvalues ascending; Z: m x m row-major, eigenvector j in column j.

@@ -41,7 +41,7 @@ class ProblemT(ctypes.Structure):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("precision", c_i32), ("n_slices", c_i32), ("workspace_bytes", c_i64),
                 ("flags", c_i32), ("kpart", c_i32), ("tile_policy", c_i32), ("macro_min", c_i32),
-                ("alloc_fn", c_vp), ("free_fn", c_vp), ("alloc_ctx", c_vp), ("tune_cache", ctypes.c_char_p)]
+                ("wide_min", c_i32), ("pad_opts", c_i32), ("alloc_fn", c_vp), ("free_fn", c_vp), ("alloc_ctx", c_vp), ("tune_cache", ctypes.c_char_p)]
 
 
 # device allocator callbacks of dmrg_plan_opts_t
@@ -81,7 +81,7 @@ class PlanStats(ctypes.Structure):
                 ("stage1_flops", c_dbl), ("stage2_flops", c_dbl), ("workspace_bytes", c_i64),
                 ("n_chunks", c_i32), ("kpart", c_i32), ("tile_policy", c_i32), ("xcd", c_i32),
                 ("tuned", c_i32), ("launches", c_i32), ("workspace_cap", c_i64), ("tune_ms", c_dbl),
-                ("tasks_ms", c_dbl), ("plan_ms", c_dbl), ("macro_min", c_i32), ("pad2", c_i32),
+                ("tasks_ms", c_dbl), ("plan_ms", c_dbl), ("macro_min", c_i32), ("wide_min", c_i32),
                 ("device_bytes", c_i64)]
 
     def as_dict(self):
@@ -130,6 +130,8 @@ def load(path=None):
                                        ctypes.POINTER(c_dbl)]
         L.dmrg_debug_plan_host_apply.argtypes = [ctypes.POINTER(ProblemT), c_vp, c_vp,
                                                  ctypes.POINTER(PlanOpts), ctypes.POINTER(PlanStats)]
+        L.dmrg_debug_plan_tiles.argtypes = [ctypes.POINTER(ProblemT), ctypes.POINTER(PlanOpts), c_i32, c_vp, c_i64]
+        L.dmrg_debug_plan_tiles.restype = c_i64
         c_f = ctypes.c_float
         L.dmrg_mlp_create.argtypes = [c_i32, ctypes.c_uint64, ctypes.POINTER(c_vp)]
         L.dmrg_mlp_num_params.argtypes = [c_vp]
@@ -182,7 +184,7 @@ class ProblemArgs:
 
 
 def debug_plan_host_apply(prob, psi, workspace_bytes=0, lib=None, precision=0, n_slices=0, kpart=0,
-                          tile_policy=0, macro_min=0):
+                          tile_policy=0, macro_min=0, wide_min=0):
     """Test-only: run the device plan's tile lists on the CPU (no GPU).
 
     ``psi=None`` only builds the plan and returns its statistics."""
@@ -191,7 +193,8 @@ def debug_plan_host_apply(prob, psi, workspace_bytes=0, lib=None, precision=0, n
     rd = np.ascontiguousarray(prob.right.data)
     args = ProblemArgs(prob, ld.ctypes.data, rd.ctypes.data)
     st = PlanStats()
-    opts = PlanOpts(precision, n_slices, workspace_bytes, 0, kpart, tile_policy, macro_min, None, None, None, None)
+    opts = PlanOpts(precision, n_slices, workspace_bytes, 0, kpart, tile_policy, macro_min, wide_min, 0,
+                    None, None, None, None)
     if psi is None:
         check(L.dmrg_debug_plan_host_apply(ctypes.byref(args.s), None, None, ctypes.byref(opts),
                                            ctypes.byref(st)), L)
@@ -201,6 +204,24 @@ def debug_plan_host_apply(prob, psi, workspace_bytes=0, lib=None, precision=0, n
     check(L.dmrg_debug_plan_host_apply(ctypes.byref(args.s), x.ctypes.data, y.ctypes.data,
                                        ctypes.byref(opts), ctypes.byref(st)), L)
     return y, st.as_dict()
+
+
+def debug_plan_tiles(prob, stage, lib=None, precision=0, n_slices=0, kpart=0, tile_policy=0, macro_min=0,
+                     wide_min=0):
+    """Test-only: the tiles of one stage of the plan for one problem, an
+    array of rows (rows, columns, segments, summed K, output rows, output
+    columns, kind) -- see dmrg_debug_plan_tiles."""
+    L = lib or load()
+    ld = np.ascontiguousarray(prob.left.data)
+    rd = np.ascontiguousarray(prob.right.data)
+    args = ProblemArgs(prob, ld.ctypes.data, rd.ctypes.data)
+    opts = PlanOpts(precision, n_slices, 0, 0, kpart, tile_policy, macro_min, wide_min, 0, None, None, None, None)
+    n = L.dmrg_debug_plan_tiles(ctypes.byref(args.s), ctypes.byref(opts), stage, None, 0)
+    if n < 0:
+        check(int(n), L)
+    out = np.zeros((max(n, 1), 7), dtype=np.int64)
+    L.dmrg_debug_plan_tiles(ctypes.byref(args.s), ctypes.byref(opts), stage, out.ctypes.data, n)
+    return out[:n]
 
 
 def debug_jacobi(A, lib=None, sweeps=False):

@@ -1,13 +1,16 @@
 // Split-precision (BF16 slices) kernels for the stripe products of H.psi.
 //
 // A product C = A B of FP64 operands is computed from fixed-point BF16 slices
-// (see SliceJob): C_ij = 2^(e_i + f_j) sum_{t+u <= s-1} 2^(-8(t+u+2)) sum_k a^t_ik b^u_kj.
-// The inner sums run on v_mfma_f32_16x16x32_bf16; products of slices are
-// integers of at most 16 bits, and sums grouped by d = t+u stay exact in FP32
-// for split_fold_k(s) terms, after which they are folded into FP64 with the
-// line scales.  FP64 remains for the fold, the scales and the identity
-// segments.  Lane layout of v_mfma_f32_16x16x32_bf16 (lane l, element e/r):
-// A[l%16][8(l/16)+e], B[8(l/16)+e][l%16], D[4(l/16)+r][l%16].
+// (see SliceJob): C_ij = 2^(e_i + f_j - 16) sum_{t+u <= s-1} sum_k a^t_ik b^u_kj
+// with slice t holding digit t at its weight 2^(-8t).  The inner sums run on
+// MFMA into FP32 sums per product group d = t + u (exact for the leading
+// groups, one rounded sum for the trailing ones, see slice_groups), and every
+// split_fold_k terms the sums are folded into FP64 with the line scales.
+// FP64 remains for the fold, the scales and the identity segments.
+// Lane layouts (lane l, element e/r):
+//   v_mfma_f32_16x16x32_bf16: A[l%16][8(l/16)+e], B[8(l/16)+e][l%16], D[4(l/16)+r][l%16];
+//   v_mfma_f32_32x32x16_bf16: A[l%32][8(l/32)+e], B[8(l/32)+e][l%32],
+//                             D[8(r/4)+4(l/32)+r%4][l%32].
 #include <hip/hip_runtime.h>
 #include <climits>
 #include "plan.hpp"
@@ -26,6 +29,13 @@ __device__ __forceinline__ const double *sbase_ptr(int id, const double *const *
 }
 
 // ------------------------------------------------------------------ slicing
+// 2^(-8t), the weight at which slice t stores its digit
+static_assert(SLICE_BITS == 8, "digit weights assume 8-bit slices");
+__device__ constexpr float digit_weight(int t) {
+  return t == 0 ? 1.0f : t == 1 ? 0x1p-8f : t == 2 ? 0x1p-16f : t == 3 ? 0x1p-24f : t == 4 ? 0x1p-32f
+                                                                                        : t == 5 ? 0x1p-40f : 0x1p-48f;
+}
+
 __global__ void __launch_bounds__(256) slice_kernel(const SliceJob *__restrict__ jobs, int njobs, int ns,
                                                      const double *const *__restrict__ bases,
                                                      const double *__restrict__ psi,
@@ -34,8 +44,6 @@ __global__ void __launch_bounds__(256) slice_kernel(const SliceJob *__restrict__
   for (int jb = blockIdx.x; jb < njobs; jb += gridDim.x) {
     const SliceJob J = jobs[jb];
     const double *src = sbase_ptr(J.src_base, bases, psi, nullptr, work, nullptr) + J.src_off;
-    uint16_t *dst = bufs.data[J.dst_buf] + J.dst_off;
-    const int64_t plane = bufs.plane[J.dst_buf];
     int32_t *exps = bufs.exps[J.dst_buf] + J.exp_off;
     // line lengths fit in 32 bits (checked when the plan is built): the
     // (position, offset) split of an index is a 32-bit division
@@ -68,14 +76,15 @@ __global__ void __launch_bounds__(256) slice_kernel(const SliceJob *__restrict__
         e = (mant == 0.5) ? ex - 1 : ex;      // smallest e with m <= 2^e
       }
       if (lane == 0) exps[rho] = e;
-      uint16_t *out = dst + (int64_t)rho * len;
+      // the line starts at a multiple of 8: its slices start at ns times that
+      uint16_t *out = bufs.data[J.dst_buf] + (J.dst_off + (int64_t)rho * len) * ns;
       auto slice_out = [&](int idx, double x) {
         double yv = ldexp(x, -e);
         for (int t = 0; t < ns; t++) {
           double a = rint(yv * 256.0);
           yv = yv * 256.0 - a;
-          float af = (float)a;                       // integer, |a| <= 256: exact in BF16
-          out[(int64_t)t * plane + idx] = (uint16_t)(__float_as_uint(af) >> 16);
+          const float af = (float)a * digit_weight(t);   // |a| <= 256 at weight 2^(-8t): exact in BF16
+          out[slice_index(idx, t, ns)] = (uint16_t)(__float_as_uint(af) >> 16);
         }
       };
       auto raw = [&](int idx) {
@@ -96,10 +105,10 @@ __global__ void __launch_bounds__(256) slice_kernel(const SliceJob *__restrict__
 }
 
 // stripe slices, one work group per chunk of TSLICE_CHUNK elements, four
-// consecutive elements per thread.  Line lengths, position blocks (kbp), plane
-// strides and job offsets are multiples of 8, so a group of four never
-// straddles a line or a position block and its slices are one aligned 8-byte
-// store per plane.
+// consecutive elements per thread.  Line lengths, position blocks (kbp) and
+// job offsets are multiples of 8, so a group of four never straddles a line,
+// a position block or a chunk of 8, and each of its slices is one aligned
+// 8-byte store.
 static_assert(TSLICE_CHUNK == 4 * 256, "one chunk is 256 threads x 4 elements");
 __global__ void __launch_bounds__(256) tslice_kernel(const SliceJob *__restrict__ jobs,
                                                       const TSliceItem *__restrict__ items, int nitems, int ns,
@@ -108,8 +117,7 @@ __global__ void __launch_bounds__(256) tslice_kernel(const SliceJob *__restrict_
     const TSliceItem I = items[it];
     const SliceJob J = jobs[I.job];
     const double *src = work + J.src_off;
-    uint16_t *dst = bufs.data[SBUF_T] + J.dst_off;
-    const int64_t plane = bufs.plane[SBUF_T];
+    uint16_t *dst = bufs.data[SBUF_T];
     const int32_t *exps = bufs.exps[SBUF_T] + J.exp_off;
     const unsigned kb = (unsigned)J.kb, kbp = (unsigned)J.kbp, len = (unsigned)(J.npos * J.kbp);
     const unsigned tot = len * (unsigned)J.nrho;
@@ -130,10 +138,10 @@ __global__ void __launch_bounds__(256) tslice_kernel(const SliceJob *__restrict_
       for (int i = 0; i < 4; i++) {
         const double a = rint(yv[i] * 256.0);
         yv[i] = yv[i] * 256.0 - a;
-        const float af = (float)a;                 // integer, |a| <= 256: exact in BF16
+        const float af = (float)a * digit_weight(t);   // exact in BF16 (see slice_kernel)
         packed |= (uint64_t)(__float_as_uint(af) >> 16) << (16 * i);
       }
-      *(uint64_t *)(dst + (int64_t)t * plane + e) = packed;
+      *(uint64_t *)(dst + slice_index(J.dst_off + e, t, ns)) = packed;
     }
   }
 }
@@ -164,6 +172,9 @@ void launch_slices(const SliceJob *jobs, int njobs, int nslices, const double *c
 }
 
 // ------------------------------------------------------------------ split products
+// descriptor arrays read through the constant address space (scalar loads)
+typedef const SegS __attribute__((address_space(4))) CSegS;
+typedef const Seg __attribute__((address_space(4))) CSeg;
 // slice buffers live in device global memory: global (not flat) loads
 typedef const void __attribute__((address_space(1))) *gvptr;
 typedef void __attribute__((address_space(3))) *lvptr;
@@ -174,11 +185,17 @@ constexpr int WAIT_VM0 = 0x0F70, WAIT_LGKM0 = 0xC07F;
 // LDS stage of one wavefront: (MB + NB) * NS chunks of 64 lanes x 16 bytes
 constexpr int stage_bytes(int ns) { return 5 * ns * 1024; }
 
-// 2^(-8(d+2)), the weight of slice-product group d
+// FP32 sum of slice-product group d for s = NS (see slice_groups)
+template <int NS>
+__device__ constexpr int sgroup(int d) { return d < slice_groups(NS) - 1 ? d : slice_groups(NS) - 1; }
 static_assert(SLICE_BITS == 8, "fold weights assume 8-bit slices");
-__device__ constexpr double fold_scale(int d) {
-  return d == 0 ? 0x1p-16 : d == 1 ? 0x1p-24 : d == 2 ? 0x1p-32 : d == 3 ? 0x1p-40 : d == 4 ? 0x1p-48
-                                                                                             : d == 5 ? 0x1p-56 : 0x1p-64;
+
+// fold of the group sums of one element: their FP64 sum (group 0 first)
+template <int G, typename V>
+__device__ __forceinline__ double fold_groups(const V *q, int r) {
+  double x = (double)q[0][r];
+  for (int g = 1; g < G; g++) x += (double)q[g][r];
+  return x;
 }
 
 template <int MB, int NS>
@@ -215,9 +232,10 @@ __device__ __forceinline__ void item_split(const Tile &T, const Seg *__restrict_
         }
       continue;
     }
-    const uint16_t *A = bufs.data[Q.a_buf] + Q.a_off;
-    const uint16_t *B = bufs.data[Q.b_buf] + Q.b_off;
-    const int64_t pa = bufs.plane[Q.a_buf], pb = bufs.plane[Q.b_buf];
+    // segment offsets and line lengths are multiples of 8: a segment's slices
+    // start at NS times its offset, a line's at NS times its start
+    const uint16_t *A = bufs.data[Q.a_buf] + Q.a_off * NS;
+    const uint16_t *B = bufs.data[Q.b_buf] + Q.b_off * NS;
     const int32_t *ea = bufs.exps[Q.a_buf] + Q.a_exp;
     const int32_t *eb = bufs.exps[Q.b_buf] + Q.b_exp;
     // lanes past the last row / column read the last one: their outputs are
@@ -225,17 +243,19 @@ __device__ __forceinline__ void item_split(const Tile &T, const Seg *__restrict_
     // wave-uniform slice base plus a 32-bit lane offset within the segment's
     // lines (checked when the plan is built).
     uint32_t arow[MB], bcol[NB];   // byte offsets
-    for (int bi = 0; bi < MB; bi++) arow[bi] = (uint32_t)(T.i0 + min(16 * bi + r16, mrem - 1)) * (uint32_t)Q.a_ld * 2u;
-    for (int bj = 0; bj < NB; bj++) bcol[bj] = (uint32_t)(T.j0 + min(16 * bj + r16, nrem - 1)) * (uint32_t)Q.b_ld * 2u;
+    for (int bi = 0; bi < MB; bi++)
+      arow[bi] = (uint32_t)(T.i0 + min(16 * bi + r16, mrem - 1)) * (uint32_t)Q.a_ld * (2u * NS);
+    for (int bj = 0; bj < NB; bj++)
+      bcol[bj] = (uint32_t)(T.j0 + min(16 * bj + r16, nrem - 1)) * (uint32_t)Q.b_ld * (2u * NS);
     // scale exponents of this lane's output elements
     int erow[MB][4], fcol[NB];
     for (int bi = 0; bi < MB; bi++)
       for (int r = 0; r < 4; r++) erow[bi][r] = ea[T.i0 + min(16 * bi + 4 * q4 + r, mrem - 1)];
     for (int bj = 0; bj < NB; bj++) fcol[bj] = eb[T.j0 + min(16 * bj + r16, nrem - 1)];
-    v4f q[MB][NB][NS];
+    v4f q[MB][NB][slice_groups(NS)];
     for (int bi = 0; bi < MB; bi++)
       for (int bj = 0; bj < NB; bj++)
-        for (int d = 0; d < NS; d++) q[bi][bj][d] = (v4f){0.f, 0.f, 0.f, 0.f};
+        for (int g = 0; g < slice_groups(NS); g++) q[bi][bj][g] = (v4f){0.f, 0.f, 0.f, 0.f};
     // K is a multiple of 8 and the lines are zero-padded to it, so the chunk
     // of 8 at min(k, K - 8) is always inside the operand; a lane whose chunk
     // starts at or past K multiplies a zeroed A operand.  The operands of a
@@ -244,9 +264,9 @@ __device__ __forceinline__ void item_split(const Tile &T, const Seg *__restrict_
     // loads of the next step fly while the MFMAs of this one run without
     // holding a second set of registers.
     auto dma = [&](int k0) {
-      const uint32_t kl = 2u * (uint32_t)min(k0 + 8 * q4, Q.K - 8);
+      const uint32_t kl = (2u * NS) * (uint32_t)min(k0 + 8 * q4, Q.K - 8);
       for (int t = 0; t < NS; t++) {
-        const char *at = (const char *)(A + (int64_t)t * pa), *bt = (const char *)(B + (int64_t)t * pb);
+        const char *at = (const char *)A + 16 * t, *bt = (const char *)B + 16 * t;
         for (int bi = 0; bi < MB; bi++)
           __builtin_amdgcn_global_load_lds((gvptr)(at + (arow[bi] + kl)), (lvptr)(stage + (bi * NS + t) * 1024), 16, 0, 0);
         for (int bj = 0; bj < NB; bj++)
@@ -271,19 +291,19 @@ __device__ __forceinline__ void item_split(const Tile &T, const Seg *__restrict_
         for (int t = 0; t <= d; t++)
           for (int bi = 0; bi < MB; bi++)
             for (int bj = 0; bj < NB; bj++)
-              q[bi][bj][d] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as[bi][t], bs[bj][d - t], q[bi][bj][d], 0, 0, 0);
+              q[bi][bj][sgroup<NS>(d)] =
+                  __builtin_amdgcn_mfma_f32_16x16x32_bf16(as[bi][t], bs[bj][d - t], q[bi][bj][sgroup<NS>(d)], 0, 0, 0);
     };
     auto fold = [&]() {
       for (int bi = 0; bi < MB; bi++)
         for (int bj = 0; bj < NB; bj++)
           for (int r = 0; r < 4; r++) {
-            double x = 0.0;   // q * 2^(-8(d+2)) is exact: the FMA rounds the sum only
-            for (int d = 0; d < NS; d++) x = fma((double)q[bi][bj][d][r], fold_scale(d), x);
-            acc[bi][bj][r] += S.s * ldexp(x, erow[bi][r] + fcol[bj]);
+            const double x = fold_groups<slice_groups(NS)>(q[bi][bj], r);
+            acc[bi][bj][r] += S.s * ldexp(x, erow[bi][r] + fcol[bj] - 2 * SLICE_BITS);
           }
       for (int bi = 0; bi < MB; bi++)
         for (int bj = 0; bj < NB; bj++)
-          for (int d = 0; d < NS; d++) q[bi][bj][d] = (v4f){0.f, 0.f, 0.f, 0.f};
+          for (int g = 0; g < slice_groups(NS); g++) q[bi][bj][g] = (v4f){0.f, 0.f, 0.f, 0.f};
     };
     constexpr int FOLD = split_fold_k(NS);
     static_assert(FOLD % 32 == 0, "the K loop folds after whole 32-wide steps");
@@ -436,22 +456,21 @@ __device__ __forceinline__ void macro_split(const Tile &T, const Seg *__restrict
     // lines are zero-padded to it: the chunk of 8 at min(k, K - 8) is inside
     // the operand; lanes whose chunk starts at or past K are zeroed at the MFMA)
     auto issue = [&](const SegS &Q, int k0, int b) {
-      const char *A = (const char *)(bufs.data[Q.a_buf] + Q.a_off);
-      const char *B = (const char *)(bufs.data[Q.b_buf] + Q.b_off);
-      const int64_t pa = 2 * bufs.plane[Q.a_buf], pb = 2 * bufs.plane[Q.b_buf];
-      const uint32_t kl = 2u * (uint32_t)min(k0 + 8 * q4, Q.K - 8);
-      const uint32_t ao = lrow * (uint32_t)Q.a_ld * 2u + kl, bo = lcol * (uint32_t)Q.b_ld * 2u + kl;
+      const char *A = (const char *)(bufs.data[Q.a_buf] + Q.a_off * NS);   // slices interleaved (see item_split)
+      const char *B = (const char *)(bufs.data[Q.b_buf] + Q.b_off * NS);
+      const uint32_t kl = (2u * NS) * (uint32_t)min(k0 + 8 * q4, Q.K - 8);
+      const uint32_t ao = lrow * (uint32_t)Q.a_ld * (2u * NS) + kl, bo = lcol * (uint32_t)Q.b_ld * (2u * NS) + kl;
       char *st = lds + b * STAGE;
       for (int t = 0; t < NS; t++) {
-        __builtin_amdgcn_global_load_lds((gvptr)(A + t * pa + ao), (lvptr)(st + (wave * NS + t) * 1024), 16, 0, 0);
-        __builtin_amdgcn_global_load_lds((gvptr)(B + t * pb + bo), (lvptr)(st + ((4 + wave) * NS + t) * 1024), 16,
+        __builtin_amdgcn_global_load_lds((gvptr)(A + 16 * t + ao), (lvptr)(st + (wave * NS + t) * 1024), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((gvptr)(B + 16 * t + bo), (lvptr)(st + ((4 + wave) * NS + t) * 1024), 16,
                                          0, 0);
       }
     };
-    v4f q[MB][NB][NS];
+    v4f q[MB][NB][slice_groups(NS)];
     for (int bi = 0; bi < MB; bi++)
       for (int bj = 0; bj < NB; bj++)
-        for (int d = 0; d < NS; d++) q[bi][bj][d] = (v4f){0.f, 0.f, 0.f, 0.f};
+        for (int g = 0; g < slice_groups(NS); g++) q[bi][bj][g] = (v4f){0.f, 0.f, 0.f, 0.f};
     SegS Q = ssegs[T.seg0 + si];
     double sc = segs[T.seg0 + si].s;
     int erow[MB][4], fcol[NB];
@@ -502,18 +521,18 @@ __device__ __forceinline__ void macro_split(const Tile &T, const Seg *__restrict
         for (int t = 0; t <= d; t++)
           for (int bi = 0; bi < MB; bi++)
             for (int bj = 0; bj < NB; bj++)
-              q[bi][bj][d] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as[bi][t], bs[bj][d - t], q[bi][bj][d], 0, 0, 0);
+              q[bi][bj][sgroup<NS>(d)] =
+                  __builtin_amdgcn_mfma_f32_16x16x32_bf16(as[bi][t], bs[bj][d - t], q[bi][bj][sgroup<NS>(d)], 0, 0, 0);
       if (newseg || (k0 + 32) % FOLD == 0) {
         for (int bi = 0; bi < MB; bi++)
           for (int bj = 0; bj < NB; bj++)
             for (int r = 0; r < 4; r++) {
-              double x = 0.0;   // q * 2^(-8(d+2)) is exact: the FMA rounds the sum only
-              for (int d = 0; d < NS; d++) x = fma((double)q[bi][bj][d][r], fold_scale(d), x);
-              acc[bi][bj][r] += sc * ldexp(x, erow[bi][r] + fcol[bj]);
+              const double x = fold_groups<slice_groups(NS)>(q[bi][bj], r);
+              acc[bi][bj][r] += sc * ldexp(x, erow[bi][r] + fcol[bj] - 2 * SLICE_BITS);
             }
         for (int bi = 0; bi < MB; bi++)
           for (int bj = 0; bj < NB; bj++)
-            for (int d = 0; d < NS; d++) q[bi][bj][d] = (v4f){0.f, 0.f, 0.f, 0.f};
+            for (int g = 0; g < slice_groups(NS); g++) q[bi][bj][g] = (v4f){0.f, 0.f, 0.f, 0.f};
       }
       if (!more) break;
       if (newseg) {
@@ -616,6 +635,274 @@ MACRO_KERNELS(5)
 MACRO_KERNELS(6)
 MACRO_KERNELS(7)
 
+// ------------------------------------------------------------ wide work-group tiles
+// A 128 x 128 output tile (WIDE_MB) computed by the eight wavefronts of a
+// work group, two per SIMD: wave w owns rows 32 (w >> 1) .. + 32 and columns
+// 64 (w & 1) .. + 64 as two blocks of v_mfma_f32_32x32x16_bf16.  The MFMA
+// takes the B lines (output columns) as its first operand and the A lines
+// (output rows) as its second, so lane l holds output row l % 32 of a block
+// and its columns wcol(r) = 8 (r / 4) + 4 (l / 32) + r % 4: the column-major
+// stores of 32 lanes are contiguous 256-byte runs.  Each 32-wide K step of
+// the operands (A: 4 row blocks of 32 lines, B: 4 column blocks, two K halves
+// of 16, NS slices; 1 KiB per block, half and slice) goes from global memory
+// through registers into one of two LDS stages -- wave w loads row block
+// w % 4 and column block w % 4 of K half w / 4 -- while the step before runs
+// on the other stage.  The stages are two separate LDS objects, so the
+// compiler knows that the stores into one never alias the reads of the other.
+constexpr int wstage_bytes(int ns) { return 16 * ns * 1024; }
+__device__ __forceinline__ int wcol(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
+
+template <int NS>
+__device__ __forceinline__ void wide_split(const Tile &T, const Seg *__restrict__ segs,
+                                           const SegS *__restrict__ ssegs, const double *const *bases,
+                                           const double *psi, double *y, double *work, double *part,
+                                           const SliceBufs &bufs, char *lds0, char *lds1, int wave, int lane) {
+  constexpr int FOLD = split_fold_k(NS);
+  static_assert(FOLD % 32 == 0, "the K loop folds after whole 32-wide steps");
+  typedef float v16f __attribute__((ext_vector_type(16)));
+  // the tile and segment descriptors do not change during the launch: read
+  // through the constant address space they are scalar loads (scalar cache,
+  // no vector memory wait on the K loop's path)
+  const CSegS *cs = (const CSegS *)ssegs;
+  const CSeg *cg = (const CSeg *)segs;
+  // the lane index passes through an empty asm per tile: the per-lane column
+  // offsets derived from it are recomputed per tile instead of being hoisted
+  // out of the tile loop into registers that the K loop needs
+  asm volatile("" : "+v"(lane));
+  const int c32 = lane & 31, h = lane >> 5;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int i0 = T.i0 + 32 * wr, j0 = T.j0 + 64 * wc;    // this wave's part
+  const int mrem = T.m - i0, nrem = T.n - j0;             // <= 0: part outside the output
+  // operand lines this lane loads: row block / column block wave % 4, K half
+  // wave / 4 (see issue)
+  const int lb = wave & 3, lkh = wave >> 2;
+  double acc[2][16];
+  for (int bj = 0; bj < 2; bj++)
+    for (int r = 0; r < 16; r++) acc[bj][r] = 0.0;
+  // identity left operators: exact FP64 additions of the FP64 operand
+  for (int si = 0; si < T.nseg; si++) {
+    if (cs[T.seg0 + si].K != 0) continue;
+    CSeg &S = cg[T.seg0 + si];
+    const double *B = sbase_ptr(S.b_base, bases, psi, y, work, part) + S.b_off;
+    if (c32 >= mrem) continue;
+    const int k = i0 + c32;
+    const int pk = k / S.b_kb;
+    const int64_t ko = (int64_t)pk * S.b_pk + (int64_t)(k - pk * S.b_kb) * S.b_k;
+    for (int bj = 0; bj < 2; bj++)
+      for (int r = 0; r < 16; r++) {
+        const int j = 32 * bj + wcol(r, h);
+        if (j < nrem) {
+          const int n = j0 + j;
+          const int pn = n / S.b_nb;
+          acc[bj][r] += S.s * B[ko + (int64_t)pn * S.b_pn + (int64_t)(n - pn * S.b_nb) * S.b_n];
+        }
+      }
+  }
+  int si = 0;
+  while (si < T.nseg && cs[T.seg0 + si].K == 0) si++;
+  // every wave has finished reading the LDS stages of its previous tile
+  __syncthreads();
+  if (si < T.nseg) {
+    // one operand's NS chunks of a K step of segment qi at k0 (operand 0: the A
+    // lines of row block wave % 4, 1: the B lines of column block wave % 4; K
+    // half wave / 4) into registers.  K is a multiple of 8 and lines are
+    // zero-padded to it: the chunk of 8 at min(k, K - 8) is inside the operand;
+    // lanes whose chunk starts at or past K are zeroed at the MFMA.  Plain
+    // vector loads: under load they complete about 2.5 times sooner than
+    // loads straight into LDS.
+    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+    auto load = [&](int qi, int k0, int op, v4u *pre) {
+      CSegS &Q = cs[T.seg0 + qi];
+      const int buf = op ? Q.b_buf : Q.a_buf;
+      const char *X = (const char *)(bufs.data[buf] + (op ? Q.b_off : Q.a_off) * NS);   // see item_split
+      // the lane index is recomputed here (volatile: not kept in a register
+      // across the K loop); lines past the output read the last one (never stored)
+      int ln;
+      asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(ln));
+      const uint32_t line = (uint32_t)(op ? min(T.j0 + 32 * lb + (ln & 31), T.n - 1)
+                                          : min(T.i0 + 32 * lb + (ln & 31), T.m - 1));
+      const uint32_t kl = (2u * NS) * (uint32_t)min(k0 + 16 * lkh + 8 * (ln >> 5), Q.K - 8);
+      const uint32_t xo = line * (uint32_t)(op ? Q.b_ld : Q.a_ld) * (2u * NS) + kl;
+      for (int t = 0; t < NS; t++) pre[t] = *(const v4u *)(X + xo + 16 * t);
+    };
+    // ... and from registers into LDS stage st, in the MFMA operand layout
+    auto store = [&](int op, const v4u *pre, char *st) {
+      int ln;
+      asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(ln));
+      for (int t = 0; t < NS; t++)
+        *(v4u *)(st + (8 * NS * op + (2 * lb + lkh) * NS + t) * 1024 + 16 * ln) = pre[t];
+    };
+    v16f q[2][slice_groups(NS)];
+    for (int bj = 0; bj < 2; bj++)
+      for (int g = 0; g < slice_groups(NS); g++) q[bj][g] = (v16f){};
+    // one K half kh of this step's products from stage st: the row block's A
+    // slices, then per column block its B slices one at a time (slice u
+    // meets A slices t <= NS - 1 - u), the next one read while the MFMAs of
+    // the current one run; so only five A and two B operands are in registers
+    auto compute = [&](const char *st, int k0, int K, int kh) {
+      v8bf a[NS];
+      for (int t = 0; t < NS; t++) a[t] = *(const lv8ptr)(st + ((2 * wr + kh) * NS + t) * 1024 + 16 * lane);
+      if (k0 + 32 > K && k0 + 16 * kh + 8 * h >= K)   // only a segment's last step has such lanes
+        for (int t = 0; t < NS; t++) a[t] = (v8bf){};
+      for (int bj = 0; bj < 2; bj++) {
+        const char *bs = st + (8 * NS + (2 * (2 * wc + bj) + kh) * NS) * 1024 + 16 * lane;
+        v8bf b = *(const lv8ptr)bs;
+#pragma unroll
+        for (int u = 0; u < NS; u++) {
+          const v8bf bn = u + 1 < NS ? *(const lv8ptr)(bs + (u + 1) * 1024) : b;
+#pragma unroll
+          for (int t = 0; t + u < NS; t++)
+            q[bj][sgroup<NS>(t + u)] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b, a[t], q[bj][sgroup<NS>(t + u)], 0, 0, 0);
+          b = bn;
+        }
+      }
+    };
+    // segment descriptors are read where needed (wave-uniform, scalar loads)
+    // rather than copied, so that they never sit in scratch memory
+    // fold into FP64 with the scale exponents of this lane's row and its 32
+    // columns, read here (the exponent arrays hold WIDE_EDGE spare entries, so
+    // the lines past the output read in bounds; their outputs are never
+    // stored).  Exponents are in [-1100, 1100] or the all-zero sentinel, which
+    // only meets zero sums: int16 keeps every sum of two in range.
+    auto fold = [&]() {
+      CSegS &Q = cs[T.seg0 + si];
+      const double sc = cg[T.seg0 + si].s;
+      const int32_t *ea = bufs.exps[Q.a_buf] + Q.a_exp + (i0 + c32);
+      const int32_t *eb = bufs.exps[Q.b_buf] + Q.b_exp + (j0 + 4 * h);
+      const int er = (int16_t)ea[0];
+      for (int bj = 0; bj < 2; bj++)
+        for (int r = 0; r < 16; r++) {
+          const int f = (int16_t)eb[32 * bj + 8 * (r >> 2) + (r & 3)];
+          const double x = fold_groups<slice_groups(NS)>(q[bj], r);
+          acc[bj][r] += sc * ldexp(x, er + f - 2 * SLICE_BITS);
+        }
+      for (int bj = 0; bj < 2; bj++)
+        for (int g = 0; g < slice_groups(NS); g++) q[bj][g] = (v16f){};
+    };
+    {
+      v4u pre[NS];
+      load(si, 0, 0, pre);
+      store(0, pre, lds0);
+      load(si, 0, 1, pre);
+      store(1, pre, lds0);
+    }
+    int k0 = 0;
+    // one step on stage cur; the next one (across segment boundaries) goes
+    // through registers into nxt, its loads in flight during the whole step.
+    // Returns false after the tile's last step.
+    auto step = [&](const char *cur, char *nxt) -> bool {
+      __syncthreads();   // every wave's chunks of this step are in cur; nxt is free
+      const int K = cs[T.seg0 + si].K;
+      int nsi = si, nk0 = k0 + 32;
+      const bool newseg = nk0 >= K;
+      if (newseg) {
+        nk0 = 0;
+        nsi++;
+        while (nsi < T.nseg && cs[T.seg0 + nsi].K == 0) nsi++;
+      }
+      const bool more = nsi < T.nseg;
+      v4u pa[NS], pb[NS];
+      if (more) {
+        load(nsi, nk0, 0, pa);
+        load(nsi, nk0, 1, pb);
+      }
+      compute(cur, k0, K, 0);
+      compute(cur, k0, K, 1);
+      __builtin_amdgcn_sched_barrier(0);
+      if (more) {
+        store(0, pa, nxt);
+        store(1, pb, nxt);
+      }
+      if (newseg || (k0 + 32) % FOLD == 0) fold();
+      si = nsi;
+      k0 = nk0;
+      return more;
+    };
+    while (step(lds0, lds1) && step(lds1, lds0)) {
+    }
+  }
+  double *C = const_cast<double *>(sbase_ptr(T.c_base, bases, psi, y, work, part)) + T.c_off;
+  const int ci0 = T.ci0 + 32 * wr, cj0 = T.cj0 + 64 * wc;
+  for (int bj = 0; bj < 2; bj++)
+    for (int r = 0; r < 16; r++) {
+      const int i = c32, j = 32 * bj + wcol(r, h);
+      if (i < mrem && j < nrem) {
+        double *c = T.rowmajor ? C + (int64_t)(ci0 + i) * T.ldc + (cj0 + j)
+                               : C + (int64_t)(ci0 + i) + (int64_t)(cj0 + j) * T.ldc;
+        *c = T.accumulate ? *c + acc[bj][r] : acc[bj][r];
+      }
+    }
+  // first-stage tiles: exponent of every stripe column written (see
+  // item_split), the maximum of the elements' exponents over the rows
+  CSegS &Q0 = cs[T.seg0];
+  if (Q0.t_exp >= 0) {
+    int32_t *ex = bufs.exps[SBUF_T] + Q0.t_exp;
+    for (int bj = 0; bj < 2; bj++)
+      for (int r = 0; r < 16; r++) {
+        const int j = 32 * bj + wcol(r, h);
+        const double m = fabs(acc[bj][r]);
+        int e = INT_MIN;
+        if (c32 < mrem && j < nrem && m > 0.0) {
+          int e2;
+          const double mant = frexp(m, &e2);
+          e = mant == 0.5 ? e2 - 1 : e2;
+        }
+        for (int off = 16; off > 0; off >>= 1) e = max(e, __shfl_xor(e, off));
+        if (c32 == 0 && j < nrem && e != INT_MIN) atomicMax(ex + (cj0 + j) % Q0.t_nb, e);
+      }
+  }
+}
+
+template <int NS>
+__device__ __forceinline__ void wide_items(const Tile *__restrict__ tiles, const Seg *__restrict__ segs,
+                                           const SegS *__restrict__ ssegs, const XcdQueues &q,
+                                           int32_t *__restrict__ counters,
+                                           const double *const *__restrict__ bases, const double *__restrict__ psi,
+                                           double *__restrict__ y, double *__restrict__ work,
+                                           double *__restrict__ part, const SliceBufs &bufs) {
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // the two operand stages fill the LDS (one work group of eight wavefronts
+  // per CU); the tile index reaches the wavefronts through the work group's
+  // mailbox as in macro_items
+  __shared__ __attribute__((aligned(1024))) char lds0[wstage_bytes(NS)];
+  __shared__ __attribute__((aligned(1024))) char lds1[wstage_bytes(NS)];
+  int32_t *mailbox = counters + NXCD + blockIdx.x;
+  const int x = xcc_id();
+  int qi = 0;
+  for (;;) {
+    if (threadIdx.x == 0) atomicExch(mailbox, queue_next(q, counters, x, qi));
+    __syncthreads();
+    int v = 0;
+    if (lane == 0) v = atomicAdd(mailbox, 0);
+    const int t = __builtin_amdgcn_readfirstlane(v);
+    if (t < 0) break;
+    const Tile T = tiles[t];
+    wide_split<NS>(T, segs, ssegs, bases, psi, y, work, part, bufs, lds0, lds1, wave, lane);
+  }
+}
+
+#define WIDE_KERNELS(NS)                                                                                    \
+  __global__ void __launch_bounds__(64 * WIDE_WAVES) __attribute__((amdgpu_waves_per_eu(2, 2)))           \
+  stage1_wsplit##NS##_kernel(const Tile *__restrict__ tiles, const Seg *__restrict__ segs,                  \
+                             const SegS *__restrict__ ssegs, XcdQueues q, int32_t *__restrict__ counters,   \
+                             const double *const *__restrict__ bases, const double *__restrict__ psi,       \
+                             double *__restrict__ y, double *__restrict__ work, double *__restrict__ part,   \
+                             SliceBufs bufs) {                                                              \
+    wide_items<NS>(tiles, segs, ssegs, q, counters, bases, psi, y, work, part, bufs);                       \
+  }                                                                                                         \
+  __global__ void __launch_bounds__(64 * WIDE_WAVES) __attribute__((amdgpu_waves_per_eu(2, 2)))           \
+  stage2_wsplit##NS##_kernel(const Tile *__restrict__ tiles, const Seg *__restrict__ segs,                  \
+                             const SegS *__restrict__ ssegs, XcdQueues q, int32_t *__restrict__ counters,   \
+                             const double *const *__restrict__ bases, const double *__restrict__ psi,       \
+                             double *__restrict__ y, double *__restrict__ work, double *__restrict__ part,   \
+                             SliceBufs bufs) {                                                              \
+    wide_items<NS>(tiles, segs, ssegs, q, counters, bases, psi, y, work, part, bufs);                       \
+  }
+
+WIDE_KERNELS(3)
+WIDE_KERNELS(4)
+WIDE_KERNELS(5)
+
 #define SPLIT_KERNELS(NS)                                                                                   \
   __global__ void __launch_bounds__(64 * WAVES) stage1_split##NS##_kernel(                                  \
       const Tile *__restrict__ tiles, const Seg *__restrict__ segs, const SegS *__restrict__ ssegs,         \
@@ -663,6 +950,30 @@ void launch_macro_split(int stage, const Tile *tiles, const Seg *segs, const Seg
   MLAUNCH(6)
   MLAUNCH(7)
 #undef MLAUNCH
+}
+
+void launch_wide_split(int stage, const Tile *tiles, const Seg *segs, const SegS *ssegs, int ntiles,
+                       const XcdQueues &q, int32_t *counters, int nslices, const double *const *bases,
+                       const double *psi, double *y, double *work, double *part, SliceBufs bufs, void *stream) {
+  if (ntiles <= 0) return;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, s, counters, (int64_t)NXCD, 0);
+  // one work group per CU (the two stages take all 160 KiB of LDS at s = 5)
+  const int grid = std::max(8, std::min((ntiles + 7) / 8 * 8, WIDE_GRID));
+#define WLAUNCH(NS)                                                                                         \
+  if (nslices == NS) {                                                                                      \
+    if (stage == 1)                                                                                         \
+      hipLaunchKernelGGL(stage1_wsplit##NS##_kernel, dim3(grid), dim3(64 * WIDE_WAVES), 0, s, tiles, segs,  \
+                         ssegs, q, counters, bases, psi, y, work, part, bufs);                              \
+    else                                                                                                    \
+      hipLaunchKernelGGL(stage2_wsplit##NS##_kernel, dim3(grid), dim3(64 * WIDE_WAVES), 0, s, tiles, segs,  \
+                         ssegs, q, counters, bases, psi, y, work, part, bufs);                              \
+    return;                                                                                                 \
+  }
+  WLAUNCH(3)
+  WLAUNCH(4)
+  WLAUNCH(5)
+#undef WLAUNCH
 }
 
 void launch_tiles_split(int stage, const Tile *tiles, const Seg *segs, const SegS *ssegs, int ntiles,

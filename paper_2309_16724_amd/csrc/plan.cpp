@@ -114,6 +114,7 @@ struct dmrg_plan {
   // settings of the tile lists
   int kpart = KPART, tile_policy = 0, xcd = 0, flags = 0;
   int macro_min = MACRO_MIN;          // split plans: work-group tiles for outputs >= this (0: none)
+  int wide_min = WIDE_MIN;            // split plans, s <= 5: wide tiles for outputs >= this (0: none)
   int64_t budget = DEFAULT_WORKSPACE;
   int tuned = 0;
   double tune_ms = 0.0;
@@ -259,6 +260,40 @@ bool use_macro(const dmrg_plan *P, int m, int n) {
   return P->precision == DMRG_SPLIT_BF16 && P->macro_min > 0 && m >= P->macro_min && n >= P->macro_min;
 }
 
+bool use_wide(const dmrg_plan *P, int m, int n) {
+  return P->precision == DMRG_SPLIT_BF16 && P->n_slices <= WIDE_MAX_SLICES && P->wide_min > 0 &&
+         m >= P->wide_min && n >= P->wide_min;
+}
+
+// Tiles of an m x n output (top-left corner and kind mb).  Outputs that take
+// wide tiles are cut into 128-wide row and column bands (a last band of at
+// least WIDE_TAIL lines is wide too): the wide x wide cells in patch order,
+// then the rest of the output -- the columns beyond the wide bands next to
+// them, then the rows below -- in tiles chosen for those strips.  Other
+// outputs get one kind of tile in patch order.
+struct Cell { int i0, j0, mb; };
+std::vector<Cell> output_cells(const dmrg_plan *P, int m, int n) {
+  std::vector<Cell> v;
+  auto grid = [&](int r0, int c0, int rows, int cols) {
+    if (rows <= 0 || cols <= 0) return;
+    const int mb = use_macro(P, rows, cols) ? MACRO_MB : tile_mb(rows, cols, P->tile_policy);
+    const int tr = tile_rows(mb), tc = tile_cols(mb);
+    for (const auto &c : patch_order((rows + tr - 1) / tr, (cols + tc - 1) / tc))
+      v.push_back({r0 + c.first * tr, c0 + c.second * tc, mb});
+  };
+  if (!use_wide(P, m, n)) {
+    grid(0, 0, m, n);
+    return v;
+  }
+  auto bands = [](int len) { return len / WIDE_EDGE + (len % WIDE_EDGE >= WIDE_TAIL ? 1 : 0); };
+  const int nr = bands(m), nc = bands(n);
+  const int mw = std::min(m, nr * WIDE_EDGE), nw = std::min(n, nc * WIDE_EDGE);
+  for (const auto &c : patch_order(nr, nc)) v.push_back({c.first * WIDE_EDGE, c.second * WIDE_EDGE, WIDE_MB});
+  grid(0, nw, mw, n - nw);
+  grid(mw, 0, m - mw, n);
+  return v;
+}
+
 int prepare_device(dmrg_plan *P);
 int autotune(dmrg_plan *P, void *stream);
 int replan(dmrg_plan *P);
@@ -314,7 +349,7 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
       for (const auto &pa : T.rows[tk.row].pos) s.slots.push_back(pa.pD);
     }
     int64_t woff = 0;
-    std::vector<double> cost1, cost1m;   // K of every stage-1 tile
+    std::vector<double> cost1, cost1m, cost1x;   // K of every stage-1 tile
     for (auto &kv : stripes) {
       Stripe &s = kv.second;
       std::sort(s.slots.begin(), s.slots.end());
@@ -363,10 +398,8 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
         double fl = 2.0 * s.dL * s.dRin * N;
         P->stats.stage1_flops += fl;
         ch.flops1 += fl;
-        int mb = use_macro(P, s.dL, N) ? MACRO_MB : tile_mb(s.dL, N, P->tile_policy);
-        const int tr = tile_rows(mb), tc = tile_cols(mb);
-        for (const auto &cell : patch_order((s.dL + tr - 1) / tr, (N + tc - 1) / tc)) {
-            const int i0 = cell.first * tr, j0 = cell.second * tc;
+        for (const Cell &cell : output_cells(P, s.dL, N)) {
+            const int i0 = cell.i0, j0 = cell.j0, mb = cell.mb;
             Tile t{};
             t.c_base = BASE_WORK;
             if (trow) {
@@ -380,7 +413,10 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
             t.m = s.dL; t.n = N; t.i0 = i0; t.j0 = j0; t.ci0 = i0; t.cj0 = j0;
             t.mb = mb;
             t.seg0 = sidx; t.nseg = 1; t.accumulate = 0;
-            if (mb == MACRO_MB) {
+            if (mb == WIDE_MB) {
+              ch.tile1x.push_back(t);
+              cost1x.push_back(s.dRin);
+            } else if (mb == MACRO_MB) {
               ch.tile1m.push_back(t);
               cost1m.push_back(s.dRin);
             } else {
@@ -470,7 +506,7 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
         q = q1;
       }
     }
-    std::vector<std::pair<double, Tile>> tiles2, tiles2m;
+    std::vector<std::pair<double, Tile>> tiles2, tiles2m, tiles2x;
     int64_t npart = 0;   // partial-tile elements
     for (auto &kv : byF) {
       const ProbPlan &pp = *P->probs[kv.first.first];
@@ -517,17 +553,19 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
       int seg0 = (int)ch.seg2.size();
       for (auto &g : pieces) ch.seg2.push_back(g);
       for (auto &gi : pinfo) ch.s2info.push_back(gi);
-      const int mb = use_macro(P, F.dL, F.dR) ? MACRO_MB : tile_mb(F.dL, F.dR, P->tile_policy);
-      const int tm = tile_rows(mb), tn = tile_cols(mb);
-      auto &dst = mb == MACRO_MB ? tiles2m : tiles2;
-      const auto cells = patch_order((F.dL + tm - 1) / tm, (F.dR + tn - 1) / tn);
+      const auto cells = output_cells(P, F.dL, F.dR);
       const int np = (int)parts.size();
-      // partial tiles of cell c, part p at npart + (c np + p) tm tn; the list
-      // runs over parts (outer) and cells in patch order (inner), so the tiles
-      // that run together share their K range
+      // partial tiles of cell c, part p at npart + coff[c] + p tm tn (tm x tn
+      // the cell's tile shape); the list runs over parts (outer) and cells in
+      // patch order (inner), so the tiles that run together share their K range
+      std::vector<int64_t> coff(cells.size() + 1, 0);
+      for (size_t c = 0; c < cells.size(); c++)
+        coff[c + 1] = coff[c] + (int64_t)np * tile_rows(cells[c].mb) * tile_cols(cells[c].mb);
       for (int pi = 0; pi < np; pi++)
         for (size_t c = 0; c < cells.size(); c++) {
-          const int i0 = cells[c].first * tm, j0 = cells[c].second * tn;
+          const int i0 = cells[c].i0, j0 = cells[c].j0, mb = cells[c].mb;
+          const int tm = tile_rows(mb), tn = tile_cols(mb);
+          auto &dst = mb == WIDE_MB ? tiles2x : mb == MACRO_MB ? tiles2m : tiles2;
           Tile t{};
           t.m = F.dL; t.n = F.dR; t.i0 = i0; t.j0 = j0; t.mb = mb;
           t.seg0 = seg0 + parts[pi].first;
@@ -543,20 +581,20 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
               Reduce r{};
               r.y_off = pp.psi_off + F.off;
               r.ldc = F.dL;
-              r.part_off = npart + (int64_t)c * np * tm * tn;
+              r.part_off = npart + coff[c];
               r.m = F.dL; r.n = F.dR; r.i0 = i0; r.j0 = j0; r.tm = tm; r.tn = tn;
               r.nparts = np;
               ch.red2.push_back(r);
             }
             t.c_base = BASE_PART;
-            t.c_off = npart + ((int64_t)c * np + pi) * tm * tn;
+            t.c_off = npart + coff[c] + (int64_t)pi * tm * tn;
             t.ldc = tm;
             t.ci0 = 0; t.cj0 = 0;
             t.accumulate = 0;
           }
           dst.push_back({pcost[pi], t});
         }
-      if (np > 1) npart += (int64_t)cells.size() * np * tm * tn;
+      if (np > 1) npart += coff[cells.size()];
     }
     ch.part_elems = npart;
     P->part_elems = std::max(P->part_elems, ch.part_elems);
@@ -565,7 +603,8 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
     };
     std::stable_sort(tiles2.begin(), tiles2.end(), by_cost);
     std::stable_sort(tiles2m.begin(), tiles2m.end(), by_cost);
-    std::vector<double> cost2, cost2m;
+    std::stable_sort(tiles2x.begin(), tiles2x.end(), by_cost);
+    std::vector<double> cost2, cost2m, cost2x;
     for (auto &x : tiles2) {
       ch.tile2.push_back(x.second);
       cost2.push_back(x.first);
@@ -573,6 +612,10 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
     for (auto &x : tiles2m) {
       ch.tile2m.push_back(x.second);
       cost2m.push_back(x.first);
+    }
+    for (auto &x : tiles2x) {
+      ch.tile2x.push_back(x.second);
+      cost2x.push_back(x.first);
     }
     ch.q1 = xcd_queues(cost1);
     ch.q2 = xcd_queues(cost2);
@@ -582,6 +625,10 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
     ch.flops2w = list_flops(ch.tile2, ch.seg2);
     ch.q1m = xcd_queues(cost1m);
     ch.q2m = xcd_queues(cost2m);
+    ch.flops1x = list_flops(ch.tile1x, ch.seg1);
+    ch.flops2x = list_flops(ch.tile2x, ch.seg2);
+    ch.q1x = xcd_queues(cost1x);
+    ch.q2x = xcd_queues(cost2x);
     P->chunks.push_back(std::move(ch));
   }
   P->stats.flops = P->stats.stage1_flops + P->stats.stage2_flops;
@@ -637,6 +684,7 @@ int build_plan(dmrg_plan *P, int64_t budget_bytes, bool device) {
     if ((rc = upload(P, ch.seg1, &ch.d_seg1)) || (rc = upload(P, ch.seg2, &ch.d_seg2)) ||
         (rc = upload(P, ch.tile1, &ch.d_tile1)) || (rc = upload(P, ch.tile2, &ch.d_tile2)) ||
         (rc = upload(P, ch.tile1m, &ch.d_tile1m)) || (rc = upload(P, ch.tile2m, &ch.d_tile2m)) ||
+        (rc = upload(P, ch.tile1x, &ch.d_tile1x)) || (rc = upload(P, ch.tile2x, &ch.d_tile2x)) ||
         (rc = upload(P, ch.red2, &ch.d_red2)))
       return rc;
     P->stats.n_stage1 += (int64_t)ch.seg1.size();
@@ -923,16 +971,17 @@ void build_split(dmrg_plan *P) {
   check_jobs(P->jobs_psi);
   for (auto &ch : P->chunks) check_jobs(ch.tjobs);
   // the split kernels address a segment's slice lines with 32-bit byte
-  // offsets from the slice base: rows * ld * 2 bytes must stay below 2^32
+  // offsets from the slice base: rows * ld * 2 s bytes must stay below 2^32
   for (auto &ch : P->chunks)
-    for (int st = 0; st < 4; st++) {
-      const auto &tiles = st == 0 ? ch.tile1 : st == 1 ? ch.tile1m : st == 2 ? ch.tile2 : ch.tile2m;
-      const auto &ss = st < 2 ? ch.sseg1 : ch.sseg2;
+    for (int st = 0; st < 6; st++) {
+      const auto &tiles = st == 0 ? ch.tile1 : st == 1 ? ch.tile1m : st == 2 ? ch.tile1x
+                        : st == 3 ? ch.tile2 : st == 4 ? ch.tile2m : ch.tile2x;
+      const auto &ss = st < 3 ? ch.sseg1 : ch.sseg2;
       for (const Tile &t : tiles)
         for (int i = 0; i < t.nseg; i++) {
           const SegS &q = ss[t.seg0 + i];
-          if (q.K > 0 && ((int64_t)t.m * q.a_ld * 2 >= ((int64_t)1 << 32) ||
-                          (int64_t)t.n * q.b_ld * 2 >= ((int64_t)1 << 32)))
+          if (q.K > 0 && ((int64_t)t.m * q.a_ld * 2 * P->n_slices >= ((int64_t)1 << 32) ||
+                          (int64_t)t.n * q.b_ld * 2 * P->n_slices >= ((int64_t)1 << 32)))
             throw std::length_error("split operand lines span 4 GiB or more");
         }
     }
@@ -952,7 +1001,9 @@ int upload_split(dmrg_plan *P) {
   for (int b = 0; b < N_SBUF; b++) {
     void *d = P->dalloc(sizeof(uint16_t) * std::max<int64_t>(1, P->sb_elems[b] * P->n_slices));
     if (d) P->plan_allocs.push_back(d);
-    void *e = d ? P->dalloc(sizeof(int32_t) * std::max<int64_t>(1, P->sb_exps[b])) : nullptr;
+    // exponent arrays carry WIDE_EDGE spare entries: the wide tiles read the
+    // exponents of up to 128 lines past an output's last line (never stored)
+    void *e = d ? P->dalloc(sizeof(int32_t) * (P->sb_exps[b] + WIDE_EDGE)) : nullptr;
     if (!d || !e) {
       set_error("device allocation failed for slice buffers");
       return DMRG_ENOMEM;
@@ -960,7 +1011,6 @@ int upload_split(dmrg_plan *P) {
     P->plan_allocs.push_back(e);
     P->sb.data[b] = (uint16_t *)d;
     P->sb.exps[b] = (int32_t *)e;
-    P->sb.plane[b] = P->sb_elems[b];
   }
   // operator slices: once per plan (the operators are constant during Davidson)
   launch_slices(P->d_jobs_ops, (int)P->jobs_ops.size(), P->n_slices, P->d_bases, nullptr, nullptr, P->sb,
@@ -1003,7 +1053,8 @@ int count_launches(const dmrg_plan *P) {
   if (split) n += !P->jobs_psi.empty();
   for (const Chunk &ch : P->chunks) {
     // every tile launch clears its queue counters first
-    n += 2 * (!ch.tile1.empty() + !ch.tile2.empty() + !ch.tile1m.empty() + !ch.tile2m.empty()) +
+    n += 2 * (!ch.tile1.empty() + !ch.tile2.empty() + !ch.tile1m.empty() + !ch.tile2m.empty() +
+              !ch.tile1x.empty() + !ch.tile2x.empty()) +
          !ch.red2.empty();
     if (split) n += (ch.t_exps > 0) + !ch.titems.empty();
   }
@@ -1054,6 +1105,7 @@ uint64_t plan_hash(const dmrg_plan *P) {
   mix(P->n_slices);
   mix(P->xcd);
   mix(P->macro_min);
+  mix(P->wide_min);
   mix(P->budget);
   for (const auto &pp : P->probs) {
     mix((int64_t)pp->T.blocks.size());
@@ -1065,21 +1117,21 @@ uint64_t plan_hash(const dmrg_plan *P) {
 }
 
 std::mutex g_tune_mu;
-// kpart, tile policy, workspace cap, work-group tile threshold
-using TuneChoice = std::array<int64_t, 4>;
+// kpart, tile policy, workspace cap, work-group tile threshold, wide tile threshold
+using TuneChoice = std::array<int64_t, 5>;
 std::map<uint64_t, TuneChoice> g_tune_cache;
 
-// one line per plan-shape hash: "<hash> <kpart> <tile_policy> <cap> <macro_min>"
+// one line per plan-shape hash: "<hash> <kpart> <tile_policy> <cap> <macro_min> <wide_min>"
 bool read_tune_file(const std::string &path, uint64_t key, TuneChoice &out) {
   if (path.empty()) return false;
   FILE *f = std::fopen(path.c_str(), "r");
   if (!f) return false;
   unsigned long long h;
-  long long a, b, c, d;
+  long long a, b, c, d, e;
   bool found = false;
-  while (std::fscanf(f, "%llx %lld %lld %lld %lld", &h, &a, &b, &c, &d) == 5)
+  while (std::fscanf(f, "%llx %lld %lld %lld %lld %lld", &h, &a, &b, &c, &d, &e) == 6)
     if ((uint64_t)h == key) {   // the last line of a key wins
-      out = {a, b, c, d};
+      out = {a, b, c, d, e};
       found = true;
     }
   std::fclose(f);
@@ -1090,8 +1142,8 @@ void append_tune_file(const std::string &path, uint64_t key, const TuneChoice &c
   if (path.empty()) return;
   FILE *f = std::fopen(path.c_str(), "a");
   if (!f) return;
-  std::fprintf(f, "%016llx %lld %lld %lld %lld\n", (unsigned long long)key, (long long)c[0], (long long)c[1],
-               (long long)c[2], (long long)c[3]);
+  std::fprintf(f, "%016llx %lld %lld %lld %lld %lld\n", (unsigned long long)key, (long long)c[0], (long long)c[1],
+               (long long)c[2], (long long)c[3], (long long)c[4]);
   std::fclose(f);
 }
 
@@ -1100,6 +1152,7 @@ void apply_choice(dmrg_plan *P, const TuneChoice &c) {
   P->tile_policy = (int)c[1];
   P->budget = c[2];
   P->macro_min = (int)c[3];
+  P->wide_min = (int)c[4];
 }
 
 // Times candidate settings on the live plan and keeps the fastest (see
@@ -1142,7 +1195,7 @@ int autotune(dmrg_plan *P, void *stream) {
                ? DMRG_OK : DMRG_EHIP;
   const int64_t base = P->budget;
   double best = 1e300;
-  TuneChoice bc{P->kpart, P->tile_policy, base, P->macro_min};
+  TuneChoice bc{P->kpart, P->tile_policy, base, P->macro_min, P->wide_min};
   auto trial = [&](const TuneChoice &c) {
     if (rc) return;
     apply_choice(P, c);
@@ -1155,18 +1208,23 @@ int autotune(dmrg_plan *P, void *stream) {
       bc = c;
     }
   };
-  const int64_t mm0 = P->macro_min;
+  const int64_t mm0 = P->macro_min, wm0 = P->wide_min;
   for (int kp : {1024, 2048, 4096})
-    for (int pol : {0, 1}) trial({kp, pol, base, mm0});
+    for (int pol : {0, 1}) trial({kp, pol, base, mm0, wm0});
   if (P->precision == DMRG_SPLIT_BF16) {
     const TuneChoice b0 = bc;
     for (int mm : {0, 32, 48, 96})
-      if (mm != mm0) trial({b0[0], b0[1], base, mm});
+      if (mm != mm0) trial({b0[0], b0[1], base, mm, b0[4]});
+    if (P->n_slices <= WIDE_MAX_SLICES) {
+      const TuneChoice b2 = bc;
+      for (int wm : {0, 96, 192})
+        if (wm != wm0) trial({b2[0], b2[1], base, b2[3], wm});
+    }
   }
   {
     const TuneChoice b1 = bc;
     for (int64_t b : {(int64_t)512 << 20, (int64_t)192 << 20})
-      if (b < base) trial({b1[0], b1[1], b, b1[3]});
+      if (b < base) trial({b1[0], b1[1], b, b1[3], b1[4]});
   }
   P->dfree(x);
   P->dfree(y);
@@ -1289,6 +1347,7 @@ extern "C" int dmrg_build_tasks(const dmrg_problem_t *probs, int32_t n_probs, co
     P->kpart = (opts && opts->kpart > 0) ? opts->kpart : KPART;
     P->tile_policy = opts ? opts->tile_policy : 0;
     P->macro_min = !opts || opts->macro_min == 0 ? MACRO_MIN : std::max(0, opts->macro_min);
+    P->wide_min = !opts || opts->wide_min == 0 ? WIDE_MIN : std::max(0, opts->wide_min);
     P->budget = budget;
     if (P->kpart < 64 || P->kpart > (1 << 20) || P->tile_policy < 0 || P->tile_policy > 1) {
       set_error("kpart must be in [64, 2^20] and tile_policy 0 or 1");
@@ -1348,7 +1407,8 @@ int enqueue_with(dmrg_plan *p, const double *psi, double *hpsi, void *stream, bo
       if (split && stage == 2)
         launch_tslices(ch.d_tjobs, ch.d_titems, (int)ch.titems.size(), p->n_slices, B.work, B.sb, stream);
       // profiling: an event pair around each tile launch, marked 10 + stage
-      // (work-group tiles) or 20 + stage (wavefront tiles) with its flops
+      // (work-group tiles), 20 + stage (wavefront tiles) or 30 + stage (wide
+      // tiles) with its flops
       auto timed = [&](int code, double flops, auto &&launch) -> int {
         if (!prof) {
           launch();
@@ -1368,9 +1428,16 @@ int enqueue_with(dmrg_plan *p, const double *psi, double *hpsi, void *stream, bo
       };
       int rc = DMRG_OK;
       if (split) {
-        // work-group tiles (the larger outputs) first, then the wavefront tiles
+        // wide tiles, work-group tiles (the larger outputs), then the wavefront tiles
         const bool s1 = stage == 1;
-        if (!(s1 ? ch.tile1m : ch.tile2m).empty())
+        if (!(s1 ? ch.tile1x : ch.tile2x).empty())
+          rc = timed(30 + stage, s1 ? ch.flops1x : ch.flops2x, [&] {
+            launch_wide_split(stage, s1 ? ch.d_tile1x : ch.d_tile2x, s1 ? ch.d_seg1 : ch.d_seg2,
+                              s1 ? ch.d_sseg1 : ch.d_sseg2, (int)(s1 ? ch.tile1x : ch.tile2x).size(),
+                              s1 ? ch.q1x : ch.q2x, B.counters, p->n_slices, p->d_bases, psi, hpsi, B.work,
+                              B.part, B.sb, stream);
+          });
+        if (!rc && !(s1 ? ch.tile1m : ch.tile2m).empty())
           rc = timed(10 + stage, s1 ? ch.flops1m : ch.flops2m, [&] {
             launch_macro_split(stage, s1 ? ch.d_tile1m : ch.d_tile2m, s1 ? ch.d_seg1 : ch.d_seg2,
                                s1 ? ch.d_sseg1 : ch.d_sseg2, (int)(s1 ? ch.tile1m : ch.tile2m).size(),
@@ -1420,7 +1487,7 @@ int64_t plan_scratch_layout(const dmrg_plan_t *p, int64_t off[SCRATCH_REGIONS]) 
   off[0] = o; o = up(o + 8 * std::max<int64_t>(p->work_elems, 1));
   off[1] = o; o = up(o + 8 * std::max<int64_t>(p->part_elems, 1));
   off[2] = o; if (split) o = up(o + 2 * std::max<int64_t>(p->sb_elems[SBUF_T], 1) * p->n_slices);
-  off[3] = o; if (split) o = up(o + 4 * std::max<int64_t>(p->sb_exps[SBUF_T], 1));
+  off[3] = o; if (split) o = up(o + 4 * (p->sb_exps[SBUF_T] + WIDE_EDGE));   // spare entries: see upload_split
   off[4] = o; o = up(o + 4 * QUEUE_INTS);
   return o;
 }
@@ -1493,7 +1560,7 @@ extern "C" int dmrg_set_profiling(dmrg_plan_t *p, int32_t on) {
 
 extern "C" int dmrg_get_profile(dmrg_plan_t *p, int32_t stage, int64_t *n_launches, double *total_ms,
                                 double *total_flops) {
-  if (!p || !(stage == 1 || stage == 2 || stage == 11 || stage == 12 || stage == 21 || stage == 22)) {
+  if (!p || !(stage == 1 || stage == 2 || ((stage / 10 >= 1 && stage / 10 <= 3) && (stage % 10 == 1 || stage % 10 == 2)))) {
     set_error("bad plan or stage");
     return DMRG_EINVAL;
   }
@@ -1533,6 +1600,7 @@ extern "C" int dmrg_plan_stats(const dmrg_plan_t *p, dmrg_plan_stats_t *st) {
   st->workspace_cap = p->budget;
   st->tune_ms = p->tune_ms;
   st->macro_min = p->precision == DMRG_SPLIT_BF16 ? p->macro_min : 0;
+  st->wide_min = p->precision == DMRG_SPLIT_BF16 && p->n_slices <= WIDE_MAX_SLICES ? p->wide_min : 0;
   st->device_bytes = p->held;
   return DMRG_OK;
 }
@@ -1588,7 +1656,7 @@ static void host_tiles(const std::vector<Tile> &tiles, const std::vector<Seg> &s
 
 // host emulation of slice_kernel
 static void host_slices(const std::vector<SliceJob> &jobs, int ns, const std::vector<const double *> &bases,
-                        const double *psi, const double *work, std::vector<uint16_t> *sbd, const int64_t *plane,
+                        const double *psi, const double *work, std::vector<uint16_t> *sbd,
                         std::vector<int32_t> *sbe) {
   auto base = [&](int id) -> const double * {
     return id == BASE_PSI ? psi : id == BASE_WORK ? work : bases[id - BASE_OPS];
@@ -1615,10 +1683,10 @@ static void host_slices(const std::vector<SliceJob> &jobs, int ns, const std::ve
         for (int t = 0; t < ns; t++) {
           double a = std::nearbyint(yv * 256.0);
           yv = yv * 256.0 - a;
-          float af = (float)a;
+          float af = (float)std::ldexp(a, -SLICE_BITS * t);   // digit t at its weight 2^(-8t)
           uint32_t bits;
           std::memcpy(&bits, &af, 4);
-          sbd[J.dst_buf][J.dst_off + (int64_t)t * plane[J.dst_buf] + (int64_t)rho * len + idx] = (uint16_t)(bits >> 16);
+          sbd[J.dst_buf][slice_index(J.dst_off + (int64_t)rho * len + idx, t, ns)] = (uint16_t)(bits >> 16);
         }
       }
     }
@@ -1636,7 +1704,7 @@ static double bf16v(uint16_t b) {
 static void host_tiles_split(const std::vector<Tile> &tiles, const std::vector<Seg> &segs,
                              const std::vector<SegS> &ssegs, int ns, const std::vector<const double *> &bases,
                              const double *psi, double *y, double *work, double *part,
-                             std::vector<uint16_t> *sbd, const int64_t *plane, std::vector<int32_t> *sbe) {
+                             std::vector<uint16_t> *sbd, std::vector<int32_t> *sbe) {
   auto base = [&](int id) -> const double * {
     return id == BASE_PSI ? psi : id == BASE_Y ? y : id == BASE_WORK ? work : id == BASE_PART ? part
                                                                                                : bases[id - BASE_OPS];
@@ -1659,14 +1727,13 @@ static void host_tiles_split(const std::vector<Tile> &tiles, const std::vector<S
           }
         continue;
       }
-      const uint16_t *A = sbd[Q.a_buf].data() + Q.a_off;
-      const uint16_t *B = sbd[Q.b_buf].data() + Q.b_off;
+      const uint16_t *A = sbd[Q.a_buf].data(), *B = sbd[Q.b_buf].data();   // slices interleaved
       const int32_t *ea = sbe[Q.a_buf].data() + Q.a_exp;
       const int32_t *eb = sbe[Q.b_buf].data() + Q.b_exp;
       for (int j = 0; j < nt; j++)
         for (int i = 0; i < mt; i++) {
-          const uint16_t *ar = A + (int64_t)(T.i0 + i) * Q.a_ld;
-          const uint16_t *bc = B + (int64_t)(T.j0 + j) * Q.b_ld;
+          const int64_t ar = Q.a_off + (int64_t)(T.i0 + i) * Q.a_ld;   // line starts (unsliced layout)
+          const int64_t bc = Q.b_off + (int64_t)(T.j0 + j) * Q.b_ld;
           double tot = 0.0;
           for (int k0 = 0; k0 < Q.K; k0 += split_fold_k(ns)) {
             double x = 0.0;
@@ -1674,8 +1741,8 @@ static void host_tiles_split(const std::vector<Tile> &tiles, const std::vector<S
               double qd = 0.0;
               for (int t = 0; t <= d; t++)
                 for (int k = k0; k < std::min(Q.K, k0 + split_fold_k(ns)); k++)
-                  qd += bf16v(ar[(int64_t)t * plane[Q.a_buf] + k]) * bf16v(bc[(int64_t)(d - t) * plane[Q.b_buf] + k]);
-              x += std::ldexp(qd, -SLICE_BITS * (d + 2));
+                  qd += bf16v(A[slice_index(ar + k, t, ns)]) * bf16v(B[slice_index(bc + k, d - t, ns)]);
+              x += std::ldexp(qd, -2 * SLICE_BITS);   // slices carry their digit weights
             }
             tot += S.s * std::ldexp(x, ea[T.i0 + i] + eb[T.j0 + j]);
           }
@@ -1715,6 +1782,7 @@ extern "C" int dmrg_debug_plan_host_apply(const dmrg_problem_t *prob, const doub
   P->kpart = (opts && opts->kpart > 0) ? opts->kpart : KPART;
   P->tile_policy = opts ? opts->tile_policy : 0;
   P->macro_min = !opts || opts->macro_min == 0 ? MACRO_MIN : std::max(0, opts->macro_min);
+  P->wide_min = !opts || opts->wide_min == 0 ? WIDE_MIN : std::max(0, opts->wide_min);
   auto pp = std::make_unique<ProbPlan>();
   Error err{0, ""};
   auto tt0 = std::chrono::steady_clock::now();
@@ -1766,24 +1834,26 @@ extern "C" int dmrg_debug_plan_host_apply(const dmrg_problem_t *prob, const doub
       return DMRG_EINVAL;
     }
     int ns = P->n_slices;
-    int64_t plane[N_SBUF];
     for (int b = 0; b < N_SBUF; b++) {
       P->h_sb[b].assign((size_t)std::max<int64_t>(1, P->sb_elems[b] * ns), 0);
       P->h_se[b].assign((size_t)std::max<int64_t>(1, P->sb_exps[b]), 0);
-      plane[b] = P->sb_elems[b];
     }
-    host_slices(P->jobs_ops, ns, P->bases_h, psi, work.data(), P->h_sb, plane, P->h_se);
-    host_slices(P->jobs_psi, ns, P->bases_h, psi, work.data(), P->h_sb, plane, P->h_se);
+    host_slices(P->jobs_ops, ns, P->bases_h, psi, work.data(), P->h_sb, P->h_se);
+    host_slices(P->jobs_psi, ns, P->bases_h, psi, work.data(), P->h_sb, P->h_se);
     for (auto &ch : P->chunks) {
       host_tiles_split(ch.tile1m, ch.seg1, ch.sseg1, ns, P->bases_h, psi, y, work.data(), part.data(), P->h_sb,
-                       plane, P->h_se);
+                       P->h_se);
+      host_tiles_split(ch.tile1x, ch.seg1, ch.sseg1, ns, P->bases_h, psi, y, work.data(), part.data(), P->h_sb,
+                       P->h_se);
       host_tiles_split(ch.tile1, ch.seg1, ch.sseg1, ns, P->bases_h, psi, y, work.data(), part.data(), P->h_sb,
-                       plane, P->h_se);
-      host_slices(ch.tjobs, ns, P->bases_h, psi, work.data(), P->h_sb, plane, P->h_se);
+                       P->h_se);
+      host_slices(ch.tjobs, ns, P->bases_h, psi, work.data(), P->h_sb, P->h_se);
       host_tiles_split(ch.tile2m, ch.seg2, ch.sseg2, ns, P->bases_h, psi, y, work.data(), part.data(), P->h_sb,
-                       plane, P->h_se);
+                       P->h_se);
+      host_tiles_split(ch.tile2x, ch.seg2, ch.sseg2, ns, P->bases_h, psi, y, work.data(), part.data(), P->h_sb,
+                       P->h_se);
       host_tiles_split(ch.tile2, ch.seg2, ch.sseg2, ns, P->bases_h, psi, y, work.data(), part.data(), P->h_sb,
-                       plane, P->h_se);
+                       P->h_se);
       host_reduce(ch.red2, part.data(), y);
     }
     delete P;
@@ -1800,10 +1870,16 @@ extern "C" int dmrg_debug_plan_host_apply(const dmrg_problem_t *prob, const doub
 
 // Test-only: per-tile work of one stage of the plan built for `prob` (host
 // operator data): rows of (m, n, number of segments, summed K).
-extern "C" int64_t dmrg_debug_plan_tiles(const dmrg_problem_t *prob, int32_t stage, int64_t *out,
-                                         int64_t cap) {
+extern "C" int64_t dmrg_debug_plan_tiles(const dmrg_problem_t *prob, const dmrg_plan_opts_t *opts, int32_t stage,
+                                         int64_t *out, int64_t cap) {
   dmrg_plan *P = new dmrg_plan();
   std::memset(&P->stats, 0, sizeof(P->stats));
+  P->precision = opts ? opts->precision : DMRG_FP64;
+  P->n_slices = opts ? opts->n_slices : 0;
+  P->kpart = (opts && opts->kpart > 0) ? opts->kpart : KPART;
+  P->tile_policy = opts ? opts->tile_policy : 0;
+  P->macro_min = !opts || opts->macro_min == 0 ? MACRO_MIN : std::max(0, opts->macro_min);
+  P->wide_min = !opts || opts->wide_min == 0 ? WIDE_MIN : std::max(0, opts->wide_min);
   auto pp = std::make_unique<ProbPlan>();
   Error err{0, ""};
   if (build_tasks_for_problem(*prob, pp->L, pp->R, pp->T, err)) { set_error(err.msg); delete P; return err.code; }
@@ -1815,17 +1891,22 @@ extern "C" int64_t dmrg_debug_plan_tiles(const dmrg_problem_t *prob, int32_t sta
   if (rc) { delete P; return rc; }
   int64_t n = 0;
   for (auto &ch : P->chunks) {
-    std::vector<Tile> tiles = stage == 1 ? ch.tile1m : ch.tile2m;
+    std::vector<Tile> tiles = stage == 1 ? ch.tile1x : ch.tile2x;
+    for (const Tile &t : stage == 1 ? ch.tile1m : ch.tile2m) tiles.push_back(t);
     for (const Tile &t : stage == 1 ? ch.tile1 : ch.tile2) tiles.push_back(t);
     const auto &segs = stage == 1 ? ch.seg1 : ch.seg2;
     for (const Tile &t : tiles) {
       int64_t sk = 0;
       for (int i = 0; i < t.nseg; i++) sk += segs[t.seg0 + i].a_base < 0 ? 0 : segs[t.seg0 + i].K;
-      if (n < cap) {
-        out[4 * n] = std::min(tile_rows(t.mb), t.m - t.i0);
-        out[4 * n + 1] = std::min(tile_cols(t.mb), t.n - t.j0);
-        out[4 * n + 2] = t.nseg;
-        out[4 * n + 3] = sk;
+      if (out && n < cap) {
+        int64_t *o = out + 7 * n;
+        o[0] = std::min(tile_rows(t.mb), t.m - t.i0);
+        o[1] = std::min(tile_cols(t.mb), t.n - t.j0);
+        o[2] = t.nseg;
+        o[3] = sk;
+        o[4] = t.m;
+        o[5] = t.n;
+        o[6] = t.mb;
       }
       n++;
     }

@@ -28,8 +28,20 @@ struct Seg {
 constexpr int MACRO_MB = 8;
 constexpr int MACRO_EDGE = 64;
 constexpr int MACRO_MIN = 48;   // default: outputs with both dims >= 48 get work-group tiles
-constexpr int tile_rows(int mb) { return mb == MACRO_MB ? MACRO_EDGE : 16 * mb; }
-constexpr int tile_cols(int mb) { return mb == MACRO_MB ? MACRO_EDGE : 64 / mb; }
+// Wide work-group tiles (split plans, s <= 5): WIDE_MB tiles are 128 x 128,
+// computed by the eight wavefronts of a work group (two per SIMD, 32 x 64
+// each, v_mfma_f32_32x32x16_bf16) from two 80 KiB LDS stages.  An
+// output with both sides >= wide_min is cut into 128-wide bands (a last band
+// of >= WIDE_TAIL lines is a wide band too); the rest of it gets 64 x 64 or
+// wavefront tiles.
+constexpr int WIDE_MB = 16;
+constexpr int WIDE_EDGE = 128;
+constexpr int WIDE_MIN = 96;
+constexpr int WIDE_TAIL = 96;
+constexpr int WIDE_WAVES = 8;
+constexpr int WIDE_MAX_SLICES = 5;
+constexpr int tile_rows(int mb) { return mb == WIDE_MB ? WIDE_EDGE : mb == MACRO_MB ? MACRO_EDGE : 16 * mb; }
+constexpr int tile_cols(int mb) { return mb == WIDE_MB ? WIDE_EDGE : mb == MACRO_MB ? MACRO_EDGE : 64 / mb; }
 
 // Per-XCD queues of a work-group tile list: the list (cost-sorted, operand
 // bands in patches) is cut into NXCD contiguous ranges of equal cost; the work
@@ -38,6 +50,7 @@ constexpr int tile_cols(int mb) { return mb == MACRO_MB ? MACRO_EDGE : 64 / mb; 
 // on one XCD are neighbours in the list and share operand bands in its L2.
 constexpr int NXCD = 8;
 constexpr int MACRO_GRID = 512;          // work groups of a work-group tile launch (two per CU)
+constexpr int WIDE_GRID = 256;           // work groups of a wide tile launch (one per CU)
 constexpr int QUEUE_INTS = NXCD + MACRO_GRID;   // queue counters, then one mailbox per work group
 struct XcdQueues {
   int32_t start[NXCD + 1];
@@ -96,21 +109,32 @@ struct DressItem {
 // ---------------------------------------------------------------- split BF16
 // Fixed-point slicing (Ozaki-style): a line x (row of an A operand or column
 // of a B operand, over its K range) is scaled by 2^-e with e the smallest
-// integer such that max|x| <= 2^e, then cut into s integer slices of SLICE_BITS
-// bits, x = 2^e sum_t a_t 2^(-8(t+1)) + O(2^(e-8s)), |a_0| <= 256, |a_t| <= 128:
-// all exact in BF16.  Lines are stored K-contiguous (operand-ready) and each
-// position block of K is padded to a multiple of 8 with zeros.
+// integer such that max|x| <= 2^e, then cut into s integer digits of SLICE_BITS
+// bits, x = 2^e sum_t a_t 2^(-8(t+1)) + O(2^(e-8s)), |a_0| <= 256, |a_t| <= 128.
+// Slice t stores a_t 2^(-8t), exact in BF16 (at most 8 significant bits), so
+// that a product of slices t and u already carries the relative weight
+// 2^(-8(t+u)) of its group d = t + u and every group folds with 2^-16.  Lines
+// are stored K-contiguous (operand-ready), each position block of K padded to
+// a multiple of 8 with zeros, and the s slices interleaved per chunk of 8: the
+// element at index e of the unsliced layout (offsets, line lengths: multiples
+// of 8) has slice t at (e - e % 8) s + 8 t + e % 8 (slice_index), so that the
+// s slices of a K step of a line are one contiguous run of memory.
 constexpr int SLICE_BITS = 8;
-// Sums of slice products are folded into FP64 every split_fold_k(s) terms of
-// K.  Group d sums the products a_t b_(d-t), t = 0..d: the two with t = 0 or
-// t = d are bounded by 256 * 128 = 2^15 and the others by 2^14, so per k the
-// group is at most (s + 2) 2^14 in magnitude for every d < s (s >= 2), and K
-// terms stay integers below 2^24 -- exact in FP32 -- while K (s + 2) <= 2^10.
-constexpr int split_fold_k(int ns) { return ns <= 6 ? 128 : 64; }
+// Slice products accumulate in slice_groups(s) FP32 sums: groups d = t + u
+// below s - 3 each in its own sum, exact, and all groups d >= s - 3 in one
+// more sum (for s <= 3 that is the only one).  Per k an exact group d is at
+// most 2^16 (d <= 1) or (d + 3) 2^14 (d >= 2) in units of its resolution
+// 2^(-8d), so over split_fold_k(s) terms its sum stays an integer (in those
+// units) below 2^24: exact in FP32.  The merged sum is rounded, but its terms
+// weigh at most about 2^(-8(s-3)+1) of group 0, so FP32 rounding (2^-24) puts
+// its error at the level of the truncation after s digits (2^-8s).  Every
+// split_fold_k(s) terms of K the sums are folded into FP64.
+constexpr int slice_groups(int ns) { return ns <= 3 ? 1 : ns - 2; }
+constexpr int split_fold_k(int ns) { return ns <= 5 ? 256 : 128; }
 
 // One slicing job: lines rho < nrho, position blocks p < npos of kb valid
 // entries (padded to kbp);  source x(rho, p, kk) at src[src_off + rho*s_rho + p*s_pos + kk*s_k];
-// destination plane t line rho at dst[dst_off + t*plane + rho*npos*kbp + p*kbp + kk];
+// slice t of the element at e = dst_off + rho*npos*kbp + p*kbp + kk at dst[slice_index(e, t, s)];
 // exponent of line rho at exps[exp_off + rho].
 struct SliceJob {
   int64_t src_off, s_rho, s_pos, s_k;
@@ -141,10 +165,11 @@ struct TSliceItem {
 enum { SBUF_OPS = 0, SBUF_PSIR = 1, SBUF_PSIC = 2, SBUF_T = 3, N_SBUF = 4 };
 
 struct SliceBufs {
-  uint16_t *data[N_SBUF];     // bf16 bit patterns
-  int64_t plane[N_SBUF];      // plane stride (elements)
+  uint16_t *data[N_SBUF];     // bf16 bit patterns, slices interleaved (slice_index)
   int32_t *exps[N_SBUF];
 };
+// position of slice t of element e (index in the unsliced layout) for s slices
+__host__ __device__ inline int64_t slice_index(int64_t e, int t, int s) { return (e - (e & 7)) * s + 8 * t + (e & 7); }
 
 
 // bookkeeping that lets the split-precision plan mirror the FP64 segments
@@ -164,14 +189,17 @@ struct Chunk {
   std::vector<Seg> seg1, seg2;
   std::vector<Tile> tile1, tile2;       // one wavefront per tile
   std::vector<Tile> tile1m, tile2m;     // work-group (macro) tiles
-  XcdQueues q1{}, q2{}, q1m{}, q2m{};   // per-XCD ranges of the four lists
+  std::vector<Tile> tile1x, tile2x;     // wide work-group tiles
+  XcdQueues q1{}, q2{}, q1m{}, q2m{}, q1x{}, q2x{};   // per-XCD ranges of the six lists
   std::vector<Reduce> red2;
   Seg *d_seg1 = nullptr, *d_seg2 = nullptr;
   Tile *d_tile1 = nullptr, *d_tile2 = nullptr;
   Tile *d_tile1m = nullptr, *d_tile2m = nullptr;
+  Tile *d_tile1x = nullptr, *d_tile2x = nullptr;
   Reduce *d_red2 = nullptr;
   double flops1 = 0.0, flops2 = 0.0;    // algorithmic flops of each stage
   double flops1m = 0.0, flops2m = 0.0;  // ... of its work-group tiles
+  double flops1x = 0.0, flops2x = 0.0;  // ... of its wide tiles
   double flops1w = 0.0, flops2w = 0.0;  // ... of its wavefront tiles
   int64_t part_elems = 0;               // partial-tile buffer needed
   // split precision (filled only for split plans)
@@ -229,5 +257,9 @@ void launch_tiles_split(int stage, const Tile *tiles, const Seg *segs, const Seg
 void launch_macro_split(int stage, const Tile *tiles, const Seg *segs, const SegS *ssegs, int ntiles,
                         const XcdQueues &q, int32_t *counters, int nslices, const double *const *bases,
                         const double *psi, double *y, double *work, double *part, SliceBufs bufs, void *stream);
+// wide (WIDE_MB) tiles, s <= WIDE_MAX_SLICES, same queue protocol
+void launch_wide_split(int stage, const Tile *tiles, const Seg *segs, const SegS *ssegs, int ntiles,
+                       const XcdQueues &q, int32_t *counters, int nslices, const double *const *bases,
+                       const double *psi, double *y, double *work, double *part, SliceBufs bufs, void *stream);
 
 }  // namespace dmrg

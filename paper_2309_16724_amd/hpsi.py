@@ -52,7 +52,7 @@ class TorchAllocator:
 class Plan:
     def __init__(self, problems, precision=B.DMRG_FP64, n_slices=0, workspace_bytes=0,
                  device="cuda:0", flags=0, kpart=0, tile_policy=0, macro_min=0, allocator=None,
-                 tune_cache=None):
+                 tune_cache=None, wide_min=0):
         """allocator: None (the library uses hipMalloc), "torch" (PyTorch's
         caching allocator on the current stream) or a TorchAllocator;
         tune_cache: file of autotuned settings (with DMRG_PLAN_AUTOTUNE)."""
@@ -86,7 +86,7 @@ class Plan:
         tc = None if tune_cache is None else str(tune_cache).encode()
         self._keep.append(tc)
         opts = B.PlanOpts(precision, n_slices, workspace_bytes, flags, kpart, tile_policy, macro_min,
-                          fa, ff, None, tc)
+                          wide_min, 0, fa, ff, None, tc)
         h = ctypes.c_void_p()
         stream = torch.cuda.current_stream(self.device).cuda_stream
         torch.cuda.synchronize(self.device)

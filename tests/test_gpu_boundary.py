@@ -48,6 +48,7 @@ def test_caller_allocator_gets_every_allocation(torch, prec, ns):
     # the tuned settings may differ from the defaults: compare with a plan of the same settings
     p_same = Plan(prob, precision=prec, n_slices=ns, kpart=st["kpart"], tile_policy=st["tile_policy"],
                   macro_min=st["macro_min"] if st["macro_min"] > 0 else -1,
+                  wide_min=st["wide_min"] if st["wide_min"] > 0 else -1,
                   workspace_bytes=st["workspace_cap"])
     y_cb, y_same = p_cb.apply(x), p_same.apply(x)
     torch.cuda.synchronize()
@@ -73,7 +74,7 @@ plan = Plan(random_problem(10, 10, 0, 22, D=150), precision=1, n_slices=5, flags
             tune_cache=%r)
 st = plan.stats()
 plan.free()
-print(json.dumps({k: st[k] for k in ("tuned", "kpart", "tile_policy", "macro_min", "workspace_cap")}))
+print(json.dumps({k: st[k] for k in ("tuned", "kpart", "tile_policy", "macro_min", "wide_min", "workspace_cap")}))
 """
 
 
@@ -89,6 +90,6 @@ def test_tune_cache_survives_a_process_restart(torch, tmp_path):
         outs.append(json.loads(r.stdout.strip().splitlines()[-1]))
         _say("process %d: %s" % (k, outs[-1]))
     assert outs[0]["tuned"] > 0 and outs[1]["tuned"] == -1
-    for key in ("kpart", "tile_policy", "macro_min", "workspace_cap"):
+    for key in ("kpart", "tile_policy", "macro_min", "wide_min", "workspace_cap"):
         assert outs[0][key] == outs[1][key]
     assert len(path.read_text().strip().splitlines()) == 1

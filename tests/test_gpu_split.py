@@ -37,6 +37,13 @@ def _apply(torch, prob, x, **kw):
 
 
 BOUND = {3: 5e-6, 4: 5e-9, 5: 1e-10, 6: 1e-12, 7: 1e-13}
+# Two split paths over the same slices differ only in the rounding of the
+# FP32 sum that holds the trailing product groups (d >= s - 3, all groups for
+# s = 3), whose terms weigh about 2^(-8(s-3)) of the leading ones: 2^-24 times
+# that, the level of the truncation after s slices, amplified like it by the
+# accumulation and the cancellation in H.psi (measured: 5e-8, 2.8e-9, 2.0e-11
+# for s = 3, 4, 5 on the wide-tile problem), with margin.
+TILE_TOL = {3: 2e-6, 4: 1e-8, 5: 6e-11, 6: 5e-13, 7: 5e-14}
 
 
 @pytest.mark.parametrize("ns", [3, 4, 5, 6, 7])
@@ -61,7 +68,8 @@ def test_split_equals_host_emulation(torch):
         B.debug_plan_host_apply(prob, None)[1]["psi_len"])
     yh, _ = B.debug_plan_host_apply(prob, x, precision=1, n_slices=5)
     y = _apply(torch, prob, x, precision=1, n_slices=5)
-    assert np.abs(y - yh).max() <= 1e-14 * np.abs(yh).max()
+    _say("  rel diff to the emulation %.3e" % (np.abs(y - yh).max() / np.abs(yh).max()))
+    assert np.abs(y - yh).max() <= TILE_TOL[5] * np.abs(yh).max()
 
 
 def test_split_full_size_vs_oracle(torch):
@@ -103,5 +111,34 @@ def test_workgroup_tiles_match_oracle_and_emulation(torch, ns):
         _say("    rel err %.3e vs oracle, %.3e vs emulation, %.3e vs wavefront tiles"
              % (err, np.abs(y - yh).max() / np.abs(yh).max(), np.abs(y - yw).max() / np.abs(yw).max()))
         assert err <= BOUND[ns]
-        assert np.abs(y - yh).max() <= 1e-14 * np.abs(yh).max()
-        assert np.abs(y - yw).max() <= 1e-14 * np.abs(yw).max()
+        assert np.abs(y - yh).max() <= TILE_TOL[ns] * np.abs(yh).max()
+        assert np.abs(y - yw).max() <= TILE_TOL[ns] * np.abs(yw).max()
+
+
+@pytest.mark.parametrize("ns", [3, 4, 5])
+def test_wide_tiles_match_oracle(torch, ns):
+    """Outputs of 96 and more on both sides go to 128 x 128 wide tiles (eight
+    wavefronts, v_mfma_f32_32x32x16_bf16, two LDS stages as separate
+    objects): a 212-row output as one wide band plus 64-row tiles, 106-line
+    outputs as partial wide bands, split K (kpart 256) and whole segments;
+    against the oracle and the same plan without wide tiles (wide_min < 0)
+    and without any work-group tiles."""
+    from oracle.hpsi import HEff
+    from paper_2309_16724_amd import binding as B
+    prob = random_problem(6, 6, 0, 1, D=500, D_right=250, cap=False)
+    kinds = set(B.debug_plan_tiles(prob, 2, precision=1, n_slices=ns)[:, 6])
+    assert 16 in kinds and 8 in kinds
+    he = HEff(prob)
+    x = np.random.default_rng(7).standard_normal(he.size)
+    ref = he.apply(x)
+    for kp in (0, 256):
+        _say("  wide s=%d kpart=%d" % (ns, kp))
+        y = _apply(torch, prob, x, precision=1, n_slices=ns, kpart=kp)
+        yn = _apply(torch, prob, x, precision=1, n_slices=ns, kpart=kp, wide_min=-1)
+        yw = _apply(torch, prob, x, precision=1, n_slices=ns, kpart=kp, wide_min=-1, macro_min=-1)
+        err = np.abs(y - ref).max() / np.abs(ref).max()
+        dn = np.abs(y - yn).max() / np.abs(yn).max()
+        dw = np.abs(y - yw).max() / np.abs(yw).max()
+        _say("    rel err %.3e vs oracle, %.3e vs 64x64 tiles, %.3e vs wavefront tiles" % (err, dn, dw))
+        assert err <= BOUND[ns]
+        assert dn <= TILE_TOL[ns] and dw <= TILE_TOL[ns]
