@@ -201,6 +201,10 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
 }
 
 // Y tile += sum of its partial tiles, in part order
+// one output tile per blockIdx.x (grid-stride), its elements shared by the
+// REDUCE_SPLIT blocks along y: the 128 x 128 tiles of wide plans have 16384
+// elements, which one block of 256 threads would take alone
+constexpr int REDUCE_SPLIT = 16;
 __global__ void reduce_kernel(const Reduce *__restrict__ red, int nred, const double *__restrict__ part,
                               double *__restrict__ y) {
   for (int r = blockIdx.x; r < nred; r += gridDim.x) {
@@ -208,7 +212,7 @@ __global__ void reduce_kernel(const Reduce *__restrict__ red, int nred, const do
     int mt = min(R.tm, R.m - R.i0);
     int nt = min(R.tn, R.n - R.j0);
     const int64_t ps = (int64_t)R.tm * R.tn;
-    for (int e = threadIdx.x; e < mt * nt; e += blockDim.x) {
+    for (int e = blockIdx.y * blockDim.x + threadIdx.x; e < mt * nt; e += gridDim.y * blockDim.x) {
       int i = e % mt, j = e / mt;
       double v = 0.0;
       for (int p = 0; p < R.nparts; p++) v += part[R.part_off + (int64_t)p * ps + i + (int64_t)j * R.tm];
@@ -288,8 +292,8 @@ void launch_tiles_f64(int stage, const Tile *tiles, const Seg *segs, int ntiles,
 
 void launch_reduce(const Reduce *red, int nred, const double *part, double *y, void *stream) {
   if (nred <= 0) return;
-  hipLaunchKernelGGL(reduce_kernel, dim3(std::min(nred, 8192)), dim3(256), 0, (hipStream_t)stream, red, nred,
-                     part, y);
+  hipLaunchKernelGGL(reduce_kernel, dim3(std::min(nred, 8192), REDUCE_SPLIT), dim3(256), 0, (hipStream_t)stream, red,
+                     nred, part, y);
 }
 
 void launch_diag(const DiagBlock *blocks, const DiagTerm *terms, int nblocks, const double *const *bases,

@@ -105,44 +105,50 @@ __global__ void __launch_bounds__(256) slice_kernel(const SliceJob *__restrict__
 }
 
 // stripe slices, one work group per chunk of TSLICE_CHUNK elements, four
-// consecutive elements per thread.  Line lengths, position blocks (kbp) and
-// job offsets are multiples of 8, so a group of four never straddles a line,
-// a position block or a chunk of 8, and each of its slices is one aligned
-// 8-byte store.
+// consecutive elements per thread.  Line lengths, position blocks (kbp), job
+// offsets and chunk starts are multiples of 8, so a group of four never
+// straddles a line, a position block or a chunk of 8, and the slices of a
+// work group's elements are one contiguous range of the slice buffer: they
+// are assembled in LDS and written out in whole 16-byte pieces.
 static_assert(TSLICE_CHUNK == 4 * 256, "one chunk is 256 threads x 4 elements");
 __global__ void __launch_bounds__(256) tslice_kernel(const SliceJob *__restrict__ jobs,
                                                       const TSliceItem *__restrict__ items, int nitems, int ns,
                                                       const double *__restrict__ work, SliceBufs bufs) {
+  __shared__ __attribute__((aligned(16))) uint16_t out[TSLICE_CHUNK * 7];
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const TSliceItem I = items[it];
     const SliceJob J = jobs[I.job];
-    const double *src = work + J.src_off;
-    uint16_t *dst = bufs.data[SBUF_T];
-    const int32_t *exps = bufs.exps[SBUF_T] + J.exp_off;
     const unsigned kb = (unsigned)J.kb, kbp = (unsigned)J.kbp, len = (unsigned)(J.npos * J.kbp);
     const unsigned tot = len * (unsigned)J.nrho;
-    const unsigned e = (unsigned)I.e0 + 4u * threadIdx.x;
-    if (e >= tot) continue;
-    const unsigned rho = e / len, idx = e - rho * len;
-    const unsigned p = idx / kbp, kk = idx - p * kbp;
-    const double *line = src + (int64_t)rho * J.s_rho + (int64_t)p * J.s_pos;
-    const int ex = exps[rho];
-    double yv[4];
-    for (int i = 0; i < 4; i++) {
-      const unsigned k = kk + i;
-      const double x = line[(int64_t)min(k, kb - 1) * J.s_k];    // padding reads a valid entry ...
-      yv[i] = ldexp(k < kb ? x : 0.0, ex == INT_MIN ? 0 : -ex);  // ... and slices zero
-    }
-    for (int t = 0; t < ns; t++) {
-      uint64_t packed = 0;
+    const unsigned n = min((unsigned)TSLICE_CHUNK, tot - (unsigned)I.e0);   // a multiple of 8
+    const unsigned el = 4u * threadIdx.x, e = (unsigned)I.e0 + el;
+    if (el < n) {
+      const unsigned rho = e / len, idx = e - rho * len;
+      const unsigned p = idx / kbp, kk = idx - p * kbp;
+      const double *line = work + J.src_off + (int64_t)rho * J.s_rho + (int64_t)p * J.s_pos;
+      const int ex = bufs.exps[SBUF_T][J.exp_off + rho];
+      double yv[4];
       for (int i = 0; i < 4; i++) {
-        const double a = rint(yv[i] * 256.0);
-        yv[i] = yv[i] * 256.0 - a;
-        const float af = (float)a * digit_weight(t);   // exact in BF16 (see slice_kernel)
-        packed |= (uint64_t)(__float_as_uint(af) >> 16) << (16 * i);
+        const unsigned k = kk + i;
+        const double x = line[(int64_t)min(k, kb - 1) * J.s_k];    // padding reads a valid entry ...
+        yv[i] = ldexp(k < kb ? x : 0.0, ex == INT_MIN ? 0 : -ex);  // ... and slices zero
       }
-      *(uint64_t *)(dst + slice_index(J.dst_off + e, t, ns)) = packed;
+      for (int t = 0; t < ns; t++) {
+        uint64_t packed = 0;
+        for (int i = 0; i < 4; i++) {
+          const double a = rint(yv[i] * 256.0);
+          yv[i] = yv[i] * 256.0 - a;
+          const float af = (float)a * digit_weight(t);   // exact in BF16 (see slice_kernel)
+          packed |= (uint64_t)(__float_as_uint(af) >> 16) << (16 * i);
+        }
+        *(uint64_t *)(out + slice_index(el, t, ns)) = packed;
+      }
     }
+    __syncthreads();
+    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+    v4u *dst = (v4u *)(bufs.data[SBUF_T] + slice_index(J.dst_off + I.e0, 0, ns));
+    for (unsigned u = threadIdx.x; u < n * ns / 8; u += blockDim.x) dst[u] = ((const v4u *)out)[u];
+    __syncthreads();   // out is reused by the next chunk
   }
 }
 
