@@ -291,7 +291,10 @@ enum { DMRG_MLP_IN = 2 };
 int dmrg_mlp_create(int32_t width, uint64_t seed, dmrg_mlp_t **out);
 int64_t dmrg_mlp_num_params(const dmrg_mlp_t *m);
 /* Host <-> device parameter copies of exactly num_params floats; setting the
- * parameters resets the Adam state. */
+ * parameters resets the Adam state.  Both (and dmrg_mlp_free) first wait for
+ * the last dmrg_mlp_forward / dmrg_mlp_adam_step launches of this network,
+ * which return before their work is done (an event on their stream, not a
+ * device-wide synchronisation). */
 int dmrg_mlp_set_params(dmrg_mlp_t *m, const float *host, int64_t n);
 int dmrg_mlp_get_params(const dmrg_mlp_t *m, float *host, int64_t n);
 /* g[i] := network output for row x[i] (device arrays x[n][2], g[n]). */

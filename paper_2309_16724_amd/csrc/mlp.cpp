@@ -98,6 +98,19 @@ int adam(dmrg_mlp *m, const float *grad, float lr, float b1, float b2, float eps
 
 }  // namespace
 
+namespace {
+int mark_done(const dmrg_mlp *m, void *stream) {
+  if (!m->done) HIPCHK(hipEventCreateWithFlags(&m->done, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(m->done, (hipStream_t)stream));
+  m->pending = true;
+  return DMRG_OK;
+}
+void wait_done(const dmrg_mlp *m) {
+  if (m->done && m->pending) (void)hipEventSynchronize(m->done);
+  m->pending = false;
+}
+}  // namespace
+
 extern "C" int dmrg_mlp_create(int32_t width, uint64_t seed, dmrg_mlp_t **out) {
   if (!out) { set_error("null output handle"); return DMRG_EINVAL; }
   *out = nullptr;
@@ -136,6 +149,7 @@ extern "C" int dmrg_mlp_set_params(dmrg_mlp_t *m, const float *host, int64_t n) 
   if (!m || !host || n != m->nparams) { set_error("parameter count mismatch"); return DMRG_EINVAL; }
   for (int64_t i = 0; i < n; i++)
     if (!std::isfinite(host[i])) { set_error("non-finite network parameter"); return DMRG_ENONFINITE; }
+  wait_done(m);
   HIPCHK(hipMemcpy(m->p, host, sizeof(float) * n, hipMemcpyHostToDevice));
   HIPCHK(hipMemset(m->m, 0, sizeof(float) * n));
   HIPCHK(hipMemset(m->v, 0, sizeof(float) * n));
@@ -145,7 +159,7 @@ extern "C" int dmrg_mlp_set_params(dmrg_mlp_t *m, const float *host, int64_t n) 
 
 extern "C" int dmrg_mlp_get_params(const dmrg_mlp_t *m, float *host, int64_t n) {
   if (!m || !host || n != m->nparams) { set_error("parameter count mismatch"); return DMRG_EINVAL; }
-  HIPCHK(hipDeviceSynchronize());
+  wait_done(m);
   HIPCHK(hipMemcpy(host, m->p, sizeof(float) * n, hipMemcpyDeviceToHost));
   return DMRG_OK;
 }
@@ -160,7 +174,7 @@ extern "C" int dmrg_mlp_forward(dmrg_mlp_t *m, const float *x, int64_t n, float 
   A.g = g;
   launch_mlp_forward(m->width, 0, A, stream);
   HIPCHK(hipGetLastError());
-  return DMRG_OK;
+  return mark_done(m, stream);
 }
 
 extern "C" int dmrg_mlp_step(const dmrg_mlp_t *m, const double *diag, const double *r, int32_t nseg,
@@ -239,7 +253,8 @@ extern "C" int dmrg_mlp_adam_step(dmrg_mlp_t *m, const float *grad, float lr, fl
     set_error("bad Adam arguments");
     return DMRG_EINVAL;
   }
-  return adam(m, grad, lr, beta1, beta2, eps, stream);
+  int rc = adam(m, grad, lr, beta1, beta2, eps, stream);
+  return rc ? rc : mark_done(m, stream);
 }
 
 extern "C" int dmrg_mlp_train(dmrg_mlp_t *m, const float *x, const float *a, const float *b, int64_t n,
@@ -266,7 +281,8 @@ extern "C" int dmrg_mlp_train(dmrg_mlp_t *m, const float *x, const float *a, con
 
 extern "C" void dmrg_mlp_free(dmrg_mlp_t *m) {
   if (!m) return;
-  (void)hipDeviceSynchronize();
+  wait_done(m);
+  if (m->done) (void)hipEventDestroy(m->done);
   release_scratch(m);
   for (void *q : {(void *)m->p, (void *)m->m, (void *)m->v, (void *)m->grad})
     if (q) (void)hipFree(q);

@@ -50,4 +50,9 @@ struct dmrg_mlp {
   float *xb = nullptr, *ab = nullptr, *bb = nullptr, *g = nullptr, *dg = nullptr;
   float *z1 = nullptr, *z2 = nullptr, *dz2 = nullptr, *dz1 = nullptr;
   double *lpart = nullptr;
+  // completion of the last launch sequence of the entry points that return
+  // before their work is done (forward, step, adam_step): reading or freeing
+  // the parameters waits for it instead of for the whole device
+  mutable hipEvent_t done = nullptr;
+  mutable bool pending = false;
 };
