@@ -105,7 +105,7 @@ enum { DMRG_FP64 = 0, DMRG_SPLIT_BF16 = 1 };
  *    settings -- kpart in {1024, 2048, 4096} x tile_policy in {0, 1}, then
  *    for split plans the work-group tile threshold (macro_min) in
  *    {none, 32, 48, 96} at the best of those and the wide tile threshold
- *    (wide_min) in {none, 96, 192}, then workspace caps of 512 MiB and
+ *    (wide_min) in {none, 48, 96, 192}, then workspace caps of 512 MiB and
  *    192 MiB -- and keeps the fastest; choices are cached by a hash of the
  *    plan's block shapes and options, for the process and in opts.tune_cache.
  *    The chosen values are in dmrg_plan_stats.
@@ -125,9 +125,11 @@ typedef struct {
                                computed in 64x64 tiles by whole work groups
                                sharing LDS-staged operands (0: 48; < 0: never) */
   int32_t wide_min;         /* split plans with n_slices <= 5: outputs with both
-                               sides >= this are cut into 128x128 tiles of one
-                               work group each (one per CU), the rest of them
-                               into the tiles above (0: 96; < 0: never)     */
+                               sides >= this are cut into 128-wide bands (a
+                               last band of >= this many lines included) of
+                               128x128 tiles of one work group each (one per
+                               CU), the rest of them into the tiles above
+                               (0: 48; < 0: never)                          */
   int32_t pad_opts;
   /* Device memory of the plan (descriptors, operator copies, slices,
    * workspace), of the autotuner and of dmrg_davidson / dmrg_mlp_collect on

@@ -267,7 +267,7 @@ bool use_wide(const dmrg_plan *P, int m, int n) {
 
 // Tiles of an m x n output (top-left corner and kind mb).  Outputs that take
 // wide tiles are cut into 128-wide row and column bands (a last band of at
-// least WIDE_TAIL lines is wide too): the wide x wide cells in patch order,
+// least wide_min lines is wide too): the wide x wide cells in patch order,
 // then the rest of the output -- the columns beyond the wide bands next to
 // them, then the rows below -- in tiles chosen for those strips.  Other
 // outputs get one kind of tile in patch order.
@@ -285,7 +285,8 @@ std::vector<Cell> output_cells(const dmrg_plan *P, int m, int n) {
     grid(0, 0, m, n);
     return v;
   }
-  auto bands = [](int len) { return len / WIDE_EDGE + (len % WIDE_EDGE >= WIDE_TAIL ? 1 : 0); };
+  const int tail = std::min(P->wide_min, WIDE_EDGE);
+  auto bands = [&](int len) { return len / WIDE_EDGE + (len % WIDE_EDGE >= tail ? 1 : 0); };
   const int nr = bands(m), nc = bands(n);
   const int mw = std::min(m, nr * WIDE_EDGE), nw = std::min(n, nc * WIDE_EDGE);
   for (const auto &c : patch_order(nr, nc)) v.push_back({c.first * WIDE_EDGE, c.second * WIDE_EDGE, WIDE_MB});
@@ -1217,7 +1218,7 @@ int autotune(dmrg_plan *P, void *stream) {
       if (mm != mm0) trial({b0[0], b0[1], base, mm, b0[4]});
     if (P->n_slices <= WIDE_MAX_SLICES) {
       const TuneChoice b2 = bc;
-      for (int wm : {0, 96, 192})
+      for (int wm : {0, 48, 96, 192})
         if (wm != wm0) trial({b2[0], b2[1], base, b2[3], wm});
     }
   }

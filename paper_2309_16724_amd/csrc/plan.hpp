@@ -32,12 +32,11 @@ constexpr int MACRO_MIN = 48;   // default: outputs with both dims >= 48 get wor
 // computed by the eight wavefronts of a work group (two per SIMD, 32 x 64
 // each, v_mfma_f32_32x32x16_bf16) from two 80 KiB LDS stages.  An
 // output with both sides >= wide_min is cut into 128-wide bands (a last band
-// of >= WIDE_TAIL lines is a wide band too); the rest of it gets 64 x 64 or
+// of >= wide_min lines is a wide band too); the rest of it gets 64 x 64 or
 // wavefront tiles.
 constexpr int WIDE_MB = 16;
 constexpr int WIDE_EDGE = 128;
-constexpr int WIDE_MIN = 96;
-constexpr int WIDE_TAIL = 96;
+constexpr int WIDE_MIN = 48;
 constexpr int WIDE_WAVES = 8;
 constexpr int WIDE_MAX_SLICES = 5;
 constexpr int tile_rows(int mb) { return mb == WIDE_MB ? WIDE_EDGE : mb == MACRO_MB ? MACRO_EDGE : 16 * mb; }

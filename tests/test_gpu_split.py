@@ -117,28 +117,31 @@ def test_workgroup_tiles_match_oracle_and_emulation(torch, ns):
 
 @pytest.mark.parametrize("ns", [3, 4, 5])
 def test_wide_tiles_match_oracle(torch, ns):
-    """Outputs of 96 and more on both sides go to 128 x 128 wide tiles (eight
-    wavefronts, v_mfma_f32_32x32x16_bf16, two LDS stages as separate
-    objects): a 212-row output as one wide band plus 64-row tiles, 106-line
-    outputs as partial wide bands, split K (kpart 256) and whole segments;
-    against the oracle and the same plan without wide tiles (wide_min < 0)
-    and without any work-group tiles."""
+    """Outputs of wide_min and more on both sides go to 128 x 128 wide tiles
+    (eight wavefronts, v_mfma_f32_32x32x16_bf16, two LDS stages as separate
+    objects).  With wide_min = 96: a 212-row output as one wide band plus
+    64-row tiles, 106-line outputs as partial wide bands; with the default
+    (48): partial bands down to 48 lines.  Split K (kpart 256) and whole
+    segments; against the oracle and the same plan without wide tiles
+    (wide_min < 0) and without any work-group tiles."""
     from oracle.hpsi import HEff
     from paper_2309_16724_amd import binding as B
     prob = random_problem(6, 6, 0, 1, D=500, D_right=250, cap=False)
-    kinds = set(B.debug_plan_tiles(prob, 2, precision=1, n_slices=ns)[:, 6])
+    kinds = set(B.debug_plan_tiles(prob, 2, precision=1, n_slices=ns, wide_min=96)[:, 6])
     assert 16 in kinds and 8 in kinds
     he = HEff(prob)
     x = np.random.default_rng(7).standard_normal(he.size)
     ref = he.apply(x)
     for kp in (0, 256):
         _say("  wide s=%d kpart=%d" % (ns, kp))
-        y = _apply(torch, prob, x, precision=1, n_slices=ns, kpart=kp)
         yn = _apply(torch, prob, x, precision=1, n_slices=ns, kpart=kp, wide_min=-1)
         yw = _apply(torch, prob, x, precision=1, n_slices=ns, kpart=kp, wide_min=-1, macro_min=-1)
-        err = np.abs(y - ref).max() / np.abs(ref).max()
-        dn = np.abs(y - yn).max() / np.abs(yn).max()
-        dw = np.abs(y - yw).max() / np.abs(yw).max()
-        _say("    rel err %.3e vs oracle, %.3e vs 64x64 tiles, %.3e vs wavefront tiles" % (err, dn, dw))
-        assert err <= BOUND[ns]
-        assert dn <= TILE_TOL[ns] and dw <= TILE_TOL[ns]
+        for wm in (96, 0):
+            y = _apply(torch, prob, x, precision=1, n_slices=ns, kpart=kp, wide_min=wm)
+            err = np.abs(y - ref).max() / np.abs(ref).max()
+            dn = np.abs(y - yn).max() / np.abs(yn).max()
+            dw = np.abs(y - yw).max() / np.abs(yw).max()
+            _say("    wide_min %d: rel err %.3e vs oracle, %.3e vs 64x64 tiles, %.3e vs wavefront tiles"
+                 % (wm, err, dn, dw))
+            assert err <= BOUND[ns]
+            assert dn <= TILE_TOL[ns] and dw <= TILE_TOL[ns]

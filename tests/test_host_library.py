@@ -254,25 +254,30 @@ def test_wigner_tables_at_large_block_spins(lib):
 
 
 def test_wide_tile_cells_cover_every_output_once(lib):
-    """Split plans with s <= 5 cut outputs of 96 and more on both sides into
-    128 x 128 work-group tiles, a last band of >= 96 lines being a partial
-    wide band, and cover the rest with 64 x 64 or wavefront tiles.  Summed
-    over the tiles, 2 (tile rows) (tile columns) K must equal each stage's
-    algorithmic flops (no gap, no overlap); a 212-row output takes one wide
-    band plus 64-row tiles, a 106-column one a partial wide band."""
+    """Split plans with s <= 5 cut outputs of wide_min and more on both sides
+    into 128 x 128 work-group tiles, a last band of >= wide_min lines being a
+    partial wide band, and cover the rest with 64 x 64 or wavefront tiles.
+    Summed over the tiles, 2 (tile rows) (tile columns) K must equal each
+    stage's algorithmic flops (no gap, no overlap); with wide_min = 96 a
+    212-row output takes one wide band plus 64-row tiles, a 106-column one a
+    partial wide band; with the default (48) the 212-row output is two wide
+    bands."""
     prob = random_problem(6, 6, 0, 1, D=500, D_right=250, cap=False)
     _, st = B.debug_plan_host_apply(prob, None, precision=1, n_slices=5, lib=lib)
     for stage, key in ((1, "stage1_flops"), (2, "stage2_flops")):
-        T = B.debug_plan_tiles(prob, stage, lib=lib, precision=1, n_slices=5)
+        T = B.debug_plan_tiles(prob, stage, lib=lib, precision=1, n_slices=5, wide_min=96)
         assert (2.0 * T[:, 0] * T[:, 1] * T[:, 3]).sum() == st[key]
         wide = T[T[:, 6] == 16]
         assert len(wide) > 0
         assert wide[:, :2].max() == 128 and wide[:, :2].min() >= 96
         assert (T[:, 0] <= np.where(T[:, 6] == 16, 128, 64)).all()
-    T2 = B.debug_plan_tiles(prob, 2, lib=lib, precision=1, n_slices=5)
+    T2 = B.debug_plan_tiles(prob, 2, lib=lib, precision=1, n_slices=5, wide_min=96)
     mixed = T2[T2[:, 4] == 212]
     assert set(mixed[:, 6]) >= {16, 8}
     assert (T2[(T2[:, 6] == 16) & (T2[:, 5] == 106)][:, 1] == 106).all()
+    T2d = B.debug_plan_tiles(prob, 2, lib=lib, precision=1, n_slices=5)
+    assert set(T2d[(T2d[:, 4] == 212) & (T2d[:, 5] >= 48)][:, 6]) == {16}
+    assert (2.0 * T2d[:, 0] * T2d[:, 1] * T2d[:, 3]).sum() == st["stage2_flops"]
     for kw in (dict(precision=1, n_slices=6), dict(precision=1, n_slices=5, wide_min=-1), dict()):
         T = B.debug_plan_tiles(prob, 2, lib=lib, **kw)
         assert not (T[:, 6] == 16).any()
