@@ -127,17 +127,19 @@ def cpu_baseline(flops_bench, bench_workload):
     }
 
 
-# HBM bytes per launch of the dominant stage kernels at L24_D512 from the
-# FETCH_SIZE and WRITE_SIZE runs summarised in profiles/hpsi_L24_D512_split5.md
-# and profiles/hpsi_L24_D512_fp64.md: FETCH scaled by 2.000 and WRITE by 1.000,
-# what the same counters read for a plain 256 MiB device copy and fill in the
-# same runs.  A figure holds only while the sources that decide the kernel's
-# memory traffic are the ones it was taken on (their hash); else null.
+# HBM bytes per launch of the stage kernels at L54_D2048 from the FETCH_SIZE
+# and WRITE_SIZE runs summarised in profiles/hpsi_L54_D2048_split5.md and
+# profiles/hpsi_L54_D2048_fp64.md: FETCH scaled by 2.000 and WRITE by 1.000,
+# what the same counters read for a plain 256 MiB device copy in the same
+# runs.  A figure holds only while the sources that decide the kernel's memory
+# traffic are the ones it was taken on (their hash); else null.
+_SPLIT_SRC = ("kernels_split.hip", "plan.cpp", "plan.hpp", "model.cpp")
+_F64_SRC = ("kernels_f64.hip", "plan.cpp", "plan.hpp", "model.cpp")
 MEASURED_TRAFFIC = {
-    ("L24_D512", "stage2_split5_kernel"):
-        (1.1229e10, ("kernels_split.hip", "plan.cpp", "plan.hpp", "model.cpp"), "f37f097fc51fca79"),
-    ("L24_D512", "stage_f64_kernel<2>"):
-        (9.7688e9, ("kernels_f64.hip", "plan.cpp", "plan.hpp", "model.cpp"), "6845b5fd10cebf51"),
+    ("L54_D2048", "stage1_wsplit5_kernel"): (1.6826e11, _SPLIT_SRC, "fd14f25f69d6d718"),
+    ("L54_D2048", "stage2_wsplit5_kernel"): (2.2778e11, _SPLIT_SRC, "fd14f25f69d6d718"),
+    ("L54_D2048", "stage_f64_kernel<1>"): (3.5086e11, _F64_SRC, "69c8d5cbc4f75ca9"),
+    ("L54_D2048", "stage_f64_kernel<2>"): (1.0639e12, _F64_SRC, "69c8d5cbc4f75ca9"),
 }
 
 
