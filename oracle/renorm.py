@@ -1,0 +1,298 @@
+"""Renormalization of the left block through the left site (oracle).
+
+TEST INFRASTRUCTURE ONLY (see the package header).
+
+After a two-site step the left block L = [0, p) and the site p are merged
+into the block L' = [0, p + 1) of the next bond (Sec. I: renormalized block
+operators are formed during the network contraction; Sec. II C: block x site
+tensor products whose SU(2) factors come from W9j^(l)).  A basis of L' is
+given per (N, 2S) sector by a matrix U whose rows index the coupled product
+states ((L S_L) x (l s)) S and whose columns are the kept states; every
+operator of L' is O' = U^T <product-basis reduced matrix of O> U.
+
+This module computes that definition directly, without 6j/9j recoupling:
+
+1. the M-resolved product space of L x l is built from the M-resolved
+   groups of L (Wigner-Eckart expansion of its stored reduced blocks) and
+   the four Fock states of the site; a site operator acting on
+   |L string>|site string> picks up (-1)^(parity * N_L);
+2. every operator of L' is written as a sum of products of L operators and
+   site operators in that space: members with all labels in L are the
+   stored L members (times the site identity); members with a label p are
+   products of single creation/annihilation operators; the block
+   Hamiltonian of L' is H restricted to the orbitals [0, p], with the terms
+   that have two or more indices in L taken from the stored complementary
+   operators S_p, P_pp, Q_pp of L (definitions in
+   paper_2309_16724_amd.synth.catalogue) and the rest explicit;
+3. the coupled kept states of L' are formed with Clebsch-Gordan coefficients
+   and U, and reduced elements are read off by the Wigner-Eckart theorem.
+
+Layout of the product basis of L' (a convention of the interface): its
+sectors are the reachable (N, 2S) pairs in ascending order; the rows of a
+sector are made of components (L sector a, site multiplet m) in the order a
+ascending, then m = 0 (empty), 1 (one electron), 2 (doubly occupied), each
+contributing d_a consecutive rows in the order of the L sector's states.
+
+Families produced: H, C, A0, A1, B0, B1 of the left block at bond p + 1.
+Pinned in tests/test_oracle_renorm.py against the same families built
+directly in the Fock space of the enlarged block (untruncated and
+truncated), against U = identity invariants and against hermiticity.
+"""
+import numpy as np
+
+from paper_2309_16724_amd.synth import catalogue as cat
+from paper_2309_16724_amd.synth.problem import BlockData
+from .wigner import cg
+from .hpsi import MBlock, Factors, SITE_N, SITE_2M, SITE_MULT_STATES, site_cre, site_ann
+from .layout import SITE
+
+RENORM_FAMILIES = (cat.H, cat.C, cat.A0, cat.A1, cat.B0, cat.B1)
+
+
+def product_sectors(lsec):
+    """[(N, 2S, rows, [(iL, site multiplet, row0, d)])] of L x l, (N, 2S) ascending."""
+    comps = {}
+    for iL, (N, S, d) in enumerate(lsec):
+        for m, (n, s) in enumerate(SITE):
+            for S2 in range(abs(S - s), S + s + 1, 2):
+                comps.setdefault((N + n, S2), []).append((iL, m, d))
+    out = []
+    for key in sorted(comps):
+        rows, lst = 0, []
+        for iL, m, d in comps[key]:
+            lst.append((iL, m, rows, d))
+            rows += d
+        out.append((key[0], key[1], rows, lst))
+    return out
+
+
+class _ProductSpace:
+    """M-resolved L x l space: index 4 * xL + f (xL an M-resolved L state,
+    f a site Fock state)."""
+
+    def __init__(self, blk):
+        self.mL = MBlock(blk)
+        self.fL = Factors(self.mL)
+        self.goff, n = {}, 0
+        for g in sorted(self.mL.gdim):
+            self.goff[g] = n
+            n += self.mL.gdim[g]
+        self.nL = n
+        nel = np.zeros(n, dtype=np.int64)
+        for g, o in self.goff.items():
+            nel[o:o + self.mL.gdim[g]] = g[0]
+        self.jw = np.where(nel % 2 == 1, -1.0, 1.0)     # (-1)^N_L per L state
+        self.dim = 4 * n
+
+    def dense_L(self, op):
+        m = np.zeros((self.nL, self.nL))
+        for (g2, g), blk in op.items():
+            o2, o = self.goff[g2], self.goff[g]
+            m[o2:o2 + blk.shape[0], o:o + blk.shape[1]] += blk
+        return m
+
+    def index_L(self, sec, M2, mu):
+        g, o = self.mL.gidx[(sec, M2)]
+        return self.goff[g] + o + mu
+
+    def product(self, coef, factors):
+        """Matrix of coef * (product of factors); factors are (part, op, parity)
+        with part 0 (L, op a {(g', g): matrix} dict) or 1 (site, 4 x 4)."""
+        sign = 1.0
+        for i in range(len(factors)):
+            for j in range(i + 1, len(factors)):
+                if factors[i][0] > factors[j][0] and factors[i][2] and factors[j][2]:
+                    sign = -sign
+        OL, Ol, par = None, np.eye(4), 0
+        for pt, op, pa in sorted(factors, key=lambda f: f[0]):
+            if pt == 0:
+                assert OL is None, "one L factor per product"
+                OL = self.dense_L(op)
+            else:
+                Ol = Ol @ op
+                par ^= pa
+        if OL is None:
+            OL = np.eye(self.nL)
+        if par:
+            OL = OL * self.jw[None, :]
+        return (coef * sign) * np.kron(OL, Ol)
+
+
+def _h_terms(ps, p, h, eri):
+    """H restricted to orbitals [0, p]: (coefficient, factors) pairs."""
+    fL, mL = ps.fL, ps.mL
+    spins = (1, -1)
+
+    def single(x, s2, dagger):
+        if x < p:
+            return (0, fL.cre(x, s2, 0) if dagger else fL.T("cre", x, s2, 0), 1)
+        return (1, site_cre(s2) if dagger else site_ann(s2), 1)
+
+    yield 1.0, [(0, mL.tensor(cat.H, 0, 0), 0)]
+    # three indices in L: sum_s a+_ps (S_p)_s + h.c.
+    for s in spins:
+        yield 1.0, [single(p, s, True), (0, fL.S(p, s, 0), 1)]
+        yield 1.0, [(0, fL.T("S", p, s, 0), 1), single(p, s, False)]
+    # two indices in L, two at p: 1/2 sum a+_ps a+_pt (P_pp)_ts + h.c.; sum (Q_pp)_ts a+_pt a_ps
+    for s in spins:
+        for t in spins:
+            yield 0.5, [single(p, s, True), single(p, t, True), (0, fL.P(p, p, t, s, 0), 0)]
+            yield 0.5, [(0, fL.T("P", p, p, t, s, 0), 0), single(p, t, False), single(p, s, False)]
+            yield 1.0, [(0, fL.Q(p, p, t, s, 0), 0), single(p, t, True), single(p, s, False)]
+    # at most one index in L, the others at p
+    idx = range(p + 1)
+    nl = lambda t: sum(1 for i in t if i < p)
+    for i in idx:
+        for j in idx:
+            if nl((i, j)) > 1 or h[i, j] == 0.0:
+                continue
+            for s in spins:
+                yield h[i, j], [single(i, s, True), single(j, s, False)]
+    for i in idx:
+        for j in idx:
+            for k in idx:
+                for l in idx:
+                    if nl((i, j, k, l)) > 1 or eri[i, j, k, l] == 0.0:
+                        continue
+                    for s in spins:
+                        for t in spins:
+                            if (i == k or j == l) and s == t:
+                                continue
+                            yield 0.5 * eri[i, j, k, l], [single(i, s, True), single(k, t, True),
+                                                          single(l, t, False), single(j, s, False)]
+
+
+def _target(ps, fam, lab, q, p, h, eri):
+    """Component q of one family member of L' as a product-space matrix."""
+    fL, mL = ps.fL, ps.mL
+    if fam == cat.H:
+        acc = np.zeros((ps.dim, ps.dim))
+        for coef, fs in _h_terms(ps, p, h, eri):
+            acc += ps.product(coef, fs)
+        return acc
+    if all(x < p for x in lab):          # member of L itself, times the site identity
+        return ps.product(1.0, [(0, mL.tensor(fam, mL.pos(fam, lab), q), cat.TWO_K[fam] % 2)])
+
+    def single(x, s2, dagger):
+        if x < p:
+            return (0, fL.cre(x, s2, 0) if dagger else fL.T("cre", x, s2, 0), 1)
+        return (1, site_cre(s2) if dagger else site_ann(s2), 1)
+
+    if fam == cat.C:
+        return ps.product(1.0, [single(lab[0], q, True)])
+    K = 0 if fam in (cat.A0, cat.B0) else 2
+    i, j = lab
+    acc = np.zeros((ps.dim, ps.dim))
+    for s in (1, -1):
+        t = q - s
+        if abs(t) != 1:
+            continue
+        c = cg(1, s, 1, t, K, q)
+        if c == 0.0:
+            continue
+        if fam in (cat.A0, cat.A1):
+            acc += ps.product(c, [single(i, s, True), single(j, t, True)])
+        else:   # a~_{j t} = (-1)^(1/2 - t) a_{j, -t}
+            ph = -1.0 if ((1 - t) // 2) % 2 else 1.0
+            acc += ps.product(c * ph, [single(i, s, True), single(j, -t, False)])
+    return acc
+
+
+def _coupled(ps, lsec, comps, U, two_s, M2):
+    """Product-space vectors of the kept states of one L' sector at projection M2."""
+    V = np.zeros((ps.dim, U.shape[1]))
+    for (iL, m, row0, d) in comps:
+        S = lsec[iL][1]
+        s = SITE[m][1]
+        for ms, f in SITE_MULT_STATES[m].items():
+            ML = M2 - ms
+            if abs(ML) > S or (S - ML) % 2:
+                continue
+            c = cg(S, ML, s, ms, two_s, M2)
+            if c == 0.0:
+                continue
+            for mu in range(d):
+                V[4 * ps.index_L(iL, ML, mu) + f, :] += c * U[row0 + mu, :]
+    return V
+
+
+def renormalize(prob, keep, families=RENORM_FAMILIES):
+    """Operators of the enlarged left block [0, p + 1).
+
+    prob: a Problem whose left block and integrals are used (p = prob.p >= 1).
+    keep: list of (N, 2S, U) with U a [rows of that product sector, kept]
+    array; sectors not listed are dropped.  Returns a BlockData (role "L",
+    bond p + 1) whose sectors are (N, 2S, kept) in the order of ``keep`` and
+    whose records hold the requested families (blocks that are zero to
+    1e-13 are left out)."""
+    blk, p = prob.left, prob.p
+    assert p >= 1
+    ps = _ProductSpace(blk)
+    lsec = blk.sectors
+    prod = {(N, S): comps for (N, S, rows, comps) in product_sectors(lsec)}
+    sectors, kinfo = [], []
+    for (N, S, U) in keep:
+        comps = prod[(N, S)]
+        U = np.asarray(U, dtype=float)
+        assert U.shape[0] == sum(c[3] for c in comps)
+        sectors.append((N, S, U.shape[1]))
+        kinfo.append((comps, U))
+    cache = {}
+
+    def vec(i, M2):
+        key = (i, M2)
+        if key not in cache:
+            comps, U = kinfo[i]
+            cache[key] = _coupled(ps, lsec, comps, U, sectors[i][1], M2)
+        return cache[key]
+
+    out = BlockData("L", prob.n_orb, p + 1, sectors)
+    fam_blocks = {}
+    for fam in families:
+        labs = cat.labels(fam, "L", prob.n_orb, p + 1)
+        k2 = cat.TWO_K[fam]
+        per = []
+        for lab in labs:
+            comp = {q: _target(ps, fam, lab, q, p, prob.h, prob.eri) for q in range(-k2, k2 + 1, 2)}
+            red = {}
+            for a, (Na, Sa, da) in enumerate(sectors):
+                for b, (Nb, Sb, db) in enumerate(sectors):
+                    if Nb != Na + cat.DN[fam] or not (abs(Sa - k2) <= Sb <= Sa + k2):
+                        continue
+                    best = None
+                    for q in range(-k2, k2 + 1, 2):
+                        ma = Sb - q
+                        if abs(ma) > Sa:
+                            continue
+                        c = cg(Sa, ma, k2, q, Sb, Sb)
+                        if c != 0.0 and (best is None or abs(c) > abs(best[0])):
+                            best = (c, q, ma)
+                    if best is None:
+                        continue
+                    c, q, ma = best
+                    m = vec(b, Sb).T @ comp[q] @ vec(a, ma) / c
+                    if np.abs(m).max() > 1e-13:
+                        red[(b, a)] = m
+            per.append(red)
+        keys = sorted({k for d in per for k in d})
+        if not keys:
+            continue
+        fb = {}
+        for (b, a) in keys:
+            arr = np.zeros((len(per), sectors[b][2], sectors[a][2]))
+            for i, d in enumerate(per):
+                if (b, a) in d:
+                    arr[i] = d[(b, a)]
+            fb[(b, a)] = arr
+        fam_blocks[fam] = fb
+    recs, chunks, off = [], [], 0
+    for fam in sorted(fam_blocks):
+        for (r, c) in sorted(fam_blocks[fam]):
+            arr = fam_blocks[fam][(r, c)]
+            flat = np.ascontiguousarray(arr.transpose(0, 2, 1)).reshape(-1)
+            recs.append((fam, r, c, off, arr.shape[0]))
+            chunks.append(flat)
+            off += flat.size
+    out.records = recs
+    out.data = np.concatenate(chunks) if chunks else np.zeros(0)
+    return out
