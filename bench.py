@@ -412,6 +412,61 @@ def davidson_runs(torch, args, plan_flags):
     return out
 
 
+def renorm_run(torch, prob, steps, warmup):
+    """Renormalization of the workload's left block through its left site
+    (families H, C, A0, A1, B0, B1 of the enlarged block, FP64): every product
+    sector keeps a quarter of its rows (about D states in all) through a U
+    with orthonormal columns (QR of a seeded Gaussian matrix).  Timed like
+    H.psi: warm-up, then `steps` applies bracketed by synchronisation."""
+    import numpy as np
+    from paper_2309_16724_amd import binding as B
+    from paper_2309_16724_amd.hpsi import Renorm
+    secs, _ = B.renorm_product(prob)
+    rng = np.random.default_rng(7)
+    keep = [(n, s2, np.linalg.qr(rng.standard_normal((rows, max(1, rows // 4))))[0]) for (n, s2, rows) in secs]
+    t0 = time.time()
+    r = Renorm(prob, keep)
+    st = r.stats()
+    print("# renormalization lists built in %.1f s: %s" % (time.time() - t0, json.dumps(st)), file=sys.stderr,
+          flush=True)
+    for _ in range(warmup):
+        r.apply()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        r.apply()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t1) * 1e3 / steps
+    first = r.out.clone()
+    r.apply()
+    torch.cuda.synchronize()
+    repro = bool(torch.equal(first, r.out))
+    del first
+    # H of the new block is a scalar: diagonal sector blocks only, symmetric
+    asym, nh = 0.0, 0
+    for rec in r.recs[:r.n_rec]:
+        if rec.fam != 0:
+            continue
+        n = keep[rec.row_sec][2].shape[1]
+        m = r.out[rec.off:rec.off + n * n].view(n, n)
+        asym = max(asym, float((m - m.T).abs().max() / max(float(m.abs().max()), 1e-300)))
+        nh += 1
+    flops = st["flops1"] + st["flops2"]
+    tf = flops / (ms * 1e-3) / 1e12
+    r.free()
+    return {"ms": ms, "tflops": tf, "flops": flops, "flops_stage1": st["flops1"], "flops_stage2": st["flops2"],
+            "kept_states": int(sum(u.shape[1] for _, _, u in keep)),
+            "product_states": int(sum(u.shape[0] for _, _, u in keep)),
+            "families": "H C A0 A1 B0 B1", "records": r.n_rec, "out_elems": st["out_elems"],
+            "terms": st["n_terms"], "products": [st["n_products1"], st["n_products2"]],
+            "tiles": [st["n_tiles1"], st["n_tiles2"]], "build_ms": st["build_ms"],
+            "bitwise_repeat": repro, "h_blocks": nh, "h_asymmetry": asym,
+            "roofline": {"bound": "mfma", "kernel": "stage_f64_kernel<1>, <2> (both launches)",
+                         "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tf / FP64_PEAK_TFLOPS, "traffic": None,
+                         "note": "time of dmrg_renorm_apply: output clear and the two product launches"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -441,6 +496,9 @@ def main():
                     help="instead of the single workload, time H.psi of a batch of this many "
                          "uneven problems (L in [16, 32], D in [128, 768], S in {0, 1})")
     ap.add_argument("--no-autotune", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--no-renorm", action="store_true", help="skip the renormalization leg")
+    ap.add_argument("--renorm-only", action="store_true",
+                    help="time only the renormalization of the workload's left block (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -478,6 +536,10 @@ def main():
         del x, y
         return st, ms, prof, yv
 
+    if args.renorm_only:
+        print(json.dumps({"renorm_only": True, "workload": args.workload,
+                          **renorm_run(torch, prob, args.steps, args.warmup)}), flush=True)
+        return
     if args.hpsi_only:
         ref = torch.empty(32 << 20, dtype=torch.float64, device="cuda")   # 256 MiB
         ref2 = torch.empty_like(ref)
@@ -498,6 +560,11 @@ def main():
     err5 = sampled_errors(y5, args.workload, prob)
     rel = float(np.abs(y5 - y64).max() / np.abs(y64).max())
     del y5, y64
+    ren = None
+    if not args.no_renorm:
+        ren = renorm_run(torch, prob, args.steps, args.warmup)
+        ren["workload"] = "%s left block (orbitals 0..%d) x site %d" % (args.workload, prob.p - 1, prob.p)
+        print("# renormalization: %s" % json.dumps(ren), file=sys.stderr, flush=True)
     dav = None
     if not args.no_davidson:
         dav = davidson_runs(torch, args, plan_flags)
@@ -541,6 +608,7 @@ def main():
                  "stages_ms_per_step": {str(k): v[1] / args.steps for k, v in prof64.items()}},
         "speedup_split_vs_fp64": ms64 / ms5,
         "davidson": dav,
+        "renormalization": ren,
         "split_stages_ms_per_step": {str(k): v[1] / args.steps for k, v in prof5.items()},
         "roofline": {"bound": "mfma", "kernel": kname5,
                      "achieved": achieved, "peak": split_peak, "unit": "TFLOP/s",

@@ -359,6 +359,74 @@ int dmrg_get_profile(dmrg_plan_t *p, int32_t stage, int64_t *n_launches, double 
 void dmrg_plan_free(dmrg_plan_t *p);
 const char *dmrg_last_error(void);
 
+/* ---- renormalization of the left block through the left site ----------
+ * After a two-site step the left block [0, l) and the site l merge into the
+ * block [0, l] of the next bond (Sec. I: renormalized block operators are
+ * formed during the contraction; Sec. II C: block x site tensor products,
+ * each sector product scaled by the Eq. (4) factor C~ -- the W9j(l) role --
+ * followed by the truncation).  The problem's left block (sectors, records,
+ * DEVICE data), site_l, n_orb and integrals are the input; site_l >= 1.
+ *
+ * Product basis: the sectors of (left block) x (site) are the reachable
+ * (N, 2S) pairs in ascending order; the rows of one are components
+ * (left sector a, site multiplet m) in the order a ascending, then m = 0, 1,
+ * 2, each d_a consecutive rows in the order of sector a's states
+ * (dmrg_renorm_product lists them).  The caller keeps, per chosen product
+ * sector, `kept` states given by a column-major rows x kept matrix U at
+ * u_off of one DEVICE array (orthonormal columns in a DMRG sweep; any matrix
+ * is accepted).  The new block's sectors are the keep entries, in their
+ * order: (n, two_s, kept).
+ *
+ * Output: the families H, C, A0, A1, B0, B1 of the new block (labels of a left
+ * block at bond site_l + 1), as records in the input format -- one per
+ * (family, row sector, column sector) with any contribution, all positions,
+ * [npos][kept_row][kept_col] column-major -- in a caller-owned DEVICE array
+ * of data_len elements.  Members of the new block whose labels lie in the
+ * old one are [A (x) 1]; members with the label l are products of single
+ * creation/annihilation operators; H is the Hamiltonian restricted to
+ * [0, l], with the parts of two or more indices in the old block taken from
+ * its S_l, P_ll and Q_ll.  S, P and Q of the new block are not produced (they
+ * need complementary operators of the old block for every outside pair;
+ * the H.psi input keeps only the pairs touching the two sites): a fam_mask
+ * naming them is DMRG_EINVAL.
+ *
+ * dmrg_renorm_create builds the term and product lists on the host and
+ * copies them to the device (hipMalloc, freed by dmrg_renorm_free); the
+ * left data pointer is kept until then.  dmrg_renorm_apply runs the two
+ * FP64 product stages of the H.psi engine on `stream` (T = op(A) U rows,
+ * then new = sum coef U^T T per output tile in a fixed order: bitwise
+ * reproducible) and returns before they finish.  Errors: DMRG_EINVAL
+ * (arguments, families), DMRG_ESYM (a kept (N, 2S) that is no product
+ * sector), DMRG_ERANGE (U beyond u_len, outputs too small), DMRG_ENONFINITE
+ * (integrals), DMRG_ENOMEM, DMRG_EHIP. */
+typedef struct { int32_t n, two_s, kept, pad; int64_t u_off; } dmrg_rkeep_t;
+typedef struct { int32_t sec, l_sec, site, row0, dim, pad; } dmrg_rcomp_t;
+typedef struct dmrg_renorm dmrg_renorm_t;
+typedef struct {
+  int64_t n_terms;       /* coupled terms alpha [A (x) B]^K over all members */
+  int64_t n_products1;   /* first-stage products op(A) U_rows               */
+  int64_t n_products2;   /* second-stage products coef U_rows^T T           */
+  int64_t n_tiles1, n_tiles2;
+  int64_t work_elems;    /* first-stage workspace (doubles)                  */
+  int64_t out_elems;     /* = data_len                                       */
+  int64_t n_records;     /* output records                                   */
+  double flops1, flops2; /* algorithmic 2mnk of the two stages               */
+  double build_ms;
+} dmrg_renorm_stats_t;
+/* Sectors (n, two_s, rows) and components of the product basis.  Either
+ * output may be NULL (counts only); DMRG_ERANGE when a capacity is short. */
+int dmrg_renorm_product(const dmrg_problem_t *prob, dmrg_sector_t *sec, int32_t sec_cap, int32_t *n_sec,
+                        dmrg_rcomp_t *comp, int32_t comp_cap, int32_t *n_comp);
+/* fam_mask: bit f for family f (0 = H, C, A0, A1, B0, B1); u_len: elements of
+ * the U array that dmrg_renorm_apply will be given. */
+int dmrg_renorm_create(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int32_t n_keep, int32_t fam_mask,
+                       int64_t u_len, dmrg_renorm_t **out);
+/* Output records (rec may be NULL to size) and the output length. */
+int dmrg_renorm_records(const dmrg_renorm_t *r, dmrg_oprec_t *rec, int64_t cap, int64_t *n_rec, int64_t *data_len);
+int dmrg_renorm_apply(dmrg_renorm_t *r, const double *u, double *out, void *stream);
+int dmrg_renorm_stats(const dmrg_renorm_t *r, dmrg_renorm_stats_t *st);
+void dmrg_renorm_free(dmrg_renorm_t *r);
+
 /* ---- host-logic inspection (no GPU use; for tests of the host tables) ---- */
 /* Wigner 6j {a b c; d e f}, 9j and the Eq. (4) factor, doubled spins.       */
 double dmrg_wigner_6j(int a, int b, int c, int d, int e, int f);
@@ -383,6 +451,13 @@ int dmrg_debug_plan_host_apply(const dmrg_problem_t *prob, const double *psi, do
  * of tiles (call with out = NULL to size) or a negative status. */
 int64_t dmrg_debug_plan_tiles(const dmrg_problem_t *prob, const dmrg_plan_opts_t *opts, int32_t stage,
                               int64_t *out, int64_t cap);
+/* Test-only: the renormalization lists built as by dmrg_renorm_create for a
+ * problem whose ldata is a HOST array, executed on the CPU with the kernels'
+ * addressing (u, out HOST; out = NULL: statistics only); rec (may be NULL)
+ * receives up to rec_cap output records. */
+int dmrg_debug_renorm_host(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int32_t n_keep, int32_t fam_mask,
+                           const double *u, int64_t u_len, double *out, int64_t out_len, dmrg_oprec_t *rec,
+                           int64_t rec_cap, dmrg_renorm_stats_t *st);
 /* Test-only: the host eigensolver dmrg_davidson applies to its projected
  * matrix (cyclic Jacobi).  A: m x m symmetric, row-major, HOST, 1 <= m <= 64;
  * w: m eigenvalues ascending; Z: m x m row-major, eigenvector j in column j.

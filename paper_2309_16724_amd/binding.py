@@ -88,6 +88,24 @@ class PlanStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
 
 
+class RKeep(ctypes.Structure):
+    _fields_ = [("n", c_i32), ("two_s", c_i32), ("kept", c_i32), ("pad", c_i32), ("u_off", c_i64)]
+
+
+class RComp(ctypes.Structure):
+    _fields_ = [("sec", c_i32), ("l_sec", c_i32), ("site", c_i32), ("row0", c_i32), ("dim", c_i32),
+                ("pad", c_i32)]
+
+
+class RenormStats(ctypes.Structure):
+    _fields_ = [("n_terms", c_i64), ("n_products1", c_i64), ("n_products2", c_i64), ("n_tiles1", c_i64),
+                ("n_tiles2", c_i64), ("work_elems", c_i64), ("out_elems", c_i64), ("n_records", c_i64), ("flops1", c_dbl),
+                ("flops2", c_dbl), ("build_ms", c_dbl)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -149,6 +167,17 @@ def load(path=None):
                                        ctypes.POINTER(c_i64), ctypes.POINTER(c_i32), c_vp]
         L.dmrg_mlp_free.argtypes = [c_vp]
         L.dmrg_mlp_free.restype = None
+    if hasattr(L, "dmrg_renorm_create"):
+        L.dmrg_renorm_product.argtypes = [ctypes.POINTER(ProblemT), c_vp, c_i32, ctypes.POINTER(c_i32), c_vp,
+                                          c_i32, ctypes.POINTER(c_i32)]
+        L.dmrg_renorm_create.argtypes = [ctypes.POINTER(ProblemT), c_vp, c_i32, c_i32, c_i64, ctypes.POINTER(c_vp)]
+        L.dmrg_renorm_records.argtypes = [c_vp, c_vp, c_i64, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]
+        L.dmrg_renorm_apply.argtypes = [c_vp, c_vp, c_vp, c_vp]
+        L.dmrg_renorm_stats.argtypes = [c_vp, ctypes.POINTER(RenormStats)]
+        L.dmrg_renorm_free.argtypes = [c_vp]
+        L.dmrg_renorm_free.restype = None
+        L.dmrg_debug_renorm_host.argtypes = [ctypes.POINTER(ProblemT), c_vp, c_i32, c_i32, c_vp, c_i64, c_vp,
+                                             c_i64, c_vp, c_i64, ctypes.POINTER(RenormStats)]
     if path is None:
         _lib = L
     return L
@@ -250,3 +279,60 @@ def debug_host_apply(prob, psi, lib=None):
     check(L.dmrg_debug_host_apply(ctypes.byref(args.s), x.ctypes.data, y.ctypes.data,
                                   ctypes.byref(st)), L)
     return y, st
+
+
+def renorm_product(prob, lib=None):
+    """Product basis of the left block x site: [(n, 2S, rows)] and components
+    [(sector, left sector, site multiplet, row0, dim)] (dmrg_renorm_product)."""
+    L = lib or load()
+    args = ProblemArgs(prob, 0, 0)
+    ns, nc = c_i32(), c_i32()
+    check(L.dmrg_renorm_product(ctypes.byref(args.s), None, 0, ctypes.byref(ns), None, 0, ctypes.byref(nc)), L)
+    sec = (Sector * max(1, ns.value))()
+    comp = (RComp * max(1, nc.value))()
+    check(L.dmrg_renorm_product(ctypes.byref(args.s), ctypes.addressof(sec), ns.value, ctypes.byref(ns),
+                                ctypes.addressof(comp), nc.value, ctypes.byref(nc)), L)
+    return ([(s.n, s.two_s, s.dim) for s in sec[:ns.value]],
+            [(c.sec, c.l_sec, c.site, c.row0, c.dim) for c in comp[:nc.value]])
+
+
+def keep_array(keep):
+    """keep: [(n, 2S, U)] -> (RKeep array, flat U (column-major per sector), length)."""
+    offs, parts, off = [], [], 0
+    for (n, S, U) in keep:
+        U = np.asarray(U, dtype=np.float64)
+        offs.append(RKeep(n, S, U.shape[1], 0, off))
+        parts.append(np.asfortranarray(U).reshape(-1, order="F"))
+        off += U.size
+    arr = (RKeep * len(offs))(*offs)
+    flat = np.concatenate(parts) if parts else np.zeros(1)
+    return arr, flat, off
+
+
+def records_block(prob, keep, recs, data):
+    """Output of a renormalization as the oracle's BlockData (role L, bond p + 1)."""
+    from .synth.problem import BlockData
+    blk = BlockData("L", prob.n_orb, prob.p + 1, [(n, S, np.asarray(U).shape[1]) for (n, S, U) in keep])
+    blk.records = [(r.fam, r.row_sec, r.col_sec, r.off, r.npos) for r in recs]
+    blk.data = np.asarray(data, dtype=np.float64)
+    return blk
+
+
+def debug_renorm_host(prob, keep, fam_mask=0, lib=None, execute=True):
+    """Test-only: the renormalization lists executed on the CPU (no GPU).
+    Returns (BlockData of the new block or None, statistics)."""
+    L = lib or load()
+    ld = np.ascontiguousarray(prob.left.data)
+    args = ProblemArgs(prob, ld.ctypes.data, 0)
+    karr, u, ulen = keep_array(keep)
+    st = RenormStats()
+    check(L.dmrg_debug_renorm_host(ctypes.byref(args.s), ctypes.addressof(karr), len(keep), fam_mask,
+                                   None, ulen, None, 0, None, 0, ctypes.byref(st)), L)
+    if not execute:
+        return None, st.as_dict()
+    out = np.zeros(max(1, st.out_elems))
+    recs = (OpRec * max(1, st.n_records))()
+    check(L.dmrg_debug_renorm_host(ctypes.byref(args.s), ctypes.addressof(karr), len(keep), fam_mask,
+                                   u.ctypes.data, ulen, out.ctypes.data, out.size, ctypes.addressof(recs),
+                                   st.n_records, ctypes.byref(st)), L)
+    return records_block(prob, keep, recs[:st.n_records], out[:st.out_elems]), st.as_dict()

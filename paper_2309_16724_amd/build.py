@@ -14,7 +14,7 @@ OUT = os.path.join(HERE, "libdmrg_hpsi.so")
 BUILD = os.path.join(HERE, "_build")
 
 HOST_SRC = ["wigner.cpp", "model.cpp", "api_host.cpp"]
-HIP_HOST_SRC = ["plan.cpp", "davidson.cpp", "mlp.cpp"]
+HIP_HOST_SRC = ["plan.cpp", "davidson.cpp", "mlp.cpp", "renorm.cpp"]
 HIP_SRC = ["kernels_f64.hip", "kernels_vec.hip", "kernels_split.hip", "kernels_mlp.hip", "apply_static.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

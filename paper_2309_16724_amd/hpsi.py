@@ -214,3 +214,66 @@ class Plan:
             self.free()
         except Exception:
             pass
+
+
+class Renorm:
+    """Renormalization of a problem's left block through its left site on the
+    GPU (dmrg_renorm_*): the families H, C, A0, A1, B0, B1 of the block
+    [0, site_l] in the kept basis.  ``keep`` is [(n, 2S, U)] with U a host
+    array (rows of that product sector x kept) or ``u`` a device tensor that
+    already holds the matrices at the offsets ``keep_array`` would give."""
+
+    def __init__(self, prob, keep, device="cuda:0", fam_mask=0, ldata=None):
+        torch = _torch()
+        self.lib = B.load()
+        if not hasattr(self.lib, "dmrg_renorm_create"):
+            raise RuntimeError("library has no renormalization entry points")
+        self.device = torch.device(device)
+        self.prob, self.keep = prob, keep
+        self.ld = ldata if ldata is not None else \
+            torch.from_numpy(np.ascontiguousarray(prob.left.data)).to(self.device)
+        self.args = B.ProblemArgs(prob, self.ld.data_ptr(), 0)
+        self.karr, flat, self.u_len = B.keep_array(keep)
+        self.u = torch.from_numpy(flat).to(self.device)
+        h = ctypes.c_void_p()
+        B.check(self.lib.dmrg_renorm_create(ctypes.byref(self.args.s), ctypes.addressof(self.karr), len(keep),
+                                            fam_mask, self.u_len, ctypes.byref(h)), self.lib)
+        self.handle = h
+        n, ln = ctypes.c_int64(), ctypes.c_int64()
+        B.check(self.lib.dmrg_renorm_records(self.handle, None, 0, ctypes.byref(n), ctypes.byref(ln)), self.lib)
+        self.recs = (B.OpRec * max(1, n.value))()
+        B.check(self.lib.dmrg_renorm_records(self.handle, ctypes.addressof(self.recs), n.value, ctypes.byref(n),
+                                             ctypes.byref(ln)), self.lib)
+        self.n_rec, self.out_len = n.value, ln.value
+        self.out = torch.empty(max(1, self.out_len), dtype=torch.float64, device=self.device)
+
+    def stats(self):
+        st = B.RenormStats()
+        B.check(self.lib.dmrg_renorm_stats(self.handle, ctypes.byref(st)), self.lib)
+        return st.as_dict()
+
+    def apply(self, stream=None):
+        torch = _torch()
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        B.check(self.lib.dmrg_renorm_apply(self.handle, ctypes.c_void_p(self.u.data_ptr()),
+                                           ctypes.c_void_p(self.out.data_ptr()), ctypes.c_void_p(s.cuda_stream)),
+                self.lib)
+        return self.out
+
+    def block(self):
+        """The new block as host BlockData (after apply)."""
+        _torch().cuda.synchronize(self.device)
+        return B.records_block(self.prob, self.keep, self.recs[:self.n_rec],
+                               self.out[:self.out_len].cpu().numpy())
+
+    def free(self):
+        if getattr(self, "handle", None):
+            _torch().cuda.synchronize(self.device)
+            self.lib.dmrg_renorm_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

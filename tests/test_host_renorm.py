@@ -1,0 +1,105 @@
+"""Host side of the renormalization entry points (no GPU): the product-basis
+layout, the term and product lists executed on the CPU with the kernels'
+addressing (dmrg_debug_renorm_host) against the oracle, and the error codes."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2309_16724_amd import binding as B
+from paper_2309_16724_amd.synth import catalogue as cat
+from paper_2309_16724_amd.synth.problem import exact_problem, random_problem
+from oracle.renorm import renormalize, product_sectors, RENORM_FAMILIES
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return B.load()
+
+
+def rand_keep(prob, frac, seed):
+    rng = np.random.default_rng(seed)
+    keep = []
+    for (N, S, rows, comps) in product_sectors(prob.left.sectors):
+        k = max(1, int(round(rows * frac)))
+        keep.append((N, S, np.linalg.qr(rng.standard_normal((rows, k)))[0]))
+    return keep
+
+
+def max_family_diff(got, want, fam):
+    g = {(r, c): got.block(fam, r, c) for (f, r, c, o, n) in got.records if f == fam}
+    w = {(r, c): want.block(fam, r, c) for (f, r, c, o, n) in want.records if f == fam}
+    d = 0.0
+    for k in set(g) | set(w):
+        a, b = g.get(k), w.get(k)
+        if a is None:
+            a = np.zeros_like(b)
+        if b is None:
+            b = np.zeros_like(a)
+        d = max(d, np.abs(a - b).max())
+    scale = max([np.abs(x).max() for x in w.values()] + [1.0])
+    return d / scale
+
+
+def test_product_layout_matches_oracle(lib):
+    prob = random_problem(10, 10, 0, 7, 48, p=4)
+    secs, comps = B.renorm_product(prob, lib)
+    want = product_sectors(prob.left.sectors)
+    assert secs == [(N, S, rows) for (N, S, rows, c) in want]
+    flat = [(i, a, m, r0, d) for i, (N, S, rows, cs) in enumerate(want) for (a, m, r0, d) in cs]
+    assert comps == flat
+
+
+@pytest.mark.parametrize("case", ["exact_full", "exact_cut", "random_cut", "random_odd"])
+def test_host_lists_match_oracle(lib, case):
+    if case == "exact_full":
+        prob, frac = exact_problem(6, 6, 0, 21, p=2), 1.0
+    elif case == "exact_cut":
+        prob, frac = exact_problem(7, 7, 1, 22, p=3), 0.6
+    elif case == "random_cut":
+        prob, frac = random_problem(10, 10, 0, 7, 32, p=4), 0.5
+    else:
+        prob, frac = random_problem(9, 9, 1, 8, 40, p=4), 0.7
+    keep = rand_keep(prob, frac, 3)
+    want = renormalize(prob, keep)
+    got, st = B.debug_renorm_host(prob, keep, lib=lib)
+    assert st["n_records"] == len(got.records) > 0
+    for fam in RENORM_FAMILIES:
+        assert max_family_diff(got, want, fam) < 1e-12, cat.NAMES[fam]
+
+
+def test_family_mask_selects_families(lib):
+    prob = random_problem(10, 10, 0, 7, 32, p=4)
+    keep = rand_keep(prob, 0.5, 4)
+    got, _ = B.debug_renorm_host(prob, keep, fam_mask=(1 << cat.H) | (1 << cat.B1), lib=lib)
+    assert {r[0] for r in got.records} == {cat.H, cat.B1}
+    want = renormalize(prob, keep, families=(cat.H, cat.B1))
+    for fam in (cat.H, cat.B1):
+        assert max_family_diff(got, want, fam) < 1e-12
+
+
+def test_renorm_error_codes(lib):
+    prob = random_problem(10, 10, 0, 7, 32, p=4)
+    keep = rand_keep(prob, 0.5, 5)
+    ld = np.ascontiguousarray(prob.left.data)
+    args = B.ProblemArgs(prob, ld.ctypes.data, 0)
+    karr, u, ulen = B.keep_array(keep)
+    st = B.RenormStats()
+
+    def call(a=args, k=karr, nk=len(keep), mask=0, ul=ulen):
+        return lib.dmrg_debug_renorm_host(ctypes.byref(a.s), ctypes.addressof(k), nk, mask, None, ul, None, 0,
+                                          None, 0, ctypes.byref(st))
+    assert call() == 0
+    assert call(mask=1 << cat.S) == -1                # S, P, Q are not produced
+    assert call(ul=ulen - 1) == -3                     # U beyond its array
+    bad = (B.RKeep * 1)(B.RKeep(99, 0, 1, 0, 0))
+    assert call(k=bad, nk=1) == -2                     # no such product sector
+    big = (B.RKeep * 1)(B.RKeep(karr[0].n, karr[0].two_s, 10 ** 6, 0, 0))
+    assert call(k=big, nk=1, ul=10 ** 12) == -1         # more kept states than rows
+    twice = (B.RKeep * 2)(karr[0], karr[0])
+    assert call(k=twice, nk=2) == -1
+    prob0 = random_problem(10, 10, 0, 7, 32, p=0)
+    a0 = B.ProblemArgs(prob0, np.ascontiguousarray(prob0.left.data).ctypes.data, 0)
+    assert call(a=a0) == -1                            # empty left block
+    args.eri[1, 2, 3, 4] = np.nan
+    assert call() == -6
