@@ -417,6 +417,8 @@ struct Built {
   std::vector<Seg> s1, s2;
   XcdQueues q1{}, q2{};
   int64_t work_len = 0;
+  std::vector<TransJob> ujobs;   // U -> U^T per kept sector (every apply)
+  std::vector<TransJob> ljobs;   // left records used as adjoints -> transposed copy (once)
   int64_t n_terms = 0;
   double flops1 = 0.0, flops2 = 0.0;
   double build_ms = 0.0;
@@ -557,18 +559,34 @@ int build_renorm(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int n_kee
   B.work_len = 0;
   B.flops1 = B.flops2 = 0.0;
   auto add_tiles = [&](std::vector<Tile> &tiles, std::vector<double> &cost, int m, int n, int c_base,
-                       int64_t c_off, int64_t ldc, int seg0, int nseg, double ksum) {
+                       int64_t c_off, int64_t ldc, int seg0, int nseg, double ksum, int rowmajor) {
     const int mb = tile_mb(m, n), tr = tile_rows(mb), tc = tile_cols(mb);
     for (int i0 = 0; i0 < m; i0 += tr)
       for (int j0 = 0; j0 < n; j0 += tc) {
         Tile T{};
         T.c_off = c_off; T.ldc = ldc; T.c_base = c_base;
         T.m = m; T.n = n; T.i0 = i0; T.j0 = j0; T.ci0 = i0; T.cj0 = j0;
-        T.mb = mb; T.seg0 = seg0; T.nseg = nseg; T.accumulate = 0; T.rowmajor = 0;
+        T.mb = mb; T.seg0 = seg0; T.nseg = nseg; T.accumulate = 0; T.rowmajor = rowmajor;
         tiles.push_back(T);
         cost.push_back((double)std::min(tr, m - i0) * std::min(tc, n - j0) * ksum);
       }
   };
+  // Operand layouts that let every wavefront load whole lines (lanes run
+  // along output rows of A and along output columns of B): U is read from
+  // its per-sector transpose U^T (kept x rows, column-major), adjoint left
+  // members from a transposed copy of their records, and T is stored
+  // row-major (ket kept states fastest).
+  std::vector<char> ladj(L.rec.size(), 0);
+  for (const TKey &k : tkeys)
+    if (k.adj) ladj[k.rec] = 1;
+  B.ljobs.clear();
+  for (size_t i = 0; i < L.rec.size(); i++)
+    if (ladj[i]) {
+      const dmrg_oprec_t &r = L.rec[i];
+      B.ljobs.push_back(TransJob{r.off, L.sec[r.row_sec].dim, L.sec[r.col_sec].dim, r.npos, 0});
+    }
+  B.ujobs.clear();
+  for (int k = 0; k < n_keep; k++) B.ujobs.push_back(TransJob{keep[k].u_off, prows(k), kept(k), 1, 0});
   for (size_t i = 0; i < tkeys.size(); i++) {
     const TKey &k = tkeys[i];
     const dmrg_oprec_t &r = L.rec[k.rec];
@@ -576,21 +594,21 @@ int build_renorm(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int n_kee
     const int m = k.adj ? rc : rr, K = k.adj ? rr : rc, n = kept(k.ak);
     const RComp &ca = comp(k.ak, k.ac);
     Seg S{};
-    S.a_base = BASE_OPS;
+    S.a_base = k.adj ? BASE_OPS + 1 : BASE_OPS;
     S.a_off = r.off + (int64_t)k.posA * rr * rc;
-    S.a_i = k.adj ? rr : 1;
-    S.a_k = k.adj ? 1 : rr;
+    S.a_i = 1;
+    S.a_k = k.adj ? rc : rr;       // the transposed record is rc x rr
     S.a_p = 0;
     S.a_kb = K;
-    S.b_base = BASE_PSI;
-    S.b_off = keep[k.ak].u_off + ca.row0;
-    S.b_k = 1; S.b_n = prows(k.ak); S.b_kb = K; S.b_nb = n; S.b_pk = 0; S.b_pn = 0;
+    S.b_base = BASE_PSI;            // U^T: element (c, r) at u_off + c + r * kept
+    S.b_off = keep[k.ak].u_off + (int64_t)ca.row0 * n;
+    S.b_k = n; S.b_n = 1; S.b_kb = K; S.b_nb = n; S.b_pk = 0; S.b_pn = 0;
     S.K = K;
     S.s = 1.0;
     toff[i] = B.work_len;
     int seg0 = (int)B.s1.size();
     B.s1.push_back(S);
-    add_tiles(B.t1, cost1, m, n, BASE_WORK, toff[i], m, seg0, 1, K);
+    add_tiles(B.t1, cost1, m, n, BASE_WORK, toff[i], n, seg0, 1, K, 1);
     B.work_len += (int64_t)m * n;
     B.flops1 += 2.0 * m * n * K;
   }
@@ -604,24 +622,22 @@ int build_renorm(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int n_kee
       const CKey &c = cv.first;
       const RComp &cb = comp(c.bk, c.bc);
       Seg S{};
-      S.a_base = BASE_PSI;
-      S.a_off = keep[c.bk].u_off + cb.row0;
-      S.a_i = prows(c.bk);
-      S.a_k = 1;
+      S.a_base = BASE_PSI;          // U_b'^T rows block: A(i, k) = U^T[i + (row0 + k) kept_b']
+      S.a_off = keep[c.bk].u_off + (int64_t)cb.row0 * m;
+      S.a_i = 1;
+      S.a_k = m;
       S.a_p = 0;
       S.K = cb.dim;
       S.a_kb = S.K;
-      if (c.tix >= 0) {
+      if (c.tix >= 0) {             // T row-major, d_b x kept_a'
         S.b_base = BASE_WORK;
         S.b_off = toff[c.tix];
-        S.b_k = 1;
-        S.b_n = cb.dim;
-      } else {
+      } else {                      // identity left factor: U_a'^T rows block
         S.b_base = BASE_PSI;
-        S.b_off = keep[c.ak].u_off + comp(c.ak, c.ac).row0;
-        S.b_k = 1;
-        S.b_n = prows(c.ak);
+        S.b_off = keep[c.ak].u_off + (int64_t)comp(c.ak, c.ac).row0 * n;
       }
+      S.b_k = n;
+      S.b_n = 1;
       S.b_kb = S.K; S.b_nb = n; S.b_pk = 0; S.b_pn = 0;
       S.s = cv.second;
       B.s2.push_back(S);
@@ -629,7 +645,7 @@ int build_renorm(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int n_kee
       B.flops2 += 2.0 * m * n * S.K;
     }
     const int64_t off = rec_off[{o.fam, o.bk, o.ak}] + (int64_t)o.pos * m * n;
-    add_tiles(B.t2, cost2, m, n, BASE_Y, off, m, seg0, (int)B.s2.size() - seg0, ksum);
+    add_tiles(B.t2, cost2, m, n, BASE_Y, off, m, seg0, (int)B.s2.size() - seg0, ksum, 0);
   }
   // every element a kernel lane may touch lies inside its array (lanes past
   // the tile or K read inside the operand: row 0, column 0, element K - 1)
@@ -637,7 +653,8 @@ int build_renorm(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int n_kee
     auto len = [&](int base) { return base == BASE_PSI ? u_len : base == BASE_Y ? B.out_len
                                     : base == BASE_WORK ? B.work_len : pr.ldata_len; };
     for (const Tile &T : tiles) {
-      if (T.c_off < 0 || T.c_off + (T.m - 1) + (int64_t)(T.n - 1) * T.ldc >= len(T.c_base)) return false;
+      const int64_t last = T.rowmajor ? (int64_t)(T.m - 1) * T.ldc + (T.n - 1) : (T.m - 1) + (int64_t)(T.n - 1) * T.ldc;
+      if (T.c_off < 0 || T.c_off + last >= len(T.c_base)) return false;
       for (int i = 0; i < T.nseg; i++) {
         const Seg &S = segs[T.seg0 + i];
         if (S.K <= 0 || S.a_off < 0 || S.b_off < 0) return false;
@@ -671,10 +688,10 @@ int build_renorm(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int n_kee
 }
 
 // host execution of a tile list with the kernels' addressing (test path)
-void host_run(const std::vector<Tile> &tiles, const std::vector<Seg> &segs, const double *ops, const double *u,
-              double *out, double *work) {
+void host_run(const std::vector<Tile> &tiles, const std::vector<Seg> &segs, const double *ops, const double *opsT,
+              const double *u, double *out, double *work) {
   auto base = [&](int id) -> const double * {
-    return id == BASE_PSI ? u : id == BASE_Y ? out : id == BASE_WORK ? work : ops;
+    return id == BASE_PSI ? u : id == BASE_Y ? out : id == BASE_WORK ? work : id == BASE_OPS ? ops : opsT;
   };
   for (const Tile &T : tiles) {
     const int mt = std::min(tile_rows(T.mb), T.m - T.i0), nt = std::min(tile_cols(T.mb), T.n - T.j0);
@@ -692,7 +709,19 @@ void host_run(const std::vector<Tile> &tiles, const std::vector<Seg> &segs, cons
     }
     double *C = const_cast<double *>(base(T.c_base)) + T.c_off;
     for (int j = 0; j < nt; j++)
-      for (int i = 0; i < mt; i++) C[(int64_t)(T.ci0 + i) + (int64_t)(T.cj0 + j) * T.ldc] = acc[i + (size_t)j * mt];
+      for (int i = 0; i < mt; i++)
+        C[T.rowmajor ? (int64_t)(T.ci0 + i) * T.ldc + (T.cj0 + j) : (int64_t)(T.ci0 + i) + (int64_t)(T.cj0 + j) * T.ldc] =
+            acc[i + (size_t)j * mt];
+  }
+}
+
+// dst block (c, r) = src block (r, c) for every job (the transpose kernel's rule)
+void host_transpose(const std::vector<TransJob> &jobs, const double *src, double *dst) {
+  for (const TransJob &J : jobs) {
+    const int64_t bs = (int64_t)J.rows * J.cols;
+    for (int p = 0; p < J.npos; p++)
+      for (int c = 0; c < J.cols; c++)
+        for (int r = 0; r < J.rows; r++) dst[J.off + p * bs + c + (int64_t)r * J.cols] = src[J.off + p * bs + r + (int64_t)c * J.rows];
   }
 }
 
@@ -703,14 +732,17 @@ struct dmrg_renorm {
   const double *ldata = nullptr;
   Tile *d_t1 = nullptr, *d_t2 = nullptr;
   Seg *d_s1 = nullptr, *d_s2 = nullptr;
+  TransJob *d_uj = nullptr, *d_lj = nullptr;
   const double **d_bases = nullptr;
   int32_t *d_cnt = nullptr;
-  double *d_work = nullptr;
+  double *d_work = nullptr, *d_ut = nullptr, *d_lt = nullptr;
+  int64_t u_len = 0;
 };
 
 extern "C" void dmrg_renorm_free(dmrg_renorm_t *r) {
   if (!r) return;
-  void *ptrs[] = {r->d_t1, r->d_t2, r->d_s1, r->d_s2, (void *)r->d_bases, r->d_cnt, r->d_work};
+  void *ptrs[] = {r->d_t1, r->d_t2, r->d_s1, r->d_s2, r->d_uj, r->d_lj, (void *)r->d_bases, r->d_cnt,
+                  r->d_work, r->d_ut, r->d_lt};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete r;
@@ -756,8 +788,13 @@ extern "C" int dmrg_renorm_create(const dmrg_problem_t *prob, const dmrg_rkeep_t
       if (hipMalloc(dst, bytes) != hipSuccess) return false;
       return !src || hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
     };
-    const double *bases[1] = {prob->ldata};
-    bool ok = up((void **)&r->d_t1, r->b.t1.data(), r->b.t1.size() * sizeof(Tile)) &&
+    r->u_len = u_len;
+    bool ok = up((void **)&r->d_ut, nullptr, (size_t)u_len * sizeof(double)) &&
+              up((void **)&r->d_lt, nullptr, r->b.ljobs.empty() ? 0 : (size_t)prob->ldata_len * sizeof(double)) &&
+              up((void **)&r->d_uj, r->b.ujobs.data(), r->b.ujobs.size() * sizeof(TransJob)) &&
+              up((void **)&r->d_lj, r->b.ljobs.data(), r->b.ljobs.size() * sizeof(TransJob));
+    const double *bases[2] = {prob->ldata, r->d_lt};
+    ok = ok && up((void **)&r->d_t1, r->b.t1.data(), r->b.t1.size() * sizeof(Tile)) &&
               up((void **)&r->d_t2, r->b.t2.data(), r->b.t2.size() * sizeof(Tile)) &&
               up((void **)&r->d_s1, r->b.s1.data(), r->b.s1.size() * sizeof(Seg)) &&
               up((void **)&r->d_s2, r->b.s2.data(), r->b.s2.size() * sizeof(Seg)) &&
@@ -768,6 +805,15 @@ extern "C" int dmrg_renorm_create(const dmrg_problem_t *prob, const dmrg_rkeep_t
       dmrg_renorm_free(r.release());
       set_error("device allocation or copy failed");
       return DMRG_ENOMEM;
+    }
+    // transposed copies of the left records applied as adjoints (once)
+    if (!r->b.ljobs.empty()) {
+      launch_transpose(r->d_lj, (int)r->b.ljobs.size(), prob->ldata, r->d_lt, nullptr);
+      if (hipStreamSynchronize(nullptr) != hipSuccess) {
+        dmrg_renorm_free(r.release());
+        set_error("transposing the left records failed");
+        return DMRG_EHIP;
+      }
     }
     *out = r.release();
     return DMRG_OK;
@@ -794,11 +840,12 @@ extern "C" int dmrg_renorm_records(const dmrg_renorm_t *r, dmrg_oprec_t *rec, in
 
 extern "C" int dmrg_renorm_apply(dmrg_renorm_t *r, const double *u, double *out, void *stream) {
   if (!r || !u || !out) { set_error("null argument"); return DMRG_EINVAL; }
+  launch_transpose(r->d_uj, (int)r->b.ujobs.size(), u, r->d_ut, stream);
   launch_zero(out, r->b.out_len, stream);
-  launch_tiles_f64(1, r->d_t1, r->d_s1, (int)r->b.t1.size(), r->b.q1, r->d_cnt, r->d_bases, u, out, r->d_work,
-                   nullptr, stream);
-  launch_tiles_f64(2, r->d_t2, r->d_s2, (int)r->b.t2.size(), r->b.q2, r->d_cnt, r->d_bases, u, out, r->d_work,
-                   nullptr, stream);
+  launch_tiles_f64(1, r->d_t1, r->d_s1, (int)r->b.t1.size(), r->b.q1, r->d_cnt, r->d_bases, r->d_ut, out,
+                   r->d_work, nullptr, stream);
+  launch_tiles_f64(2, r->d_t2, r->d_s2, (int)r->b.t2.size(), r->b.q2, r->d_cnt, r->d_bases, r->d_ut, out,
+                   r->d_work, nullptr, stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) { set_error(std::string("HIP: ") + hipGetErrorString(e)); return DMRG_EHIP; }
   return DMRG_OK;
@@ -847,9 +894,15 @@ extern "C" int dmrg_debug_renorm_host(const dmrg_problem_t *prob, const dmrg_rke
     if (!out) return DMRG_OK;
     if (!u || !prob->ldata || out_len < b.out_len) { set_error("missing input or output too small"); return DMRG_EINVAL; }
     std::vector<double> work((size_t)std::max<int64_t>(b.work_len, 1));
+    std::vector<double> ut((size_t)std::max<int64_t>(u_len, 1)), lt;
+    host_transpose(b.ujobs, u, ut.data());
+    if (!b.ljobs.empty()) {
+      lt.assign((size_t)prob->ldata_len, 0.0);
+      host_transpose(b.ljobs, prob->ldata, lt.data());
+    }
     std::fill(out, out + b.out_len, 0.0);
-    host_run(b.t1, b.s1, prob->ldata, u, out, work.data());
-    host_run(b.t2, b.s2, prob->ldata, u, out, work.data());
+    host_run(b.t1, b.s1, prob->ldata, lt.data(), ut.data(), out, work.data());
+    host_run(b.t2, b.s2, prob->ldata, lt.data(), ut.data(), out, work.data());
     return DMRG_OK;
   } catch (const std::bad_alloc &) {
     set_error("host allocation failed");
