@@ -135,11 +135,15 @@ def cpu_baseline(flops_bench, bench_workload):
 # traffic are the ones it was taken on (their hash); else null.
 _SPLIT_SRC = ("kernels_split.hip", "plan.cpp", "plan.hpp", "model.cpp")
 _F64_SRC = ("kernels_f64.hip", "plan.cpp", "plan.hpp", "model.cpp")
+_REN_SRC = ("renorm.cpp", "kernels_f64.hip")
 MEASURED_TRAFFIC = {
     ("L54_D2048", "stage1_wsplit5_kernel"): (1.6826e11, _SPLIT_SRC, "fd14f25f69d6d718"),
     ("L54_D2048", "stage2_wsplit5_kernel"): (2.2778e11, _SPLIT_SRC, "fd14f25f69d6d718"),
     ("L54_D2048", "stage_f64_kernel<1>"): (3.5086e11, _F64_SRC, "69c8d5cbc4f75ca9"),
     ("L54_D2048", "stage_f64_kernel<2>"): (1.0639e12, _F64_SRC, "69c8d5cbc4f75ca9"),
+    # renormalization of the L54_D2048 left block (profiles/renorm_L54_D2048_fp64.md)
+    ("L54_D2048", "renorm:stage_f64_kernel<1>"): (1.2457e11, _REN_SRC, "5061d91d70bbc02f"),
+    ("L54_D2048", "renorm:stage_f64_kernel<2>"): (1.5508e11, _REN_SRC, "5061d91d70bbc02f"),
 }
 
 
@@ -412,7 +416,7 @@ def davidson_runs(torch, args, plan_flags):
     return out
 
 
-def renorm_run(torch, prob, steps, warmup):
+def renorm_run(torch, prob, workload, steps, warmup):
     """Renormalization of the workload's left block through its left site
     (families H, C, A0, A1, B0, B1 of the enlarged block, FP64): every product
     sector keeps a quarter of its rows (about D states in all) through a U
@@ -437,6 +441,12 @@ def renorm_run(torch, prob, steps, warmup):
         r.apply()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t1) * 1e3 / steps
+    r.set_profiling(True)
+    for _ in range(steps):
+        r.apply()
+    torch.cuda.synchronize()
+    prof = {s_: r.profile(s_) for s_ in (1, 2)}
+    r.set_profiling(False)
     first = r.out.clone()
     r.apply()
     torch.cuda.synchronize()
@@ -454,6 +464,10 @@ def renorm_run(torch, prob, steps, warmup):
     flops = st["flops1"] + st["flops2"]
     tf = flops / (ms * 1e-3) / 1e12
     r.free()
+    dom = max((1, 2), key=lambda s_: prof[s_][1])
+    n_d, ms_d, fl_d = prof[dom]
+    ach = (fl_d / n_d) / (ms_d / n_d * 1e-3) / 1e12
+    kname = "stage_f64_kernel<%d>" % dom
     return {"ms": ms, "tflops": tf, "flops": flops, "flops_stage1": st["flops1"], "flops_stage2": st["flops2"],
             "kept_states": int(sum(u.shape[1] for _, _, u in keep)),
             "product_states": int(sum(u.shape[0] for _, _, u in keep)),
@@ -461,10 +475,10 @@ def renorm_run(torch, prob, steps, warmup):
             "terms": st["n_terms"], "products": [st["n_products1"], st["n_products2"]],
             "tiles": [st["n_tiles1"], st["n_tiles2"]], "build_ms": st["build_ms"],
             "bitwise_repeat": repro, "h_blocks": nh, "h_asymmetry": asym,
-            "roofline": {"bound": "mfma", "kernel": "stage_f64_kernel<1>, <2> (both launches)",
-                         "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                         "frac": tf / FP64_PEAK_TFLOPS, "traffic": None,
-                         "note": "time of dmrg_renorm_apply: output clear and the two product launches"}}
+            "stages_ms": {str(k): v[1] / max(v[0], 1) for k, v in prof.items()},
+            "roofline": {"bound": "mfma", "kernel": kname, "achieved": ach, "peak": FP64_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
+                         "traffic": measured_traffic(workload, "renorm:" + kname)}}
 
 
 def main():
@@ -538,7 +552,7 @@ def main():
 
     if args.renorm_only:
         print(json.dumps({"renorm_only": True, "workload": args.workload,
-                          **renorm_run(torch, prob, args.steps, args.warmup)}), flush=True)
+                          **renorm_run(torch, prob, args.workload, args.steps, args.warmup)}), flush=True)
         return
     if args.hpsi_only:
         ref = torch.empty(32 << 20, dtype=torch.float64, device="cuda")   # 256 MiB
@@ -562,7 +576,7 @@ def main():
     del y5, y64
     ren = None
     if not args.no_renorm:
-        ren = renorm_run(torch, prob, args.steps, args.warmup)
+        ren = renorm_run(torch, prob, args.workload, args.steps, args.warmup)
         ren["workload"] = "%s left block (orbitals 0..%d) x site %d" % (args.workload, prob.p - 1, prob.p)
         print("# renormalization: %s" % json.dumps(ren), file=sys.stderr, flush=True)
     dav = None

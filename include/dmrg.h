@@ -425,6 +425,14 @@ int dmrg_renorm_create(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int
 int dmrg_renorm_records(const dmrg_renorm_t *r, dmrg_oprec_t *rec, int64_t cap, int64_t *n_rec, int64_t *data_len);
 int dmrg_renorm_apply(dmrg_renorm_t *r, const double *u, double *out, void *stream);
 int dmrg_renorm_stats(const dmrg_renorm_t *r, dmrg_renorm_stats_t *st);
+/* Profiling as for plans: when on, dmrg_renorm_apply records a hipEvent pair
+ * on its stream around the first-stage (1) and the second-stage (2) product
+ * launch; dmrg_renorm_get_profile waits for them and returns the number of
+ * launches, their summed duration and algorithmic flops since the last
+ * dmrg_renorm_set_profiling call. */
+int dmrg_renorm_set_profiling(dmrg_renorm_t *r, int32_t on);
+int dmrg_renorm_get_profile(dmrg_renorm_t *r, int32_t stage, int64_t *n_launches, double *total_ms,
+                            double *total_flops);
 void dmrg_renorm_free(dmrg_renorm_t *r);
 
 /* ---- host-logic inspection (no GPU use; for tests of the host tables) ---- */

@@ -737,10 +737,14 @@ struct dmrg_renorm {
   int32_t *d_cnt = nullptr;
   double *d_work = nullptr, *d_ut = nullptr, *d_lt = nullptr;
   int64_t u_len = 0;
+  // profiling: an event pair around each stage launch of every apply
+  bool prof = false;
+  std::vector<hipEvent_t> ev;      // 4 per recorded apply
 };
 
 extern "C" void dmrg_renorm_free(dmrg_renorm_t *r) {
   if (!r) return;
+  for (hipEvent_t e : r->ev) (void)hipEventDestroy(e);
   void *ptrs[] = {r->d_t1, r->d_t2, r->d_s1, r->d_s2, r->d_uj, r->d_lj, (void *)r->d_bases, r->d_cnt,
                   r->d_work, r->d_ut, r->d_lt};
   for (void *p : ptrs)
@@ -840,14 +844,56 @@ extern "C" int dmrg_renorm_records(const dmrg_renorm_t *r, dmrg_oprec_t *rec, in
 
 extern "C" int dmrg_renorm_apply(dmrg_renorm_t *r, const double *u, double *out, void *stream) {
   if (!r || !u || !out) { set_error("null argument"); return DMRG_EINVAL; }
+  hipEvent_t ev[4] = {};
+  if (r->prof) {
+    for (auto &x : ev)
+      if (hipEventCreate(&x) != hipSuccess) { set_error("hipEventCreate failed"); return DMRG_EHIP; }
+  }
+  hipStream_t hs = (hipStream_t)stream;
   launch_transpose(r->d_uj, (int)r->b.ujobs.size(), u, r->d_ut, stream);
   launch_zero(out, r->b.out_len, stream);
+  if (r->prof) (void)hipEventRecord(ev[0], hs);
   launch_tiles_f64(1, r->d_t1, r->d_s1, (int)r->b.t1.size(), r->b.q1, r->d_cnt, r->d_bases, r->d_ut, out,
                    r->d_work, nullptr, stream);
+  if (r->prof) { (void)hipEventRecord(ev[1], hs); (void)hipEventRecord(ev[2], hs); }
   launch_tiles_f64(2, r->d_t2, r->d_s2, (int)r->b.t2.size(), r->b.q2, r->d_cnt, r->d_bases, r->d_ut, out,
                    r->d_work, nullptr, stream);
+  if (r->prof) {
+    (void)hipEventRecord(ev[3], hs);
+    for (auto &x : ev) r->ev.push_back(x);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) { set_error(std::string("HIP: ") + hipGetErrorString(e)); return DMRG_EHIP; }
+  return DMRG_OK;
+}
+
+extern "C" int dmrg_renorm_set_profiling(dmrg_renorm_t *r, int32_t on) {
+  if (!r) { set_error("null argument"); return DMRG_EINVAL; }
+  for (hipEvent_t e : r->ev) (void)hipEventDestroy(e);
+  r->ev.clear();
+  r->prof = on != 0;
+  return DMRG_OK;
+}
+
+extern "C" int dmrg_renorm_get_profile(dmrg_renorm_t *r, int32_t stage, int64_t *n_launches, double *total_ms,
+                                       double *total_flops) {
+  if (!r || (stage != 1 && stage != 2) || !n_launches || !total_ms || !total_flops) {
+    set_error("bad renormalization profile query");
+    return DMRG_EINVAL;
+  }
+  int64_t n = 0;
+  double ms = 0.0;
+  for (size_t i = 0; i + 3 < r->ev.size(); i += 4) {
+    hipEvent_t a = r->ev[i + (stage == 1 ? 0 : 2)], b = r->ev[i + (stage == 1 ? 1 : 3)];
+    if (hipEventSynchronize(b) != hipSuccess) { set_error("hipEventSynchronize failed"); return DMRG_EHIP; }
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, a, b) != hipSuccess) { set_error("hipEventElapsedTime failed"); return DMRG_EHIP; }
+    ms += t;
+    n++;
+  }
+  *n_launches = n;
+  *total_ms = ms;
+  *total_flops = n * (stage == 1 ? r->b.flops1 : r->b.flops2);
   return DMRG_OK;
 }
 

@@ -260,6 +260,16 @@ class Renorm:
                 self.lib)
         return self.out
 
+    def set_profiling(self, on=True):
+        B.check(self.lib.dmrg_renorm_set_profiling(self.handle, 1 if on else 0), self.lib)
+
+    def profile(self, stage):
+        """(launches, total ms, total algorithmic flops) of stage 1 or 2 since set_profiling."""
+        n, ms, fl = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        B.check(self.lib.dmrg_renorm_get_profile(self.handle, stage, ctypes.byref(n), ctypes.byref(ms),
+                                                 ctypes.byref(fl)), self.lib)
+        return n.value, ms.value, fl.value
+
     def block(self):
         """The new block as host BlockData (after apply)."""
         _torch().cuda.synchronize(self.device)
