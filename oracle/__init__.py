@@ -12,5 +12,6 @@ Modules
   layout   canonical list of SU(2) wavefunction blocks
   hpsi     H_eff psi through the M-resolved expansion of the reduced blocks
   davidson plain Davidson solver
+  renorm   the enlarged left block's operators after renormalization
 Parity status of every function is stated in its module header.
 """
