@@ -418,7 +418,7 @@ def davidson_runs(torch, args, plan_flags):
 
 def renorm_run(torch, prob, workload, steps, warmup):
     """Renormalization of the workload's left block through its left site
-    (families H, C, A0, A1, B0, B1 of the enlarged block, FP64): every product
+    (families H, C, A0, A1, B0, B1, S of the enlarged block, FP64): every product
     sector keeps a quarter of its rows (about D states in all) through a U
     with orthonormal columns (QR of a seeded Gaussian matrix).  Timed like
     H.psi: warm-up, then `steps` applies bracketed by synchronisation."""
@@ -471,7 +471,7 @@ def renorm_run(torch, prob, workload, steps, warmup):
     return {"ms": ms, "tflops": tf, "flops": flops, "flops_stage1": st["flops1"], "flops_stage2": st["flops2"],
             "kept_states": int(sum(u.shape[1] for _, _, u in keep)),
             "product_states": int(sum(u.shape[0] for _, _, u in keep)),
-            "families": "H C A0 A1 B0 B1", "records": r.n_rec, "out_elems": st["out_elems"],
+            "families": "H C A0 A1 B0 B1 S", "records": r.n_rec, "out_elems": st["out_elems"],
             "terms": st["n_terms"], "products": [st["n_products1"], st["n_products2"]],
             "tiles": [st["n_tiles1"], st["n_tiles2"]], "build_ms": st["build_ms"],
             "bitwise_repeat": repro, "h_blocks": nh, "h_asymmetry": asym,

@@ -377,7 +377,7 @@ const char *dmrg_last_error(void);
  * is accepted).  The new block's sectors are the keep entries, in their
  * order: (n, two_s, kept).
  *
- * Output: the families H, C, A0, A1, B0, B1 of the new block (labels of a left
+ * Output: the families H, C, A0, A1, B0, B1, S of the new block (labels of a left
  * block at bond site_l + 1), as records in the input format -- one per
  * (family, row sector, column sector) with any contribution, all positions,
  * [npos][kept_row][kept_col] column-major -- in a caller-owned DEVICE array
@@ -385,10 +385,11 @@ const char *dmrg_last_error(void);
  * old one are [A (x) 1]; members with the label l are products of single
  * creation/annihilation operators; H is the Hamiltonian restricted to
  * [0, l], with the parts of two or more indices in the old block taken from
- * its S_l, P_ll and Q_ll.  S, P and Q of the new block are not produced (they
- * need complementary operators of the old block for every outside pair;
- * the H.psi input keeps only the pairs touching the two sites): a fam_mask
- * naming them is DMRG_EINVAL.
+ * its S_l, P_ll and Q_ll; S_x (x > l) is S_x of the old block plus its P_xl
+ * and Q_xl times single site operators plus explicit products.  P and Q of
+ * the new block are not produced (they need P and Q of the old block for
+ * every outside pair; the H.psi input keeps only the pairs touching the two
+ * sites): a fam_mask naming them is DMRG_EINVAL.
  *
  * dmrg_renorm_create builds the term and product lists on the host and
  * copies them to the device (hipMalloc, freed by dmrg_renorm_free); the
@@ -417,7 +418,7 @@ typedef struct {
  * output may be NULL (counts only); DMRG_ERANGE when a capacity is short. */
 int dmrg_renorm_product(const dmrg_problem_t *prob, dmrg_sector_t *sec, int32_t sec_cap, int32_t *n_sec,
                         dmrg_rcomp_t *comp, int32_t comp_cap, int32_t *n_comp);
-/* fam_mask: bit f for family f (0 = H, C, A0, A1, B0, B1); u_len: elements of
+/* fam_mask: bit f for family f (0 = H, C, A0, A1, B0, B1, S); u_len: elements of
  * the U array that dmrg_renorm_apply will be given. */
 int dmrg_renorm_create(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int32_t n_keep, int32_t fam_mask,
                        int64_t u_len, dmrg_renorm_t **out);

@@ -33,7 +33,11 @@ sector are made of components (L sector a, site multiplet m) in the order a
 ascending, then m = 0 (empty), 1 (one electron), 2 (doubly occupied), each
 contributing d_a consecutive rows in the order of the L sector's states.
 
-Families produced: H, C, A0, A1, B0, B1 of the left block at bond p + 1.
+Families produced: H, C, A0, A1, B0, B1 and S of the left block at bond
+p + 1.  S_x of the new block (x > p) is (S_x)_s = sum over j, k, l in [0, p]
+of (xj|kl) E_kl a_js: its part inside L is the stored S_x; the parts with one
+index at p are sum_t (P_xp)_ts a+_pt and sum_t (Q_xp)_st a_pt of L (the same
+spin-orbital forms of P and Q that H_eff uses); the rest is explicit.
 Pinned in tests/test_oracle_renorm.py against the same families built
 directly in the Fock space of the enlarged block (untruncated and
 truncated), against U = identity invariants and against hermiticity.
@@ -46,7 +50,7 @@ from .wigner import cg
 from .hpsi import MBlock, Factors, SITE_N, SITE_2M, SITE_MULT_STATES, site_cre, site_ann
 from .layout import SITE
 
-RENORM_FAMILIES = (cat.H, cat.C, cat.A0, cat.A1, cat.B0, cat.B1)
+RENORM_FAMILIES = (cat.H, cat.C, cat.A0, cat.A1, cat.B0, cat.B1, cat.S)
 
 
 def product_sectors(lsec):
@@ -170,6 +174,12 @@ def _target(ps, fam, lab, q, p, h, eri):
         for coef, fs in _h_terms(ps, p, h, eri):
             acc += ps.product(coef, fs)
         return acc
+    if fam == cat.S:
+        # component q of the S tensor: (S_x)_s = -sqrt2 (-1)^(1/2+s) S_{-s}, so
+        # S_q = -(S_x)_{-q} / (sqrt2 (-1)^(1/2-q))
+        x, s_ = lab[0], -q
+        scale = -1.0 / (np.sqrt(2.0) * (-1.0 if ((1 + s_) // 2) % 2 else 1.0))
+        return scale * _s_spin(ps, x, s_, p, eri)
     if all(x < p for x in lab):          # member of L itself, times the site identity
         return ps.product(1.0, [(0, mL.tensor(fam, mL.pos(fam, lab), q), cat.TWO_K[fam] % 2)])
 
@@ -195,6 +205,32 @@ def _target(ps, fam, lab, q, p, h, eri):
         else:   # a~_{j t} = (-1)^(1/2 - t) a_{j, -t}
             ph = -1.0 if ((1 - t) // 2) % 2 else 1.0
             acc += ps.product(c * ph, [single(i, s, True), single(j, -t, False)])
+    return acc
+
+
+def _s_spin(ps, x, s2, p, eri):
+    """(S_x)_s = sum_{j,k,l in [0, p]} (xj|kl) sum_t a+_kt a_lt a_js of the
+    enlarged block, as a product-space matrix."""
+    fL, mL = ps.fL, ps.mL
+
+    def single(y, t2, dagger):
+        if y < p:
+            return (0, fL.cre(y, t2, 0) if dagger else fL.T("cre", y, t2, 0), 1)
+        return (1, site_cre(t2) if dagger else site_ann(t2), 1)
+
+    acc = ps.product(1.0, [(0, fL.S(x, s2, 0), 1)])           # j, k, l in L
+    for t in (1, -1):
+        # one index at p, two in L: P and Q of L with the label pair (x, p)
+        acc += ps.product(1.0, [(0, fL.P(x, p, t, s2, 0), 0), single(p, t, True)])
+        acc += ps.product(1.0, [(0, fL.Q(x, p, s2, t, 0), 0), single(p, t, False)])
+    idx = range(p + 1)
+    for j in idx:
+        for k in idx:
+            for l in idx:
+                if sum(1 for i in (j, k, l) if i == p) < 2 or eri[x, j, k, l] == 0.0:
+                    continue
+                for t in (1, -1):
+                    acc += ps.product(eri[x, j, k, l], [single(k, t, True), single(l, t, False), single(j, s2, False)])
     return acc
 
 

@@ -21,11 +21,13 @@
 // label l are products of single creation and annihilation operators; the
 // block Hamiltonian of L' is H restricted to the orbitals [0, l] with the
 // parts of two or more indices in L taken from the complementary operators
-// S_l, P_ll, Q_ll of L.  Spin-orbital products are projected onto the
+// S_l, P_ll, Q_ll of L; S_x of L' (x > l) is S_x of L plus the parts with
+// one index at l, which are P_xl and Q_xl of L times a single site operator,
+// plus explicit products.  Spin-orbital products are projected onto the
 // coupled form by their Q = K component (the same Clebsch-Gordan projection
-// the operator table of H.psi uses).  S, P and Q of L' are not produced: they
-// need complementary operators of L for every outside pair, while the H.psi
-// input keeps only the pairs that touch the two sites.
+// the operator table of H.psi uses).  P and Q of L' are not produced: they
+// need P and Q of L for every outside pair, while the H.psi input keeps only
+// the pairs that touch the two sites.
 #include <hip/hip_runtime.h>
 #include "common.hpp"
 #include "plan.hpp"
@@ -64,7 +66,8 @@ XcdQueues equal_cost_ranges(const std::vector<double> &cost) {
 
 const int RSITE_N[3] = {0, 1, 2};
 const int RSITE_S[3] = {0, 1, 0};
-constexpr int RENORM_DEFAULT_MASK = (1 << F_H) | (1 << F_C) | (1 << F_A0) | (1 << F_A1) | (1 << F_B0) | (1 << F_B1);
+constexpr int RENORM_DEFAULT_MASK =
+    (1 << F_H) | (1 << F_C) | (1 << F_A0) | (1 << F_A1) | (1 << F_B0) | (1 << F_B1) | (1 << F_S);
 
 // factor of a spin-orbital product: part 0 the block (a family component),
 // part 1 the site (an elementary a+ (adj 0) or a~ (adj 1) component)
@@ -202,8 +205,9 @@ int project_rank(const std::vector<RProd> &prods, SiteAlgebra &site, int K2,
   return DMRG_OK;
 }
 
-// label lists of the left block's normal families at bond p (orbitals [0, p))
-std::vector<std::array<int, 2>> left_labels(int fam, int p) {
+// label lists of the left block's families H, C, A, B and S at bond p
+// (orbitals [0, p); S: outside orbitals [p, n))
+std::vector<std::array<int, 2>> left_labels(int fam, int p, int n) {
   std::vector<std::array<int, 2>> res;
   auto grouped = [&](bool strict) {
     for (int x = 0; x < p; x++) for (int y = x + 1; y < p; y++) res.push_back({x, y});
@@ -214,6 +218,7 @@ std::vector<std::array<int, 2>> left_labels(int fam, int p) {
     case F_C: for (int i = 0; i < p; i++) res.push_back({i, -1}); break;
     case F_A0: case F_B0: case F_B1: grouped(false); break;
     case F_A1: grouped(true); break;
+    case F_S: for (int x = p; x < n; x++) res.push_back({x, -1}); break;
     default: break;
   }
   return res;
@@ -251,7 +256,7 @@ int build_terms(const dmrg_problem_t &pr, const BlockModel &L, SiteAlgebra &site
   auto v = [&](int i, int j, int k, int l) { return pr.eri[(((int64_t)i * n + j) * n + k) * n + l]; };
   for (int fam = 0; fam < N_FAM; fam++) {
     if (!(mask & (1 << fam))) continue;
-    auto labs = left_labels(fam, p + 1);
+    auto labs = left_labels(fam, p + 1, n);
     for (int pos = 0; pos < (int)labs.size(); pos++) {
       const int x = labs[pos][0], y = labs[pos][1];
       if (fam == F_H) {
@@ -350,6 +355,79 @@ int build_terms(const dmrg_problem_t &pr, const BlockModel &L, SiteAlgebra &site
         }
         continue;
       }
+      if (fam == F_S) {
+        // S_x of L' (x > l): component +1/2 = -(S_x)_dn / sqrt2 with
+        // (S_x)_s = sum_{j,k,l in [0, l]} (xj|kl) E_kl a_js; the part inside L
+        // is the stored S_x, the parts with one index at l are
+        // sum_t (P_xl)_ts a+_lt and sum_t (Q_xl)_st a_lt of L, the rest explicit
+        const double scale = -1.0 / std::sqrt(2.0);
+        const int s = -1;
+        {
+          RTerm t;
+          t.fam = fam; t.pos = pos;
+          t.ta.kind = 1; t.ta.id = F_S; t.ta.adj = 0; t.ta.k2 = 1; t.ta.par = FAM_PAR[F_S];
+          t.posA = L.pos(F_S, x);
+          if (t.posA < 0) { err = {DMRG_EINVAL, "left block lacks S for an outside orbital"}; return err.code; }
+          t.alpha = 1.0;
+          terms.push_back(t);
+        }
+        // (P_xl)_ts = -(P_lx)_st; (P_lx)_st = (-1)^(1+s+t) sum_K <1/2 -s, 1/2 -t|K -s-t> P^K_{-s-t}
+        {
+          std::vector<RProd> pp;
+          for (int t : sp)
+            for (int K = 0; K <= 2; K += 2) {
+              double cP = sgn2(2 + s + t) * cg(1, -s, 1, -t, K, -s - t);
+              if (cP == 0.0) continue;
+              RProd q;
+              q.coef = -scale * cP;
+              q.f.push_back(famc(K == 0 ? F_P0 : F_P1, 0, -s - t));
+              q.f.push_back(elem(p, p, t, true, q.coef));
+              pp.push_back(q);
+            }
+          if (add_projected(pp, site, L, fam, pos, p, x, terms, err)) return err.code;
+        }
+        // sum_t (Q_xl)_st a_lt = [sum_t a+_lt (Q_lx)_ts]^+
+        {
+          std::vector<RProd> pp;
+          for (int t : sp) {
+            std::vector<std::pair<double, RF>> parts;
+            if (s == t) parts.push_back({-1.0 / std::sqrt(2.0), famc(F_Q0, 0, 0)});
+            double c1 = cg(1, s, 1, -t, 2, s - t);
+            if (c1 != 0.0) parts.push_back({-sgn2(1 + t) * c1 / std::sqrt(3.0), famc(F_Q1, 0, s - t)});
+            for (auto &qp : parts) {
+              RProd q;
+              q.coef = scale * qp.first;
+              q.f.push_back(elem(p, p, t, true, q.coef));
+              q.f.push_back(qp.second);
+              pp.push_back(adjoint(q));
+            }
+          }
+          if (add_projected(pp, site, L, fam, pos, p, x, terms, err)) return err.code;
+        }
+        // two or three of j, k, l at l: explicit, one instance per L orbital
+        for (int li = -1; li < p; li++) {
+          std::vector<RProd> pp;
+          for (int j = 0; j <= p; j++)
+            for (int k = 0; k <= p; k++)
+              for (int l = 0; l <= p; l++) {
+                int atp = (j == p) + (k == p) + (l == p);
+                if (atp < 2 || v(x, j, k, l) == 0.0) continue;
+                int which = j < p ? j : k < p ? k : l < p ? l : -1;
+                if (which != li) continue;
+                for (int t : sp) {
+                  RProd q;
+                  q.coef = scale * v(x, j, k, l);
+                  q.f.push_back(elem(k, p, t, true, q.coef));
+                  q.f.push_back(elem(l, p, t, false, q.coef));
+                  q.f.push_back(elem(j, p, s, false, q.coef));
+                  pp.push_back(q);
+                }
+              }
+          if (pp.empty()) continue;
+          if (add_projected(pp, site, L, fam, pos, li, -1, terms, err)) return err.code;
+        }
+        continue;
+      }
       if (x < p && (y < 0 || y < p)) {
         // a member of L: [A (x) 1]
         RTerm t;
@@ -435,7 +513,7 @@ int build_renorm(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int n_kee
   }
   if (mask == 0) mask = RENORM_DEFAULT_MASK;
   if (mask & ~RENORM_DEFAULT_MASK) {
-    err = {DMRG_EINVAL, "only H, C, A0, A1, B0, B1 of the enlarged block are produced"};
+    err = {DMRG_EINVAL, "only H, C, A0, A1, B0, B1 and S of the enlarged block are produced"};
     return err.code;
   }
   const int n4 = pr.n_orb;
@@ -543,7 +621,7 @@ int build_renorm(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int n_kee
     r.fam = kv.first[0];
     r.row_sec = kv.first[1];
     r.col_sec = kv.first[2];
-    r.npos = (int32_t)left_labels(r.fam, pr.site_l + 1).size();
+    r.npos = (int32_t)left_labels(r.fam, pr.site_l + 1, pr.n_orb).size();
     r.off = B.out_len;
     kv.second = B.out_len;
     B.out_len += (int64_t)r.npos * keep[r.row_sec].kept * keep[r.col_sec].kept;

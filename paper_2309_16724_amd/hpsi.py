@@ -218,7 +218,7 @@ class Plan:
 
 class Renorm:
     """Renormalization of a problem's left block through its left site on the
-    GPU (dmrg_renorm_*): the families H, C, A0, A1, B0, B1 of the block
+    GPU (dmrg_renorm_*): the families H, C, A0, A1, B0, B1, S of the block
     [0, site_l] in the kept basis.  ``keep`` is [(n, 2S, U)] with U a host
     array (rows of that product sector x kept) or ``u`` a device tensor that
     already holds the matrices at the offsets ``keep_array`` would give."""

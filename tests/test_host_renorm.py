@@ -90,7 +90,8 @@ def test_renorm_error_codes(lib):
         return lib.dmrg_debug_renorm_host(ctypes.byref(a.s), ctypes.addressof(k), nk, mask, None, ul, None, 0,
                                           None, 0, ctypes.byref(st))
     assert call() == 0
-    assert call(mask=1 << cat.S) == -1                # S, P, Q are not produced
+    assert call(mask=1 << cat.P0) == -1               # P, Q are not produced
+    assert call(mask=1 << cat.Q1) == -1
     assert call(ul=ulen - 1) == -3                     # U beyond its array
     bad = (B.RKeep * 1)(B.RKeep(99, 0, 1, 0, 0))
     assert call(k=bad, nk=1) == -2                     # no such product sector

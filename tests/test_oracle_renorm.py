@@ -122,6 +122,15 @@ def test_planted_mistakes_are_caught():
             compare(got, big, cat.B0, 1e-12)
     finally:
         R._ProductSpace.__init__ = orig_jw
+    # S of the enlarged block without its Q_xp part
+    orig_q = R.Factors.Q
+    R.Factors.Q = lambda self, x, y, t, s, side: {} if x > y else orig_q(self, x, y, t, s, side)
+    try:
+        got = renormalize(prob, keep, families=(cat.S,))
+        with pytest.raises(AssertionError):
+            compare(got, big, cat.S, 1e-12)
+    finally:
+        R.Factors.Q = orig_q
 
 
 def test_hamiltonian_is_symmetric_and_identity_keeps_l_members():
