@@ -148,7 +148,7 @@ class MBlock:
         return out
 
     def labels(self, fam):
-        return cat.labels(fam, self.blk.role, self.blk.n_orb, self.blk.p)
+        return cat.labels(fam, self.blk.role, self.blk.n_orb, self.blk.p, getattr(self.blk, "all_pairs", False))
 
     def pos(self, fam, lab):
         return self.labels(fam).index(tuple(lab))

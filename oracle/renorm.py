@@ -34,7 +34,12 @@ ascending, then m = 0 (empty), 1 (one electron), 2 (doubly occupied), each
 contributing d_a consecutive rows in the order of the L sector's states.
 
 Families produced: H, C, A0, A1, B0, B1 and S of the left block at bond
-p + 1.  S_x of the new block (x > p) is (S_x)_s = sum over j, k, l in [0, p]
+p + 1, and P0, P1, Q0, Q1 when the left block holds P and Q for every pair
+of its outside orbitals (``all_pairs``; the new block then holds them for
+every pair of its own).  With (P_xy)_ts = sum (xj|yl) a_lt a_js and
+(Q_xy)_ts = delta_ts sum (xy|kl) E_kl - sum (xl|ky) a+_ks a_lt over the
+block's orbitals, the new block's are those of L (same pair) plus the terms
+with an index at p, explicit.  S_x of the new block (x > p) is (S_x)_s = sum over j, k, l in [0, p]
 of (xj|kl) E_kl a_js: its part inside L is the stored S_x; the parts with one
 index at p are sum_t (P_xp)_ts a+_pt and sum_t (Q_xp)_st a_pt of L (the same
 spin-orbital forms of P and Q that H_eff uses); the rest is explicit.
@@ -51,6 +56,7 @@ from .hpsi import MBlock, Factors, SITE_N, SITE_2M, SITE_MULT_STATES, site_cre, 
 from .layout import SITE
 
 RENORM_FAMILIES = (cat.H, cat.C, cat.A0, cat.A1, cat.B0, cat.B1, cat.S)
+PAIR_FAMILIES = (cat.P0, cat.P1, cat.Q0, cat.Q1)
 
 
 def product_sectors(lsec):
@@ -174,6 +180,8 @@ def _target(ps, fam, lab, q, p, h, eri):
         for coef, fs in _h_terms(ps, p, h, eri):
             acc += ps.product(coef, fs)
         return acc
+    if fam in PAIR_FAMILIES:
+        return _pq_component(ps, fam, lab, q, p, eri)
     if fam == cat.S:
         # component q of the S tensor: (S_x)_s = -sqrt2 (-1)^(1/2+s) S_{-s}, so
         # S_q = -(S_x)_{-q} / (sqrt2 (-1)^(1/2-q))
@@ -234,6 +242,70 @@ def _s_spin(ps, x, s2, p, eri):
     return acc
 
 
+def _pq_spin(ps, fam, x, y, t, s, p, eri):
+    """(P_xy)_ts or (Q_xy)_ts of the enlarged block (x, y > p)."""
+    fL = ps.fL
+
+    def single(z, t2, dagger):
+        if z < p:
+            return (0, fL.cre(z, t2, 0) if dagger else fL.T("cre", z, t2, 0), 1)
+        return (1, site_cre(t2) if dagger else site_ann(t2), 1)
+
+    idx = range(p + 1)
+    if fam in (cat.P0, cat.P1):
+        acc = ps.product(1.0, [(0, fL.P(x, y, t, s, 0), 0)])
+        for j in idx:
+            for l in idx:
+                if (j < p and l < p) or eri[x, j, y, l] == 0.0:
+                    continue
+                acc += ps.product(eri[x, j, y, l], [single(l, t, False), single(j, s, False)])
+        return acc
+    acc = ps.product(1.0, [(0, fL.Q(x, y, t, s, 0), 0)])
+    for k in idx:
+        for l in idx:
+            if k < p and l < p:
+                continue
+            if t == s and eri[x, y, k, l] != 0.0:
+                for sg in (1, -1):
+                    acc += ps.product(eri[x, y, k, l], [single(k, sg, True), single(l, sg, False)])
+            if eri[x, l, k, y] != 0.0:
+                acc += ps.product(-eri[x, l, k, y], [single(k, s, True), single(l, t, False)])
+    return acc
+
+
+def _pq_component(ps, fam, lab, q, p, eri):
+    """Tensor component q of P^K or Q^K of the enlarged block from its
+    spin-orbital forms, inverting
+      (P_xy)_ts = (-1)^(1+t+s) sum_K <1/2 -t, 1/2 -s|K -t-s> P^K_{-t-s},
+      (Q_xy)_ts = -delta_ts Q0 / sqrt2 + a_ts Q1_{s-t},
+      a_ts = -(-1)^(1/2+t) <1/2 s, 1/2 -t|1 s-t> / sqrt3
+    (Clebsch-Gordan orthogonality for P; Q0 from the trace, where the Q1
+    parts cancel; Q1_q = sum a_ts (Q)_ts / sum a_ts^2, where the Q0 parts
+    cancel)."""
+    x, y = lab
+    K = 0 if fam in (cat.P0, cat.Q0) else 2
+    ph = lambda e2: -1.0 if (e2 // 2) % 2 else 1.0
+    coefs = []
+    for t in (1, -1):
+        for s in (1, -1):
+            if fam in (cat.P0, cat.P1):
+                if -t - s == q:
+                    coefs.append((t, s, cg(1, -t, 1, -s, K, q) * ph(2 + t + s)))
+            elif fam == cat.Q0:
+                if t == s:
+                    coefs.append((t, s, -1.0 / np.sqrt(2.0)))
+            elif s - t == q:
+                coefs.append((t, s, -ph(1 + t) * cg(1, s, 1, -t, 2, q) / np.sqrt(3.0)))
+    if fam == cat.Q1:
+        norm = sum(c * c for _, _, c in coefs)
+        coefs = [(t, s, c / norm) for t, s, c in coefs]
+    acc = np.zeros((ps.dim, ps.dim))
+    for t, s, c in coefs:
+        if c != 0.0:
+            acc += c * _pq_spin(ps, fam, x, y, t, s, p, eri)
+    return acc
+
+
 def _coupled(ps, lsec, comps, U, two_s, M2):
     """Product-space vectors of the kept states of one L' sector at projection M2."""
     V = np.zeros((ps.dim, U.shape[1]))
@@ -252,15 +324,16 @@ def _coupled(ps, lsec, comps, U, two_s, M2):
     return V
 
 
-def renormalize(prob, keep, families=RENORM_FAMILIES):
+def renormalize(prob, keep, families=None):
     """Operators of the enlarged left block [0, p + 1).
 
     prob: a Problem whose left block and integrals are used (p = prob.p >= 1).
     keep: list of (N, 2S, U) with U a [rows of that product sector, kept]
     array; sectors not listed are dropped.  Returns a BlockData (role "L",
     bond p + 1) whose sectors are (N, 2S, kept) in the order of ``keep`` and
-    whose records hold the requested families (blocks that are zero to
-    1e-13 are left out)."""
+    whose records hold the requested families (default: H, C, A0, A1, B0,
+    B1, S, and P0, P1, Q0, Q1 for an all-pairs left block; blocks that are
+    zero to 1e-13 are left out)."""
     blk, p = prob.left, prob.p
     assert p >= 1
     ps = _ProductSpace(blk)
@@ -282,10 +355,14 @@ def renormalize(prob, keep, families=RENORM_FAMILIES):
             cache[key] = _coupled(ps, lsec, comps, U, sectors[i][1], M2)
         return cache[key]
 
-    out = BlockData("L", prob.n_orb, p + 1, sectors)
+    all_pairs = getattr(blk, "all_pairs", False)
+    if families is None:
+        families = RENORM_FAMILIES + (PAIR_FAMILIES if all_pairs else ())
+    assert all_pairs or not set(families) & set(PAIR_FAMILIES), "P, Q need a left block with all pairs"
+    out = BlockData("L", prob.n_orb, p + 1, sectors, all_pairs=all_pairs)
     fam_blocks = {}
     for fam in families:
-        labs = cat.labels(fam, "L", prob.n_orb, p + 1)
+        labs = cat.labels(fam, "L", prob.n_orb, p + 1, all_pairs)
         k2 = cat.TWO_K[fam]
         per = []
         for lab in labs:

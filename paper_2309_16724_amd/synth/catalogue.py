@@ -34,6 +34,9 @@ Label order (fixes the position index of every family member):
   left-block pairs (P, Q on L): lexicographic (x outer, y inner).
 This grouping keeps the positions of the partner operators of one
 operator-table row consecutive, so their products form long stripes.
+A left block may instead hold P and Q for every pair of its outside orbitals
+(``all_pairs``: x <= y, x < y for P1, both in [p, L), lexicographic), the
+form a renormalization needs to produce P and Q of the next block.
 """
 
 H, C, A0, A1, B0, B1, S, P0, P1, Q0, Q1 = range(11)
@@ -52,8 +55,9 @@ def outside(role: str, n_orb: int, p: int):
     return list(range(p, n_orb)) if role == "L" else list(range(0, p + 2))
 
 
-def labels(fam: int, role: str, n_orb: int, p: int):
-    """Canonical label list of a family on block ``role``."""
+def labels(fam: int, role: str, n_orb: int, p: int, all_pairs: bool = False):
+    """Canonical label list of a family on block ``role`` (``all_pairs``: a
+    left block's P and Q over every outside pair)."""
     lo, hi = block_range(role, n_orb, p)
     inside = list(range(lo, hi))
     if fam == H:
@@ -74,7 +78,7 @@ def labels(fam: int, role: str, n_orb: int, p: int):
     for x in out:
         for y in out:
             if (x < y) if strict else (x <= y):
-                if x >= p + 2 and y >= p + 2:
+                if x >= p + 2 and y >= p + 2 and not all_pairs:
                     continue
                 res.append((x, y))
     return res

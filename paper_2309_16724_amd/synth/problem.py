@@ -39,6 +39,11 @@ class BlockData:
     # exact blocks only: per sector a list (over M = S, S-1, ..., -S) of
     # Fock-space matrices (4^n x dim); plus the block's orbital range
     basis: list = None
+    # left blocks: P and Q over every outside pair (catalogue.labels)
+    all_pairs: bool = False
+
+    def labels(self, fam):
+        return cat.labels(fam, self.role, self.n_orb, self.p, self.all_pairs)
 
     @property
     def dim(self):
@@ -372,7 +377,7 @@ def _pack(block: BlockData, fam_blocks):
     block.data = np.concatenate(chunks) if chunks else np.zeros(0)
 
 
-def build_exact_block(role, n_orb, p, h, eri, max_mult=None):
+def build_exact_block(role, n_orb, p, h, eri, max_mult=None, all_pairs=False):
     lo, hi = cat.block_range(role, n_orb, p)
     orbs = list(range(lo, hi))
     n = len(orbs)
@@ -395,11 +400,11 @@ def build_exact_block(role, n_orb, p, h, eri, max_mult=None):
         sectors.append((key[0], key[1], hw.shape[1]))
         ladder = _m_ladder(hw, key[1], Sm)
         basis.append(ladder)
-    blk = BlockData(role, n_orb, p, sectors, basis=basis)
+    blk = BlockData(role, n_orb, p, sectors, basis=basis, all_pairs=all_pairs and role == "L")
     fams = cat.LEFT_FAMILIES if role == "L" else cat.RIGHT_FAMILIES
     fam_blocks = {}
     for fam in fams:
-        labs = cat.labels(fam, role, n_orb, p)
+        labs = blk.labels(fam)
         if fam == cat.H:
             per = [_reduce({0: H}, 0, basis, sectors)]
         else:
@@ -421,12 +426,13 @@ def build_exact_block(role, n_orb, p, h, eri, max_mult=None):
     return blk
 
 
-def exact_problem(n_orb, n_elec, two_s, seed, p=None, max_mult=None):
-    """Problem with blocks built exactly from their Fock spaces."""
+def exact_problem(n_orb, n_elec, two_s, seed, p=None, max_mult=None, all_pairs=False):
+    """Problem with blocks built exactly from their Fock spaces (all_pairs:
+    the left block's P and Q over every outside pair)."""
     h, eri = make_integrals(n_orb, seed)
     if p is None:
         p = middle_bond(n_orb)
-    left = build_exact_block("L", n_orb, p, h, eri, max_mult)
+    left = build_exact_block("L", n_orb, p, h, eri, max_mult, all_pairs)
     right = build_exact_block("R", n_orb, p, h, eri, max_mult)
     return Problem(n_orb, n_elec, two_s, p, h, eri, left, right, "exact")
 
@@ -461,14 +467,14 @@ def synthetic_sectors(n, n_share, D, rng, spin_ratio=0.6, sigma_frac=0.15, cap=T
     return secs
 
 
-def _rand_records(role, n_orb, p, sectors, fams):
+def _rand_records(role, n_orb, p, sectors, fams, all_pairs=False):
     """Record list [(fam, row_sec, col_sec, npos)] of a synthetic block: every
     (row, column) sector pair the family's electron change and spin rank
     allow (block Hamiltonian: diagonal pairs only), families in order, pairs
     sorted (the packing order of ``_pack``)."""
     recs = []
     for fam in sorted(fams):
-        npos = len(cat.labels(fam, role, n_orb, p))
+        npos = len(cat.labels(fam, role, n_orb, p, all_pairs))
         if npos == 0:
             continue
         k2, dn = cat.TWO_K[fam], cat.DN[fam]
@@ -497,11 +503,11 @@ def _fill_record(data, off, npos, db, da, seed, key, scale):
     return rng
 
 
-def _rand_block(role, n_orb, p, sectors, seed, op_scale, share, n):
+def _rand_block(role, n_orb, p, sectors, seed, op_scale, share, n, all_pairs=False):
     """Synthetic block: records, packed data, self-adjoint constraints."""
-    blk = BlockData(role, n_orb, p, sectors)
+    blk = BlockData(role, n_orb, p, sectors, all_pairs=all_pairs)
     fams = cat.LEFT_FAMILIES if role == "L" else cat.RIGHT_FAMILIES
-    recs = _rand_records(role, n_orb, p, sectors, fams) if n > 0 else []
+    recs = _rand_records(role, n_orb, p, sectors, fams, all_pairs) if n > 0 else []
     offs, off = [], 0
     for (fam, b, a, npos) in recs:
         offs.append(off)
@@ -539,7 +545,7 @@ def _rand_block(role, n_orb, p, sectors, seed, op_scale, share, n):
         if fam == cat.H:
             diag = [0]
         elif fam in (cat.B0, cat.B1, cat.Q0, cat.Q1):
-            diag = [k for k, lab in enumerate(cat.labels(fam, role, n_orb, p)) if lab[0] == lab[1]]
+            diag = [k for k, lab in enumerate(blk.labels(fam)) if lab[0] == lab[1]]
         else:
             continue
         if b == a:
@@ -560,7 +566,7 @@ def _rand_block(role, n_orb, p, sectors, seed, op_scale, share, n):
 
 
 def random_problem(n_orb, n_elec, two_s, seed, D, p=None, spin_ratio=0.6,
-                   sigma_frac=0.15, op_scale=0.3, cap=True, D_right=None):
+                   sigma_frac=0.15, op_scale=0.3, cap=True, D_right=None, all_pairs=False):
     """Problem with synthetic sector tables and random reduced operators.
 
     D multiplets per block (D_right for the right block when given).  Every
@@ -578,7 +584,8 @@ def random_problem(n_orb, n_elec, two_s, seed, D, p=None, spin_ratio=0.6,
         Db = D if role == "L" or D_right is None else D_right
         secs = synthetic_sectors(n, share, Db, None, spin_ratio, sigma_frac, cap) if n > 0 \
             else [(0, 0, 1)]
-        blocks.append(_rand_block(role, n_orb, p, secs, 10_000_000 + seed, op_scale, share, n))
+        blocks.append(_rand_block(role, n_orb, p, secs, 10_000_000 + seed, op_scale, share, n,
+                                  all_pairs and role == "L"))
     return Problem(n_orb, n_elec, two_s, p, h, eri, blocks[0], blocks[1], "random")
 
 

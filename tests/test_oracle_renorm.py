@@ -168,3 +168,18 @@ def test_hamiltonian_is_symmetric_and_identity_keeps_l_members():
                             assert np.allclose(a, rr * b, atol=1e-10 * np.abs(b).max())
                             ratio = rr if ratio is None else ratio
                             assert abs(rr - ratio) < 1e-10
+
+
+@pytest.mark.parametrize("n_orb,p,max_mult", [(6, 2, None), (7, 3, None), (7, 3, 40)])
+def test_pair_families_match_fock_space(n_orb, p, max_mult):
+    """P and Q of the enlarged block from a left block holding them for every
+    outside pair, against the Fock-space block in the same form."""
+    from oracle.renorm import PAIR_FAMILIES
+    prob = exact_problem(n_orb, n_orb, n_orb % 2, 24, p=p, all_pairs=True)
+    big = build_exact_block("L", n_orb, p + 1, prob.h, prob.eri, max_mult=max_mult, all_pairs=True)
+    keep = exact_keep(prob.left, big)
+    got = renormalize(prob, keep)
+    assert got.all_pairs
+    for fam in RENORM_FAMILIES + PAIR_FAMILIES:
+        assert dense_records(big, fam), cat.NAMES[fam]
+        compare(got, big, fam, 1e-12)
