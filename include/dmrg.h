@@ -377,7 +377,8 @@ const char *dmrg_last_error(void);
  * is accepted).  The new block's sectors are the keep entries, in their
  * order: (n, two_s, kept).
  *
- * Output: the families H, C, A0, A1, B0, B1, S of the new block (labels of a left
+ * Output: the families H, C, A0, A1, B0, B1, S (and with DMRG_RENORM_ALL_PAIRS
+ * also P0, P1, Q0, Q1) of the new block (labels of a left
  * block at bond site_l + 1), as records in the input format -- one per
  * (family, row sector, column sector) with any contribution, all positions,
  * [npos][kept_row][kept_col] column-major -- in a caller-owned DEVICE array
@@ -387,9 +388,15 @@ const char *dmrg_last_error(void);
  * [0, l], with the parts of two or more indices in the old block taken from
  * its S_l, P_ll and Q_ll; S_x (x > l) is S_x of the old block plus its P_xl
  * and Q_xl times single site operators plus explicit products.  P and Q of
- * the new block are not produced (they need P and Q of the old block for
- * every outside pair; the H.psi input keeps only the pairs touching the two
- * sites): a fam_mask naming them is DMRG_EINVAL.
+ * the new block need P and Q of the old block for every outside pair, while
+ * the H.psi input keeps only the pairs touching the two sites: with the flag
+ * DMRG_RENORM_ALL_PAIRS the left block's P0, P1, Q0, Q1 records hold every
+ * pair (x, y) of outside orbitals (x <= y, x < y for P1, lexicographic; the
+ * other families as in the family table) and the new block's P, Q come out
+ * in the same form, (P_xy)_ts = sum (xj|yl) a_lt a_js and
+ * (Q_xy)_ts = delta_ts sum (xy|kl) E_kl - sum (xl|ky) a+_ks a_lt being those
+ * of the old block plus their terms with an index at l.  Without the flag a
+ * fam_mask naming P or Q is DMRG_EINVAL.
  *
  * dmrg_renorm_create builds the term and product lists on the host and
  * copies them to the device (hipMalloc, freed by dmrg_renorm_free); the
@@ -418,10 +425,12 @@ typedef struct {
  * output may be NULL (counts only); DMRG_ERANGE when a capacity is short. */
 int dmrg_renorm_product(const dmrg_problem_t *prob, dmrg_sector_t *sec, int32_t sec_cap, int32_t *n_sec,
                         dmrg_rcomp_t *comp, int32_t comp_cap, int32_t *n_comp);
-/* fam_mask: bit f for family f (0 = H, C, A0, A1, B0, B1, S); u_len: elements of
- * the U array that dmrg_renorm_apply will be given. */
+/* fam_mask: bit f for family f (0 = every family the flags allow); flags:
+ * 0 or DMRG_RENORM_ALL_PAIRS; u_len: elements of the U array that
+ * dmrg_renorm_apply will be given. */
+enum { DMRG_RENORM_ALL_PAIRS = 1 };
 int dmrg_renorm_create(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int32_t n_keep, int32_t fam_mask,
-                       int64_t u_len, dmrg_renorm_t **out);
+                       int32_t flags, int64_t u_len, dmrg_renorm_t **out);
 /* Output records (rec may be NULL to size) and the output length. */
 int dmrg_renorm_records(const dmrg_renorm_t *r, dmrg_oprec_t *rec, int64_t cap, int64_t *n_rec, int64_t *data_len);
 int dmrg_renorm_apply(dmrg_renorm_t *r, const double *u, double *out, void *stream);
@@ -465,7 +474,7 @@ int64_t dmrg_debug_plan_tiles(const dmrg_problem_t *prob, const dmrg_plan_opts_t
  * addressing (u, out HOST; out = NULL: statistics only); rec (may be NULL)
  * receives up to rec_cap output records. */
 int dmrg_debug_renorm_host(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int32_t n_keep, int32_t fam_mask,
-                           const double *u, int64_t u_len, double *out, int64_t out_len, dmrg_oprec_t *rec,
+                           int32_t flags, const double *u, int64_t u_len, double *out, int64_t out_len, dmrg_oprec_t *rec,
                            int64_t rec_cap, dmrg_renorm_stats_t *st);
 /* Test-only: the host eigensolver dmrg_davidson applies to its projected
  * matrix (cyclic Jacobi).  A: m x m symmetric, row-major, HOST, 1 <= m <= 64;

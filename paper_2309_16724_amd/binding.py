@@ -19,6 +19,7 @@ DMRG_SPLIT_BF16 = 1
 DMRG_PLAN_GRAPH = 1
 DMRG_PLAN_XCD = 2
 DMRG_PLAN_AUTOTUNE = 4
+DMRG_RENORM_ALL_PAIRS = 1
 
 
 class Sector(ctypes.Structure):
@@ -170,7 +171,8 @@ def load(path=None):
     if hasattr(L, "dmrg_renorm_create"):
         L.dmrg_renorm_product.argtypes = [ctypes.POINTER(ProblemT), c_vp, c_i32, ctypes.POINTER(c_i32), c_vp,
                                           c_i32, ctypes.POINTER(c_i32)]
-        L.dmrg_renorm_create.argtypes = [ctypes.POINTER(ProblemT), c_vp, c_i32, c_i32, c_i64, ctypes.POINTER(c_vp)]
+        L.dmrg_renorm_create.argtypes = [ctypes.POINTER(ProblemT), c_vp, c_i32, c_i32, c_i32, c_i64,
+                                         ctypes.POINTER(c_vp)]
         L.dmrg_renorm_records.argtypes = [c_vp, c_vp, c_i64, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]
         L.dmrg_renorm_apply.argtypes = [c_vp, c_vp, c_vp, c_vp]
         L.dmrg_renorm_stats.argtypes = [c_vp, ctypes.POINTER(RenormStats)]
@@ -179,8 +181,8 @@ def load(path=None):
                                               ctypes.POINTER(c_dbl)]
         L.dmrg_renorm_free.argtypes = [c_vp]
         L.dmrg_renorm_free.restype = None
-        L.dmrg_debug_renorm_host.argtypes = [ctypes.POINTER(ProblemT), c_vp, c_i32, c_i32, c_vp, c_i64, c_vp,
-                                             c_i64, c_vp, c_i64, ctypes.POINTER(RenormStats)]
+        L.dmrg_debug_renorm_host.argtypes = [ctypes.POINTER(ProblemT), c_vp, c_i32, c_i32, c_i32, c_vp, c_i64,
+                                             c_vp, c_i64, c_vp, c_i64, ctypes.POINTER(RenormStats)]
     if path is None:
         _lib = L
     return L
@@ -315,7 +317,8 @@ def keep_array(keep):
 def records_block(prob, keep, recs, data):
     """Output of a renormalization as the oracle's BlockData (role L, bond p + 1)."""
     from .synth.problem import BlockData
-    blk = BlockData("L", prob.n_orb, prob.p + 1, [(n, S, np.asarray(U).shape[1]) for (n, S, U) in keep])
+    blk = BlockData("L", prob.n_orb, prob.p + 1, [(n, S, np.asarray(U).shape[1]) for (n, S, U) in keep],
+                    all_pairs=getattr(prob.left, "all_pairs", False))
     blk.records = [(r.fam, r.row_sec, r.col_sec, r.off, r.npos) for r in recs]
     blk.data = np.asarray(data, dtype=np.float64)
     return blk
@@ -329,13 +332,14 @@ def debug_renorm_host(prob, keep, fam_mask=0, lib=None, execute=True):
     args = ProblemArgs(prob, ld.ctypes.data, 0)
     karr, u, ulen = keep_array(keep)
     st = RenormStats()
-    check(L.dmrg_debug_renorm_host(ctypes.byref(args.s), ctypes.addressof(karr), len(keep), fam_mask,
+    flags = DMRG_RENORM_ALL_PAIRS if getattr(prob.left, "all_pairs", False) else 0
+    check(L.dmrg_debug_renorm_host(ctypes.byref(args.s), ctypes.addressof(karr), len(keep), fam_mask, flags,
                                    None, ulen, None, 0, None, 0, ctypes.byref(st)), L)
     if not execute:
         return None, st.as_dict()
     out = np.zeros(max(1, st.out_elems))
     recs = (OpRec * max(1, st.n_records))()
-    check(L.dmrg_debug_renorm_host(ctypes.byref(args.s), ctypes.addressof(karr), len(keep), fam_mask,
+    check(L.dmrg_debug_renorm_host(ctypes.byref(args.s), ctypes.addressof(karr), len(keep), fam_mask, flags,
                                    u.ctypes.data, ulen, out.ctypes.data, out.size, ctypes.addressof(recs),
                                    st.n_records, ctypes.byref(st)), L)
     return records_block(prob, keep, recs[:st.n_records], out[:st.out_elems]), st.as_dict()

@@ -68,6 +68,8 @@ const int RSITE_N[3] = {0, 1, 2};
 const int RSITE_S[3] = {0, 1, 0};
 constexpr int RENORM_DEFAULT_MASK =
     (1 << F_H) | (1 << F_C) | (1 << F_A0) | (1 << F_A1) | (1 << F_B0) | (1 << F_B1) | (1 << F_S);
+constexpr int RENORM_PAIR_MASK = (1 << F_P0) | (1 << F_P1) | (1 << F_Q0) | (1 << F_Q1);
+constexpr int RENORM_ALL_PAIRS = 1;   // dmrg_renorm_create flag
 
 // factor of a spin-orbital product: part 0 the block (a family component),
 // part 1 the site (an elementary a+ (adj 0) or a~ (adj 1) component)
@@ -205,8 +207,9 @@ int project_rank(const std::vector<RProd> &prods, SiteAlgebra &site, int K2,
   return DMRG_OK;
 }
 
-// label lists of the left block's families H, C, A, B and S at bond p
-// (orbitals [0, p); S: outside orbitals [p, n))
+// label lists of the left block's families at bond p (orbitals [0, p); S:
+// outside orbitals [p, n); P, Q: every outside pair, lexicographic -- the
+// all-pairs form)
 std::vector<std::array<int, 2>> left_labels(int fam, int p, int n) {
   std::vector<std::array<int, 2>> res;
   auto grouped = [&](bool strict) {
@@ -219,7 +222,10 @@ std::vector<std::array<int, 2>> left_labels(int fam, int p, int n) {
     case F_A0: case F_B0: case F_B1: grouped(false); break;
     case F_A1: grouped(true); break;
     case F_S: for (int x = p; x < n; x++) res.push_back({x, -1}); break;
-    default: break;
+    default:
+      for (int x = p; x < n; x++)
+        for (int y = x + (fam == F_P1 ? 1 : 0); y < n; y++) res.push_back({x, y});
+      break;
   }
   return res;
 }
@@ -350,6 +356,80 @@ int build_terms(const dmrg_problem_t &pr, const BlockModel &L, SiteAlgebra &site
                       pp.push_back(q);
                     }
                 }
+          if (pp.empty()) continue;
+          if (add_projected(pp, site, L, fam, pos, li, -1, terms, err)) return err.code;
+        }
+        continue;
+      }
+      if (fam == F_P0 || fam == F_P1 || fam == F_Q0 || fam == F_Q1) {
+        // P^K / Q^K of L' for the pair (x, y) (x, y > l): the member of L for
+        // the same pair plus the terms with an index at l, explicit, from
+        //   (P_xy)_ts = sum (xj|yl) a_lt a_js,
+        //   (Q_xy)_ts = delta_ts sum (xy|kl) E_kl - sum (xl|ky) a+_ks a_lt,
+        // and the tensor components they carry:
+        //   P^K_K = sum_{-t-s=K} <1/2 -t, 1/2 -s|K K> (-1)^(1+t+s) (P_xy)_ts,
+        //   Q0 = -sum_s (Q_xy)_ss / sqrt2,  Q1_{+1} = -sqrt3 (Q_xy)_{dn up}
+        {
+          RTerm t;
+          t.fam = fam; t.pos = pos;
+          t.ta.kind = 1; t.ta.id = fam; t.ta.adj = 0; t.ta.k2 = FAM_TWO_K[fam]; t.ta.par = FAM_PAR[fam];
+          t.posA = L.pos(fam, x, y);
+          if (t.posA < 0) { err = {DMRG_EINVAL, "left block lacks P or Q for an outside pair"}; return err.code; }
+          t.alpha = 1.0;
+          terms.push_back(t);
+        }
+        const int K2 = FAM_TWO_K[fam];
+        std::vector<std::array<double, 3>> ts;    // (t, s, weight)
+        for (int t : sp)
+          for (int s2 : sp) {
+            if (fam == F_P0 || fam == F_P1) {
+              if (-t - s2 == K2) ts.push_back({(double)t, (double)s2, cg(1, -t, 1, -s2, K2, K2) * sgn2(2 + t + s2)});
+            } else if (fam == F_Q0) {
+              if (t == s2) ts.push_back({(double)t, (double)s2, -1.0 / std::sqrt(2.0)});
+            } else if (t == -1 && s2 == 1) {
+              ts.push_back({(double)t, (double)s2, -std::sqrt(3.0)});
+            }
+          }
+        for (int li = -1; li < p; li++) {
+          auto inst = [&](int i1, int i2) {
+            if (i1 < p && i2 < p) return false;
+            int which = i1 < p ? i1 : i2 < p ? i2 : -1;
+            return which == li;
+          };
+          std::vector<RProd> pp;
+          for (auto &w : ts) {
+            const int t = (int)w[0], s2 = (int)w[1];
+            if (w[2] == 0.0) continue;
+            for (int a = 0; a <= p; a++)
+              for (int b = 0; b <= p; b++) {
+                if (!inst(a, b)) continue;
+                if (fam == F_P0 || fam == F_P1) {         // j = a, l = b: (xj|yl) a_lt a_js
+                  double vv = v(x, a, y, b);
+                  if (vv == 0.0) continue;
+                  RProd q;
+                  q.coef = w[2] * vv;
+                  q.f.push_back(elem(b, p, t, false, q.coef));
+                  q.f.push_back(elem(a, p, s2, false, q.coef));
+                  pp.push_back(q);
+                } else {                                   // k = a, l = b
+                  if (t == s2 && v(x, y, a, b) != 0.0)
+                    for (int sg : sp) {
+                      RProd q;
+                      q.coef = w[2] * v(x, y, a, b);
+                      q.f.push_back(elem(a, p, sg, true, q.coef));
+                      q.f.push_back(elem(b, p, sg, false, q.coef));
+                      pp.push_back(q);
+                    }
+                  if (v(x, b, a, y) != 0.0) {
+                    RProd q;
+                    q.coef = -w[2] * v(x, b, a, y);
+                    q.f.push_back(elem(a, p, s2, true, q.coef));
+                    q.f.push_back(elem(b, p, t, false, q.coef));
+                    pp.push_back(q);
+                  }
+                }
+              }
+          }
           if (pp.empty()) continue;
           if (add_projected(pp, site, L, fam, pos, li, -1, terms, err)) return err.code;
         }
@@ -502,8 +582,53 @@ struct Built {
   double build_ms = 0.0;
 };
 
-int build_renorm(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int n_keep, int mask, int64_t u_len,
-                 Built &B, Error &err) {
+// The left block in the catalogue form (build_block) or, with all_pairs,
+// with P and Q over every outside pair: the other families are read as
+// usual and P, Q are checked and indexed here.
+int build_left(BlockModel &L, const dmrg_problem_t &pr, bool all_pairs, Error &err) {
+  if (!all_pairs) return build_block(L, 0, pr, err);
+  auto is_pq = [](int f) { return f == F_P0 || f == F_P1 || f == F_Q0 || f == F_Q1; };
+  std::vector<dmrg_oprec_t> other, pq;
+  for (int64_t i = 0; i < pr.n_lrec; i++) (is_pq(pr.lrec[i].fam) ? pq : other).push_back(pr.lrec[i]);
+  dmrg_problem_t p2 = pr;
+  p2.lrec = other.data();
+  p2.n_lrec = (int64_t)other.size();
+  if (build_block(L, 0, p2, err)) return err.code;
+  for (int f : {F_P0, F_P1, F_Q0, F_Q1}) {
+    L.labels[f] = left_labels(f, pr.site_l, pr.n_orb);
+    L.label_pos[f].clear();
+    for (size_t i = 0; i < L.labels[f].size(); i++) L.label_pos[f][L.labels[f][i]] = (int)i;
+  }
+  for (const dmrg_oprec_t &r : pq) {
+    const int ns = (int)L.sec.size();
+    if (r.row_sec < 0 || r.row_sec >= ns || r.col_sec < 0 || r.col_sec >= ns) {
+      err = {DMRG_EINVAL, "operator record with bad family or sector"};
+      return err.code;
+    }
+    if (r.npos != (int)L.labels[r.fam].size()) {
+      err = {DMRG_EINVAL, "record npos differs from the all-pairs label count"};
+      return err.code;
+    }
+    const auto &sr = L.sec[r.row_sec], &sc = L.sec[r.col_sec];
+    const int k2 = FAM_TWO_K[r.fam];
+    if (sr.n != sc.n + FAM_DN[r.fam] || sr.two_s < std::abs(sc.two_s - k2) || sr.two_s > sc.two_s + k2) {
+      err = {DMRG_ESYM, "operator record violates N or spin selection rules"};
+      return err.code;
+    }
+    if (r.off < 0 || r.off + (int64_t)r.npos * sr.dim * sc.dim > L.data_len) {
+      err = {DMRG_ERANGE, "operator record beyond its data array"};
+      return err.code;
+    }
+    const int64_t key = ((int64_t)r.fam * 1000003 + r.row_sec) * 1000003 + r.col_sec;
+    if (L.rec_index.count(key)) { err = {DMRG_EINVAL, "duplicate operator record"}; return err.code; }
+    L.rec_index[key] = (int)L.rec.size();
+    L.rec.push_back(r);
+  }
+  return DMRG_OK;
+}
+
+int build_renorm(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int n_keep, int mask, int flags,
+                 int64_t u_len, Built &B, Error &err) {
   auto t0 = std::chrono::steady_clock::now();
   if (!prob || !keep || n_keep <= 0) { err = {DMRG_EINVAL, "null problem or empty keep list"}; return err.code; }
   const dmrg_problem_t &pr = *prob;
@@ -511,9 +636,13 @@ int build_renorm(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int n_kee
     err = {DMRG_EINVAL, "renormalization needs a non-empty left block, the site and the integrals"};
     return err.code;
   }
-  if (mask == 0) mask = RENORM_DEFAULT_MASK;
-  if (mask & ~RENORM_DEFAULT_MASK) {
-    err = {DMRG_EINVAL, "only H, C, A0, A1, B0, B1 and S of the enlarged block are produced"};
+  const bool all_pairs = flags & RENORM_ALL_PAIRS;
+  if (flags & ~RENORM_ALL_PAIRS) { err = {DMRG_EINVAL, "unknown renormalization flag"}; return err.code; }
+  const int allowed = RENORM_DEFAULT_MASK | (all_pairs ? RENORM_PAIR_MASK : 0);
+  if (mask == 0) mask = allowed;
+  if (mask & ~allowed) {
+    err = {DMRG_EINVAL, all_pairs ? "unknown family in the mask"
+                                  : "P and Q of the enlarged block need a left block with all outside pairs"};
     return err.code;
   }
   const int n4 = pr.n_orb;
@@ -522,7 +651,7 @@ int build_renorm(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int n_kee
   for (int64_t i = 0; i < (int64_t)n4 * n4 * n4 * n4; i++)
     if (!std::isfinite(pr.eri[i])) { err = {DMRG_ENONFINITE, "non-finite two-electron integral"}; return err.code; }
   BlockModel L;
-  if (build_block(L, 0, pr, err)) return err.code;
+  if (build_left(L, pr, all_pairs, err)) return err.code;
   SiteAlgebra site;
   std::vector<RTerm> terms;
   if (build_terms(pr, L, site, mask, terms, err)) return err.code;
@@ -856,13 +985,13 @@ extern "C" int dmrg_renorm_product(const dmrg_problem_t *prob, dmrg_sector_t *se
 }
 
 extern "C" int dmrg_renorm_create(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int32_t n_keep,
-                                  int32_t fam_mask, int64_t u_len, dmrg_renorm_t **out) {
+                                  int32_t fam_mask, int32_t flags, int64_t u_len, dmrg_renorm_t **out) {
   if (!out) { set_error("null output"); return DMRG_EINVAL; }
   *out = nullptr;
   try {
     auto r = std::make_unique<dmrg_renorm>();
     Error err{0, ""};
-    if (build_renorm(prob, keep, n_keep, fam_mask, u_len, r->b, err)) { set_error(err.msg); return err.code; }
+    if (build_renorm(prob, keep, n_keep, fam_mask, flags, u_len, r->b, err)) { set_error(err.msg); return err.code; }
     if (!prob->ldata) { set_error("left operator data missing"); return DMRG_EINVAL; }
     r->ldata = prob->ldata;
     auto up = [&](void **dst, const void *src, size_t bytes) -> bool {
@@ -993,13 +1122,13 @@ extern "C" int dmrg_renorm_stats(const dmrg_renorm_t *r, dmrg_renorm_stats_t *st
 }
 
 extern "C" int dmrg_debug_renorm_host(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int32_t n_keep,
-                                      int32_t fam_mask, const double *u, int64_t u_len, double *out,
+                                      int32_t fam_mask, int32_t flags, const double *u, int64_t u_len, double *out,
                                       int64_t out_len, dmrg_oprec_t *rec, int64_t rec_cap,
                                       dmrg_renorm_stats_t *st) {
   try {
     Built b;
     Error err{0, ""};
-    if (build_renorm(prob, keep, n_keep, fam_mask, u_len, b, err)) { set_error(err.msg); return err.code; }
+    if (build_renorm(prob, keep, n_keep, fam_mask, flags, u_len, b, err)) { set_error(err.msg); return err.code; }
     if (st) {
       std::memset(st, 0, sizeof(*st));
       st->n_terms = b.n_terms;

@@ -218,7 +218,8 @@ class Plan:
 
 class Renorm:
     """Renormalization of a problem's left block through its left site on the
-    GPU (dmrg_renorm_*): the families H, C, A0, A1, B0, B1, S of the block
+    GPU (dmrg_renorm_*): the families H, C, A0, A1, B0, B1, S (and P, Q for a
+    left block that holds them for every outside pair) of the block
     [0, site_l] in the kept basis.  ``keep`` is [(n, 2S, U)] with U a host
     array (rows of that product sector x kept) or ``u`` a device tensor that
     already holds the matrices at the offsets ``keep_array`` would give."""
@@ -236,8 +237,9 @@ class Renorm:
         self.karr, flat, self.u_len = B.keep_array(keep)
         self.u = torch.from_numpy(flat).to(self.device)
         h = ctypes.c_void_p()
+        flags = B.DMRG_RENORM_ALL_PAIRS if getattr(prob.left, "all_pairs", False) else 0
         B.check(self.lib.dmrg_renorm_create(ctypes.byref(self.args.s), ctypes.addressof(self.karr), len(keep),
-                                            fam_mask, self.u_len, ctypes.byref(h)), self.lib)
+                                            fam_mask, flags, self.u_len, ctypes.byref(h)), self.lib)
         self.handle = h
         n, ln = ctypes.c_int64(), ctypes.c_int64()
         B.check(self.lib.dmrg_renorm_records(self.handle, None, 0, ctypes.byref(n), ctypes.byref(ln)), self.lib)

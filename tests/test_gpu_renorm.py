@@ -80,17 +80,34 @@ def test_renorm_matches_oracle(torch, case):
         assert d < TOL, (cat.NAMES[fam], d)
 
 
+def test_renorm_pair_families_match_oracle(torch):
+    """A left block holding P and Q for every outside pair: every family of
+    the enlarged block, P0, P1, Q0, Q1 included, against the oracle."""
+    from oracle.renorm import PAIR_FAMILIES
+    args = dict(n_orb=12, n_elec=12, two_s=0, seed=34, D=96, p=5, spin_ratio=0.3, sigma_frac=0.08, all_pairs=True)
+    _say("renorm all-pairs parity %s" % args)
+    prob = random_problem(**args)
+    keep = rand_keep(prob, 0.6, 8)
+    got, st = _gpu_block(prob, keep)
+    want = renormalize(prob, keep)
+    assert got.all_pairs
+    for fam in RENORM_FAMILIES + PAIR_FAMILIES:
+        d = rel_diff(got, want, fam)
+        assert d < TOL, (cat.NAMES[fam], d)
+
+
 def test_renorm_reproduces_fock_space_block(torch):
     """Untruncated exact left block: the GPU result in the exact enlarged
     block's basis is that block (Fock-space ground truth)."""
     from tests.test_oracle_renorm import exact_keep
     n_orb, p = 7, 3
     _say("renorm exact L=%d p=%d" % (n_orb, p))
-    prob = exact_problem(n_orb, 7, 1, 21, p=p)
-    big = build_exact_block("L", n_orb, p + 1, prob.h, prob.eri, max_mult=48)
+    from oracle.renorm import PAIR_FAMILIES
+    prob = exact_problem(n_orb, 7, 1, 21, p=p, all_pairs=True)
+    big = build_exact_block("L", n_orb, p + 1, prob.h, prob.eri, max_mult=48, all_pairs=True)
     keep = exact_keep(prob.left, big)
     got, _ = _gpu_block(prob, keep)
-    for fam in RENORM_FAMILIES:
+    for fam in RENORM_FAMILIES + PAIR_FAMILIES:
         assert rel_diff(got, big, fam) < TOL, cat.NAMES[fam]
 
 

@@ -87,7 +87,7 @@ def test_renorm_error_codes(lib):
     st = B.RenormStats()
 
     def call(a=args, k=karr, nk=len(keep), mask=0, ul=ulen):
-        return lib.dmrg_debug_renorm_host(ctypes.byref(a.s), ctypes.addressof(k), nk, mask, None, ul, None, 0,
+        return lib.dmrg_debug_renorm_host(ctypes.byref(a.s), ctypes.addressof(k), nk, mask, 0, None, ul, None, 0,
                                           None, 0, ctypes.byref(st))
     assert call() == 0
     assert call(mask=1 << cat.P0) == -1               # P, Q are not produced
@@ -104,3 +104,20 @@ def test_renorm_error_codes(lib):
     assert call(a=a0) == -1                            # empty left block
     args.eri[1, 2, 3, 4] = np.nan
     assert call() == -6
+
+
+@pytest.mark.parametrize("case", ["exact", "random"])
+def test_host_pair_families_match_oracle(lib, case):
+    """All-pairs left blocks: P0, P1, Q0, Q1 of the enlarged block (and the
+    other families) from the host-executed lists against the oracle."""
+    from oracle.renorm import PAIR_FAMILIES
+    if case == "exact":
+        prob = exact_problem(7, 7, 1, 25, p=3, all_pairs=True)
+    else:
+        prob = random_problem(10, 10, 0, 9, 32, p=4, all_pairs=True)
+    keep = rand_keep(prob, 0.6, 6)
+    want = renormalize(prob, keep)
+    got, st = B.debug_renorm_host(prob, keep, lib=lib)
+    assert got.all_pairs
+    for fam in RENORM_FAMILIES + PAIR_FAMILIES:
+        assert max_family_diff(got, want, fam) < 1e-12, cat.NAMES[fam]
