@@ -35,10 +35,13 @@ WORKLOADS = {
 GEN_KEYS = ("D", "spin_ratio", "sigma_frac")
 
 
-def make_problem(w):
+def make_problem(w, all_pairs=False):
+    """The workload's problem; all_pairs: its left block holds P and Q for
+    every outside pair (the form a renormalization of every family needs;
+    the other families are the same draws)."""
     from paper_2309_16724_amd.synth.problem import random_problem
     return random_problem(w["n_orb"], w["n_elec"], w["two_s"], w["seed"],
-                          **{k: w[k] for k in GEN_KEYS if k in w})
+                          **{k: w[k] for k in GEN_KEYS if k in w}, all_pairs=all_pairs)
 
 
 FP64_PEAK_TFLOPS = 78.6       # MI355X dense FP64 (matrix and vector)
@@ -142,8 +145,8 @@ MEASURED_TRAFFIC = {
     ("L54_D2048", "stage_f64_kernel<1>"): (3.5086e11, _F64_SRC, "69c8d5cbc4f75ca9"),
     ("L54_D2048", "stage_f64_kernel<2>"): (1.0639e12, _F64_SRC, "69c8d5cbc4f75ca9"),
     # renormalization of the L54_D2048 left block (profiles/renorm_L54_D2048_fp64.md)
-    ("L54_D2048", "renorm:stage_f64_kernel<1>"): (1.2457e11, _REN_SRC, "5061d91d70bbc02f"),
-    ("L54_D2048", "renorm:stage_f64_kernel<2>"): (1.5508e11, _REN_SRC, "5061d91d70bbc02f"),
+    ("L54_D2048", "renorm:stage_f64_kernel<1>"): (1.3443e11, _REN_SRC, "e42109076685ca83"),
+    ("L54_D2048", "renorm:stage_f64_kernel<2>"): (2.8595e11, _REN_SRC, "e42109076685ca83"),
 }
 
 
@@ -416,15 +419,22 @@ def davidson_runs(torch, args, plan_flags):
     return out
 
 
-def renorm_run(torch, prob, workload, steps, warmup):
-    """Renormalization of the workload's left block through its left site
-    (families H, C, A0, A1, B0, B1, S of the enlarged block, FP64): every product
-    sector keeps a quarter of its rows (about D states in all) through a U
-    with orthonormal columns (QR of a seeded Gaussian matrix).  Timed like
-    H.psi: warm-up, then `steps` applies bracketed by synchronisation."""
+def renorm_run(torch, workload, steps, warmup, prob=None, all_pairs=False):
+    """Renormalization of the workload's left block through its left site,
+    FP64: the families H, C, A0, A1, B0, B1, S of the enlarged block (with
+    all_pairs the left block is drawn with P and Q over every outside pair and
+    P0, P1, Q0, Q1 are produced too); every product sector keeps a quarter of
+    its rows (about D states in all) through a U with orthonormal columns (QR
+    of a seeded Gaussian matrix).  Timed like H.psi: warm-up, then `steps`
+    applies bracketed by synchronisation."""
     import numpy as np
     from paper_2309_16724_amd import binding as B
     from paper_2309_16724_amd.hpsi import Renorm
+    if prob is None or all_pairs:
+        t0 = time.time()
+        prob = make_problem(WORKLOADS[workload], all_pairs=all_pairs)
+        print("# left block of %s generated in %.1f s (%d elements)"
+              % (workload, time.time() - t0, prob.left.data.size), file=sys.stderr, flush=True)
     secs, _ = B.renorm_product(prob)
     rng = np.random.default_rng(7)
     keep = [(n, s2, np.linalg.qr(rng.standard_normal((rows, max(1, rows // 4))))[0]) for (n, s2, rows) in secs]
@@ -471,7 +481,8 @@ def renorm_run(torch, prob, workload, steps, warmup):
     return {"ms": ms, "tflops": tf, "flops": flops, "flops_stage1": st["flops1"], "flops_stage2": st["flops2"],
             "kept_states": int(sum(u.shape[1] for _, _, u in keep)),
             "product_states": int(sum(u.shape[0] for _, _, u in keep)),
-            "families": "H C A0 A1 B0 B1 S", "records": r.n_rec, "out_elems": st["out_elems"],
+            "families": "H C A0 A1 B0 B1 S" + (" P0 P1 Q0 Q1" if all_pairs else ""), "records": r.n_rec,
+            "left_elems": int(prob.left.data.size), "out_elems": st["out_elems"],
             "terms": st["n_terms"], "products": [st["n_products1"], st["n_products2"]],
             "tiles": [st["n_tiles1"], st["n_tiles2"]], "build_ms": st["build_ms"],
             "bitwise_repeat": repro, "h_blocks": nh, "h_asymmetry": asym,
@@ -513,6 +524,9 @@ def main():
     ap.add_argument("--no-renorm", action="store_true", help="skip the renormalization leg")
     ap.add_argument("--renorm-only", action="store_true",
                     help="time only the renormalization of the workload's left block (for profiler runs)")
+    ap.add_argument("--renorm-all-pairs", action="store_true",
+                    help="with --renorm-only: draw the left block with P and Q over every outside pair and "
+                         "renormalize every family")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -552,7 +566,8 @@ def main():
 
     if args.renorm_only:
         print(json.dumps({"renorm_only": True, "workload": args.workload,
-                          **renorm_run(torch, prob, args.workload, args.steps, args.warmup)}), flush=True)
+                          **renorm_run(torch, args.workload, args.steps, args.warmup, prob,
+                                                     args.renorm_all_pairs)}), flush=True)
         return
     if args.hpsi_only:
         ref = torch.empty(32 << 20, dtype=torch.float64, device="cuda")   # 256 MiB
@@ -576,7 +591,7 @@ def main():
     del y5, y64
     ren = None
     if not args.no_renorm:
-        ren = renorm_run(torch, prob, args.workload, args.steps, args.warmup)
+        ren = renorm_run(torch, args.workload, args.steps, args.warmup, prob)
         ren["workload"] = "%s left block (orbitals 0..%d) x site %d" % (args.workload, prob.p - 1, prob.p)
         print("# renormalization: %s" % json.dumps(ren), file=sys.stderr, flush=True)
     dav = None
