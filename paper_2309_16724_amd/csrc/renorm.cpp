@@ -237,6 +237,14 @@ struct RTerm {
   int posA;
   PT tb;             // site factor (kind 0 identity, 2 site family)
   double alpha;
+  int dress = -1;    // >= 0: the L factor is dressed operator `dress` (posA unused)
+};
+
+// A dressed operator: sum_j alpha_j C_j (or the sum of their adjoints) over
+// positions j of the C family, one block per C record.
+struct DressG {
+  int adj;
+  std::vector<std::pair<int, double>> src;   // (position, alpha)
 };
 
 int add_projected(const std::vector<RProd> &prods, SiteAlgebra &site, const BlockModel &L, int fam, int pos,
@@ -244,7 +252,7 @@ int add_projected(const std::vector<RProd> &prods, SiteAlgebra &site, const Bloc
   std::vector<std::pair<TermKey, double>> outs;
   if (project_rank(prods, site, FAM_TWO_K[fam], outs, err)) return err.code;
   for (auto &o : outs) {
-    RTerm t{fam, pos, o.first.a, 0, o.first.b, o.second};
+    RTerm t{fam, pos, o.first.a, 0, o.first.b, o.second, -1};
     if (t.ta.kind == 1) {
       t.posA = L.pos(t.ta.id, x, y);
       if (t.posA < 0) { err = {DMRG_EINVAL, "internal: left label not in family"}; return err.code; }
@@ -577,6 +585,10 @@ struct Built {
   int64_t work_len = 0;
   std::vector<TransJob> ujobs;   // U -> U^T per kept sector (every apply)
   std::vector<TransJob> ljobs;   // left records used as adjoints -> transposed copy (once)
+  std::vector<DressItem> ditems; // dressed operators (once, after the transposed copy)
+  std::vector<int64_t> dsrc;     // their source offsets ...
+  std::vector<double> dalpha;    // ... and weights
+  int64_t dress_len = 0;
   int64_t n_terms = 0;
   double flops1 = 0.0, flops2 = 0.0;
   double build_ms = 0.0;
@@ -655,6 +667,49 @@ int build_renorm(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int n_kee
   SiteAlgebra site;
   std::vector<RTerm> terms;
   if (build_terms(pr, L, site, mask, terms, err)) return err.code;
+  // Dressing: terms that differ only in the position of their C factor (a
+  // sum over an orbital j with integral weights, e.g. sum_j (xj|yl) C~_j (x)
+  // a~_l in P_xy) are merged into one term on sum_j alpha_j C_j, formed once
+  // when the lists are created (the dressing H.psi applies to its right-block
+  // rows); the products then run once per merged term instead of once per j.
+  std::vector<DressG> dress;
+  {
+    struct DK {
+      int fam, pos, adj;
+      PT tb;
+      bool operator<(const DK &o) const {
+        if (std::tie(fam, pos, adj) != std::tie(o.fam, o.pos, o.adj)) return std::tie(fam, pos, adj) < std::tie(o.fam, o.pos, o.adj);
+        return tb < o.tb;
+      }
+    };
+    std::map<DK, std::vector<int>> groups;
+    for (int i = 0; i < (int)terms.size(); i++) {
+      const RTerm &t = terms[i];
+      if (t.ta.kind == 1 && t.ta.id == F_C) groups[{t.fam, t.pos, t.ta.adj, t.tb}].push_back(i);
+    }
+    std::vector<char> drop(terms.size(), 0);
+    std::vector<RTerm> merged;
+    for (auto &kv : groups) {
+      if (kv.second.size() < 2) continue;
+      DressG g;
+      g.adj = kv.first.adj;
+      for (int i : kv.second) {
+        g.src.push_back({terms[i].posA, terms[i].alpha});
+        drop[i] = 1;
+      }
+      RTerm t = terms[kv.second[0]];
+      t.alpha = 1.0;
+      t.posA = 0;
+      t.dress = (int)dress.size();
+      dress.push_back(g);
+      merged.push_back(t);
+    }
+    std::vector<RTerm> kept_terms;
+    for (size_t i = 0; i < terms.size(); i++)
+      if (!drop[i]) kept_terms.push_back(terms[i]);
+    for (auto &t : merged) kept_terms.push_back(t);
+    terms.swap(kept_terms);
+  }
   B.n_terms = (int64_t)terms.size();
   std::vector<RSec> prod = product_sectors(L.sec);
   std::map<std::pair<int, int>, int> pidx;
@@ -728,7 +783,7 @@ int build_renorm(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int n_kee
             if (std::fabs(coef) < 1e-300) continue;
             int tix = -1;
             if (rec >= 0) {
-              TKey tk{rec, t.posA, t.ta.adj, ak, ac};
+              TKey tk{rec, t.dress >= 0 ? -1 - t.dress : t.posA, t.ta.adj, ak, ac};
               auto it = tindex.find(tk);
               if (it == tindex.end()) {
                 it = tindex.emplace(tk, (int)tkeys.size()).first;
@@ -786,6 +841,38 @@ int build_renorm(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int n_kee
   std::vector<char> ladj(L.rec.size(), 0);
   for (const TKey &k : tkeys)
     if (k.adj) ladj[k.rec] = 1;
+  // dressed operators: one block per C record per group, from the records
+  // (or their transposed copies for adjoint groups)
+  std::vector<int> crec;
+  for (size_t i = 0; i < L.rec.size(); i++)
+    if (L.rec[i].fam == F_C) crec.push_back((int)i);
+  std::vector<int64_t> crec_off(L.rec.size(), -1);
+  int64_t csize = 0;
+  for (int i : crec) {
+    crec_off[i] = csize;
+    csize += (int64_t)L.sec[L.rec[i].row_sec].dim * L.sec[L.rec[i].col_sec].dim;
+  }
+  B.ditems.clear(); B.dsrc.clear(); B.dalpha.clear();
+  B.dress_len = csize * (int64_t)dress.size();
+  for (size_t g = 0; g < dress.size(); g++) {
+    for (int i : crec) {
+      const dmrg_oprec_t &r = L.rec[i];
+      const int64_t bs = (int64_t)L.sec[r.row_sec].dim * L.sec[r.col_sec].dim;
+      if (dress[g].adj) ladj[i] = 1;
+      DressItem d{};
+      d.dst_off = (int64_t)g * csize + crec_off[i];
+      d.n = bs;
+      d.t0 = (int32_t)B.dsrc.size();
+      for (auto &sa : dress[g].src) {
+        B.dsrc.push_back(r.off + (int64_t)sa.first * bs);
+        B.dalpha.push_back(sa.second);
+      }
+      d.t1 = (int32_t)B.dsrc.size();
+      d.src_base = dress[g].adj ? BASE_OPS + 1 : BASE_OPS;
+      d.dst_base = BASE_OPS + 2;
+      B.ditems.push_back(d);
+    }
+  }
   B.ljobs.clear();
   for (size_t i = 0; i < L.rec.size(); i++)
     if (ladj[i]) {
@@ -801,8 +888,13 @@ int build_renorm(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int n_kee
     const int m = k.adj ? rc : rr, K = k.adj ? rr : rc, n = kept(k.ak);
     const RComp &ca = comp(k.ak, k.ac);
     Seg S{};
-    S.a_base = k.adj ? BASE_OPS + 1 : BASE_OPS;
-    S.a_off = r.off + (int64_t)k.posA * rr * rc;
+    if (k.posA >= 0) {
+      S.a_base = k.adj ? BASE_OPS + 1 : BASE_OPS;
+      S.a_off = r.off + (int64_t)k.posA * rr * rc;
+    } else {                        // dressed operator -1 - posA, same orientation
+      S.a_base = BASE_OPS + 2;
+      S.a_off = (int64_t)(-1 - k.posA) * csize + crec_off[k.rec];
+    }
     S.a_i = 1;
     S.a_k = k.adj ? rc : rr;       // the transposed record is rc x rr
     S.a_p = 0;
@@ -858,7 +950,8 @@ int build_renorm(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int n_kee
   // the tile or K read inside the operand: row 0, column 0, element K - 1)
   auto inside = [&](const std::vector<Tile> &tiles, const std::vector<Seg> &segs) {
     auto len = [&](int base) { return base == BASE_PSI ? u_len : base == BASE_Y ? B.out_len
-                                    : base == BASE_WORK ? B.work_len : pr.ldata_len; };
+                                    : base == BASE_WORK ? B.work_len : base == BASE_OPS + 2 ? B.dress_len
+                                    : pr.ldata_len; };
     for (const Tile &T : tiles) {
       const int64_t last = T.rowmajor ? (int64_t)(T.m - 1) * T.ldc + (T.n - 1) : (T.m - 1) + (int64_t)(T.n - 1) * T.ldc;
       if (T.c_off < 0 || T.c_off + last >= len(T.c_base)) return false;
@@ -896,9 +989,10 @@ int build_renorm(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int n_kee
 
 // host execution of a tile list with the kernels' addressing (test path)
 void host_run(const std::vector<Tile> &tiles, const std::vector<Seg> &segs, const double *ops, const double *opsT,
-              const double *u, double *out, double *work) {
+              const double *dressed, const double *u, double *out, double *work) {
   auto base = [&](int id) -> const double * {
-    return id == BASE_PSI ? u : id == BASE_Y ? out : id == BASE_WORK ? work : id == BASE_OPS ? ops : opsT;
+    return id == BASE_PSI ? u : id == BASE_Y ? out : id == BASE_WORK ? work : id == BASE_OPS ? ops
+         : id == BASE_OPS + 1 ? opsT : dressed;
   };
   for (const Tile &T : tiles) {
     const int mt = std::min(tile_rows(T.mb), T.m - T.i0), nt = std::min(tile_cols(T.mb), T.n - T.j0);
@@ -942,7 +1036,10 @@ struct dmrg_renorm {
   TransJob *d_uj = nullptr, *d_lj = nullptr;
   const double **d_bases = nullptr;
   int32_t *d_cnt = nullptr;
-  double *d_work = nullptr, *d_ut = nullptr, *d_lt = nullptr;
+  double *d_work = nullptr, *d_ut = nullptr, *d_lt = nullptr, *d_dress = nullptr;
+  DressItem *d_di = nullptr;
+  int64_t *d_dsrc = nullptr;
+  double *d_dalpha = nullptr;
   int64_t u_len = 0;
   // profiling: an event pair around each stage launch of every apply
   bool prof = false;
@@ -953,7 +1050,7 @@ extern "C" void dmrg_renorm_free(dmrg_renorm_t *r) {
   if (!r) return;
   for (hipEvent_t e : r->ev) (void)hipEventDestroy(e);
   void *ptrs[] = {r->d_t1, r->d_t2, r->d_s1, r->d_s2, r->d_uj, r->d_lj, (void *)r->d_bases, r->d_cnt,
-                  r->d_work, r->d_ut, r->d_lt};
+                  r->d_work, r->d_ut, r->d_lt, r->d_dress, r->d_di, r->d_dsrc, r->d_dalpha};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete r;
@@ -1004,7 +1101,11 @@ extern "C" int dmrg_renorm_create(const dmrg_problem_t *prob, const dmrg_rkeep_t
               up((void **)&r->d_lt, nullptr, r->b.ljobs.empty() ? 0 : (size_t)prob->ldata_len * sizeof(double)) &&
               up((void **)&r->d_uj, r->b.ujobs.data(), r->b.ujobs.size() * sizeof(TransJob)) &&
               up((void **)&r->d_lj, r->b.ljobs.data(), r->b.ljobs.size() * sizeof(TransJob));
-    const double *bases[2] = {prob->ldata, r->d_lt};
+    ok = ok && up((void **)&r->d_dress, nullptr, (size_t)r->b.dress_len * sizeof(double)) &&
+         up((void **)&r->d_di, r->b.ditems.data(), r->b.ditems.size() * sizeof(DressItem)) &&
+         up((void **)&r->d_dsrc, r->b.dsrc.data(), r->b.dsrc.size() * sizeof(int64_t)) &&
+         up((void **)&r->d_dalpha, r->b.dalpha.data(), r->b.dalpha.size() * sizeof(double));
+    const double *bases[3] = {prob->ldata, r->d_lt, r->d_dress};
     ok = ok && up((void **)&r->d_t1, r->b.t1.data(), r->b.t1.size() * sizeof(Tile)) &&
               up((void **)&r->d_t2, r->b.t2.data(), r->b.t2.size() * sizeof(Tile)) &&
               up((void **)&r->d_s1, r->b.s1.data(), r->b.s1.size() * sizeof(Seg)) &&
@@ -1017,12 +1118,14 @@ extern "C" int dmrg_renorm_create(const dmrg_problem_t *prob, const dmrg_rkeep_t
       set_error("device allocation or copy failed");
       return DMRG_ENOMEM;
     }
-    // transposed copies of the left records applied as adjoints (once)
-    if (!r->b.ljobs.empty()) {
+    // transposed copies of the left records applied as adjoints, then the
+    // dressed operators (once)
+    if (!r->b.ljobs.empty() || !r->b.ditems.empty()) {
       launch_transpose(r->d_lj, (int)r->b.ljobs.size(), prob->ldata, r->d_lt, nullptr);
+      launch_dress(r->d_di, (int)r->b.ditems.size(), r->d_dsrc, r->d_dalpha, r->d_bases, r->d_dress, nullptr);
       if (hipStreamSynchronize(nullptr) != hipSuccess) {
         dmrg_renorm_free(r.release());
-        set_error("transposing the left records failed");
+        set_error("transposing or dressing the left records failed");
         return DMRG_EHIP;
       }
     }
@@ -1153,9 +1256,18 @@ extern "C" int dmrg_debug_renorm_host(const dmrg_problem_t *prob, const dmrg_rke
       lt.assign((size_t)prob->ldata_len, 0.0);
       host_transpose(b.ljobs, prob->ldata, lt.data());
     }
+    std::vector<double> dr((size_t)std::max<int64_t>(b.dress_len, 1), 0.0);
+    for (const DressItem &d : b.ditems) {
+      const double *src = d.src_base == BASE_OPS ? prob->ldata : lt.data();
+      for (int64_t e = 0; e < d.n; e++) {
+        double acc = 0.0;
+        for (int t = d.t0; t < d.t1; t++) acc += b.dalpha[t] * src[b.dsrc[t] + e];
+        dr[d.dst_off + e] = acc;
+      }
+    }
     std::fill(out, out + b.out_len, 0.0);
-    host_run(b.t1, b.s1, prob->ldata, lt.data(), ut.data(), out, work.data());
-    host_run(b.t2, b.s2, prob->ldata, lt.data(), ut.data(), out, work.data());
+    host_run(b.t1, b.s1, prob->ldata, lt.data(), dr.data(), ut.data(), out, work.data());
+    host_run(b.t2, b.s2, prob->ldata, lt.data(), dr.data(), ut.data(), out, work.data());
     return DMRG_OK;
   } catch (const std::bad_alloc &) {
     set_error("host allocation failed");
