@@ -145,8 +145,8 @@ MEASURED_TRAFFIC = {
     ("L54_D2048", "stage_f64_kernel<1>"): (3.5086e11, _F64_SRC, "69c8d5cbc4f75ca9"),
     ("L54_D2048", "stage_f64_kernel<2>"): (1.0639e12, _F64_SRC, "69c8d5cbc4f75ca9"),
     # renormalization of the L54_D2048 left block (profiles/renorm_L54_D2048_fp64.md)
-    ("L54_D2048", "renorm:stage_f64_kernel<1>"): (1.3443e11, _REN_SRC, "e42109076685ca83"),
-    ("L54_D2048", "renorm:stage_f64_kernel<2>"): (2.8595e11, _REN_SRC, "e42109076685ca83"),
+    ("L54_D2048", "renorm:stage_f64_kernel<1>"): (1.4020e11, _REN_SRC, "d0c760c170acfe42"),
+    ("L54_D2048", "renorm:stage_f64_kernel<2>"): (1.8112e11, _REN_SRC, "d0c760c170acfe42"),
 }
 
 
