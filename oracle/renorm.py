@@ -273,7 +273,7 @@ def _pq_spin(ps, fam, x, y, t, s, p, eri):
     return acc
 
 
-def _pq_component(ps, fam, lab, q, p, eri):
+def _pq_component(ps, fam, lab, q, p, eri, spin=None):
     """Tensor component q of P^K or Q^K of the enlarged block from its
     spin-orbital forms, inverting
       (P_xy)_ts = (-1)^(1+t+s) sum_K <1/2 -t, 1/2 -s|K -t-s> P^K_{-t-s},
@@ -302,7 +302,7 @@ def _pq_component(ps, fam, lab, q, p, eri):
     acc = np.zeros((ps.dim, ps.dim))
     for t, s, c in coefs:
         if c != 0.0:
-            acc += c * _pq_spin(ps, fam, x, y, t, s, p, eri)
+            acc += c * (spin or _pq_spin)(ps, fam, x, y, t, s, p, eri)
     return acc
 
 
@@ -404,6 +404,290 @@ def renormalize(prob, keep, families=None):
             arr = fam_blocks[fam][(r, c)]
             flat = np.ascontiguousarray(arr.transpose(0, 2, 1)).reshape(-1)
             recs.append((fam, r, c, off, arr.shape[0]))
+            chunks.append(flat)
+            off += flat.size
+    out.records = recs
+    out.data = np.concatenate(chunks) if chunks else np.zeros(0)
+    return out
+
+
+# ------------------------------------------------------------ right block
+# The mirror step: the site r = p + 1 and the right block R = [p + 2, L)
+# merge into the right block R' = [p + 1, L) of bond p - 1 (Sec. II C: the
+# site x block product, whose SU(2) factors the paper keeps in W9j^(r)).
+# Coupled states ((r s) x (R S_R)) S, site first as in the two-site basis;
+# product basis rows: components (site multiplet m, R sector b) in the order
+# m = 0, 1, 2, then b ascending, d_b rows each.  An operator of R acting on
+# |site string>|R string> passes the site string: (-1)^(parity * n_site).
+# Families produced: H, C, S, P0, P1, Q0, Q1 of a right block (labels at bond
+# p - 1); the right block's P and Q hold every pair of its outside orbitals,
+# so no special input form is needed.
+
+RIGHT_FAMILIES = (cat.H, cat.C, cat.S, cat.P0, cat.P1, cat.Q0, cat.Q1)
+
+
+def product_sectors_right(rsec):
+    """[(N, 2S, rows, [(site multiplet, iR, row0, d)])] of r x R, (N, 2S) ascending."""
+    comps = {}
+    for m, (n, s) in enumerate(SITE):
+        for iR, (N, S, d) in enumerate(rsec):
+            for S2 in range(abs(S - s), S + s + 1, 2):
+                comps.setdefault((N + n, S2), []).append((m, iR, d))
+    out = []
+    for key in sorted(comps):
+        rows, lst = 0, []
+        for m, iR, d in comps[key]:
+            lst.append((m, iR, rows, d))
+            rows += d
+        out.append((key[0], key[1], rows, lst))
+    return out
+
+
+class _RightSpace:
+    """M-resolved r x R space: index f * nR + xR (f a site Fock state, xR an
+    M-resolved R state); factors (part, op, parity) with part 0 the site and
+    part 1 the block (Jordan-Wigner order)."""
+
+    SITE_PAR = np.array([1.0 if n % 2 == 0 else -1.0 for n in SITE_N])
+
+    def __init__(self, blk):
+        self.mB = MBlock(blk)
+        self.fB = Factors(self.mB)
+        self.goff, n = {}, 0
+        for g in sorted(self.mB.gdim):
+            self.goff[g] = n
+            n += self.mB.gdim[g]
+        self.nR = n
+        self.dim = 4 * n
+
+    def dense_R(self, op):
+        m = np.zeros((self.nR, self.nR))
+        for (g2, g), blk in op.items():
+            o2, o = self.goff[g2], self.goff[g]
+            m[o2:o2 + blk.shape[0], o:o + blk.shape[1]] += blk
+        return m
+
+    def index_R(self, sec, M2, mu):
+        g, o = self.mB.gidx[(sec, M2)]
+        return self.goff[g] + o + mu
+
+    def product(self, coef, factors):
+        sign = 1.0
+        for i in range(len(factors)):
+            for j in range(i + 1, len(factors)):
+                if factors[i][0] > factors[j][0] and factors[i][2] and factors[j][2]:
+                    sign = -sign
+        Os, OR, par = np.eye(4), None, 0
+        for pt, op, pa in sorted(factors, key=lambda f: f[0]):
+            if pt == 1:
+                assert OR is None, "one R factor per product"
+                OR = self.dense_R(op)
+                par ^= pa
+            else:
+                Os = Os @ op
+        if OR is None:
+            OR = np.eye(self.nR)
+        if par:
+            Os = Os * self.SITE_PAR[None, :]
+        return (coef * sign) * np.kron(Os, OR)
+
+
+def _right_single(ps, r):
+    fB = ps.fB
+
+    def single(x, s2, dagger):
+        if x > r:
+            return (1, fB.cre(x, s2, 0) if dagger else fB.T("cre", x, s2, 0), 1)
+        return (0, site_cre(s2) if dagger else site_ann(s2), 1)
+    return single
+
+
+def _right_h(ps, r, n, h, eri):
+    """H restricted to orbitals [r, n)."""
+    fB, mB = ps.fB, ps.mB
+    single = _right_single(ps, r)
+    spins = (1, -1)
+    acc = ps.product(1.0, [(1, mB.tensor(cat.H, 0, 0), 0)])
+    for s in spins:
+        acc += ps.product(1.0, [single(r, s, True), (1, fB.S(r, s, 0), 1)])
+        acc += ps.product(1.0, [(1, fB.T("S", r, s, 0), 1), single(r, s, False)])
+    for s in spins:
+        for t in spins:
+            acc += ps.product(0.5, [single(r, s, True), single(r, t, True), (1, fB.P(r, r, t, s, 0), 0)])
+            acc += ps.product(0.5, [(1, fB.T("P", r, r, t, s, 0), 0), single(r, t, False), single(r, s, False)])
+            acc += ps.product(1.0, [(1, fB.Q(r, r, t, s, 0), 0), single(r, t, True), single(r, s, False)])
+    idx = range(r, n)
+    nb = lambda t: sum(1 for i in t if i > r)
+    for i in idx:
+        for j in idx:
+            if nb((i, j)) > 1 or h[i, j] == 0.0:
+                continue
+            for s in spins:
+                acc += ps.product(h[i, j], [single(i, s, True), single(j, s, False)])
+    for i in idx:
+        for j in idx:
+            for k in idx:
+                for l in idx:
+                    if nb((i, j, k, l)) > 1 or eri[i, j, k, l] == 0.0:
+                        continue
+                    for s in spins:
+                        for t in spins:
+                            if (i == k or j == l) and s == t:
+                                continue
+                            acc += ps.product(0.5 * eri[i, j, k, l], [single(i, s, True), single(k, t, True),
+                                                                      single(l, t, False), single(j, s, False)])
+    return acc
+
+
+def _right_s_spin(ps, x, s2, r, n, eri):
+    """(S_x)_s of the enlarged right block, x < r."""
+    fB = ps.fB
+    single = _right_single(ps, r)
+    acc = ps.product(1.0, [(1, fB.S(x, s2, 0), 1)])
+    for t in (1, -1):
+        acc += ps.product(1.0, [(1, fB.P(x, r, t, s2, 0), 0), single(r, t, True)])
+        acc += ps.product(1.0, [(1, fB.Q(x, r, s2, t, 0), 0), single(r, t, False)])
+    idx = range(r, n)
+    for j in idx:
+        for k in idx:
+            for l in idx:
+                if sum(1 for i in (j, k, l) if i == r) < 2 or eri[x, j, k, l] == 0.0:
+                    continue
+                for t in (1, -1):
+                    acc += ps.product(eri[x, j, k, l], [single(k, t, True), single(l, t, False), single(j, s2, False)])
+    return acc
+
+
+def _right_pq_spin_factory(r, n):
+    def spin(ps, fam, x, y, t, s, p_, eri):
+        fB = ps.fB
+        single = _right_single(ps, r)
+        idx = range(r, n)
+        if fam in (cat.P0, cat.P1):
+            acc = ps.product(1.0, [(1, fB.P(x, y, t, s, 0), 0)])
+            for j in idx:
+                for l in idx:
+                    if (j > r and l > r) or eri[x, j, y, l] == 0.0:
+                        continue
+                    acc += ps.product(eri[x, j, y, l], [single(l, t, False), single(j, s, False)])
+            return acc
+        acc = ps.product(1.0, [(1, fB.Q(x, y, t, s, 0), 0)])
+        for k in idx:
+            for l in idx:
+                if k > r and l > r:
+                    continue
+                if t == s and eri[x, y, k, l] != 0.0:
+                    for sg in (1, -1):
+                        acc += ps.product(eri[x, y, k, l], [single(k, sg, True), single(l, sg, False)])
+                if eri[x, l, k, y] != 0.0:
+                    acc += ps.product(-eri[x, l, k, y], [single(k, s, True), single(l, t, False)])
+        return acc
+    return spin
+
+
+def _right_target(ps, fam, lab, q, r, n, h, eri):
+    if fam == cat.H:
+        return _right_h(ps, r, n, h, eri)
+    if fam in PAIR_FAMILIES:
+        return _pq_component(ps, fam, lab, q, r, eri, spin=_right_pq_spin_factory(r, n))
+    if fam == cat.S:
+        x, s_ = lab[0], -q
+        scale = -1.0 / (np.sqrt(2.0) * (-1.0 if ((1 + s_) // 2) % 2 else 1.0))
+        return scale * _right_s_spin(ps, x, s_, r, n, eri)
+    assert fam == cat.C
+    x = lab[0]
+    if x > r:
+        return ps.product(1.0, [(1, ps.mB.tensor(cat.C, ps.mB.pos(cat.C, lab), q), 1)])
+    return ps.product(1.0, [_right_single(ps, r)(x, q, True)])
+
+
+def _right_coupled(ps, rsec, comps, U, two_s, M2):
+    V = np.zeros((ps.dim, U.shape[1]))
+    for (m, iR, row0, d) in comps:
+        S = rsec[iR][1]
+        s = SITE[m][1]
+        for ms, f in SITE_MULT_STATES[m].items():
+            MR = M2 - ms
+            if abs(MR) > S or (S - MR) % 2:
+                continue
+            c = cg(s, ms, S, MR, two_s, M2)
+            if c == 0.0:
+                continue
+            for mu in range(d):
+                V[f * ps.nR + ps.index_R(iR, MR, mu), :] += c * U[row0 + mu, :]
+    return V
+
+
+def renormalize_right(prob, keep, families=RIGHT_FAMILIES):
+    """Operators of the enlarged right block [p + 1, L) (a right block at bond
+    p - 1) from the problem's right block, the site p + 1 and the integrals;
+    keep as in ``renormalize`` with the rows of product_sectors_right."""
+    blk, p, n = prob.right, prob.p, prob.n_orb
+    assert p >= 1
+    r = p + 1
+    ps = _RightSpace(blk)
+    rsec = blk.sectors
+    prod = {(N, S): comps for (N, S, rows, comps) in product_sectors_right(rsec)}
+    sectors, kinfo = [], []
+    for (N, S, U) in keep:
+        comps = prod[(N, S)]
+        U = np.asarray(U, dtype=float)
+        assert U.shape[0] == sum(c[3] for c in comps)
+        sectors.append((N, S, U.shape[1]))
+        kinfo.append((comps, U))
+    cache = {}
+
+    def vec(i, M2):
+        if (i, M2) not in cache:
+            comps, U = kinfo[i]
+            cache[(i, M2)] = _right_coupled(ps, rsec, comps, U, sectors[i][1], M2)
+        return cache[(i, M2)]
+
+    out = BlockData("R", n, p - 1, sectors)
+    fam_blocks = {}
+    for fam in families:
+        labs = cat.labels(fam, "R", n, p - 1)
+        k2 = cat.TWO_K[fam]
+        per = []
+        for lab in labs:
+            comp = {q: _right_target(ps, fam, lab, q, r, n, prob.h, prob.eri) for q in range(-k2, k2 + 1, 2)}
+            red = {}
+            for a, (Na, Sa, da) in enumerate(sectors):
+                for b, (Nb, Sb, db) in enumerate(sectors):
+                    if Nb != Na + cat.DN[fam] or not (abs(Sa - k2) <= Sb <= Sa + k2):
+                        continue
+                    best = None
+                    for q in range(-k2, k2 + 1, 2):
+                        ma = Sb - q
+                        if abs(ma) > Sa:
+                            continue
+                        c = cg(Sa, ma, k2, q, Sb, Sb)
+                        if c != 0.0 and (best is None or abs(c) > abs(best[0])):
+                            best = (c, q, ma)
+                    if best is None:
+                        continue
+                    c, q, ma = best
+                    m = vec(b, Sb).T @ comp[q] @ vec(a, ma) / c
+                    if np.abs(m).max() > 1e-13:
+                        red[(b, a)] = m
+            per.append(red)
+        keys = sorted({k for d in per for k in d})
+        if not keys:
+            continue
+        fb = {}
+        for (b, a) in keys:
+            arr = np.zeros((len(per), sectors[b][2], sectors[a][2]))
+            for i, d in enumerate(per):
+                if (b, a) in d:
+                    arr[i] = d[(b, a)]
+            fb[(b, a)] = arr
+        fam_blocks[fam] = fb
+    recs, chunks, off = [], [], 0
+    for fam in sorted(fam_blocks):
+        for (rr, cc) in sorted(fam_blocks[fam]):
+            arr = fam_blocks[fam][(rr, cc)]
+            flat = np.ascontiguousarray(arr.transpose(0, 2, 1)).reshape(-1)
+            recs.append((fam, rr, cc, off, arr.shape[0]))
             chunks.append(flat)
             off += flat.size
     out.records = recs

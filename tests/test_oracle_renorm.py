@@ -183,3 +183,46 @@ def test_pair_families_match_fock_space(n_orb, p, max_mult):
     for fam in RENORM_FAMILIES + PAIR_FAMILIES:
         assert dense_records(big, fam), cat.NAMES[fam]
         compare(got, big, fam, 1e-12)
+
+
+def exact_keep_right(right, big):
+    """U of every product sector of site x right block onto the states of the
+    exact enlarged right block ``big`` (Fock index site + 4 * block)."""
+    from oracle.renorm import product_sectors_right
+    nf = 4 ** (right.n_orb - right.p - 2)
+    bidx = {(N, S): b for b, (N, S, d) in enumerate(big.sectors)}
+    keep = []
+    for (N, S, rows, comps) in product_sectors_right(right.sectors):
+        b = bidx.get((N, S))
+        if b is None:
+            continue
+        V = big.basis[b][0]
+        U = np.zeros((rows, V.shape[1]))
+        for (m, iR, row0, d) in comps:
+            SR = right.sectors[iR][1]
+            s = SITE[m][1]
+            for ms, f in SITE_MULT_STATES[m].items():
+                MR = S - ms
+                if abs(MR) > SR or (SR - MR) % 2:
+                    continue
+                c = cg(s, ms, SR, MR, S, S)
+                if c == 0.0:
+                    continue
+                Rv = right.basis[iR][(SR - MR) // 2]
+                U[row0:row0 + d, :] += c * (Rv.T @ V[f + 4 * np.arange(nf), :])
+        keep.append((N, S, U))
+    return keep
+
+
+@pytest.mark.parametrize("n_orb,p,max_mult", [(6, 2, None), (7, 2, None), (7, 2, 40)])
+def test_right_block_matches_fock_space(n_orb, p, max_mult):
+    """Site x right block: every family of the enlarged right block against
+    the Fock-space block (untruncated and truncated)."""
+    from oracle.renorm import renormalize_right, RIGHT_FAMILIES
+    prob = exact_problem(n_orb, n_orb, n_orb % 2, 26, p=p)
+    big = build_exact_block("R", n_orb, p - 1, prob.h, prob.eri, max_mult=max_mult)
+    keep = exact_keep_right(prob.right, big)
+    got = renormalize_right(prob, keep)
+    for fam in RIGHT_FAMILIES:
+        assert dense_records(big, fam), cat.NAMES[fam]
+        compare(got, big, fam, 1e-12)
