@@ -419,27 +419,29 @@ def davidson_runs(torch, args, plan_flags):
     return out
 
 
-def renorm_run(torch, workload, steps, warmup, prob=None, all_pairs=False):
+def renorm_run(torch, workload, steps, warmup, prob=None, all_pairs=False, right=False):
     """Renormalization of the workload's left block through its left site,
     FP64: the families H, C, A0, A1, B0, B1, S of the enlarged block (with
     all_pairs the left block is drawn with P and Q over every outside pair and
     P0, P1, Q0, Q1 are produced too); every product sector keeps a quarter of
     its rows (about D states in all) through a U with orthonormal columns (QR
     of a seeded Gaussian matrix).  Timed like H.psi: warm-up, then `steps`
-    applies bracketed by synchronisation."""
+    applies bracketed by synchronisation.  right: the right block through
+    the right site instead (site x block; H, C, S, P0, P1, Q0, Q1 of the
+    enlarged right block)."""
     import numpy as np
     from paper_2309_16724_amd import binding as B
     from paper_2309_16724_amd.hpsi import Renorm
-    if prob is None or all_pairs:
+    if prob is None or (all_pairs and not right):
         t0 = time.time()
         prob = make_problem(WORKLOADS[workload], all_pairs=all_pairs)
         print("# left block of %s generated in %.1f s (%d elements)"
               % (workload, time.time() - t0, prob.left.data.size), file=sys.stderr, flush=True)
-    secs, _ = B.renorm_product(prob)
+    secs, _ = B.renorm_product(prob, right=right)
     rng = np.random.default_rng(7)
     keep = [(n, s2, np.linalg.qr(rng.standard_normal((rows, max(1, rows // 4))))[0]) for (n, s2, rows) in secs]
     t0 = time.time()
-    r = Renorm(prob, keep)
+    r = Renorm(prob, keep, right=right)
     st = r.stats()
     print("# renormalization lists built in %.1f s: %s" % (time.time() - t0, json.dumps(st)), file=sys.stderr,
           flush=True)
@@ -481,15 +483,16 @@ def renorm_run(torch, workload, steps, warmup, prob=None, all_pairs=False):
     return {"ms": ms, "tflops": tf, "flops": flops, "flops_stage1": st["flops1"], "flops_stage2": st["flops2"],
             "kept_states": int(sum(u.shape[1] for _, _, u in keep)),
             "product_states": int(sum(u.shape[0] for _, _, u in keep)),
-            "families": "H C A0 A1 B0 B1 S" + (" P0 P1 Q0 Q1" if all_pairs else ""), "records": r.n_rec,
-            "left_elems": int(prob.left.data.size), "out_elems": st["out_elems"],
+            "families": ("H C S P0 P1 Q0 Q1" if right else
+                         "H C A0 A1 B0 B1 S" + (" P0 P1 Q0 Q1" if all_pairs else "")), "records": r.n_rec,
+            "block_elems": int((prob.right if right else prob.left).data.size), "out_elems": st["out_elems"],
             "terms": st["n_terms"], "products": [st["n_products1"], st["n_products2"]],
             "tiles": [st["n_tiles1"], st["n_tiles2"]], "build_ms": st["build_ms"],
             "bitwise_repeat": repro, "h_blocks": nh, "h_asymmetry": asym,
             "stages_ms": {str(k): v[1] / max(v[0], 1) for k, v in prof.items()},
             "roofline": {"bound": "mfma", "kernel": kname, "achieved": ach, "peak": FP64_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
-                         "traffic": measured_traffic(workload, "renorm:" + kname)}}
+                         "traffic": measured_traffic(workload, ("renorm_right:" if right else "renorm:") + kname)}}
 
 
 def main():
@@ -524,6 +527,8 @@ def main():
     ap.add_argument("--no-renorm", action="store_true", help="skip the renormalization leg")
     ap.add_argument("--renorm-only", action="store_true",
                     help="time only the renormalization of the workload's left block (for profiler runs)")
+    ap.add_argument("--renorm-right", action="store_true",
+                    help="with --renorm-only: the right block through the right site instead")
     ap.add_argument("--renorm-all-pairs", action="store_true",
                     help="with --renorm-only: draw the left block with P and Q over every outside pair and "
                          "renormalize every family")
@@ -567,7 +572,7 @@ def main():
     if args.renorm_only:
         print(json.dumps({"renorm_only": True, "workload": args.workload,
                           **renorm_run(torch, args.workload, args.steps, args.warmup, prob,
-                                                     args.renorm_all_pairs)}), flush=True)
+                                                     args.renorm_all_pairs, args.renorm_right)}), flush=True)
         return
     if args.hpsi_only:
         ref = torch.empty(32 << 20, dtype=torch.float64, device="cuda")   # 256 MiB
@@ -593,6 +598,10 @@ def main():
     if not args.no_renorm:
         ren = renorm_run(torch, args.workload, args.steps, args.warmup, prob)
         ren["workload"] = "%s left block (orbitals 0..%d) x site %d" % (args.workload, prob.p - 1, prob.p)
+        ren_r = renorm_run(torch, args.workload, args.steps, args.warmup, prob, right=True)
+        ren_r["workload"] = "%s site %d x right block (orbitals %d..%d)" % (args.workload, prob.p + 1, prob.p + 2,
+                                                                         prob.n_orb - 1)
+        ren["right_block"] = ren_r
         print("# renormalization: %s" % json.dumps(ren), file=sys.stderr, flush=True)
     dav = None
     if not args.no_davidson:

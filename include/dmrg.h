@@ -398,6 +398,18 @@ const char *dmrg_last_error(void);
  * of the old block plus their terms with an index at l.  Without the flag a
  * fam_mask naming P or Q is DMRG_EINVAL.
  *
+ * Right block (flag DMRG_RENORM_RIGHT, the sweep's other direction): the
+ * site r = site_l + 1 and the right block [r + 1, L) merge into the right
+ * block [r, L) of bond site_l - 1 (Sec. II C: site x block, the W9j(r)
+ * factor; coupled states ((r s) x (R S_R)) S, site first as in the two-site
+ * basis; an R operator picks up (-1)^(its parity x the site's electrons)).
+ * Product basis rows: components (site multiplet m, right sector b) in the
+ * order m = 0, 1, 2, then b ascending (dmrg_renorm_product with the flag;
+ * dmrg_rcomp_t.l_sec then names the right sector).  Output: H, C, S, P0, P1,
+ * Q0, Q1 of a right block at bond site_l - 1, every one of them (the right
+ * block's S, P, Q already cover every orbital and pair left of it).  Not
+ * combined with DMRG_RENORM_ALL_PAIRS.
+ *
  * dmrg_renorm_create builds the term and product lists on the host and
  * copies them to the device (hipMalloc, freed by dmrg_renorm_free); the
  * left data pointer is kept until then.  dmrg_renorm_apply runs the two
@@ -423,12 +435,12 @@ typedef struct {
 } dmrg_renorm_stats_t;
 /* Sectors (n, two_s, rows) and components of the product basis.  Either
  * output may be NULL (counts only); DMRG_ERANGE when a capacity is short. */
-int dmrg_renorm_product(const dmrg_problem_t *prob, dmrg_sector_t *sec, int32_t sec_cap, int32_t *n_sec,
-                        dmrg_rcomp_t *comp, int32_t comp_cap, int32_t *n_comp);
+int dmrg_renorm_product(const dmrg_problem_t *prob, int32_t flags, dmrg_sector_t *sec, int32_t sec_cap,
+                        int32_t *n_sec, dmrg_rcomp_t *comp, int32_t comp_cap, int32_t *n_comp);
 /* fam_mask: bit f for family f (0 = every family the flags allow); flags:
- * 0 or DMRG_RENORM_ALL_PAIRS; u_len: elements of the U array that
- * dmrg_renorm_apply will be given. */
-enum { DMRG_RENORM_ALL_PAIRS = 1 };
+ * 0, DMRG_RENORM_ALL_PAIRS or DMRG_RENORM_RIGHT; u_len: elements of the U
+ * array that dmrg_renorm_apply will be given. */
+enum { DMRG_RENORM_ALL_PAIRS = 1, DMRG_RENORM_RIGHT = 2 };
 int dmrg_renorm_create(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int32_t n_keep, int32_t fam_mask,
                        int32_t flags, int64_t u_len, dmrg_renorm_t **out);
 /* Output records (rec may be NULL to size) and the output length. */

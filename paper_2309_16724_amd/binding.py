@@ -20,6 +20,7 @@ DMRG_PLAN_GRAPH = 1
 DMRG_PLAN_XCD = 2
 DMRG_PLAN_AUTOTUNE = 4
 DMRG_RENORM_ALL_PAIRS = 1
+DMRG_RENORM_RIGHT = 2
 
 
 class Sector(ctypes.Structure):
@@ -169,8 +170,8 @@ def load(path=None):
         L.dmrg_mlp_free.argtypes = [c_vp]
         L.dmrg_mlp_free.restype = None
     if hasattr(L, "dmrg_renorm_create"):
-        L.dmrg_renorm_product.argtypes = [ctypes.POINTER(ProblemT), c_vp, c_i32, ctypes.POINTER(c_i32), c_vp,
-                                          c_i32, ctypes.POINTER(c_i32)]
+        L.dmrg_renorm_product.argtypes = [ctypes.POINTER(ProblemT), c_i32, c_vp, c_i32, ctypes.POINTER(c_i32),
+                                          c_vp, c_i32, ctypes.POINTER(c_i32)]
         L.dmrg_renorm_create.argtypes = [ctypes.POINTER(ProblemT), c_vp, c_i32, c_i32, c_i32, c_i64,
                                          ctypes.POINTER(c_vp)]
         L.dmrg_renorm_records.argtypes = [c_vp, c_vp, c_i64, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]
@@ -286,16 +287,18 @@ def debug_host_apply(prob, psi, lib=None):
     return y, st
 
 
-def renorm_product(prob, lib=None):
-    """Product basis of the left block x site: [(n, 2S, rows)] and components
-    [(sector, left sector, site multiplet, row0, dim)] (dmrg_renorm_product)."""
+def renorm_product(prob, lib=None, right=False):
+    """Product basis of the left block x site (right: site x right block):
+    [(n, 2S, rows)] and components [(sector, block sector, site multiplet,
+    row0, dim)] (dmrg_renorm_product)."""
     L = lib or load()
     args = ProblemArgs(prob, 0, 0)
+    fl = DMRG_RENORM_RIGHT if right else 0
     ns, nc = c_i32(), c_i32()
-    check(L.dmrg_renorm_product(ctypes.byref(args.s), None, 0, ctypes.byref(ns), None, 0, ctypes.byref(nc)), L)
+    check(L.dmrg_renorm_product(ctypes.byref(args.s), fl, None, 0, ctypes.byref(ns), None, 0, ctypes.byref(nc)), L)
     sec = (Sector * max(1, ns.value))()
     comp = (RComp * max(1, nc.value))()
-    check(L.dmrg_renorm_product(ctypes.byref(args.s), ctypes.addressof(sec), ns.value, ctypes.byref(ns),
+    check(L.dmrg_renorm_product(ctypes.byref(args.s), fl, ctypes.addressof(sec), ns.value, ctypes.byref(ns),
                                 ctypes.addressof(comp), nc.value, ctypes.byref(nc)), L)
     return ([(s.n, s.two_s, s.dim) for s in sec[:ns.value]],
             [(c.sec, c.l_sec, c.site, c.row0, c.dim) for c in comp[:nc.value]])
@@ -314,25 +317,33 @@ def keep_array(keep):
     return arr, flat, off
 
 
-def records_block(prob, keep, recs, data):
-    """Output of a renormalization as the oracle's BlockData (role L, bond p + 1)."""
+def records_block(prob, keep, recs, data, right=False):
+    """Output of a renormalization as BlockData (role L at bond p + 1, or
+    role R at bond p - 1 for the right block)."""
     from .synth.problem import BlockData
-    blk = BlockData("L", prob.n_orb, prob.p + 1, [(n, S, np.asarray(U).shape[1]) for (n, S, U) in keep],
-                    all_pairs=getattr(prob.left, "all_pairs", False))
+    secs = [(n, S, np.asarray(U).shape[1]) for (n, S, U) in keep]
+    if right:
+        blk = BlockData("R", prob.n_orb, prob.p - 1, secs)
+    else:
+        blk = BlockData("L", prob.n_orb, prob.p + 1, secs, all_pairs=getattr(prob.left, "all_pairs", False))
     blk.records = [(r.fam, r.row_sec, r.col_sec, r.off, r.npos) for r in recs]
     blk.data = np.asarray(data, dtype=np.float64)
     return blk
 
 
-def debug_renorm_host(prob, keep, fam_mask=0, lib=None, execute=True):
+def debug_renorm_host(prob, keep, fam_mask=0, lib=None, execute=True, right=False):
     """Test-only: the renormalization lists executed on the CPU (no GPU).
     Returns (BlockData of the new block or None, statistics)."""
     L = lib or load()
     ld = np.ascontiguousarray(prob.left.data)
-    args = ProblemArgs(prob, ld.ctypes.data, 0)
+    rd = np.ascontiguousarray(prob.right.data)
+    args = ProblemArgs(prob, ld.ctypes.data, rd.ctypes.data)
     karr, u, ulen = keep_array(keep)
     st = RenormStats()
-    flags = DMRG_RENORM_ALL_PAIRS if getattr(prob.left, "all_pairs", False) else 0
+    if right:
+        flags = DMRG_RENORM_RIGHT
+    else:
+        flags = DMRG_RENORM_ALL_PAIRS if getattr(prob.left, "all_pairs", False) else 0
     check(L.dmrg_debug_renorm_host(ctypes.byref(args.s), ctypes.addressof(karr), len(keep), fam_mask, flags,
                                    None, ulen, None, 0, None, 0, ctypes.byref(st)), L)
     if not execute:
@@ -342,4 +353,4 @@ def debug_renorm_host(prob, keep, fam_mask=0, lib=None, execute=True):
     check(L.dmrg_debug_renorm_host(ctypes.byref(args.s), ctypes.addressof(karr), len(keep), fam_mask, flags,
                                    u.ctypes.data, ulen, out.ctypes.data, out.size, ctypes.addressof(recs),
                                    st.n_records, ctypes.byref(st)), L)
-    return records_block(prob, keep, recs[:st.n_records], out[:st.out_elems]), st.as_dict()
+    return records_block(prob, keep, recs[:st.n_records], out[:st.out_elems], right), st.as_dict()

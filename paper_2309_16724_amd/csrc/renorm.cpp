@@ -69,7 +69,10 @@ const int RSITE_S[3] = {0, 1, 0};
 constexpr int RENORM_DEFAULT_MASK =
     (1 << F_H) | (1 << F_C) | (1 << F_A0) | (1 << F_A1) | (1 << F_B0) | (1 << F_B1) | (1 << F_S);
 constexpr int RENORM_PAIR_MASK = (1 << F_P0) | (1 << F_P1) | (1 << F_Q0) | (1 << F_Q1);
-constexpr int RENORM_ALL_PAIRS = 1;   // dmrg_renorm_create flag
+constexpr int RENORM_ALL_PAIRS = 1;   // dmrg_renorm_create flags
+constexpr int RENORM_RIGHT = 2;
+constexpr int RENORM_RIGHT_MASK =
+    (1 << F_H) | (1 << F_C) | (1 << F_S) | (1 << F_P0) | (1 << F_P1) | (1 << F_Q0) | (1 << F_Q1);
 
 // factor of a spin-orbital product: part 0 the block (a family component),
 // part 1 the site (an elementary a+ (adj 0) or a~ (adj 1) component)
@@ -116,10 +119,13 @@ struct TermKey {
   }
 };
 
-// Coupled terms alpha [A (x) B]^K of products that make up the Q = K
-// component of a rank-K operator.
+// Coupled terms alpha [A (x) B]^K (side 0: block A then site B) or
+// alpha [B (x) A]^K (side 1: site then block) of products that make up the
+// Q = K component of a rank-K operator.  Factors are reordered into
+// Jordan-Wigner order: the block first on side 0, the site first on side 1.
 int project_rank(const std::vector<RProd> &prods, SiteAlgebra &site, int K2,
-                 std::vector<std::pair<TermKey, double>> &out, Error &err) {
+                 std::vector<std::pair<TermKey, double>> &out, Error &err, int side = 0) {
+  auto jw = [side](const RF &c) { return side == 0 ? c.part : 1 - c.part; };
   std::map<TermKey, std::map<std::pair<int, int>, double>> F;
   for (const RProd &pr : prods) {
     if (pr.coef == 0.0) continue;
@@ -127,8 +133,8 @@ int project_rank(const std::vector<RProd> &prods, SiteAlgebra &site, int K2,
     double sign = 1.0;
     for (size_t i = 0; i < f.size(); i++)
       for (size_t j = i + 1; j < f.size(); j++)
-        if (f[i].part > f[j].part && rf_parity(f[i]) && rf_parity(f[j])) sign = -sign;
-    std::stable_sort(f.begin(), f.end(), [](const RF &a, const RF &b) { return a.part < b.part; });
+        if (jw(f[i]) > jw(f[j]) && rf_parity(f[i]) && rf_parity(f[j])) sign = -sign;
+    std::stable_sort(f.begin(), f.end(), [&](const RF &a, const RF &b) { return jw(a) < jw(b); });
     PT ta;
     int qa = 0;
     std::vector<int> adj;
@@ -186,7 +192,7 @@ int project_rank(const std::vector<RProd> &prods, SiteAlgebra &site, int K2,
     for (int q1 = -ka; q1 <= ka; q1 += 2) {
       int q2 = K2 - q1;
       if (std::abs(q2) > kb) continue;
-      double c = cg(ka, q1, kb, q2, K2, K2);
+      double c = side == 0 ? cg(ka, q1, kb, q2, K2, K2) : cg(kb, q2, ka, q1, K2, K2);
       auto it = kv.second.find({q1, q2});
       double fv = it == kv.second.end() ? 0.0 : it->second;
       num += c * fv;
@@ -195,7 +201,8 @@ int project_rank(const std::vector<RProd> &prods, SiteAlgebra &site, int K2,
     double alpha = den > 0.0 ? num / den : 0.0;
     double resid = 0.0;
     for (auto &qv : kv.second) {
-      double c = cg(ka, qv.first.first, kb, qv.first.second, K2, K2);
+      double c = side == 0 ? cg(ka, qv.first.first, kb, qv.first.second, K2, K2)
+                           : cg(kb, qv.first.second, ka, qv.first.first, K2, K2);
       resid = std::max(resid, std::fabs(qv.second - alpha * c));
     }
     if (resid > 1e-10 * fmax) {
@@ -248,9 +255,9 @@ struct DressG {
 };
 
 int add_projected(const std::vector<RProd> &prods, SiteAlgebra &site, const BlockModel &L, int fam, int pos,
-                  int x, int y, std::vector<RTerm> &terms, Error &err) {
+                  int x, int y, std::vector<RTerm> &terms, Error &err, int side = 0) {
   std::vector<std::pair<TermKey, double>> outs;
-  if (project_rank(prods, site, FAM_TWO_K[fam], outs, err)) return err.code;
+  if (project_rank(prods, site, FAM_TWO_K[fam], outs, err, side)) return err.code;
   for (auto &o : outs) {
     RTerm t{fam, pos, o.first.a, 0, o.first.b, o.second, -1};
     if (t.ta.kind == 1) {
@@ -554,11 +561,306 @@ int build_terms(const dmrg_problem_t &pr, const BlockModel &L, SiteAlgebra &site
   return DMRG_OK;
 }
 
+// label lists of a right block's families at bond p (block [p + 2, n); the
+// H.psi catalogue: S over [0, p + 2), P and Q over the grouped pairs)
+std::vector<std::array<int, 2>> right_labels(int fam, int p, int n) {
+  std::vector<std::array<int, 2>> res;
+  const bool strict = fam == F_P1;
+  switch (fam) {
+    case F_H: res.push_back({-1, -1}); break;
+    case F_C: for (int i = p + 2; i < n; i++) res.push_back({i, -1}); break;
+    case F_S: for (int x = 0; x < p + 2; x++) res.push_back({x, -1}); break;
+    case F_P0: case F_P1: case F_Q0: case F_Q1:
+      for (int x = 0; x < p; x++) for (int y = x + 1; y < p; y++) res.push_back({x, y});
+      if (!strict) for (int x = 0; x < p; x++) res.push_back({x, x});
+      for (int x = 0; x < p; x++) res.push_back({x, p});
+      for (int x = 0; x < p; x++) res.push_back({x, p + 1});
+      if (!strict) res.push_back({p, p});
+      res.push_back({p, p + 1});
+      if (!strict) res.push_back({p + 1, p + 1});
+      break;
+    default: break;
+  }
+  return res;
+}
+
+// a+_{x s} / a_{x s} on the right side: block orbitals x > r, the site r
+RF elem_r(int x, int r, int s2, bool dagger, double &coef) {
+  RF f{x > r ? 0 : 1, F_C, dagger ? 0 : 1, 1, dagger ? s2 : -s2};
+  if (!dagger && ((1 + s2) / 2) % 2) coef = -coef;
+  return f;
+}
+
+// Terms of the enlarged right block R' = [r, n) (r = site_l + 1), a right
+// block at bond site_l - 1: H restricted to [r, n) (S_r, P_rr, Q_rr of R for
+// the parts with two or more indices in R), C, S_x, P_xy, Q_xy (x, y < r) --
+// the mirror of build_terms with the site before the block.
+int build_terms_right(const dmrg_problem_t &pr, const BlockModel &R, SiteAlgebra &site, int mask,
+                      std::vector<RTerm> &terms, Error &err) {
+  const int p = pr.site_l, n = pr.n_orb, r = p + 1;
+  const int sp[2] = {1, -1};
+  auto h = [&](int i, int j) { return pr.h1[(int64_t)i * n + j]; };
+  auto v = [&](int i, int j, int k, int l) { return pr.eri[(((int64_t)i * n + j) * n + k) * n + l]; };
+  auto direct = [&](int fam, int pos, int x, int y) -> bool {
+    RTerm t;
+    t.fam = fam; t.pos = pos;
+    t.ta.kind = 1; t.ta.id = fam; t.ta.adj = 0; t.ta.k2 = FAM_TWO_K[fam]; t.ta.par = FAM_PAR[fam];
+    t.posA = R.pos(fam, x, y);
+    t.alpha = 1.0;
+    if (t.posA < 0) { err = {DMRG_EINVAL, "right block lacks a member the enlarged block needs"}; return false; }
+    terms.push_back(t);
+    return true;
+  };
+  auto proj = [&](const std::vector<RProd> &pp, int fam, int pos, int x, int y) {
+    return add_projected(pp, site, R, fam, pos, x, y, terms, err, 1);
+  };
+  for (int fam = 0; fam < N_FAM; fam++) {
+    if (!(mask & (1 << fam))) continue;
+    auto labs = right_labels(fam, p - 1, n);
+    for (int pos = 0; pos < (int)labs.size(); pos++) {
+      const int x = labs[pos][0], y = labs[pos][1];
+      if (fam == F_H) {
+        { std::vector<RProd> pp{{1.0, {famc(F_H, 0, 0)}}}; if (proj(pp, fam, pos, -1, -1)) return err.code; }
+        {
+          std::vector<RProd> pp;
+          for (int s : sp) {
+            RProd q;
+            q.coef = -std::sqrt(2.0) * sgn2(1 + s);
+            q.f.push_back(elem_r(r, r, s, true, q.coef));
+            q.f.push_back(famc(F_S, 0, -s));
+            pp.push_back(q);
+          }
+          for (size_t i = 0, m = pp.size(); i < m; i++) pp.push_back(adjoint(pp[i]));
+          if (proj(pp, fam, pos, r, -1)) return err.code;
+        }
+        {
+          std::vector<RProd> pp;
+          for (int s : sp)
+            for (int t : sp) {
+              double cP = sgn2(2 + t + s) * cg(1, -t, 1, -s, 0, -t - s);
+              if (cP == 0.0) continue;
+              RProd q;
+              q.coef = 0.5 * cP;
+              q.f.push_back(elem_r(r, r, s, true, q.coef));
+              q.f.push_back(elem_r(r, r, t, true, q.coef));
+              q.f.push_back(famc(F_P0, 0, -t - s));
+              pp.push_back(q);
+            }
+          for (size_t i = 0, m = pp.size(); i < m; i++) pp.push_back(adjoint(pp[i]));
+          if (proj(pp, fam, pos, r, r)) return err.code;
+        }
+        {
+          std::vector<RProd> pp;
+          for (int s : sp)
+            for (int t : sp) {
+              std::vector<std::pair<double, RF>> parts;
+              if (s == t) parts.push_back({-1.0 / std::sqrt(2.0), famc(F_Q0, 0, 0)});
+              double c1 = cg(1, s, 1, -t, 2, s - t);
+              if (c1 != 0.0) parts.push_back({-sgn2(1 + t) * c1 / std::sqrt(3.0), famc(F_Q1, 0, s - t)});
+              for (auto &qp : parts) {
+                RProd q;
+                q.coef = qp.first;
+                q.f.push_back(qp.second);
+                q.f.push_back(elem_r(r, r, t, true, q.coef));
+                q.f.push_back(elem_r(r, r, s, false, q.coef));
+                pp.push_back(q);
+              }
+            }
+          if (proj(pp, fam, pos, r, r)) return err.code;
+        }
+        for (int bi = -1; bi < n; bi++) {
+          if (bi >= 0 && bi <= r) continue;
+          auto in_inst = [&](std::initializer_list<int> idx) {
+            int nb = 0, which = -1;
+            for (int i : idx) if (i > r) { nb++; which = i; }
+            return nb == (bi < 0 ? 0 : 1) && (bi < 0 || which == bi);
+          };
+          std::vector<RProd> pp;
+          for (int i = r; i < n; i++)
+            for (int j = r; j < n; j++) {
+              if (!in_inst({i, j}) || h(i, j) == 0.0) continue;
+              for (int s : sp) {
+                RProd q;
+                q.coef = h(i, j);
+                q.f.push_back(elem_r(i, r, s, true, q.coef));
+                q.f.push_back(elem_r(j, r, s, false, q.coef));
+                pp.push_back(q);
+              }
+            }
+          for (int i = r; i < n; i++)
+            for (int j = r; j < n; j++)
+              for (int k = r; k < n; k++)
+                for (int l = r; l < n; l++) {
+                  if (!in_inst({i, j, k, l}) || v(i, j, k, l) == 0.0) continue;
+                  for (int s : sp)
+                    for (int t : sp) {
+                      if ((i == k || j == l) && s == t) continue;
+                      RProd q;
+                      q.coef = 0.5 * v(i, j, k, l);
+                      q.f.push_back(elem_r(i, r, s, true, q.coef));
+                      q.f.push_back(elem_r(k, r, t, true, q.coef));
+                      q.f.push_back(elem_r(l, r, t, false, q.coef));
+                      q.f.push_back(elem_r(j, r, s, false, q.coef));
+                      pp.push_back(q);
+                    }
+                }
+          if (pp.empty()) continue;
+          if (proj(pp, fam, pos, bi, -1)) return err.code;
+        }
+        continue;
+      }
+      if (fam == F_C) {
+        if (x > r) { if (!direct(fam, pos, x, -1)) return err.code; continue; }
+        RProd q;
+        q.coef = 1.0;
+        q.f.push_back(elem_r(r, r, 1, true, q.coef));
+        if (proj({q}, fam, pos, -1, -1)) return err.code;
+        continue;
+      }
+      if (fam == F_S) {
+        // (S_x)_s of R' (x < r): S_x of R + sum_t (P_xr)_ts a+_rt + sum_t (Q_xr)_st a_rt + explicit
+        const double scale = -1.0 / std::sqrt(2.0);
+        const int s = -1;
+        if (!direct(fam, pos, x, -1)) return err.code;
+        {
+          std::vector<RProd> pp;
+          for (int t : sp)
+            for (int K = 0; K <= 2; K += 2) {
+              double cP = sgn2(2 + t + s) * cg(1, -t, 1, -s, K, -t - s);
+              if (cP == 0.0) continue;
+              RProd q;
+              q.coef = scale * cP;
+              q.f.push_back(famc(K == 0 ? F_P0 : F_P1, 0, -t - s));
+              q.f.push_back(elem_r(r, r, t, true, q.coef));
+              pp.push_back(q);
+            }
+          if (proj(pp, fam, pos, x, r)) return err.code;
+        }
+        {
+          std::vector<RProd> pp;
+          for (int t : sp) {
+            std::vector<std::pair<double, RF>> parts;   // (Q_xr)_st: t2 = s, s2 = t
+            if (t == s) parts.push_back({-1.0 / std::sqrt(2.0), famc(F_Q0, 0, 0)});
+            double c1 = cg(1, t, 1, -s, 2, t - s);
+            if (c1 != 0.0) parts.push_back({-sgn2(1 + s) * c1 / std::sqrt(3.0), famc(F_Q1, 0, t - s)});
+            for (auto &qp : parts) {
+              RProd q;
+              q.coef = scale * qp.first;
+              q.f.push_back(qp.second);
+              q.f.push_back(elem_r(r, r, t, false, q.coef));
+              pp.push_back(q);
+            }
+          }
+          if (proj(pp, fam, pos, x, r)) return err.code;
+        }
+        for (int bi = -1; bi < n; bi++) {
+          if (bi >= 0 && bi <= r) continue;
+          std::vector<RProd> pp;
+          for (int j = r; j < n; j++)
+            for (int k = r; k < n; k++)
+              for (int l = r; l < n; l++) {
+                int atr = (j == r) + (k == r) + (l == r);
+                if (atr < 2 || v(x, j, k, l) == 0.0) continue;
+                int which = j > r ? j : k > r ? k : l > r ? l : -1;
+                if (which != bi) continue;
+                for (int t : sp) {
+                  RProd q;
+                  q.coef = scale * v(x, j, k, l);
+                  q.f.push_back(elem_r(k, r, t, true, q.coef));
+                  q.f.push_back(elem_r(l, r, t, false, q.coef));
+                  q.f.push_back(elem_r(j, r, s, false, q.coef));
+                  pp.push_back(q);
+                }
+              }
+          if (pp.empty()) continue;
+          if (proj(pp, fam, pos, bi, -1)) return err.code;
+        }
+        continue;
+      }
+      // P^K / Q^K of R' for the pair (x, y), x, y < r
+      if (!direct(fam, pos, x, y)) return err.code;
+      const int K2 = FAM_TWO_K[fam];
+      std::vector<std::array<double, 3>> ts;
+      for (int t : sp)
+        for (int s2 : sp) {
+          if (fam == F_P0 || fam == F_P1) {
+            if (-t - s2 == K2) ts.push_back({(double)t, (double)s2, cg(1, -t, 1, -s2, K2, K2) * sgn2(2 + t + s2)});
+          } else if (fam == F_Q0) {
+            if (t == s2) ts.push_back({(double)t, (double)s2, -1.0 / std::sqrt(2.0)});
+          } else if (t == -1 && s2 == 1) {
+            ts.push_back({(double)t, (double)s2, -std::sqrt(3.0)});
+          }
+        }
+      for (int bi = -1; bi < n; bi++) {
+        if (bi >= 0 && bi <= r) continue;
+        auto inst = [&](int i1, int i2) {
+          if (i1 > r && i2 > r) return false;
+          int which = i1 > r ? i1 : i2 > r ? i2 : -1;
+          return which == bi;
+        };
+        std::vector<RProd> pp;
+        for (auto &w : ts) {
+          const int t = (int)w[0], s2 = (int)w[1];
+          for (int a = r; a < n; a++)
+            for (int b = r; b < n; b++) {
+              if (!inst(a, b)) continue;
+              if (fam == F_P0 || fam == F_P1) {
+                double vv = v(x, a, y, b);
+                if (vv == 0.0) continue;
+                RProd q;
+                q.coef = w[2] * vv;
+                q.f.push_back(elem_r(b, r, t, false, q.coef));
+                q.f.push_back(elem_r(a, r, s2, false, q.coef));
+                pp.push_back(q);
+              } else {
+                if (t == s2 && v(x, y, a, b) != 0.0)
+                  for (int sg : sp) {
+                    RProd q;
+                    q.coef = w[2] * v(x, y, a, b);
+                    q.f.push_back(elem_r(a, r, sg, true, q.coef));
+                    q.f.push_back(elem_r(b, r, sg, false, q.coef));
+                    pp.push_back(q);
+                  }
+                if (v(x, b, a, y) != 0.0) {
+                  RProd q;
+                  q.coef = -w[2] * v(x, b, a, y);
+                  q.f.push_back(elem_r(a, r, s2, true, q.coef));
+                  q.f.push_back(elem_r(b, r, t, false, q.coef));
+                  pp.push_back(q);
+                }
+              }
+            }
+        }
+        if (pp.empty()) continue;
+        if (proj(pp, fam, pos, bi, -1)) return err.code;
+      }
+    }
+  }
+  return DMRG_OK;
+}
+
 struct RComp { int lsec, site, row0, dim; };
 struct RSec {
   int n, two_s, rows;
   std::vector<RComp> comps;
 };
+
+// right side: components (site multiplet, block sector) with the site outer
+std::vector<RSec> product_sectors_right(const std::vector<dmrg_sector_t> &bsec) {
+  std::map<std::pair<int, int>, RSec> m;
+  for (int s = 0; s < 3; s++)
+    for (int a = 0; a < (int)bsec.size(); a++)
+      for (int S = std::abs(bsec[a].two_s - RSITE_S[s]); S <= bsec[a].two_s + RSITE_S[s]; S += 2) {
+        auto &r = m[{bsec[a].n + RSITE_N[s], S}];
+        r.n = bsec[a].n + RSITE_N[s];
+        r.two_s = S;
+        r.comps.push_back({a, s, r.rows, bsec[a].dim});
+        r.rows += bsec[a].dim;
+      }
+  std::vector<RSec> out;
+  for (auto &kv : m) out.push_back(kv.second);
+  return out;
+}
 
 std::vector<RSec> product_sectors(const std::vector<dmrg_sector_t> &lsec) {
   std::map<std::pair<int, int>, RSec> m;
@@ -649,8 +951,16 @@ int build_renorm(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int n_kee
     return err.code;
   }
   const bool all_pairs = flags & RENORM_ALL_PAIRS;
-  if (flags & ~RENORM_ALL_PAIRS) { err = {DMRG_EINVAL, "unknown renormalization flag"}; return err.code; }
-  const int allowed = RENORM_DEFAULT_MASK | (all_pairs ? RENORM_PAIR_MASK : 0);
+  const bool right = flags & RENORM_RIGHT;
+  if (flags & ~(RENORM_ALL_PAIRS | RENORM_RIGHT) || (right && all_pairs)) {
+    err = {DMRG_EINVAL, "unknown renormalization flag or combination"};
+    return err.code;
+  }
+  if (right && pr.site_l + 2 >= pr.n_orb) {
+    err = {DMRG_EINVAL, "renormalization of the right block needs a non-empty right block"};
+    return err.code;
+  }
+  const int allowed = right ? RENORM_RIGHT_MASK : RENORM_DEFAULT_MASK | (all_pairs ? RENORM_PAIR_MASK : 0);
   if (mask == 0) mask = allowed;
   if (mask & ~allowed) {
     err = {DMRG_EINVAL, all_pairs ? "unknown family in the mask"
@@ -662,11 +972,14 @@ int build_renorm(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int n_kee
     if (!std::isfinite(pr.h1[i])) { err = {DMRG_ENONFINITE, "non-finite one-electron integral"}; return err.code; }
   for (int64_t i = 0; i < (int64_t)n4 * n4 * n4 * n4; i++)
     if (!std::isfinite(pr.eri[i])) { err = {DMRG_ENONFINITE, "non-finite two-electron integral"}; return err.code; }
+  // L: the block being enlarged (the right block with RENORM_RIGHT)
   BlockModel L;
-  if (build_left(L, pr, all_pairs, err)) return err.code;
+  if (right ? build_block(L, 1, pr, err) : build_left(L, pr, all_pairs, err)) return err.code;
+  const int64_t blen = right ? pr.rdata_len : pr.ldata_len;
   SiteAlgebra site;
   std::vector<RTerm> terms;
-  if (build_terms(pr, L, site, mask, terms, err)) return err.code;
+  if (right ? build_terms_right(pr, L, site, mask, terms, err) : build_terms(pr, L, site, mask, terms, err))
+    return err.code;
   // Dressing: terms that differ only in the position of their C factor (a
   // sum over an orbital j with integral weights, e.g. sum_j (xj|yl) C~_j (x)
   // a~_l in P_xy) are merged into one term on sum_j alpha_j C_j, formed once
@@ -711,7 +1024,7 @@ int build_renorm(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int n_kee
     terms.swap(kept_terms);
   }
   B.n_terms = (int64_t)terms.size();
-  std::vector<RSec> prod = product_sectors(L.sec);
+  std::vector<RSec> prod = right ? product_sectors_right(L.sec) : product_sectors(L.sec);
   std::map<std::pair<int, int>, int> pidx;
   for (int i = 0; i < (int)prod.size(); i++) pidx[{prod[i].n, prod[i].two_s}] = i;
   std::vector<int> kp(n_keep);
@@ -776,9 +1089,18 @@ int build_renorm(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int n_kee
               ph = sgn2(Sa + t.ta.k2 - Sb) * std::sqrt((Sa + 1.0) / (Sb + 1.0));
             }
             if (t.ta.kind && rec < 0) continue;
-            double c = wl.get(Sa, RSITE_S[ca.site], pa.two_s, kA, kB, K, Sb, RSITE_S[cb.site], pb.two_s);
+            // Eq. (4) factor in the W9j(l) role (block x site) or the W9j(r)
+            // role (site x block); Jordan-Wigner sign of the later factor
+            // passing the earlier part of the ket
+            double c, sgn;
+            if (!right) {
+              c = wl.get(Sa, RSITE_S[ca.site], pa.two_s, kA, kB, K, Sb, RSITE_S[cb.site], pb.two_s);
+              sgn = (t.tb.kind && t.tb.par && (L.sec[ca.lsec].n % 2)) ? -1.0 : 1.0;
+            } else {
+              c = wl.get(RSITE_S[ca.site], Sa, pa.two_s, kB, kA, K, RSITE_S[cb.site], Sb, pb.two_s);
+              sgn = (t.ta.kind && t.ta.par && (RSITE_N[ca.site] % 2)) ? -1.0 : 1.0;
+            }
             if (c == 0.0) continue;
-            double sgn = (t.tb.kind && t.tb.par && (L.sec[ca.lsec].n % 2)) ? -1.0 : 1.0;
             double coef = t.alpha * sv * c * sgn * ph;
             if (std::fabs(coef) < 1e-300) continue;
             int tix = -1;
@@ -805,7 +1127,7 @@ int build_renorm(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int n_kee
     r.fam = kv.first[0];
     r.row_sec = kv.first[1];
     r.col_sec = kv.first[2];
-    r.npos = (int32_t)left_labels(r.fam, pr.site_l + 1, pr.n_orb).size();
+    r.npos = (int32_t)(right ? right_labels(r.fam, pr.site_l - 1, pr.n_orb) : left_labels(r.fam, pr.site_l + 1, pr.n_orb)).size();
     r.off = B.out_len;
     kv.second = B.out_len;
     B.out_len += (int64_t)r.npos * keep[r.row_sec].kept * keep[r.col_sec].kept;
@@ -951,7 +1273,7 @@ int build_renorm(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int n_kee
   auto inside = [&](const std::vector<Tile> &tiles, const std::vector<Seg> &segs) {
     auto len = [&](int base) { return base == BASE_PSI ? u_len : base == BASE_Y ? B.out_len
                                     : base == BASE_WORK ? B.work_len : base == BASE_OPS + 2 ? B.dress_len
-                                    : pr.ldata_len; };
+                                    : blen; };
     for (const Tile &T : tiles) {
       const int64_t last = T.rowmajor ? (int64_t)(T.m - 1) * T.ldc + (T.n - 1) : (T.m - 1) + (int64_t)(T.n - 1) * T.ldc;
       if (T.c_off < 0 || T.c_off + last >= len(T.c_base)) return false;
@@ -1056,14 +1378,17 @@ extern "C" void dmrg_renorm_free(dmrg_renorm_t *r) {
   delete r;
 }
 
-extern "C" int dmrg_renorm_product(const dmrg_problem_t *prob, dmrg_sector_t *sec, int32_t sec_cap, int32_t *n_sec,
-                                   dmrg_rcomp_t *comp, int32_t comp_cap, int32_t *n_comp) {
-  if (!prob || !n_sec || !n_comp || prob->n_lsec <= 0 || !prob->lsec) {
-    set_error("null argument or empty left sector table");
+extern "C" int dmrg_renorm_product(const dmrg_problem_t *prob, int32_t flags, dmrg_sector_t *sec, int32_t sec_cap,
+                                   int32_t *n_sec, dmrg_rcomp_t *comp, int32_t comp_cap, int32_t *n_comp) {
+  const bool right = flags & RENORM_RIGHT;
+  const int ns = prob ? (right ? prob->n_rsec : prob->n_lsec) : 0;
+  const dmrg_sector_t *bs = prob ? (right ? prob->rsec : prob->lsec) : nullptr;
+  if (!prob || !n_sec || !n_comp || ns <= 0 || !bs) {
+    set_error("null argument or empty sector table");
     return DMRG_EINVAL;
   }
-  std::vector<dmrg_sector_t> ls(prob->lsec, prob->lsec + prob->n_lsec);
-  std::vector<RSec> prod = product_sectors(ls);
+  std::vector<dmrg_sector_t> ls(bs, bs + ns);
+  std::vector<RSec> prod = right ? product_sectors_right(ls) : product_sectors(ls);
   *n_sec = (int32_t)prod.size();
   int32_t nc = 0;
   for (int i = 0; i < (int)prod.size(); i++) {
@@ -1089,8 +1414,11 @@ extern "C" int dmrg_renorm_create(const dmrg_problem_t *prob, const dmrg_rkeep_t
     auto r = std::make_unique<dmrg_renorm>();
     Error err{0, ""};
     if (build_renorm(prob, keep, n_keep, fam_mask, flags, u_len, r->b, err)) { set_error(err.msg); return err.code; }
-    if (!prob->ldata) { set_error("left operator data missing"); return DMRG_EINVAL; }
-    r->ldata = prob->ldata;
+    const bool right = flags & RENORM_RIGHT;
+    const double *bdata = right ? prob->rdata : prob->ldata;
+    const int64_t blen = right ? prob->rdata_len : prob->ldata_len;
+    if (!bdata) { set_error("operator data of the block missing"); return DMRG_EINVAL; }
+    r->ldata = bdata;
     auto up = [&](void **dst, const void *src, size_t bytes) -> bool {
       if (bytes == 0) bytes = 16;
       if (hipMalloc(dst, bytes) != hipSuccess) return false;
@@ -1098,14 +1426,14 @@ extern "C" int dmrg_renorm_create(const dmrg_problem_t *prob, const dmrg_rkeep_t
     };
     r->u_len = u_len;
     bool ok = up((void **)&r->d_ut, nullptr, (size_t)u_len * sizeof(double)) &&
-              up((void **)&r->d_lt, nullptr, r->b.ljobs.empty() ? 0 : (size_t)prob->ldata_len * sizeof(double)) &&
+              up((void **)&r->d_lt, nullptr, r->b.ljobs.empty() ? 0 : (size_t)blen * sizeof(double)) &&
               up((void **)&r->d_uj, r->b.ujobs.data(), r->b.ujobs.size() * sizeof(TransJob)) &&
               up((void **)&r->d_lj, r->b.ljobs.data(), r->b.ljobs.size() * sizeof(TransJob));
     ok = ok && up((void **)&r->d_dress, nullptr, (size_t)r->b.dress_len * sizeof(double)) &&
          up((void **)&r->d_di, r->b.ditems.data(), r->b.ditems.size() * sizeof(DressItem)) &&
          up((void **)&r->d_dsrc, r->b.dsrc.data(), r->b.dsrc.size() * sizeof(int64_t)) &&
          up((void **)&r->d_dalpha, r->b.dalpha.data(), r->b.dalpha.size() * sizeof(double));
-    const double *bases[3] = {prob->ldata, r->d_lt, r->d_dress};
+    const double *bases[3] = {bdata, r->d_lt, r->d_dress};
     ok = ok && up((void **)&r->d_t1, r->b.t1.data(), r->b.t1.size() * sizeof(Tile)) &&
               up((void **)&r->d_t2, r->b.t2.data(), r->b.t2.size() * sizeof(Tile)) &&
               up((void **)&r->d_s1, r->b.s1.data(), r->b.s1.size() * sizeof(Seg)) &&
@@ -1121,7 +1449,7 @@ extern "C" int dmrg_renorm_create(const dmrg_problem_t *prob, const dmrg_rkeep_t
     // transposed copies of the left records applied as adjoints, then the
     // dressed operators (once)
     if (!r->b.ljobs.empty() || !r->b.ditems.empty()) {
-      launch_transpose(r->d_lj, (int)r->b.ljobs.size(), prob->ldata, r->d_lt, nullptr);
+      launch_transpose(r->d_lj, (int)r->b.ljobs.size(), bdata, r->d_lt, nullptr);
       launch_dress(r->d_di, (int)r->b.ditems.size(), r->d_dsrc, r->d_dalpha, r->d_bases, r->d_dress, nullptr);
       if (hipStreamSynchronize(nullptr) != hipSuccess) {
         dmrg_renorm_free(r.release());
@@ -1248,17 +1576,20 @@ extern "C" int dmrg_debug_renorm_host(const dmrg_problem_t *prob, const dmrg_rke
     }
     if (rec) std::memcpy(rec, b.recs.data(), std::min<int64_t>(rec_cap, (int64_t)b.recs.size()) * sizeof(dmrg_oprec_t));
     if (!out) return DMRG_OK;
-    if (!u || !prob->ldata || out_len < b.out_len) { set_error("missing input or output too small"); return DMRG_EINVAL; }
+    const bool right = flags & RENORM_RIGHT;
+    const double *bdata = right ? prob->rdata : prob->ldata;
+    const int64_t blen = right ? prob->rdata_len : prob->ldata_len;
+    if (!u || !bdata || out_len < b.out_len) { set_error("missing input or output too small"); return DMRG_EINVAL; }
     std::vector<double> work((size_t)std::max<int64_t>(b.work_len, 1));
     std::vector<double> ut((size_t)std::max<int64_t>(u_len, 1)), lt;
     host_transpose(b.ujobs, u, ut.data());
     if (!b.ljobs.empty()) {
-      lt.assign((size_t)prob->ldata_len, 0.0);
-      host_transpose(b.ljobs, prob->ldata, lt.data());
+      lt.assign((size_t)blen, 0.0);
+      host_transpose(b.ljobs, bdata, lt.data());
     }
     std::vector<double> dr((size_t)std::max<int64_t>(b.dress_len, 1), 0.0);
     for (const DressItem &d : b.ditems) {
-      const double *src = d.src_base == BASE_OPS ? prob->ldata : lt.data();
+      const double *src = d.src_base == BASE_OPS ? bdata : lt.data();
       for (int64_t e = 0; e < d.n; e++) {
         double acc = 0.0;
         for (int t = d.t0; t < d.t1; t++) acc += b.dalpha[t] * src[b.dsrc[t] + e];
@@ -1266,8 +1597,8 @@ extern "C" int dmrg_debug_renorm_host(const dmrg_problem_t *prob, const dmrg_rke
       }
     }
     std::fill(out, out + b.out_len, 0.0);
-    host_run(b.t1, b.s1, prob->ldata, lt.data(), dr.data(), ut.data(), out, work.data());
-    host_run(b.t2, b.s2, prob->ldata, lt.data(), dr.data(), ut.data(), out, work.data());
+    host_run(b.t1, b.s1, bdata, lt.data(), dr.data(), ut.data(), out, work.data());
+    host_run(b.t2, b.s2, bdata, lt.data(), dr.data(), ut.data(), out, work.data());
     return DMRG_OK;
   } catch (const std::bad_alloc &) {
     set_error("host allocation failed");

@@ -224,20 +224,27 @@ class Renorm:
     array (rows of that product sector x kept) or ``u`` a device tensor that
     already holds the matrices at the offsets ``keep_array`` would give."""
 
-    def __init__(self, prob, keep, device="cuda:0", fam_mask=0, ldata=None):
+    def __init__(self, prob, keep, device="cuda:0", fam_mask=0, ldata=None, right=False):
+        """right: renormalize the right block through the right site instead
+        (``ldata`` then stands for the right block's device data)."""
         torch = _torch()
         self.lib = B.load()
         if not hasattr(self.lib, "dmrg_renorm_create"):
             raise RuntimeError("library has no renormalization entry points")
         self.device = torch.device(device)
         self.prob, self.keep = prob, keep
+        self.right = right
+        blk = prob.right if right else prob.left
         self.ld = ldata if ldata is not None else \
-            torch.from_numpy(np.ascontiguousarray(prob.left.data)).to(self.device)
-        self.args = B.ProblemArgs(prob, self.ld.data_ptr(), 0)
+            torch.from_numpy(np.ascontiguousarray(blk.data)).to(self.device)
+        self.args = B.ProblemArgs(prob, 0 if right else self.ld.data_ptr(), self.ld.data_ptr() if right else 0)
         self.karr, flat, self.u_len = B.keep_array(keep)
         self.u = torch.from_numpy(flat).to(self.device)
         h = ctypes.c_void_p()
-        flags = B.DMRG_RENORM_ALL_PAIRS if getattr(prob.left, "all_pairs", False) else 0
+        if right:
+            flags = B.DMRG_RENORM_RIGHT
+        else:
+            flags = B.DMRG_RENORM_ALL_PAIRS if getattr(prob.left, "all_pairs", False) else 0
         B.check(self.lib.dmrg_renorm_create(ctypes.byref(self.args.s), ctypes.addressof(self.karr), len(keep),
                                             fam_mask, flags, self.u_len, ctypes.byref(h)), self.lib)
         self.handle = h
@@ -276,7 +283,7 @@ class Renorm:
         """The new block as host BlockData (after apply)."""
         _torch().cuda.synchronize(self.device)
         return B.records_block(self.prob, self.keep, self.recs[:self.n_rec],
-                               self.out[:self.out_len].cpu().numpy())
+                               self.out[:self.out_len].cpu().numpy(), self.right)
 
     def free(self):
         if getattr(self, "handle", None):

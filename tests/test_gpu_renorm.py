@@ -148,3 +148,30 @@ def test_renorm_properties_at_larger_size(torch):
         want = np.einsum("ji,pjk,kl->pil", rots[rs], a, rots[cs])
         worst = max(worst, np.abs(b - want).max() / max(1.0, np.abs(a).max()))
     assert worst < 1e-11
+
+
+def test_right_block_matches_oracle(torch):
+    """Site x right block on the GPU: every family of the enlarged right
+    block against the oracle (product sectors over 64 rows, ragged tiles),
+    and the Fock-space block of an exact problem."""
+    from oracle.renorm import renormalize_right, product_sectors_right, RIGHT_FAMILIES
+    from tests.test_oracle_renorm import exact_keep_right
+    args = dict(n_orb=12, n_elec=12, two_s=0, seed=35, D=160, p=5, spin_ratio=0.3, sigma_frac=0.06)
+    _say("renorm right parity %s" % args)
+    prob = random_problem(**args)
+    rng = np.random.default_rng(12)
+    keep = [(N, S, np.linalg.qr(rng.standard_normal((rows, max(1, (2 * rows) // 3))))[0])
+            for (N, S, rows, comps) in product_sectors_right(prob.right.sectors)]
+    assert max(U.shape[0] for _, _, U in keep) > 64
+    got, st = _gpu_block(prob, keep, right=True)
+    want = renormalize_right(prob, keep)
+    for fam in RIGHT_FAMILIES:
+        d = rel_diff(got, want, fam)
+        assert d < TOL, (cat.NAMES[fam], d)
+    _say("renorm right exact L=7 p=2")
+    prob = exact_problem(7, 7, 1, 21, p=2)
+    big = build_exact_block("R", 7, 1, prob.h, prob.eri, max_mult=48)
+    keep = exact_keep_right(prob.right, big)
+    got, _ = _gpu_block(prob, keep, right=True)
+    for fam in RIGHT_FAMILIES:
+        assert rel_diff(got, big, fam) < TOL, cat.NAMES[fam]

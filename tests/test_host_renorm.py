@@ -121,3 +121,64 @@ def test_host_pair_families_match_oracle(lib, case):
     assert got.all_pairs
     for fam in RENORM_FAMILIES + PAIR_FAMILIES:
         assert max_family_diff(got, want, fam) < 1e-12, cat.NAMES[fam]
+
+
+def rand_keep_right(prob, frac, seed):
+    from oracle.renorm import product_sectors_right
+    rng = np.random.default_rng(seed)
+    keep = []
+    for (N, S, rows, comps) in product_sectors_right(prob.right.sectors):
+        k = max(1, int(round(rows * frac)))
+        keep.append((N, S, np.linalg.qr(rng.standard_normal((rows, k)))[0]))
+    return keep
+
+
+def test_right_product_layout_matches_oracle(lib):
+    from oracle.renorm import product_sectors_right
+    prob = random_problem(10, 10, 0, 7, 48, p=4)
+    secs, comps = B.renorm_product(prob, lib, right=True)
+    want = product_sectors_right(prob.right.sectors)
+    assert secs == [(N, S, rows) for (N, S, rows, c) in want]
+    assert comps == [(i, b, m, r0, d) for i, (N, S, rows, cs) in enumerate(want) for (m, b, r0, d) in cs]
+
+
+@pytest.mark.parametrize("case", ["exact_full", "exact_cut", "random_cut", "random_odd"])
+def test_host_right_block_matches_oracle(lib, case):
+    """Site x right block: every family of the enlarged right block from the
+    host-executed lists against the oracle."""
+    from oracle.renorm import renormalize_right, RIGHT_FAMILIES
+    if case == "exact_full":
+        prob, frac = exact_problem(6, 6, 0, 21, p=2), 1.0
+    elif case == "exact_cut":
+        prob, frac = exact_problem(7, 7, 1, 22, p=2), 0.6
+    elif case == "random_cut":
+        prob, frac = random_problem(10, 10, 0, 7, 32, p=4), 0.5
+    else:
+        prob, frac = random_problem(9, 9, 1, 8, 40, p=3), 0.7
+    keep = rand_keep_right(prob, frac, 3)
+    want = renormalize_right(prob, keep)
+    got, st = B.debug_renorm_host(prob, keep, lib=lib, right=True)
+    assert got.role == "R" and got.p == prob.p - 1
+    for fam in RIGHT_FAMILIES:
+        assert max_family_diff(got, want, fam) < 1e-12, cat.NAMES[fam]
+
+
+def test_right_renorm_error_codes(lib):
+    prob = random_problem(10, 10, 0, 7, 32, p=4)
+    keep = rand_keep_right(prob, 0.5, 5)
+    ld, rd = np.ascontiguousarray(prob.left.data), np.ascontiguousarray(prob.right.data)
+    args = B.ProblemArgs(prob, ld.ctypes.data, rd.ctypes.data)
+    karr, u, ulen = B.keep_array(keep)
+    st = B.RenormStats()
+
+    def call(flags, mask=0, a=args):
+        return lib.dmrg_debug_renorm_host(ctypes.byref(a.s), ctypes.addressof(karr), len(keep), mask, flags, None,
+                                          ulen, None, 0, None, 0, ctypes.byref(st))
+    assert call(B.DMRG_RENORM_RIGHT) == 0
+    assert call(B.DMRG_RENORM_RIGHT | B.DMRG_RENORM_ALL_PAIRS) == -1
+    assert call(B.DMRG_RENORM_RIGHT, mask=1 << cat.A0) == -1     # no pair families A/B on the right
+    assert call(8) == -1
+    pe = random_problem(10, 10, 0, 7, 32, p=8)                    # empty right block
+    ae = B.ProblemArgs(pe, np.ascontiguousarray(pe.left.data).ctypes.data,
+                       np.ascontiguousarray(pe.right.data).ctypes.data)
+    assert call(B.DMRG_RENORM_RIGHT, a=ae) == -1
