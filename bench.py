@@ -144,9 +144,12 @@ MEASURED_TRAFFIC = {
     ("L54_D2048", "stage2_wsplit5_kernel"): (2.2778e11, _SPLIT_SRC, "fd14f25f69d6d718"),
     ("L54_D2048", "stage_f64_kernel<1>"): (3.5086e11, _F64_SRC, "69c8d5cbc4f75ca9"),
     ("L54_D2048", "stage_f64_kernel<2>"): (1.0639e12, _F64_SRC, "69c8d5cbc4f75ca9"),
-    # renormalization of the L54_D2048 left block (profiles/renorm_L54_D2048_fp64.md)
-    ("L54_D2048", "renorm:stage_f64_kernel<1>"): (1.4020e11, _REN_SRC, "d0c760c170acfe42"),
-    ("L54_D2048", "renorm:stage_f64_kernel<2>"): (1.8112e11, _REN_SRC, "d0c760c170acfe42"),
+    # renormalization of the L54_D2048 left block (profiles/renorm_left_L54_D2048_fp64.md)
+    ("L54_D2048", "renorm:stage_f64_kernel<1>"): (1.3855e11, _REN_SRC, "7150222daa7f2493"),
+    ("L54_D2048", "renorm:stage_f64_kernel<2>"): (1.7818e11, _REN_SRC, "7150222daa7f2493"),
+    # the right block through the right site (profiles/renorm_right_L54_D2048_fp64.md)
+    ("L54_D2048", "renorm_right:stage_f64_kernel<1>"): (3.1297e11, _REN_SRC, "7150222daa7f2493"),
+    ("L54_D2048", "renorm_right:stage_f64_kernel<2>"): (5.3775e11, _REN_SRC, "7150222daa7f2493"),
 }
 
 
