@@ -412,10 +412,17 @@ const char *dmrg_last_error(void);
  *
  * dmrg_renorm_create builds the term and product lists on the host and
  * copies them to the device (hipMalloc, freed by dmrg_renorm_free); the
- * left data pointer is kept until then.  dmrg_renorm_apply runs the two
- * FP64 product stages of the H.psi engine on `stream` (T = op(A) U rows,
- * then new = sum coef U^T T per output tile in a fixed order: bitwise
- * reproducible) and returns before they finish.  Errors: DMRG_EINVAL
+ * block's data pointer is kept until then and its contents must not change:
+ * create also makes, on the null stream and waiting for them, a transposed
+ * copy of the records applied as adjoints and the dressed operators (terms
+ * that differ only in the position of their C factor merged into one term
+ * on sum_j alpha_j C_j).  The lists' memory is about the first-stage
+ * workspace (work_elems doubles) plus one block-data-sized buffer.
+ * dmrg_renorm_apply transposes U per kept sector and runs the two FP64
+ * product stages of the H.psi engine on `stream` (T = op(A) U rows, then
+ * new = sum coef U^T T per output tile in a fixed order: bitwise
+ * reproducible) and returns before they finish; calls on one handle must
+ * not overlap (they share its workspace).  Errors: DMRG_EINVAL
  * (arguments, families), DMRG_ESYM (a kept (N, 2S) that is no product
  * sector), DMRG_ERANGE (U beyond u_len, outputs too small), DMRG_ENONFINITE
  * (integrals), DMRG_ENOMEM, DMRG_EHIP. */
