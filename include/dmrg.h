@@ -464,6 +464,30 @@ int dmrg_renorm_get_profile(dmrg_renorm_t *r, int32_t stage, int64_t *n_launches
                             double *total_flops);
 void dmrg_renorm_free(dmrg_renorm_t *r);
 
+/* ---- truncation of a two-site step (the U of dmrg_renorm_create) -------
+ * Sec. II (two-site DMRG; the truncation rule is left to the reviews the
+ * paper cites): for every product sector (N, 2S) of (left block) x (left
+ * site), rows as in the renormalization's product basis, the reduced density
+ * matrix rho(a, a') = sum_c X_{a,c} X_{a',c}^T over the right parts c =
+ * (r, right sector, 2S_rR) of the wavefunction blocks (psi: DEVICE, the
+ * problem's reduced coefficients in the dmrg_psi_layout order) is formed on
+ * the GPU tile engine and diagonalised with rocSOLVER (dsyevd) on `stream`;
+ * the eigenvectors of the max_kept largest eigenvalues over all sectors
+ * (eigenvalues <= cutoff dropped; ties by sector order, then rank) are kept.
+ * Outputs: keep[n_keep] (host) in product-sector order, sectors without
+ * kept states left out, u_off into u (DEVICE, u_len elements: per kept
+ * sector a column-major rows x kept matrix, columns in descending eigenvalue
+ * order, signs as the eigensolver returns them) -- exactly the input of
+ * dmrg_renorm_create; weights[0] = kept eigenvalue sum, weights[1] = trace
+ * (|psi|^2), if weights is not NULL.  With keep or u NULL only the sizes
+ * (n_keep, u_len) and weights are returned; DMRG_ERANGE when keep_cap or
+ * u_cap is short.  Device scratch (rho, lists, eigensolver workspace) is
+ * taken with hipMalloc and freed before returning; the call waits for its
+ * work on `stream`. */
+int dmrg_truncate(const dmrg_problem_t *prob, const double *psi, int32_t max_kept, double cutoff,
+                  dmrg_rkeep_t *keep, int32_t keep_cap, int32_t *n_keep, double *u, int64_t u_cap,
+                  int64_t *u_len, double *weights, void *stream);
+
 /* ---- host-logic inspection (no GPU use; for tests of the host tables) ---- */
 /* Wigner 6j {a b c; d e f}, 9j and the Eq. (4) factor, doubled spins.       */
 double dmrg_wigner_6j(int a, int b, int c, int d, int e, int f);

@@ -14,7 +14,9 @@ OUT = os.path.join(HERE, "libdmrg_hpsi.so")
 BUILD = os.path.join(HERE, "_build")
 
 HOST_SRC = ["wigner.cpp", "model.cpp", "api_host.cpp"]
-HIP_HOST_SRC = ["plan.cpp", "davidson.cpp", "mlp.cpp", "renorm.cpp"]
+HIP_HOST_SRC = ["plan.cpp", "davidson.cpp", "mlp.cpp", "renorm.cpp", "truncate.cpp"]
+# rocSOLVER (dsyevd) for the truncation's eigenvectors
+LINK_LIBS = ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocsolver", "-lrocblas"]
 HIP_SRC = ["kernels_f64.hip", "kernels_vec.hip", "kernels_split.hip", "kernels_mlp.hip", "apply_static.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
@@ -46,7 +48,7 @@ def build(verbose=False):
         list(ex.map(lambda j: _run(j[0]), jobs))
     objs = [o for _, o in jobs]
     tmp = OUT + ".tmp"
-    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + LINK_LIBS)
     os.replace(tmp, OUT)
     if verbose:
         print("built", OUT)
