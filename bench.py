@@ -498,6 +498,32 @@ def renorm_run(torch, workload, steps, warmup, prob=None, all_pairs=False, right
                          "traffic": measured_traffic(workload, ("renorm_right:" if right else "renorm:") + kname)}}
 
 
+def truncation_run(torch, prob, D, reps=3):
+    """Truncation of a two-site step on the workload (dmrg_truncate): the
+    reduced density matrix of (left block x left site) per sector from a
+    seeded normalized wavefunction, its eigenvectors, the D largest kept.
+    Wall time of the whole call (lists, products, eigensolver, copies)."""
+    import numpy as np
+    from paper_2309_16724_amd.hpsi import truncate
+    from paper_2309_16724_amd.binding import renorm_product
+    from oracle.layout import psi_blocks
+    _, size = psi_blocks(prob.left.sectors, prob.right.sectors, prob.n_elec, prob.two_s)
+    x = np.random.default_rng(100).standard_normal(size)
+    psi = torch.from_numpy(x / np.linalg.norm(x)).cuda()
+    secs, _ = renorm_product(prob)
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        keep, u, (kw, tr) = truncate(prob, psi, D, 1e-14)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    return {"ms": min(times), "ms_all": times, "max_kept": D, "kept": int(sum(k[2] for k in keep)),
+            "kept_sectors": len(keep), "product_sectors": len(secs), "largest_sector_rows": max(r for _, _, r in secs),
+            "kept_weight": kw, "trace": tr,
+            "note": "random normalized wavefunction; rho per sector on the FP64 tile engine, rocSOLVER dsyevd"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -605,6 +631,7 @@ def main():
         ren_r["workload"] = "%s site %d x right block (orbitals %d..%d)" % (args.workload, prob.p + 1, prob.p + 2,
                                                                          prob.n_orb - 1)
         ren["right_block"] = ren_r
+        ren["truncation"] = truncation_run(torch, prob, WORKLOADS[args.workload]["D"])
         print("# renormalization: %s" % json.dumps(ren), file=sys.stderr, flush=True)
     dav = None
     if not args.no_davidson:
