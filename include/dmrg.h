@@ -483,8 +483,11 @@ void dmrg_renorm_free(dmrg_renorm_t *r);
  * (n_keep, u_len) and weights are returned; DMRG_ERANGE when keep_cap or
  * u_cap is short.  Device scratch (rho, lists, eigensolver workspace) is
  * taken with hipMalloc and freed before returning; the call waits for its
- * work on `stream`. */
-int dmrg_truncate(const dmrg_problem_t *prob, const double *psi, int32_t max_kept, double cutoff,
+ * work on `stream`.  flags: 0, or DMRG_RENORM_RIGHT for the mirror -- the
+ * sectors of (right site) x (right block) in the right renormalization's
+ * product order, rho(b, b') = sum over left parts c = (left sector, l,
+ * 2S_Ll) of X_{c,b}^T X_{c,b'}. */
+int dmrg_truncate(const dmrg_problem_t *prob, int32_t flags, const double *psi, int32_t max_kept, double cutoff,
                   dmrg_rkeep_t *keep, int32_t keep_cap, int32_t *n_keep, double *u, int64_t u_cap,
                   int64_t *u_len, double *weights, void *stream);
 

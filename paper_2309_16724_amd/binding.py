@@ -178,7 +178,7 @@ def load(path=None):
         L.dmrg_renorm_apply.argtypes = [c_vp, c_vp, c_vp, c_vp]
         L.dmrg_renorm_stats.argtypes = [c_vp, ctypes.POINTER(RenormStats)]
         L.dmrg_renorm_set_profiling.argtypes = [c_vp, c_i32]
-        L.dmrg_truncate.argtypes = [ctypes.POINTER(ProblemT), c_vp, c_i32, c_dbl, c_vp, c_i32, ctypes.POINTER(c_i32),
+        L.dmrg_truncate.argtypes = [ctypes.POINTER(ProblemT), c_i32, c_vp, c_i32, c_dbl, c_vp, c_i32, ctypes.POINTER(c_i32),
                                     c_vp, c_i64, ctypes.POINTER(c_i64), c_vp, c_vp]
         L.dmrg_renorm_get_profile.argtypes = [c_vp, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_dbl),
                                               ctypes.POINTER(c_dbl)]

@@ -11,7 +11,9 @@
 // part c = (r, R sector, 2S_rR).  The products run on the FP64 tile engine
 // (one output tile per rho block, every right part a segment along K); the
 // eigenvectors come from rocSOLVER's dsyevd, sector by sector on the
-// caller's stream; the largest eigenvalues over all sectors are kept.
+// caller's stream; the largest eigenvalues over all sectors are kept.  The
+// mirror cuts (right site) x (right block) for the renormalization of the
+// right block: rho(b, b') = sum over left parts c of X_{c,b}^T X_{c,b'}.
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
@@ -35,6 +37,24 @@ struct TSec {
   std::vector<TComp> comps;
 };
 
+// product sectors of (site) x (right block), (N, 2S) ascending: components
+// site multiplet outer, right sector inner
+std::vector<TSec> right_product(const std::vector<dmrg_sector_t> &rsec) {
+  std::map<std::pair<int, int>, TSec> m;
+  for (int s = 0; s < 3; s++)
+    for (int a = 0; a < (int)rsec.size(); a++)
+      for (int S = std::abs(rsec[a].two_s - TSITE_S[s]); S <= rsec[a].two_s + TSITE_S[s]; S += 2) {
+        TSec &r = m[{rsec[a].n + TSITE_N[s], S}];
+        r.n = rsec[a].n + TSITE_N[s];
+        r.two_s = S;
+        r.comps.push_back({a, s, r.rows, rsec[a].dim});
+        r.rows += rsec[a].dim;
+      }
+  std::vector<TSec> out;
+  for (auto &kv : m) out.push_back(kv.second);
+  return out;
+}
+
 // product sectors of (left block) x (site), (N, 2S) ascending; components
 // in the order left sector, then site multiplet
 std::vector<TSec> left_product(const std::vector<dmrg_sector_t> &lsec) {
@@ -57,10 +77,14 @@ int tile_shape(int m, int n) { return m <= 16 ? 1 : n <= 16 ? 4 : 2; }
 
 }  // namespace
 
-extern "C" int dmrg_truncate(const dmrg_problem_t *prob, const double *psi, int32_t max_kept, double cutoff,
+extern "C" int dmrg_truncate(const dmrg_problem_t *prob, int32_t flags, const double *psi, int32_t max_kept, double cutoff,
                              dmrg_rkeep_t *keep, int32_t keep_cap, int32_t *n_keep, double *u, int64_t u_cap,
                              int64_t *u_len, double *weights, void *stream) {
-  if (!prob || !psi || !n_keep || !u_len || max_kept < 0) { set_error("null argument or negative max_kept"); return DMRG_EINVAL; }
+  if (!prob || !psi || !n_keep || !u_len || max_kept < 0 || (flags & ~2)) {
+    set_error("null argument, negative max_kept or unknown flag");
+    return DMRG_EINVAL;
+  }
+  const bool right = flags & 2;   // DMRG_RENORM_RIGHT: (right site) x (right block)
   Error err{0, ""};
   BlockModel L, R;
   if (build_block(L, 0, *prob, err) || build_block(R, 1, *prob, err)) { set_error(err.msg); return err.code; }
@@ -68,18 +92,20 @@ extern "C" int dmrg_truncate(const dmrg_problem_t *prob, const double *psi, int3
   int64_t size = 0;
   psi_blocks(L, R, prob->n_elec, prob->two_s, blocks, size);
   if (blocks.empty()) { set_error("no wavefunction block has the target N and S"); return DMRG_ESYM; }
-  std::vector<TSec> prod = left_product(L.sec);
+  std::vector<TSec> prod = right ? right_product(R.sec) : left_product(L.sec);
   std::map<std::pair<int, int>, int> sidx;
   for (int i = 0; i < (int)prod.size(); i++) sidx[{prod[i].n, prod[i].two_s}] = i;
   // per sector: component -> (right part -> block)
   std::vector<std::map<int, std::map<std::tuple<int, int, int>, int>>> parts(prod.size());
   for (int bi = 0; bi < (int)blocks.size(); bi++) {
     const PsiBlock &b = blocks[bi];
-    const int si = sidx.at({L.sec[b.iL].n + TSITE_N[b.l], b.SLl});
+    const int si = right ? sidx.at({R.sec[b.iR].n + TSITE_N[b.r], b.SrR}) : sidx.at({L.sec[b.iL].n + TSITE_N[b.l], b.SLl});
     int ci = -1;
     for (int c = 0; c < (int)prod[si].comps.size(); c++)
-      if (prod[si].comps[c].lsec == b.iL && prod[si].comps[c].site == b.l) ci = c;
-    parts[si][ci][std::make_tuple(b.r, b.iR, b.SrR)] = bi;
+      if (right ? (prod[si].comps[c].lsec == b.iR && prod[si].comps[c].site == b.r)
+                : (prod[si].comps[c].lsec == b.iL && prod[si].comps[c].site == b.l))
+        ci = c;
+    parts[si][ci][right ? std::make_tuple(b.iL, b.l, b.SLl) : std::make_tuple(b.r, b.iR, b.SrR)] = bi;
   }
   // rho blocks as tiles: rho(a, a') += X_{a,c} X_{a',c}^T over common right parts c
   std::vector<int64_t> roff(prod.size() + 1, 0);
@@ -99,9 +125,16 @@ extern "C" int dmrg_truncate(const dmrg_problem_t *prob, const double *psi, int3
           if (it == kb.second.end()) continue;
           const PsiBlock &A = blocks[pc.second], &Bb = blocks[it->second];
           Seg S{};
-          S.a_base = BASE_PSI; S.a_off = A.off; S.a_i = 1; S.a_k = A.dL; S.a_p = 0;
-          S.b_base = BASE_PSI; S.b_off = Bb.off; S.b_k = Bb.dL; S.b_n = 1; S.b_pk = 0; S.b_pn = 0;
-          S.K = A.dR; S.a_kb = S.K; S.b_kb = S.K; S.b_nb = Bb.dL;
+          S.a_base = BASE_PSI; S.a_off = A.off; S.a_p = 0;
+          S.b_base = BASE_PSI; S.b_off = Bb.off; S.b_pk = 0; S.b_pn = 0;
+          if (!right) {   // X_a X_a'^T: K over the right part's columns
+            S.a_i = 1; S.a_k = A.dL; S.b_k = Bb.dL; S.b_n = 1;
+            S.K = A.dR; S.b_nb = Bb.dL;
+          } else {        // X_b^T X_b': K over the left part's rows
+            S.a_i = A.dL; S.a_k = 1; S.b_k = 1; S.b_n = Bb.dL;
+            S.K = A.dL; S.b_nb = Bb.dR;
+          }
+          S.a_kb = S.K; S.b_kb = S.K;
           S.s = 1.0;
           segs.push_back(S);
           ksum += S.K;
@@ -126,8 +159,8 @@ extern "C" int dmrg_truncate(const dmrg_problem_t *prob, const double *psi, int3
   for (const Tile &T : tiles)
     for (int i = 0; i < T.nseg; i++) {
       const Seg &S = segs[T.seg0 + i];
-      if (S.a_off + (int64_t)(T.m - 1) + (int64_t)(S.K - 1) * S.a_k >= size ||
-          S.b_off + (int64_t)(S.K - 1) * S.b_k + (T.n - 1) >= size) {
+      if (S.a_off + (int64_t)(T.m - 1) * S.a_i + (int64_t)(S.K - 1) * S.a_k >= size ||
+          S.b_off + (int64_t)(S.K - 1) * S.b_k + (int64_t)(T.n - 1) * S.b_n >= size) {
         set_error("internal: a density-matrix product reaches beyond psi");
         return DMRG_ERANGE;
       }

@@ -298,7 +298,7 @@ class Renorm:
             pass
 
 
-def truncate(prob, psi, max_kept, cutoff=0.0, stream=None):
+def truncate(prob, psi, max_kept, cutoff=0.0, stream=None, right=False):
     """Kept multiplets of (left block x left site) from the reduced density
     matrix of psi (a device tensor of the problem's reduced coefficients):
     (keep [(n, 2S, kept, u_off)], u device tensor, (kept weight, trace)) --
@@ -310,20 +310,21 @@ def truncate(prob, psi, max_kept, cutoff=0.0, stream=None):
     args = B.ProblemArgs(prob, 0, 0)
     nk, ul = ctypes.c_int32(), ctypes.c_int64()
     w = (ctypes.c_double * 2)()
-    B.check(lib.dmrg_truncate(ctypes.byref(args.s), ctypes.c_void_p(psi.data_ptr()), max_kept, cutoff, None, 0,
+    fl = B.DMRG_RENORM_RIGHT if right else 0
+    B.check(lib.dmrg_truncate(ctypes.byref(args.s), fl, ctypes.c_void_p(psi.data_ptr()), max_kept, cutoff, None, 0,
                               ctypes.byref(nk), None, 0, ctypes.byref(ul), w, ctypes.c_void_p(s.cuda_stream)), lib)
     karr = (B.RKeep * max(1, nk.value))()
     u = torch.empty(max(1, ul.value), dtype=torch.float64, device=psi.device)
-    B.check(lib.dmrg_truncate(ctypes.byref(args.s), ctypes.c_void_p(psi.data_ptr()), max_kept, cutoff,
+    B.check(lib.dmrg_truncate(ctypes.byref(args.s), fl, ctypes.c_void_p(psi.data_ptr()), max_kept, cutoff,
                               ctypes.addressof(karr), nk.value, ctypes.byref(nk), ctypes.c_void_p(u.data_ptr()),
                               u.numel(), ctypes.byref(ul), w, ctypes.c_void_p(s.cuda_stream)), lib)
     keep = [(k.n, k.two_s, k.kept, k.u_off) for k in karr[:nk.value]]
     return keep, u, (w[0], w[1])
 
 
-def keep_host(prob, keep, u):
+def keep_host(prob, keep, u, right=False):
     """[(n, 2S, U host array)] from truncate's outputs (rows from the product basis)."""
-    secs, _ = B.renorm_product(prob)
+    secs, _ = B.renorm_product(prob, right=right)
     rows = {(n, s2): r for (n, s2, r) in secs}
     uh = u.cpu().numpy()
     out = []

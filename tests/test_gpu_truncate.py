@@ -74,3 +74,30 @@ def test_truncation_then_renormalization(torch):
         a = np.linalg.eigvalsh(got.block(cat.H, row, col)[0])
         b = np.linalg.eigvalsh(want.block(cat.H, row, col)[0])
         assert np.abs(a - b).max() < 1e-9 * max(1.0, np.abs(b).max())
+
+
+def test_right_truncation_matches_oracle_and_chains(torch):
+    """Mirror: (right site) x (right block) against the oracle, then the
+    right renormalization with its U against the oracle chain."""
+    from paper_2309_16724_amd.hpsi import truncate, keep_host, Renorm
+    from oracle.truncate import truncate_right
+    from oracle.renorm import renormalize_right
+    prob = random_problem(12, 12, 0, 44, 96, p=5, spin_ratio=0.3, sigma_frac=0.08)
+    psi = _psi(prob, 11)
+    cut = 1e-12 * float(psi @ psi)
+    _say("truncate right")
+    keep, u, (kw, tr) = truncate(prob, torch.from_numpy(psi).cuda(), 60, cut, right=True)
+    got = keep_host(prob, keep, u, right=True)
+    want, eig = truncate_right(prob, psi, 60, cut)
+    assert [(n, s, U.shape[1]) for n, s, U in got] == [(n, s, U.shape[1]) for n, s, U in want]
+    for (n, s, Ug), (_, _, Uw) in zip(got, want):
+        assert np.abs(Ug @ Ug.T - Uw @ Uw.T).max() < 1e-9, (n, s)
+    r = Renorm(prob, got, fam_mask=1 << cat.H, right=True)
+    r.apply()
+    blk = r.block()
+    r.free()
+    ref = renormalize_right(prob, want, families=(cat.H,))
+    for (f, row, col, off, npos) in ref.records:
+        a = np.linalg.eigvalsh(blk.block(cat.H, row, col)[0])
+        b = np.linalg.eigvalsh(ref.block(cat.H, row, col)[0])
+        assert np.abs(a - b).max() < 1e-9 * max(1.0, np.abs(b).max())

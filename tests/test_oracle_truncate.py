@@ -70,3 +70,21 @@ def test_selection_keeps_the_largest_and_all_reproduces_psi():
         M = mats[(N, S)][0]
         assert np.allclose(U.T @ U, np.eye(U.shape[1]), atol=1e-12)
         assert np.abs(U @ (U.T @ M) - M).max() < 1e-12
+
+
+def test_right_trace_and_singlet_spectrum():
+    """Right-growing mirror: the trace is |psi|^2, and for a singlet the two
+    sides of the cut (L l) | (r R) share their nonzero reduced-density-matrix
+    eigenvalues spin by spin (Schmidt decomposition in each S_Ll = S_rR)."""
+    from oracle.truncate import sector_matrices_right
+    prob = exact_problem(6, 6, 0, 28, p=2)
+    psi = _psi(prob, 8)
+    left = sector_matrices(prob, psi)
+    right = sector_matrices_right(prob, psi)
+    assert abs(sum(float(np.sum(M * M)) for M, _ in right.values()) - float(psi @ psi)) < 1e-12
+    for S2 in sorted({S for (_, S) in left}):
+        wl = np.sort(np.concatenate([np.linalg.eigvalsh(M @ M.T) for (N, S), (M, _) in left.items() if S == S2]))
+        wr = np.sort(np.concatenate([np.linalg.eigvalsh(M @ M.T) for (N, S), (M, _) in right.items() if S == S2]
+                                    or [np.zeros(0)]))
+        wl, wr = wl[wl > 1e-13], wr[wr > 1e-13]
+        assert len(wl) == len(wr) and np.abs(wl - wr).max(initial=0.0) < 1e-12, S2
