@@ -332,3 +332,61 @@ def keep_host(prob, keep, u, right=False):
         r = rows[(n, s2)]
         out.append((n, s2, uh[off:off + r * kept].reshape(kept, r).T.copy()))
     return out
+
+
+def catalogue_left(blk):
+    """The H.psi form of a left block that holds P and Q for every outside
+    pair: its P0, P1, Q0, Q1 records cut to the pairs that touch the two
+    sites (a selection of positions, no arithmetic)."""
+    from .synth.problem import BlockData
+    from .synth import catalogue as cat
+    if not getattr(blk, "all_pairs", False):
+        return blk
+    out = BlockData(blk.role, blk.n_orb, blk.p, blk.sectors)
+    recs, chunks, off = [], [], 0
+    for (f, r, c, o, npos) in blk.records:
+        dr, dc = blk.sectors[r][2], blk.sectors[c][2]
+        arr = blk.data[o:o + npos * dr * dc].reshape(npos, dr * dc)
+        if f in (cat.P0, cat.P1, cat.Q0, cat.Q1):
+            full = cat.labels(f, "L", blk.n_orb, blk.p, True)
+            arr = arr[[full.index(lab) for lab in cat.labels(f, "L", blk.n_orb, blk.p)]]
+        if arr.shape[0] == 0:
+            continue
+        recs.append((f, r, c, off, arr.shape[0]))
+        chunks.append(arr.reshape(-1))
+        off += arr.size
+    out.records = recs
+    out.data = np.concatenate(chunks) if chunks else np.zeros(0)
+    return out
+
+
+def sweep_left_to_right(left, rights, h, eri, n_elec, two_s, D, tol=1e-9, seed=100, device="cuda:0"):
+    """One left-to-right two-site sweep through the library's entry points:
+    at every bond p from left.p to the last, the two-site problem of the
+    left block (P and Q over every outside pair) and rights[p] is solved by
+    Davidson (dmrg_davidson), its wavefunction cut to at most D multiplets of
+    (left block x site) (dmrg_truncate) and the left block renormalized with
+    that basis (dmrg_renorm_*, all-pairs form) into the left block of the
+    next bond.  Returns [(bond, energy, kept multiplets, kept weight)]."""
+    torch = _torch()
+    from .synth.problem import Problem, random_vector
+    n_orb = h.shape[0]
+    out = []
+    for p in range(left.p, n_orb - 1):
+        prob = Problem(n_orb, n_elec, two_s, p, h, eri, catalogue_left(left), rights[p])
+        plan = Plan(prob, device=device)
+        x = random_vector(plan.size, seed + p)
+        x0 = torch.from_numpy(x / np.linalg.norm(x)).to(device)
+        e, psi, st = plan.davidson(x0, tol=tol)
+        plan.free()
+        if p == n_orb - 2:
+            out.append((p, e, None, None))
+            break
+        keep, u, (kw, tr) = truncate(prob, psi, D, 1e-14)
+        full = Problem(n_orb, n_elec, two_s, p, h, eri, left, rights[p])
+        r = Renorm(full, keep_host(full, keep, u), device=device)
+        r.apply()
+        left = r.block()
+        r.free()
+        out.append((p, e, sum(k[2] for k in keep), kw / tr))
+    return out

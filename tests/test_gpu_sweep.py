@@ -1,0 +1,62 @@
+"""A left-to-right two-site sweep through the library (Davidson, truncation,
+renormalization at every bond) on an exact small system, against full CI."""
+import numpy as np
+import pytest
+
+from paper_2309_16724_amd.synth.problem import exact_problem, build_exact_block
+from oracle.fock import fci
+
+pytestmark = pytest.mark.gpu
+N_ORB, N_ELEC = 6, 6
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def system():
+    prob = exact_problem(N_ORB, N_ELEC, 0, 31, p=1)
+    e_fci = fci(prob.h, prob.eri, N_ELEC, 0)[0]
+    left = build_exact_block("L", N_ORB, 1, prob.h, prob.eri, all_pairs=True)
+    rights = {p: build_exact_block("R", N_ORB, p, prob.h, prob.eri) for p in range(1, N_ORB - 1)}
+    return prob, e_fci, left, rights
+
+
+def _sweep(system, D):
+    from paper_2309_16724_amd.hpsi import sweep_left_to_right
+    prob, e_fci, left, rights = system
+    print("sweep L=%d D=%d" % (N_ORB, D), flush=True)
+    res = sweep_left_to_right(left, rights, prob.h, prob.eri, N_ELEC, 0, D)
+    for bond, e, kept, w in res:
+        print(bond, e - e_fci, kept, w, flush=True)
+    assert [b for b, *_ in res] == list(range(1, N_ORB - 1))
+    return res
+
+
+def test_untruncated_sweep_is_full_ci(torch, system):
+    """D above every sector's size: every bond's energy is the FCI energy."""
+    e_fci = system[1]
+    for bond, e, kept, w in _sweep(system, 4096):
+        assert abs(e - e_fci) < 1e-8, (bond, e, e_fci)
+        assert w is None or abs(w - 1.0) < 1e-12
+
+
+def test_truncated_sweep_is_variational_and_nested(torch, system):
+    """Truncated: exact until the first cut, above FCI after it, and a larger
+    D (whose kept states contain the smaller D's, the same density matrices'
+    leading eigenvectors) is never worse."""
+    e_fci = system[1]
+    small, large = _sweep(system, 12), _sweep(system, 20)
+    for res in (small, large):
+        cut = next(i for i, (_, _, kept, w) in enumerate(res) if w is not None and w < 1.0 - 1e-12)
+        for i, (bond, e, kept, w) in enumerate(res):
+            if i <= cut:
+                assert abs(e - e_fci) < 1e-8, (bond, e)
+            assert e > e_fci - 1e-9, (bond, e, e_fci)
+    assert small[-1][1] - e_fci > 1e-6
+    assert large[-1][1] <= small[-1][1] + 1e-10

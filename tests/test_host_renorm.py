@@ -182,3 +182,15 @@ def test_right_renorm_error_codes(lib):
     ae = B.ProblemArgs(pe, np.ascontiguousarray(pe.left.data).ctypes.data,
                        np.ascontiguousarray(pe.right.data).ctypes.data)
     assert call(B.DMRG_RENORM_RIGHT, a=ae) == -1
+
+
+def test_catalogue_selection_of_an_all_pairs_block():
+    """The H.psi form cut from an all-pairs left block is the catalogue block."""
+    from paper_2309_16724_amd.hpsi import catalogue_left
+    from paper_2309_16724_amd.synth.problem import build_exact_block
+    prob = exact_problem(6, 6, 0, 31, p=1)
+    for p in (1, 2, 3):
+        a = catalogue_left(build_exact_block("L", 6, p, prob.h, prob.eri, all_pairs=True))
+        b = build_exact_block("L", 6, p, prob.h, prob.eri)
+        assert [r[:3] + (r[4],) for r in a.records] == [r[:3] + (r[4],) for r in b.records]
+        assert np.array_equal(a.data, b.data)
