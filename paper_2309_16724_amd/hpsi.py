@@ -390,3 +390,33 @@ def sweep_left_to_right(left, rights, h, eri, n_elec, two_s, D, tol=1e-9, seed=1
         r.free()
         out.append((p, e, sum(k[2] for k in keep), kw / tr))
     return out
+
+
+def sweep_right_to_left(lefts, right, h, eri, n_elec, two_s, D, tol=1e-9, seed=200, device="cuda:0"):
+    """One right-to-left two-site sweep, the mirror of sweep_left_to_right:
+    at every bond p from right.p down to 0, the problem of lefts[p] (the
+    H.psi form) and the right block is solved by Davidson, cut to at most D
+    multiplets of (right site x right block) (dmrg_truncate with the right
+    flag) and the right block renormalized with that basis into the right
+    block of bond p - 1.  Returns [(bond, energy, kept, kept weight)]."""
+    torch = _torch()
+    from .synth.problem import Problem, random_vector
+    n_orb = h.shape[0]
+    out = []
+    for p in range(right.p, -1, -1):
+        prob = Problem(n_orb, n_elec, two_s, p, h, eri, catalogue_left(lefts[p]), right)
+        plan = Plan(prob, device=device)
+        x = random_vector(plan.size, seed + p)
+        x0 = torch.from_numpy(x / np.linalg.norm(x)).to(device)
+        e, psi, st = plan.davidson(x0, tol=tol)
+        plan.free()
+        if p == 0:
+            out.append((p, e, None, None))
+            break
+        keep, u, (kw, tr) = truncate(prob, psi, D, 1e-14, right=True)
+        r = Renorm(prob, keep_host(prob, keep, u, right=True), device=device, right=True)
+        r.apply()
+        right = r.block()
+        r.free()
+        out.append((p, e, sum(k[2] for k in keep), kw / tr))
+    return out

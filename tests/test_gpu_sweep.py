@@ -60,3 +60,23 @@ def test_truncated_sweep_is_variational_and_nested(torch, system):
             assert e > e_fci - 1e-9, (bond, e, e_fci)
     assert small[-1][1] - e_fci > 1e-6
     assert large[-1][1] <= small[-1][1] + 1e-10
+
+
+def test_right_to_left_sweep(torch, system):
+    """The mirror direction: exact left blocks, the right block grown from
+    the last bond by right truncations and renormalizations; untruncated it
+    is full CI at every bond, truncated it is variational."""
+    from paper_2309_16724_amd.hpsi import sweep_right_to_left
+    prob, e_fci = system[0], system[1]
+    lefts = {p: build_exact_block("L", N_ORB, p, prob.h, prob.eri) for p in range(0, N_ORB - 1)}
+    right = build_exact_block("R", N_ORB, N_ORB - 3, prob.h, prob.eri)
+    for D in (4096, 12):
+        print("sweep right to left D=%d" % D, flush=True)
+        res = sweep_right_to_left(lefts, right, prob.h, prob.eri, N_ELEC, 0, D)
+        assert [b for b, *_ in res] == list(range(N_ORB - 3, -1, -1))
+        for bond, e, kept, w in res:
+            print(bond, e - e_fci, kept, w, flush=True)
+            if D == 4096:
+                assert abs(e - e_fci) < 1e-8, (bond, e, e_fci)
+            else:
+                assert e > e_fci - 1e-9, (bond, e, e_fci)
