@@ -522,6 +522,12 @@ int64_t dmrg_debug_plan_tiles(const dmrg_problem_t *prob, const dmrg_plan_opts_t
 int dmrg_debug_renorm_host(const dmrg_problem_t *prob, const dmrg_rkeep_t *keep, int32_t n_keep, int32_t fam_mask,
                            int32_t flags, const double *u, int64_t u_len, double *out, int64_t out_len, dmrg_oprec_t *rec,
                            int64_t rec_cap, dmrg_renorm_stats_t *st);
+/* Test-only: the density matrices of dmrg_truncate from a HOST psi, formed
+ * on the CPU with the kernels' addressing: every product sector's rho in
+ * product order, column-major rows x rows, concatenated (rho NULL: only the
+ * length in *len). */
+int dmrg_debug_truncate_rho_host(const dmrg_problem_t *prob, int32_t flags, const double *psi, double *rho,
+                                 int64_t cap, int64_t *len);
 /* Test-only: the host eigensolver dmrg_davidson applies to its projected
  * matrix (cyclic Jacobi).  A: m x m symmetric, row-major, HOST, 1 <= m <= 64;
  * w: m eigenvalues ascending; Z: m x m row-major, eigenvector j in column j.

@@ -178,6 +178,8 @@ def load(path=None):
         L.dmrg_renorm_apply.argtypes = [c_vp, c_vp, c_vp, c_vp]
         L.dmrg_renorm_stats.argtypes = [c_vp, ctypes.POINTER(RenormStats)]
         L.dmrg_renorm_set_profiling.argtypes = [c_vp, c_i32]
+        L.dmrg_debug_truncate_rho_host.argtypes = [ctypes.POINTER(ProblemT), c_i32, c_vp, c_vp, c_i64,
+                                                   ctypes.POINTER(c_i64)]
         L.dmrg_truncate.argtypes = [ctypes.POINTER(ProblemT), c_i32, c_vp, c_i32, c_dbl, c_vp, c_i32, ctypes.POINTER(c_i32),
                                     c_vp, c_i64, ctypes.POINTER(c_i64), c_vp, c_vp]
         L.dmrg_renorm_get_profile.argtypes = [c_vp, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_dbl),
@@ -356,3 +358,22 @@ def debug_renorm_host(prob, keep, fam_mask=0, lib=None, execute=True, right=Fals
                                    u.ctypes.data, ulen, out.ctypes.data, out.size, ctypes.addressof(recs),
                                    st.n_records, ctypes.byref(st)), L)
     return records_block(prob, keep, recs[:st.n_records], out[:st.out_elems], right), st.as_dict()
+
+
+def debug_truncate_rho_host(prob, psi, right=False, lib=None):
+    """Test-only: dmrg_debug_truncate_rho_host -> {(n, 2S): rho} in product order."""
+    L = lib or load()
+    args = ProblemArgs(prob, 0, 0)
+    fl = DMRG_RENORM_RIGHT if right else 0
+    n = c_i64()
+    check(L.dmrg_debug_truncate_rho_host(ctypes.byref(args.s), fl, None, None, 0, ctypes.byref(n)), L)
+    x = np.ascontiguousarray(psi, dtype=np.float64)
+    rho = np.zeros(max(1, n.value))
+    check(L.dmrg_debug_truncate_rho_host(ctypes.byref(args.s), fl, x.ctypes.data, rho.ctypes.data, rho.size,
+                                         ctypes.byref(n)), L)
+    secs, _ = renorm_product(prob, L, right=right)
+    out, off = {}, 0
+    for (sn, s2, rows) in secs:
+        out[(sn, s2)] = rho[off:off + rows * rows].reshape(rows, rows).T.copy()
+        off += rows * rows
+    return out

@@ -75,16 +75,23 @@ std::vector<TSec> left_product(const std::vector<dmrg_sector_t> &lsec) {
 
 int tile_shape(int m, int n) { return m <= 16 ? 1 : n <= 16 ? 4 : 2; }
 
-}  // namespace
+// The density-matrix products of one truncation: rho of every product
+// sector (offsets roff, column-major rows x rows) as tiles over psi.
+struct RhoLists {
+  std::vector<TSec> prod;
+  std::vector<int64_t> roff;
+  std::vector<Tile> tiles;
+  std::vector<Seg> segs;
+  std::vector<double> cost;
+};
 
-extern "C" int dmrg_truncate(const dmrg_problem_t *prob, int32_t flags, const double *psi, int32_t max_kept, double cutoff,
-                             dmrg_rkeep_t *keep, int32_t keep_cap, int32_t *n_keep, double *u, int64_t u_cap,
-                             int64_t *u_len, double *weights, void *stream) {
-  if (!prob || !psi || !n_keep || !u_len || max_kept < 0 || (flags & ~2)) {
-    set_error("null argument, negative max_kept or unknown flag");
-    return DMRG_EINVAL;
-  }
+int build_rho(const dmrg_problem_t *prob, int32_t flags, RhoLists &RL) {
   const bool right = flags & 2;   // DMRG_RENORM_RIGHT: (right site) x (right block)
+  std::vector<TSec> &prod = RL.prod;
+  std::vector<int64_t> &roff = RL.roff;
+  std::vector<Tile> &tiles = RL.tiles;
+  std::vector<Seg> &segs = RL.segs;
+  std::vector<double> &cost = RL.cost;
   Error err{0, ""};
   BlockModel L, R;
   if (build_block(L, 0, *prob, err) || build_block(R, 1, *prob, err)) { set_error(err.msg); return err.code; }
@@ -92,7 +99,7 @@ extern "C" int dmrg_truncate(const dmrg_problem_t *prob, int32_t flags, const do
   int64_t size = 0;
   psi_blocks(L, R, prob->n_elec, prob->two_s, blocks, size);
   if (blocks.empty()) { set_error("no wavefunction block has the target N and S"); return DMRG_ESYM; }
-  std::vector<TSec> prod = right ? right_product(R.sec) : left_product(L.sec);
+  prod = right ? right_product(R.sec) : left_product(L.sec);
   std::map<std::pair<int, int>, int> sidx;
   for (int i = 0; i < (int)prod.size(); i++) sidx[{prod[i].n, prod[i].two_s}] = i;
   // per sector: component -> (right part -> block)
@@ -108,11 +115,8 @@ extern "C" int dmrg_truncate(const dmrg_problem_t *prob, int32_t flags, const do
     parts[si][ci][right ? std::make_tuple(b.iL, b.l, b.SLl) : std::make_tuple(b.r, b.iR, b.SrR)] = bi;
   }
   // rho blocks as tiles: rho(a, a') += X_{a,c} X_{a',c}^T over common right parts c
-  std::vector<int64_t> roff(prod.size() + 1, 0);
+  roff.assign(prod.size() + 1, 0);
   for (size_t i = 0; i < prod.size(); i++) roff[i + 1] = roff[i] + (int64_t)prod[i].rows * prod[i].rows;
-  std::vector<Tile> tiles;
-  std::vector<Seg> segs;
-  std::vector<double> cost;
   for (size_t si = 0; si < prod.size(); si++) {
     const TSec &P = prod[si];
     for (auto &ka : parts[si])
@@ -165,6 +169,25 @@ extern "C" int dmrg_truncate(const dmrg_problem_t *prob, int32_t flags, const do
         return DMRG_ERANGE;
       }
     }
+  return DMRG_OK;
+}
+
+}  // namespace
+
+extern "C" int dmrg_truncate(const dmrg_problem_t *prob, int32_t flags, const double *psi, int32_t max_kept, double cutoff,
+                             dmrg_rkeep_t *keep, int32_t keep_cap, int32_t *n_keep, double *u, int64_t u_cap,
+                             int64_t *u_len, double *weights, void *stream) {
+  if (!prob || !psi || !n_keep || !u_len || max_kept < 0 || (flags & ~2)) {
+    set_error("null argument, negative max_kept or unknown flag");
+    return DMRG_EINVAL;
+  }
+  RhoLists RL;
+  if (int rc = build_rho(prob, flags, RL)) return rc;
+  std::vector<TSec> &prod = RL.prod;
+  std::vector<int64_t> &roff = RL.roff;
+  std::vector<Tile> &tiles = RL.tiles;
+  std::vector<Seg> &segs = RL.segs;
+  std::vector<double> &cost = RL.cost;
   std::vector<int> ord(tiles.size());
   for (size_t i = 0; i < ord.size(); i++) ord[i] = (int)i;
   std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cost[a] > cost[b]; });
@@ -277,5 +300,35 @@ extern "C" int dmrg_truncate(const dmrg_problem_t *prob, int32_t flags, const do
   }
   if (hipStreamSynchronize(hs) != hipSuccess) return fail(DMRG_EHIP, "truncation failed");
   cleanup();
+  return DMRG_OK;
+}
+
+// Test-only: the density matrices of dmrg_truncate computed on the host with
+// the kernels' addressing from a HOST psi: rho of every product sector in
+// product order, column-major rows x rows, concatenated (rho NULL: only the
+// length in *len).
+extern "C" int dmrg_debug_truncate_rho_host(const dmrg_problem_t *prob, int32_t flags, const double *psi,
+                                            double *rho, int64_t cap, int64_t *len) {
+  if (!prob || !len || (flags & ~2)) { set_error("null argument or unknown flag"); return DMRG_EINVAL; }
+  RhoLists RL;
+  if (int rc = build_rho(prob, flags, RL)) return rc;
+  *len = RL.roff.back();
+  if (!rho) return DMRG_OK;
+  if (!psi || cap < *len) { set_error("missing psi or rho too small"); return DMRG_ERANGE; }
+  std::fill(rho, rho + *len, 0.0);
+  for (const Tile &T : RL.tiles) {
+    const int mt = std::min(tile_rows(T.mb), T.m - T.i0), nt = std::min(tile_cols(T.mb), T.n - T.j0);
+    for (int j = 0; j < nt; j++)
+      for (int i = 0; i < mt; i++) {
+        double acc = 0.0;
+        for (int si = 0; si < T.nseg; si++) {
+          const Seg &S = RL.segs[T.seg0 + si];
+          for (int k = 0; k < S.K; k++)
+            acc += S.s * psi[S.a_off + (int64_t)(T.i0 + i) * S.a_i + (int64_t)k * S.a_k] *
+                   psi[S.b_off + (int64_t)k * S.b_k + (int64_t)(T.j0 + j) * S.b_n];
+        }
+        rho[T.c_off + (T.ci0 + i) + (int64_t)(T.cj0 + j) * T.ldc] = acc;
+      }
+  }
   return DMRG_OK;
 }

@@ -194,3 +194,20 @@ def test_catalogue_selection_of_an_all_pairs_block():
         b = build_exact_block("L", 6, p, prob.h, prob.eri)
         assert [r[:3] + (r[4],) for r in a.records] == [r[:3] + (r[4],) for r in b.records]
         assert np.array_equal(a.data, b.data)
+
+
+@pytest.mark.parametrize("right", [False, True])
+def test_truncation_density_matrices_on_host(lib, right):
+    """dmrg_truncate's density-matrix lists executed on the host against the
+    oracle's M M^T, for both cuts."""
+    from oracle.truncate import sector_matrices, sector_matrices_right
+    from oracle.layout import psi_blocks
+    from paper_2309_16724_amd.synth.problem import random_vector
+    prob = random_problem(10, 10, 0, 12, 40, p=4)
+    _, size = psi_blocks(prob.left.sectors, prob.right.sectors, prob.n_elec, prob.two_s)
+    psi = random_vector(size, 13)
+    got = B.debug_truncate_rho_host(prob, psi, right=right, lib=lib)
+    want = (sector_matrices_right if right else sector_matrices)(prob, psi)
+    assert set(got) == set(want)
+    for key, (M, _) in want.items():
+        assert np.abs(got[key] - M @ M.T).max() < 1e-13 * max(1.0, float(np.abs(M).max()) ** 2)
