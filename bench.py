@@ -397,7 +397,27 @@ def davidson_runs(torch, args, plan_flags):
         both = dst["converged"] == 1 and sst["converged"] == 1
         out["split"] = {"s_per_step": t_sp, "iterations": sst["iters"], "converged": sst["converged"],
                         "residual": sst["residual"], "energy_minus_fp64": (e_sp - e_dav) if both else None}
+        # mixed precision: split H.psi down to a residual the split error
+        # (about 1e-8 in norm here) does not disturb, then an FP64 plan from
+        # that vector to the tolerance; timed end to end, the FP64 plan's
+        # construction included (the two plans do not fit in HBM together)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        e_a, psi_a, st_a = splan.davidson(x0, tol=args.refine_tol, check=False, verbose=1, **fk)
         splan.free()
+        rplan = Plan(prob, flags=plan_flags)
+        e_b, psi_b, st_b = rplan.davidson(psi_a, tol=1e-8, check=False, verbose=1, **fk)
+        torch.cuda.synchronize()
+        t_mix = time.time() - t0
+        rplan.free()
+        ok = dst["converged"] == 1 and st_b["converged"] == 1
+        print("# davidson split to %.0e then fp64: %d + %d iterations, %.1f s"
+              % (args.refine_tol, st_a["iters"], st_b["iters"], t_mix), file=sys.stderr, flush=True)
+        out["split_then_fp64"] = {"s_per_step": t_mix, "switch_residual": args.refine_tol,
+                                  "split_iterations": st_a["iters"], "fp64_iterations": st_b["iters"],
+                                  "converged": st_b["converged"], "residual": st_b["residual"],
+                                  "energy_minus_fp64": (e_b - e_dav) if ok else None,
+                                  "speedup_vs_fp64": (t_dav / t_mix) if ok else None}
     del prob
     if not args.no_mlp:
         net, info = train_preconditioner(torch, [(24, 24, 0, 10000 + k, 512) for k in range(4)], floor=args.dav_floor)
@@ -542,6 +562,8 @@ def main():
                          "(L64_D3072 for the learned preconditioner's evaluation configuration)")
     ap.add_argument("--no-split-davidson", action="store_true",
                     help="skip the Davidson solve with split-precision H.psi")
+    ap.add_argument("--refine-tol", type=float, default=1e-6,
+                    help="residual at which the mixed-precision Davidson leaves split H.psi for FP64")
     ap.add_argument("--dav-floor", type=float, default=None,
                     help="relative preconditioner floor of the Davidson solves (library default if omitted)")
     ap.add_argument("--hpsi-only", choices=("fp64", "split"),
