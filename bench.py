@@ -332,6 +332,29 @@ def dominant(prof, split):
     return KERNEL_NAMES[code][0 if split else 1], n, ms, fl
 
 
+# site multiplets (electrons, doubled spin): empty, one electron, doubly occupied
+_SITE = ((0, 0), (1, 1), (2, 0))
+
+
+def psi_layout(lsec, rsec, n_elec, two_s):
+    """Wavefunction blocks in the order include/dmrg.h fixes (nested loops over
+    left sector, l, 2S_Ll, r, right sector, 2S_rR; column-major dL x dR blocks
+    concatenated): ([{iL, l, SLl, r, iR, SrR, off, dL, dR}], length)."""
+    out, off = [], 0
+    for iL, (NL, SL, dL) in enumerate(lsec):
+        for l, (nl, sl) in enumerate(_SITE):
+            for SLl in range(abs(SL - sl), SL + sl + 1, 2):
+                for r, (nr, sr) in enumerate(_SITE):
+                    for iR, (NR, SR, dR) in enumerate(rsec):
+                        if NL + nl + nr + NR != n_elec:
+                            continue
+                        for SrR in range(abs(sr - SR), sr + SR + 1, 2):
+                            if abs(SLl - SrR) <= two_s <= SLl + SrR:
+                                out.append(dict(iL=iL, l=l, SLl=SLl, r=r, iR=iR, SrR=SrR, off=off, dL=dL, dR=dR))
+                                off += dL * dR
+    return out, off
+
+
 def sampled_errors(yv, workload, prob):
     """Largest error of H.psi at the oracle's stored sample of this workload
     (tests/golden/hpsi_samples.json), relative to the largest sampled value."""
@@ -343,8 +366,7 @@ def sampled_errors(yv, workload, prob):
         case = json.load(f).get("cases", {}).get(workload)
     if case is None:
         return None
-    from oracle.layout import psi_blocks
-    blocks, size = psi_blocks(prob.left.sectors, prob.right.sectors, prob.n_elec, prob.two_s)
+    blocks, size = psi_layout(prob.left.sectors, prob.right.sectors, prob.n_elec, prob.two_s)
     if size != case["psi_len"]:
         return None
     err, scale, n = 0.0, 0.0, 0
@@ -530,8 +552,7 @@ def truncation_run(torch, prob, D, reps=3):
     import numpy as np
     from paper_2309_16724_amd.hpsi import truncate
     from paper_2309_16724_amd.binding import renorm_product
-    from oracle.layout import psi_blocks
-    _, size = psi_blocks(prob.left.sectors, prob.right.sectors, prob.n_elec, prob.two_s)
+    _, size = psi_layout(prob.left.sectors, prob.right.sectors, prob.n_elec, prob.two_s)
     x = np.random.default_rng(100).standard_normal(size)
     psi = torch.from_numpy(x / np.linalg.norm(x)).cuda()
     secs, _ = renorm_product(prob)

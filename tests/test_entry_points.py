@@ -40,3 +40,15 @@ def test_davidson_defaults_match_the_oracle():
     assert col["floor"].default == ref["floor"].default
     for f in (omlp.diagonal_step, omlp.training_rows, omlp.mlp_step):
         assert inspect.signature(f).parameters["floor"].default == ref["floor"].default
+
+
+def test_bench_layout_matches_the_documented_order():
+    """bench.py computes wavefunction block offsets itself (its timed legs do
+    not touch the oracle); they follow the order the header fixes."""
+    import bench
+    from oracle.layout import psi_blocks
+    from paper_2309_16724_amd.synth.problem import random_problem
+    for args in ((12, 12, 0, 3, 64), (11, 11, 1, 4, 48)):
+        p = random_problem(*args, p=5)
+        assert bench.psi_layout(p.left.sectors, p.right.sectors, p.n_elec, p.two_s) == \
+            psi_blocks(p.left.sectors, p.right.sectors, p.n_elec, p.two_s)
