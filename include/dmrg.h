@@ -491,6 +491,41 @@ int dmrg_truncate(const dmrg_problem_t *prob, int32_t flags, const double *psi, 
                   dmrg_rkeep_t *keep, int32_t keep_cap, int32_t *n_keep, double *u, int64_t u_cap,
                   int64_t *u_len, double *weights, void *stream);
 
+/* ---- a left-to-right two-site sweep on the device -----------------------
+ * Sec. II (two-site DMRG) and Sec. I (Davidson, then the renormalization):
+ * at every bond p = bond0 .. n_orb - 2 the two-site problem of the current
+ * left block and rights[p - bond0] is planned (dmrg_build_tasks, FP64) and
+ * solved (dmrg_davidson with `dav`, NULL: defaults; start vector drawn from
+ * `seed` and the bond); below the last bond the wavefunction is cut to at
+ * most max_kept multiplets (dmrg_truncate) and the left block renormalized
+ * in that basis (dmrg_renorm_*, DMRG_RENORM_ALL_PAIRS) into the left block
+ * of bond p + 1.  `left` is the left block of bond0 in the all-pairs form;
+ * rights[i] the right block of bond bond0 + i in the H.psi form; block data
+ * are DEVICE arrays (borrowed), tables host arrays.  The blocks built on the
+ * way stay in device memory; the H.psi form of each left block (P and Q of
+ * the pairs at the two sites) is cut from its all-pairs records by device
+ * copies.  steps[i] (host, n_orb - 1 - bond0 entries) receive the bond, the
+ * Ritz value, the Davidson iterations, the kept multiplets and the kept
+ * weight (last bond: kept 0, weight 1).  Device memory is taken with
+ * hipMalloc and freed before returning; errors as the calls it makes. */
+typedef struct {
+  int32_t n_sec, pad;
+  const dmrg_sector_t *sec;
+  int64_t n_rec;
+  const dmrg_oprec_t *rec;
+  const double *data;          /* DEVICE */
+  int64_t data_len;
+} dmrg_block_t;
+typedef struct {
+  int32_t bond, kept;
+  double energy, kept_weight;
+  int32_t iters, pad;
+} dmrg_sweep_step_t;
+int dmrg_sweep_left_to_right(int32_t n_orb, int32_t n_elec, int32_t two_s, const double *h1, const double *eri,
+                             int32_t bond0, const dmrg_block_t *left, const dmrg_block_t *rights,
+                             int32_t max_kept, const dmrg_dav_opts_t *dav, uint64_t seed,
+                             dmrg_sweep_step_t *steps, void *stream);
+
 /* ---- host-logic inspection (no GPU use; for tests of the host tables) ---- */
 /* Wigner 6j {a b c; d e f}, 9j and the Eq. (4) factor, doubled spins.       */
 double dmrg_wigner_6j(int a, int b, int c, int d, int e, int f);

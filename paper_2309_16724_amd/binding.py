@@ -108,6 +108,16 @@ class RenormStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class BlockT(ctypes.Structure):
+    _fields_ = [("n_sec", c_i32), ("pad", c_i32), ("sec", c_vp), ("n_rec", c_i64), ("rec", c_vp), ("data", c_vp),
+                ("data_len", c_i64)]
+
+
+class SweepStep(ctypes.Structure):
+    _fields_ = [("bond", c_i32), ("kept", c_i32), ("energy", c_dbl), ("kept_weight", c_dbl), ("iters", c_i32),
+                ("pad", c_i32)]
+
+
 _lib = None
 
 
@@ -180,6 +190,8 @@ def load(path=None):
         L.dmrg_renorm_set_profiling.argtypes = [c_vp, c_i32]
         L.dmrg_debug_truncate_rho_host.argtypes = [ctypes.POINTER(ProblemT), c_i32, c_vp, c_vp, c_i64,
                                                    ctypes.POINTER(c_i64)]
+        L.dmrg_sweep_left_to_right.argtypes = [c_i32, c_i32, c_i32, c_vp, c_vp, c_i32, ctypes.POINTER(BlockT),
+                                               ctypes.POINTER(BlockT), c_i32, c_vp, ctypes.c_uint64, c_vp, c_vp]
         L.dmrg_truncate.argtypes = [ctypes.POINTER(ProblemT), c_i32, c_vp, c_i32, c_dbl, c_vp, c_i32, ctypes.POINTER(c_i32),
                                     c_vp, c_i64, ctypes.POINTER(c_i64), c_vp, c_vp]
         L.dmrg_renorm_get_profile.argtypes = [c_vp, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_dbl),

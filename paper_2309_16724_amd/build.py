@@ -14,7 +14,7 @@ OUT = os.path.join(HERE, "libdmrg_hpsi.so")
 BUILD = os.path.join(HERE, "_build")
 
 HOST_SRC = ["wigner.cpp", "model.cpp", "api_host.cpp"]
-HIP_HOST_SRC = ["plan.cpp", "davidson.cpp", "mlp.cpp", "renorm.cpp", "truncate.cpp"]
+HIP_HOST_SRC = ["plan.cpp", "davidson.cpp", "mlp.cpp", "renorm.cpp", "truncate.cpp", "sweep.cpp"]
 # rocSOLVER (dsyevd) for the truncation's eigenvectors
 LINK_LIBS = ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocsolver", "-lrocblas"]
 HIP_SRC = ["kernels_f64.hip", "kernels_vec.hip", "kernels_split.hip", "kernels_mlp.hip", "apply_static.hip"]

@@ -420,3 +420,36 @@ def sweep_right_to_left(lefts, right, h, eri, n_elec, two_s, D, tol=1e-9, seed=2
         r.free()
         out.append((p, e, sum(k[2] for k in keep), kw / tr))
     return out
+
+
+def sweep_native(left, rights, h, eri, n_elec, two_s, D, tol=1e-9, seed=100, device="cuda:0", stream=None):
+    """dmrg_sweep_left_to_right: the left-to-right sweep of
+    sweep_left_to_right with every block kept on the device inside the
+    library.  left: all-pairs left block of bond left.p; rights: {bond:
+    right block}.  Returns [(bond, energy, kept, kept weight, iterations)]."""
+    torch = _torch()
+    lib = B.load()
+    n_orb = h.shape[0]
+    keepalive = []
+
+    def block(blk):
+        sec = (B.Sector * max(1, len(blk.sectors)))(*[B.Sector(*x) for x in blk.sectors])
+        rec = (B.OpRec * max(1, len(blk.records)))(*[B.OpRec(f, r, c, n, o) for (f, r, c, o, n) in blk.records])
+        data = torch.from_numpy(np.ascontiguousarray(blk.data if blk.data.size else np.zeros(1))).to(device)
+        keepalive.extend([sec, rec, data])
+        return B.BlockT(len(blk.sectors), 0, ctypes.addressof(sec), len(blk.records), ctypes.addressof(rec),
+                        data.data_ptr(), blk.data.size)
+
+    bonds = list(range(left.p, n_orb - 1))
+    lb = block(left)
+    rb = (B.BlockT * len(bonds))(*[block(rights[p]) for p in bonds])
+    steps = (B.SweepStep * len(bonds))()
+    hh = np.ascontiguousarray(h, dtype=np.float64)
+    ee = np.ascontiguousarray(eri, dtype=np.float64)
+    s = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
+    torch.cuda.synchronize()
+    opts = Plan._dav_opts(tol, 1000, 24, 1e-2)
+    B.check(lib.dmrg_sweep_left_to_right(n_orb, n_elec, two_s, hh.ctypes.data, ee.ctypes.data, left.p,
+                                         ctypes.byref(lb), rb, D, ctypes.byref(opts), seed, steps,
+                                         ctypes.c_void_p(s.cuda_stream)), lib)
+    return [(st.bond, st.energy, st.kept, st.kept_weight, st.iters) for st in steps]

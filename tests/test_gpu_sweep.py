@@ -80,3 +80,23 @@ def test_right_to_left_sweep(torch, system):
                 assert abs(e - e_fci) < 1e-8, (bond, e, e_fci)
             else:
                 assert e > e_fci - 1e-9, (bond, e, e_fci)
+
+
+def test_native_sweep_matches_the_composed_one(torch, system):
+    """dmrg_sweep_left_to_right (blocks kept on the device) gives the energies
+    of the sweep composed from the single entry points: full CI untruncated,
+    the same truncated energies with D = 12."""
+    from paper_2309_16724_amd.hpsi import sweep_native
+    prob, e_fci, left, rights = system
+    for D in (4096, 12):
+        print("native sweep D=%d" % D, flush=True)
+        res = sweep_native(left, rights, prob.h, prob.eri, N_ELEC, 0, D)
+        ref = _sweep(system, D)
+        assert [r[0] for r in res] == [r[0] for r in ref]
+        for (bond, e, kept, w, it), (_, e2, kept2, w2) in zip(res, ref):
+            print(bond, e - e_fci, kept, w, it, flush=True)
+            assert abs(e - e2) < 1e-7, (bond, e, e2)
+            if D == 4096:
+                assert abs(e - e_fci) < 1e-8
+            if kept2 is not None:
+                assert kept == kept2 and abs(w - w2) < 1e-7
