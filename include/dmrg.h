@@ -507,7 +507,14 @@ int dmrg_truncate(const dmrg_problem_t *prob, int32_t flags, const double *psi, 
  * copies.  steps[i] (host, n_orb - 1 - bond0 entries) receive the bond, the
  * Ritz value, the Davidson iterations, the kept multiplets and the kept
  * weight (last bond: kept 0, weight 1).  Device memory is taken with
- * hipMalloc and freed before returning; errors as the calls it makes. */
+ * hipMalloc and freed before returning; errors as the calls it makes.
+ *
+ * dmrg_sweep_right_to_left is the mirror: bonds p = bond0 .. 0 (bond0 <=
+ * n_orb - 3), `right` the right block of bond0, lefts[p] (p = 0 .. bond0)
+ * the left block of bond p in the H.psi form; below bond 0 the
+ * wavefunction is cut to multiplets of (right site x right block)
+ * (DMRG_RENORM_RIGHT) and the right block renormalized into that of bond
+ * p - 1.  steps[i] (bond0 + 1 entries) describe bond bond0 - i. */
 typedef struct {
   int32_t n_sec, pad;
   const dmrg_sector_t *sec;
@@ -523,6 +530,10 @@ typedef struct {
 } dmrg_sweep_step_t;
 int dmrg_sweep_left_to_right(int32_t n_orb, int32_t n_elec, int32_t two_s, const double *h1, const double *eri,
                              int32_t bond0, const dmrg_block_t *left, const dmrg_block_t *rights,
+                             int32_t max_kept, const dmrg_dav_opts_t *dav, uint64_t seed,
+                             dmrg_sweep_step_t *steps, void *stream);
+int dmrg_sweep_right_to_left(int32_t n_orb, int32_t n_elec, int32_t two_s, const double *h1, const double *eri,
+                             int32_t bond0, const dmrg_block_t *lefts, const dmrg_block_t *right,
                              int32_t max_kept, const dmrg_dav_opts_t *dav, uint64_t seed,
                              dmrg_sweep_step_t *steps, void *stream);
 

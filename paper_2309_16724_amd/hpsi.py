@@ -422,11 +422,15 @@ def sweep_right_to_left(lefts, right, h, eri, n_elec, two_s, D, tol=1e-9, seed=2
     return out
 
 
-def sweep_native(left, rights, h, eri, n_elec, two_s, D, tol=1e-9, seed=100, device="cuda:0", stream=None):
-    """dmrg_sweep_left_to_right: the left-to-right sweep of
-    sweep_left_to_right with every block kept on the device inside the
-    library.  left: all-pairs left block of bond left.p; rights: {bond:
-    right block}.  Returns [(bond, energy, kept, kept weight, iterations)]."""
+
+def sweep_native(blocks, grown, h, eri, n_elec, two_s, D, tol=1e-9, seed=100, device="cuda:0", stream=None,
+                 right_to_left=False):
+    """A sweep inside the library, every grown block kept on the device.
+    Left to right (dmrg_sweep_left_to_right): grown is the all-pairs left
+    block of bond grown.p, blocks = {bond: right block}.  Right to left
+    (dmrg_sweep_right_to_left): grown is the right block of bond grown.p,
+    blocks = {bond: left block}.  Returns [(bond, energy, kept, kept
+    weight, iterations)] in sweep order."""
     torch = _torch()
     lib = B.load()
     n_orb = h.shape[0]
@@ -440,16 +444,21 @@ def sweep_native(left, rights, h, eri, n_elec, two_s, D, tol=1e-9, seed=100, dev
         return B.BlockT(len(blk.sectors), 0, ctypes.addressof(sec), len(blk.records), ctypes.addressof(rec),
                         data.data_ptr(), blk.data.size)
 
-    bonds = list(range(left.p, n_orb - 1))
-    lb = block(left)
-    rb = (B.BlockT * len(bonds))(*[block(rights[p]) for p in bonds])
-    steps = (B.SweepStep * len(bonds))()
+    if right_to_left:
+        table = list(range(0, grown.p + 1))
+        fn = lib.dmrg_sweep_right_to_left
+    else:
+        table = list(range(grown.p, n_orb - 1))
+        fn = lib.dmrg_sweep_left_to_right
+    gb = block(grown)
+    tb = (B.BlockT * len(table))(*[block(blocks[p]) for p in table])
+    steps = (B.SweepStep * len(table))()
     hh = np.ascontiguousarray(h, dtype=np.float64)
     ee = np.ascontiguousarray(eri, dtype=np.float64)
     s = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
-    torch.cuda.synchronize()
     opts = Plan._dav_opts(tol, 1000, 24, 1e-2)
-    B.check(lib.dmrg_sweep_left_to_right(n_orb, n_elec, two_s, hh.ctypes.data, ee.ctypes.data, left.p,
-                                         ctypes.byref(lb), rb, D, ctypes.byref(opts), seed, steps,
-                                         ctypes.c_void_p(s.cuda_stream)), lib)
+    torch.cuda.synchronize()
+    first, second = (tb, ctypes.byref(gb)) if right_to_left else (ctypes.byref(gb), tb)
+    B.check(fn(n_orb, n_elec, two_s, hh.ctypes.data, ee.ctypes.data, grown.p, first, second, D,
+               ctypes.byref(opts), seed, steps, ctypes.c_void_p(s.cuda_stream)), lib)
     return [(st.bond, st.energy, st.kept, st.kept_weight, st.iters) for st in steps]

@@ -90,9 +90,30 @@ def test_native_sweep_matches_the_composed_one(torch, system):
     prob, e_fci, left, rights = system
     for D in (4096, 12):
         print("native sweep D=%d" % D, flush=True)
-        res = sweep_native(left, rights, prob.h, prob.eri, N_ELEC, 0, D)
+        res = sweep_native(rights, left, prob.h, prob.eri, N_ELEC, 0, D)
         ref = _sweep(system, D)
         assert [r[0] for r in res] == [r[0] for r in ref]
+        for (bond, e, kept, w, it), (_, e2, kept2, w2) in zip(res, ref):
+            print(bond, e - e_fci, kept, w, it, flush=True)
+            assert abs(e - e2) < 1e-7, (bond, e, e2)
+            if D == 4096:
+                assert abs(e - e_fci) < 1e-8
+            if kept2 is not None:
+                assert kept == kept2 and abs(w - w2) < 1e-7
+
+
+def test_native_right_to_left_sweep(torch, system):
+    """dmrg_sweep_right_to_left against the composed mirror sweep: full CI
+    untruncated, the same energies, kept counts and weights with D = 12."""
+    from paper_2309_16724_amd.hpsi import sweep_native, sweep_right_to_left
+    prob, e_fci = system[0], system[1]
+    lefts = {p: build_exact_block("L", N_ORB, p, prob.h, prob.eri) for p in range(0, N_ORB - 2)}
+    right = build_exact_block("R", N_ORB, N_ORB - 3, prob.h, prob.eri)
+    for D in (4096, 12):
+        print("native sweep right to left D=%d" % D, flush=True)
+        res = sweep_native(lefts, right, prob.h, prob.eri, N_ELEC, 0, D, seed=200, right_to_left=True)
+        ref = sweep_right_to_left(lefts, right, prob.h, prob.eri, N_ELEC, 0, D)
+        assert [r[0] for r in res] == [r[0] for r in ref] == list(range(N_ORB - 3, -1, -1))
         for (bond, e, kept, w, it), (_, e2, kept2, w2) in zip(res, ref):
             print(bond, e - e_fci, kept, w, it, flush=True)
             assert abs(e - e2) < 1e-7, (bond, e, e2)
