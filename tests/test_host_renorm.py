@@ -211,3 +211,29 @@ def test_truncation_density_matrices_on_host(lib, right):
     assert set(got) == set(want)
     for key, (M, _) in want.items():
         assert np.abs(got[key] - M @ M.T).max() < 1e-13 * max(1.0, float(np.abs(M).max()) ** 2)
+
+
+def test_sweep_argument_errors(lib):
+    """The sweeps reject bad bonds, D and block tables before any device
+    work (DMRG_EINVAL = -1)."""
+    n = 6
+    h = np.zeros((n, n))
+    eri = np.zeros((n,) * 4)
+    sec = (B.Sector * 1)(B.Sector(0, 0, 1))
+    blk = B.BlockT(1, 0, ctypes.addressof(sec), 0, None, None, 0)
+    table = (B.BlockT * n)(*[blk] * n)
+    steps = (B.SweepStep * n)()
+    bad_tab = (B.BlockT * n)(*[blk] * n)
+    bad_tab[2] = B.BlockT(-1, 0, None, 0, None, None, 0)
+
+    def l2r(bond0=1, D=4, left=ctypes.byref(blk), rights=table):
+        return lib.dmrg_sweep_left_to_right(n, n, 0, h.ctypes.data, eri.ctypes.data, bond0, left, rights, D, None, 1,
+                                            steps, None)
+
+    def r2l(bond0=3, D=4, lefts=table, right=ctypes.byref(blk)):
+        return lib.dmrg_sweep_right_to_left(n, n, 0, h.ctypes.data, eri.ctypes.data, bond0, lefts, right, D, None, 1,
+                                            steps, None)
+    for rc in (l2r(bond0=0), l2r(bond0=n - 1), l2r(D=0), l2r(left=None), l2r(rights=bad_tab),
+               r2l(bond0=-1), r2l(bond0=n - 2), r2l(D=0), r2l(right=None), r2l(lefts=bad_tab)):
+        assert rc == -1
+    assert b"sweep" in lib.dmrg_last_error() or b"block" in lib.dmrg_last_error()
