@@ -506,15 +506,22 @@ int dmrg_truncate(const dmrg_problem_t *prob, int32_t flags, const double *psi, 
  * the pairs at the two sites) is cut from its all-pairs records by device
  * copies.  steps[i] (host, n_orb - 1 - bond0 entries) receive the bond, the
  * Ritz value, the Davidson iterations, the kept multiplets and the kept
- * weight (last bond: kept 0, weight 1).  Device memory is taken with
- * hipMalloc and freed before returning; errors as the calls it makes.
+ * weight (last bond: kept 0, weight 1).  grown_out (host, as many entries
+ * as steps, or NULL): entry i receives the block grown at step i -- the left
+ * block of bond bond0 + i + 1 in the all-pairs form (the last entry stays
+ * empty) -- with tables from malloc and device data from hipMalloc, owned by
+ * the caller (dmrg_block_release); on an error none is returned.  Other
+ * device memory is taken with hipMalloc and freed before returning; errors
+ * as the calls it makes.
  *
  * dmrg_sweep_right_to_left is the mirror: bonds p = bond0 .. 0 (bond0 <=
  * n_orb - 3), `right` the right block of bond0, lefts[p] (p = 0 .. bond0)
- * the left block of bond p in the H.psi form; below bond 0 the
+ * the left block of bond p in the H.psi form or in the all-pairs form (the
+ * blocks a left-to-right sweep returns); below bond 0 the
  * wavefunction is cut to multiplets of (right site x right block)
  * (DMRG_RENORM_RIGHT) and the right block renormalized into that of bond
- * p - 1.  steps[i] (bond0 + 1 entries) describe bond bond0 - i. */
+ * p - 1.  steps[i] and grown_out[i] (bond0 + 1 entries) describe bond
+ * bond0 - i; grown_out[i] is the right block of bond bond0 - i - 1. */
 typedef struct {
   int32_t n_sec, pad;
   const dmrg_sector_t *sec;
@@ -531,11 +538,13 @@ typedef struct {
 int dmrg_sweep_left_to_right(int32_t n_orb, int32_t n_elec, int32_t two_s, const double *h1, const double *eri,
                              int32_t bond0, const dmrg_block_t *left, const dmrg_block_t *rights,
                              int32_t max_kept, const dmrg_dav_opts_t *dav, uint64_t seed,
-                             dmrg_sweep_step_t *steps, void *stream);
+                             dmrg_sweep_step_t *steps, dmrg_block_t *grown_out, void *stream);
 int dmrg_sweep_right_to_left(int32_t n_orb, int32_t n_elec, int32_t two_s, const double *h1, const double *eri,
                              int32_t bond0, const dmrg_block_t *lefts, const dmrg_block_t *right,
                              int32_t max_kept, const dmrg_dav_opts_t *dav, uint64_t seed,
-                             dmrg_sweep_step_t *steps, void *stream);
+                             dmrg_sweep_step_t *steps, dmrg_block_t *grown_out, void *stream);
+/* Frees a block returned by a sweep (tables and device data) and empties it. */
+void dmrg_block_release(dmrg_block_t *b);
 
 /* ---- host-logic inspection (no GPU use; for tests of the host tables) ---- */
 /* Wigner 6j {a b c; d e f}, 9j and the Eq. (4) factor, doubled spins.       */

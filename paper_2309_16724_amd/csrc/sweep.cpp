@@ -12,11 +12,15 @@
 //    its H.psi form (the pairs that touch the two sites) is cut from the
 //    all-pairs records by device copies of the selected positions;
 //  - right to left: the right block grows; the caller's left blocks are in
-//    the H.psi form.
+//    the H.psi form or in the all-pairs form (cut the same way), so that the
+//    left blocks a left-to-right sweep returns can be passed straight in.
+// With an output table, every grown block is handed to the caller (host
+// tables from malloc, device data from hipMalloc; dmrg_block_release).
 #include <hip/hip_runtime.h>
 #include "common.hpp"
 #include <array>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -75,6 +79,57 @@ bool valid_block(const dmrg_block_t *b) {
   return b && b->n_sec >= 0 && b->n_rec >= 0 && (b->n_sec == 0 || b->sec) && (b->n_rec == 0 || b->rec);
 }
 
+// The H.psi form of a left block at bond p: records and the positions to
+// copy.  P and Q records in the all-pairs form are cut to the pairs that
+// touch the sites; records already in the H.psi form pass (unless
+// require_all); the other records pass whole.
+struct Copy { int64_t dst, src, n; };
+int hpsi_form(const std::vector<dmrg_sector_t> &sec, const dmrg_oprec_t *rec, int64_t n_rec, int64_t len, int p,
+              int n_orb, bool require_all, std::vector<dmrg_oprec_t> &crec, std::vector<Copy> &copies,
+              int64_t &clen) {
+  crec.clear();
+  copies.clear();
+  clen = 0;
+  for (int64_t k = 0; k < n_rec; k++) {
+    const dmrg_oprec_t &r = rec[k];
+    if (r.row_sec < 0 || r.row_sec >= (int)sec.size() || r.col_sec < 0 || r.col_sec >= (int)sec.size()) {
+      set_error("left block record with a bad sector");
+      return DMRG_EINVAL;
+    }
+    const int64_t bs = (int64_t)sec[r.row_sec].dim * sec[r.col_sec].dim;
+    if (r.npos < 0 || r.off < 0 || r.off + (int64_t)r.npos * bs > len) {
+      set_error("left block record outside its data");
+      return DMRG_EINVAL;
+    }
+    dmrg_oprec_t c = r;
+    c.off = clen;
+    if (is_pq(r.fam)) {
+      auto all = pq_labels(r.fam, p, n_orb, true), want = pq_labels(r.fam, p, n_orb, false);
+      if ((int)all.size() == r.npos) {
+        c.npos = (int32_t)want.size();
+        size_t j = 0;
+        for (size_t i = 0; i < all.size() && j < want.size(); i++)
+          if (all[i] == want[j]) {
+            copies.push_back({clen + (int64_t)j * bs, r.off + (int64_t)i * bs, bs});
+            j++;
+          }
+      } else if (!require_all && (int)want.size() == r.npos) {
+        copies.push_back({clen, r.off, (int64_t)r.npos * bs});
+      } else {
+        set_error(require_all ? "left block P/Q records are not in the all-pairs form"
+                              : "left block P/Q records are in neither the all-pairs nor the H.psi form");
+        return DMRG_EINVAL;
+      }
+    } else {
+      copies.push_back({clen, r.off, (int64_t)r.npos * bs});
+    }
+    if (c.npos == 0) continue;
+    clen += (int64_t)c.npos * bs;
+    crec.push_back(c);
+  }
+  return DMRG_OK;
+}
+
 // the per-bond resources of a sweep and its two steps
 struct Sweep {
   hipStream_t hs;
@@ -83,8 +138,10 @@ struct Sweep {
   dmrg_renorm_t *ren = nullptr;
   double *psi = nullptr, *u = nullptr, *cat = nullptr, *out = nullptr;
   OwnedBlock grown;   // the block that the sweep grows
+  dmrg_block_t *outs = nullptr;   // caller's table of grown blocks, or NULL
+  int n_out = 0;                  // entries filled so far
 
-  explicit Sweep(void *s) : hs((hipStream_t)s), stream(s) {}
+  explicit Sweep(void *s, dmrg_block_t *o) : hs((hipStream_t)s), stream(s), outs(o) {}
   void free_bond() {
     (void)hipStreamSynchronize(hs);
     if (plan) dmrg_plan_free(plan);
@@ -100,8 +157,30 @@ struct Sweep {
     std::string msg = dmrg_last_error();
     free_bond();
     grown.release();
+    for (int i = 0; i < n_out; i++) dmrg_block_release(&outs[i]);
     set_error(msg);
     return rc;
+  }
+
+  // the grown block goes to the caller's table (entry i); the sweep keeps
+  // reading it until the next cut but no longer frees it
+  int hand_out(int i) {
+    if (!outs) return DMRG_OK;
+    dmrg_block_t &b = outs[i];
+    auto *sec = (dmrg_sector_t *)std::malloc(sizeof(dmrg_sector_t) * std::max<size_t>(grown.sec.size(), 1));
+    auto *rec = (dmrg_oprec_t *)std::malloc(sizeof(dmrg_oprec_t) * std::max<size_t>(grown.rec.size(), 1));
+    if (!sec || !rec) {
+      std::free(sec);
+      std::free(rec);
+      set_error("out of host memory");
+      return DMRG_ENOMEM;
+    }
+    std::copy(grown.sec.begin(), grown.sec.end(), sec);
+    std::copy(grown.rec.begin(), grown.rec.end(), rec);
+    b = dmrg_block_t{(int32_t)grown.sec.size(), 0, sec, (int64_t)grown.rec.size(), rec, grown.data, grown.len};
+    grown.owned = false;
+    n_out = i + 1;
+    return DMRG_OK;
   }
 
   // Davidson on the problem `pr` from a seeded start vector
@@ -222,7 +301,8 @@ dmrg_block_t view(const OwnedBlock &b) {
 extern "C" int dmrg_sweep_left_to_right(int32_t n_orb, int32_t n_elec, int32_t two_s, const double *h1,
                                         const double *eri, int32_t bond0, const dmrg_block_t *left,
                                         const dmrg_block_t *rights, int32_t max_kept, const dmrg_dav_opts_t *dav,
-                                        uint64_t seed, dmrg_sweep_step_t *steps, void *stream) {
+                                        uint64_t seed, dmrg_sweep_step_t *steps, dmrg_block_t *grown_out,
+                                        void *stream) {
   if (!h1 || !eri || !valid_block(left) || !rights || !steps || bond0 < 1 || bond0 > n_orb - 2 || max_kept < 1) {
     set_error("bad sweep arguments (1 <= bond0 <= n_orb - 2, max_kept >= 1)");
     return DMRG_EINVAL;
@@ -232,48 +312,19 @@ extern "C" int dmrg_sweep_left_to_right(int32_t n_orb, int32_t n_elec, int32_t t
       set_error("bad right block table");
       return DMRG_EINVAL;
     }
-  Sweep W(stream);
+  if (grown_out)
+    for (int i = 0; i <= n_orb - 2 - bond0; i++) grown_out[i] = dmrg_block_t{0, 0, nullptr, 0, nullptr, nullptr, 0};
+  Sweep W(stream, grown_out);
   OwnedBlock &L = W.grown;
   L.borrow(*left);
   for (int p = bond0; p <= n_orb - 2; p++) {
     const dmrg_block_t &Rb = rights[p - bond0];
     // H.psi form of the left block: P and Q positions of the pairs at the sites
     std::vector<dmrg_oprec_t> crec;
-    int64_t clen = 0;
-    struct Copy { int64_t dst, src, n; };
     std::vector<Copy> copies;
-    for (const dmrg_oprec_t &r : L.rec) {
-      if (r.row_sec < 0 || r.row_sec >= (int)L.sec.size() || r.col_sec < 0 || r.col_sec >= (int)L.sec.size()) {
-        set_error("left block record with a bad sector");
-        return W.fail(DMRG_EINVAL);
-      }
-      const int64_t bs = (int64_t)L.sec[r.row_sec].dim * L.sec[r.col_sec].dim;
-      if (r.npos < 0 || r.off < 0 || r.off + (int64_t)r.npos * bs > L.len) {
-        set_error("left block record outside its data");
-        return W.fail(DMRG_EINVAL);
-      }
-      dmrg_oprec_t c = r;
-      c.off = clen;
-      if (is_pq(r.fam)) {
-        auto all = pq_labels(r.fam, p, n_orb, true), want = pq_labels(r.fam, p, n_orb, false);
-        if ((int)all.size() != r.npos) {
-          set_error("left block P/Q records are not in the all-pairs form");
-          return W.fail(DMRG_EINVAL);
-        }
-        c.npos = (int32_t)want.size();
-        size_t j = 0;
-        for (size_t i = 0; i < all.size() && j < want.size(); i++)
-          if (all[i] == want[j]) {
-            copies.push_back({clen + (int64_t)j * bs, r.off + (int64_t)i * bs, bs});
-            j++;
-          }
-      } else {
-        copies.push_back({clen, r.off, (int64_t)r.npos * bs});
-      }
-      if (c.npos == 0) continue;
-      clen += (int64_t)c.npos * bs;
-      crec.push_back(c);
-    }
+    int64_t clen = 0;
+    if (int rc = hpsi_form(L.sec, L.rec.data(), (int64_t)L.rec.size(), L.len, p, n_orb, true, crec, copies, clen))
+      return W.fail(rc);
     if (hipMalloc(&W.cat, sizeof(double) * std::max<int64_t>(clen, 1)) != hipSuccess) {
       set_error("hipMalloc failed");
       return W.fail(DMRG_ENOMEM);
@@ -295,6 +346,7 @@ extern "C" int dmrg_sweep_left_to_right(int32_t n_orb, int32_t n_elec, int32_t t
     const dmrg_problem_t pa = make_problem(n_orb, n_elec, two_s, h1, eri, p, L.sec, L.rec.data(),
                                            (int64_t)L.rec.size(), L.data, L.len, Rb);
     if (int rc = W.cut(pr, pa, DMRG_RENORM_ALL_PAIRS, max_kept, S)) return W.fail(rc);
+    if (int rc = W.hand_out(p - bond0)) return W.fail(rc);
     W.free_bond();
   }
   W.free_bond();
@@ -305,7 +357,8 @@ extern "C" int dmrg_sweep_left_to_right(int32_t n_orb, int32_t n_elec, int32_t t
 extern "C" int dmrg_sweep_right_to_left(int32_t n_orb, int32_t n_elec, int32_t two_s, const double *h1,
                                         const double *eri, int32_t bond0, const dmrg_block_t *lefts,
                                         const dmrg_block_t *right, int32_t max_kept, const dmrg_dav_opts_t *dav,
-                                        uint64_t seed, dmrg_sweep_step_t *steps, void *stream) {
+                                        uint64_t seed, dmrg_sweep_step_t *steps, dmrg_block_t *grown_out,
+                                        void *stream) {
   if (!h1 || !eri || !lefts || !valid_block(right) || !steps || bond0 < 0 || bond0 > n_orb - 3 || max_kept < 1) {
     set_error("bad sweep arguments (0 <= bond0 <= n_orb - 3, max_kept >= 1)");
     return DMRG_EINVAL;
@@ -315,23 +368,50 @@ extern "C" int dmrg_sweep_right_to_left(int32_t n_orb, int32_t n_elec, int32_t t
       set_error("bad left block table");
       return DMRG_EINVAL;
     }
-  Sweep W(stream);
+  if (grown_out)
+    for (int i = 0; i <= bond0; i++) grown_out[i] = dmrg_block_t{0, 0, nullptr, 0, nullptr, nullptr, 0};
+  Sweep W(stream, grown_out);
   OwnedBlock &R = W.grown;
   R.borrow(*right);
   for (int p = bond0; p >= 0; p--) {
     const dmrg_block_t &Lb = lefts[p];
     const std::vector<dmrg_sector_t> lsec(Lb.sec, Lb.sec + Lb.n_sec);
+    std::vector<dmrg_oprec_t> crec;
+    std::vector<Copy> copies;
+    int64_t clen = 0;
+    if (int rc = hpsi_form(lsec, Lb.rec, Lb.n_rec, Lb.data_len, p, n_orb, false, crec, copies, clen))
+      return W.fail(rc);
+    if (hipMalloc(&W.cat, sizeof(double) * std::max<int64_t>(clen, 1)) != hipSuccess) {
+      set_error("hipMalloc failed");
+      return W.fail(DMRG_ENOMEM);
+    }
+    for (const Copy &c : copies)
+      if (c.n > 0 &&
+          hipMemcpyAsync(W.cat + c.dst, Lb.data + c.src, sizeof(double) * c.n, hipMemcpyDeviceToDevice, W.hs) !=
+              hipSuccess) {
+        set_error("copying the left block failed");
+        return W.fail(DMRG_EHIP);
+      }
     const dmrg_block_t Rb = view(R);
     const dmrg_problem_t pr =
-        make_problem(n_orb, n_elec, two_s, h1, eri, p, lsec, Lb.rec, Lb.n_rec, Lb.data, Lb.data_len, Rb);
+        make_problem(n_orb, n_elec, two_s, h1, eri, p, lsec, crec.data(), (int64_t)crec.size(), W.cat, clen, Rb);
     dmrg_sweep_step_t &S = steps[bond0 - p];
     S.bond = p;
     if (int rc = W.solve(pr, dav, seed, p, S)) return W.fail(rc);
     if (p == 0) break;
     if (int rc = W.cut(pr, pr, DMRG_RENORM_RIGHT, max_kept, S)) return W.fail(rc);
+    if (int rc = W.hand_out(bond0 - p)) return W.fail(rc);
     W.free_bond();
   }
   W.free_bond();
   R.release();
   return DMRG_OK;
+}
+
+extern "C" void dmrg_block_release(dmrg_block_t *b) {
+  if (!b) return;
+  std::free(const_cast<dmrg_sector_t *>(b->sec));
+  std::free(const_cast<dmrg_oprec_t *>(b->rec));
+  if (b->data) (void)hipFree(const_cast<double *>(b->data));
+  *b = dmrg_block_t{0, 0, nullptr, 0, nullptr, nullptr, 0};
 }

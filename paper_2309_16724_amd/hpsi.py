@@ -424,19 +424,24 @@ def sweep_right_to_left(lefts, right, h, eri, n_elec, two_s, D, tol=1e-9, seed=2
 
 
 def sweep_native(blocks, grown, h, eri, n_elec, two_s, D, tol=1e-9, seed=100, device="cuda:0", stream=None,
-                 right_to_left=False):
+                 right_to_left=False, keep_blocks=False):
     """A sweep inside the library, every grown block kept on the device.
     Left to right (dmrg_sweep_left_to_right): grown is the all-pairs left
     block of bond grown.p, blocks = {bond: right block}.  Right to left
     (dmrg_sweep_right_to_left): grown is the right block of bond grown.p,
-    blocks = {bond: left block}.  Returns [(bond, energy, kept, kept
-    weight, iterations)] in sweep order."""
+    blocks = {bond: left block}; a block is a BlockData or a BlockT that
+    an earlier sweep returned (device data).  Returns [(bond, energy, kept,
+    kept weight, iterations)] in sweep order, and with keep_blocks also the
+    grown blocks as BlockT (entry i: grown at step i; release_blocks frees
+    them)."""
     torch = _torch()
     lib = B.load()
     n_orb = h.shape[0]
     keepalive = []
 
     def block(blk):
+        if isinstance(blk, B.BlockT):
+            return blk
         sec = (B.Sector * max(1, len(blk.sectors)))(*[B.Sector(*x) for x in blk.sectors])
         rec = (B.OpRec * max(1, len(blk.records)))(*[B.OpRec(f, r, c, n, o) for (f, r, c, o, n) in blk.records])
         data = torch.from_numpy(np.ascontiguousarray(blk.data if blk.data.size else np.zeros(1))).to(device)
@@ -453,6 +458,7 @@ def sweep_native(blocks, grown, h, eri, n_elec, two_s, D, tol=1e-9, seed=100, de
     gb = block(grown)
     tb = (B.BlockT * len(table))(*[block(blocks[p]) for p in table])
     steps = (B.SweepStep * len(table))()
+    outs = (B.BlockT * len(table))() if keep_blocks else None
     hh = np.ascontiguousarray(h, dtype=np.float64)
     ee = np.ascontiguousarray(eri, dtype=np.float64)
     s = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
@@ -460,5 +466,13 @@ def sweep_native(blocks, grown, h, eri, n_elec, two_s, D, tol=1e-9, seed=100, de
     torch.cuda.synchronize()
     first, second = (tb, ctypes.byref(gb)) if right_to_left else (ctypes.byref(gb), tb)
     B.check(fn(n_orb, n_elec, two_s, hh.ctypes.data, ee.ctypes.data, grown.p, first, second, D,
-               ctypes.byref(opts), seed, steps, ctypes.c_void_p(s.cuda_stream)), lib)
-    return [(st.bond, st.energy, st.kept, st.kept_weight, st.iters) for st in steps]
+               ctypes.byref(opts), seed, steps, outs, ctypes.c_void_p(s.cuda_stream)), lib)
+    res = [(st.bond, st.energy, st.kept, st.kept_weight, st.iters) for st in steps]
+    return (res, list(outs)) if keep_blocks else res
+
+
+def release_blocks(blocks):
+    """dmrg_block_release on blocks a sweep returned."""
+    lib = B.load()
+    for b in blocks:
+        lib.dmrg_block_release(ctypes.byref(b))

@@ -121,3 +121,34 @@ def test_native_right_to_left_sweep(torch, system):
                 assert abs(e - e_fci) < 1e-8
             if kept2 is not None:
                 assert kept == kept2 and abs(w - w2) < 1e-7
+
+
+def test_chained_sweeps(torch, system):
+    """A left-to-right sweep that returns its grown left blocks (all-pairs,
+    on the device) feeding a right-to-left sweep: untruncated every bond of
+    both is full CI; with D = 12 the second sweep's first bond is the first
+    sweep's last problem (the same energy), and every energy stays above
+    full CI."""
+    from paper_2309_16724_amd.hpsi import sweep_native, release_blocks
+    prob, e_fci, left, rights = system
+    n = N_ORB
+    for D in (4096, 12):
+        print("chained sweeps D=%d" % D, flush=True)
+        r1, grown = sweep_native(rights, left, prob.h, prob.eri, N_ELEC, 0, D, keep_blocks=True)
+        assert [b.n_sec > 0 for b in grown] == [True] * (n - 3) + [False]
+        lefts = {p: build_exact_block("L", n, p, prob.h, prob.eri) for p in range(0, 2)}
+        lefts.update({p: grown[p - 2] for p in range(2, n - 2)})
+        right = build_exact_block("R", n, n - 3, prob.h, prob.eri)
+        r2, grown_r = sweep_native(lefts, right, prob.h, prob.eri, N_ELEC, 0, D, seed=300, right_to_left=True,
+                                   keep_blocks=True)
+        assert [b.n_sec > 0 for b in grown_r] == [True] * (n - 3) + [False]
+        for bond, e, kept, w, it in r1 + r2:
+            print(bond, e - e_fci, kept, w, it, flush=True)
+            assert e > e_fci - 1e-9, (bond, e)
+            if D == 4096:
+                assert abs(e - e_fci) < 1e-8, (bond, e)
+        e_last = dict((b, e) for b, e, *_ in r1)[n - 3]
+        assert r2[0][0] == n - 3 and abs(r2[0][1] - e_last) < 1e-8
+        release_blocks(grown)
+        release_blocks(grown_r)
+        assert all(b.n_sec == 0 and not b.data for b in grown)
