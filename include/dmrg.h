@@ -494,7 +494,8 @@ int dmrg_truncate(const dmrg_problem_t *prob, int32_t flags, const double *psi, 
 /* ---- a left-to-right two-site sweep on the device -----------------------
  * Sec. II (two-site DMRG) and Sec. I (Davidson, then the renormalization):
  * at every bond p = bond0 .. n_orb - 2 the two-site problem of the current
- * left block and rights[p - bond0] is planned (dmrg_build_tasks, FP64) and
+ * left block and rights[p - bond0] is planned (dmrg_build_tasks with
+ * plan_opts; NULL: the FP64 defaults; allocator callbacks apply to the plans) and
  * solved (dmrg_davidson with `dav`, NULL: defaults; start vector drawn from
  * `seed` and the bond); below the last bond the wavefunction is cut to at
  * most max_kept multiplets (dmrg_truncate) and the left block renormalized
@@ -537,12 +538,12 @@ typedef struct {
 } dmrg_sweep_step_t;
 int dmrg_sweep_left_to_right(int32_t n_orb, int32_t n_elec, int32_t two_s, const double *h1, const double *eri,
                              int32_t bond0, const dmrg_block_t *left, const dmrg_block_t *rights,
-                             int32_t max_kept, const dmrg_dav_opts_t *dav, uint64_t seed,
-                             dmrg_sweep_step_t *steps, dmrg_block_t *grown_out, void *stream);
+                             int32_t max_kept, const dmrg_plan_opts_t *plan_opts, const dmrg_dav_opts_t *dav,
+                             uint64_t seed, dmrg_sweep_step_t *steps, dmrg_block_t *grown_out, void *stream);
 int dmrg_sweep_right_to_left(int32_t n_orb, int32_t n_elec, int32_t two_s, const double *h1, const double *eri,
                              int32_t bond0, const dmrg_block_t *lefts, const dmrg_block_t *right,
-                             int32_t max_kept, const dmrg_dav_opts_t *dav, uint64_t seed,
-                             dmrg_sweep_step_t *steps, dmrg_block_t *grown_out, void *stream);
+                             int32_t max_kept, const dmrg_plan_opts_t *plan_opts, const dmrg_dav_opts_t *dav,
+                             uint64_t seed, dmrg_sweep_step_t *steps, dmrg_block_t *grown_out, void *stream);
 /* Frees a block returned by a sweep (tables and device data) and empties it. */
 void dmrg_block_release(dmrg_block_t *b);
 

@@ -191,8 +191,8 @@ def load(path=None):
         L.dmrg_debug_truncate_rho_host.argtypes = [ctypes.POINTER(ProblemT), c_i32, c_vp, c_vp, c_i64,
                                                    ctypes.POINTER(c_i64)]
         L.dmrg_sweep_left_to_right.argtypes = [c_i32, c_i32, c_i32, c_vp, c_vp, c_i32, ctypes.POINTER(BlockT),
-                                               ctypes.POINTER(BlockT), c_i32, c_vp, ctypes.c_uint64, c_vp, c_vp,
-                                               c_vp]
+                                               ctypes.POINTER(BlockT), c_i32, c_vp, c_vp, ctypes.c_uint64, c_vp,
+                                               c_vp, c_vp]
         L.dmrg_block_release.argtypes = [ctypes.POINTER(BlockT)]
         L.dmrg_block_release.restype = None
         L.dmrg_sweep_right_to_left.argtypes = L.dmrg_sweep_left_to_right.argtypes

@@ -1,7 +1,7 @@
 // Two-site sweeps on the device (Sec. II: two-site DMRG; Sec. I: the
 // Davidson solve and the renormalization of the block operators are the two
 // parts of every step).  At every bond the two-site problem of the current
-// blocks is planned (dmrg_build_tasks, FP64) and solved (dmrg_davidson); the
+// blocks is planned (dmrg_build_tasks) and solved (dmrg_davidson); the
 // wavefunction is cut to at most D multiplets of the growing block and its
 // site (dmrg_truncate) and that block is renormalized in the kept basis
 // (dmrg_renorm_*) into the block of the next bond.  Grown blocks stay in
@@ -184,8 +184,9 @@ struct Sweep {
   }
 
   // Davidson on the problem `pr` from a seeded start vector
-  int solve(const dmrg_problem_t &pr, const dmrg_dav_opts_t *dav, uint64_t seed, int p, dmrg_sweep_step_t &S) {
-    if (int rc = dmrg_build_tasks(&pr, 1, nullptr, stream, &plan)) return rc;
+  int solve(const dmrg_problem_t &pr, const dmrg_plan_opts_t *popts, const dmrg_dav_opts_t *dav, uint64_t seed,
+            int p, dmrg_sweep_step_t &S) {
+    if (int rc = dmrg_build_tasks(&pr, 1, popts, stream, &plan)) return rc;
     int64_t off = 0, n = 0;
     dmrg_plan_stats_t pst{};
     if (int rc = dmrg_psi_layout(plan, 0, &off, &n)) return rc;
@@ -300,8 +301,9 @@ dmrg_block_t view(const OwnedBlock &b) {
 
 extern "C" int dmrg_sweep_left_to_right(int32_t n_orb, int32_t n_elec, int32_t two_s, const double *h1,
                                         const double *eri, int32_t bond0, const dmrg_block_t *left,
-                                        const dmrg_block_t *rights, int32_t max_kept, const dmrg_dav_opts_t *dav,
-                                        uint64_t seed, dmrg_sweep_step_t *steps, dmrg_block_t *grown_out,
+                                        const dmrg_block_t *rights, int32_t max_kept, const dmrg_plan_opts_t *plan_opts,
+                                        const dmrg_dav_opts_t *dav, uint64_t seed, dmrg_sweep_step_t *steps,
+                                        dmrg_block_t *grown_out,
                                         void *stream) {
   if (!h1 || !eri || !valid_block(left) || !rights || !steps || bond0 < 1 || bond0 > n_orb - 2 || max_kept < 1) {
     set_error("bad sweep arguments (1 <= bond0 <= n_orb - 2, max_kept >= 1)");
@@ -340,7 +342,7 @@ extern "C" int dmrg_sweep_left_to_right(int32_t n_orb, int32_t n_elec, int32_t t
         make_problem(n_orb, n_elec, two_s, h1, eri, p, L.sec, crec.data(), (int64_t)crec.size(), W.cat, clen, Rb);
     dmrg_sweep_step_t &S = steps[p - bond0];
     S.bond = p;
-    if (int rc = W.solve(pr, dav, seed, p, S)) return W.fail(rc);
+    if (int rc = W.solve(pr, plan_opts, dav, seed, p, S)) return W.fail(rc);
     if (p == n_orb - 2) break;
     // truncation (H.psi form) and renormalization of the all-pairs block
     const dmrg_problem_t pa = make_problem(n_orb, n_elec, two_s, h1, eri, p, L.sec, L.rec.data(),
@@ -356,8 +358,9 @@ extern "C" int dmrg_sweep_left_to_right(int32_t n_orb, int32_t n_elec, int32_t t
 
 extern "C" int dmrg_sweep_right_to_left(int32_t n_orb, int32_t n_elec, int32_t two_s, const double *h1,
                                         const double *eri, int32_t bond0, const dmrg_block_t *lefts,
-                                        const dmrg_block_t *right, int32_t max_kept, const dmrg_dav_opts_t *dav,
-                                        uint64_t seed, dmrg_sweep_step_t *steps, dmrg_block_t *grown_out,
+                                        const dmrg_block_t *right, int32_t max_kept, const dmrg_plan_opts_t *plan_opts,
+                                        const dmrg_dav_opts_t *dav, uint64_t seed, dmrg_sweep_step_t *steps,
+                                        dmrg_block_t *grown_out,
                                         void *stream) {
   if (!h1 || !eri || !lefts || !valid_block(right) || !steps || bond0 < 0 || bond0 > n_orb - 3 || max_kept < 1) {
     set_error("bad sweep arguments (0 <= bond0 <= n_orb - 3, max_kept >= 1)");
@@ -397,7 +400,7 @@ extern "C" int dmrg_sweep_right_to_left(int32_t n_orb, int32_t n_elec, int32_t t
         make_problem(n_orb, n_elec, two_s, h1, eri, p, lsec, crec.data(), (int64_t)crec.size(), W.cat, clen, Rb);
     dmrg_sweep_step_t &S = steps[bond0 - p];
     S.bond = p;
-    if (int rc = W.solve(pr, dav, seed, p, S)) return W.fail(rc);
+    if (int rc = W.solve(pr, plan_opts, dav, seed, p, S)) return W.fail(rc);
     if (p == 0) break;
     if (int rc = W.cut(pr, pr, DMRG_RENORM_RIGHT, max_kept, S)) return W.fail(rc);
     if (int rc = W.hand_out(bond0 - p)) return W.fail(rc);

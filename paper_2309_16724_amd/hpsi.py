@@ -424,7 +424,7 @@ def sweep_right_to_left(lefts, right, h, eri, n_elec, two_s, D, tol=1e-9, seed=2
 
 
 def sweep_native(blocks, grown, h, eri, n_elec, two_s, D, tol=1e-9, seed=100, device="cuda:0", stream=None,
-                 right_to_left=False, keep_blocks=False):
+                 right_to_left=False, keep_blocks=False, precision=B.DMRG_FP64, n_slices=0):
     """A sweep inside the library, every grown block kept on the device.
     Left to right (dmrg_sweep_left_to_right): grown is the all-pairs left
     block of bond grown.p, blocks = {bond: right block}.  Right to left
@@ -433,7 +433,7 @@ def sweep_native(blocks, grown, h, eri, n_elec, two_s, D, tol=1e-9, seed=100, de
     an earlier sweep returned (device data).  Returns [(bond, energy, kept,
     kept weight, iterations)] in sweep order, and with keep_blocks also the
     grown blocks as BlockT (entry i: grown at step i; release_blocks frees
-    them)."""
+    them).  precision / n_slices: the plans' arithmetic (dmrg_plan_opts_t)."""
     torch = _torch()
     lib = B.load()
     n_orb = h.shape[0]
@@ -463,10 +463,11 @@ def sweep_native(blocks, grown, h, eri, n_elec, two_s, D, tol=1e-9, seed=100, de
     ee = np.ascontiguousarray(eri, dtype=np.float64)
     s = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
     opts = Plan._dav_opts(tol, 1000, 24, 1e-2)
+    popts = B.PlanOpts(precision, n_slices, 0, 0, 0, 0, 0, 0, 0, None, None, None, None)
     torch.cuda.synchronize()
     first, second = (tb, ctypes.byref(gb)) if right_to_left else (ctypes.byref(gb), tb)
     B.check(fn(n_orb, n_elec, two_s, hh.ctypes.data, ee.ctypes.data, grown.p, first, second, D,
-               ctypes.byref(opts), seed, steps, outs, ctypes.c_void_p(s.cuda_stream)), lib)
+               ctypes.byref(popts), ctypes.byref(opts), seed, steps, outs, ctypes.c_void_p(s.cuda_stream)), lib)
     res = [(st.bond, st.energy, st.kept, st.kept_weight, st.iters) for st in steps]
     return (res, list(outs)) if keep_blocks else res
 

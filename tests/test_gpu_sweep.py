@@ -152,3 +152,20 @@ def test_chained_sweeps(torch, system):
         release_blocks(grown)
         release_blocks(grown_r)
         assert all(b.n_sec == 0 and not b.data for b in grown)
+
+
+def test_native_sweep_on_the_split_path(torch, system):
+    """The left-to-right sweep with split-BF16 plans (5 slices) against the
+    FP64 one: full CI untruncated, the FP64 sweep's energies with D = 12."""
+    from paper_2309_16724_amd import binding as B
+    from paper_2309_16724_amd.hpsi import sweep_native
+    prob, e_fci, left, rights = system
+    for D in (4096, 12):
+        print("split sweep D=%d" % D, flush=True)
+        ref = sweep_native(rights, left, prob.h, prob.eri, N_ELEC, 0, D)
+        res = sweep_native(rights, left, prob.h, prob.eri, N_ELEC, 0, D, precision=B.DMRG_SPLIT_BF16, n_slices=5)
+        for (bond, e, kept, w, it), (_, e2, kept2, w2, _) in zip(res, ref):
+            print(bond, e - e_fci, e - e2, kept, w, it, flush=True)
+            assert abs(e - e2) < 1e-8 and kept == kept2 and abs(w - w2) < 1e-7, bond
+            if D == 4096:
+                assert abs(e - e_fci) < 1e-8

@@ -227,12 +227,12 @@ def test_sweep_argument_errors(lib):
     bad_tab[2] = B.BlockT(-1, 0, None, 0, None, None, 0)
 
     def l2r(bond0=1, D=4, left=ctypes.byref(blk), rights=table):
-        return lib.dmrg_sweep_left_to_right(n, n, 0, h.ctypes.data, eri.ctypes.data, bond0, left, rights, D, None, 1,
-                                            steps, None, None)
+        return lib.dmrg_sweep_left_to_right(n, n, 0, h.ctypes.data, eri.ctypes.data, bond0, left, rights, D, None, None,
+                                            1, steps, None, None)
 
     def r2l(bond0=3, D=4, lefts=table, right=ctypes.byref(blk)):
-        return lib.dmrg_sweep_right_to_left(n, n, 0, h.ctypes.data, eri.ctypes.data, bond0, lefts, right, D, None, 1,
-                                            steps, None, None)
+        return lib.dmrg_sweep_right_to_left(n, n, 0, h.ctypes.data, eri.ctypes.data, bond0, lefts, right, D, None, None,
+                                            1, steps, None, None)
     for rc in (l2r(bond0=0), l2r(bond0=n - 1), l2r(D=0), l2r(left=None), l2r(rights=bad_tab),
                r2l(bond0=-1), r2l(bond0=n - 2), r2l(D=0), r2l(right=None), r2l(lefts=bad_tab)):
         assert rc == -1
